@@ -1,0 +1,483 @@
+/*
+ * pam_oracle.c -- plain, slow, obviously-correct CPU reference of PAM.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark may.  It shares no code, header, table or helper with the
+ * GPU path.
+ *
+ * What it computes (Schubert & Rousseeuw, "Fast and Eager k-Medoids
+ * Clustering", arXiv 2008.05171):
+ *   - the total deviation TD                         (Sec. 2, Eq. td)
+ *   - PAM BUILD, the greedy initialisation           (Sec. 2, Alg. 1)
+ *   - the per-object loss change of a swap           (Sec. 3, Eq. change)
+ *   - PAM SWAP, best-swap steepest descent           (Sec. 2, Alg. 2)
+ *   - the best-swap-per-medoid eager variant that the paper calls FastPAM2
+ *     (Sec. 3.2, one sentence, no pseudocode), in the reading stated below.
+ *
+ * FastPAM1 (Alg. 3) performs exactly the swaps of PAM (Sec. 3.1), so the
+ * plain definition -- original PAM with Eq. change -- is the reference for it.
+ *
+ * All arithmetic is FP64.  For integer dissimilarities every intermediate
+ * value is an integer below 2^53, so FP64 is exact there.
+ *
+ * Readings of points the paper leaves open (each is also listed in the
+ * design notes of the repository):
+ *   R1 BUILD self-term: by default the candidate's own gain -dn(c) is added
+ *      to its change, so each BUILD step picks the candidate that lowers TD
+ *      most (Sec. 2 text and the TD update of Alg. 1).  exclude_self=1 gives
+ *      the literal loop bounds of Alg. 1, which skip x_c.
+ *   R2 Ties: every argmin keeps the first minimum in ascending order
+ *      (strict "<"), BUILD over c, SWAP over (slot i, then c) as in Alg. 2.
+ *   R3 A swap keeps the slot: the new medoid takes the removed one's slot.
+ *   R4 nearest(o) is the smallest slot at the minimum distance; ds(o) is the
+ *      minimum over all other slots (it equals dn(o) on ties).
+ *   R5 FastPAM2: one search gives, per slot i, the best candidate c*_i
+ *      (first minimum over ascending c).  Slots with a negative best are
+ *      visited in order of (delta, i); a visit is skipped when c*_i has become
+ *      a medoid meanwhile, otherwise the change of swapping (i, c*_i) is
+ *      evaluated again against the current medoids and the swap is applied
+ *      when that change is negative.  Converged when a search finds no
+ *      negative change.
+ *   R6 k == 1: SWAP is not run (the second-nearest distance does not exist);
+ *      BUILD's first medoid is the medoid of the whole set (Eq. def-medoid).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_ERR_ARG (-1)
+#define ORC_ERR_MEM (-2)
+#define ORC_ERR_TD (-3)      /* running TD disagrees with a fresh sum */
+#define ORC_WARN_MAXITER 1
+
+/* ------------------------------------------------------------------ */
+/* Dissimilarity source: a dense n x n matrix, or points and a metric. */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    const double *D;  /* row-major n x n, D[o*n + c] = d(x_o, x_c); may be NULL */
+    const double *X;  /* row-major n x dim points, used when D is NULL */
+    int64_t n;
+    int32_t dim;
+    int32_t metric;   /* 1 = Manhattan (L1), 2 = Euclidean (L2) */
+} src_t;
+
+static double dist(const src_t *s, int64_t a, int64_t b)
+{
+    if (s->D) return s->D[a * s->n + b];
+    const double *x = s->X + a * (int64_t)s->dim;
+    const double *y = s->X + b * (int64_t)s->dim;
+    double acc = 0.0;
+    if (s->metric == 1) {
+        for (int32_t j = 0; j < s->dim; ++j) acc += fabs(x[j] - y[j]);
+        return acc;
+    }
+    for (int32_t j = 0; j < s->dim; ++j) {
+        double t = x[j] - y[j];
+        acc += t * t;
+    }
+    return sqrt(acc);
+}
+
+static int make_src(src_t *s, const double *D, const double *X, int64_t n,
+                    int32_t dim, int32_t metric)
+{
+    if (n < 1) return ORC_ERR_ARG;
+    if (!D && (!X || dim < 1 || (metric != 1 && metric != 2))) return ORC_ERR_ARG;
+    s->D = D; s->X = X; s->n = n; s->dim = dim; s->metric = metric;
+    return ORC_OK;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Full dissimilarity matrix from points (L1 or L2), FP64. */
+int orc_dist_matrix(const double *X, int64_t n, int32_t dim, int32_t metric, double *D)
+{
+    src_t s;
+    if (!D || make_src(&s, NULL, X, n, dim, metric)) return ORC_ERR_ARG;
+    #pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < n; ++a)
+        for (int64_t b = 0; b < n; ++b)
+            D[a * n + b] = dist(&s, a, b);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Nearest / second-nearest medoid of every object (reading R4).        */
+/* ------------------------------------------------------------------ */
+static void nearest_all(const src_t *s, const int32_t *med, int32_t k,
+                        int32_t *near, double *dn, double *ds)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t o = 0; o < s->n; ++o) {
+        int32_t bi = 0;
+        double bd = dist(s, o, med[0]);
+        for (int32_t i = 1; i < k; ++i) {
+            double d = dist(s, o, med[i]);
+            if (d < bd) { bd = d; bi = i; }
+        }
+        double sd = INFINITY;
+        for (int32_t i = 0; i < k; ++i) {
+            if (i == bi) continue;
+            double d = dist(s, o, med[i]);
+            if (d < sd) sd = d;
+        }
+        near[o] = bi;
+        dn[o] = bd;
+        ds[o] = sd;
+    }
+}
+
+int orc_nearest(const double *D, const double *X, int64_t n, int32_t dim, int32_t metric,
+                const int32_t *med, int32_t k, int32_t *near, double *dn, double *ds)
+{
+    src_t s;
+    if (make_src(&s, D, X, n, dim, metric) || !med || k < 1 || !near || !dn || !ds)
+        return ORC_ERR_ARG;
+    nearest_all(&s, med, k, near, dn, ds);
+    return ORC_OK;
+}
+
+/* Total deviation TD = sum over objects of the distance to the nearest
+ * medoid (Eq. td), summed in ascending object order.  labels optional. */
+double orc_td(const double *D, const double *X, int64_t n, int32_t dim, int32_t metric,
+              const int32_t *med, int32_t k, int32_t *labels)
+{
+    src_t s;
+    if (make_src(&s, D, X, n, dim, metric) || !med || k < 1) return NAN;
+    double *dn = (double *)malloc(sizeof(double) * (size_t)n);
+    double *ds = (double *)malloc(sizeof(double) * (size_t)n);
+    int32_t *near = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!dn || !ds || !near) { free(dn); free(ds); free(near); return NAN; }
+    nearest_all(&s, med, k, near, dn, ds);
+    double td = 0.0;
+    for (int64_t o = 0; o < n; ++o) td += dn[o];
+    if (labels) memcpy(labels, near, sizeof(int32_t) * (size_t)n);
+    free(dn); free(ds); free(near);
+    return td;
+}
+
+/* ------------------------------------------------------------------ */
+/* Eq. change: loss change of object o when medoid m_i is replaced by x_c.
+ *   d     = d(x_o, x_c)
+ *   is_i  = (nearest(o) == i)
+ *   dn,ds = distances of o to its nearest and second-nearest medoid     */
+/* ------------------------------------------------------------------ */
+double orc_change(double d, int32_t is_i, double dn, double ds)
+{
+    if (!is_i) {
+        if (d >= dn) return 0.0;          /* case (a): stays with its medoid  */
+        return d - dn;                    /* case (c): moves to x_c           */
+    }
+    if (d < ds) return d - dn;            /* case (b1): m_i removed, x_c wins */
+    return ds - dn;                       /* case (b2): goes to second nearest */
+}
+
+/* Delta TD of replacing the medoid in slot i by x_c, given the caches:
+ * the sum of Eq. change over every x_o that is not one of the other medoids
+ * (Alg. 2 inner loop). */
+static double delta_swap(const src_t *s, const int32_t *med, int32_t k,
+                         const unsigned char *is_med, const int32_t *near,
+                         const double *dn, const double *ds, int32_t i, int64_t c)
+{
+    double acc = 0.0;
+    for (int64_t o = 0; o < s->n; ++o) {
+        if (is_med[o] && o != med[i]) continue;
+        acc += orc_change(dist(s, o, c), near[o] == i, dn[o], ds[o]);
+    }
+    (void)k;
+    return acc;
+}
+
+static unsigned char *medoid_mask(int64_t n, const int32_t *med, int32_t k)
+{
+    unsigned char *m = (unsigned char *)calloc((size_t)n, 1);
+    if (!m) return NULL;
+    for (int32_t i = 0; i < k; ++i) m[med[i]] = 1;
+    return m;
+}
+
+/* Delta TD of the single swap (slot i, candidate c) for the medoid set med. */
+double orc_delta(const double *D, const double *X, int64_t n, int32_t dim, int32_t metric,
+                 const int32_t *med, int32_t k, int32_t i, int64_t c)
+{
+    src_t s;
+    if (make_src(&s, D, X, n, dim, metric) || !med || k < 2 || i < 0 || i >= k || c < 0 || c >= n)
+        return NAN;
+    double *dn = (double *)malloc(sizeof(double) * (size_t)n);
+    double *ds = (double *)malloc(sizeof(double) * (size_t)n);
+    int32_t *near = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    unsigned char *is_med = medoid_mask(n, med, k);
+    double r = NAN;
+    if (dn && ds && near && is_med) {
+        nearest_all(&s, med, k, near, dn, ds);
+        r = is_med[c] ? NAN : delta_swap(&s, med, k, is_med, near, dn, ds, i, c);
+    }
+    free(dn); free(ds); free(near); free(is_med);
+    return r;
+}
+
+/* ------------------------------------------------------------------ */
+/* PAM BUILD (Alg. 1) with reading R1 for the self-term.                */
+/* ------------------------------------------------------------------ */
+int orc_build(const double *D, const double *X, int64_t n, int32_t dim, int32_t metric,
+              int32_t k, int32_t exclude_self, int32_t *med, double *td_out,
+              double *step_delta /* optional [k]: change chosen at each step */)
+{
+    src_t s;
+    if (make_src(&s, D, X, n, dim, metric) || k < 1 || k > n || !med) return ORC_ERR_ARG;
+    double *dn = (double *)malloc(sizeof(double) * (size_t)n);
+    double *chg = (double *)malloc(sizeof(double) * (size_t)n);
+    unsigned char *is_med = (unsigned char *)calloc((size_t)n, 1);
+    if (!dn || !chg || !is_med) { free(dn); free(chg); free(is_med); return ORC_ERR_MEM; }
+
+    /* First medoid: smallest sum of distances to all other objects. */
+    #pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c) {
+        double sum = 0.0;
+        for (int64_t o = 0; o < n; ++o)
+            if (o != c) sum += dist(&s, o, c);
+        chg[c] = sum;
+    }
+    int64_t m1 = -1;
+    double best = INFINITY;
+    for (int64_t c = 0; c < n; ++c)
+        if (chg[c] < best) { best = chg[c]; m1 = c; }
+    med[0] = (int32_t)m1;
+    is_med[m1] = 1;
+    if (step_delta) step_delta[0] = best;
+    for (int64_t o = 0; o < n; ++o) dn[o] = (o == m1) ? 0.0 : dist(&s, m1, o);
+
+    /* Remaining medoids: the candidate with the most negative change. */
+    for (int32_t t = 1; t < k; ++t) {
+        #pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < n; ++c) {
+            if (is_med[c]) continue;
+            double acc = 0.0;
+            for (int64_t o = 0; o < n; ++o) {
+                if (is_med[o] || o == c) continue;
+                double delta = dist(&s, o, c) - dn[o];
+                if (delta < 0.0) acc += delta;
+            }
+            if (!exclude_self) acc -= dn[c];   /* x_c itself drops to distance 0 */
+            chg[c] = acc;
+        }
+        int64_t bc = -1;
+        double bd = INFINITY;
+        for (int64_t c = 0; c < n; ++c)
+            if (!is_med[c] && chg[c] < bd) { bd = chg[c]; bc = c; }
+        med[t] = (int32_t)bc;
+        is_med[bc] = 1;
+        if (step_delta) step_delta[t] = bd;
+        for (int64_t o = 0; o < n; ++o) {
+            if (o == bc) { dn[o] = 0.0; continue; }
+            if (is_med[o]) continue;
+            double d = dist(&s, o, bc);
+            if (d < dn[o]) dn[o] = d;
+        }
+    }
+    if (td_out) {
+        double td = 0.0;   /* recomputed, not the running sum */
+        for (int64_t o = 0; o < n; ++o) td += dn[o];
+        *td_out = td;
+    }
+    free(dn); free(chg); free(is_med);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* SWAP search: the change of every (slot, candidate) pair.             */
+/* tab[i*n + c] = Delta TD of swap (i, c); NAN where c is a medoid.     */
+/* ------------------------------------------------------------------ */
+static void swap_table(const src_t *s, const int32_t *med, int32_t k,
+                       const unsigned char *is_med, const int32_t *near,
+                       const double *dn, const double *ds,
+                       int64_t c_begin, int64_t c_end, double *tab)
+{
+    const int64_t n = s->n;
+    #pragma omp parallel for collapse(2) schedule(dynamic, 16)
+    for (int32_t i = 0; i < k; ++i)
+        for (int64_t c = c_begin; c < c_end; ++c)
+            tab[(int64_t)i * n + c] =
+                is_med[c] ? NAN : delta_swap(s, med, k, is_med, near, dn, ds, i, c);
+}
+
+/* One SWAP search over candidates in [c_begin, c_end): the best swap in the
+ * order of Alg. 2 (slot outer, candidate inner, strict "<", start at 0).
+ * Returns 1 if an improving swap exists, 0 if not, <0 on error. */
+int orc_swap_search(const double *D, const double *X, int64_t n, int32_t dim, int32_t metric,
+                    const int32_t *med, int32_t k, int64_t c_begin, int64_t c_end,
+                    double *best_delta, int32_t *best_slot, int64_t *best_c)
+{
+    src_t s;
+    if (make_src(&s, D, X, n, dim, metric) || !med || k < 2 || k > n ||
+        c_begin < 0 || c_end > n || c_begin > c_end)
+        return ORC_ERR_ARG;
+    double *dn = (double *)malloc(sizeof(double) * (size_t)n);
+    double *ds = (double *)malloc(sizeof(double) * (size_t)n);
+    int32_t *near = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    double *tab = (double *)malloc(sizeof(double) * (size_t)n * (size_t)k);
+    unsigned char *is_med = medoid_mask(n, med, k);
+    int rc = ORC_ERR_MEM;
+    if (dn && ds && near && tab && is_med) {
+        nearest_all(&s, med, k, near, dn, ds);
+        swap_table(&s, med, k, is_med, near, dn, ds, c_begin, c_end, tab);
+        double bd = 0.0;
+        int32_t bi = -1;
+        int64_t bc = -1;
+        for (int32_t i = 0; i < k; ++i)
+            for (int64_t c = c_begin; c < c_end; ++c) {
+                if (is_med[c]) continue;
+                double v = tab[(int64_t)i * n + c];
+                if (v < bd) { bd = v; bi = i; bc = c; }
+            }
+        if (best_delta) *best_delta = bd;
+        if (best_slot) *best_slot = bi;
+        if (best_c) *best_c = bc;
+        rc = (bi >= 0) ? 1 : 0;
+    }
+    free(dn); free(ds); free(near); free(tab); free(is_med);
+    return rc;
+}
+
+static int td_matches(double running, double fresh)
+{
+    double tol = 1e-9 * fabs(fresh) + 1e-9;
+    return fabs(running - fresh) <= tol;
+}
+
+/* ------------------------------------------------------------------ */
+/* PAM SWAP (Alg. 2), and the FastPAM2 reading R5.                      */
+/*   variant 1 = best swap per iteration (PAM; FastPAM1 gives the same) */
+/*   variant 2 = best swap per medoid, applied eagerly (reading R5)     */
+/* med is read (slot order) and overwritten with the result.            */
+/* trace_* (optional, capacity trace_cap) receive every applied swap.   */
+/* ------------------------------------------------------------------ */
+int orc_swap(const double *D, const double *X, int64_t n, int32_t dim, int32_t metric,
+             int32_t *med, int32_t k, int32_t variant, int32_t max_iter,
+             int32_t *trace_slot, int64_t *trace_c, double *trace_delta, int32_t trace_cap,
+             int32_t *n_iter, int32_t *n_swaps, double *td_out)
+{
+    src_t s;
+    if (make_src(&s, D, X, n, dim, metric) || !med || k < 1 || k > n ||
+        (variant != 1 && variant != 2) || max_iter < 0)
+        return ORC_ERR_ARG;
+    unsigned char *is_med = (unsigned char *)calloc((size_t)n, 1);
+    if (!is_med) return ORC_ERR_MEM;
+    for (int32_t i = 0; i < k; ++i) {
+        if (med[i] < 0 || med[i] >= n || is_med[med[i]]) { free(is_med); return ORC_ERR_ARG; }
+        is_med[med[i]] = 1;
+    }
+    double *dn = (double *)malloc(sizeof(double) * (size_t)n);
+    double *ds = (double *)malloc(sizeof(double) * (size_t)n);
+    int32_t *near = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    double *tab = (k >= 2) ? (double *)malloc(sizeof(double) * (size_t)n * (size_t)k) : NULL;
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+    double *bdel = (double *)malloc(sizeof(double) * (size_t)k);
+    int64_t *bcand = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+    if (!dn || !ds || !near || (k >= 2 && !tab) || !order || !bdel || !bcand) {
+        free(is_med); free(dn); free(ds); free(near); free(tab); free(order); free(bdel); free(bcand);
+        return ORC_ERR_MEM;
+    }
+
+    int rc = ORC_OK;
+    int32_t iters = 0, swaps = 0;
+    nearest_all(&s, med, k, near, dn, ds);
+    double td = 0.0;
+    for (int64_t o = 0; o < n; ++o) td += dn[o];
+
+    while (k >= 2 && k < n) {
+        if (iters >= max_iter) { rc = ORC_WARN_MAXITER; break; }
+        ++iters;
+        swap_table(&s, med, k, is_med, near, dn, ds, 0, n, tab);
+        int applied = 0;
+        if (variant == 1) {
+            double bd = 0.0;
+            int32_t bi = -1;
+            int64_t bc = -1;
+            for (int32_t i = 0; i < k; ++i)
+                for (int64_t c = 0; c < n; ++c) {
+                    if (is_med[c]) continue;
+                    double v = tab[(int64_t)i * n + c];
+                    if (v < bd) { bd = v; bi = i; bc = c; }
+                }
+            if (bi < 0) break;   /* no swap lowers TD: converged */
+            is_med[med[bi]] = 0;
+            med[bi] = (int32_t)bc;
+            is_med[bc] = 1;
+            td += bd;
+            if (trace_slot && swaps < trace_cap) {
+                trace_slot[swaps] = bi; trace_c[swaps] = bc; trace_delta[swaps] = bd;
+            }
+            ++swaps;
+            applied = 1;
+            nearest_all(&s, med, k, near, dn, ds);
+        } else {
+            /* best candidate of every slot: first minimum over ascending c */
+            int32_t m = 0;
+            for (int32_t i = 0; i < k; ++i) {
+                double bd = INFINITY;
+                int64_t bc = -1;
+                for (int64_t c = 0; c < n; ++c) {
+                    if (is_med[c]) continue;
+                    double v = tab[(int64_t)i * n + c];
+                    if (v < bd) { bd = v; bc = c; }
+                }
+                bdel[i] = bd;
+                bcand[i] = bc;
+                if (bc >= 0 && bd < 0.0) order[m++] = i;
+            }
+            if (m == 0) break;
+            /* visit slots by (delta, slot): insertion sort, stable on slot */
+            for (int32_t a = 1; a < m; ++a) {
+                int32_t v = order[a], b = a - 1;
+                while (b >= 0 && bdel[order[b]] > bdel[v]) { order[b + 1] = order[b]; --b; }
+                order[b + 1] = v;
+            }
+            for (int32_t a = 0; a < m; ++a) {
+                int32_t i = order[a];
+                int64_t c = bcand[i];
+                if (is_med[c]) continue;
+                double dcur = delta_swap(&s, med, k, is_med, near, dn, ds, i, c);
+                if (!(dcur < 0.0)) continue;
+                is_med[med[i]] = 0;
+                med[i] = (int32_t)c;
+                is_med[c] = 1;
+                td += dcur;
+                if (trace_slot && swaps < trace_cap) {
+                    trace_slot[swaps] = i; trace_c[swaps] = c; trace_delta[swaps] = dcur;
+                }
+                ++swaps;
+                applied = 1;
+                nearest_all(&s, med, k, near, dn, ds);
+            }
+        }
+        if (applied) {
+            double fresh = 0.0;
+            for (int64_t o = 0; o < n; ++o) fresh += dn[o];
+            if (!td_matches(td, fresh)) { rc = ORC_ERR_TD; break; }
+            td = fresh;
+        }
+    }
+    if (n_iter) *n_iter = iters;
+    if (n_swaps) *n_swaps = swaps;
+    if (td_out) {
+        double fresh = 0.0;
+        for (int64_t o = 0; o < n; ++o) fresh += dn[o];
+        *td_out = fresh;
+    }
+    free(is_med); free(dn); free(ds); free(near); free(tab); free(order); free(bdel); free(bcand);
+    return rc;
+}

@@ -1,0 +1,118 @@
+"""Brute-force k-medoids checks for tiny inputs (pure Python over a matrix).
+
+Independent of the oracle: everything here recomputes the total deviation
+TD(M) = sum_o min_{m in M} d(o, m) (Eq. td) from scratch for every medoid set
+it considers, instead of using cached nearest/second distances or the change
+formula.
+"""
+from itertools import combinations
+
+
+def td_of(D, med):
+    n = len(D)
+    return sum(min(D[o][m] for m in med) for o in range(n))
+
+
+def build_greedy(D, k, exclude_self=False):
+    """Greedy BUILD by full TD recomputation.  Step 0: smallest distance sum.
+    Later steps: the candidate whose addition lowers TD most (first on ties);
+    with exclude_self the candidate's own drop to zero is not counted."""
+    n = len(D)
+    sums = [sum(D[o][c] for o in range(n) if o != c) for c in range(n)]
+    best, m1 = None, None
+    for c in range(n):
+        if best is None or sums[c] < best:
+            best, m1 = sums[c], c
+    med = [m1]
+    for _ in range(1, k):
+        base = td_of(D, med)
+        dn = [min(D[o][m] for m in med) for o in range(n)]
+        best, bc = None, None
+        for c in range(n):
+            if c in med:
+                continue
+            ch = td_of(D, med + [c]) - base
+            if exclude_self:
+                ch += dn[c]
+            if best is None or ch < best:
+                best, bc = ch, c
+        med.append(bc)
+    return med
+
+
+def all_swaps(D, med):
+    """{(slot, cand): TD change} for every swap of a medoid slot with a non-medoid."""
+    n = len(D)
+    base = td_of(D, med)
+    out = {}
+    for i in range(len(med)):
+        for c in range(n):
+            if c in med:
+                continue
+            m2 = list(med)
+            m2[i] = c
+            out[(i, c)] = td_of(D, m2) - base
+    return out
+
+
+def best_swap(D, med):
+    """Lexicographic minimum over (delta, slot, cand) among negative deltas, or None."""
+    sw = all_swaps(D, med)
+    best = None
+    for (i, c), v in sw.items():
+        if v < 0 and (best is None or (v, i, c) < best):
+            best = (v, i, c)
+    return best
+
+
+def pam_swap(D, med, max_iter=1000):
+    med = list(med)
+    trace = []
+    for _ in range(max_iter):
+        b = best_swap(D, med)
+        if b is None:
+            break
+        v, i, c = b
+        med[i] = c
+        trace.append((i, c, v))
+    return med, trace
+
+
+def fastpam2_swap(D, med, max_iter=1000):
+    """Best swap per medoid, visited by (delta, slot), each re-checked by a
+    full TD recomputation against the current medoids before it is applied."""
+    n = len(D)
+    med = list(med)
+    trace = []
+    for _ in range(max_iter):
+        sw = all_swaps(D, med)
+        per = []
+        for i in range(len(med)):
+            bv, bc = None, None
+            for c in range(n):
+                if (i, c) in sw and (bv is None or sw[(i, c)] < bv):
+                    bv, bc = sw[(i, c)], c
+            if bc is not None and bv < 0:
+                per.append((bv, i, bc))
+        if not per:
+            break
+        per.sort()
+        for _, i, c in per:
+            if c in med:
+                continue
+            m2 = list(med)
+            m2[i] = c
+            ch = td_of(D, m2) - td_of(D, med)
+            if ch < 0:
+                med = m2
+                trace.append((i, c, ch))
+    return med, trace
+
+
+def global_optimum(D, k):
+    n = len(D)
+    return min(td_of(D, list(s)) for s in combinations(range(n), k))
+
+
+def is_local_optimum(D, med):
+    return all(v >= 0 for v in all_swaps(D, med).values())

@@ -1,0 +1,294 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+The oracle (plain C, FP64) is the reference the GPU path is compared with, so
+it is itself checked here against things other than its own code:
+
+* Eq. change against the definition of the change (new nearest minus old
+  nearest distance), exhaustively over small integer distances with ties.
+* The restructured form (Eq. better-change3 and the decomposition proved in
+  the paper's appendix) against Eq. change.
+* The worked example of Fig. 1 (printed losses 10 -> 7 -> 6, golden file).
+* BUILD against greedy minimisation by full TD recomputation (Alg. 1).
+* SWAP against best-swap steepest descent by full TD recomputation (Alg. 2):
+  the whole trajectory, the local-optimum property at convergence, and the
+  global optimum over all k-subsets as a lower bound.
+* The FastPAM2 reading against a brute-force version of the same reading.
+* Distance matrices against scipy's cdist; k = 1, k = n, duplicates.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import cdist
+
+import oracle
+from paper_2008_05171_amd import datagen
+from tests import brute
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _tiny_int_D(rng, n, dim=2, hi=10):
+    X = rng.integers(0, hi, size=(n, dim))
+    return oracle.dist_matrix(X, oracle.L1), X
+
+
+# ---------------------------------------------------------------- Eq. change
+def test_change_matches_definition_exhaustive():
+    """For k medoid distances and a candidate distance, the change of object o
+    when slot i is replaced by x_c is min(d_c, min_{j!=i} d_j) - min_j d_j."""
+    vals = range(0, 5)
+    for k in (2, 3):
+        for dm in itertools.product(vals, repeat=k):
+            near = min(range(k), key=lambda j: (dm[j], j))
+            dn = dm[near]
+            ds = min(dm[j] for j in range(k) if j != near)
+            for d in vals:
+                for i in range(k):
+                    want = min([d] + [dm[j] for j in range(k) if j != i]) - dn
+                    got = oracle.change(d, near == i, dn, ds)
+                    assert got == want, (dm, d, i)
+
+
+def test_better_change3_decomposition_equals_change():
+    """Appendix proof: removal loss + shared term + per-medoid term equals Eq.
+    change for every object; and the per-medoid term equals med3(d,dn,ds)-ds."""
+    rng = np.random.default_rng(7)
+    cases = list(itertools.product(range(6), range(6), range(6), (0, 1)))
+    cases += [tuple(rng.uniform(0, 5, 3)) + (int(rng.integers(0, 2)),) for _ in range(2000)]
+    for d, a, b, is_i in cases:
+        dn, ds = min(a, b), max(a, b)
+        rem = (ds - dn) if is_i else 0.0
+        shared = (d - dn) if d < dn else 0.0
+        if is_i and d < dn:
+            per = dn - ds
+        elif is_i and d < ds:
+            per = d - ds
+        else:
+            per = 0.0
+        med3 = sorted((d, dn, ds))[1]
+        assert per == ((med3 - ds) if is_i else 0.0)
+        assert rem + shared + per == pytest.approx(oracle.change(d, is_i, dn, ds), abs=1e-12)
+
+
+# ---------------------------------------------------------------- Fig. 1
+def _read_golden(name):
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, *vals = line.split()
+            out[key] = vals
+    return out
+
+
+@pytest.mark.parametrize("variant", ["printed", "drawn"])
+def test_fig1_worked_example(variant):
+    g = _read_golden("fig1_swap.txt")
+    pts = g["points"] if variant == "printed" else g["points_drawn"]
+    losses = g["losses"] if variant == "printed" else g["losses_drawn"]
+    names = [p.split("=")[0] for p in pts]
+    X = np.array([[float(p.split("=")[1])] for p in pts])
+    D = oracle.dist_matrix(X, oracle.L1)
+    start = [names.index(s) for s in g["start"]]
+    assert oracle.td(start, D=D)[0] == float(losses[0])
+    r = oracle.swap(start, D=D)
+    want_swaps = [(int(s.split(":")[0]), names.index(s.split(":")[1])) for s in g["swaps"]]
+    assert [(s, c) for s, c, _ in r.trace] == want_swaps
+    tds = [float(losses[0])]
+    for _, _, dl in r.trace:
+        tds.append(tds[-1] + dl)
+    assert tds == [float(v) for v in losses]
+    assert [names[m] for m in r.medoids] == g["final"]
+    assert r.iterations == r.swaps + 1 and r.rc == 0
+    # the final loss is the global optimum for k = 2 here
+    assert brute.global_optimum(D.tolist(), 2) == float(losses[-1])
+
+
+def test_fig1_build_readings():
+    """BUILD on Fig. 1's points: with the self-term (default reading) it picks
+    C then A (TD 7); with the literal loop bounds it picks C then D (TD 12).
+    Both then converge to TD 6."""
+    X = np.array([[-7.0], [0], [1], [2], [3], [4]])
+    D = oracle.dist_matrix(X, oracle.L1)
+    m, tdb, _ = oracle.build(2, D=D)
+    assert list(m) == [2, 0] and tdb == 7.0
+    m2, tdb2, _ = oracle.build(2, D=D, exclude_self=True)
+    assert list(m2) == [2, 3] and tdb2 == 12.0
+    assert oracle.pam(2, D=D).td == 6.0
+    assert oracle.pam(2, D=D, exclude_self=True).td == 6.0
+
+
+# ---------------------------------------------------------------- distances
+def test_dist_matrix_vs_scipy():
+    rng = np.random.default_rng(3)
+    X = rng.normal(size=(37, 5))
+    np.testing.assert_allclose(oracle.dist_matrix(X, oracle.L2), cdist(X, X), rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(oracle.dist_matrix(X, oracle.L1), cdist(X, X, "cityblock"),
+                               rtol=1e-13, atol=1e-13)
+    Xi = datagen.int_points(50, 2, 0, 1000, seed=1)
+    assert np.array_equal(oracle.dist_matrix(Xi, oracle.L1), cdist(Xi, Xi, "cityblock"))
+
+
+# ---------------------------------------------------------------- BUILD
+@pytest.mark.parametrize("exclude_self", [False, True])
+def test_build_is_greedy_td(exclude_self):
+    rng = np.random.default_rng(11)
+    for trial in range(40):
+        n = int(rng.integers(3, 13))
+        k = int(rng.integers(1, n + 1))
+        D, _ = _tiny_int_D(rng, n, hi=6)      # many ties
+        m, tdb, _ = oracle.build(k, D=D, exclude_self=exclude_self)
+        want = brute.build_greedy(D.tolist(), k, exclude_self=exclude_self)
+        assert list(m) == want, (trial, n, k)
+        assert tdb == brute.td_of(D.tolist(), want)
+
+
+def test_k1_is_the_medoid():
+    """k = 1: BUILD's first pick is the medoid of the set (Eq. def-medoid)."""
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        n = int(rng.integers(1, 30))
+        X = rng.normal(size=(n, 3))
+        D = oracle.dist_matrix(X)
+        r = oracle.pam(1, D=D)
+        sums = [sum(D[o][c] for o in range(n)) for c in range(n)]
+        assert r.medoids[0] == int(np.argmin(sums))
+        assert r.swaps == 0 and r.iterations == 0
+        assert r.td == pytest.approx(min(sums), rel=1e-12)
+
+
+# ---------------------------------------------------------------- SWAP
+def test_swap_trajectory_is_steepest_descent():
+    """Every applied swap is the best (delta, slot, cand) over all swaps by
+    full TD recomputation; the result is a local optimum and no better than
+    the global optimum (Alg. 2)."""
+    rng = np.random.default_rng(12)
+    for trial in range(30):
+        n = int(rng.integers(4, 12))
+        k = int(rng.integers(2, min(5, n - 1) + 1))
+        D, _ = _tiny_int_D(rng, n, hi=8)
+        start = [int(v) for v in rng.choice(n, size=k, replace=False)]
+        r = oracle.swap(start, D=D)
+        Dl = D.tolist()
+        med_b, trace_b = brute.pam_swap(Dl, start)
+        assert [(s, c) for s, c, _ in r.trace] == [(i, c) for i, c, _ in trace_b], trial
+        assert [d for _, _, d in r.trace] == [v for _, _, v in trace_b]
+        assert list(r.medoids) == med_b
+        assert brute.is_local_optimum(Dl, med_b)
+        assert r.td == brute.td_of(Dl, med_b) >= brute.global_optimum(Dl, k)
+        assert r.iterations == r.swaps + 1
+
+
+def test_swap_cross_tie_takes_pam_order():
+    """Equal best changes at different (slot, cand): the swap taken is the
+    first in slot-then-candidate order, as Alg. 2's loops give."""
+    X = np.array([[3], [2], [4], [4], [5], [5], [2], [5]], float)
+    D = oracle.dist_matrix(X, oracle.L1)
+    found, dl, slot, c = oracle.swap_search([3, 0], D=D)
+    b = brute.best_swap(D.tolist(), [3, 0])
+    assert found and (dl, slot, c) == b
+    # the brute force shows a second swap with the same change in a later slot
+    sw = brute.all_swaps(D.tolist(), [3, 0])
+    assert any(v == dl and i > slot for (i, _), v in sw.items())
+
+
+def test_delta_matches_td_difference():
+    rng = np.random.default_rng(21)
+    for _ in range(30):
+        n = int(rng.integers(4, 20))
+        k = int(rng.integers(2, n))
+        X = rng.normal(size=(n, 2))
+        D = oracle.dist_matrix(X)
+        med = [int(v) for v in rng.choice(n, size=k, replace=False)]
+        non = [c for c in range(n) if c not in med]
+        i = int(rng.integers(0, k))
+        c = int(rng.choice(non))
+        m2 = list(med)
+        m2[i] = c
+        want = brute.td_of(D.tolist(), m2) - brute.td_of(D.tolist(), med)
+        assert oracle.delta(med, i, c, D=D) == pytest.approx(want, abs=1e-12)
+        # points mode computes the same distances on the fly
+        assert oracle.delta(med, i, c, X=X) == pytest.approx(want, abs=1e-12)
+
+
+def test_pam_from_build_matches_bruteforce():
+    rng = np.random.default_rng(31)
+    for _ in range(15):
+        n = int(rng.integers(5, 13))
+        k = int(rng.integers(2, 5))
+        D, _ = _tiny_int_D(rng, n, hi=7)
+        r = oracle.pam(k, D=D)
+        Dl = D.tolist()
+        bm = brute.build_greedy(Dl, k)
+        med_b, _ = brute.pam_swap(Dl, bm)
+        assert list(r.medoids) == med_b
+        assert r.td == brute.td_of(Dl, med_b)
+        assert r.td_build == brute.td_of(Dl, bm)
+        near = [min(range(k), key=lambda j: (Dl[o][med_b[j]], j)) for o in range(n)]
+        assert list(r.labels) == near
+
+
+# ---------------------------------------------------------------- FastPAM2 reading
+def test_fastpam2_reading_matches_bruteforce():
+    rng = np.random.default_rng(41)
+    for trial in range(30):
+        n = int(rng.integers(5, 12))
+        k = int(rng.integers(2, min(5, n - 1) + 1))
+        D, _ = _tiny_int_D(rng, n, hi=9)
+        start = [int(v) for v in rng.choice(n, size=k, replace=False)]
+        r = oracle.swap(start, D=D, variant=oracle.FASTPAM2)
+        med_b, trace_b = brute.fastpam2_swap(D.tolist(), start)
+        assert list(r.medoids) == med_b, trial
+        assert [(s, c, d) for s, c, d in r.trace] == [(i, c, v) for i, c, v in trace_b]
+        assert brute.is_local_optimum(D.tolist(), med_b)
+
+
+def test_fastpam2_first_swap_equals_pam_first_swap():
+    rng = np.random.default_rng(43)
+    for _ in range(20):
+        n = int(rng.integers(6, 14))
+        k = int(rng.integers(2, 5))
+        D, _ = _tiny_int_D(rng, n, hi=20)
+        start = [int(v) for v in rng.choice(n, size=k, replace=False)]
+        a = oracle.swap(start, D=D, variant=oracle.PAM, max_iter=1)
+        b = oracle.swap(start, D=D, variant=oracle.FASTPAM2, max_iter=1)
+        if a.trace:
+            assert b.trace[0] == a.trace[0]
+
+
+# ---------------------------------------------------------------- degenerate cases
+def test_k_equals_n_and_duplicates():
+    X = np.array([[0.0], [0.0], [1.0], [1.0], [5.0]])
+    D = oracle.dist_matrix(X, oracle.L1)
+    r = oracle.pam(5, D=D)
+    assert r.td == 0.0 and sorted(r.medoids) == [0, 1, 2, 3, 4]
+    r2 = oracle.pam(2, D=D)
+    assert r2.td == brute.global_optimum(D.tolist(), 2)
+    # duplicate points with zero distance keep caches consistent
+    r3 = oracle.pam(3, D=D)
+    assert r3.td == brute.td_of(D.tolist(), list(r3.medoids))
+    assert brute.is_local_optimum(D.tolist(), list(r3.medoids))
+
+
+def test_invalid_medoids_rejected():
+    D = np.zeros((4, 4))
+    with pytest.raises(ValueError):
+        oracle.swap([0, 0], D=D)
+    with pytest.raises(ValueError):
+        oracle.swap([0, 7], D=D)
+
+
+def test_running_td_bookkeeping_on_int_workload():
+    """On the 1000-point integer workload shape (smaller n for speed) the
+    running TD equals a fresh sum after every swap (checked inside the C code,
+    rc would be negative) and iterations == swaps + 1."""
+    X = datagen.workload_l1_int(n=300, seed=1001)
+    D = oracle.dist_matrix(X, oracle.L1)
+    r = oracle.pam(5, D=D)
+    assert r.rc == 0 and r.iterations == r.swaps + 1
+    tdv, _ = oracle.td(r.medoids, D=D)
+    assert tdv == r.td == float(int(r.td))
