@@ -1,0 +1,168 @@
+/*
+ * pamx.h -- C ABI of the MI355X (gfx950) k-medoids library.
+ *
+ * The library implements PAM (Kaufman & Rousseeuw) with the SWAP
+ * improvements of Schubert & Rousseeuw, "Fast and Eager k-Medoids
+ * Clustering", arXiv 2008.05171:
+ *   - BUILD, the greedy initialisation                   (Sec. 2, Alg. 1)
+ *   - FastPAM1 SWAP: one pass per candidate over all objects gives the
+ *     change of all k swaps at once (Sec. 3.1, Alg. 3, Eq. better-change3);
+ *     it performs exactly the swaps of PAM SWAP           (Sec. 2, Alg. 2)
+ *   - eager FastPAM2 SWAP: the best swap of every medoid from one pass,
+ *     applied one after another in the same iteration     (Sec. 3.2)
+ *
+ * Conventions shared by every entry point:
+ *   - Array arguments are DEVICE pointers owned by the caller (for instance
+ *     torch tensors on the GPU).  Scalar outputs (td, stats) are HOST
+ *     pointers, written after the call has synchronised its stream.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Every call returns after the work on `stream` has finished.
+ *   - The library allocates no device memory.  Scratch space is the caller's
+ *     workspace `ws` of `ws_bytes` bytes, 256-byte aligned, sized by
+ *     pamx_workspace_bytes() for the same arguments.
+ *   - Dissimilarities are a row-major n x n matrix with leading dimension
+ *     `ld` >= n (elements): D[o*ld + c] = d(x_o, x_c).  D must be symmetric,
+ *     non-negative and have a zero diagonal (Sec. 2 requires only a
+ *     dissimilarity; symmetry lets the library read row c for column c).
+ *     Element type PAMX_I32 (exact int64 sums) or PAMX_F32.
+ *   - Medoids are object indices in SLOT order.  A swap keeps the slot: the
+ *     new medoid takes the slot of the medoid it replaces.  labels[o] is the
+ *     slot of o's nearest medoid (smallest slot on distance ties).
+ *   - Ties: BUILD takes the smallest candidate index among equal changes;
+ *     SWAP takes the smallest (change, slot, candidate) in lexicographic
+ *     order, which is the order of Alg. 2's loops, so FastPAM1 reproduces
+ *     PAM exactly on integer dissimilarities.
+ *   - A swap is applied only if it lowers TD strictly (Alg. 2 and 3 stop
+ *     when the best change is >= 0).
+ *   - Return value: PAMX_OK (0), PAMX_WARN_MAXITER (1: results valid, the
+ *     iteration cap was reached), or a negative PAMX_ERR_* code; then
+ *     pamx_last_error() describes it.  Argument errors are detected on the
+ *     host before any device work is enqueued.
+ *   - Results are deterministic: no floating-point atomics are used, so the
+ *     same inputs give bitwise identical outputs.
+ */
+#ifndef PAMX_H
+#define PAMX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* element types */
+#define PAMX_I32 1
+#define PAMX_F32 2
+
+/* input kinds of pamx_fit */
+#define PAMX_INPUT_D 0 /* an n x n dissimilarity matrix */
+#define PAMX_INPUT_X 1 /* n points of `dim` coordinates, row-major */
+
+/* metrics for points */
+#define PAMX_L1 1 /* Manhattan: int32 points give exact int32 distances */
+#define PAMX_L2 2 /* Euclidean: float32 points */
+
+/* SWAP variants */
+#define PAMX_FASTPAM1 1 /* best swap per iteration (Alg. 3)               */
+#define PAMX_FASTPAM2 2 /* best swap per medoid, applied eagerly (Sec. 3.2) */
+
+/* accumulation of the loss changes for PAMX_F32 dissimilarities */
+#define PAMX_ACC_F64 0 /* FP64 sums (default)                              */
+#define PAMX_ACC_F32 1 /* FP32 sums; candidates whose change lies within a
+                          rigorous FP32 error bound of the best are scored
+                          again in FP64 before the swap is chosen          */
+
+/* return codes */
+#define PAMX_OK 0
+#define PAMX_WARN_MAXITER 1
+#define PAMX_ERR_ARG (-1)
+#define PAMX_ERR_WORKSPACE (-2)
+#define PAMX_ERR_HIP (-3)
+#define PAMX_ERR_INVALID_MEDOIDS (-4)
+#define PAMX_ERR_UNSUPPORTED (-5)
+
+typedef struct pamx_options {
+    int32_t variant;            /* PAMX_FASTPAM1 (default) or PAMX_FASTPAM2   */
+    int32_t accum;              /* PAMX_ACC_F64 (default) or PAMX_ACC_F32     */
+    int32_t max_iter;           /* SWAP iterations (searches) cap; default 10000 */
+    int32_t build_exclude_self; /* 0 (default): a BUILD candidate's own drop to
+                                   distance 0 counts in its change, so each step
+                                   adds the point that lowers TD most; 1: the
+                                   literal loop bounds of Alg. 1 (x_c skipped) */
+    int32_t trace_cap;          /* capacity of `trace` in records (0: none)   */
+    int32_t chunk;              /* objects per pass work-group; 0 = automatic */
+    void *trace;                /* optional DEVICE array of pamx_swap_record:
+                                   every applied swap in order               */
+} pamx_options;
+
+typedef struct pamx_swap_record {
+    int32_t slot;   /* medoid slot that was replaced */
+    int32_t cand;   /* object that became the medoid */
+    double delta;   /* change of TD of the swap (exact for PAMX_I32) */
+} pamx_swap_record;
+
+typedef struct pamx_stats {
+    int32_t iterations; /* SWAP searches performed (PAM: swaps + 1 when converged) */
+    int32_t swaps;      /* swaps applied */
+    int32_t converged;  /* 1 if the last search found no improving swap */
+    int32_t rescored;   /* candidates scored again in FP64 (PAMX_ACC_F32) */
+    double td_build;    /* TD after BUILD (pamx_fit) */
+    double td;          /* final TD, summed afresh (FP64; exact for PAMX_I32) */
+    double ms_dist, ms_build, ms_swap, ms_total; /* device time per phase */
+    int64_t pass_pairs; /* candidate-object pairs read by SWAP passes */
+    int64_t build_pairs;/* candidate-object pairs read by BUILD passes */
+} pamx_stats;
+
+/* Fills `opt` with the defaults listed above. */
+void pamx_default_options(pamx_options *opt);
+
+/* Workspace bytes needed by pamx_build / pamx_swap / pamx_fit for these
+ * arguments.  input_kind PAMX_INPUT_X includes room for the n x n matrix
+ * (row stride rounded up to 64 elements).  Returns 0 or PAMX_ERR_ARG. */
+int pamx_workspace_bytes(int64_t n, int32_t k, int32_t dim, int32_t input_kind,
+                         int32_t dtype, const pamx_options *opt, size_t *bytes);
+
+/* Dissimilarity matrix of n points (Sec. 2: PAM consumes a matrix).
+ *   X      device, n x dim row-major; PAMX_I32 with PAMX_L1 (exact), or
+ *          PAMX_F32 with PAMX_L2 (Euclidean; the Gram term on MFMA).
+ *   D      device, n x ld output of the same element type; ld >= n,
+ *          a multiple of 4.  Diagonal written as 0, D symmetric bitwise. */
+int pamx_dist(const void *X, int32_t dtype, int64_t n, int32_t dim, int32_t metric,
+              void *D, int64_t ld, void *stream);
+
+/* BUILD (Alg. 1): k initial medoids in slot order (the order picked).
+ *   D        device dissimilarities (see conventions)
+ *   medoids  device int32[k] output
+ *   td       host double output: TD of the k medoids, summed afresh */
+int pamx_build(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+               const pamx_options *opt, int32_t *medoids, double *td,
+               void *ws, size_t ws_bytes, void *stream);
+
+/* SWAP (Alg. 3, or eager FastPAM2) from the given medoids to a local
+ * optimum: no single swap lowers TD (Sec. 2).
+ *   medoids  device int32[k], read and overwritten, slot order; entries must
+ *            be distinct and in [0, n), else PAMX_ERR_INVALID_MEDOIDS
+ *   labels   device int32[n] output (may be NULL)
+ *   td       host double output (may be NULL)
+ *   stats    host output (may be NULL) */
+int pamx_swap(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+              const pamx_options *opt, int32_t *medoids, int32_t *labels, double *td,
+              pamx_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* Whole fit: distances (for points), BUILD, SWAP, labels and TD.
+ *   XorD  device: n x n matrix (input_kind PAMX_INPUT_D, ld = n) or n x dim
+ *         points (PAMX_INPUT_X; the matrix is written into the workspace). */
+int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int64_t n, int32_t dim,
+             int32_t metric, int32_t k, const pamx_options *opt, int32_t *medoids,
+             int32_t *labels, double *td, pamx_stats *stats, void *ws, size_t ws_bytes,
+             void *stream);
+
+/* Message for the last non-zero return on this thread ("" if none). */
+const char *pamx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAMX_H */

@@ -1,1 +1,133 @@
-"""MI355X-native FastPAM1 / eager FastPAM2 k-medoids (package stub)."""
+"""MI355X-native k-medoids: PAM BUILD with FastPAM1 / eager FastPAM2 SWAP.
+
+Schubert & Rousseeuw, "Fast and Eager k-Medoids Clustering: O(k) Runtime
+Improvement of the PAM, CLARA, and CLARANS Algorithms", arXiv 2008.05171.
+
+All compute runs in libpamx.so (hand-written HIP for gfx950); the functions
+here allocate outputs and the workspace with torch and call the C ABI through
+``paper_2008_05171_amd.pamx``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+from . import pamx as _abi
+from .pamx import (PAMX_ACC_F32, PAMX_ACC_F64, PAMX_FASTPAM1, PAMX_FASTPAM2, PAMX_INPUT_D,
+                   PAMX_INPUT_X, PAMX_L1, PAMX_L2, PamxError)
+
+__all__ = ["fit", "build", "swap", "dist", "FitResult", "PamxError", "PAMX_FASTPAM1",
+           "PAMX_FASTPAM2", "PAMX_L1", "PAMX_L2", "PAMX_ACC_F64", "PAMX_ACC_F32",
+           "PAMX_INPUT_D", "PAMX_INPUT_X"]
+
+_VARIANTS = {"fastpam1": PAMX_FASTPAM1, "fastpam2": PAMX_FASTPAM2,
+             PAMX_FASTPAM1: PAMX_FASTPAM1, PAMX_FASTPAM2: PAMX_FASTPAM2}
+
+
+@dataclass
+class FitResult:
+    medoids: object          # torch.int32 [k] on the device, slot order
+    labels: object           # torch.int32 [n] on the device
+    td: float
+    rc: int
+    stats: dict
+    trace: list = field(default_factory=list)   # [(slot, candidate, delta)]
+
+
+def _options(variant="fastpam1", accum=PAMX_ACC_F64, max_iter=10000, exclude_self=False,
+             chunk=0, trace_buf=None, trace_cap=0):
+    o = _abi.pamx_default_options()
+    o.variant = _VARIANTS[variant]
+    o.accum = int(accum)
+    o.max_iter = int(max_iter)
+    o.build_exclude_self = int(bool(exclude_self))
+    o.chunk = int(chunk)
+    if trace_buf is not None:
+        o.trace = trace_buf.data_ptr()
+        o.trace_cap = int(trace_cap)
+    return o
+
+
+def _workspace(nbytes, device):
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _trace_list(buf, count):
+    import numpy as np
+    if buf is None or count <= 0:
+        return []
+    raw = buf[: count * 16].cpu().numpy()
+    rec = np.frombuffer(raw.tobytes(), dtype=np.dtype([("slot", "<i4"), ("cand", "<i4"),
+                                                         ("delta", "<f8")]))
+    return [(int(r["slot"]), int(r["cand"]), float(r["delta"])) for r in rec]
+
+
+def _stats_dict(st):
+    return {f: getattr(st, f) for f, _ in _abi.pamx_stats._fields_}
+
+
+def fit(data, k, *, input_kind=PAMX_INPUT_X, metric=None, variant="fastpam1",
+        accum=PAMX_ACC_F64, max_iter=10000, exclude_self=False, trace=False, chunk=0,
+        stream=None) -> FitResult:
+    """Distances (for points), BUILD, SWAP, labels and TD on the GPU.
+
+    data: device tensor, n x dim points (int32 -> L1, float32 -> L2) or an
+    n x n dissimilarity matrix with input_kind=PAMX_INPUT_D."""
+    import torch
+    n = data.shape[0]
+    dim = data.shape[1] if input_kind == PAMX_INPUT_X else 0
+    dtype = _abi._dtype_code(data)
+    if metric is None:
+        metric = PAMX_L1 if dtype == _abi.PAMX_I32 else PAMX_L2
+    cap = (max_iter * (k if variant in ("fastpam2", PAMX_FASTPAM2) else 1) + 16) if trace else 0
+    tbuf = torch.empty(cap * 16, dtype=torch.uint8, device=data.device) if trace else None
+    opt = _options(variant, accum, max_iter, exclude_self, chunk, tbuf, cap)
+    nbytes = _abi.pamx_workspace_bytes(n, k, dim, input_kind, dtype, opt)
+    ws = _workspace(nbytes, data.device)
+    med = torch.empty(k, dtype=torch.int32, device=data.device)
+    lab = torch.empty(n, dtype=torch.int32, device=data.device)
+    rc, td, st = _abi.pamx_fit(data, input_kind, k, med, lab, ws, metric=metric, opt=opt,
+                               stream=stream)
+    return FitResult(med, lab, td, rc, _stats_dict(st), _trace_list(tbuf, min(st.swaps, cap)))
+
+
+def build(D, k, *, exclude_self=False, stream=None):
+    """BUILD only: returns (medoids tensor [k], TD)."""
+    import torch
+    n = D.shape[0]
+    opt = _options(exclude_self=exclude_self)
+    nbytes = _abi.pamx_workspace_bytes(n, k, 0, PAMX_INPUT_D, _abi._dtype_code(D), opt)
+    ws = _workspace(nbytes, D.device)
+    med = torch.empty(k, dtype=torch.int32, device=D.device)
+    _, td = _abi.pamx_build(D, k, med, ws, opt=opt, stream=stream)
+    return med, td
+
+
+def swap(D, medoids, *, variant="fastpam1", accum=PAMX_ACC_F64, max_iter=10000, trace=False,
+         chunk=0, stream=None) -> FitResult:
+    """SWAP from the given medoids (device int32 tensor, slot order; copied)."""
+    import torch
+    n = D.shape[0]
+    k = int(medoids.numel())
+    cap = (max_iter * (k if variant in ("fastpam2", PAMX_FASTPAM2) else 1) + 16) if trace else 0
+    tbuf = torch.empty(cap * 16, dtype=torch.uint8, device=D.device) if trace else None
+    opt = _options(variant, accum, max_iter, False, chunk, tbuf, cap)
+    nbytes = _abi.pamx_workspace_bytes(n, k, 0, PAMX_INPUT_D, _abi._dtype_code(D), opt)
+    ws = _workspace(nbytes, D.device)
+    med = medoids.to(device=D.device, dtype=torch.int32).clone()
+    lab = torch.empty(n, dtype=torch.int32, device=D.device)
+    rc, td, st = _abi.pamx_swap(D, k, med, ws, labels=lab, opt=opt, stream=stream)
+    return FitResult(med, lab, td, rc, _stats_dict(st), _trace_list(tbuf, min(st.swaps, cap)))
+
+
+def dist(X, *, metric=None, ld=None, stream=None):
+    """n x n dissimilarity matrix of points X (int32 -> L1, float32 -> L2)."""
+    import torch
+    n = X.shape[0]
+    dtype = _abi._dtype_code(X)
+    if metric is None:
+        metric = PAMX_L1 if dtype == _abi.PAMX_I32 else PAMX_L2
+    ld = ((n + 3) // 4) * 4 if ld is None else ld
+    D = torch.empty((n, ld), dtype=X.dtype, device=X.device)
+    _abi.pamx_dist(X, metric, D, ld=ld, stream=stream)
+    return D[:, :n]

@@ -1,0 +1,181 @@
+// dist.hip -- dissimilarity matrices for PAM (which consumes an n x n matrix,
+// Sec. 2 of Schubert & Rousseeuw, arXiv 2008.05171).
+//
+//  * k_dist_l1_i32 : exact Manhattan distances of int32 points (VALU).
+//  * k_dist_l2_f32 : Euclidean distances d = sqrt(max(|x|^2 + |y|^2 - 2 x.y, 0))
+//                    with the Gram term x.y on the FP32 matrix cores
+//                    (v_mfma_f32_32x32x2_f32), 64 x 64 tiles staged in LDS and
+//                    written back as full 256-byte row segments.
+//  Both write a zero diagonal and are bitwise symmetric.
+#include "pamx_internal.h"
+
+namespace pamx {
+
+// ---------------------------------------------------------------- L1 int32
+// One thread computes 4 consecutive columns of one row.  Points are tiny
+// (dim is small for integer coordinates), so they are read through the cache.
+__global__ __launch_bounds__(256) void k_dist_l1_i32(const int32_t *__restrict__ X, int64_t n,
+                                                     int32_t dim, int32_t *__restrict__ D,
+                                                     int64_t ld) {
+    const int64_t o = (int64_t)blockIdx.y * 16 + (threadIdx.x >> 4);
+    const int64_t c = ((int64_t)blockIdx.x * 16 + (threadIdx.x & 15)) * 4;
+    if (o >= n || c >= n) return;
+    int32_t acc[4] = {0, 0, 0, 0};
+    const int32_t *xo = X + o * dim;
+    for (int j = 0; j < dim; ++j) {
+        const int32_t a = xo[j];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            if (c + v < n) {
+                const int32_t b = X[(c + v) * dim + j];
+                acc[v] += (a > b) ? (a - b) : (b - a);
+            }
+        }
+    }
+    int32_t *row = D + o * ld;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        if (c + v < n) row[c + v] = (c + v == o) ? 0 : acc[v];
+}
+
+hipError_t launch_dist_l1_i32(const int32_t *X, int64_t n, int32_t dim, int32_t *D, int64_t ld,
+                              hipStream_t s) {
+    dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n + 15) / 16));
+    hipLaunchKernelGGL(k_dist_l1_i32, grid, dim3(256), 0, s, X, n, dim, D, ld);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- centring
+// Subtracting the mean does not change Euclidean distances but shrinks |x|^2,
+// which bounds the cancellation error of the Gram form.  The mean of each
+// coordinate is summed in FP64 in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_center_mean(const float *__restrict__ X, int64_t n,
+                                                     int32_t dim, float *__restrict__ mean) {
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t o = threadIdx.x; o < n; o += 256) acc += (double)X[o * dim + j];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) mean[j] = (float)(red[0] / (double)n);
+}
+
+__global__ __launch_bounds__(256) void k_center_sub(const float *__restrict__ X, int64_t total,
+                                                    int32_t dim, const float *__restrict__ mean,
+                                                    float *__restrict__ Xc) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < total) Xc[t] = X[t] - mean[t % dim];
+}
+
+hipError_t launch_center_f32(const float *X, int64_t n, int32_t dim, float *Xc, hipStream_t s) {
+    // the mean is parked right after the centred copy (the workspace reserves it)
+    float *mean = Xc + n * dim;
+    hipLaunchKernelGGL(k_center_mean, dim3(dim), dim3(256), 0, s, X, n, dim, mean);
+    const int64_t total = n * dim;
+    hipLaunchKernelGGL(k_center_sub, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, X,
+                       total, dim, (const float *)mean, Xc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- L2 f32 (MFMA)
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kT = 64;        // output tile edge
+constexpr int kKC = 32;       // coordinates staged per LDS round (even)
+constexpr int kLdsK = kKC + 1; // padded row stride of the staged points
+
+// Work-group: 4 waves, each owns a 32 x 32 quarter of the 64 x 64 tile.
+// v_mfma_f32_32x32x2_f32 operand layout (wave64): lane l supplies A[l%32][l/32]
+// and B[l/32][l%32]; accumulator element v of lane l is C[8*(v/4) + 4*(l/32) +
+// v%4][l%32].
+__global__ __launch_bounds__(256) void k_dist_l2_f32(const float *__restrict__ X, int64_t n,
+                                                     int32_t dim, float *__restrict__ D,
+                                                     int64_t ld) {
+    __shared__ float xa[kT * kLdsK];
+    __shared__ float xb[kT * kLdsK];
+    __shared__ float na[kT], nb[kT];
+    __shared__ float tile[kT * (kT + 4)];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.y * kT;   // rows (objects o)
+    const int64_t c0 = (int64_t)blockIdx.x * kT;   // columns (candidates c)
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+
+    floatx16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    float nacc = 0.0f;  // threads 0..63: row norms, 64..127: column norms
+
+    for (int k0 = 0; k0 < dim; k0 += kKC) {
+        const int kc = min(kKC, dim - k0);
+        __syncthreads();
+        for (int e = tid; e < kT * kKC; e += 256) {
+            const int r = e / kKC, kk = e % kKC;
+            float va = 0.0f, vb = 0.0f;
+            if (kk < kc) {
+                if (r0 + r < n) va = X[(r0 + r) * dim + k0 + kk];
+                if (c0 + r < n) vb = X[(c0 + r) * dim + k0 + kk];
+            }
+            xa[r * kLdsK + kk] = va;
+            xb[r * kLdsK + kk] = vb;
+        }
+        __syncthreads();
+        if (tid < 128) {
+            const float *src = (tid < 64) ? &xa[tid * kLdsK] : &xb[(tid - 64) * kLdsK];
+            for (int kk = 0; kk < kc; ++kk) nacc = fmaf(src[kk], src[kk], nacc);
+        }
+        const int i = lane & 31, h = lane >> 5;
+        for (int kk = 0; kk < kc; kk += 2) {
+            const float a = xa[(wr + i) * kLdsK + kk + h];
+            const float b = xb[(wc + i) * kLdsK + kk + h];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        }
+    }
+    if (tid < 64) na[tid] = nacc;
+    else if (tid < 128) nb[tid - 64] = nacc;
+    __syncthreads();
+
+    {
+        const int j = lane & 31, h = lane >> 5;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int r = wr + 8 * (v >> 2) + 4 * h + (v & 3);
+            const int c = wc + j;
+            const float s = (na[r] + nb[c]) - 2.0f * acc[v];
+            float d = sqrtf(fmaxf(s, 0.0f));
+            if (r0 + r == c0 + c) d = 0.0f;
+            tile[r * (kT + 4) + c] = d;
+        }
+    }
+    __syncthreads();
+    // write 64 rows x 64 columns: each thread stores 4 float4 (16 per row)
+    const bool full = (c0 + kT <= n) && ((ld & 3) == 0);
+    for (int e = tid; e < kT * (kT / 4); e += 256) {
+        const int r = e >> 4, q = (e & 15) * 4;
+        const int64_t o = r0 + r;
+        if (o >= n) continue;
+        const float *t = &tile[r * (kT + 4) + q];
+        float *dst = D + o * ld + c0 + q;
+        if (full) {
+            *reinterpret_cast<float4 *>(dst) = make_float4(t[0], t[1], t[2], t[3]);
+        } else {
+            for (int v = 0; v < 4; ++v)
+                if (c0 + q + v < n) dst[v] = t[v];
+        }
+    }
+}
+
+hipError_t launch_dist_l2_f32(const float *X, int64_t n, int32_t dim, float *D, int64_t ld,
+                              hipStream_t s) {
+    dim3 grid((unsigned)((n + kT - 1) / kT), (unsigned)((n + kT - 1) / kT));
+    hipLaunchKernelGGL(k_dist_l2_f32, grid, dim3(256), 0, s, X, n, dim, D, ld);
+    return hipGetLastError();
+}
+
+}  // namespace pamx

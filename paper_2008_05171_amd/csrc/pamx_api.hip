@@ -1,0 +1,451 @@
+// pamx_api.hip -- host side of the C ABI declared in include/pamx.h:
+// argument validation (before any device work), workspace layout, and the
+// orchestration of BUILD (Alg. 1) and SWAP (Alg. 3 / eager FastPAM2) of
+// Schubert & Rousseeuw, arXiv 2008.05171.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <type_traits>
+
+#include "pamx_internal.h"
+
+namespace pamx {
+template <typename T>
+hipError_t enqueue_swap_caches(const T *D, int64_t ld, const Layout &L, const int32_t *medoids,
+                               void *ws, hipStream_t s);
+}
+
+using namespace pamx;
+
+static thread_local char g_err[512] = "";
+
+static int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(PAMX_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+extern "C" const char *pamx_last_error(void) { return g_err; }
+
+extern "C" void pamx_default_options(pamx_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->variant = PAMX_FASTPAM1;
+    opt->accum = PAMX_ACC_F64;
+    opt->max_iter = 10000;
+}
+
+static size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+namespace pamx {
+
+// Chunk length: enough object chunks that the pass grid has ~1024
+// work-groups (4 per CU), each chunk a multiple of 8 objects.
+static int32_t auto_chunk(int64_t n, int32_t n_ctiles) {
+    int64_t Q = (1024 + n_ctiles - 1) / n_ctiles;
+    const int64_t qmax = (n + 63) / 64;
+    if (Q > qmax) Q = qmax;
+    if (Q < 1) Q = 1;
+    int64_t Lc = (n + Q - 1) / Q;
+    Lc = (Lc + 7) & ~int64_t(7);
+    return (int32_t)Lc;
+}
+
+int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t dtype,
+                int64_t ld, const pamx_options *opt, Layout *L, const void *D) {
+    std::memset(L, 0, sizeof(*L));
+    L->n = n;
+    L->k = k;
+    L->dtype = dtype;
+    L->esz = 4;
+    L->asz = 8;
+    L->ld_fit = (n + 63) & ~int64_t(63);
+    const int64_t ldx = (input_kind == PAMX_INPUT_X) ? L->ld_fit : ld;
+    // 16-byte loads need 4 | ld and a 16-byte aligned matrix
+    const bool aligned = (input_kind == PAMX_INPUT_X) || !D ||
+                         (reinterpret_cast<uintptr_t>(D) & 15) == 0;
+    L->vec = (ldx % 4 == 0 && aligned) ? 4 : 1;
+    L->tile = kWG * L->vec;
+    L->n_ctiles = (int32_t)((n + L->tile - 1) / L->tile);
+    L->ncp = (int64_t)L->n_ctiles * L->tile;
+    int32_t Lc = (opt && opt->chunk > 0) ? opt->chunk : auto_chunk(n, L->n_ctiles);
+    if (Lc > n) Lc = (int32_t)n;
+    L->L = Lc;
+    L->Q = (int32_t)((n + Lc - 1) / Lc);
+    L->n_oblk = (int32_t)((n + kObjBlk - 1) / kObjBlk);
+    L->n_mwg = (int32_t)((n + kWG - 1) / kWG);
+    const bool p2 = opt && opt->variant == PAMX_FASTPAM2;
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = up256(off + (bytes ? bytes : 1)); return o; };
+    L->D = SIZE_MAX;
+    L->Xc = SIZE_MAX;
+    if (input_kind == PAMX_INPUT_X) {
+        L->D = take((size_t)n * (size_t)L->ld_fit * 4);
+        if (dtype == PAMX_F32) L->Xc = take(((size_t)n * dim + dim) * 4);
+    }
+    L->near = take((size_t)n * 4);
+    L->sec = take((size_t)n * 4);
+    L->dn = take((size_t)n * 4);
+    L->ds = take((size_t)n * 4);
+    L->is_med = take((size_t)n);
+    L->srow = take((size_t)n * 4);
+    L->sdn = take((size_t)n * 4);
+    L->sds = take((size_t)n * 4);
+    L->blkcnt = take((size_t)L->n_oblk * k * 4);
+    L->blkbase = take((size_t)L->Q * 16);            // chunk carry map
+    L->seg_off = take((size_t)(k + 1) * 4);
+    L->segc = take((size_t)k * 8);
+    L->part = take((size_t)L->Q * 4 * L->ncp * 8);
+    L->part_i = take((size_t)L->Q * L->ncp * 4);
+    L->cand_v = take(8);
+    L->cand_i = take(8);
+    L->cand_a = take((size_t)L->ncp * 8);
+    L->wg_v = take((size_t)L->n_mwg * 8);
+    L->wg_i = take((size_t)L->n_mwg * 4);
+    L->wg_c = take((size_t)L->n_mwg * 4);
+    L->P = p2 ? take((size_t)k * L->ncp * 8) : SIZE_MAX;
+    L->slot_v = take((size_t)k * 8);
+    L->slot_c = take((size_t)k * 4);
+    L->list = take((size_t)(n > k ? n : k) * 4);
+    L->list_v = take(8);
+    L->list_i = take(8);
+    L->state = take(sizeof(DevState));
+    L->total = off;
+    return PAMX_OK;
+}
+
+}  // namespace pamx
+
+// ---------------------------------------------------------------- validation
+static int check_common(int64_t n, int32_t k, int32_t dtype, const pamx_options *opt) {
+    if (n < 1) return fail(PAMX_ERR_ARG, "n must be >= 1 (got %lld)", (long long)n);
+    if (n > (int64_t)INT32_MAX - 1) return fail(PAMX_ERR_ARG, "n too large for int32 indices");
+    if (k < 1) return fail(PAMX_ERR_ARG, "k must be >= 1 (got %d)", k);
+    if (k > n) return fail(PAMX_ERR_ARG, "k (%d) must not exceed n (%lld)", k, (long long)n);
+    if (k > kMaxK) return fail(PAMX_ERR_ARG, "k (%d) exceeds the supported maximum %d", k, kMaxK);
+    if (dtype != PAMX_I32 && dtype != PAMX_F32)
+        return fail(PAMX_ERR_ARG, "unknown dtype %d", dtype);
+    if (opt) {
+        if (opt->variant != PAMX_FASTPAM1 && opt->variant != PAMX_FASTPAM2)
+            return fail(PAMX_ERR_ARG, "unknown variant %d", opt->variant);
+        if (opt->accum != PAMX_ACC_F64 && opt->accum != PAMX_ACC_F32)
+            return fail(PAMX_ERR_ARG, "unknown accum %d", opt->accum);
+        if (opt->accum == PAMX_ACC_F32 && dtype != PAMX_F32)
+            return fail(PAMX_ERR_ARG, "accum PAMX_ACC_F32 needs PAMX_F32 dissimilarities");
+        if (opt->accum == PAMX_ACC_F32)
+            return fail(PAMX_ERR_UNSUPPORTED, "accum PAMX_ACC_F32 is not available in this build");
+        if (opt->max_iter < 0) return fail(PAMX_ERR_ARG, "max_iter must be >= 0");
+        if (opt->trace_cap < 0) return fail(PAMX_ERR_ARG, "trace_cap must be >= 0");
+        if (opt->chunk < 0) return fail(PAMX_ERR_ARG, "chunk must be >= 0");
+        if (opt->build_exclude_self != 0 && opt->build_exclude_self != 1)
+            return fail(PAMX_ERR_ARG, "build_exclude_self must be 0 or 1");
+    }
+    return PAMX_OK;
+}
+
+static int check_matrix(const void *D, int64_t n, int64_t ld) {
+    if (!D) return fail(PAMX_ERR_ARG, "D is NULL");
+    if (ld < n) return fail(PAMX_ERR_ARG, "ld (%lld) must be >= n (%lld)", (long long)ld, (long long)n);
+    if (ld > (int64_t)1 << 40 || n > ((int64_t)1 << 62) / ld)
+        return fail(PAMX_ERR_ARG, "n * ld overflows");
+    return PAMX_OK;
+}
+
+static int check_ws(void *ws, size_t ws_bytes, const Layout &L) {
+    if (!ws) return fail(PAMX_ERR_WORKSPACE, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return fail(PAMX_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total)
+        return fail(PAMX_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    return PAMX_OK;
+}
+
+extern "C" int pamx_workspace_bytes(int64_t n, int32_t k, int32_t dim, int32_t input_kind,
+                                    int32_t dtype, const pamx_options *opt, size_t *bytes) {
+    if (!bytes) return fail(PAMX_ERR_ARG, "bytes is NULL");
+    int rc = check_common(n, k, dtype, opt);
+    if (rc) return rc;
+    if (input_kind != PAMX_INPUT_D && input_kind != PAMX_INPUT_X)
+        return fail(PAMX_ERR_ARG, "unknown input_kind %d", input_kind);
+    if (input_kind == PAMX_INPUT_X && dim < 1) return fail(PAMX_ERR_ARG, "dim must be >= 1");
+    Layout L;
+    // the pass tiling depends on ld and on the matrix alignment: take the
+    // larger of the 16-byte-load and scalar-load layouts
+    make_layout(n, k, dim, input_kind, dtype, (n + 3) & ~int64_t(3), opt, &L, nullptr);
+    size_t b4 = L.total;
+    make_layout(n, k, dim, input_kind, dtype, (n % 4) ? n : n + 1, opt, &L, nullptr);
+    *bytes = b4 > L.total ? b4 : L.total;
+    return PAMX_OK;
+}
+
+// ---------------------------------------------------------------- distances
+static int dist_impl(const void *X, int32_t dtype, int64_t n, int32_t dim, int32_t metric, void *D,
+                     int64_t ld, hipStream_t s) {
+    if (dtype == PAMX_I32 && metric == PAMX_L1)
+        HIP_TRY(launch_dist_l1_i32(static_cast<const int32_t *>(X), n, dim, static_cast<int32_t *>(D),
+                                   ld, s));
+    else
+        HIP_TRY(launch_dist_l2_f32(static_cast<const float *>(X), n, dim, static_cast<float *>(D), ld,
+                                   s));
+    return PAMX_OK;
+}
+
+static int check_points(const void *X, int32_t dtype, int64_t n, int32_t dim, int32_t metric) {
+    if (!X) return fail(PAMX_ERR_ARG, "X is NULL");
+    if (dim < 1) return fail(PAMX_ERR_ARG, "dim must be >= 1 (got %d)", dim);
+    if (metric != PAMX_L1 && metric != PAMX_L2) return fail(PAMX_ERR_ARG, "unknown metric %d", metric);
+    if (dtype == PAMX_I32 && metric != PAMX_L1)
+        return fail(PAMX_ERR_UNSUPPORTED, "int32 points support the L1 metric only");
+    if (dtype == PAMX_F32 && metric != PAMX_L2)
+        return fail(PAMX_ERR_UNSUPPORTED, "float32 points support the L2 metric only");
+    return PAMX_OK;
+}
+
+extern "C" int pamx_dist(const void *X, int32_t dtype, int64_t n, int32_t dim, int32_t metric,
+                         void *D, int64_t ld, void *stream) {
+    if (n < 1) return fail(PAMX_ERR_ARG, "n must be >= 1");
+    if (dtype != PAMX_I32 && dtype != PAMX_F32) return fail(PAMX_ERR_ARG, "unknown dtype %d", dtype);
+    int rc = check_points(X, dtype, n, dim, metric);
+    if (rc) return rc;
+    rc = check_matrix(D, n, ld);
+    if (rc) return rc;
+    if (ld % 4) return fail(PAMX_ERR_ARG, "ld must be a multiple of 4");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = dist_impl(X, dtype, n, dim, metric, D, ld, s);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    return PAMX_OK;
+}
+
+// ---------------------------------------------------------------- BUILD / SWAP
+namespace {
+
+struct Timer {
+    hipEvent_t e[6];
+    bool ok = false;
+    Timer() {
+        ok = true;
+        for (auto &x : e)
+            if (hipEventCreate(&x) != hipSuccess) ok = false;
+    }
+    ~Timer() {
+        for (auto &x : e) (void)hipEventDestroy(x);
+    }
+    void rec(int i, hipStream_t s) {
+        if (ok) (void)hipEventRecord(e[i], s);
+    }
+    double ms(int a, int b) {
+        float v = 0.f;
+        if (ok && hipEventElapsedTime(&v, e[a], e[b]) == hipSuccess) return v;
+        return 0.0;
+    }
+};
+
+int read_state(const Layout &L, void *ws, hipStream_t s, DevState *out) {
+    const char *w = static_cast<const char *>(ws);
+    HIP_TRY(hipMemcpyAsync(out, w + L.state, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PAMX_OK;
+}
+
+template <typename T>
+int build_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const pamx_options &opt,
+               int32_t *medoids, double *td, void *ws, hipStream_t s) {
+    HIP_TRY(run_build<T>(D, ld, L, k, opt.build_exclude_self, medoids, ws, s));
+    DevState st;
+    int rc = read_state(L, ws, s, &st);
+    if (rc) return rc;
+    if (st.bad_medoids) return fail(PAMX_ERR_HIP, "BUILD found no candidate");
+    if (td) *td = st.td;
+    return PAMX_OK;
+}
+
+template <typename T>
+int swap_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const pamx_options &opt,
+              int32_t *medoids, int32_t *labels, double *td, pamx_stats *stats, void *ws,
+              hipStream_t s, Timer &tm) {
+    const int64_t n = L.n;
+    HIP_TRY(enqueue_swap_init<T>(D, ld, L, medoids, opt, ws, s));
+    DevState st;
+    int rc = read_state(L, ws, s, &st);
+    if (rc) return rc;
+    if (st.bad_medoids)
+        return fail(PAMX_ERR_INVALID_MEDOIDS, "medoids must be distinct and in [0, n)");
+    tm.rec(2, s);
+    int enq = 0;
+    if (k >= 2 && k < n) {
+        HIP_TRY(enqueue_swap_caches<T>(D, ld, L, medoids, ws, s));
+        int batch = 4;
+        for (;;) {
+            int b = batch;
+            if (b > opt.max_iter + 1 - enq) b = opt.max_iter + 1 - enq;
+            if (b < 1) b = 1;
+            for (int j = 0; j < b; ++j) HIP_TRY(enqueue_swap_iteration<T>(D, ld, L, medoids, opt, ws, s));
+            enq += b;
+            rc = read_state(L, ws, s, &st);
+            if (rc) return rc;
+            if (st.done) break;
+            if (batch < 32) batch *= 2;
+        }
+    }
+    tm.rec(3, s);
+    HIP_TRY(enqueue_finalize<T>(D, ld, L, medoids, labels, ws, s));
+    rc = read_state(L, ws, s, &st);
+    if (rc) return rc;
+    if (td) *td = st.td;
+    if (stats) {
+        stats->iterations = st.iter;
+        stats->swaps = st.swaps;
+        stats->converged = (k >= 2 && k < n) ? (st.done && !st.capped) : 1;
+        stats->rescored = st.rescored;
+        stats->td = st.td;
+        stats->pass_pairs = (int64_t)st.iter * n * (n - k);
+    }
+    return st.capped ? PAMX_WARN_MAXITER : PAMX_OK;
+}
+
+}  // namespace
+
+static int swap_args(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                     const pamx_options *opt, const int32_t *medoids) {
+    int rc = check_common(n, k, dtype, opt);
+    if (rc) return rc;
+    rc = check_matrix(D, n, ld);
+    if (rc) return rc;
+    if (!medoids) return fail(PAMX_ERR_ARG, "medoids is NULL");
+    if (opt && opt->trace_cap > 0 && !opt->trace)
+        return fail(PAMX_ERR_ARG, "trace_cap > 0 needs a trace array");
+    return PAMX_OK;
+}
+
+extern "C" int pamx_build(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                          const pamx_options *opt_in, int32_t *medoids, double *td, void *ws,
+                          size_t ws_bytes, void *stream) {
+    pamx_options opt;
+    pamx_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    int rc = swap_args(D, dtype, n, ld, k, &opt, medoids);
+    if (rc) return rc;
+    Layout L;
+    make_layout(n, k, 0, PAMX_INPUT_D, dtype, ld, &opt, &L, D);
+    rc = check_ws(ws, ws_bytes, L);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == PAMX_F32)
+        return build_impl<float>(static_cast<const float *>(D), ld, L, k, opt, medoids, td, ws, s);
+    return build_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, opt, medoids, td, ws, s);
+}
+
+extern "C" int pamx_swap(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                         const pamx_options *opt_in, int32_t *medoids, int32_t *labels, double *td,
+                         pamx_stats *stats, void *ws, size_t ws_bytes, void *stream) {
+    pamx_options opt;
+    pamx_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    int rc = swap_args(D, dtype, n, ld, k, &opt, medoids);
+    if (rc) return rc;
+    Layout L;
+    make_layout(n, k, 0, PAMX_INPUT_D, dtype, ld, &opt, &L, D);
+    rc = check_ws(ws, ws_bytes, L);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    Timer tm;
+    tm.rec(0, s);
+    if (dtype == PAMX_F32)
+        rc = swap_impl<float>(static_cast<const float *>(D), ld, L, k, opt, medoids, labels, td,
+                              stats, ws, s, tm);
+    else
+        rc = swap_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, opt, medoids, labels, td,
+                                stats, ws, s, tm);
+    if (rc < 0) return rc;
+    tm.rec(4, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(PAMX_ERR_HIP, "stream synchronize failed");
+    if (stats) {
+        stats->ms_swap = tm.ms(2, 3);
+        stats->ms_total = tm.ms(0, 4);
+    }
+    return rc;
+}
+
+extern "C" int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int64_t n, int32_t dim,
+                        int32_t metric, int32_t k, const pamx_options *opt_in, int32_t *medoids,
+                        int32_t *labels, double *td, pamx_stats *stats, void *ws, size_t ws_bytes,
+                        void *stream) {
+    pamx_options opt;
+    pamx_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    int rc = check_common(n, k, dtype, &opt);
+    if (rc) return rc;
+    if (input_kind != PAMX_INPUT_D && input_kind != PAMX_INPUT_X)
+        return fail(PAMX_ERR_ARG, "unknown input_kind %d", input_kind);
+    if (input_kind == PAMX_INPUT_X) {
+        rc = check_points(XorD, dtype, n, dim, metric);
+        if (rc) return rc;
+    } else {
+        rc = check_matrix(XorD, n, n);
+        if (rc) return rc;
+    }
+    if (!medoids) return fail(PAMX_ERR_ARG, "medoids is NULL");
+    if (opt.trace_cap > 0 && !opt.trace) return fail(PAMX_ERR_ARG, "trace_cap > 0 needs a trace array");
+    Layout L;
+    make_layout(n, k, dim, input_kind, dtype, n, &opt, &L,
+                input_kind == PAMX_INPUT_D ? XorD : nullptr);
+    rc = check_ws(ws, ws_bytes, L);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    Timer tm;
+    tm.rec(0, s);
+    const void *D = XorD;
+    int64_t ld = n;
+    if (input_kind == PAMX_INPUT_X) {
+        char *w = static_cast<char *>(ws);
+        void *Dw = w + L.D;
+        ld = L.ld_fit;
+        const void *Xuse = XorD;
+        if (dtype == PAMX_F32) {
+            float *Xc = reinterpret_cast<float *>(w + L.Xc);
+            HIP_TRY(launch_center_f32(static_cast<const float *>(XorD), n, dim, Xc, s));
+            Xuse = Xc;
+        }
+        rc = dist_impl(Xuse, dtype, n, dim, metric, Dw, ld, s);
+        if (rc) return rc;
+        D = Dw;
+    }
+    tm.rec(1, s);
+    double td_build = 0.0;
+    if (dtype == PAMX_F32)
+        rc = build_impl<float>(static_cast<const float *>(D), ld, L, k, opt, medoids, &td_build, ws, s);
+    else
+        rc = build_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, opt, medoids, &td_build, ws, s);
+    if (rc) return rc;
+    if (dtype == PAMX_F32)
+        rc = swap_impl<float>(static_cast<const float *>(D), ld, L, k, opt, medoids, labels, td, stats,
+                              ws, s, tm);
+    else
+        rc = swap_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, opt, medoids, labels, td,
+                                stats, ws, s, tm);
+    if (rc < 0) return rc;
+    tm.rec(4, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(PAMX_ERR_HIP, "stream synchronize failed");
+    if (stats) {
+        stats->td_build = td_build;
+        stats->ms_dist = tm.ms(0, 1);
+        stats->ms_build = tm.ms(1, 2);
+        stats->ms_swap = tm.ms(2, 3);
+        stats->ms_total = tm.ms(0, 4);
+        stats->build_pairs = (int64_t)k * n * n;
+    }
+    return rc;
+}

@@ -1,0 +1,123 @@
+// pamx_internal.h -- shared declarations of the gfx950 k-medoids library:
+// device state, workspace layout, value traits and small device helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <climits>
+#include <cmath>
+
+#include "pamx.h"
+
+namespace pamx {
+
+constexpr int kWG = 256;          // threads per work-group in pass kernels
+constexpr int kObjBlk = 256;      // objects per block in segment kernels
+constexpr int kMaxK = 16384;      // largest k accepted (slot histogram in LDS)
+
+// Accumulator and "infinity" per element type.  Integer dissimilarities are
+// summed exactly in int64; float32 ones in FP64 (or FP32 with re-scoring).
+template <typename T> struct VT;
+template <> struct VT<float> {
+    using acc = double;
+    __host__ __device__ static constexpr float inf() { return __builtin_huge_valf(); }
+    __host__ __device__ static constexpr double acc_inf() { return __builtin_huge_val(); }
+};
+template <> struct VT<int32_t> {
+    using acc = long long;
+    __host__ __device__ static constexpr int32_t inf() { return INT_MAX; }
+    __host__ __device__ static constexpr long long acc_inf() { return LLONG_MAX; }
+};
+
+// Device-resident state of one BUILD or SWAP run.  Every iteration kernel
+// reads `done` first and returns at once when it is set, so the host can
+// enqueue several iterations ahead and poll rarely.
+struct alignas(64) DevState {
+    int32_t iter;        // SWAP searches performed
+    int32_t swaps;       // swaps applied
+    int32_t done;        // converged or capped: later iteration kernels idle
+    int32_t capped;      // max_iter reached
+    int32_t max_iter;
+    int32_t empty_slot;  // smallest slot without assigned objects, or k
+    int32_t swapped;     // this iteration applied a FastPAM1 swap
+    int32_t new_slot;    // slot replaced this iteration
+    int32_t new_med;     // object that became the medoid
+    int32_t old_med;     // object that stopped being a medoid
+    int32_t bad_medoids; // input medoids duplicated or out of range
+    int32_t trace_cap;
+    int32_t rescored;    // candidates scored again in FP64
+    int32_t n_list;      // length of the re-score list
+    int32_t best_i, best_c;
+    double best_v;       // FP64 best change (float path)
+    long long best_vi;   // int64 best change (int path)
+    double td;           // running TD (float path)
+    long long td_i;      // running TD (int path)
+    double margin;       // FP32 error bound used for re-scoring
+    double f32_best;     // FP32 best change before re-scoring
+};
+
+// Lexicographic "a is better than b" on (value, slot, candidate).
+template <typename A>
+__device__ __forceinline__ bool lex_less(A va, int ia, int ca, A vb, int ib, int cb) {
+    if (va != vb) return va < vb;
+    if (ia != ib) return ia < ib;
+    return ca < cb;
+}
+
+// Workspace layout (byte offsets, 256-aligned) for one (n, k, dtype) run.
+struct Layout {
+    int64_t n;
+    int32_t k;
+    int32_t dtype;
+    int32_t vec;         // candidates per lane in pass kernels (4, or 1 if ld % 4)
+    int32_t tile;        // candidates per pass work-group = kWG * vec
+    int32_t n_ctiles;    // candidate tiles
+    int32_t L;           // objects per pass work-group (chunk)
+    int32_t Q;           // object chunks
+    int64_t ncp;         // padded candidate count = n_ctiles * tile
+    int32_t n_oblk;      // object blocks of kObjBlk
+    int32_t n_mwg;       // merge work-groups = ceil(n / kWG)
+    size_t esz;          // element size of D (4)
+    size_t asz;          // accumulator size (8)
+    // offsets
+    size_t D;            // stored matrix (pamx_fit with points), or SIZE_MAX
+    size_t Xc;           // centred copy of points (L2 fit), or SIZE_MAX
+    size_t near, sec, dn, ds, is_med;
+    size_t srow, sdn, sds;
+    size_t blkcnt, blkbase, seg_off, segc;
+    size_t part, part_i;
+    size_t cand_v, cand_i, cand_a;
+    size_t wg_v, wg_i, wg_c;
+    size_t P, slot_v, slot_c;
+    size_t list, list_v, list_i;
+    size_t state;
+    size_t total;
+    int64_t ld_fit;      // row stride of the stored matrix in pamx_fit
+};
+
+// host helpers (pamx_api.cpp)
+int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t dtype,
+                int64_t ld, const pamx_options *opt, Layout *L, const void *D);
+
+// launchers (one per kernel family); each returns hipSuccess or an error.
+hipError_t launch_dist_l1_i32(const int32_t *X, int64_t n, int32_t dim, int32_t *D, int64_t ld,
+                              hipStream_t s);
+hipError_t launch_center_f32(const float *X, int64_t n, int32_t dim, float *Xc, hipStream_t s);
+hipError_t launch_dist_l2_f32(const float *X, int64_t n, int32_t dim, float *D, int64_t ld,
+                              hipStream_t s);
+
+template <typename T>
+hipError_t run_build(const T *D, int64_t ld, const Layout &L, int32_t k, int32_t exclude_self,
+                     int32_t *medoids, void *ws, hipStream_t s);
+
+template <typename T>
+hipError_t enqueue_swap_init(const T *D, int64_t ld, const Layout &L, const int32_t *medoids,
+                             const pamx_options &opt, void *ws, hipStream_t s);
+template <typename T>
+hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32_t *medoids,
+                                  const pamx_options &opt, void *ws, hipStream_t s);
+template <typename T>
+hipError_t enqueue_finalize(const T *D, int64_t ld, const Layout &L, const int32_t *medoids,
+                            int32_t *labels, void *ws, hipStream_t s);
+
+}  // namespace pamx

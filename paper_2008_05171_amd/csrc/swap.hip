@@ -1,0 +1,995 @@
+// swap.hip -- BUILD and SWAP kernels for gfx950.
+//
+// Paper: Schubert & Rousseeuw, "Fast and Eager k-Medoids Clustering",
+// arXiv 2008.05171.  Notation: nearest(o), dn(o), ds(o) are the slot of and
+// the distances to o's nearest and second-nearest medoid (Sec. 2).
+//
+// Loss change of swapping slot i with candidate c (Eq. better-change3):
+//     Delta(i, c) = R_i + B(c) + S_i(c)
+//     R_i  = sum_{nearest(o)=i} (ds - dn)                   removal loss
+//     B(c) = sum_o min(d(o,c) - dn, 0)                      shared term
+//     S_i  = sum_{nearest(o)=i} (med3(d(o,c), dn, ds) - ds) per-medoid term
+// (med3(d, dn, ds) - ds is the three-way case of the paper's last sum, as
+// dn <= ds).  For exact sums it is regrouped here into sums of non-negative
+// terms that need no subtraction per pair:
+//     B(c)            = A(c) - TD,        A(c)   = sum_o min(d(o,c), dn(o))
+//     R_i + S_i(c)    = M_i(c) - DN_i,    M_i(c) = sum_{nearest(o)=i} med3(d, dn, ds)
+//                                          DN_i   = sum_{nearest(o)=i} dn(o)
+// so one pair costs min, med3 and two adds.
+//
+// Layout of the hot pass: objects are sorted by nearest slot (a stable
+// counting sort), so the per-medoid sums M_i are segment sums over
+// consecutive objects.  A work-group owns a tile of candidates (4 per lane,
+// one 16-byte load of D per object) and a chunk of sorted objects; for each
+// object it reads the contiguous candidate slice of row o of D (D symmetric,
+// so row o holds d(o, c) for all c).  Per-object cache values are wave
+// uniform.  Segments cut by a chunk edge leave partial sums ("carries") that
+// a merge kernel adds in chunk order: every sum is formed in a fixed order,
+// so results are deterministic.
+#include "pamx_internal.h"
+
+namespace pamx {
+
+template <typename T> using AccT = typename VT<T>::acc;
+
+// ---------------------------------------------------------------- helpers
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = f32x4; };
+template <> struct Vec4<int32_t> { using type = i32x4; };
+
+template <typename T, int VEC>
+__device__ __forceinline__ void load_vec(const T *__restrict__ p, T (&v)[VEC]) {
+    if constexpr (VEC == 4) {
+        const auto q = __builtin_nontemporal_load(reinterpret_cast<const typename Vec4<T>::type *>(p));
+        v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; v[3] = q[3];
+    } else {
+        v[0] = __builtin_nontemporal_load(p);
+    }
+}
+
+__device__ __forceinline__ float vmin(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ int32_t vmin(int32_t a, int32_t b) { return min(a, b); }
+// median of (d, lo, hi) for lo <= hi
+__device__ __forceinline__ float vmed3(float d, float lo, float hi) {
+    return __builtin_amdgcn_fmed3f(d, lo, hi);
+}
+__device__ __forceinline__ int32_t vmed3(int32_t d, int32_t lo, int32_t hi) {
+    return max(lo, min(d, hi));
+}
+
+// lexicographic (value, index) "a < b"
+template <typename A>
+__device__ __forceinline__ bool lt2(A va, int ia, A vb, int ib) {
+    return va < vb || (va == vb && ia < ib);
+}
+
+// Block-wide lexicographic argmin over (v, i, c); result in thread 0.
+template <typename A, int NT>
+__device__ void block_argmin3(A &v, int &i, int &c) {
+    __shared__ A sv[NT];
+    __shared__ int si[NT], sc[NT];
+    const int t = threadIdx.x;
+    sv[t] = v; si[t] = i; sc[t] = c;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (t < w && lex_less(sv[t + w], si[t + w], sc[t + w], sv[t], si[t], sc[t])) {
+            sv[t] = sv[t + w]; si[t] = si[t + w]; sc[t] = sc[t + w];
+        }
+        __syncthreads();
+    }
+    v = sv[0]; i = si[0]; c = sc[0];
+    __syncthreads();
+}
+
+// Block-wide sum in a fixed tree order; result returned to every thread.
+template <typename A, int NT>
+__device__ A block_sum(A x) {
+    __shared__ A s[NT];
+    const int t = threadIdx.x;
+    s[t] = x;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (t < w) s[t] += s[t + w];
+        __syncthreads();
+    }
+    const A r = s[0];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------- fills
+template <typename X>
+__global__ __launch_bounds__(256) void k_fill(X *__restrict__ p, int64_t cnt, X v) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < cnt) p[t] = v;
+}
+template <typename X>
+static void fill(X *p, int64_t cnt, X v, hipStream_t s) {
+    if (cnt <= 0) return;
+    hipLaunchKernelGGL(k_fill<X>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, p, cnt, v);
+}
+
+__global__ void k_state_init(DevState *st, int32_t max_iter, int32_t trace_cap) {
+    if (threadIdx.x == 0) {
+        DevState z{};
+        z.max_iter = max_iter;
+        z.trace_cap = trace_cap;
+        z.best_i = -1;
+        z.best_c = -1;
+        *st = z;
+    }
+}
+
+// ================================================================ BUILD (Alg. 1)
+// A(c) = sum_o min(D[o][c], dn(o)) for every candidate c, one partial per
+// object chunk.  Step 0 runs with dn = +inf, giving the column sums.  The
+// candidate's own row contributes min(0, dn(c)) = 0, so A(c) - TD is the full
+// TD change of adding c (self-term included); medoids have dn = 0 and add 0.
+template <typename T, int VEC>
+__global__ __launch_bounds__(kWG) void k_build_pass(const T *__restrict__ D, int64_t ld, int64_t n,
+                                                    const T *__restrict__ dn, int32_t L,
+                                                    int64_t ncp, AccT<T> *__restrict__ part) {
+    using A = AccT<T>;
+    constexpr int U = 8;
+    const int64_t a = (int64_t)blockIdx.y * L;
+    const int64_t b = min(a + (int64_t)L, n);
+    const int64_t c0 = ((int64_t)blockIdx.x * kWG + threadIdx.x) * VEC;
+    A acc[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[e] = 0;
+    if (c0 < n) {
+        int64_t o = a;
+        for (; o + U <= b; o += U) {
+            T v[U][VEC];
+            T m[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                load_vec<T, VEC>(D + (o + u) * ld + c0, v[u]);
+                m[u] = dn[o + u];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc[e] += (A)vmin(v[u][e], m[u]);
+        }
+        for (; o < b; ++o) {
+            T v[VEC];
+            load_vec<T, VEC>(D + o * ld + c0, v);
+            const T m = dn[o];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[e] += (A)vmin(v[e], m);
+        }
+    }
+    A *dst = part + (int64_t)blockIdx.y * ncp + c0;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) dst[e] = acc[e];
+}
+
+// Sum the chunk partials of each candidate (chunk order) and reduce the
+// work-group's best (value, candidate) among non-medoids.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_build_merge(const AccT<T> *__restrict__ part, int32_t Q,
+                                                     int64_t ncp, int64_t n,
+                                                     const T *__restrict__ dn,
+                                                     const uint8_t *__restrict__ is_med,
+                                                     int32_t add_self, AccT<T> *__restrict__ wg_v,
+                                                     int32_t *__restrict__ wg_c) {
+    using A = AccT<T>;
+    const int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    A v = VT<T>::acc_inf();
+    int ci = INT_MAX;
+    if (c < n && !is_med[c]) {
+        A s = 0;
+        for (int q = 0; q < Q; ++q) s += part[(int64_t)q * ncp + c];
+        if (add_self) s += (A)dn[c];   // literal Alg. 1: x_c's own gain not counted
+        v = s;
+        ci = (int)c;
+    }
+    int dummy = 0;
+    block_argmin3<A, kWG>(v, dummy, ci);
+    if (threadIdx.x == 0) {
+        wg_v[blockIdx.x] = v;
+        wg_c[blockIdx.x] = ci;
+    }
+}
+
+// Pick the step's medoid: the smallest change, smallest index on ties.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_build_select(const AccT<T> *__restrict__ wg_v,
+                                                       const int32_t *__restrict__ wg_c, int32_t nwg,
+                                                       int32_t t, int32_t *__restrict__ medoids,
+                                                       uint8_t *__restrict__ is_med,
+                                                       DevState *__restrict__ st) {
+    using A = AccT<T>;
+    A v = VT<T>::acc_inf();
+    int c = INT_MAX, dummy = 0;
+    for (int w = threadIdx.x; w < nwg; w += 1024) {
+        if (lex_less(wg_v[w], 0, wg_c[w], v, 0, c)) { v = wg_v[w]; c = wg_c[w]; }
+    }
+    block_argmin3<A, 1024>(v, dummy, c);
+    if (threadIdx.x == 0) {
+        st->best_c = c;
+        if (c != INT_MAX) {
+            medoids[t] = c;
+            is_med[c] = 1;
+        } else {
+            st->bad_medoids = 1;  // no candidate left (cannot happen for k <= n)
+        }
+    }
+}
+
+// dn(o) <- min(dn(o), d(o, m_t)), reading row m_t (= column m_t).
+template <typename T>
+__global__ __launch_bounds__(256) void k_build_update(const T *__restrict__ D, int64_t ld, int64_t n,
+                                                      T *__restrict__ dn, const DevState *__restrict__ st,
+                                                      int32_t first) {
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int c = st->best_c;
+    if (o >= n || c == INT_MAX) return;
+    const T d = D[(int64_t)c * ld + o];
+    dn[o] = first ? d : vmin(dn[o], d);
+}
+
+// TD = sum_o dn(o) in a fixed order (single work-group).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_td_sum(const T *__restrict__ dn, int64_t n,
+                                                 DevState *__restrict__ st) {
+    using A = AccT<T>;
+    A s = 0;
+    for (int64_t o = threadIdx.x; o < n; o += 1024) s += (A)dn[o];
+    s = block_sum<A, 1024>(s);
+    if (threadIdx.x == 0) {
+        if constexpr (sizeof(T) == 4 && std::is_same<T, float>::value) st->td = s;
+        else { st->td_i = s; st->td = (double)s; }
+    }
+}
+
+template <typename T>
+hipError_t run_build(const T *D, int64_t ld, const Layout &L, int32_t k, int32_t exclude_self,
+                     int32_t *medoids, void *ws, hipStream_t s) {
+    using A = AccT<T>;
+    char *w = static_cast<char *>(ws);
+    const int64_t n = L.n;
+    T *dn = reinterpret_cast<T *>(w + L.dn);
+    uint8_t *is_med = reinterpret_cast<uint8_t *>(w + L.is_med);
+    A *part = reinterpret_cast<A *>(w + L.part);
+    A *wg_v = reinterpret_cast<A *>(w + L.wg_v);
+    int32_t *wg_c = reinterpret_cast<int32_t *>(w + L.wg_c);
+    DevState *st = reinterpret_cast<DevState *>(w + L.state);
+
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, 0, 0);
+    fill<uint8_t>(is_med, n, 0, s);
+    fill<T>(dn, n, VT<T>::inf(), s);
+    const dim3 pgrid(L.n_ctiles, L.Q);
+    for (int32_t t = 0; t < k; ++t) {
+        if (L.vec == 4)
+            hipLaunchKernelGGL((k_build_pass<T, 4>), pgrid, dim3(kWG), 0, s, D, ld, n,
+                               (const T *)dn, L.L, L.ncp, part);
+        else
+            hipLaunchKernelGGL((k_build_pass<T, 1>), pgrid, dim3(kWG), 0, s, D, ld, n,
+                               (const T *)dn, L.L, L.ncp, part);
+        hipLaunchKernelGGL(k_build_merge<T>, dim3(L.n_mwg), dim3(kWG), 0, s, (const A *)part, L.Q,
+                           L.ncp, n, (const T *)dn, (const uint8_t *)is_med,
+                           (int32_t)(exclude_self && t > 0), wg_v, wg_c);
+        hipLaunchKernelGGL(k_build_select<T>, dim3(1), dim3(1024), 0, s, (const A *)wg_v,
+                           (const int32_t *)wg_c, L.n_mwg, t, medoids, is_med, st);
+        hipLaunchKernelGGL(k_build_update<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           D, ld, n, dn, (const DevState *)st, (int32_t)(t == 0));
+    }
+    hipLaunchKernelGGL(k_td_sum<T>, dim3(1), dim3(1024), 0, s, (const T *)dn, n, st);
+    return hipGetLastError();
+}
+
+// ================================================================ SWAP (Alg. 3)
+// ---- nearest / second nearest of every object (O(nk), rows of the medoids)
+// Order on (distance, slot) is lexicographic: nearest is the smallest slot at
+// the minimum distance and ds the minimum over the other slots.
+template <typename T>
+__device__ __forceinline__ void scan_medoids(const T *__restrict__ D, int64_t ld, int k,
+                                             const int32_t *__restrict__ med, int64_t o,
+                                             int32_t &nr, int32_t &sc, T &dn, T &ds) {
+    nr = -1; sc = -1;
+    dn = VT<T>::inf(); ds = VT<T>::inf();
+    for (int j = 0; j < k; ++j) {
+        const T d = D[(int64_t)med[j] * ld + o];
+        if (nr < 0 || d < dn) {
+            sc = nr; ds = dn;
+            nr = j; dn = d;
+        } else if (sc < 0 || d < ds) {
+            sc = j; ds = d;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cache_init(const T *__restrict__ D, int64_t ld, int64_t n,
+                                                    int32_t k, const int32_t *__restrict__ med,
+                                                    int32_t *__restrict__ near,
+                                                    int32_t *__restrict__ sec, T *__restrict__ dn,
+                                                    T *__restrict__ ds, int32_t *__restrict__ labels) {
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= n) return;
+    int32_t nr, sc;
+    T a, b;
+    scan_medoids<T>(D, ld, k, med, o, nr, sc, a, b);
+    near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b;
+    if (labels) labels[o] = nr;
+}
+
+// Input check: medoids distinct and in range (uses `mark` zeroed beforehand).
+__global__ __launch_bounds__(256) void k_check_medoids(const int32_t *__restrict__ med, int32_t k,
+                                                       int64_t n, int32_t *__restrict__ mark,
+                                                       uint8_t *__restrict__ is_med,
+                                                       DevState *__restrict__ st) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= k) return;
+    const int32_t m = med[j];
+    if (m < 0 || (int64_t)m >= n) { atomicOr(&st->bad_medoids, 1); return; }
+    if (atomicAdd(&mark[m], 1) != 0) atomicOr(&st->bad_medoids, 1);
+    is_med[m] = 1;
+}
+
+// ---- per-object cache update after slot `slot` received medoid `c`.
+// Objects that keep both nearest and second medoid only compare against the
+// new one; objects that lost one of them scan all k medoids again.
+template <typename T>
+__device__ __forceinline__ void cache_update_one(const T *__restrict__ D, int64_t ld, int k,
+                                                 const int32_t *__restrict__ med, int64_t o, int slot,
+                                                 T dnew, int32_t &nr, int32_t &sc, T &dn, T &ds) {
+    if (nr == slot || sc == slot) {
+        scan_medoids<T>(D, ld, k, med, o, nr, sc, dn, ds);
+    } else if (lt2(dnew, slot, dn, nr)) {
+        sc = nr; ds = dn;
+        nr = slot; dn = dnew;
+    } else if (lt2(dnew, slot, ds, sc)) {
+        sc = slot; ds = dnew;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cache_update(const T *__restrict__ D, int64_t ld, int64_t n,
+                                                      int32_t k, const int32_t *__restrict__ med,
+                                                      int32_t *__restrict__ near,
+                                                      int32_t *__restrict__ sec, T *__restrict__ dn,
+                                                      T *__restrict__ ds,
+                                                      const DevState *__restrict__ st) {
+    if (st->done || !st->swapped) return;
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= n) return;
+    const int slot = st->new_slot;
+    const T dnew = D[(int64_t)st->new_med * ld + o];
+    int32_t nr = near[o], sc = sec[o];
+    T a = dn[o], b = ds[o];
+    cache_update_one<T>(D, ld, k, med, o, slot, dnew, nr, sc, a, b);
+    near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b;
+}
+
+// ---- iteration start: iteration cap
+__global__ void k_iter_begin(DevState *st) {
+    if (threadIdx.x != 0 || st->done) return;
+    st->swapped = 0;
+    if (st->iter >= st->max_iter) {
+        st->done = 1;
+        st->capped = 1;
+    }
+}
+
+// ---- stable counting sort of objects by nearest slot
+__global__ __launch_bounds__(kObjBlk) void k_seg_count(const int32_t *__restrict__ near, int64_t n,
+                                                       int32_t k, int32_t *__restrict__ blkcnt,
+                                                       const DevState *__restrict__ st) {
+    if (st->done) return;
+    extern __shared__ int32_t hist[];
+    for (int i = threadIdx.x; i < k; i += kObjBlk) hist[i] = 0;
+    __syncthreads();
+    const int64_t o = (int64_t)blockIdx.x * kObjBlk + threadIdx.x;
+    if (o < n) atomicAdd(&hist[near[o]], 1);
+    __syncthreads();
+    int32_t *dst = blkcnt + (int64_t)blockIdx.x * k;
+    for (int i = threadIdx.x; i < k; i += kObjBlk) dst[i] = hist[i];
+}
+
+struct ChunkInfo {
+    int32_t sa, sb, flags;  // segment of the first / last object, carry flags
+};
+constexpr int kHead = 1, kTail = 2;
+
+// Per-slot totals, block bases, segment offsets, the smallest empty slot,
+// TD and sum of ds (for the rounding bound), and the carry map of every chunk.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_seg_scan(int32_t *__restrict__ blkcnt, int32_t nblk,
+                                                   int32_t k, int64_t n, int32_t *__restrict__ seg_off,
+                                                   const T *__restrict__ dn, const T *__restrict__ ds,
+                                                   int32_t L, int32_t Q, ChunkInfo *__restrict__ cinfo,
+                                                   DevState *__restrict__ st) {
+    using A = AccT<T>;
+    if (st->done) return;
+    __shared__ int32_t carry;
+    __shared__ int32_t empty_min;
+    const int t = threadIdx.x;
+    if (t == 0) { carry = 0; empty_min = k; }
+    // totals per slot (reuse seg_off[i+1] as the total, then scan)
+    for (int i = t; i < k; i += 1024) {
+        int32_t run = 0;
+        for (int b = 0; b < nblk; ++b) {
+            const int32_t c = blkcnt[(int64_t)b * k + i];
+            blkcnt[(int64_t)b * k + i] = run;  // exclusive prefix over blocks
+            run += c;
+        }
+        seg_off[i + 1] = run;
+        if (run == 0) atomicMin(&empty_min, i);
+    }
+    __syncthreads();
+    // exclusive scan of totals, 1024 at a time
+    __shared__ int32_t buf[1024];
+    for (int base = 0; base < k; base += 1024) {
+        const int i = base + t;
+        const int32_t v = (i < k) ? seg_off[i + 1] : 0;
+        buf[t] = v;
+        __syncthreads();
+        for (int w = 1; w < 1024; w <<= 1) {
+            const int32_t x = (t >= w) ? buf[t - w] : 0;
+            __syncthreads();
+            buf[t] += x;
+            __syncthreads();
+        }
+        if (i < k) seg_off[i + 1] = carry + buf[t];   // inclusive
+        __syncthreads();
+        if (t == 1023) carry += buf[1023];
+        __syncthreads();
+    }
+    if (t == 0) seg_off[0] = 0;
+    __syncthreads();
+    // add segment starts to the block bases
+    for (int i = t; i < k; i += 1024) {
+        const int32_t s0 = seg_off[i];
+        for (int b = 0; b < nblk; ++b) blkcnt[(int64_t)b * k + i] += s0;
+    }
+    // TD and sum of ds, fixed order
+    A s1 = 0, s2 = 0;
+    for (int64_t o = t; o < n; o += 1024) { s1 += (A)dn[o]; s2 += (A)ds[o]; }
+    s1 = block_sum<A, 1024>(s1);
+    s2 = block_sum<A, 1024>(s2);
+    __syncthreads();
+    // carry map of each chunk
+    for (int q = t; q < Q; q += 1024) {
+        const int64_t a = (int64_t)q * L, b = min(a + (int64_t)L, n);
+        int lo = 0, hi = k;
+        while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (seg_off[m] <= a) lo = m; else hi = m; }
+        const int sa = lo;
+        lo = 0; hi = k;
+        while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (seg_off[m] <= b - 1) lo = m; else hi = m; }
+        const int sb = lo;
+        int f = 0;
+        if (seg_off[sa] < a || seg_off[sa + 1] > b) f |= kHead;
+        if (sb != sa && seg_off[sb + 1] > b) f |= kTail;
+        cinfo[q] = ChunkInfo{sa, sb, f};
+    }
+    if (t == 0) {
+        st->empty_slot = empty_min;
+        if constexpr (std::is_same<T, float>::value) {
+            st->td = s1;
+            // bound on the FP64 rounding of a computed change: every partial
+            // sum is <= sum(ds), chains are at most n + Q + 64 additions long
+            st->margin = 4.0 * ((double)n + Q + 68) * 0x1p-53 * (double)s2;
+        } else {
+            st->td_i = s1;
+            st->td = (double)s1;
+            st->margin = 0.0;
+        }
+    }
+}
+
+// Scatter objects to their sorted position: block base + rank among the
+// block's objects of the same slot (stable).
+template <typename T>
+__global__ __launch_bounds__(kObjBlk) void k_seg_scatter(const int32_t *__restrict__ near,
+                                                         const T *__restrict__ dn,
+                                                         const T *__restrict__ ds, int64_t n,
+                                                         int32_t k, const int32_t *__restrict__ blkbase,
+                                                         int32_t *__restrict__ srow,
+                                                         T *__restrict__ sdn, T *__restrict__ sds,
+                                                         const DevState *__restrict__ st) {
+    if (st->done) return;
+    __shared__ int32_t ln[kObjBlk];
+    const int t = threadIdx.x;
+    const int64_t o = (int64_t)blockIdx.x * kObjBlk + t;
+    const int32_t s = (o < n) ? near[o] : -1;
+    ln[t] = s;
+    __syncthreads();
+    if (o >= n) return;
+    int rank = 0;
+    for (int u = 0; u < t; ++u) rank += (ln[u] == s);
+    const int32_t pos = blkbase[(int64_t)blockIdx.x * k + s] + rank;
+    srow[pos] = (int32_t)o;
+    sdn[pos] = dn[o];
+    sds[pos] = ds[o];
+}
+
+// DN_i = sum over segment i of dn, one wave per segment, fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_seg_const(const T *__restrict__ sdn,
+                                                   const int32_t *__restrict__ seg_off, int32_t k,
+                                                   AccT<T> *__restrict__ segc,
+                                                   const DevState *__restrict__ st) {
+    using A = AccT<T>;
+    if (st->done) return;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= k) return;
+    A s = 0;
+    for (int64_t j = seg_off[i] + lane; j < seg_off[i + 1]; j += 64) s += (A)sdn[j];
+    for (int w = 32; w > 0; w >>= 1) s += __shfl_xor(s, w);
+    if (lane == 0) segc[i] = s;
+}
+
+// ---- the hot pass.  See the file header for the arithmetic.
+// Output per candidate and chunk: part[q][0] = A partial, [1] head carry,
+// [2] tail carry, [3] best value over segments complete in the chunk, and
+// part_i = its slot.  P2 (FastPAM2) also stores M_i - DN_i of complete
+// segments into P[i][c].
+template <typename T, int VEC, bool P2>
+__global__ __launch_bounds__(kWG) void k_swap_pass(
+    const T *__restrict__ D, int64_t ld, int64_t n, int32_t k, const int32_t *__restrict__ srow,
+    const T *__restrict__ sdn, const T *__restrict__ sds, const int32_t *__restrict__ seg_off,
+    const AccT<T> *__restrict__ segc, const ChunkInfo *__restrict__ cinfo, int32_t L, int64_t ncp,
+    AccT<T> *__restrict__ part, int32_t *__restrict__ part_i, AccT<T> *__restrict__ P,
+    const DevState *__restrict__ st) {
+    using A = AccT<T>;
+    constexpr int U = 8;
+    if (st->done) return;
+    const int q = blockIdx.y;
+    const int64_t a = (int64_t)q * L;
+    const int64_t b = min(a + (int64_t)L, n);
+    const int64_t c0 = ((int64_t)blockIdx.x * kWG + threadIdx.x) * VEC;
+    const bool active = c0 < n;
+    const ChunkInfo ci = cinfo[q];
+
+    A accA[VEC], bv[VEC];
+    int32_t bi[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) { accA[e] = 0; bv[e] = VT<T>::acc_inf(); bi[e] = INT_MAX; }
+    A *pq = part + (int64_t)q * 4 * ncp + c0;
+
+    for (int s = ci.sa; s <= ci.sb; ++s) {
+        const int64_t so = seg_off[s], se = seg_off[s + 1];
+        if (so == se) continue;
+        const int64_t p0 = max(a, so), p1 = min(b, se);
+        A M[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) M[e] = 0;
+        if (active) {
+            int64_t j = p0;
+            for (; j + U <= p1; j += U) {
+                T v[U][VEC];
+                T lo[U], hi[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t o = srow[j + u];
+                    load_vec<T, VEC>(D + o * ld + c0, v[u]);
+                    lo[u] = sdn[j + u];
+                    hi[u] = sds[j + u];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        accA[e] += (A)vmin(v[u][e], lo[u]);
+                        M[e] += (A)vmed3(v[u][e], lo[u], hi[u]);
+                    }
+            }
+            for (; j < p1; ++j) {
+                const int64_t o = srow[j];
+                T v[VEC];
+                load_vec<T, VEC>(D + o * ld + c0, v);
+                const T lo = sdn[j], hi = sds[j];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    accA[e] += (A)vmin(v[e], lo);
+                    M[e] += (A)vmed3(v[e], lo, hi);
+                }
+            }
+        }
+        if (s == ci.sa && (ci.flags & kHead)) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) pq[1 * ncp + e] = M[e];
+        } else if (s == ci.sb && (ci.flags & kTail)) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) pq[2 * ncp + e] = M[e];
+        } else {
+            const A dns = segc[s];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const A v = M[e] - dns;
+                if (v < bv[e]) { bv[e] = v; bi[e] = s; }
+                if constexpr (P2) {
+                    if (active) P[(int64_t)s * ncp + c0 + e] = v;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        pq[0 * ncp + e] = accA[e];
+        pq[3 * ncp + e] = bv[e];
+        part_i[(int64_t)q * ncp + c0 + e] = bi[e];
+    }
+}
+
+// ---- merge chunk partials per candidate (fixed chunk order).
+// Writes, per candidate, its best change over slots (FastPAM1) and the
+// work-group's best (value, slot, candidate); for FastPAM2 it completes
+// P[i][c] for carried segments and stores B(c) = A(c) - TD.
+template <typename T, bool P2>
+__global__ __launch_bounds__(kWG) void k_swap_merge(
+    const AccT<T> *__restrict__ part, const int32_t *__restrict__ part_i,
+    const ChunkInfo *__restrict__ cinfo, int32_t Q, int64_t n, int32_t k, int64_t ncp,
+    const AccT<T> *__restrict__ segc, const uint8_t *__restrict__ is_med,
+    const DevState *__restrict__ st, AccT<T> *__restrict__ P, AccT<T> *__restrict__ cand_a,
+    AccT<T> *__restrict__ wg_v, int32_t *__restrict__ wg_i, int32_t *__restrict__ wg_c) {
+    using A = AccT<T>;
+    if (st->done) return;
+    const int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    A bestv = VT<T>::acc_inf();
+    int besti = INT_MAX;
+    int cc = INT_MAX;
+    if (c < n) {
+        A accA = 0;
+        int run_s = -1;
+        A run_m = 0;
+        auto flush = [&]() {
+            if (run_s >= 0) {
+                const A v = run_m - segc[run_s];
+                if (lt2(v, run_s, bestv, besti)) { bestv = v; besti = run_s; }
+                if constexpr (P2) P[(int64_t)run_s * ncp + c] = v;
+            }
+        };
+        for (int q = 0; q < Q; ++q) {
+            const ChunkInfo ci = cinfo[q];
+            const A *pq = part + (int64_t)q * 4 * ncp + c;
+            accA += pq[0];
+            const int32_t i = part_i[(int64_t)q * ncp + c];
+            if (i != INT_MAX) {
+                const A v = pq[3 * ncp];
+                if (lt2(v, i, bestv, besti)) { bestv = v; besti = i; }
+            }
+            if (ci.flags & kHead) {
+                const A m = pq[1 * ncp];
+                if (ci.sa == run_s) run_m += m;
+                else { flush(); run_s = ci.sa; run_m = m; }
+            }
+            if (ci.flags & kTail) {
+                const A m = pq[2 * ncp];
+                if (ci.sb == run_s) run_m += m;
+                else { flush(); run_s = ci.sb; run_m = m; }
+            }
+        }
+        flush();
+        const int e = st->empty_slot;   // an empty slot changes by 0 + B(c)
+        if (e < k && lt2((A)0, e, bestv, besti)) { bestv = 0; besti = e; }
+        A td;
+        if constexpr (std::is_same<T, float>::value) td = st->td; else td = st->td_i;
+        const A bsh = accA - td;
+        if constexpr (P2) cand_a[c] = bsh;
+        if (!is_med[c]) {
+            bestv = bestv + bsh;
+            cc = (int)c;
+        } else {
+            bestv = VT<T>::acc_inf();
+            besti = INT_MAX;
+        }
+    }
+    block_argmin3<A, kWG>(bestv, besti, cc);
+    if (threadIdx.x == 0) {
+        wg_v[blockIdx.x] = bestv;
+        wg_i[blockIdx.x] = besti;
+        wg_c[blockIdx.x] = cc;
+    }
+}
+
+// ---- FastPAM1: global best (value, slot, candidate), then apply it if it
+// lowers TD.  The float path requires the FP64 change to be below -margin,
+// the bound on its rounding, so TD decreases strictly and SWAP cannot cycle.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_swap_select(const AccT<T> *__restrict__ wg_v,
+                                                      const int32_t *__restrict__ wg_i,
+                                                      const int32_t *__restrict__ wg_c, int32_t nwg,
+                                                      int32_t *__restrict__ med,
+                                                      uint8_t *__restrict__ is_med,
+                                                      DevState *__restrict__ st,
+                                                      pamx_swap_record *__restrict__ trace) {
+    using A = AccT<T>;
+    if (st->done) return;
+    A v = VT<T>::acc_inf();
+    int i = INT_MAX, c = INT_MAX;
+    for (int w = threadIdx.x; w < nwg; w += 1024)
+        if (lex_less(wg_v[w], wg_i[w], wg_c[w], v, i, c)) { v = wg_v[w]; i = wg_i[w]; c = wg_c[w]; }
+    block_argmin3<A, 1024>(v, i, c);
+    if (threadIdx.x != 0) return;
+    st->iter += 1;
+    st->best_i = i;
+    st->best_c = c;
+    if constexpr (std::is_same<T, float>::value) st->best_v = v; else { st->best_vi = v; st->best_v = (double)v; }
+    bool apply;
+    if constexpr (std::is_same<T, float>::value) apply = (c != INT_MAX) && (v < -st->margin);
+    else apply = (c != INT_MAX) && (v < 0);
+    if (!apply) {
+        st->done = 1;
+        st->swapped = 0;
+        return;
+    }
+    const int old = med[i];
+    is_med[old] = 0;
+    is_med[c] = 1;
+    med[i] = c;
+    st->old_med = old;
+    st->new_slot = i;
+    st->new_med = c;
+    st->swapped = 1;
+    if constexpr (std::is_same<T, float>::value) st->td += v; else { st->td_i += v; st->td = (double)st->td_i; }
+    if (trace && st->swaps < st->trace_cap) trace[st->swaps] = pamx_swap_record{i, c, (double)v};
+    st->swaps += 1;
+}
+
+// ---- FastPAM2: best candidate of every slot, (value, candidate) order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_slot_best(const AccT<T> *__restrict__ P,
+                                                   const AccT<T> *__restrict__ cand_a,
+                                                   const int32_t *__restrict__ seg_off, int64_t n,
+                                                   int64_t ncp, const uint8_t *__restrict__ is_med,
+                                                   AccT<T> *__restrict__ slot_v,
+                                                   int32_t *__restrict__ slot_c,
+                                                   const DevState *__restrict__ st) {
+    using A = AccT<T>;
+    if (st->done) return;
+    const int i = blockIdx.x;
+    const bool empty = seg_off[i] == seg_off[i + 1];
+    A v = VT<T>::acc_inf();
+    int c = INT_MAX, dummy = 0;
+    for (int64_t x = threadIdx.x; x < n; x += 256) {
+        if (is_med[x]) continue;
+        const A d = (empty ? (A)0 : P[(int64_t)i * ncp + x]) + cand_a[x];
+        if (d < v) { v = d; c = (int)x; }   // ascending x: first minimum per thread
+    }
+    block_argmin3<A, 256>(v, dummy, c);
+    if (threadIdx.x == 0) { slot_v[i] = v; slot_c[i] = c; }
+}
+
+// ---- FastPAM2 eager application (one work-group).  Slots with a negative
+// best change are visited by (change, slot); a visit is skipped if its
+// candidate became a medoid meanwhile, otherwise the swap's change is
+// computed again against the current caches (sum of Eq. change over all
+// objects) and the swap applied when negative.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_eager_apply(
+    const T *__restrict__ D, int64_t ld, int64_t n, int32_t k, int32_t *__restrict__ med,
+    uint8_t *__restrict__ is_med, int32_t *__restrict__ near, int32_t *__restrict__ sec,
+    T *__restrict__ dn, T *__restrict__ ds, const AccT<T> *__restrict__ slot_v,
+    const int32_t *__restrict__ slot_c, int32_t *__restrict__ order, DevState *__restrict__ st,
+    pamx_swap_record *__restrict__ trace) {
+    using A = AccT<T>;
+    if (st->done) return;
+    __shared__ int32_t cnt;
+    __shared__ int32_t go;
+    const int t = threadIdx.x;
+    A thr;
+    if constexpr (std::is_same<T, float>::value) thr = -st->margin; else thr = 0;
+    if (t == 0) cnt = 0;
+    __syncthreads();
+    // rank the negative slots by (value, slot)
+    for (int i = t; i < k; i += 1024) {
+        const A vi = slot_v[i];
+        if (!(slot_c[i] != INT_MAX && vi < thr)) continue;
+        int r = 0;
+        for (int j = 0; j < k; ++j) {
+            const A vj = slot_v[j];
+            if (slot_c[j] != INT_MAX && vj < thr && lt2(vj, j, vi, i)) ++r;
+        }
+        order[r] = i;
+        atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    const int m = cnt;
+    int applied = 0;
+    for (int r = 0; r < m; ++r) {
+        const int i = order[r];
+        const int c = slot_c[i];
+        if (is_med[c]) continue;   // uniform: all threads read the same byte
+        const T *rowc = D + (int64_t)c * ld;
+        A s = 0;
+        for (int64_t o = t; o < n; o += 1024) {
+            const T d = rowc[o];
+            const T a = dn[o];
+            if (near[o] == i) s += (A)vmin(d, ds[o]) - (A)a;   // cases (b1), (b2)
+            else s += (A)vmin(d, a) - (A)a;                    // cases (a), (c)
+        }
+        s = block_sum<A, 1024>(s);
+        if (t == 0) go = (s < thr) ? 1 : 0;
+        __syncthreads();
+        if (!go) { __syncthreads(); continue; }
+        if (t == 0) {
+            const int old = med[i];
+            is_med[old] = 0;
+            is_med[c] = 1;
+            med[i] = c;
+            if constexpr (std::is_same<T, float>::value) st->td += s; else { st->td_i += s; st->td = (double)st->td_i; }
+            if (trace && st->swaps < st->trace_cap) trace[st->swaps] = pamx_swap_record{i, c, (double)s};
+            st->swaps += 1;
+        }
+        __syncthreads();
+        for (int64_t o = t; o < n; o += 1024) {
+            int32_t nr = near[o], sc = sec[o];
+            T a = dn[o], b2 = ds[o];
+            cache_update_one<T>(D, ld, k, med, o, i, rowc[o], nr, sc, a, b2);
+            near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b2;
+        }
+        ++applied;
+        __syncthreads();
+    }
+    if (t == 0) {
+        st->iter += 1;
+        if (applied == 0) st->done = 1;
+    }
+}
+
+// ================================================================ host side
+template <typename T>
+struct SwapPtrs {
+    int32_t *near, *sec, *srow, *blkcnt, *seg_off, *part_i, *wg_i, *wg_c, *slot_c, *order;
+    T *dn, *ds, *sdn, *sds;
+    uint8_t *is_med;
+    AccT<T> *segc, *part, *wg_v, *P, *cand_a, *slot_v;
+    ChunkInfo *cinfo;
+    DevState *st;
+};
+
+template <typename T>
+static SwapPtrs<T> ptrs(const Layout &L, void *ws) {
+    char *w = static_cast<char *>(ws);
+    SwapPtrs<T> p;
+    p.near = reinterpret_cast<int32_t *>(w + L.near);
+    p.sec = reinterpret_cast<int32_t *>(w + L.sec);
+    p.dn = reinterpret_cast<T *>(w + L.dn);
+    p.ds = reinterpret_cast<T *>(w + L.ds);
+    p.is_med = reinterpret_cast<uint8_t *>(w + L.is_med);
+    p.srow = reinterpret_cast<int32_t *>(w + L.srow);
+    p.sdn = reinterpret_cast<T *>(w + L.sdn);
+    p.sds = reinterpret_cast<T *>(w + L.sds);
+    p.blkcnt = reinterpret_cast<int32_t *>(w + L.blkcnt);
+    p.seg_off = reinterpret_cast<int32_t *>(w + L.seg_off);
+    p.cinfo = reinterpret_cast<ChunkInfo *>(w + L.blkbase);
+    p.segc = reinterpret_cast<AccT<T> *>(w + L.segc);
+    p.part = reinterpret_cast<AccT<T> *>(w + L.part);
+    p.part_i = reinterpret_cast<int32_t *>(w + L.part_i);
+    p.cand_a = reinterpret_cast<AccT<T> *>(w + L.cand_a);
+    p.wg_v = reinterpret_cast<AccT<T> *>(w + L.wg_v);
+    p.wg_i = reinterpret_cast<int32_t *>(w + L.wg_i);
+    p.wg_c = reinterpret_cast<int32_t *>(w + L.wg_c);
+    p.P = (L.P != SIZE_MAX) ? reinterpret_cast<AccT<T> *>(w + L.P) : nullptr;
+    p.slot_v = reinterpret_cast<AccT<T> *>(w + L.slot_v);
+    p.slot_c = reinterpret_cast<int32_t *>(w + L.slot_c);
+    p.order = reinterpret_cast<int32_t *>(w + L.list);
+    p.st = reinterpret_cast<DevState *>(w + L.state);
+    return p;
+}
+
+template <typename T>
+hipError_t enqueue_swap_init(const T *D, int64_t ld, const Layout &L, const int32_t *medoids,
+                             const pamx_options &opt, void *ws, hipStream_t s) {
+    auto p = ptrs<T>(L, ws);
+    const int64_t n = L.n;
+    const int32_t k = L.k;
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, p.st, opt.max_iter,
+                       opt.trace ? opt.trace_cap : 0);
+    fill<uint8_t>(p.is_med, n, 0, s);
+    fill<int32_t>(p.near, n, 0, s);
+    hipLaunchKernelGGL(k_check_medoids, dim3((k + 255) / 256), dim3(256), 0, s, medoids, k, n,
+                       p.near, p.is_med, p.st);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t enqueue_caches(const T *D, int64_t ld, const Layout &L, const int32_t *medoids,
+                                 int32_t *labels, void *ws, hipStream_t s) {
+    auto p = ptrs<T>(L, ws);
+    const int64_t n = L.n;
+    hipLaunchKernelGGL(k_cache_init<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, D, ld,
+                       n, L.k, medoids, p.near, p.sec, p.dn, p.ds, labels);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32_t *medoids,
+                                  const pamx_options &opt, void *ws, hipStream_t s) {
+    using A = AccT<T>;
+    auto p = ptrs<T>(L, ws);
+    const int64_t n = L.n;
+    const int32_t k = L.k;
+    const bool p2 = opt.variant == PAMX_FASTPAM2;
+    pamx_swap_record *trace = static_cast<pamx_swap_record *>(opt.trace);
+    const unsigned ob = (unsigned)((n + 255) / 256);
+
+    hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(1), 0, s, p.st);
+    hipLaunchKernelGGL(k_seg_count, dim3(L.n_oblk), dim3(kObjBlk), (size_t)k * 4, s,
+                       (const int32_t *)p.near, n, k, p.blkcnt, (const DevState *)p.st);
+    hipLaunchKernelGGL(k_seg_scan<T>, dim3(1), dim3(1024), 0, s, p.blkcnt, L.n_oblk, k, n,
+                       p.seg_off, (const T *)p.dn, (const T *)p.ds, L.L, L.Q, p.cinfo, p.st);
+    hipLaunchKernelGGL(k_seg_scatter<T>, dim3(L.n_oblk), dim3(kObjBlk), 0, s,
+                       (const int32_t *)p.near, (const T *)p.dn, (const T *)p.ds, n, k,
+                       (const int32_t *)p.blkcnt, p.srow, p.sdn, p.sds, (const DevState *)p.st);
+    hipLaunchKernelGGL(k_seg_const<T>, dim3((k + 3) / 4), dim3(256), 0, s, (const T *)p.sdn,
+                       (const int32_t *)p.seg_off, k, p.segc, (const DevState *)p.st);
+    const dim3 pgrid(L.n_ctiles, L.Q);
+#define PAMX_PASS(VEC, P2)                                                                    \
+    hipLaunchKernelGGL((k_swap_pass<T, VEC, P2>), pgrid, dim3(kWG), 0, s, D, ld, n, k,       \
+                       (const int32_t *)p.srow, (const T *)p.sdn, (const T *)p.sds,           \
+                       (const int32_t *)p.seg_off, (const A *)p.segc,                         \
+                       (const ChunkInfo *)p.cinfo, L.L, L.ncp, p.part, p.part_i, p.P,         \
+                       (const DevState *)p.st)
+    if (L.vec == 4) { if (p2) PAMX_PASS(4, true); else PAMX_PASS(4, false); }
+    else { if (p2) PAMX_PASS(1, true); else PAMX_PASS(1, false); }
+#undef PAMX_PASS
+    if (p2) {
+        hipLaunchKernelGGL((k_swap_merge<T, true>), dim3(L.n_mwg), dim3(kWG), 0, s,
+                           (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
+                           L.Q, n, k, L.ncp, (const A *)p.segc, (const uint8_t *)p.is_med,
+                           (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
+        hipLaunchKernelGGL(k_slot_best<T>, dim3(k), dim3(256), 0, s, (const A *)p.P,
+                           (const A *)p.cand_a, (const int32_t *)p.seg_off, n, L.ncp,
+                           (const uint8_t *)p.is_med, p.slot_v, p.slot_c, (const DevState *)p.st);
+        hipLaunchKernelGGL(k_eager_apply<T>, dim3(1), dim3(1024), 0, s, D, ld, n, k, medoids,
+                           p.is_med, p.near, p.sec, p.dn, p.ds, (const A *)p.slot_v,
+                           (const int32_t *)p.slot_c, p.order, p.st, trace);
+    } else {
+        hipLaunchKernelGGL((k_swap_merge<T, false>), dim3(L.n_mwg), dim3(kWG), 0, s,
+                           (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
+                           L.Q, n, k, L.ncp, (const A *)p.segc, (const uint8_t *)p.is_med,
+                           (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
+        hipLaunchKernelGGL(k_swap_select<T>, dim3(1), dim3(1024), 0, s, (const A *)p.wg_v,
+                           (const int32_t *)p.wg_i, (const int32_t *)p.wg_c, L.n_mwg, medoids,
+                           p.is_med, p.st, trace);
+        hipLaunchKernelGGL(k_cache_update<T>, dim3(ob), dim3(256), 0, s, D, ld, n, k,
+                           (const int32_t *)medoids, p.near, p.sec, p.dn, p.ds,
+                           (const DevState *)p.st);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t enqueue_finalize(const T *D, int64_t ld, const Layout &L, const int32_t *medoids,
+                            int32_t *labels, void *ws, hipStream_t s) {
+    auto p = ptrs<T>(L, ws);
+    hipError_t e = enqueue_caches<T>(D, ld, L, medoids, labels, ws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_td_sum<T>, dim3(1), dim3(1024), 0, s, (const T *)p.dn, L.n, p.st);
+    return hipGetLastError();
+}
+
+// caches for the first iteration (after enqueue_swap_init's medoid check)
+template <typename T>
+hipError_t enqueue_swap_caches(const T *D, int64_t ld, const Layout &L, const int32_t *medoids,
+                               void *ws, hipStream_t s) {
+    return enqueue_caches<T>(D, ld, L, medoids, nullptr, ws, s);
+}
+
+// explicit instantiations
+#define PAMX_INST(T)                                                                           \
+    template hipError_t run_build<T>(const T *, int64_t, const Layout &, int32_t, int32_t,     \
+                                     int32_t *, void *, hipStream_t);                          \
+    template hipError_t enqueue_swap_init<T>(const T *, int64_t, const Layout &,               \
+                                             const int32_t *, const pamx_options &, void *,    \
+                                             hipStream_t);                                     \
+    template hipError_t enqueue_swap_iteration<T>(const T *, int64_t, const Layout &,          \
+                                                  int32_t *, const pamx_options &, void *,     \
+                                                  hipStream_t);                                \
+    template hipError_t enqueue_finalize<T>(const T *, int64_t, const Layout &,                \
+                                            const int32_t *, int32_t *, void *, hipStream_t);  \
+    template hipError_t enqueue_swap_caches<T>(const T *, int64_t, const Layout &,             \
+                                               const int32_t *, void *, hipStream_t);
+PAMX_INST(float)
+PAMX_INST(int32_t)
+#undef PAMX_INST
+
+}  // namespace pamx

@@ -1,0 +1,171 @@
+"""ctypes binding of libpamx.so (C ABI in include/pamx.h).
+
+Argument marshalling only: every step of BUILD and SWAP runs in the HIP
+kernels of libpamx.so.  Torch tensors provide device memory and the stream.
+If the library is missing this module raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpamx.so")
+
+# constants of include/pamx.h
+PAMX_I32, PAMX_F32 = 1, 2
+PAMX_INPUT_D, PAMX_INPUT_X = 0, 1
+PAMX_L1, PAMX_L2 = 1, 2
+PAMX_FASTPAM1, PAMX_FASTPAM2 = 1, 2
+PAMX_ACC_F64, PAMX_ACC_F32 = 0, 1
+PAMX_OK, PAMX_WARN_MAXITER = 0, 1
+PAMX_ERR_ARG, PAMX_ERR_WORKSPACE, PAMX_ERR_HIP = -1, -2, -3
+PAMX_ERR_INVALID_MEDOIDS, PAMX_ERR_UNSUPPORTED = -4, -5
+
+
+class pamx_options(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("accum", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("build_exclude_self", ctypes.c_int32),
+                ("trace_cap", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("trace", ctypes.c_void_p)]
+
+
+class pamx_swap_record(ctypes.Structure):
+    _fields_ = [("slot", ctypes.c_int32), ("cand", ctypes.c_int32), ("delta", ctypes.c_double)]
+
+
+class pamx_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("swaps", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("rescored", ctypes.c_int32),
+                ("td_build", ctypes.c_double), ("td", ctypes.c_double),
+                ("ms_dist", ctypes.c_double), ("ms_build", ctypes.c_double),
+                ("ms_swap", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("pass_pairs", ctypes.c_int64), ("build_pairs", ctypes.c_int64)]
+
+
+EXPORTS = ("pamx_default_options", "pamx_workspace_bytes", "pamx_dist", "pamx_build",
+           "pamx_swap", "pamx_fit", "pamx_last_error")
+
+
+class PamxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("pamx error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpamx.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libpamx.so is not built (%s); run "
+                           "`python -m paper_2008_05171_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    opt_p = ctypes.POINTER(pamx_options)
+    st_p = ctypes.POINTER(pamx_stats)
+    dbl_p = ctypes.POINTER(ctypes.c_double)
+    lib.pamx_default_options.argtypes = [opt_p]
+    lib.pamx_default_options.restype = None
+    lib.pamx_workspace_bytes.argtypes = [i64, i32, i32, i32, i32, opt_p, ctypes.POINTER(sz)]
+    lib.pamx_dist.argtypes = [P, i32, i64, i32, i32, P, i64, P]
+    lib.pamx_build.argtypes = [P, i32, i64, i64, i32, opt_p, P, dbl_p, P, sz, P]
+    lib.pamx_swap.argtypes = [P, i32, i64, i64, i32, opt_p, P, P, dbl_p, st_p, P, sz, P]
+    lib.pamx_fit.argtypes = [P, i32, i32, i64, i32, i32, i32, opt_p, P, P, dbl_p, st_p, P, sz, P]
+    lib.pamx_last_error.argtypes = []
+    lib.pamx_last_error.restype = ctypes.c_char_p
+    for name in ("pamx_workspace_bytes", "pamx_dist", "pamx_build", "pamx_swap", "pamx_fit"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc < 0:
+        raise PamxError(rc, load().pamx_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.int32:
+        return PAMX_I32
+    if t.dtype == torch.float32:
+        return PAMX_F32
+    raise TypeError("dissimilarities/points must be int32 or float32, got %s" % t.dtype)
+
+
+def pamx_default_options() -> pamx_options:
+    o = pamx_options()
+    load().pamx_default_options(ctypes.byref(o))
+    return o
+
+
+def pamx_workspace_bytes(n, k, dim, input_kind, dtype, opt=None) -> int:
+    out = ctypes.c_size_t()
+    _check(load().pamx_workspace_bytes(int(n), int(k), int(dim), int(input_kind), int(dtype),
+                                       ctypes.byref(opt) if opt is not None else None,
+                                       ctypes.byref(out)))
+    return int(out.value)
+
+
+def pamx_dist(X, metric, D, ld=None, stream=None):
+    n, dim = X.shape
+    ld = D.stride(0) if ld is None else ld
+    return _check(load().pamx_dist(_ptr(X), _dtype_code(X), n, dim, int(metric), _ptr(D), int(ld),
+                                   _stream(stream)))
+
+
+def pamx_build(D, k, medoids, ws, opt=None, n=None, ld=None, stream=None):
+    n = D.shape[0] if n is None else n
+    ld = D.stride(0) if ld is None else ld
+    td = ctypes.c_double()
+    rc = _check(load().pamx_build(_ptr(D), _dtype_code(D), int(n), int(ld), int(k),
+                                  ctypes.byref(opt) if opt is not None else None, _ptr(medoids),
+                                  ctypes.byref(td), _ptr(ws), ws.numel() * ws.element_size(),
+                                  _stream(stream)))
+    return rc, td.value
+
+
+def pamx_swap(D, k, medoids, ws, labels=None, opt=None, n=None, ld=None, stream=None):
+    n = D.shape[0] if n is None else n
+    ld = D.stride(0) if ld is None else ld
+    td = ctypes.c_double()
+    st = pamx_stats()
+    rc = _check(load().pamx_swap(_ptr(D), _dtype_code(D), int(n), int(ld), int(k),
+                                 ctypes.byref(opt) if opt is not None else None, _ptr(medoids),
+                                 _ptr(labels), ctypes.byref(td), ctypes.byref(st), _ptr(ws),
+                                 ws.numel() * ws.element_size(), _stream(stream)))
+    return rc, td.value, st
+
+
+def pamx_fit(XorD, input_kind, k, medoids, labels, ws, metric=PAMX_L2, opt=None, stream=None):
+    n = XorD.shape[0]
+    dim = XorD.shape[1] if input_kind == PAMX_INPUT_X else 0
+    td = ctypes.c_double()
+    st = pamx_stats()
+    rc = _check(load().pamx_fit(_ptr(XorD), int(input_kind), _dtype_code(XorD), int(n), int(dim),
+                                int(metric), int(k),
+                                ctypes.byref(opt) if opt is not None else None, _ptr(medoids),
+                                _ptr(labels), ctypes.byref(td), ctypes.byref(st), _ptr(ws),
+                                ws.numel() * ws.element_size(), _stream(stream)))
+    return rc, td.value, st
+
+
+def pamx_last_error() -> str:
+    return load().pamx_last_error().decode()

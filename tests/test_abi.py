@@ -1,0 +1,122 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/pamx.h, and rejects bad arguments on the host
+before any device work (so these calls never touch HIP)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2008_05171_amd import pamx as abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(abi.LIB_PATH):
+        from paper_2008_05171_amd import build
+        build.build()
+    return abi.load()
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "pamx.h")).read()
+    return sorted(set(re.findall(r"\b(pamx_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert set(names) == set(abi.EXPORTS)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_struct_sizes_match_header():
+    assert ctypes.sizeof(abi.pamx_options) == 32
+    assert ctypes.sizeof(abi.pamx_swap_record) == 16
+    assert ctypes.sizeof(abi.pamx_stats) == 80
+
+
+def test_default_options(lib):
+    o = abi.pamx_default_options()
+    assert (o.variant, o.accum, o.max_iter, o.build_exclude_self, o.trace_cap, o.chunk) == \
+        (abi.PAMX_FASTPAM1, abi.PAMX_ACC_F64, 10000, 0, 0, 0)
+
+
+def test_workspace_bytes_grows_and_validates(lib):
+    a = abi.pamx_workspace_bytes(1000, 5, 0, abi.PAMX_INPUT_D, abi.PAMX_I32)
+    b = abi.pamx_workspace_bytes(20000, 100, 0, abi.PAMX_INPUT_D, abi.PAMX_F32)
+    c = abi.pamx_workspace_bytes(20000, 100, 16, abi.PAMX_INPUT_X, abi.PAMX_F32)
+    assert 0 < a < b < c
+    assert c - b >= 20000 * 20032 * 4          # stored matrix, 64-padded rows
+    o = abi.pamx_default_options()
+    o.variant = abi.PAMX_FASTPAM2
+    d = abi.pamx_workspace_bytes(20000, 100, 0, abi.PAMX_INPUT_D, abi.PAMX_F32, o)
+    assert d >= b + 100 * 20480 * 8            # per-medoid change buffer
+    for args in [(0, 1), (10, 0), (10, 11), (10, 20000), (30000, 17000)]:
+        with pytest.raises(abi.PamxError) as e:
+            abi.pamx_workspace_bytes(args[0], args[1], 0, abi.PAMX_INPUT_D, abi.PAMX_F32)
+        assert e.value.code == abi.PAMX_ERR_ARG
+    with pytest.raises(abi.PamxError):
+        abi.pamx_workspace_bytes(10, 2, 0, abi.PAMX_INPUT_X, abi.PAMX_F32)   # dim 0
+    with pytest.raises(abi.PamxError):
+        abi.pamx_workspace_bytes(10, 2, 0, 7, abi.PAMX_F32)
+
+
+def _call_build(lib, D, dtype, n, ld, k, ws, wsb, opt=None):
+    td = ctypes.c_double()
+    med = ctypes.c_void_p(0x1000)
+    return lib.pamx_build(D, dtype, n, ld, k, ctypes.byref(opt) if opt else None, med,
+                          ctypes.byref(td), ws, wsb, None)
+
+
+def test_host_argument_errors_before_device_work(lib):
+    fake = ctypes.c_void_p(0x100000)          # never dereferenced: rejected first
+    ws = ctypes.c_void_p(0x200000)
+    assert _call_build(lib, None, abi.PAMX_F32, 10, 10, 2, ws, 1 << 30) == abi.PAMX_ERR_ARG
+    assert "D is NULL" in abi.pamx_last_error()
+    assert _call_build(lib, fake, 9, 10, 10, 2, ws, 1 << 30) == abi.PAMX_ERR_ARG
+    assert _call_build(lib, fake, abi.PAMX_F32, 10, 9, 2, ws, 1 << 30) == abi.PAMX_ERR_ARG
+    assert _call_build(lib, fake, abi.PAMX_F32, 10, 10, 11, ws, 1 << 30) == abi.PAMX_ERR_ARG
+    assert _call_build(lib, fake, abi.PAMX_F32, 10, 10, 0, ws, 1 << 30) == abi.PAMX_ERR_ARG
+    assert _call_build(lib, fake, abi.PAMX_F32, 10, 10, 2, ws, 16) == abi.PAMX_ERR_WORKSPACE
+    assert "too small" in abi.pamx_last_error()
+    assert _call_build(lib, fake, abi.PAMX_F32, 10, 10, 2, ctypes.c_void_p(0x200010),
+                       1 << 30) == abi.PAMX_ERR_WORKSPACE
+    assert _call_build(lib, fake, abi.PAMX_F32, 10, 10, 2, None, 1 << 30) == abi.PAMX_ERR_WORKSPACE
+    o = abi.pamx_default_options()
+    o.variant = 3
+    assert _call_build(lib, fake, abi.PAMX_F32, 10, 10, 2, ws, 1 << 30, o) == abi.PAMX_ERR_ARG
+    o = abi.pamx_default_options()
+    o.accum = abi.PAMX_ACC_F32
+    assert _call_build(lib, fake, abi.PAMX_I32, 10, 10, 2, ws, 1 << 30, o) == abi.PAMX_ERR_ARG
+    o = abi.pamx_default_options()
+    o.trace_cap = 5
+    rc = lib.pamx_swap(fake, abi.PAMX_F32, 10, 10, 2, ctypes.byref(o), fake, None, None, None,
+                       ws, 1 << 30, None)
+    assert rc == abi.PAMX_ERR_ARG and "trace" in abi.pamx_last_error()
+    # overflow of n * ld
+    assert _call_build(lib, fake, abi.PAMX_F32, 1 << 30, 1 << 40, 2, ws, 1 << 62) == abi.PAMX_ERR_ARG
+
+
+def test_points_metric_rules(lib):
+    fake = ctypes.c_void_p(0x100000)
+    rc = lib.pamx_dist(fake, abi.PAMX_I32, 10, 2, abi.PAMX_L2, fake, 12, None)
+    assert rc == abi.PAMX_ERR_UNSUPPORTED
+    rc = lib.pamx_dist(fake, abi.PAMX_F32, 10, 2, abi.PAMX_L1, fake, 12, None)
+    assert rc == abi.PAMX_ERR_UNSUPPORTED
+    rc = lib.pamx_dist(fake, abi.PAMX_F32, 10, 2, abi.PAMX_L2, fake, 10, None)
+    assert rc == abi.PAMX_ERR_ARG          # ld not a multiple of 4
+    rc = lib.pamx_dist(fake, abi.PAMX_F32, 10, 0, abi.PAMX_L2, fake, 12, None)
+    assert rc == abi.PAMX_ERR_ARG
+
+
+def test_no_oracle_in_product_path():
+    """The product package never imports or loads the CPU oracle."""
+    pkg = os.path.join(ROOT, "paper_2008_05171_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "liboracle" not in txt, f
