@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""k-medoids benchmark on one MI355X: PAM BUILD + FastPAM1 SWAP.
+
+One step = one whole fit on points already resident in HBM: Euclidean
+distance matrix (FP32, Gram term on MFMA), BUILD, FastPAM1 SWAP to
+convergence, labels and TD -- every kernel of the hot path.
+
+Workload: n = 20000 points in 16 dimensions from a 50-component isotropic
+Gaussian mixture (centers uniform in [-10, 10]^16, sigma 1, seed 1002),
+k = 100, stored FP32 matrix (1.6 GB).  Synthetic data (the paper's data sets
+are not available).
+
+Reported (one JSON line):
+  value            SWAP loss-change pair evaluations per second: candidate-
+                   object pairs (n - k) * n per SWAP pass, over the SWAP phase
+                   device time of the timed fits
+  ms_per_step      wall time of one whole fit
+  roofline         SWAP pass kernel: algorithmic bytes 4 * n * (n - k) per
+                   launch over its average duration (HIP events on the
+                   library's stream), against 8 TB/s HBM
+  cpu_baseline     the CPU oracle (original PAM SWAP, FP64, OpenMP) on a
+                   bounded sample of candidates of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N, DIM, K, COMPONENTS, SEED = 20000, 16, 100, 50, 1002
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def traffic_from_profiles(n, k):
+    """HBM bytes per SWAP pass from committed rocprofv3 counter runs, or None
+    when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "swap_pass_gmm16_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_2008_05171_amd", "csrc", "swap.hip"), "rb").read()
+    if rec.get("src_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    if rec.get("n") != n or rec.get("k") != k:
+        return None
+    return float(rec["bytes_per_launch"])
+
+
+def cpu_baseline(X, k, target_s):
+    """Original PAM SWAP search (Alg. 2 with Eq. change, FP64) of the oracle
+    over a bounded sample of candidates; pairs = candidates * n."""
+    import numpy as np
+    import oracle
+    n = X.shape[0]
+    log("cpu baseline: oracle distance matrix (FP64) ...")
+    D = oracle.dist_matrix(X.astype(np.float64), oracle.L2)
+    rng = np.random.default_rng(SEED)
+    med = rng.choice(n, size=k, replace=False).astype(np.int32)
+    m0 = 8
+    t0 = time.perf_counter()
+    oracle.swap_search(med, D=D, c_begin=0, c_end=m0)
+    dt0 = time.perf_counter() - t0
+    m = int(max(m0, min(n, m0 * target_s / max(dt0, 1e-3))))
+    log("cpu baseline: %d candidates x %d objects x %d slots (calibration %.2fs)" % (m, n, k, dt0))
+    t0 = time.perf_counter()
+    oracle.swap_search(med, D=D, c_begin=0, c_end=m)
+    dt = time.perf_counter() - t0
+    del D
+    return {"value": m * n / dt, "unit": "pair-evals/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "one PAM SWAP search (all %d slots, Eq. change per pair, FP64) over "
+                      "candidates 0..%d of the same %d-point workload, %.1f s" % (k, m - 1, n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fastpam2", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
+              "(the multi-GPU design is described in DESIGN.md)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2008_05171_amd import datagen
+    from paper_2008_05171_amd import pamx as abi
+
+    dev = torch.device("cuda:0")
+    X_np = datagen.gaussian_mixture(N, DIM, COMPONENTS, seed=SEED, sigma=1.0)
+    X = torch.from_numpy(X_np).to(dev)
+
+    def make(variant):
+        opt = abi.pamx_default_options()
+        opt.variant = variant
+        opt.profile = 1
+        nbytes = abi.pamx_workspace_bytes(N, K, DIM, abi.PAMX_INPUT_X, abi.PAMX_F32, opt)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        med = torch.empty(K, dtype=torch.int32, device=dev)
+        lab = torch.empty(N, dtype=torch.int32, device=dev)
+        return opt, ws, med, lab
+
+    opt, ws, med, lab = make(abi.PAMX_FASTPAM1)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        rc, td, st = abi.pamx_fit(X, abi.PAMX_INPUT_X, K, med, lab, ws, metric=abi.PAMX_L2,
+                                  opt=opt, stream=stream)
+        return rc, td, st
+
+    for w in range(args.warmup):
+        step()
+        log("warmup %d/%d done" % (w + 1, args.warmup))
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        rc, td, st = step()
+        stats.append((rc, td, {f: getattr(st, f) for f, _ in abi.pamx_stats._fields_}))
+        log("step %d/%d: %.1f ms (dist %.1f, build %.1f, swap %.1f), %d iterations, TD %.6f" % (
+            s + 1, args.steps, st.ms_total, st.ms_dist, st.ms_build, st.ms_swap, st.iterations, td))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    swap_pairs = sum(s[2]["pass_pairs"] for s in stats)
+    swap_s = sum(s[2]["ms_swap"] for s in stats) / 1e3
+    pass_ms = sum(s[2]["ms_swap_pass"] for s in stats)
+    n_pass = sum(s[2]["n_swap_pass"] for s in stats)
+    bpass_ms = sum(s[2]["ms_build_pass"] for s in stats)
+    n_bpass = sum(s[2]["n_build_pass"] for s in stats)
+    avg_pass_ms = pass_ms / max(n_pass, 1)
+    avg_bpass_ms = bpass_ms / max(n_bpass, 1)
+    alg_bytes = 4.0 * N * (N - K)            # D entries of the non-medoid candidates
+    achieved = alg_bytes / (avg_pass_ms / 1e3) / 1e9
+    build_gbs = 4.0 * N * N / (avg_bpass_ms / 1e3) / 1e9
+    traffic = traffic_from_profiles(N, K)
+    last = stats[-1][2]
+
+    extra = {}
+    if not args.no_fastpam2:
+        opt2, ws2, med2, lab2 = make(abi.PAMX_FASTPAM2)
+        rc2, td2, st2 = abi.pamx_fit(X, abi.PAMX_INPUT_X, K, med2, lab2, ws2,
+                                     metric=abi.PAMX_L2, opt=opt2, stream=stream)
+        extra = {"fastpam2_eager": {
+            "fit_ms": round(st2.ms_total, 3), "swap_ms": round(st2.ms_swap, 3),
+            "iterations": st2.iterations, "swaps": st2.swaps, "td": td2,
+            "td_rel_vs_fastpam1": (td2 - stats[-1][1]) / stats[-1][1],
+            "swap_pass_ms_avg": round(st2.ms_swap_pass / max(st2.n_swap_pass, 1), 4)}}
+        del ws2
+        log("fastpam2: %.1f ms, %d iterations, %d swaps, TD %.6f" % (
+            st2.ms_total, st2.iterations, st2.swaps, td2))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(X_np, K, args.cpu_seconds)
+
+    out = {
+        "metric": "SWAP dTD pair-evals/s + achieved HBM GB/s; end-to-end k-medoids fit time",
+        "value": swap_pairs / swap_s,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "accum_dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "gmm16: n=20000 d=16, 50-component Gaussian mixture, stored FP32 "
+                               "Euclidean matrix (1.6 GB), k=100, BUILD init, FastPAM1",
+                   "n": N, "dim": DIM, "k": K, "components": COMPONENTS, "seed": SEED,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_swap_pass", "bytes_per_launch": alg_bytes,
+                     "avg_launch_ms": avg_pass_ms, "launches": n_pass},
+        "cpu_baseline": cpu,
+        "fit_ms": round(last["ms_total"], 3),
+        "phase_ms": {"dist": round(last["ms_dist"], 3), "build": round(last["ms_build"], 3),
+                     "swap": round(last["ms_swap"], 3)},
+        "iterations": last["iterations"], "swaps": last["swaps"], "td": stats[-1][1],
+        "td_build": last["td_build"],
+        "build_pass": {"avg_launch_ms": avg_bpass_ms, "achieved_gbs": build_gbs,
+                       "bytes_per_launch": 4.0 * N * N},
+        "swap_pass_pairs_per_s": N * (N - K) / (avg_pass_ms / 1e3),
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

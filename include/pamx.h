@@ -92,6 +92,8 @@ typedef struct pamx_options {
                                    literal loop bounds of Alg. 1 (x_c skipped) */
     int32_t trace_cap;          /* capacity of `trace` in records (0: none)   */
     int32_t chunk;              /* objects per pass work-group; 0 = automatic */
+    int32_t profile;            /* 1: time every BUILD / SWAP pass kernel with
+                                   HIP events on `stream` (pamx_stats)       */
     void *trace;                /* optional DEVICE array of pamx_swap_record:
                                    every applied swap in order               */
 } pamx_options;
@@ -112,6 +114,10 @@ typedef struct pamx_stats {
     double ms_dist, ms_build, ms_swap, ms_total; /* device time per phase */
     int64_t pass_pairs; /* candidate-object pairs read by SWAP passes */
     int64_t build_pairs;/* candidate-object pairs read by BUILD passes */
+    double ms_swap_pass;   /* profile=1: summed duration of the SWAP pass kernels */
+    double ms_build_pass;  /* profile=1: summed duration of the BUILD pass kernels */
+    int32_t n_swap_pass;   /* profile=1: SWAP pass launches that did work */
+    int32_t n_build_pass;  /* profile=1: BUILD pass launches */
 } pamx_stats;
 
 /* Fills `opt` with the defaults listed above. */

@@ -2,7 +2,7 @@
 
 Every source under ``csrc/`` is compiled with hipcc for gfx950 only, with the
 packed-FP32 VALU forms disabled, then linked into
-``paper_2008_05171_amd/libpamx.so``.  Run ``python -m paper_2008_05171_amd.build``.
+``paper_2008_05171_amd/libpamx.so``.  Run ``python -m paper_2008_05171_amd.buildlib``.
 """
 from __future__ import annotations
 

@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstring>
 #include <type_traits>
+#include <memory>
+#include <vector>
 
 #include "pamx_internal.h"
 
@@ -251,6 +253,33 @@ struct Timer {
     }
 };
 
+// A pool of HIP events bracketing pass kernels (pamx_options.profile).
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    explicit EventPool(size_t count) : ev(count, nullptr) {
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+    }
+    ~EventPool() {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    bool ok() const {
+        for (auto e : ev)
+            if (!e) return false;
+        return true;
+    }
+    // summed duration of the first `pairs` (begin, end) pairs
+    double sum(int pairs) const {
+        double t = 0.0;
+        for (int j = 0; j < pairs; ++j) {
+            float v = 0.f;
+            if (hipEventElapsedTime(&v, ev[2 * j], ev[2 * j + 1]) == hipSuccess) t += v;
+        }
+        return t;
+    }
+};
+
 int read_state(const Layout &L, void *ws, hipStream_t s, DevState *out) {
     const char *w = static_cast<const char *>(ws);
     HIP_TRY(hipMemcpyAsync(out, w + L.state, sizeof(DevState), hipMemcpyDeviceToHost, s));
@@ -260,13 +289,23 @@ int read_state(const Layout &L, void *ws, hipStream_t s, DevState *out) {
 
 template <typename T>
 int build_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const pamx_options &opt,
-               int32_t *medoids, double *td, void *ws, hipStream_t s) {
-    HIP_TRY(run_build<T>(D, ld, L, k, opt.build_exclude_self, medoids, ws, s));
+               int32_t *medoids, double *td, void *ws, hipStream_t s, pamx_stats *stats) {
+    std::unique_ptr<EventPool> pool;
+    if (opt.profile) {
+        pool.reset(new EventPool(2 * (size_t)k));
+        if (!pool->ok()) return fail(PAMX_ERR_HIP, "hipEventCreate failed");
+    }
+    HIP_TRY(run_build<T>(D, ld, L, k, opt.build_exclude_self, medoids, ws, s,
+                         pool ? pool->ev.data() : nullptr));
     DevState st;
     int rc = read_state(L, ws, s, &st);
     if (rc) return rc;
     if (st.bad_medoids) return fail(PAMX_ERR_HIP, "BUILD found no candidate");
     if (td) *td = st.td;
+    if (stats && pool) {
+        stats->ms_build_pass = pool->sum(k);
+        stats->n_build_pass = k;
+    }
     return PAMX_OK;
 }
 
@@ -283,19 +322,37 @@ int swap_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const pamx_opt
         return fail(PAMX_ERR_INVALID_MEDOIDS, "medoids must be distinct and in [0, n)");
     tm.rec(2, s);
     int enq = 0;
+    double ms_pass = 0.0;
+    int n_pass = 0;
     if (k >= 2 && k < n) {
+        constexpr int kMaxBatch = 32;
+        std::unique_ptr<EventPool> pool;
+        if (opt.profile) {
+            pool.reset(new EventPool(2 * kMaxBatch));
+            if (!pool->ok()) return fail(PAMX_ERR_HIP, "hipEventCreate failed");
+        }
         HIP_TRY(enqueue_swap_caches<T>(D, ld, L, medoids, ws, s));
         int batch = 4;
         for (;;) {
             int b = batch;
             if (b > opt.max_iter + 1 - enq) b = opt.max_iter + 1 - enq;
             if (b < 1) b = 1;
-            for (int j = 0; j < b; ++j) HIP_TRY(enqueue_swap_iteration<T>(D, ld, L, medoids, opt, ws, s));
+            const int iter0 = st.iter;
+            for (int j = 0; j < b; ++j)
+                HIP_TRY(enqueue_swap_iteration<T>(D, ld, L, medoids, opt, ws, s,
+                                                  pool ? pool->ev[2 * j] : nullptr,
+                                                  pool ? pool->ev[2 * j + 1] : nullptr));
             enq += b;
             rc = read_state(L, ws, s, &st);
             if (rc) return rc;
+            if (pool) {
+                // passes of iterations that ran (later ones returned at once)
+                const int ran = st.iter - iter0;
+                ms_pass += pool->sum(ran);
+                n_pass += ran;
+            }
             if (st.done) break;
-            if (batch < 32) batch *= 2;
+            if (batch < kMaxBatch) batch *= 2;
         }
     }
     tm.rec(3, s);
@@ -310,6 +367,8 @@ int swap_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const pamx_opt
         stats->rescored = st.rescored;
         stats->td = st.td;
         stats->pass_pairs = (int64_t)st.iter * n * (n - k);
+        stats->ms_swap_pass = ms_pass;
+        stats->n_swap_pass = n_pass;
     }
     return st.capped ? PAMX_WARN_MAXITER : PAMX_OK;
 }
@@ -342,8 +401,10 @@ extern "C" int pamx_build(const void *D, int32_t dtype, int64_t n, int64_t ld, i
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (dtype == PAMX_F32)
-        return build_impl<float>(static_cast<const float *>(D), ld, L, k, opt, medoids, td, ws, s);
-    return build_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, opt, medoids, td, ws, s);
+        return build_impl<float>(static_cast<const float *>(D), ld, L, k, opt, medoids, td, ws, s,
+                                 nullptr);
+    return build_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, opt, medoids, td, ws, s,
+                               nullptr);
 }
 
 extern "C" int pamx_swap(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
@@ -425,10 +486,14 @@ extern "C" int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int
     }
     tm.rec(1, s);
     double td_build = 0.0;
+    pamx_stats bst;
+    std::memset(&bst, 0, sizeof(bst));
     if (dtype == PAMX_F32)
-        rc = build_impl<float>(static_cast<const float *>(D), ld, L, k, opt, medoids, &td_build, ws, s);
+        rc = build_impl<float>(static_cast<const float *>(D), ld, L, k, opt, medoids, &td_build, ws, s,
+                               &bst);
     else
-        rc = build_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, opt, medoids, &td_build, ws, s);
+        rc = build_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, opt, medoids, &td_build,
+                                 ws, s, &bst);
     if (rc) return rc;
     if (dtype == PAMX_F32)
         rc = swap_impl<float>(static_cast<const float *>(D), ld, L, k, opt, medoids, labels, td, stats,
@@ -446,6 +511,8 @@ extern "C" int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int
         stats->ms_swap = tm.ms(2, 3);
         stats->ms_total = tm.ms(0, 4);
         stats->build_pairs = (int64_t)k * n * n;
+        stats->ms_build_pass = bst.ms_build_pass;
+        stats->n_build_pass = bst.n_build_pass;
     }
     return rc;
 }

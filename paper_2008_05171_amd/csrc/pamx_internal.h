@@ -108,14 +108,15 @@ hipError_t launch_dist_l2_f32(const float *X, int64_t n, int32_t dim, float *D, 
 
 template <typename T>
 hipError_t run_build(const T *D, int64_t ld, const Layout &L, int32_t k, int32_t exclude_self,
-                     int32_t *medoids, void *ws, hipStream_t s);
+                     int32_t *medoids, void *ws, hipStream_t s, hipEvent_t *ev);
 
 template <typename T>
 hipError_t enqueue_swap_init(const T *D, int64_t ld, const Layout &L, const int32_t *medoids,
                              const pamx_options &opt, void *ws, hipStream_t s);
 template <typename T>
 hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32_t *medoids,
-                                  const pamx_options &opt, void *ws, hipStream_t s);
+                                  const pamx_options &opt, void *ws, hipStream_t s,
+                                  hipEvent_t ev0, hipEvent_t ev1);
 template <typename T>
 hipError_t enqueue_finalize(const T *D, int64_t ld, const Layout &L, const int32_t *medoids,
                             int32_t *labels, void *ws, hipStream_t s);

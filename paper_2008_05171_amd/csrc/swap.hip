@@ -248,7 +248,7 @@ __global__ __launch_bounds__(1024) void k_td_sum(const T *__restrict__ dn, int64
 
 template <typename T>
 hipError_t run_build(const T *D, int64_t ld, const Layout &L, int32_t k, int32_t exclude_self,
-                     int32_t *medoids, void *ws, hipStream_t s) {
+                     int32_t *medoids, void *ws, hipStream_t s, hipEvent_t *ev) {
     using A = AccT<T>;
     char *w = static_cast<char *>(ws);
     const int64_t n = L.n;
@@ -264,12 +264,14 @@ hipError_t run_build(const T *D, int64_t ld, const Layout &L, int32_t k, int32_t
     fill<T>(dn, n, VT<T>::inf(), s);
     const dim3 pgrid(L.n_ctiles, L.Q);
     for (int32_t t = 0; t < k; ++t) {
+        if (ev) (void)hipEventRecord(ev[2 * t], s);
         if (L.vec == 4)
             hipLaunchKernelGGL((k_build_pass<T, 4>), pgrid, dim3(kWG), 0, s, D, ld, n,
                                (const T *)dn, L.L, L.ncp, part);
         else
             hipLaunchKernelGGL((k_build_pass<T, 1>), pgrid, dim3(kWG), 0, s, D, ld, n,
                                (const T *)dn, L.L, L.ncp, part);
+        if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
         hipLaunchKernelGGL(k_build_merge<T>, dim3(L.n_mwg), dim3(kWG), 0, s, (const A *)part, L.Q,
                            L.ncp, n, (const T *)dn, (const uint8_t *)is_med,
                            (int32_t)(exclude_self && t > 0), wg_v, wg_c);
@@ -902,7 +904,8 @@ static hipError_t enqueue_caches(const T *D, int64_t ld, const Layout &L, const 
 
 template <typename T>
 hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32_t *medoids,
-                                  const pamx_options &opt, void *ws, hipStream_t s) {
+                                  const pamx_options &opt, void *ws, hipStream_t s,
+                                  hipEvent_t ev0, hipEvent_t ev1) {
     using A = AccT<T>;
     auto p = ptrs<T>(L, ws);
     const int64_t n = L.n;
@@ -922,6 +925,7 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
     hipLaunchKernelGGL(k_seg_const<T>, dim3((k + 3) / 4), dim3(256), 0, s, (const T *)p.sdn,
                        (const int32_t *)p.seg_off, k, p.segc, (const DevState *)p.st);
     const dim3 pgrid(L.n_ctiles, L.Q);
+    if (ev0) (void)hipEventRecord(ev0, s);
 #define PAMX_PASS(VEC, P2)                                                                    \
     hipLaunchKernelGGL((k_swap_pass<T, VEC, P2>), pgrid, dim3(kWG), 0, s, D, ld, n, k,       \
                        (const int32_t *)p.srow, (const T *)p.sdn, (const T *)p.sds,           \
@@ -931,6 +935,7 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
     if (L.vec == 4) { if (p2) PAMX_PASS(4, true); else PAMX_PASS(4, false); }
     else { if (p2) PAMX_PASS(1, true); else PAMX_PASS(1, false); }
 #undef PAMX_PASS
+    if (ev1) (void)hipEventRecord(ev1, s);
     if (p2) {
         hipLaunchKernelGGL((k_swap_merge<T, true>), dim3(L.n_mwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
@@ -977,13 +982,13 @@ hipError_t enqueue_swap_caches(const T *D, int64_t ld, const Layout &L, const in
 // explicit instantiations
 #define PAMX_INST(T)                                                                           \
     template hipError_t run_build<T>(const T *, int64_t, const Layout &, int32_t, int32_t,     \
-                                     int32_t *, void *, hipStream_t);                          \
+                                     int32_t *, void *, hipStream_t, hipEvent_t *);            \
     template hipError_t enqueue_swap_init<T>(const T *, int64_t, const Layout &,               \
                                              const int32_t *, const pamx_options &, void *,    \
                                              hipStream_t);                                     \
     template hipError_t enqueue_swap_iteration<T>(const T *, int64_t, const Layout &,          \
                                                   int32_t *, const pamx_options &, void *,     \
-                                                  hipStream_t);                                \
+                                                  hipStream_t, hipEvent_t, hipEvent_t);        \
     template hipError_t enqueue_finalize<T>(const T *, int64_t, const Layout &,                \
                                             const int32_t *, int32_t *, void *, hipStream_t);  \
     template hipError_t enqueue_swap_caches<T>(const T *, int64_t, const Layout &,             \

@@ -27,7 +27,7 @@ class pamx_options(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("accum", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("build_exclude_self", ctypes.c_int32),
                 ("trace_cap", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("trace", ctypes.c_void_p)]
+                ("profile", ctypes.c_int32), ("trace", ctypes.c_void_p)]
 
 
 class pamx_swap_record(ctypes.Structure):
@@ -40,7 +40,9 @@ class pamx_stats(ctypes.Structure):
                 ("td_build", ctypes.c_double), ("td", ctypes.c_double),
                 ("ms_dist", ctypes.c_double), ("ms_build", ctypes.c_double),
                 ("ms_swap", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("pass_pairs", ctypes.c_int64), ("build_pairs", ctypes.c_int64)]
+                ("pass_pairs", ctypes.c_int64), ("build_pairs", ctypes.c_int64),
+                ("ms_swap_pass", ctypes.c_double), ("ms_build_pass", ctypes.c_double),
+                ("n_swap_pass", ctypes.c_int32), ("n_build_pass", ctypes.c_int32)]
 
 
 EXPORTS = ("pamx_default_options", "pamx_workspace_bytes", "pamx_dist", "pamx_build",
@@ -63,7 +65,7 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libpamx.so is not built (%s); run "
-                           "`python -m paper_2008_05171_amd.build`" % path)
+                           "`python -m paper_2008_05171_amd.buildlib`" % path)
     lib = ctypes.CDLL(path)
     P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     opt_p = ctypes.POINTER(pamx_options)

@@ -15,8 +15,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(abi.LIB_PATH):
-        from paper_2008_05171_amd import build
-        build.build()
+        from paper_2008_05171_amd import buildlib
+        buildlib.build()
     return abi.load()
 
 
@@ -33,15 +33,15 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_struct_sizes_match_header():
-    assert ctypes.sizeof(abi.pamx_options) == 32
+    assert ctypes.sizeof(abi.pamx_options) == 40
     assert ctypes.sizeof(abi.pamx_swap_record) == 16
-    assert ctypes.sizeof(abi.pamx_stats) == 80
+    assert ctypes.sizeof(abi.pamx_stats) == 104
 
 
 def test_default_options(lib):
     o = abi.pamx_default_options()
-    assert (o.variant, o.accum, o.max_iter, o.build_exclude_self, o.trace_cap, o.chunk) == \
-        (abi.PAMX_FASTPAM1, abi.PAMX_ACC_F64, 10000, 0, 0, 0)
+    assert (o.variant, o.accum, o.max_iter, o.build_exclude_self, o.trace_cap, o.chunk,
+            o.profile) == (abi.PAMX_FASTPAM1, abi.PAMX_ACC_F64, 10000, 0, 0, 0, 0)
 
 
 def test_workspace_bytes_grows_and_validates(lib):
