@@ -50,10 +50,11 @@ static size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
 namespace pamx {
 
-// Chunk length: enough object chunks that the pass grid has ~1024
-// work-groups (4 per CU), each chunk a multiple of 8 objects.
+// Chunk length: enough object chunks that the pass grid has ~512
+// work-groups (2 per CU; measured best on the 20000-point workload), each
+// chunk a multiple of 8 objects.
 static int32_t auto_chunk(int64_t n, int32_t n_ctiles) {
-    int64_t Q = (1024 + n_ctiles - 1) / n_ctiles;
+    int64_t Q = (512 + n_ctiles - 1) / n_ctiles;
     const int64_t qmax = (n + 63) / 64;
     if (Q > qmax) Q = qmax;
     if (Q < 1) Q = 1;
@@ -121,6 +122,7 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->list = take((size_t)(n > k ? n : k) * 4);
     L->list_v = take(8);
     L->list_i = take(8);
+    L->rlist = take((size_t)n * 4);
     L->state = take(sizeof(DevState));
     L->total = off;
     return PAMX_OK;

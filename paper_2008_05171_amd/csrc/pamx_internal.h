@@ -13,7 +13,7 @@ namespace pamx {
 
 constexpr int kWG = 256;          // threads per work-group in pass kernels
 constexpr int kObjBlk = 256;      // objects per block in segment kernels
-constexpr int kMaxK = 16384;      // largest k accepted (slot histogram in LDS)
+constexpr int kMaxK = 16000;      // largest k accepted (slot histogram and offsets in LDS)
 
 // Accumulator and "infinity" per element type.  Integer dissimilarities are
 // summed exactly in int64; float32 ones in FP64 (or FP32 with re-scoring).
@@ -89,7 +89,7 @@ struct Layout {
     size_t cand_v, cand_i, cand_a;
     size_t wg_v, wg_i, wg_c;
     size_t P, slot_v, slot_c;
-    size_t list, list_v, list_i;
+    size_t list, list_v, list_i, rlist;
     size_t state;
     size_t total;
     int64_t ld_fit;      // row stride of the stored matrix in pamx_fit

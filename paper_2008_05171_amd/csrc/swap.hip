@@ -182,7 +182,16 @@ __global__ __launch_bounds__(kWG) void k_build_merge(const AccT<T> *__restrict__
     int ci = INT_MAX;
     if (c < n && !is_med[c]) {
         A s = 0;
-        for (int q = 0; q < Q; ++q) s += part[(int64_t)q * ncp + c];
+        const A *pc = part + c;
+        int q = 0;
+        for (; q + 8 <= Q; q += 8) {           // loads first, then the adds in chunk order
+            A x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = pc[(int64_t)(q + u) * ncp];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += x[u];
+        }
+        for (; q < Q; ++q) s += pc[(int64_t)q * ncp];
         if (add_self) s += (A)dn[c];   // literal Alg. 1: x_c's own gain not counted
         v = s;
         ci = (int)c;
@@ -288,21 +297,71 @@ hipError_t run_build(const T *D, int64_t ld, const Layout &L, int32_t k, int32_t
 // ---- nearest / second nearest of every object (O(nk), rows of the medoids)
 // Order on (distance, slot) is lexicographic: nearest is the smallest slot at
 // the minimum distance and ds the minimum over the other slots.
+template <typename T> struct Top2 {
+    T d1, d2;
+    int32_t j1, j2;   // INT_MAX = none
+};
+
 template <typename T>
-__device__ __forceinline__ void scan_medoids(const T *__restrict__ D, int64_t ld, int k,
-                                             const int32_t *__restrict__ med, int64_t o,
-                                             int32_t &nr, int32_t &sc, T &dn, T &ds) {
-    nr = -1; sc = -1;
-    dn = VT<T>::inf(); ds = VT<T>::inf();
-    for (int j = 0; j < k; ++j) {
-        const T d = D[(int64_t)med[j] * ld + o];
-        if (nr < 0 || d < dn) {
-            sc = nr; ds = dn;
-            nr = j; dn = d;
-        } else if (sc < 0 || d < ds) {
-            sc = j; ds = d;
+__device__ __forceinline__ void top2_insert(Top2<T> &t, T d, int32_t j) {
+    if (lt2(d, j, t.d1, t.j1)) {
+        t.d2 = t.d1; t.j2 = t.j1;
+        t.d1 = d; t.j1 = j;
+    } else if (lt2(d, j, t.d2, t.j2)) {
+        t.d2 = d; t.j2 = j;
+    }
+}
+
+// Fresh scan for one object (lanes = objects): rows of the medoids are read
+// at column o, coalesced across the wave, 8 loads in flight.
+template <typename T>
+__device__ __forceinline__ Top2<T> scan_medoids(const T *__restrict__ D, int64_t ld, int k,
+                                                const int32_t *__restrict__ med, int64_t o) {
+    Top2<T> t{VT<T>::inf(), VT<T>::inf(), INT_MAX, INT_MAX};
+    int j = 0;
+    for (; j + 8 <= k; j += 8) {
+        T d[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) d[u] = D[(int64_t)med[j + u] * ld + o];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) top2_insert(t, d[u], j + u);
+    }
+    for (; j < k; ++j) top2_insert(t, D[(int64_t)med[j] * ld + o], j);
+    return t;
+}
+
+// Rescan of one object by a whole wave: lanes take slots lane, lane+64, ...
+// (row o of D at the medoid columns), then a butterfly merges the per-lane
+// top-2 lists.  Every lane returns the same result.
+template <typename T>
+__device__ __forceinline__ Top2<T> wave_scan_medoids(const T *__restrict__ D, int64_t ld, int k,
+                                                     const int32_t *__restrict__ med, int64_t o,
+                                                     int lane) {
+    Top2<T> t{VT<T>::inf(), VT<T>::inf(), INT_MAX, INT_MAX};
+    const T *row = D + o * ld;
+    for (int j = lane; j < k; j += 64) top2_insert(t, row[med[j]], j);
+    for (int w = 32; w >= 1; w >>= 1) {
+        const T e1 = __shfl_xor(t.d1, w), e2 = __shfl_xor(t.d2, w);
+        const int32_t f1 = __shfl_xor(t.j1, w), f2 = __shfl_xor(t.j2, w);
+        if (lt2(e1, f1, t.d1, t.j1)) {
+            if (lt2(e2, f2, t.d1, t.j1)) { t.d2 = e2; t.j2 = f2; }
+            else { t.d2 = t.d1; t.j2 = t.j1; }
+            t.d1 = e1; t.j1 = f1;
+        } else if (lt2(e1, f1, t.d2, t.j2)) {
+            t.d2 = e1; t.j2 = f1;
         }
     }
+    return t;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_top2(const Top2<T> &t, int64_t o, int32_t *__restrict__ near,
+                                           int32_t *__restrict__ sec, T *__restrict__ dn,
+                                           T *__restrict__ ds) {
+    near[o] = t.j1;
+    sec[o] = (t.j2 == INT_MAX) ? -1 : t.j2;
+    dn[o] = t.d1;
+    ds[o] = t.d2;
 }
 
 template <typename T>
@@ -313,11 +372,9 @@ __global__ __launch_bounds__(256) void k_cache_init(const T *__restrict__ D, int
                                                     T *__restrict__ ds, int32_t *__restrict__ labels) {
     const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (o >= n) return;
-    int32_t nr, sc;
-    T a, b;
-    scan_medoids<T>(D, ld, k, med, o, nr, sc, a, b);
-    near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b;
-    if (labels) labels[o] = nr;
+    const Top2<T> t = scan_medoids<T>(D, ld, k, med, o);
+    store_top2<T>(t, o, near, sec, dn, ds);
+    if (labels) labels[o] = t.j1;
 }
 
 // Input check: medoids distinct and in range (uses `mark` zeroed beforehand).
@@ -333,30 +390,29 @@ __global__ __launch_bounds__(256) void k_check_medoids(const int32_t *__restrict
     is_med[m] = 1;
 }
 
-// ---- per-object cache update after slot `slot` received medoid `c`.
-// Objects that keep both nearest and second medoid only compare against the
-// new one; objects that lost one of them scan all k medoids again.
+// ---- per-object cache update after slot `slot` received a new medoid.
+// An object that keeps both its nearest and its second medoid only compares
+// against the new one (O(1)); an object that lost one of them needs all k
+// medoids again and is returned as "rescan" (done by wave_scan_medoids).
 template <typename T>
-__device__ __forceinline__ void cache_update_one(const T *__restrict__ D, int64_t ld, int k,
-                                                 const int32_t *__restrict__ med, int64_t o, int slot,
-                                                 T dnew, int32_t &nr, int32_t &sc, T &dn, T &ds) {
-    if (nr == slot || sc == slot) {
-        scan_medoids<T>(D, ld, k, med, o, nr, sc, dn, ds);
-    } else if (lt2(dnew, slot, dn, nr)) {
+__device__ __forceinline__ bool cache_update_o1(int slot, T dnew, int32_t &nr, int32_t &sc, T &dn,
+                                                T &ds) {
+    if (nr == slot || sc == slot) return true;
+    if (lt2(dnew, slot, dn, nr)) {
         sc = nr; ds = dn;
         nr = slot; dn = dnew;
-    } else if (lt2(dnew, slot, ds, sc)) {
+    } else if (lt2(dnew, slot, ds, sc < 0 ? INT_MAX : sc)) {
         sc = slot; ds = dnew;
     }
+    return false;
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_cache_update(const T *__restrict__ D, int64_t ld, int64_t n,
-                                                      int32_t k, const int32_t *__restrict__ med,
                                                       int32_t *__restrict__ near,
                                                       int32_t *__restrict__ sec, T *__restrict__ dn,
-                                                      T *__restrict__ ds,
-                                                      const DevState *__restrict__ st) {
+                                                      T *__restrict__ ds, int32_t *__restrict__ rlist,
+                                                      DevState *__restrict__ st) {
     if (st->done || !st->swapped) return;
     const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (o >= n) return;
@@ -364,14 +420,38 @@ __global__ __launch_bounds__(256) void k_cache_update(const T *__restrict__ D, i
     const T dnew = D[(int64_t)st->new_med * ld + o];
     int32_t nr = near[o], sc = sec[o];
     T a = dn[o], b = ds[o];
-    cache_update_one<T>(D, ld, k, med, o, slot, dnew, nr, sc, a, b);
-    near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b;
+    if (cache_update_o1<T>(slot, dnew, nr, sc, a, b)) {
+        rlist[atomicAdd(&st->n_list, 1)] = (int32_t)o;
+    } else {
+        near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b;
+    }
 }
 
-// ---- iteration start: iteration cap
-__global__ void k_iter_begin(DevState *st) {
-    if (threadIdx.x != 0 || st->done) return;
+// One wave per listed object (the list order varies, each result does not).
+template <typename T>
+__global__ __launch_bounds__(256) void k_cache_rescan(const T *__restrict__ D, int64_t ld, int32_t k,
+                                                      const int32_t *__restrict__ med,
+                                                      int32_t *__restrict__ near,
+                                                      int32_t *__restrict__ sec, T *__restrict__ dn,
+                                                      T *__restrict__ ds,
+                                                      const int32_t *__restrict__ rlist,
+                                                      const DevState *__restrict__ st) {
+    if (st->done || !st->swapped) return;
+    const int lane = threadIdx.x & 63;
+    const int nw = gridDim.x * 4;
+    const int m = st->n_list;
+    for (int idx = blockIdx.x * 4 + (threadIdx.x >> 6); idx < m; idx += nw) {
+        const int64_t o = rlist[idx];
+        const Top2<T> t = wave_scan_medoids<T>(D, ld, k, med, o, lane);
+        if (lane == 0) store_top2<T>(t, o, near, sec, dn, ds);
+    }
+}
+
+// ---- iteration start (folded into the first block of k_seg_count): the
+// iteration cap, and the per-iteration flags.
+__device__ __forceinline__ void iter_begin(DevState *st) {
     st->swapped = 0;
+    st->n_list = 0;
     if (st->iter >= st->max_iter) {
         st->done = 1;
         st->capped = 1;
@@ -381,8 +461,9 @@ __global__ void k_iter_begin(DevState *st) {
 // ---- stable counting sort of objects by nearest slot
 __global__ __launch_bounds__(kObjBlk) void k_seg_count(const int32_t *__restrict__ near, int64_t n,
                                                        int32_t k, int32_t *__restrict__ blkcnt,
-                                                       const DevState *__restrict__ st) {
+                                                       DevState *__restrict__ st) {
     if (st->done) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) iter_begin(st);
     extern __shared__ int32_t hist[];
     for (int i = threadIdx.x; i < k; i += kObjBlk) hist[i] = 0;
     __syncthreads();
@@ -393,42 +474,56 @@ __global__ __launch_bounds__(kObjBlk) void k_seg_count(const int32_t *__restrict
     for (int i = threadIdx.x; i < k; i += kObjBlk) dst[i] = hist[i];
 }
 
+// Exclusive prefix over blocks of each slot's counts (in place), one wave per
+// slot; seg_size[i] = the slot's total.
+__global__ __launch_bounds__(256) void k_seg_colscan(int32_t *__restrict__ blkcnt, int32_t nblk,
+                                                     int32_t k, int32_t *__restrict__ seg_size,
+                                                     const DevState *__restrict__ st) {
+    if (st->done) return;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= k) return;
+    int32_t carry = 0;
+    for (int b0 = 0; b0 < nblk; b0 += 64) {
+        const int b = b0 + lane;
+        const int32_t c = (b < nblk) ? blkcnt[(int64_t)b * k + i] : 0;
+        int32_t x = c;   // inclusive wave scan
+        for (int w = 1; w < 64; w <<= 1) {
+            const int32_t y = __shfl_up(x, w);
+            if (lane >= w) x += y;
+        }
+        if (b < nblk) blkcnt[(int64_t)b * k + i] = carry + x - c;
+        carry += __shfl(x, 63);
+    }
+    if (lane == 0) seg_size[i] = carry;
+}
+
 struct ChunkInfo {
     int32_t sa, sb, flags;  // segment of the first / last object, carry flags
 };
 constexpr int kHead = 1, kTail = 2;
 
-// Per-slot totals, block bases, segment offsets, the smallest empty slot,
-// TD and sum of ds (for the rounding bound), and the carry map of every chunk.
+// Segment offsets (scan of the slot totals), the smallest empty slot, TD and
+// sum of ds (for the rounding bound), and the carry map of every chunk.
+// seg_off[1..k] holds the slot totals on entry.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_seg_scan(int32_t *__restrict__ blkcnt, int32_t nblk,
-                                                   int32_t k, int64_t n, int32_t *__restrict__ seg_off,
+__global__ __launch_bounds__(1024) void k_seg_scan(int32_t k, int64_t n, int32_t *__restrict__ seg_off,
                                                    const T *__restrict__ dn, const T *__restrict__ ds,
                                                    int32_t L, int32_t Q, ChunkInfo *__restrict__ cinfo,
                                                    DevState *__restrict__ st) {
     using A = AccT<T>;
     if (st->done) return;
+    extern __shared__ int32_t soff[];    // k + 1 offsets
     __shared__ int32_t carry;
     __shared__ int32_t empty_min;
-    const int t = threadIdx.x;
-    if (t == 0) { carry = 0; empty_min = k; }
-    // totals per slot (reuse seg_off[i+1] as the total, then scan)
-    for (int i = t; i < k; i += 1024) {
-        int32_t run = 0;
-        for (int b = 0; b < nblk; ++b) {
-            const int32_t c = blkcnt[(int64_t)b * k + i];
-            blkcnt[(int64_t)b * k + i] = run;  // exclusive prefix over blocks
-            run += c;
-        }
-        seg_off[i + 1] = run;
-        if (run == 0) atomicMin(&empty_min, i);
-    }
-    __syncthreads();
-    // exclusive scan of totals, 1024 at a time
     __shared__ int32_t buf[1024];
+    const int t = threadIdx.x;
+    if (t == 0) { carry = 0; empty_min = k; soff[0] = 0; }
+    __syncthreads();
     for (int base = 0; base < k; base += 1024) {
         const int i = base + t;
         const int32_t v = (i < k) ? seg_off[i + 1] : 0;
+        if (i < k && v == 0) atomicMin(&empty_min, i);
         buf[t] = v;
         __syncthreads();
         for (int w = 1; w < 1024; w <<= 1) {
@@ -437,36 +532,29 @@ __global__ __launch_bounds__(1024) void k_seg_scan(int32_t *__restrict__ blkcnt,
             buf[t] += x;
             __syncthreads();
         }
-        if (i < k) seg_off[i + 1] = carry + buf[t];   // inclusive
+        if (i < k) soff[i + 1] = carry + buf[t];   // inclusive
         __syncthreads();
         if (t == 1023) carry += buf[1023];
         __syncthreads();
     }
-    if (t == 0) seg_off[0] = 0;
-    __syncthreads();
-    // add segment starts to the block bases
-    for (int i = t; i < k; i += 1024) {
-        const int32_t s0 = seg_off[i];
-        for (int b = 0; b < nblk; ++b) blkcnt[(int64_t)b * k + i] += s0;
-    }
+    for (int i = t; i <= k; i += 1024) seg_off[i] = soff[i];
     // TD and sum of ds, fixed order
     A s1 = 0, s2 = 0;
     for (int64_t o = t; o < n; o += 1024) { s1 += (A)dn[o]; s2 += (A)ds[o]; }
     s1 = block_sum<A, 1024>(s1);
     s2 = block_sum<A, 1024>(s2);
-    __syncthreads();
-    // carry map of each chunk
+    // carry map of each chunk (binary searches in LDS)
     for (int q = t; q < Q; q += 1024) {
         const int64_t a = (int64_t)q * L, b = min(a + (int64_t)L, n);
         int lo = 0, hi = k;
-        while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (seg_off[m] <= a) lo = m; else hi = m; }
+        while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (soff[m] <= a) lo = m; else hi = m; }
         const int sa = lo;
         lo = 0; hi = k;
-        while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (seg_off[m] <= b - 1) lo = m; else hi = m; }
+        while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (soff[m] <= b - 1) lo = m; else hi = m; }
         const int sb = lo;
         int f = 0;
-        if (seg_off[sa] < a || seg_off[sa + 1] > b) f |= kHead;
-        if (sb != sa && seg_off[sb + 1] > b) f |= kTail;
+        if (soff[sa] < a || soff[sa + 1] > b) f |= kHead;
+        if (sb != sa && soff[sb + 1] > b) f |= kTail;
         cinfo[q] = ChunkInfo{sa, sb, f};
     }
     if (t == 0) {
@@ -484,13 +572,14 @@ __global__ __launch_bounds__(1024) void k_seg_scan(int32_t *__restrict__ blkcnt,
     }
 }
 
-// Scatter objects to their sorted position: block base + rank among the
-// block's objects of the same slot (stable).
+// Scatter objects to their sorted position: segment start + block base +
+// rank among the block's objects of the same slot (stable).
 template <typename T>
 __global__ __launch_bounds__(kObjBlk) void k_seg_scatter(const int32_t *__restrict__ near,
                                                          const T *__restrict__ dn,
                                                          const T *__restrict__ ds, int64_t n,
                                                          int32_t k, const int32_t *__restrict__ blkbase,
+                                                         const int32_t *__restrict__ seg_off,
                                                          int32_t *__restrict__ srow,
                                                          T *__restrict__ sdn, T *__restrict__ sds,
                                                          const DevState *__restrict__ st) {
@@ -504,7 +593,7 @@ __global__ __launch_bounds__(kObjBlk) void k_seg_scatter(const int32_t *__restri
     if (o >= n) return;
     int rank = 0;
     for (int u = 0; u < t; ++u) rank += (ln[u] == s);
-    const int32_t pos = blkbase[(int64_t)blockIdx.x * k + s] + rank;
+    const int32_t pos = seg_off[s] + blkbase[(int64_t)blockIdx.x * k + s] + rank;
     srow[pos] = (int32_t)o;
     sdn[pos] = dn[o];
     sds[pos] = ds[o];
@@ -648,24 +737,35 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
                 if constexpr (P2) P[(int64_t)run_s * ncp + c] = v;
             }
         };
-        for (int q = 0; q < Q; ++q) {
-            const ChunkInfo ci = cinfo[q];
-            const A *pq = part + (int64_t)q * 4 * ncp + c;
-            accA += pq[0];
-            const int32_t i = part_i[(int64_t)q * ncp + c];
-            if (i != INT_MAX) {
-                const A v = pq[3 * ncp];
-                if (lt2(v, i, bestv, besti)) { bestv = v; besti = i; }
+        constexpr int UQ = 4;   // chunks whose partials are loaded together
+        for (int q0 = 0; q0 < Q; q0 += UQ) {
+            A xa[UQ], xh[UQ], xt[UQ], xv[UQ];
+            int32_t xi[UQ];
+#pragma unroll
+            for (int u = 0; u < UQ; ++u) {
+                if (q0 + u < Q) {
+                    const A *pq = part + (int64_t)(q0 + u) * 4 * ncp + c;
+                    xa[u] = pq[0];
+                    xh[u] = pq[1 * ncp];   // read even when unused (never written then)
+                    xt[u] = pq[2 * ncp];
+                    xv[u] = pq[3 * ncp];
+                    xi[u] = part_i[(int64_t)(q0 + u) * ncp + c];
+                }
             }
-            if (ci.flags & kHead) {
-                const A m = pq[1 * ncp];
-                if (ci.sa == run_s) run_m += m;
-                else { flush(); run_s = ci.sa; run_m = m; }
-            }
-            if (ci.flags & kTail) {
-                const A m = pq[2 * ncp];
-                if (ci.sb == run_s) run_m += m;
-                else { flush(); run_s = ci.sb; run_m = m; }
+#pragma unroll
+            for (int u = 0; u < UQ; ++u) {
+                if (q0 + u >= Q) break;
+                const ChunkInfo ci = cinfo[q0 + u];
+                accA += xa[u];
+                if (xi[u] != INT_MAX && lt2(xv[u], xi[u], bestv, besti)) { bestv = xv[u]; besti = xi[u]; }
+                if (ci.flags & kHead) {
+                    if (ci.sa == run_s) run_m += xh[u];
+                    else { flush(); run_s = ci.sa; run_m = xh[u]; }
+                }
+                if (ci.flags & kTail) {
+                    if (ci.sb == run_s) run_m += xt[u];
+                    else { flush(); run_s = ci.sb; run_m = xt[u]; }
+                }
             }
         }
         flush();
@@ -769,13 +869,15 @@ __global__ __launch_bounds__(1024) void k_eager_apply(
     const T *__restrict__ D, int64_t ld, int64_t n, int32_t k, int32_t *__restrict__ med,
     uint8_t *__restrict__ is_med, int32_t *__restrict__ near, int32_t *__restrict__ sec,
     T *__restrict__ dn, T *__restrict__ ds, const AccT<T> *__restrict__ slot_v,
-    const int32_t *__restrict__ slot_c, int32_t *__restrict__ order, DevState *__restrict__ st,
-    pamx_swap_record *__restrict__ trace) {
+    const int32_t *__restrict__ slot_c, int32_t *__restrict__ order, int32_t *__restrict__ rlist,
+    DevState *__restrict__ st, pamx_swap_record *__restrict__ trace) {
     using A = AccT<T>;
     if (st->done) return;
     __shared__ int32_t cnt;
     __shared__ int32_t go;
+    __shared__ int32_t nres;
     const int t = threadIdx.x;
+    const int lane = t & 63;
     A thr;
     if constexpr (std::is_same<T, float>::value) thr = -st->margin; else thr = 0;
     if (t == 0) cnt = 0;
@@ -808,7 +910,7 @@ __global__ __launch_bounds__(1024) void k_eager_apply(
             else s += (A)vmin(d, a) - (A)a;                    // cases (a), (c)
         }
         s = block_sum<A, 1024>(s);
-        if (t == 0) go = (s < thr) ? 1 : 0;
+        if (t == 0) { go = (s < thr) ? 1 : 0; nres = 0; }
         __syncthreads();
         if (!go) { __syncthreads(); continue; }
         if (t == 0) {
@@ -824,8 +926,18 @@ __global__ __launch_bounds__(1024) void k_eager_apply(
         for (int64_t o = t; o < n; o += 1024) {
             int32_t nr = near[o], sc = sec[o];
             T a = dn[o], b2 = ds[o];
-            cache_update_one<T>(D, ld, k, med, o, i, rowc[o], nr, sc, a, b2);
-            near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b2;
+            if (cache_update_o1<T>(i, rowc[o], nr, sc, a, b2)) {
+                rlist[atomicAdd(&nres, 1)] = (int32_t)o;
+            } else {
+                near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b2;
+            }
+        }
+        __syncthreads();
+        const int mr = nres;
+        for (int idx = t >> 6; idx < mr; idx += 16) {
+            const int64_t o = rlist[idx];
+            const Top2<T> tt = wave_scan_medoids<T>(D, ld, k, med, o, lane);
+            if (lane == 0) store_top2<T>(tt, o, near, sec, dn, ds);
         }
         ++applied;
         __syncthreads();
@@ -839,7 +951,7 @@ __global__ __launch_bounds__(1024) void k_eager_apply(
 // ================================================================ host side
 template <typename T>
 struct SwapPtrs {
-    int32_t *near, *sec, *srow, *blkcnt, *seg_off, *part_i, *wg_i, *wg_c, *slot_c, *order;
+    int32_t *near, *sec, *srow, *blkcnt, *seg_off, *part_i, *wg_i, *wg_c, *slot_c, *order, *rlist;
     T *dn, *ds, *sdn, *sds;
     uint8_t *is_med;
     AccT<T> *segc, *part, *wg_v, *P, *cand_a, *slot_v;
@@ -873,6 +985,7 @@ static SwapPtrs<T> ptrs(const Layout &L, void *ws) {
     p.slot_v = reinterpret_cast<AccT<T> *>(w + L.slot_v);
     p.slot_c = reinterpret_cast<int32_t *>(w + L.slot_c);
     p.order = reinterpret_cast<int32_t *>(w + L.list);
+    p.rlist = reinterpret_cast<int32_t *>(w + L.rlist);
     p.st = reinterpret_cast<DevState *>(w + L.state);
     return p;
 }
@@ -914,14 +1027,16 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
     pamx_swap_record *trace = static_cast<pamx_swap_record *>(opt.trace);
     const unsigned ob = (unsigned)((n + 255) / 256);
 
-    hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(1), 0, s, p.st);
     hipLaunchKernelGGL(k_seg_count, dim3(L.n_oblk), dim3(kObjBlk), (size_t)k * 4, s,
-                       (const int32_t *)p.near, n, k, p.blkcnt, (const DevState *)p.st);
-    hipLaunchKernelGGL(k_seg_scan<T>, dim3(1), dim3(1024), 0, s, p.blkcnt, L.n_oblk, k, n,
+                       (const int32_t *)p.near, n, k, p.blkcnt, p.st);
+    hipLaunchKernelGGL(k_seg_colscan, dim3((k + 3) / 4), dim3(256), 0, s, p.blkcnt, L.n_oblk, k,
+                       p.seg_off + 1, (const DevState *)p.st);
+    hipLaunchKernelGGL(k_seg_scan<T>, dim3(1), dim3(1024), (size_t)(k + 1) * 4, s, k, n,
                        p.seg_off, (const T *)p.dn, (const T *)p.ds, L.L, L.Q, p.cinfo, p.st);
     hipLaunchKernelGGL(k_seg_scatter<T>, dim3(L.n_oblk), dim3(kObjBlk), 0, s,
                        (const int32_t *)p.near, (const T *)p.dn, (const T *)p.ds, n, k,
-                       (const int32_t *)p.blkcnt, p.srow, p.sdn, p.sds, (const DevState *)p.st);
+                       (const int32_t *)p.blkcnt, (const int32_t *)p.seg_off, p.srow, p.sdn,
+                       p.sds, (const DevState *)p.st);
     hipLaunchKernelGGL(k_seg_const<T>, dim3((k + 3) / 4), dim3(256), 0, s, (const T *)p.sdn,
                        (const int32_t *)p.seg_off, k, p.segc, (const DevState *)p.st);
     const dim3 pgrid(L.n_ctiles, L.Q);
@@ -946,7 +1061,7 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
                            (const uint8_t *)p.is_med, p.slot_v, p.slot_c, (const DevState *)p.st);
         hipLaunchKernelGGL(k_eager_apply<T>, dim3(1), dim3(1024), 0, s, D, ld, n, k, medoids,
                            p.is_med, p.near, p.sec, p.dn, p.ds, (const A *)p.slot_v,
-                           (const int32_t *)p.slot_c, p.order, p.st, trace);
+                           (const int32_t *)p.slot_c, p.order, p.rlist, p.st, trace);
     } else {
         hipLaunchKernelGGL((k_swap_merge<T, false>), dim3(L.n_mwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
@@ -955,9 +1070,11 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
         hipLaunchKernelGGL(k_swap_select<T>, dim3(1), dim3(1024), 0, s, (const A *)p.wg_v,
                            (const int32_t *)p.wg_i, (const int32_t *)p.wg_c, L.n_mwg, medoids,
                            p.is_med, p.st, trace);
-        hipLaunchKernelGGL(k_cache_update<T>, dim3(ob), dim3(256), 0, s, D, ld, n, k,
+        hipLaunchKernelGGL(k_cache_update<T>, dim3(ob), dim3(256), 0, s, D, ld, n, p.near, p.sec,
+                           p.dn, p.ds, p.rlist, p.st);
+        hipLaunchKernelGGL(k_cache_rescan<T>, dim3(256), dim3(256), 0, s, D, ld, k,
                            (const int32_t *)medoids, p.near, p.sec, p.dn, p.ds,
-                           (const DevState *)p.st);
+                           (const int32_t *)p.rlist, (const DevState *)p.st);
     }
     return hipGetLastError();
 }

@@ -54,7 +54,7 @@ def test_workspace_bytes_grows_and_validates(lib):
     o.variant = abi.PAMX_FASTPAM2
     d = abi.pamx_workspace_bytes(20000, 100, 0, abi.PAMX_INPUT_D, abi.PAMX_F32, o)
     assert d >= b + 100 * 20480 * 8            # per-medoid change buffer
-    for args in [(0, 1), (10, 0), (10, 11), (10, 20000), (30000, 17000)]:
+    for args in [(0, 1), (10, 0), (10, 11), (10, 20000), (30000, 16001)]:
         with pytest.raises(abi.PamxError) as e:
             abi.pamx_workspace_bytes(args[0], args[1], 0, abi.PAMX_INPUT_D, abi.PAMX_F32)
         assert e.value.code == abi.PAMX_ERR_ARG
