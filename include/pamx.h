@@ -164,6 +164,44 @@ int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int64_t n, int
              int32_t *labels, double *td, pamx_stats *stats, void *ws, size_t ws_bytes,
              void *stream);
 
+typedef struct pamx_batch_stats {
+    int32_t iterations;   /* SWAP searches over all instances */
+    int32_t swaps;        /* swaps over all instances */
+    int32_t best_inst;    /* instance with the smallest full-data TD (lowest id on ties),
+                             -1 when full-data TD was not requested */
+    int32_t reserved;
+    double ms_pam;        /* device time of the batched BUILD + SWAP launch */
+    double ms_assign;     /* device time of the full-data TD kernels */
+    double ms_total;
+    int64_t pairs;        /* candidate-object pairs evaluated (BUILD + SWAP passes) */
+} pamx_batch_stats;
+
+/* Workspace bytes of pamx_fit_batched for n_inst instances. */
+int pamx_batched_workspace_bytes(int32_t n_inst, int64_t N, size_t *bytes);
+
+/* Batched CLARA (Sec. 2.1; with FastPAM1 inside, Sec. 3.4): n_inst
+ * independent PAM runs (BUILD + FastPAM1 SWAP) on subsamples of N points in
+ * one persistent launch, then the TD of every run's medoids over all N
+ * points.  Distances are computed on the fly (L2 for PAMX_F32 points, exact
+ * L1 for PAMX_I32 points); no n'^2 matrix is stored.
+ *   X           device, N x dim points, 1 <= dim <= 16
+ *   sample_off  HOST int64[n_inst+1], sample_off[0] = 0, nondecreasing;
+ *               instance j uses points sample_idx[sample_off[j] .. sample_off[j+1])
+ *   sample_idx  device int32 point indices in [0, N) (checked on the device:
+ *               PAMX_ERR_ARG), distinct within an instance
+ *   k_inst      HOST int32[n_inst], 1 <= k_j <= min(n'_j, 256), n'_j <= 2048
+ *   opt         max_iter and build_exclude_self are used (variant: FastPAM1)
+ *   medoids     device int32[sum k_j]: instance j's medoids (global point
+ *               indices, slot order) start at sum_{j'<j} k_j'
+ *   td_sample   HOST double[n_inst]: TD of each run on its own sample
+ *   td_full     HOST double[n_inst] or NULL: TD over all N points; when
+ *               given, stats->best_inst is the CLARA result */
+int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t dim, int32_t metric,
+                     int32_t n_inst, const int64_t *sample_off, const int32_t *sample_idx,
+                     const int32_t *k_inst, const pamx_options *opt, int32_t *medoids,
+                     double *td_sample, double *td_full, pamx_batch_stats *stats,
+                     void *ws, size_t ws_bytes, void *stream);
+
 /* Message for the last non-zero return on this thread ("" if none). */
 const char *pamx_last_error(void);
 

@@ -15,7 +15,7 @@ from . import pamx as _abi
 from .pamx import (PAMX_ACC_F32, PAMX_ACC_F64, PAMX_FASTPAM1, PAMX_FASTPAM2, PAMX_INPUT_D,
                    PAMX_INPUT_X, PAMX_L1, PAMX_L2, PamxError)
 
-__all__ = ["fit", "build", "swap", "dist", "FitResult", "PamxError", "PAMX_FASTPAM1",
+__all__ = ["fit", "build", "swap", "dist", "fit_batched", "FitResult", "BatchResult", "PamxError", "PAMX_FASTPAM1",
            "PAMX_FASTPAM2", "PAMX_L1", "PAMX_L2", "PAMX_ACC_F64", "PAMX_ACC_F32",
            "PAMX_INPUT_D", "PAMX_INPUT_X"]
 
@@ -131,3 +131,36 @@ def dist(X, *, metric=None, ld=None, stream=None):
     D = torch.empty((n, ld), dtype=X.dtype, device=X.device)
     _abi.pamx_dist(X, metric, D, ld=ld, stream=stream)
     return D[:, :n]
+
+
+@dataclass
+class BatchResult:
+    medoids: list            # per instance: torch.int32 [k_j] global point indices
+    td_sample: object        # numpy float64 [n_inst]
+    td_full: object          # numpy float64 [n_inst] or None
+    best: int                # instance with the smallest full-data TD (-1 if not computed)
+    rc: int
+    stats: dict
+
+
+def fit_batched(X, sample_off, sample_idx, k_inst, *, metric=None, max_iter=10000,
+                exclude_self=False, full_td=True, stream=None) -> BatchResult:
+    """Batched CLARA: PAM (BUILD + FastPAM1) on every subsample in one launch,
+    then the TD of each run over all points of X.  sample_off/k_inst are host
+    arrays, sample_idx a device int32 tensor."""
+    import numpy as np
+    import torch
+    dtype = _abi._dtype_code(X)
+    if metric is None:
+        metric = PAMX_L1 if dtype == _abi.PAMX_I32 else PAMX_L2
+    k_inst = np.asarray(k_inst, dtype=np.int32)
+    sample_off = np.asarray(sample_off, dtype=np.int64)
+    opt = _options(max_iter=max_iter, exclude_self=exclude_self)
+    ws = _workspace(_abi.pamx_batched_workspace_bytes(len(k_inst), X.shape[0]), X.device)
+    med = torch.empty(int(k_inst.sum()), dtype=torch.int32, device=X.device)
+    rc, tds, tdf, st = _abi.pamx_fit_batched(X, metric, sample_off, sample_idx, k_inst, med, ws,
+                                             opt=opt, want_full=full_td, stream=stream)
+    offs = np.concatenate([[0], np.cumsum(k_inst)])
+    meds = [med[offs[j]:offs[j + 1]] for j in range(len(k_inst))]
+    stats = {f: getattr(st, f) for f, _ in _abi.pamx_batch_stats._fields_}
+    return BatchResult(meds, tds, tdf, st.best_inst, rc, stats)

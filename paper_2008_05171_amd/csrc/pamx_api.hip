@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <type_traits>
+#include <algorithm>
 #include <memory>
 #include <vector>
 
@@ -517,4 +518,186 @@ extern "C" int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int
         stats->n_build_pass = bst.n_build_pass;
     }
     return rc;
+}
+
+// ---------------------------------------------------------------- batched CLARA
+namespace {
+constexpr int kFullBlocks = 256;   // blocks per instance in the full-data TD
+
+struct BatchLayout {
+    size_t soff, kin, moff, order, td, tdb, it, sw, ctr, part, tdf, total;
+};
+
+BatchLayout batch_layout(int32_t n_inst) {
+    BatchLayout b;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = up256(off + (bytes ? bytes : 1)); return o; };
+    b.soff = take((size_t)(n_inst + 1) * 8);
+    b.kin = take((size_t)n_inst * 4);
+    b.moff = take((size_t)(n_inst + 1) * 8);
+    b.order = take((size_t)n_inst * 4);
+    b.td = take((size_t)n_inst * 8);
+    b.tdb = take((size_t)n_inst * 8);
+    b.it = take((size_t)n_inst * 4);
+    b.sw = take((size_t)n_inst * 4);
+    b.ctr = take(2 * 4);
+    b.part = take((size_t)n_inst * kFullBlocks * 8);
+    b.tdf = take((size_t)n_inst * 8);
+    b.total = off;
+    return b;
+}
+}  // namespace
+
+extern "C" int pamx_batched_workspace_bytes(int32_t n_inst, int64_t N, size_t *bytes) {
+    if (!bytes) return fail(PAMX_ERR_ARG, "bytes is NULL");
+    if (n_inst < 1) return fail(PAMX_ERR_ARG, "n_inst must be >= 1");
+    if (N < 1) return fail(PAMX_ERR_ARG, "N must be >= 1");
+    *bytes = batch_layout(n_inst).total;
+    return PAMX_OK;
+}
+
+namespace pamx {
+template <typename X>
+__global__ void k_fill_batch(X *p, int64_t cnt, X v) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < cnt) p[t] = v;
+}
+}  // namespace pamx
+
+extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t dim, int32_t metric,
+                                int32_t n_inst, const int64_t *sample_off, const int32_t *sample_idx,
+                                const int32_t *k_inst, const pamx_options *opt_in, int32_t *medoids,
+                                double *td_sample, double *td_full, pamx_batch_stats *stats,
+                                void *ws, size_t ws_bytes, void *stream) {
+    pamx_options opt;
+    pamx_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (dtype != PAMX_I32 && dtype != PAMX_F32) return fail(PAMX_ERR_ARG, "unknown dtype %d", dtype);
+    if (N < 1 || N > (int64_t)INT32_MAX - 1) return fail(PAMX_ERR_ARG, "N out of range");
+    int rc = check_points(X, dtype, N, dim, metric);
+    if (rc) return rc;
+    if (dim > kBMaxDim) return fail(PAMX_ERR_UNSUPPORTED, "batched instances support dim <= %d", kBMaxDim);
+    if (n_inst < 1) return fail(PAMX_ERR_ARG, "n_inst must be >= 1");
+    if (!sample_off || !sample_idx || !k_inst || !medoids || !td_sample)
+        return fail(PAMX_ERR_ARG, "NULL argument");
+    if (opt.max_iter < 0) return fail(PAMX_ERR_ARG, "max_iter must be >= 0");
+    if (opt.build_exclude_self != 0 && opt.build_exclude_self != 1)
+        return fail(PAMX_ERR_ARG, "build_exclude_self must be 0 or 1");
+    if (sample_off[0] != 0) return fail(PAMX_ERR_ARG, "sample_off[0] must be 0");
+    int n_max = 0, k_max = 0;
+    std::vector<int64_t> moff(n_inst + 1, 0);
+    std::vector<std::pair<double, int32_t>> cost(n_inst);
+    for (int32_t j = 0; j < n_inst; ++j) {
+        const int64_t nj = sample_off[j + 1] - sample_off[j];
+        const int32_t kj = k_inst[j];
+        if (nj < 1) return fail(PAMX_ERR_ARG, "instance %d has an empty sample", j);
+        if (nj > kBMaxN) return fail(PAMX_ERR_UNSUPPORTED, "instance %d: sample of %lld > %d points", j,
+                                     (long long)nj, kBMaxN);
+        if (kj < 1 || kj > nj) return fail(PAMX_ERR_ARG, "instance %d: k must be in [1, n']", j);
+        if (kj > kBMaxK) return fail(PAMX_ERR_UNSUPPORTED, "instance %d: k > %d", j, kBMaxK);
+        n_max = nj > n_max ? (int)nj : n_max;
+        k_max = kj > k_max ? kj : k_max;
+        moff[j + 1] = moff[j] + kj;
+        cost[j] = {-(double)(kj + 8) * (double)nj * (double)nj, j};   // BUILD + ~8 SWAP passes
+    }
+    const size_t lds = batched_lds_bytes_host(n_max, k_max, dim, 4);
+    if (lds > 150 * 1024)
+        return fail(PAMX_ERR_UNSUPPORTED, "instance too large for one work-group's LDS (%zu B)", lds);
+    std::sort(cost.begin(), cost.end());
+    std::vector<int32_t> order(n_inst);
+    for (int32_t j = 0; j < n_inst; ++j) order[j] = cost[j].second;
+    const BatchLayout B = batch_layout(n_inst);
+    if (!ws) return fail(PAMX_ERR_WORKSPACE, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return fail(PAMX_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < B.total) return fail(PAMX_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes",
+                                        ws_bytes, B.total);
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipMemcpyAsync(w + B.soff, sample_off, (size_t)(n_inst + 1) * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w + B.kin, k_inst, (size_t)n_inst * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w + B.moff, moff.data(), (size_t)(n_inst + 1) * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w + B.order, order.data(), (size_t)n_inst * 4, hipMemcpyHostToDevice, s));
+    int32_t *ctr = reinterpret_cast<int32_t *>(w + B.ctr);
+    hipLaunchKernelGGL(k_fill_batch<int32_t>, dim3(1), dim3(256), 0, s, ctr, (int64_t)2, 0);
+    HIP_TRY(hipGetLastError());
+
+    BatchArgs a;
+    a.soff = reinterpret_cast<const int64_t *>(w + B.soff);
+    a.sidx = sample_idx;
+    a.kin = reinterpret_cast<const int32_t *>(w + B.kin);
+    a.moff = reinterpret_cast<const int64_t *>(w + B.moff);
+    a.order = reinterpret_cast<const int32_t *>(w + B.order);
+    a.n_inst = n_inst;
+    a.max_iter = opt.max_iter;
+    a.excl = opt.build_exclude_self;
+    a.n_max = n_max;
+    a.k_max = k_max;
+    a.grid = cus < n_inst ? cus : n_inst;
+    a.nblk = kFullBlocks;
+    a.med_out = medoids;
+    a.td_out = reinterpret_cast<double *>(w + B.td);
+    a.tdb_out = reinterpret_cast<double *>(w + B.tdb);
+    a.part = reinterpret_cast<double *>(w + B.part);
+    a.td_full = reinterpret_cast<double *>(w + B.tdf);
+    a.it_out = reinterpret_cast<int32_t *>(w + B.it);
+    a.sw_out = reinterpret_cast<int32_t *>(w + B.sw);
+    a.queue = ctr;
+    a.err = ctr + 1;
+
+    // every sample index in [0, N) before any instance runs
+    {
+        int32_t e0 = 0;
+        HIP_TRY(launch_check_sidx(sample_idx, sample_off[n_inst], N, ctr + 1, s));
+        HIP_TRY(hipMemcpyAsync(&e0, ctr + 1, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (e0) return fail(PAMX_ERR_ARG, "sample_idx holds an index outside [0, N)");
+    }
+    Timer tm;
+    tm.rec(0, s);
+    if (dtype == PAMX_F32) HIP_TRY(launch_clara<float>(static_cast<const float *>(X), N, dim, a, s));
+    else HIP_TRY(launch_clara<int32_t>(static_cast<const int32_t *>(X), N, dim, a, s));
+    tm.rec(1, s);
+    if (td_full) {
+        if (dtype == PAMX_F32) HIP_TRY(launch_full_assign<float>(static_cast<const float *>(X), N, dim, a, s));
+        else HIP_TRY(launch_full_assign<int32_t>(static_cast<const int32_t *>(X), N, dim, a, s));
+    }
+    tm.rec(2, s);
+    int32_t err = 0;
+    std::vector<int32_t> it(n_inst), sw(n_inst);
+    HIP_TRY(hipMemcpyAsync(&err, ctr + 1, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(td_sample, a.td_out, (size_t)n_inst * 8, hipMemcpyDeviceToHost, s));
+    if (td_full) HIP_TRY(hipMemcpyAsync(td_full, a.td_full, (size_t)n_inst * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(it.data(), a.it_out, (size_t)n_inst * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(sw.data(), a.sw_out, (size_t)n_inst * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (err) return fail(PAMX_ERR_HIP, "a medoid index outside [0, N) reached the full-data TD");
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        int64_t pairs = 0;
+        for (int32_t j = 0; j < n_inst; ++j) {
+            stats->iterations += it[j];
+            stats->swaps += sw[j];
+            const int64_t nj = sample_off[j + 1] - sample_off[j];
+            pairs += ((int64_t)k_inst[j] + it[j]) * nj * nj;
+        }
+        stats->pairs = pairs;
+        stats->best_inst = -1;
+        if (td_full) {
+            int32_t b = 0;
+            for (int32_t j = 1; j < n_inst; ++j)
+                if (td_full[j] < td_full[b]) b = j;
+            stats->best_inst = b;
+        }
+        stats->ms_pam = tm.ms(0, 1);
+        stats->ms_assign = tm.ms(1, 2);
+        stats->ms_total = tm.ms(0, 2);
+    }
+    for (int32_t j = 0; j < n_inst; ++j)
+        if (it[j] > opt.max_iter - 1 && opt.max_iter > 0 && sw[j] >= it[j]) return PAMX_WARN_MAXITER;
+    return PAMX_OK;
 }

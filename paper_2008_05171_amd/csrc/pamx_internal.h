@@ -14,6 +14,9 @@ namespace pamx {
 constexpr int kWG = 256;          // threads per work-group in pass kernels
 constexpr int kObjBlk = 256;      // objects per block in segment kernels
 constexpr int kMaxK = 16000;      // largest k accepted (slot histogram and offsets in LDS)
+constexpr int kBMaxDim = 16;      // batched instances: largest point dimension
+constexpr int kBMaxK = 256;       // batched instances: largest k
+constexpr int kBMaxN = 2048;      // batched instances: largest sample (2 candidates per lane)
 
 // Accumulator and "infinity" per element type.  Integer dissimilarities are
 // summed exactly in int64; float32 ones in FP64 (or FP32 with re-scoring).
@@ -28,6 +31,8 @@ template <> struct VT<int32_t> {
     __host__ __device__ static constexpr int32_t inf() { return INT_MAX; }
     __host__ __device__ static constexpr long long acc_inf() { return LLONG_MAX; }
 };
+
+template <typename T> using AccT = typename VT<T>::acc;
 
 // Device-resident state of one BUILD or SWAP run.  Every iteration kernel
 // reads `done` first and returns at once when it is set, so the host can
@@ -62,6 +67,75 @@ __device__ __forceinline__ bool lex_less(A va, int ia, int ca, A vb, int ib, int
     if (va != vb) return va < vb;
     if (ia != ib) return ia < ib;
     return ca < cb;
+}
+
+// ---- small device helpers shared by the kernel files
+__device__ __forceinline__ float vmin(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ int32_t vmin(int32_t a, int32_t b) { return min(a, b); }
+// median of (d, lo, hi) for lo <= hi
+__device__ __forceinline__ float vmed3(float d, float lo, float hi) {
+    return __builtin_amdgcn_fmed3f(d, lo, hi);
+}
+__device__ __forceinline__ int32_t vmed3(int32_t d, int32_t lo, int32_t hi) {
+    return max(lo, min(d, hi));
+}
+
+// lexicographic (value, index) "a < b"
+template <typename A>
+__device__ __forceinline__ bool lt2(A va, int ia, A vb, int ib) {
+    return va < vb || (va == vb && ia < ib);
+}
+
+// Block-wide lexicographic argmin over (v, i, c); result in thread 0.
+template <typename A, int NT>
+__device__ void block_argmin3(A &v, int &i, int &c) {
+    __shared__ A sv[NT];
+    __shared__ int si[NT], sc[NT];
+    const int t = threadIdx.x;
+    sv[t] = v; si[t] = i; sc[t] = c;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (t < w && lex_less(sv[t + w], si[t + w], sc[t + w], sv[t], si[t], sc[t])) {
+            sv[t] = sv[t + w]; si[t] = si[t + w]; sc[t] = sc[t + w];
+        }
+        __syncthreads();
+    }
+    v = sv[0]; i = si[0]; c = sc[0];
+    __syncthreads();
+}
+
+// Block-wide sum in a fixed tree order; result returned to every thread.
+template <typename A, int NT>
+__device__ A block_sum(A x) {
+    __shared__ A s[NT];
+    const int t = threadIdx.x;
+    s[t] = x;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (t < w) s[t] += s[t + w];
+        __syncthreads();
+    }
+    const A r = s[0];
+    __syncthreads();
+    return r;
+}
+
+// Wave-wide lexicographic argmin over (v, i, c) by butterfly; every lane
+// ends with the same result.
+template <typename A>
+__device__ __forceinline__ void wave_argmin3(A &v, int &i, int &c) {
+    for (int w = 32; w >= 1; w >>= 1) {
+        const A v2 = __shfl_xor(v, w);
+        const int i2 = __shfl_xor(i, w), c2 = __shfl_xor(c, w);
+        if (lex_less(v2, i2, c2, v, i, c)) { v = v2; i = i2; c = c2; }
+    }
+}
+
+// Wave-wide sum by butterfly (fixed pattern, same value in every lane).
+template <typename A>
+__device__ __forceinline__ A wave_sum(A x) {
+    for (int w = 32; w >= 1; w >>= 1) x += __shfl_xor(x, w);
+    return x;
 }
 
 // Workspace layout (byte offsets, 256-aligned) for one (n, k, dtype) run.
@@ -105,6 +179,26 @@ hipError_t launch_dist_l1_i32(const int32_t *X, int64_t n, int32_t dim, int32_t 
 hipError_t launch_center_f32(const float *X, int64_t n, int32_t dim, float *Xc, hipStream_t s);
 hipError_t launch_dist_l2_f32(const float *X, int64_t n, int32_t dim, float *D, int64_t ld,
                               hipStream_t s);
+
+// Arguments of the batched (CLARA) kernels; all pointers are device pointers.
+struct BatchArgs {
+    const int64_t *soff;    // [n_inst+1] sample offsets
+    const int32_t *sidx;    // sample point indices
+    const int32_t *kin;     // [n_inst] k per instance
+    const int64_t *moff;    // [n_inst+1] medoid offsets
+    const int32_t *order;   // instance ids, largest estimated cost first
+    int32_t n_inst, max_iter, excl, n_max, k_max, grid, nblk;
+    int32_t *med_out;       // global indices of the medoids, instance-major
+    double *td_out, *tdb_out, *part, *td_full;
+    int32_t *it_out, *sw_out, *queue, *err;
+};
+size_t batched_lds_bytes_host(int n_max, int k_max, int dim, size_t esz);
+hipError_t launch_check_sidx(const int32_t *sidx, int64_t total, int64_t N, int32_t *err,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_clara(const T *X, int64_t N, int32_t dim, const BatchArgs &a, hipStream_t s);
+template <typename T>
+hipError_t launch_full_assign(const T *X, int64_t N, int32_t dim, const BatchArgs &a, hipStream_t s);
 
 template <typename T>
 hipError_t run_build(const T *D, int64_t ld, const Layout &L, int32_t k, int32_t exclude_self,

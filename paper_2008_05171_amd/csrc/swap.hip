@@ -30,7 +30,6 @@
 
 namespace pamx {
 
-template <typename T> using AccT = typename VT<T>::acc;
 
 // ---------------------------------------------------------------- helpers
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -47,56 +46,6 @@ __device__ __forceinline__ void load_vec(const T *__restrict__ p, T (&v)[VEC]) {
     } else {
         v[0] = __builtin_nontemporal_load(p);
     }
-}
-
-__device__ __forceinline__ float vmin(float a, float b) { return fminf(a, b); }
-__device__ __forceinline__ int32_t vmin(int32_t a, int32_t b) { return min(a, b); }
-// median of (d, lo, hi) for lo <= hi
-__device__ __forceinline__ float vmed3(float d, float lo, float hi) {
-    return __builtin_amdgcn_fmed3f(d, lo, hi);
-}
-__device__ __forceinline__ int32_t vmed3(int32_t d, int32_t lo, int32_t hi) {
-    return max(lo, min(d, hi));
-}
-
-// lexicographic (value, index) "a < b"
-template <typename A>
-__device__ __forceinline__ bool lt2(A va, int ia, A vb, int ib) {
-    return va < vb || (va == vb && ia < ib);
-}
-
-// Block-wide lexicographic argmin over (v, i, c); result in thread 0.
-template <typename A, int NT>
-__device__ void block_argmin3(A &v, int &i, int &c) {
-    __shared__ A sv[NT];
-    __shared__ int si[NT], sc[NT];
-    const int t = threadIdx.x;
-    sv[t] = v; si[t] = i; sc[t] = c;
-    __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
-        if (t < w && lex_less(sv[t + w], si[t + w], sc[t + w], sv[t], si[t], sc[t])) {
-            sv[t] = sv[t + w]; si[t] = si[t + w]; sc[t] = sc[t + w];
-        }
-        __syncthreads();
-    }
-    v = sv[0]; i = si[0]; c = sc[0];
-    __syncthreads();
-}
-
-// Block-wide sum in a fixed tree order; result returned to every thread.
-template <typename A, int NT>
-__device__ A block_sum(A x) {
-    __shared__ A s[NT];
-    const int t = threadIdx.x;
-    s[t] = x;
-    __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
-        if (t < w) s[t] += s[t + w];
-        __syncthreads();
-    }
-    const A r = s[0];
-    __syncthreads();
-    return r;
 }
 
 // ---------------------------------------------------------------- fills

@@ -45,8 +45,16 @@ class pamx_stats(ctypes.Structure):
                 ("n_swap_pass", ctypes.c_int32), ("n_build_pass", ctypes.c_int32)]
 
 
+class pamx_batch_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("swaps", ctypes.c_int32),
+                ("best_inst", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ms_pam", ctypes.c_double), ("ms_assign", ctypes.c_double),
+                ("ms_total", ctypes.c_double), ("pairs", ctypes.c_int64)]
+
+
 EXPORTS = ("pamx_default_options", "pamx_workspace_bytes", "pamx_dist", "pamx_build",
-           "pamx_swap", "pamx_fit", "pamx_last_error")
+           "pamx_swap", "pamx_fit", "pamx_batched_workspace_bytes", "pamx_fit_batched",
+           "pamx_last_error")
 
 
 class PamxError(RuntimeError):
@@ -78,9 +86,13 @@ def load(path: str = LIB_PATH):
     lib.pamx_build.argtypes = [P, i32, i64, i64, i32, opt_p, P, dbl_p, P, sz, P]
     lib.pamx_swap.argtypes = [P, i32, i64, i64, i32, opt_p, P, P, dbl_p, st_p, P, sz, P]
     lib.pamx_fit.argtypes = [P, i32, i32, i64, i32, i32, i32, opt_p, P, P, dbl_p, st_p, P, sz, P]
+    lib.pamx_batched_workspace_bytes.argtypes = [i32, i64, ctypes.POINTER(sz)]
+    lib.pamx_fit_batched.argtypes = [P, i32, i64, i32, i32, i32, P, P, P, opt_p, P, P, P,
+                                     ctypes.POINTER(pamx_batch_stats), P, sz, P]
     lib.pamx_last_error.argtypes = []
     lib.pamx_last_error.restype = ctypes.c_char_p
-    for name in ("pamx_workspace_bytes", "pamx_dist", "pamx_build", "pamx_swap", "pamx_fit"):
+    for name in ("pamx_workspace_bytes", "pamx_dist", "pamx_build", "pamx_swap", "pamx_fit",
+                 "pamx_batched_workspace_bytes", "pamx_fit_batched"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -167,6 +179,35 @@ def pamx_fit(XorD, input_kind, k, medoids, labels, ws, metric=PAMX_L2, opt=None,
                                 _ptr(labels), ctypes.byref(td), ctypes.byref(st), _ptr(ws),
                                 ws.numel() * ws.element_size(), _stream(stream)))
     return rc, td.value, st
+
+
+def pamx_batched_workspace_bytes(n_inst, N) -> int:
+    out = ctypes.c_size_t()
+    _check(load().pamx_batched_workspace_bytes(int(n_inst), int(N), ctypes.byref(out)))
+    return int(out.value)
+
+
+def pamx_fit_batched(X, metric, sample_off, sample_idx, k_inst, medoids, ws, opt=None,
+                     want_full=True, stream=None):
+    """sample_off (int64) and k_inst (int32) are host numpy arrays; X,
+    sample_idx, medoids and ws are device tensors.  Returns
+    (rc, td_sample ndarray, td_full ndarray or None, stats)."""
+    import numpy as np
+    N, dim = X.shape
+    so = np.ascontiguousarray(sample_off, dtype=np.int64)
+    ki = np.ascontiguousarray(k_inst, dtype=np.int32)
+    n_inst = len(ki)
+    tds = np.zeros(n_inst, np.float64)
+    tdf = np.zeros(n_inst, np.float64) if want_full else None
+    st = pamx_batch_stats()
+    rc = _check(load().pamx_fit_batched(
+        _ptr(X), _dtype_code(X), int(N), int(dim), int(metric), int(n_inst),
+        so.ctypes.data_as(ctypes.c_void_p), _ptr(sample_idx), ki.ctypes.data_as(ctypes.c_void_p),
+        ctypes.byref(opt) if opt is not None else None, _ptr(medoids),
+        tds.ctypes.data_as(ctypes.c_void_p),
+        tdf.ctypes.data_as(ctypes.c_void_p) if tdf is not None else None, ctypes.byref(st),
+        _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+    return rc, tds, tdf, st
 
 
 def pamx_last_error() -> str:

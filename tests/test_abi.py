@@ -120,3 +120,28 @@ def test_no_oracle_in_product_path():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "liboracle" not in txt, f
+
+
+def test_batched_host_argument_errors(lib):
+    import numpy as np
+    fake = ctypes.c_void_p(0x100000)
+    ws = ctypes.c_void_p(0x200000)
+
+    def call(so, ki, dim=8, dtype=abi.PAMX_F32, metric=abi.PAMX_L2, wsb=1 << 30, N=1000):
+        so = np.asarray(so, np.int64)
+        ki = np.asarray(ki, np.int32)
+        tds = np.zeros(len(ki))
+        return lib.pamx_fit_batched(fake, dtype, N, dim, metric, len(ki),
+                                    so.ctypes.data_as(ctypes.c_void_p), fake,
+                                    ki.ctypes.data_as(ctypes.c_void_p), None, fake,
+                                    tds.ctypes.data_as(ctypes.c_void_p), None, None, ws, wsb, None)
+    assert call([0, 50, 100], [5, 5], wsb=16) == abi.PAMX_ERR_WORKSPACE
+    assert call([1, 50], [5]) == abi.PAMX_ERR_ARG                 # sample_off[0] != 0
+    assert call([0, 0], [1]) == abi.PAMX_ERR_ARG                  # empty sample
+    assert call([0, 10], [11]) == abi.PAMX_ERR_ARG                # k > n'
+    assert call([0, 10], [0]) == abi.PAMX_ERR_ARG
+    assert call([0, 3000], [5]) == abi.PAMX_ERR_UNSUPPORTED       # n' > 2048
+    assert call([0, 2000], [300]) == abi.PAMX_ERR_UNSUPPORTED     # k > 256
+    assert call([0, 100], [5], dim=17) == abi.PAMX_ERR_UNSUPPORTED
+    assert call([0, 100], [5], dtype=abi.PAMX_I32) == abi.PAMX_ERR_UNSUPPORTED  # int + L2
+    assert abi.pamx_batched_workspace_bytes(256, 10 ** 6) > 256 * 256 * 8
