@@ -73,6 +73,18 @@ extern "C" {
                           rigorous FP32 error bound of the best are scored
                           again in FP64 before the swap is chosen          */
 
+/* how pamx_fit obtains distances of PAMX_F32 points */
+#define PAMX_DIST_STORED 0 /* the n x n FP32 matrix is computed once into the
+                              workspace (Gram term on FP32 MFMA)              */
+#define PAMX_DIST_BF16 1   /* mixed-precision form: no matrix; every pass
+                              recomputes distances of BF16-rounded centred
+                              points on the BF16 matrix cores, sums loss
+                              changes in FP32, and re-scores in FP64 (from the
+                              FP32 points) every candidate whose rigorous error
+                              bound reaches the best one, so BUILD and SWAP
+                              take the decisions of FP64 arithmetic.
+                              FastPAM1 only; dim <= 64, k <= 4096.            */
+
 /* return codes */
 #define PAMX_OK 0
 #define PAMX_WARN_MAXITER 1
@@ -94,6 +106,7 @@ typedef struct pamx_options {
     int32_t chunk;              /* objects per pass work-group; 0 = automatic */
     int32_t profile;            /* 1: time every BUILD / SWAP pass kernel with
                                    HIP events on `stream` (pamx_stats)       */
+    int32_t dist_mode;          /* PAMX_DIST_STORED (default) or PAMX_DIST_BF16 */
     void *trace;                /* optional DEVICE array of pamx_swap_record:
                                    every applied swap in order               */
 } pamx_options;

@@ -12,8 +12,8 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 
 from . import pamx as _abi
-from .pamx import (PAMX_ACC_F32, PAMX_ACC_F64, PAMX_FASTPAM1, PAMX_FASTPAM2, PAMX_INPUT_D,
-                   PAMX_INPUT_X, PAMX_L1, PAMX_L2, PamxError)
+from .pamx import (PAMX_ACC_F32, PAMX_ACC_F64, PAMX_DIST_BF16, PAMX_DIST_STORED, PAMX_FASTPAM1,
+                   PAMX_FASTPAM2, PAMX_INPUT_D, PAMX_INPUT_X, PAMX_L1, PAMX_L2, PamxError)
 
 __all__ = ["fit", "build", "swap", "dist", "fit_batched", "FitResult", "BatchResult", "PamxError", "PAMX_FASTPAM1",
            "PAMX_FASTPAM2", "PAMX_L1", "PAMX_L2", "PAMX_ACC_F64", "PAMX_ACC_F32",
@@ -33,9 +33,14 @@ class FitResult:
     trace: list = field(default_factory=list)   # [(slot, candidate, delta)]
 
 
+_DIST = {"stored": PAMX_DIST_STORED, "bf16": PAMX_DIST_BF16,
+         PAMX_DIST_STORED: PAMX_DIST_STORED, PAMX_DIST_BF16: PAMX_DIST_BF16}
+
+
 def _options(variant="fastpam1", accum=PAMX_ACC_F64, max_iter=10000, exclude_self=False,
-             chunk=0, trace_buf=None, trace_cap=0):
+             chunk=0, trace_buf=None, trace_cap=0, dist_mode="stored"):
     o = _abi.pamx_default_options()
+    o.dist_mode = _DIST[dist_mode]
     o.variant = _VARIANTS[variant]
     o.accum = int(accum)
     o.max_iter = int(max_iter)
@@ -68,11 +73,13 @@ def _stats_dict(st):
 
 def fit(data, k, *, input_kind=PAMX_INPUT_X, metric=None, variant="fastpam1",
         accum=PAMX_ACC_F64, max_iter=10000, exclude_self=False, trace=False, chunk=0,
-        stream=None) -> FitResult:
+        dist_mode="stored", stream=None) -> FitResult:
     """Distances (for points), BUILD, SWAP, labels and TD on the GPU.
 
     data: device tensor, n x dim points (int32 -> L1, float32 -> L2) or an
-    n x n dissimilarity matrix with input_kind=PAMX_INPUT_D."""
+    n x n dissimilarity matrix with input_kind=PAMX_INPUT_D.
+    dist_mode="bf16": the mixed-precision form (no matrix; BF16 Gram
+    distances, FP32 sums, FP64 re-scoring of every possible best swap)."""
     import torch
     n = data.shape[0]
     dim = data.shape[1] if input_kind == PAMX_INPUT_X else 0
@@ -81,7 +88,7 @@ def fit(data, k, *, input_kind=PAMX_INPUT_X, metric=None, variant="fastpam1",
         metric = PAMX_L1 if dtype == _abi.PAMX_I32 else PAMX_L2
     cap = (max_iter * (k if variant in ("fastpam2", PAMX_FASTPAM2) else 1) + 16) if trace else 0
     tbuf = torch.empty(cap * 16, dtype=torch.uint8, device=data.device) if trace else None
-    opt = _options(variant, accum, max_iter, exclude_self, chunk, tbuf, cap)
+    opt = _options(variant, accum, max_iter, exclude_self, chunk, tbuf, cap, dist_mode)
     nbytes = _abi.pamx_workspace_bytes(n, k, dim, input_kind, dtype, opt)
     ws = _workspace(nbytes, data.device)
     med = torch.empty(k, dtype=torch.int32, device=data.device)

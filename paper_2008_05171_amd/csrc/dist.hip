@@ -71,6 +71,11 @@ __global__ __launch_bounds__(256) void k_center_sub(const float *__restrict__ X,
     if (t < total) Xc[t] = X[t] - mean[t % dim];
 }
 
+hipError_t launch_mean_f32(const float *X, int64_t n, int32_t dim, float *mean, hipStream_t s) {
+    hipLaunchKernelGGL(k_center_mean, dim3(dim), dim3(256), 0, s, X, n, dim, mean);
+    return hipGetLastError();
+}
+
 hipError_t launch_center_f32(const float *X, int64_t n, int32_t dim, float *Xc, hipStream_t s) {
     // the mean is parked right after the centred copy (the workspace reserves it)
     float *mean = Xc + n * dim;

@@ -129,6 +129,68 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     return PAMX_OK;
 }
 
+int make_rc_layout(int64_t n, int32_t k, int32_t dim, const pamx_options *opt, RcLayout *R) {
+    std::memset(R, 0, sizeof(*R));
+    R->n = n;
+    R->k = k;
+    R->KP = ((dim + 15) / 16) * 16;
+    R->n_ctiles = (int32_t)((n + 255) / 256);
+    R->ncp = (int64_t)R->n_ctiles * 256;
+    R->n_oblk = (int32_t)((n + kObjBlk - 1) / kObjBlk);
+    int64_t Lc;
+    if (opt && opt->chunk > 0) {
+        Lc = opt->chunk;
+    } else {
+        int64_t Q = (1024 + R->n_ctiles - 1) / R->n_ctiles;   // ~4 work-groups per CU
+        if (Q < 1) Q = 1;
+        Lc = (n + Q - 1) / Q;
+    }
+    Lc = ((Lc + 31) / 32) * 32;
+    if (Lc > n) Lc = n;
+    R->L = (int32_t)Lc;
+    R->Q = (int32_t)((n + Lc - 1) / Lc);
+    const int64_t nmwg = (n + 255) / 256;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = up256(off + (bytes ? bytes : 1)); return o; };
+    R->Xb = take((size_t)n * R->KP * 4);              // split rows: hi and lo, bf16
+    R->nb = take((size_t)n * 4);
+    R->eo = take((size_t)n * 8);
+    R->dn64 = take((size_t)n * 8);
+    R->ds64 = take((size_t)n * 8);
+    R->dn32 = take((size_t)n * 4);
+    R->ds32 = take((size_t)n * 4);
+    R->sdn = take((size_t)n * 4);
+    R->sds = take((size_t)n * 4);
+    R->sthr = take((size_t)n * 4);
+    R->snb = take((size_t)n * 4);
+    R->thr = take((size_t)n * 4);
+    R->R64 = take((size_t)k * 8);
+    R->R32 = take((size_t)k * 4);
+    R->part = take((size_t)R->Q * 4 * R->ncp * 8);
+    R->part_i = take((size_t)R->Q * 4 * R->ncp * 4);
+    R->cand_v = take((size_t)R->ncp * 8);
+    R->cand_b = take((size_t)R->ncp * 8);
+    R->wg_u = take((size_t)nmwg * 8);
+    R->list = take((size_t)n * 4);
+    R->res_v = take((size_t)n * 8);
+    R->res_i = take((size_t)n * 4);
+    R->rlist = take((size_t)n * 4);
+    R->near = take((size_t)n * 4);
+    R->sec = take((size_t)n * 4);
+    R->srow = take((size_t)n * 4);
+    R->blkcnt = take((size_t)R->n_oblk * k * 4);
+    R->seg_off = take((size_t)(k + 1) * 4);
+    R->cinfo = take((size_t)R->Q * 12);
+    R->is_med = take((size_t)n);
+    R->mx = take(2 * 8);
+    R->eps0 = take(4 * 8);
+    R->bnd = take(4 * 8);
+    R->mean = take((size_t)dim * 4);
+    R->state = take(sizeof(DevState));
+    R->total = off;
+    return PAMX_OK;
+}
+
 }  // namespace pamx
 
 // ---------------------------------------------------------------- validation
@@ -145,16 +207,31 @@ static int check_common(int64_t n, int32_t k, int32_t dtype, const pamx_options 
             return fail(PAMX_ERR_ARG, "unknown variant %d", opt->variant);
         if (opt->accum != PAMX_ACC_F64 && opt->accum != PAMX_ACC_F32)
             return fail(PAMX_ERR_ARG, "unknown accum %d", opt->accum);
+        if (opt->dist_mode != PAMX_DIST_STORED && opt->dist_mode != PAMX_DIST_BF16)
+            return fail(PAMX_ERR_ARG, "unknown dist_mode %d", opt->dist_mode);
         if (opt->accum == PAMX_ACC_F32 && dtype != PAMX_F32)
-            return fail(PAMX_ERR_ARG, "accum PAMX_ACC_F32 needs PAMX_F32 dissimilarities");
-        if (opt->accum == PAMX_ACC_F32)
-            return fail(PAMX_ERR_UNSUPPORTED, "accum PAMX_ACC_F32 is not available in this build");
+            return fail(PAMX_ERR_ARG, "accum PAMX_ACC_F32 needs PAMX_F32 data");
+        if (opt->accum == PAMX_ACC_F32 && opt->dist_mode != PAMX_DIST_BF16)
+            return fail(PAMX_ERR_UNSUPPORTED, "accum PAMX_ACC_F32 is available with PAMX_DIST_BF16 only");
         if (opt->max_iter < 0) return fail(PAMX_ERR_ARG, "max_iter must be >= 0");
         if (opt->trace_cap < 0) return fail(PAMX_ERR_ARG, "trace_cap must be >= 0");
         if (opt->chunk < 0) return fail(PAMX_ERR_ARG, "chunk must be >= 0");
         if (opt->build_exclude_self != 0 && opt->build_exclude_self != 1)
             return fail(PAMX_ERR_ARG, "build_exclude_self must be 0 or 1");
+        if (opt->dist_mode != PAMX_DIST_STORED && opt->dist_mode != PAMX_DIST_BF16)
+            return fail(PAMX_ERR_ARG, "unknown dist_mode %d", opt->dist_mode);
     }
+    return PAMX_OK;
+}
+
+static int check_rc(int32_t input_kind, int32_t dtype, int32_t metric, int32_t dim, int32_t k,
+                    const pamx_options *opt) {
+    if (input_kind != PAMX_INPUT_X || dtype != PAMX_F32 || metric != PAMX_L2)
+        return fail(PAMX_ERR_ARG, "PAMX_DIST_BF16 needs float32 points with the L2 metric");
+    if (dim > kRcMaxDim) return fail(PAMX_ERR_UNSUPPORTED, "PAMX_DIST_BF16 supports dim <= %d", kRcMaxDim);
+    if (k > kRcMaxK) return fail(PAMX_ERR_UNSUPPORTED, "PAMX_DIST_BF16 supports k <= %d", kRcMaxK);
+    if (opt && opt->variant != PAMX_FASTPAM1)
+        return fail(PAMX_ERR_UNSUPPORTED, "PAMX_DIST_BF16 runs FastPAM1 only");
     return PAMX_OK;
 }
 
@@ -183,6 +260,14 @@ extern "C" int pamx_workspace_bytes(int64_t n, int32_t k, int32_t dim, int32_t i
     if (input_kind != PAMX_INPUT_D && input_kind != PAMX_INPUT_X)
         return fail(PAMX_ERR_ARG, "unknown input_kind %d", input_kind);
     if (input_kind == PAMX_INPUT_X && dim < 1) return fail(PAMX_ERR_ARG, "dim must be >= 1");
+    if (opt && opt->dist_mode == PAMX_DIST_BF16) {
+        rc = check_rc(input_kind, dtype, PAMX_L2, dim, k, opt);
+        if (rc) return rc;
+        RcLayout R;
+        make_rc_layout(n, k, dim, opt, &R);
+        *bytes = R.total;
+        return PAMX_OK;
+    }
     Layout L;
     // the pass tiling depends on ld and on the matrix alignment: take the
     // larger of the 16-byte-load and scalar-load layouts
@@ -378,6 +463,97 @@ int swap_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const pamx_opt
 
 }  // namespace
 
+// The mixed-precision form: BUILD and FastPAM1 on recomputed BF16-Gram
+// distances with FP64 re-scoring (precision.hip).
+static int fit_rc(const float *X, int64_t n, int32_t dim, int32_t k, const pamx_options &opt,
+                  int32_t *medoids, int32_t *labels, double *td, pamx_stats *stats, void *ws,
+                  size_t ws_bytes, hipStream_t s) {
+    RcLayout R;
+    make_rc_layout(n, k, dim, &opt, &R);
+    if (!ws) return fail(PAMX_ERR_WORKSPACE, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return fail(PAMX_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < R.total)
+        return fail(PAMX_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, R.total);
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    char *w = static_cast<char *>(ws);
+    Timer tm;
+    tm.rec(0, s);
+    float *mean = reinterpret_cast<float *>(w + R.mean);
+    HIP_TRY(launch_mean_f32(X, n, dim, mean, s));
+    tm.rec(1, s);
+    HIP_TRY(rc_prep_build(X, dim, R, k, opt, medoids, ws, s, mean));
+    HIP_TRY(rc_td(R, ws, s));
+    DevState st;
+    const Layout fake = [&] { Layout L; std::memset(&L, 0, sizeof(L)); L.state = R.state; return L; }();
+    int rc = read_state(fake, ws, s, &st);
+    if (rc) return rc;
+    if (st.bad_medoids) return fail(PAMX_ERR_HIP, "BUILD found no candidate");
+    const double td_build = st.td;
+    const int build_rescored = st.rescored;
+    tm.rec(2, s);
+    double ms_pass = 0.0;
+    int n_pass = 0;
+    HIP_TRY(rc_swap_init(X, dim, R, medoids, opt, ws, s));
+    if (k >= 2 && k < n) {
+        constexpr int kMaxBatch = 16;
+        std::unique_ptr<EventPool> pool;
+        if (opt.profile) {
+            pool.reset(new EventPool(2 * kMaxBatch));
+            if (!pool->ok()) return fail(PAMX_ERR_HIP, "hipEventCreate failed");
+        }
+        int batch = 2, enq = 0;
+        st.iter = 0;
+        for (;;) {
+            int b = batch;
+            if (b > opt.max_iter + 1 - enq) b = opt.max_iter + 1 - enq;
+            if (b < 1) b = 1;
+            const int iter0 = st.iter;
+            for (int j = 0; j < b; ++j)
+                HIP_TRY(rc_swap_iteration(X, dim, R, medoids, opt, ws, s,
+                                          pool ? pool->ev[2 * j] : nullptr,
+                                          pool ? pool->ev[2 * j + 1] : nullptr));
+            enq += b;
+            rc = read_state(fake, ws, s, &st);
+            if (rc) return rc;
+            if (pool) {
+                const int ran = st.iter - iter0;
+                ms_pass += pool->sum(ran);
+                n_pass += ran;
+            }
+            if (st.done) break;
+            if (batch < kMaxBatch) batch *= 2;
+        }
+    } else {
+        st.iter = 0; st.swaps = 0; st.capped = 0;
+    }
+    tm.rec(3, s);
+    HIP_TRY(rc_finalize(X, dim, R, medoids, labels, ws, s));
+    DevState fin;
+    rc = read_state(fake, ws, s, &fin);
+    if (rc) return rc;
+    tm.rec(4, s);
+    HIP_TRY(hipStreamSynchronize(s));
+    if (td) *td = fin.td;
+    if (stats) {
+        stats->iterations = st.iter;
+        stats->swaps = st.swaps;
+        stats->converged = (k >= 2 && k < n) ? (st.done && !st.capped) : 1;
+        stats->rescored = st.rescored + build_rescored;
+        stats->td_build = td_build;
+        stats->td = fin.td;
+        stats->ms_dist = tm.ms(0, 1);
+        stats->ms_build = tm.ms(1, 2);
+        stats->ms_swap = tm.ms(2, 3);
+        stats->ms_total = tm.ms(0, 4);
+        stats->pass_pairs = (int64_t)st.iter * n * (n - k);
+        stats->build_pairs = (int64_t)k * n * n;
+        stats->ms_swap_pass = ms_pass;
+        stats->n_swap_pass = n_pass;
+    }
+    return st.capped ? PAMX_WARN_MAXITER : PAMX_OK;
+}
+
 static int swap_args(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
                      const pamx_options *opt, const int32_t *medoids) {
     int rc = check_common(n, k, dtype, opt);
@@ -462,6 +638,12 @@ extern "C" int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int
     }
     if (!medoids) return fail(PAMX_ERR_ARG, "medoids is NULL");
     if (opt.trace_cap > 0 && !opt.trace) return fail(PAMX_ERR_ARG, "trace_cap > 0 needs a trace array");
+    if (opt.dist_mode == PAMX_DIST_BF16) {
+        rc = check_rc(input_kind, dtype, metric, dim, k, &opt);
+        if (rc) return rc;
+        return fit_rc(static_cast<const float *>(XorD), n, dim, k, opt, medoids, labels, td, stats, ws,
+                      ws_bytes, static_cast<hipStream_t>(stream));
+    }
     Layout L;
     make_layout(n, k, dim, input_kind, dtype, n, &opt, &L,
                 input_kind == PAMX_INPUT_D ? XorD : nullptr);

@@ -180,6 +180,32 @@ hipError_t launch_center_f32(const float *X, int64_t n, int32_t dim, float *Xc, 
 hipError_t launch_dist_l2_f32(const float *X, int64_t n, int32_t dim, float *D, int64_t ld,
                               hipStream_t s);
 
+// Workspace layout of the mixed-precision (BF16 Gram, FP32 sums, FP64
+// re-score) form for points.
+struct RcLayout {
+    int64_t n;
+    int32_t k, KP, n_ctiles, L, Q, n_oblk;
+    int64_t ncp;
+    size_t Xb, nb, eo, dn64, ds64, dn32, ds32, sdn, sds, sthr, snb, thr, R64, R32, part, part_i,
+        cand_v, cand_b, wg_u, list, res_v, res_i, rlist, near, sec, srow, blkcnt, seg_off, cinfo,
+        is_med, mx, eps0, bnd, mean, state, total;
+};
+constexpr int kRcMaxDim = 64;     // precision form: largest point dimension
+constexpr int kRcMaxK = 4096;     // precision form: largest k (per-slot FP64 sums in LDS)
+hipError_t rc_prep_build(const float *X, int32_t dim, const RcLayout &R, int32_t k,
+                         const pamx_options &opt, int32_t *medoids, void *ws, hipStream_t s,
+                         const float *mean);
+hipError_t rc_td(const RcLayout &R, void *ws, hipStream_t s);
+hipError_t rc_swap_init(const float *X, int32_t dim, const RcLayout &R, const int32_t *medoids,
+                        const pamx_options &opt, void *ws, hipStream_t s);
+hipError_t rc_swap_iteration(const float *X, int32_t dim, const RcLayout &R, int32_t *medoids,
+                             const pamx_options &opt, void *ws, hipStream_t s, hipEvent_t ev0,
+                             hipEvent_t ev1);
+hipError_t rc_finalize(const float *X, int32_t dim, const RcLayout &R, const int32_t *medoids,
+                       int32_t *labels, void *ws, hipStream_t s);
+hipError_t launch_mean_f32(const float *X, int64_t n, int32_t dim, float *mean, hipStream_t s);
+int make_rc_layout(int64_t n, int32_t k, int32_t dim, const pamx_options *opt, RcLayout *R);
+
 // Arguments of the batched (CLARA) kernels; all pointers are device pointers.
 struct BatchArgs {
     const int64_t *soff;    // [n_inst+1] sample offsets

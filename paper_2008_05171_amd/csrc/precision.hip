@@ -1,0 +1,1124 @@
+// precision.hip -- the mixed-precision form of BUILD and FastPAM1 SWAP for
+// Euclidean points: distances recomputed per tile from BF16-rounded points on
+// the matrix cores (no n x n matrix), loss changes summed in FP32, and every
+// candidate that could still be the best swap re-scored in FP64 from the
+// original FP32 points, so the decisions are those of FP64 arithmetic.
+//
+// Paper: Schubert & Rousseeuw, arXiv 2008.05171 -- Alg. 1 (BUILD), Alg. 3
+// and Eq. better-change3 (FastPAM1).  The paper fixes no precision; this form
+// trades the O(n^2) matrix for recomputation and keeps exactness through a
+// rigorous error bound:
+//
+//   d~(o,c) = sqrt(max(|x~o|^2 + |x~c|^2 - 2 x~o.x~c, 0)), x~ = bf16(x - mu)
+//   |d~ - d| <= 2 e_max + g_max + 2^-22 d~            (per pair)
+//     e_max = max_o |x~o - (x_o - mu)|    (BF16 rounding, exact in FP64)
+//     g_max = sqrt((KP + 8) 2^-20 max_o |x~o|^2)   (FP32 norms and Gram)
+//
+// The loss change of an object depends on d(o,c) only while d < ds(o) (the
+// second-nearest distance; dn for BUILD), so for every swap
+//   |Delta~(i,c) - Delta(i,c)| <= cnt(c) * eps1 + eps_acc
+// where cnt(c) counts objects with d~(o,c) below ds(o) + eps, and eps_acc
+// bounds the FP32 summation.  Candidates whose lower bound reaches the best
+// upper bound are re-scored exactly.
+#include "pamx_internal.h"
+
+namespace pamx {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kRT = 256;       // lanes per work-group, one candidate each
+constexpr int kRB = 32;        // objects per Gram block
+constexpr int kGS = kRB + 1;   // padded stride (floats) of the transposed tile, per candidate
+constexpr int kAS = 72;        // padded row stride (bf16) of the staged object block
+
+// ---------------------------------------------------------------- FP64 distance
+// The reference distance of this form: Euclidean, FP64, from the original
+// FP32 coordinates (differences of two floats are exact in FP64).
+__device__ __forceinline__ double d64(const float *__restrict__ X, int dim, int64_t a, int64_t b) {
+    const float *x = X + a * dim;
+    const float *y = X + b * dim;
+    double s = 0.0;
+    for (int k = 0; k < dim; ++k) {
+        const double t = (double)x[k] - (double)y[k];
+        s = fma(t, t, s);
+    }
+    return sqrt(s);
+}
+
+// ---------------------------------------------------------------- prep
+// Split BF16 representation of the centred points: hi = bf16(x - mu),
+// lo = bf16((x - mu) - hi); the effective point x~ = hi + lo is exact in
+// FP32.  Rows hold hi[KP] then lo[KP].  Also the FP32 squared norm of x~ and
+// the FP64 residual |x~ - (x - mu)|.
+__global__ __launch_bounds__(256) void k_rc_prep(const float *__restrict__ X, int64_t n, int32_t dim,
+                                                 int32_t KP, const float *__restrict__ mean,
+                                                 __bf16 *__restrict__ Xs, float *__restrict__ nb,
+                                                 double *__restrict__ eo) {
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= n) return;
+    float nrm = 0.0f;
+    double res = 0.0;
+    __bf16 *row = Xs + o * 2 * KP;
+    for (int k = 0; k < KP; ++k) {
+        float v = 0.0f;
+        double exact = 0.0;
+        if (k < dim) {
+            const float x = X[o * dim + k];
+            v = x - mean[k];
+            exact = (double)x - (double)mean[k];
+        }
+        const __bf16 hi = (__bf16)v;
+        const __bf16 lo = (__bf16)(v - (float)hi);
+        row[k] = hi;
+        row[KP + k] = lo;
+        const float eff = (float)hi + (float)lo;
+        nrm = fmaf(eff, eff, nrm);
+        const double r = (double)eff - exact;
+        res = fma(r, r, res);
+    }
+    nb[o] = nrm;
+    eo[o] = sqrt(res);
+}
+
+// max of eo and of nb (single work-group): mx[0] = e_max, mx[1] = max |x~|^2
+__global__ __launch_bounds__(1024) void k_rc_prep_max(const double *__restrict__ eo,
+                                                      const float *__restrict__ nb, int64_t n,
+                                                      double *__restrict__ out) {
+    __shared__ double s1[1024], s2[1024];
+    double a = 0.0, b = 0.0;
+    for (int64_t o = threadIdx.x; o < n; o += 1024) {
+        a = fmax(a, eo[o]);
+        b = fmax(b, (double)nb[o]);
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + w]);
+            s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = s1[0]; out[1] = s2[0]; }
+}
+
+// Per-pair distance bounds (eps0):
+//   sigma bounds |s~ - s| for s = |x~o - x~c|^2: FP32 norms (KP terms), the
+//   3 KP split-product Gram terms summed in FP32 by the matrix cores, the
+//   dropped lo*lo' term, the final fma -- all relative to |x~o|^2 + |x~c|^2,
+//   with a factor 2 of slack.  Then |d~ - |x~o - x~c|| <= min(sqrt(sigma),
+//   sigma / d~), and |x~o - x~c| is within 2 e_max of the true distance.
+//   eps0[0] = e_near = 2 e_max + sqrt(sigma)            (d~ <  delta0)
+//   eps0[1] = e_far  = 2 e_max + sigma / delta0         (d~ >= delta0)
+//   eps0[2] = delta0 = 8 sqrt(sigma);  eps0[3] = a bound on any d~
+__global__ void k_rc_eps(const double *__restrict__ mx, int32_t KP, double *__restrict__ eps0) {
+    if (threadIdx.x != 0) return;
+    const double emax = mx[0], nbmax = mx[1];
+    const double rel = 3.0 * KP * 0x1p-25 * 1.01 + KP * 0x1p-24 + 0x1p-19 + 0x1p-22;
+    const double sigma = 2.0 * (2.0 * nbmax) * rel;
+    const double d0 = 8.0 * sqrt(sigma);
+    eps0[0] = 2.0 * emax + sqrt(sigma);
+    eps0[1] = 2.0 * emax + sigma / d0;
+    eps0[2] = d0;
+    eps0[3] = 2.0 * sqrt(nbmax) * (1.0 + 0x1p-20) + sqrt(sigma);
+}
+
+// ---------------------------------------------------------------- Gram tile
+// One work-group, one block of 32 (sorted) objects: stage their split BF16
+// rows and their four per-row values in LDS; every wave computes the 32 x 64
+// Gram tile of the block against its 64 candidates on the matrix cores
+// (hi.hi' + hi.lo' + lo.hi' per 16-wide k step, v_mfma_f32_32x32x16_bf16)
+// and writes it transposed -- g[candidate][object] -- to its own LDS region.
+// Operand layout (wave64, 32x32x16): lane l supplies A[l%32][8(l/32)..+7]
+// and B[8(l/32)..+7][l%32] of each k step; accumulator element v of lane l
+// is C[(v%4) + 8(v/4) + 4(l/32)][l%32].
+// The staged rows As are read only before the second barrier, so the next
+// block may overwrite them; the row values Rv are read after it, while a
+// faster wave may already stage the next block, so callers alternate two Rv
+// buffers by block parity (no wave can be two blocks ahead of another).
+struct RowVals {
+    const float *v0, *v1, *v2, *v3;   // per (sorted) position; v3 may be null
+};
+
+template <int KS>
+__device__ __forceinline__ void gram_block(const __bf16 *__restrict__ Xs, int KP,
+                                           const int32_t *__restrict__ rows, int64_t j0, int64_t jend,
+                                           const RowVals &rvals, __bf16 *__restrict__ As,
+                                           float4 *__restrict__ Rv, float *__restrict__ Gw,
+                                           const bf16x8 (&bh)[2][KS], const bf16x8 (&bl)[2][KS]) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    constexpr int kPieces = KS * 4;   // 16-byte pieces per split row (hi + lo)
+    for (int e = tid; e < kRB * kPieces; e += kRT) {
+        const int r = e / kPieces, p = e - r * kPieces;
+        const int64_t j = j0 + r;
+        bf16x8 v;
+        if (j < jend) {
+            const int64_t o = rows ? rows[j] : j;
+            v = *reinterpret_cast<const bf16x8 *>(Xs + o * 2 * KP + p * 8);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = (__bf16)0.0f;
+        }
+        // hi pieces to [0, KP), lo pieces to [kAS, kAS + KP)
+        const int half = (p * 8) / KP, off = (p * 8) % KP;
+        *reinterpret_cast<bf16x8 *>(As + r * 2 * kAS + half * kAS + off) = v;
+    }
+    if (tid < kRB) {
+        const int64_t j = j0 + tid;
+        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (j < jend) q = make_float4(rvals.v0[j], rvals.v1[j], rvals.v2[j], rvals.v3 ? rvals.v3[j] : 0.f);
+        Rv[tid] = q;
+    }
+    __syncthreads();
+    floatx16 acc0, acc1;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) { acc0[v] = 0.0f; acc1[v] = 0.0f; }
+    const int i = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(As + i * 2 * kAS + s * 16 + h * 8);
+        const bf16x8 al = *reinterpret_cast<const bf16x8 *>(As + i * 2 * kAS + kAS + s * 16 + h * 8);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[0][s], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[1][s], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[0][s], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[1][s], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[0][s], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[1][s], acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int r = (v & 3) + 8 * (v >> 2) + 4 * h;
+        Gw[i * kGS + r] = acc0[v];
+        Gw[(32 + i) * kGS + r] = acc1[v];
+    }
+    __syncthreads();
+}
+
+// B operands (hi and lo) of a wave's two column blocks for its 64 candidates
+template <int KS>
+__device__ __forceinline__ void load_bq(const __bf16 *__restrict__ Xs, int KP, int64_t n,
+                                        int64_t cbase, bf16x8 (&bh)[2][KS], bf16x8 (&bl)[2][KS]) {
+    const int lane = threadIdx.x & 63;
+    const int i = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int64_t c = cbase + cb * 32 + i;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            if (c < n) {
+                bh[cb][s] = *reinterpret_cast<const bf16x8 *>(Xs + c * 2 * KP + s * 16 + h * 8);
+                bl[cb][s] = *reinterpret_cast<const bf16x8 *>(Xs + c * 2 * KP + KP + s * 16 + h * 8);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) { bh[cb][s][u] = (__bf16)0.0f; bl[cb][s][u] = (__bf16)0.0f; }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ float rc_dist(float g, float no, float nc) {
+    return sqrtf(fmaxf(fmaf(-2.0f, g, no + nc), 0.0f));
+}
+
+// ---------------------------------------------------------------- BUILD pass
+// A~(c) = sum_o min(d~(o,c), dn(o)) over a chunk of objects (natural order);
+// counts of objects with d~ < thr(o), split at delta0.  ACC: the sum type
+// (double, or float summed pairwise per 32-object block).
+// part[q][c] = A~ (ACC), part_i[q][0|1][c] = far / near counts.
+template <int KS, typename ACC>
+__global__ __launch_bounds__(kRT) void k_rc_build_pass(
+    const __bf16 *__restrict__ Xs, int32_t KP, const float *__restrict__ nb, int64_t n,
+    const float *__restrict__ dn, const float *__restrict__ thr, const double *__restrict__ eps0,
+    int32_t L, int64_t ncp, ACC *__restrict__ part, int32_t *__restrict__ part_i) {
+    __shared__ __align__(16) __bf16 As[kRB * 2 * kAS];
+    __shared__ float4 Rv[2][kRB];   // by block parity: a wave is at most one block ahead
+    __shared__ float G[4][64 * kGS];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int q = blockIdx.y;
+    const int64_t a = (int64_t)q * L, b = min(a + (int64_t)L, n);
+    const int64_t cbase = (int64_t)blockIdx.x * kRT + w * 64;
+    const int64_t c = cbase + lane;
+    bf16x8 bh[2][KS], bl[2][KS];
+    load_bq<KS>(Xs, KP, n, cbase, bh, bl);
+    const float nc = (c < n) ? nb[c] : 0.0f;
+    const float d0 = (float)eps0[2];
+    ACC accA = 0;
+    int cf = 0, cn = 0;
+    float *Gw = G[w];
+    const RowVals rv{nb, dn, thr, nullptr};
+    for (int64_t j0 = a; j0 < b; j0 += kRB) {
+        float4 *Rb = Rv[((j0 - a) / kRB) & 1];
+        gram_block<KS>(Xs, KP, nullptr, j0, b, rv, As, Rb, Gw, bh, bl);
+        const int m = (int)min((int64_t)kRB, b - j0);
+        ACC blk = 0;
+        for (int r = 0; r < m; ++r) {
+            const float4 q4 = Rb[r];
+            const float d = rc_dist(Gw[lane * kGS + r], q4.x, nc);
+            blk += (ACC)fminf(d, q4.y);
+            const bool cnt = d < q4.z;
+            cf += (cnt && d >= d0) ? 1 : 0;
+            cn += (cnt && d < d0) ? 1 : 0;
+        }
+        accA += blk;
+    }
+    part[(int64_t)q * ncp + c] = accA;
+    part_i[(int64_t)q * 2 * ncp + c] = cf;
+    part_i[(int64_t)q * 2 * ncp + ncp + c] = cn;
+}
+
+// ---------------------------------------------------------------- SWAP pass
+// The FastPAM1 pass (Eq. better-change3) over a chunk of segment-sorted
+// objects: B(c) += min(d~ - dn, 0); S_i(c) += med3(d~, dn, ds) - ds; at the
+// end of a segment complete in the chunk, v = R_i + S_i and the running best
+// (v, i); head and tail carries as in the stored-matrix pass.  Outputs per
+// candidate and chunk: part[q][0..3] = B, head, tail, best value (ACC);
+// part_i[q][0..3] = best slot, far count, near count.
+template <int KS, typename ACC>
+__global__ __launch_bounds__(kRT) void k_rc_swap_pass(
+    const __bf16 *__restrict__ Xs, int32_t KP, const float *__restrict__ nb, int64_t n, int32_t k,
+    const int32_t *__restrict__ srow, const float *__restrict__ sdn, const float *__restrict__ sds,
+    const float *__restrict__ sthr, const float *__restrict__ snb, const double *__restrict__ eps0,
+    const int32_t *__restrict__ seg_off, const double *__restrict__ R64, const int32_t *__restrict__ cinfo3,
+    int32_t L, int64_t ncp, ACC *__restrict__ part, int32_t *__restrict__ part_i,
+    const DevState *__restrict__ st) {
+    if (st->done) return;
+    __shared__ __align__(16) __bf16 As[kRB * 2 * kAS];
+    __shared__ float4 Rv[2][kRB];   // by block parity: a wave is at most one block ahead
+    __shared__ float G[4][64 * kGS];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int q = blockIdx.y;
+    const int64_t a = (int64_t)q * L, b = min(a + (int64_t)L, n);
+    const int64_t cbase = (int64_t)blockIdx.x * kRT + w * 64;
+    const int64_t c = cbase + lane;
+    const int sa = cinfo3[3 * q], sb = cinfo3[3 * q + 1], flags = cinfo3[3 * q + 2];
+    bf16x8 bh[2][KS], bl[2][KS];
+    load_bq<KS>(Xs, KP, n, cbase, bh, bl);
+    const float nc = (c < n) ? nb[c] : 0.0f;
+    const float d0 = (float)eps0[2];
+    ACC accB = 0, S = 0, bv = (ACC)__builtin_huge_val();
+    int bi = INT_MAX, cf = 0, cn = 0;
+    ACC *pq = part + (int64_t)q * 4 * ncp + c;
+    int cs = sa;
+    int64_t ce = seg_off[sa + 1];
+    auto finish = [&](int s) {
+        if (s == sa && (flags & 1)) pq[1 * ncp] = S;
+        else if (s == sb && (flags & 2)) pq[2 * ncp] = S;
+        else {
+            const ACC v = (ACC)R64[s] + S;
+            if (v < bv) { bv = v; bi = s; }
+        }
+        S = 0;
+    };
+    float *Gw = G[w];
+    const RowVals rv{snb, sdn, sds, sthr};
+    for (int64_t j0 = a; j0 < b; j0 += kRB) {
+        float4 *Rb = Rv[((j0 - a) / kRB) & 1];
+        gram_block<KS>(Xs, KP, srow, j0, b, rv, As, Rb, Gw, bh, bl);
+        const int m = (int)min((int64_t)kRB, b - j0);
+        ACC bblk = 0, sblk = 0;
+        for (int r = 0; r < m; ++r) {
+            const int64_t j = j0 + r;
+            if (j == ce) {             // uniform: segment boundary
+                S += sblk;
+                sblk = 0;
+                finish(cs);
+                do { ++cs; } while (seg_off[cs + 1] == seg_off[cs]);
+                ce = seg_off[cs + 1];
+            }
+            const float4 q4 = Rb[r];   // no, dn, ds, thr
+            const float d = rc_dist(Gw[lane * kGS + r], q4.x, nc);
+            bblk += (ACC)fminf(d - q4.y, 0.0f);
+            sblk += (ACC)(__builtin_amdgcn_fmed3f(d, q4.y, q4.z) - q4.z);
+            const bool cnt = d < q4.w;
+            cf += (cnt && d >= d0) ? 1 : 0;
+            cn += (cnt && d < d0) ? 1 : 0;
+        }
+        accB += bblk;
+        S += sblk;
+    }
+    finish(cs);
+    pq[0] = accB;
+    pq[3 * ncp] = bv;
+    int32_t *pi = part_i + (int64_t)q * 4 * ncp + c;
+    pi[0] = bi;
+    pi[ncp] = cf;
+    pi[2 * ncp] = cn;
+}
+
+// ---------------------------------------------------------------- merges
+// BUILD: A~(c) summed over chunks, its bound, per-WG min of the upper bound.
+// bnd[0] = e_far, bnd[1] = e_near, bnd[2] = relative summation factor.
+template <typename ACC>
+__global__ __launch_bounds__(256) void k_rc_build_merge(
+    const ACC *__restrict__ part, const int32_t *__restrict__ part_i, int32_t Q, int64_t ncp,
+    int64_t n, const double *__restrict__ dn64, const uint8_t *__restrict__ is_med, int32_t add_self,
+    const double *__restrict__ bnd, double *__restrict__ cand_v, double *__restrict__ cand_b,
+    double *__restrict__ wg_u) {
+    __shared__ double red[256];
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double up = __builtin_huge_val();
+    if (c < n && !is_med[c]) {
+        ACC s = 0;
+        int64_t cf = 0, cn = 0;
+        for (int q = 0; q < Q; ++q) {
+            s += part[(int64_t)q * ncp + c];
+            cf += part_i[(int64_t)q * 2 * ncp + c];
+            cn += part_i[(int64_t)q * 2 * ncp + ncp + c];
+        }
+        double v = (double)s;
+        double b = (double)cf * bnd[0] + (double)cn * bnd[1] + bnd[2] * v;
+        if (add_self) v += dn64[c];
+        b = b * 1.0001 + 1e-300;
+        cand_v[c] = v;
+        cand_b[c] = b;
+        up = v + b;
+    } else if (c < n) {
+        cand_v[c] = __builtin_huge_val();
+        cand_b[c] = 0.0;
+    }
+    red[threadIdx.x] = up;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) wg_u[blockIdx.x] = red[0];
+}
+
+// SWAP: chunk carries and bests -> per candidate Delta~_c and its bound.
+// bnd[0] = e_far, bnd[1] = e_near, bnd[2] = absolute summation bound.
+template <typename ACC>
+__global__ __launch_bounds__(256) void k_rc_swap_merge(
+    const ACC *__restrict__ part, const int32_t *__restrict__ part_i,
+    const int32_t *__restrict__ cinfo3, int32_t Q, int64_t n, int32_t k, int64_t ncp,
+    const double *__restrict__ R64, const uint8_t *__restrict__ is_med,
+    const DevState *__restrict__ st, const double *__restrict__ bnd, double *__restrict__ cand_v,
+    double *__restrict__ cand_b, double *__restrict__ wg_u) {
+    __shared__ double red[256];
+    if (st->done) return;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double up = __builtin_huge_val();
+    if (c < n) {
+        ACC accB = 0, bestv = (ACC)__builtin_huge_val(), run_m = 0;
+        int besti = INT_MAX, run_s = -1;
+        int64_t cf = 0, cn = 0;
+        auto flush = [&]() {
+            if (run_s >= 0) {
+                const ACC v = (ACC)R64[run_s] + run_m;
+                if (lt2(v, run_s, bestv, besti)) { bestv = v; besti = run_s; }
+            }
+        };
+        for (int q = 0; q < Q; ++q) {
+            const ACC *pq = part + (int64_t)q * 4 * ncp + c;
+            const int32_t *pi = part_i + (int64_t)q * 4 * ncp + c;
+            accB += pq[0];
+            cf += pi[ncp];
+            cn += pi[2 * ncp];
+            const int32_t i = pi[0];
+            if (i != INT_MAX && lt2(pq[3 * ncp], i, bestv, besti)) { bestv = pq[3 * ncp]; besti = i; }
+            const int sa = cinfo3[3 * q], sb = cinfo3[3 * q + 1], fl = cinfo3[3 * q + 2];
+            if (fl & 1) {
+                if (sa == run_s) run_m += pq[1 * ncp];
+                else { flush(); run_s = sa; run_m = pq[1 * ncp]; }
+            }
+            if (fl & 2) {
+                if (sb == run_s) run_m += pq[2 * ncp];
+                else { flush(); run_s = sb; run_m = pq[2 * ncp]; }
+            }
+        }
+        flush();
+        const int e = st->empty_slot;
+        if (e < k && lt2((ACC)0, e, bestv, besti)) { bestv = 0; besti = e; }
+        const double dl = (double)bestv + (double)accB;
+        const double b = ((double)cf * bnd[0] + (double)cn * bnd[1] + bnd[2]) * 1.0001 + 1e-300;
+        if (!is_med[c]) {
+            cand_v[c] = dl;
+            cand_b[c] = b;
+            up = dl + b;
+        } else {
+            cand_v[c] = __builtin_huge_val();
+            cand_b[c] = 0.0;
+        }
+    }
+    red[threadIdx.x] = up;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) wg_u[blockIdx.x] = red[0];
+}
+
+// Global minimum upper bound U*, then the list of candidates whose lower
+// bound reaches it (and, for SWAP, lies below the application threshold).
+__global__ __launch_bounds__(1024) void k_rc_upper(const double *__restrict__ wg_u, int32_t nwg,
+                                                   DevState *__restrict__ st) {
+    __shared__ double red[1024];
+    if (st->done) return;
+    double u = __builtin_huge_val();
+    for (int i = threadIdx.x; i < nwg; i += 1024) u = fmin(u, wg_u[i]);
+    red[threadIdx.x] = u;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { st->f32_best = red[0]; st->n_list = 0; }
+}
+
+__global__ __launch_bounds__(256) void k_rc_mark(const double *__restrict__ cand_v,
+                                                 const double *__restrict__ cand_b, int64_t n,
+                                                 int32_t swap_mode, int32_t *__restrict__ list,
+                                                 DevState *__restrict__ st) {
+    if (st->done) return;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= n) return;
+    const double v = cand_v[c];
+    if (v == __builtin_huge_val()) return;
+    const double lo = v - cand_b[c];
+    bool take = lo <= st->f32_best;
+    if (swap_mode) take = take && (lo < -st->margin);
+    if (take) list[atomicAdd(&st->n_list, 1)] = (int32_t)c;
+}
+
+// ---------------------------------------------------------------- FP64 re-score
+// BUILD: A64(c) = sum_o min(d64(o,c), dn64(o)) (+ dn64(c)), one work-group per
+// listed candidate, fixed summation order.
+__global__ __launch_bounds__(256) void k_rc_build_rescore(
+    const float *__restrict__ X, int32_t dim, int64_t n, const double *__restrict__ dn64,
+    int32_t add_self, const int32_t *__restrict__ list, const DevState *__restrict__ st,
+    double *__restrict__ res_v) {
+    __shared__ double red[256];
+    const int m = st->n_list;
+    for (int idx = blockIdx.x; idx < m; idx += gridDim.x) {
+        const int64_t c = list[idx];
+        double s = 0.0;
+        for (int64_t o = threadIdx.x; o < n; o += 256) s += fmin(d64(X, dim, o, c), dn64[o]);
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) res_v[idx] = red[0] + (add_self ? dn64[c] : 0.0);
+        __syncthreads();
+    }
+}
+
+// SWAP: exact Delta(i,c) = R_i + B(c) + S_i(c) for every slot i, one
+// work-group per listed candidate.  Lane t walks a contiguous range of the
+// sorted objects; segments complete in its range go to LDS directly, the
+// partial first/last ones are combined afterwards in lane order.
+__global__ __launch_bounds__(256) void k_rc_swap_rescore(
+    const float *__restrict__ X, int32_t dim, int64_t n, int32_t k, const int32_t *__restrict__ srow,
+    const double *__restrict__ dn64, const double *__restrict__ ds64,
+    const int32_t *__restrict__ near, const int32_t *__restrict__ seg_off,
+    const double *__restrict__ R64, const int32_t *__restrict__ list, const DevState *__restrict__ st,
+    double *__restrict__ res_v, int32_t *__restrict__ res_i) {
+    extern __shared__ double sarr[];          // k per-slot sums
+    __shared__ double hv[256], tv[256], red[256];
+    __shared__ int hs[256], ts[256], ri[256];
+    const int t = threadIdx.x;
+    const int m = st->n_list;
+    const int64_t per = (n + 255) / 256;
+    for (int idx = blockIdx.x; idx < m; idx += gridDim.x) {
+        const int64_t c = list[idx];
+        for (int i = t; i < k; i += 256) sarr[i] = 0.0;
+        __syncthreads();
+        const int64_t j0 = min(n, (int64_t)t * per), j1 = min(n, j0 + per);
+        double B = 0.0, S = 0.0, first = 0.0;
+        int cur = -1, fs = -1;
+        for (int64_t j = j0; j < j1; ++j) {
+            const int64_t o = srow[j];
+            const int s = near[o];
+            if (s != cur) {
+                if (cur >= 0) {
+                    if (fs < 0) { fs = cur; first = S; }   // first segment of the range
+                    else sarr[cur] = S;                    // complete inside the range
+                }
+                cur = s;
+                S = 0.0;
+            }
+            const double d = d64(X, dim, o, c), lo = dn64[o], hi = ds64[o];
+            B += fmin(d - lo, 0.0);
+            S += fmin(fmax(d, lo), hi) - hi;
+        }
+        // head = first segment of the range, tail = last (may coincide)
+        if (cur >= 0 && fs < 0) { fs = cur; first = S; cur = -1; }
+        hs[t] = fs; hv[t] = first;
+        ts[t] = cur; tv[t] = S;
+        red[t] = B;
+        __syncthreads();
+        if (t == 0) {
+            int rs = -1;
+            double rm = 0.0;
+            for (int u = 0; u < 256; ++u) {
+                if (hs[u] >= 0) {
+                    if (hs[u] == rs) rm += hv[u];
+                    else { if (rs >= 0) sarr[rs] += rm; rs = hs[u]; rm = hv[u]; }
+                }
+                if (ts[u] >= 0) {
+                    if (ts[u] == rs) rm += tv[u];
+                    else { if (rs >= 0) sarr[rs] += rm; rs = ts[u]; rm = tv[u]; }
+                }
+            }
+            if (rs >= 0) sarr[rs] += rm;
+        }
+        for (int w = 128; w > 0; w >>= 1) {
+            __syncthreads();
+            if (t < w) red[t] += red[t + w];
+        }
+        __syncthreads();
+        // best slot: smallest R_i + S_i, smallest i on ties
+        double bv = __builtin_huge_val();
+        int bi = INT_MAX;
+        for (int i = t; i < k; i += 256) {
+            const double v = R64[i] + sarr[i];
+            if (v < bv) { bv = v; bi = i; }
+        }
+        hv[t] = bv; ri[t] = bi;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (t < w && lt2(hv[t + w], ri[t + w], hv[t], ri[t])) { hv[t] = hv[t + w]; ri[t] = ri[t + w]; }
+            __syncthreads();
+        }
+        if (t == 0) { res_v[idx] = hv[0] + red[0]; res_i[idx] = ri[0]; }
+        __syncthreads();
+        (void)seg_off;
+    }
+}
+
+// Lexicographic minimum over the re-scored list; BUILD picks the medoid,
+// SWAP applies the swap if its exact change is below -margin.
+__global__ __launch_bounds__(1024) void k_rc_pick(const double *__restrict__ res_v,
+                                                  const int32_t *__restrict__ res_i,
+                                                  const int32_t *__restrict__ list, int32_t swap_mode,
+                                                  int32_t t_step, int32_t *__restrict__ med,
+                                                  uint8_t *__restrict__ is_med, DevState *__restrict__ st,
+                                                  pamx_swap_record *__restrict__ trace) {
+    if (st->done) return;
+    const int m = st->n_list;
+    double v = __builtin_huge_val();
+    int i = INT_MAX, c = INT_MAX;
+    for (int idx = threadIdx.x; idx < m; idx += 1024) {
+        const double vv = res_v[idx];
+        const int ii = swap_mode ? res_i[idx] : 0, cc = list[idx];
+        if (lex_less(vv, ii, cc, v, i, c)) { v = vv; i = ii; c = cc; }
+    }
+    block_argmin3<double, 1024>(v, i, c);
+    if (threadIdx.x != 0) return;
+    st->rescored += m;
+    if (!swap_mode) {
+        st->best_c = c;
+        if (c != INT_MAX) { med[t_step] = c; is_med[c] = 1; }
+        else st->bad_medoids = 1;
+        return;
+    }
+    st->iter += 1;
+    st->best_i = i;
+    st->best_c = c;
+    st->best_v = v;
+    if (!(c != INT_MAX && v < -st->margin)) {
+        st->done = 1;
+        st->swapped = 0;
+        return;
+    }
+    const int old = med[i];
+    is_med[old] = 0;
+    is_med[c] = 1;
+    med[i] = c;
+    st->old_med = old;
+    st->new_slot = i;
+    st->new_med = c;
+    st->swapped = 1;
+    st->td += v;
+    if (trace && st->swaps < st->trace_cap) trace[st->swaps] = pamx_swap_record{i, c, v};
+    st->swaps += 1;
+}
+
+// ---------------------------------------------------------------- caches (FP64)
+template <bool FIRST>
+__global__ __launch_bounds__(256) void k_rc_build_update(const float *__restrict__ X, int32_t dim,
+                                                         int64_t n, double *__restrict__ dn64,
+                                                         float *__restrict__ dn32,
+                                                         const DevState *__restrict__ st) {
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int c = st->best_c;
+    if (o >= n || c == INT_MAX) return;
+    const double d = d64(X, dim, o, c);
+    const double v = FIRST ? d : fmin(dn64[o], d);
+    dn64[o] = v;
+    dn32[o] = (float)v;
+}
+
+// nearest / second over the k medoids with FP64 distances; FP32 copies
+__device__ __forceinline__ void rc_scan(const float *__restrict__ X, int dim, int k,
+                                        const int32_t *__restrict__ med, int64_t o, int lane,
+                                        bool wave, int &nr, int &sc, double &dn, double &ds) {
+    double d1 = __builtin_huge_val(), d2 = __builtin_huge_val();
+    int j1 = INT_MAX, j2 = INT_MAX;
+    const int j0 = wave ? lane : 0, js = wave ? 64 : 1;
+    for (int j = j0; j < k; j += js) {
+        const double d = d64(X, dim, o, med[j]);
+        if (lt2(d, j, d1, j1)) { d2 = d1; j2 = j1; d1 = d; j1 = j; }
+        else if (lt2(d, j, d2, j2)) { d2 = d; j2 = j; }
+    }
+    if (wave) {
+        for (int w = 32; w >= 1; w >>= 1) {
+            const double e1 = __shfl_xor(d1, w), e2 = __shfl_xor(d2, w);
+            const int f1 = __shfl_xor(j1, w), f2 = __shfl_xor(j2, w);
+            if (lt2(e1, f1, d1, j1)) {
+                if (lt2(e2, f2, d1, j1)) { d2 = e2; j2 = f2; } else { d2 = d1; j2 = j1; }
+                d1 = e1; j1 = f1;
+            } else if (lt2(e1, f1, d2, j2)) { d2 = e1; j2 = f1; }
+        }
+    }
+    nr = j1; sc = (j2 == INT_MAX) ? -1 : j2; dn = d1; ds = d2;
+}
+
+__global__ __launch_bounds__(256) void k_rc_cache_init(const float *__restrict__ X, int32_t dim,
+                                                       int64_t n, int32_t k,
+                                                       const int32_t *__restrict__ med,
+                                                       int32_t *__restrict__ near, int32_t *__restrict__ sec,
+                                                       double *__restrict__ dn64, double *__restrict__ ds64,
+                                                       float *__restrict__ dn32, float *__restrict__ ds32,
+                                                       int32_t *__restrict__ labels) {
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= n) return;
+    int nr, sc;
+    double a, b;
+    rc_scan(X, dim, k, med, o, 0, false, nr, sc, a, b);
+    near[o] = nr; sec[o] = sc; dn64[o] = a; ds64[o] = b;
+    dn32[o] = (float)a; ds32[o] = (float)b;
+    if (labels) labels[o] = nr;
+}
+
+__global__ __launch_bounds__(256) void k_rc_cache_update(const float *__restrict__ X, int32_t dim,
+                                                         int64_t n, int32_t *__restrict__ near,
+                                                         int32_t *__restrict__ sec,
+                                                         double *__restrict__ dn64, double *__restrict__ ds64,
+                                                         float *__restrict__ dn32, float *__restrict__ ds32,
+                                                         int32_t *__restrict__ rlist,
+                                                         DevState *__restrict__ st) {
+    if (st->done || !st->swapped) return;
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= n) return;
+    const int slot = st->new_slot;
+    int nr = near[o], sc = sec[o];
+    if (nr == slot || sc == slot) {
+        rlist[atomicAdd(&st->n_list, 1)] = (int32_t)o;
+        return;
+    }
+    const double dnew = d64(X, dim, o, st->new_med);
+    double a = dn64[o], b = ds64[o];
+    if (lt2(dnew, slot, a, nr)) { sc = nr; b = a; nr = slot; a = dnew; }
+    else if (lt2(dnew, slot, b, sc)) { sc = slot; b = dnew; }
+    near[o] = nr; sec[o] = sc; dn64[o] = a; ds64[o] = b;
+    dn32[o] = (float)a; ds32[o] = (float)b;
+}
+
+__global__ __launch_bounds__(256) void k_rc_cache_rescan(const float *__restrict__ X, int32_t dim,
+                                                         int32_t k, const int32_t *__restrict__ med,
+                                                         int32_t *__restrict__ near, int32_t *__restrict__ sec,
+                                                         double *__restrict__ dn64, double *__restrict__ ds64,
+                                                         float *__restrict__ dn32, float *__restrict__ ds32,
+                                                         const int32_t *__restrict__ rlist,
+                                                         const DevState *__restrict__ st) {
+    if (st->done || !st->swapped) return;
+    const int lane = threadIdx.x & 63;
+    const int nw = gridDim.x * 4;
+    const int m = st->n_list;
+    for (int idx = blockIdx.x * 4 + (threadIdx.x >> 6); idx < m; idx += nw) {
+        const int64_t o = rlist[idx];
+        int nr, sc;
+        double a, b;
+        rc_scan(X, dim, k, med, o, lane, true, nr, sc, a, b);
+        if (lane == 0) {
+            near[o] = nr; sec[o] = sc; dn64[o] = a; ds64[o] = b;
+            dn32[o] = (float)a; ds32[o] = (float)b;
+        }
+    }
+}
+
+// Per segment: R_i = sum (ds64 - dn64) in sorted order (one wave per slot);
+// FP32 copy.  Sorted FP32 thresholds and norms for the pass.
+__global__ __launch_bounds__(256) void k_rc_seg_const(const int32_t *__restrict__ srow,
+                                                      const int32_t *__restrict__ seg_off, int32_t k,
+                                                      const double *__restrict__ dn64,
+                                                      const double *__restrict__ ds64,
+                                                      double *__restrict__ R64,
+                                                      const DevState *__restrict__ st) {
+    if (st->done) return;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= k) return;
+    double s = 0.0;
+    for (int64_t j = seg_off[i] + lane; j < seg_off[i + 1]; j += 64) {
+        const int64_t o = srow[j];
+        s += ds64[o] - dn64[o];
+    }
+    for (int w = 32; w > 0; w >>= 1) s += __shfl_xor(s, w);
+    if (lane == 0) R64[i] = s;
+}
+
+__global__ __launch_bounds__(256) void k_rc_sorted_aux(const int32_t *__restrict__ srow, int64_t n,
+                                                       const float *__restrict__ sds,
+                                                       const float *__restrict__ nb,
+                                                       const double *__restrict__ eps0,
+                                                       float *__restrict__ sthr, float *__restrict__ snb,
+                                                       const DevState *__restrict__ st) {
+    if (st->done) return;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    // the change of an object depends on d only below ds: count d~ < ds + e_near
+    sthr[j] = (float)(((double)sds[j] + eps0[0]) * (1.0 + 0x1p-20) + 1e-30);
+    snb[j] = nb[srow[j]];
+}
+
+// TD, sum of ds, max ds, max R -> bounds of this iteration (SWAP):
+// bnd[0] = e_far, bnd[1] = e_near (per counted object, incl. the FP32
+// rounding of the object's terms), bnd[2] = summation bound (absolute).
+__global__ __launch_bounds__(1024) void k_rc_iter_bounds(const double *__restrict__ dn64,
+                                                         const double *__restrict__ ds64, int64_t n,
+                                                         const double *__restrict__ R64, int32_t k,
+                                                         int32_t L, int32_t Q, int32_t acc64,
+                                                         const double *__restrict__ eps0,
+                                                         double *__restrict__ bnd, DevState *__restrict__ st) {
+    __shared__ double r1[1024], r2[1024], r3[1024];
+    if (st->done) return;
+    const int t = threadIdx.x;
+    double td = 0.0, sds = 0.0, mx = 0.0;
+    for (int64_t o = t; o < n; o += 1024) { td += dn64[o]; sds += ds64[o]; mx = fmax(mx, ds64[o]); }
+    r1[t] = td; r2[t] = sds; r3[t] = mx;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (t < w) { r1[t] += r1[t + w]; r2[t] += r2[t + w]; r3[t] = fmax(r3[t], r3[t + w]); }
+        __syncthreads();
+    }
+    const double tdv = r1[0], sdsv = r2[0], dsmax = r3[0];
+    __syncthreads();
+    double rmax = 0.0;
+    for (int i = t; i < k; i += 1024) rmax = fmax(rmax, R64[i]);
+    r1[t] = rmax;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (t < w) r1[t] = fmax(r1[t], r1[t + w]);
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double rm = r1[0];
+        const double thr = (dsmax + eps0[0]) * (1.0 + 0x1p-20);
+        const double small = 0x1p-22 * thr + 3.0 * 0x1p-24 * thr;   // sqrt rounding, FP32 terms
+        bnd[0] = eps0[1] + small;
+        bnd[1] = eps0[0] + small;
+        const double chain = acc64 ? ((double)L + Q + 64.0) * 0x1p-52
+                                   : (32.0 + (L + 31) / 32 + Q + 10.0) * 0x1p-24 * 1.02;
+        bnd[2] = chain * (tdv + rm) + (acc64 ? 0.0 : 0x1p-23 * rm);
+        st->td = tdv;
+        st->margin = 4.0 * ((double)n + 256.0 + k + 68.0) * 0x1p-53 * sdsv;
+    }
+}
+
+// BUILD step thresholds: dn + e_near (FP32), +inf before the first medoid.
+__global__ __launch_bounds__(256) void k_rc_build_thr(const float *__restrict__ dn32, int64_t n,
+                                                      const double *__restrict__ eps0,
+                                                      float *__restrict__ thr) {
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= n) return;
+    const double lo = (double)dn32[o];
+    thr[o] = (lo == __builtin_huge_val()) ? __builtin_huge_valf()
+                                         : (float)((lo + eps0[0]) * (1.0 + 0x1p-20) + 1e-30);
+}
+
+// BUILD step bounds: bnd[0] = e_far, bnd[1] = e_near, bnd[2] = relative
+// summation factor (times A~(c)).
+__global__ __launch_bounds__(1024) void k_rc_build_bounds(const double *__restrict__ dn64, int64_t n,
+                                                          int32_t L, int32_t Q, int32_t first,
+                                                          int32_t acc64, const double *__restrict__ eps0,
+                                                          double *__restrict__ bnd) {
+    __shared__ double r[1024];
+    double mx = 0.0;
+    if (!first)
+        for (int64_t o = threadIdx.x; o < n; o += 1024) mx = fmax(mx, dn64[o]);
+    r[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) r[threadIdx.x] = fmax(r[threadIdx.x], r[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // step 0 counts every object: its distances are below eps0[3]
+        const double thr = first ? eps0[3] : (r[0] + eps0[0]) * (1.0 + 0x1p-20);
+        const double small = 0x1p-22 * thr + 3.0 * 0x1p-24 * thr;
+        bnd[0] = eps0[1] + small;
+        bnd[1] = eps0[0] + small;
+        bnd[2] = acc64 ? ((double)L + Q + 64.0) * 0x1p-52
+                       : (32.0 + (L + 31) / 32 + Q + 10.0) * 0x1p-24 * 1.02;
+    }
+}
+
+__global__ void k_rc_reset_list(DevState *st) {
+    if (threadIdx.x == 0 && !st->done) st->n_list = 0;
+}
+
+// ================================================================ host side
+struct RcPtrs {
+    __bf16 *Xs;
+    float *nb, *dn32, *ds32, *sdn, *sds, *sthr, *snb, *thr;
+    void *part;
+    double *eo, *dn64, *ds64, *R64, *mx, *eps0, *bnd, *wg_u, *res_v, *cand_v, *cand_b;
+    int32_t *near, *sec, *srow, *blkcnt, *seg_off, *cinfo3, *part_i, *list, *res_i, *rlist;
+    uint8_t *is_med;
+    DevState *st;
+};
+
+template <int KS, typename ACC>
+static void rc_build_pass_launch(const RcPtrs &p, const RcLayout &R, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL((k_rc_build_pass<KS, ACC>), dim3(R.n_ctiles, R.Q), dim3(kRT), 0, s,
+                       (const __bf16 *)p.Xs, R.KP, (const float *)p.nb, n, (const float *)p.dn32,
+                       (const float *)p.thr, (const double *)p.eps0, R.L, R.ncp,
+                       static_cast<ACC *>(p.part), p.part_i);
+}
+
+template <int KS, typename ACC>
+static void rc_swap_pass_launch(const RcPtrs &p, const RcLayout &R, int64_t n, int k, hipStream_t s) {
+    hipLaunchKernelGGL((k_rc_swap_pass<KS, ACC>), dim3(R.n_ctiles, R.Q), dim3(kRT), 0, s,
+                       (const __bf16 *)p.Xs, R.KP, (const float *)p.nb, n, k,
+                       (const int32_t *)p.srow, (const float *)p.sdn, (const float *)p.sds,
+                       (const float *)p.sthr, (const float *)p.snb, (const double *)p.eps0,
+                       (const int32_t *)p.seg_off, (const double *)p.R64, (const int32_t *)p.cinfo3,
+                       R.L, R.ncp, static_cast<ACC *>(p.part), p.part_i, (const DevState *)p.st);
+}
+
+template <typename ACC>
+static void rc_build_pass_any(const RcPtrs &p, const RcLayout &R, int64_t n, hipStream_t s) {
+    switch (R.KP / 16) {
+        case 1: rc_build_pass_launch<1, ACC>(p, R, n, s); break;
+        case 2: rc_build_pass_launch<2, ACC>(p, R, n, s); break;
+        case 3: rc_build_pass_launch<3, ACC>(p, R, n, s); break;
+        default: rc_build_pass_launch<4, ACC>(p, R, n, s); break;
+    }
+}
+
+template <typename ACC>
+static void rc_swap_pass_any(const RcPtrs &p, const RcLayout &R, int64_t n, int k, hipStream_t s) {
+    switch (R.KP / 16) {
+        case 1: rc_swap_pass_launch<1, ACC>(p, R, n, k, s); break;
+        case 2: rc_swap_pass_launch<2, ACC>(p, R, n, k, s); break;
+        case 3: rc_swap_pass_launch<3, ACC>(p, R, n, k, s); break;
+        default: rc_swap_pass_launch<4, ACC>(p, R, n, k, s); break;
+    }
+}
+
+static RcPtrs rc_ptrs(const RcLayout &R, void *ws) {
+    char *w = static_cast<char *>(ws);
+    RcPtrs p;
+    p.Xs = reinterpret_cast<__bf16 *>(w + R.Xb);
+    p.nb = reinterpret_cast<float *>(w + R.nb);
+    p.eo = reinterpret_cast<double *>(w + R.eo);
+    p.dn64 = reinterpret_cast<double *>(w + R.dn64);
+    p.ds64 = reinterpret_cast<double *>(w + R.ds64);
+    p.dn32 = reinterpret_cast<float *>(w + R.dn32);
+    p.ds32 = reinterpret_cast<float *>(w + R.ds32);
+    p.sdn = reinterpret_cast<float *>(w + R.sdn);
+    p.sds = reinterpret_cast<float *>(w + R.sds);
+    p.sthr = reinterpret_cast<float *>(w + R.sthr);
+    p.snb = reinterpret_cast<float *>(w + R.snb);
+    p.thr = reinterpret_cast<float *>(w + R.thr);
+    p.R64 = reinterpret_cast<double *>(w + R.R64);
+    p.part = w + R.part;
+    p.part_i = reinterpret_cast<int32_t *>(w + R.part_i);
+    p.cand_v = reinterpret_cast<double *>(w + R.cand_v);
+    p.cand_b = reinterpret_cast<double *>(w + R.cand_b);
+    p.wg_u = reinterpret_cast<double *>(w + R.wg_u);
+    p.list = reinterpret_cast<int32_t *>(w + R.list);
+    p.res_v = reinterpret_cast<double *>(w + R.res_v);
+    p.res_i = reinterpret_cast<int32_t *>(w + R.res_i);
+    p.rlist = reinterpret_cast<int32_t *>(w + R.rlist);
+    p.near = reinterpret_cast<int32_t *>(w + R.near);
+    p.sec = reinterpret_cast<int32_t *>(w + R.sec);
+    p.srow = reinterpret_cast<int32_t *>(w + R.srow);
+    p.blkcnt = reinterpret_cast<int32_t *>(w + R.blkcnt);
+    p.seg_off = reinterpret_cast<int32_t *>(w + R.seg_off);
+    p.cinfo3 = reinterpret_cast<int32_t *>(w + R.cinfo);
+    p.is_med = reinterpret_cast<uint8_t *>(w + R.is_med);
+    p.mx = reinterpret_cast<double *>(w + R.mx);
+    p.eps0 = reinterpret_cast<double *>(w + R.eps0);
+    p.bnd = reinterpret_cast<double *>(w + R.bnd);
+    p.st = reinterpret_cast<DevState *>(w + R.state);
+    return p;
+}
+
+template <typename X>
+__global__ void k_rc_fill(X *p, int64_t cnt, X v) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < cnt) p[t] = v;
+}
+template <typename X>
+static void rc_fill(X *p, int64_t cnt, X v, hipStream_t s) {
+    if (cnt > 0) hipLaunchKernelGGL(k_rc_fill<X>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, p, cnt, v);
+}
+
+__global__ void k_rc_state_init(DevState *st, int32_t max_iter, int32_t trace_cap) {
+    if (threadIdx.x == 0) {
+        DevState z{};
+        z.max_iter = max_iter;
+        z.trace_cap = trace_cap;
+        *st = z;
+    }
+}
+
+// prep + BUILD (Alg. 1) in the mixed-precision form
+hipError_t rc_prep_build(const float *X, int32_t dim, const RcLayout &R, int32_t k,
+                         const pamx_options &opt, int32_t *medoids, void *ws, hipStream_t s,
+                         const float *mean) {
+    RcPtrs p = rc_ptrs(R, ws);
+    const int64_t n = R.n;
+    const bool acc64 = opt.accum != PAMX_ACC_F32;
+    const unsigned ob = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_rc_prep, dim3(ob), dim3(256), 0, s, X, n, dim, R.KP, mean, p.Xs, p.nb, p.eo);
+    hipLaunchKernelGGL(k_rc_prep_max, dim3(1), dim3(1024), 0, s, (const double *)p.eo,
+                       (const float *)p.nb, n, p.mx);
+    hipLaunchKernelGGL(k_rc_eps, dim3(1), dim3(1), 0, s, (const double *)p.mx, R.KP, p.eps0);
+    hipLaunchKernelGGL(k_rc_state_init, dim3(1), dim3(1), 0, s, p.st, opt.max_iter,
+                       opt.trace ? opt.trace_cap : 0);
+    rc_fill<uint8_t>(p.is_med, n, 0, s);
+    rc_fill<double>(p.dn64, n, __builtin_huge_val(), s);
+    rc_fill<float>(p.dn32, n, __builtin_huge_valf(), s);
+    const int nmwg = (int)((n + 255) / 256);
+    for (int32_t t = 0; t < k; ++t) {
+        hipLaunchKernelGGL(k_rc_build_thr, dim3(ob), dim3(256), 0, s, (const float *)p.dn32, n,
+                           (const double *)p.eps0, p.thr);
+        hipLaunchKernelGGL(k_rc_build_bounds, dim3(1), dim3(1024), 0, s, (const double *)p.dn64, n,
+                           R.L, R.Q, (int32_t)(t == 0), (int32_t)acc64, (const double *)p.eps0, p.bnd);
+        const int add_self = (opt.build_exclude_self && t > 0) ? 1 : 0;
+        if (acc64) {
+            rc_build_pass_any<double>(p, R, n, s);
+            hipLaunchKernelGGL(k_rc_build_merge<double>, dim3(nmwg), dim3(256), 0, s,
+                               (const double *)p.part, (const int32_t *)p.part_i, R.Q, R.ncp, n,
+                               (const double *)p.dn64, (const uint8_t *)p.is_med, add_self,
+                               (const double *)p.bnd, p.cand_v, p.cand_b, p.wg_u);
+        } else {
+            rc_build_pass_any<float>(p, R, n, s);
+            hipLaunchKernelGGL(k_rc_build_merge<float>, dim3(nmwg), dim3(256), 0, s,
+                               (const float *)p.part, (const int32_t *)p.part_i, R.Q, R.ncp, n,
+                               (const double *)p.dn64, (const uint8_t *)p.is_med, add_self,
+                               (const double *)p.bnd, p.cand_v, p.cand_b, p.wg_u);
+        }
+        hipLaunchKernelGGL(k_rc_upper, dim3(1), dim3(1024), 0, s, (const double *)p.wg_u, nmwg, p.st);
+        hipLaunchKernelGGL(k_rc_mark, dim3(nmwg), dim3(256), 0, s, (const double *)p.cand_v,
+                           (const double *)p.cand_b, n, 0, p.list, p.st);
+        hipLaunchKernelGGL(k_rc_build_rescore, dim3(1024), dim3(256), 0, s, X, dim, n,
+                           (const double *)p.dn64, add_self, (const int32_t *)p.list,
+                           (const DevState *)p.st, p.res_v);
+        hipLaunchKernelGGL(k_rc_pick, dim3(1), dim3(1024), 0, s, (const double *)p.res_v,
+                           (const int32_t *)p.res_i, (const int32_t *)p.list, 0, t, medoids, p.is_med,
+                           p.st, (pamx_swap_record *)nullptr);
+        if (t == 0)
+            hipLaunchKernelGGL(k_rc_build_update<true>, dim3(ob), dim3(256), 0, s, X, dim, n, p.dn64,
+                               p.dn32, (const DevState *)p.st);
+        else
+            hipLaunchKernelGGL(k_rc_build_update<false>, dim3(ob), dim3(256), 0, s, X, dim, n, p.dn64,
+                               p.dn32, (const DevState *)p.st);
+    }
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(1024) void k_rc_td(const double *__restrict__ dn64, int64_t n,
+                                                DevState *__restrict__ st) {
+    double s = 0.0;
+    for (int64_t o = threadIdx.x; o < n; o += 1024) s += dn64[o];
+    s = block_sum<double, 1024>(s);
+    if (threadIdx.x == 0) st->td = s;
+}
+
+hipError_t rc_td(const RcLayout &R, void *ws, hipStream_t s) {
+    RcPtrs p = rc_ptrs(R, ws);
+    hipLaunchKernelGGL(k_rc_td, dim3(1), dim3(1024), 0, s, (const double *)p.dn64, R.n, p.st);
+    return hipGetLastError();
+}
+
+hipError_t rc_swap_init(const float *X, int32_t dim, const RcLayout &R, const int32_t *medoids,
+                        const pamx_options &opt, void *ws, hipStream_t s) {
+    RcPtrs p = rc_ptrs(R, ws);
+    const int64_t n = R.n;
+    hipLaunchKernelGGL(k_rc_state_init, dim3(1), dim3(1), 0, s, p.st, opt.max_iter,
+                       opt.trace ? opt.trace_cap : 0);
+    hipLaunchKernelGGL(k_rc_cache_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, dim, n,
+                       R.k, medoids, p.near, p.sec, p.dn64, p.ds64, p.dn32, p.ds32, (int32_t *)nullptr);
+    return hipGetLastError();
+}
+
+// segment kernels of swap.hip, reused on the FP32 cache copies
+hipError_t launch_segments_f32(const int32_t *near, const float *dn, const float *ds, int64_t n,
+                               int32_t k, int32_t n_oblk, int32_t *blkcnt, int32_t *seg_off,
+                               int32_t L, int32_t Q, void *cinfo, int32_t *srow, float *sdn, float *sds,
+                               DevState *st, hipStream_t s);
+
+hipError_t rc_swap_iteration(const float *X, int32_t dim, const RcLayout &R, int32_t *medoids,
+                             const pamx_options &opt, void *ws, hipStream_t s, hipEvent_t ev0,
+                             hipEvent_t ev1) {
+    RcPtrs p = rc_ptrs(R, ws);
+    const int64_t n = R.n;
+    const int32_t k = R.k;
+    const bool acc64 = opt.accum != PAMX_ACC_F32;
+    const unsigned ob = (unsigned)((n + 255) / 256);
+    const int nmwg = (int)((n + 255) / 256);
+    hipError_t e = launch_segments_f32(p.near, p.dn32, p.ds32, n, k, R.n_oblk, p.blkcnt, p.seg_off,
+                                       R.L, R.Q, p.cinfo3, p.srow, p.sdn, p.sds, p.st, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rc_seg_const, dim3((k + 3) / 4), dim3(256), 0, s, (const int32_t *)p.srow,
+                       (const int32_t *)p.seg_off, k, (const double *)p.dn64, (const double *)p.ds64,
+                       p.R64, (const DevState *)p.st);
+    hipLaunchKernelGGL(k_rc_iter_bounds, dim3(1), dim3(1024), 0, s, (const double *)p.dn64,
+                       (const double *)p.ds64, n, (const double *)p.R64, k, R.L, R.Q, (int32_t)acc64,
+                       (const double *)p.eps0, p.bnd, p.st);
+    hipLaunchKernelGGL(k_rc_sorted_aux, dim3(ob), dim3(256), 0, s, (const int32_t *)p.srow, n,
+                       (const float *)p.sds, (const float *)p.nb, (const double *)p.eps0, p.sthr,
+                       p.snb, (const DevState *)p.st);
+    if (ev0) (void)hipEventRecord(ev0, s);
+    if (acc64) rc_swap_pass_any<double>(p, R, n, k, s);
+    else rc_swap_pass_any<float>(p, R, n, k, s);
+    if (ev1) (void)hipEventRecord(ev1, s);
+    if (acc64)
+        hipLaunchKernelGGL(k_rc_swap_merge<double>, dim3(nmwg), dim3(256), 0, s, (const double *)p.part,
+                           (const int32_t *)p.part_i, (const int32_t *)p.cinfo3, R.Q, n, k, R.ncp,
+                           (const double *)p.R64, (const uint8_t *)p.is_med, (const DevState *)p.st,
+                           (const double *)p.bnd, p.cand_v, p.cand_b, p.wg_u);
+    else
+        hipLaunchKernelGGL(k_rc_swap_merge<float>, dim3(nmwg), dim3(256), 0, s, (const float *)p.part,
+                           (const int32_t *)p.part_i, (const int32_t *)p.cinfo3, R.Q, n, k, R.ncp,
+                           (const double *)p.R64, (const uint8_t *)p.is_med, (const DevState *)p.st,
+                           (const double *)p.bnd, p.cand_v, p.cand_b, p.wg_u);
+    hipLaunchKernelGGL(k_rc_upper, dim3(1), dim3(1024), 0, s, (const double *)p.wg_u, nmwg, p.st);
+    hipLaunchKernelGGL(k_rc_mark, dim3(nmwg), dim3(256), 0, s, (const double *)p.cand_v,
+                       (const double *)p.cand_b, n, 1, p.list, p.st);
+    hipLaunchKernelGGL(k_rc_swap_rescore, dim3(1024), dim3(256), (size_t)k * 8, s, X, dim, n, k,
+                       (const int32_t *)p.srow, (const double *)p.dn64, (const double *)p.ds64,
+                       (const int32_t *)p.near, (const int32_t *)p.seg_off, (const double *)p.R64,
+                       (const int32_t *)p.list, (const DevState *)p.st, p.res_v, p.res_i);
+    hipLaunchKernelGGL(k_rc_pick, dim3(1), dim3(1024), 0, s, (const double *)p.res_v,
+                       (const int32_t *)p.res_i, (const int32_t *)p.list, 1, 0, medoids, p.is_med, p.st,
+                       static_cast<pamx_swap_record *>(opt.trace));
+    hipLaunchKernelGGL(k_rc_reset_list, dim3(1), dim3(1), 0, s, p.st);
+    hipLaunchKernelGGL(k_rc_cache_update, dim3(ob), dim3(256), 0, s, X, dim, n, p.near, p.sec, p.dn64,
+                       p.ds64, p.dn32, p.ds32, p.rlist, p.st);
+    hipLaunchKernelGGL(k_rc_cache_rescan, dim3(256), dim3(256), 0, s, X, dim, k,
+                       (const int32_t *)medoids, p.near, p.sec, p.dn64, p.ds64, p.dn32, p.ds32,
+                       (const int32_t *)p.rlist, (const DevState *)p.st);
+    return hipGetLastError();
+}
+
+hipError_t rc_finalize(const float *X, int32_t dim, const RcLayout &R, const int32_t *medoids,
+                       int32_t *labels, void *ws, hipStream_t s) {
+    RcPtrs p = rc_ptrs(R, ws);
+    const int64_t n = R.n;
+    hipLaunchKernelGGL(k_rc_cache_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, dim, n,
+                       R.k, medoids, p.near, p.sec, p.dn64, p.ds64, p.dn32, p.ds32, labels);
+    hipLaunchKernelGGL(k_rc_td, dim3(1), dim3(1024), 0, s, (const double *)p.dn64, n, p.st);
+    return hipGetLastError();
+}
+
+}  // namespace pamx

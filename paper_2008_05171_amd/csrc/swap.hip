@@ -1045,6 +1045,23 @@ hipError_t enqueue_swap_caches(const T *D, int64_t ld, const Layout &L, const in
     return enqueue_caches<T>(D, ld, L, medoids, nullptr, ws, s);
 }
 
+// The segment kernels on FP32 caches, for the mixed-precision form.
+hipError_t launch_segments_f32(const int32_t *near, const float *dn, const float *ds, int64_t n,
+                               int32_t k, int32_t n_oblk, int32_t *blkcnt, int32_t *seg_off,
+                               int32_t L, int32_t Q, void *cinfo, int32_t *srow, float *sdn, float *sds,
+                               DevState *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_count, dim3(n_oblk), dim3(kObjBlk), (size_t)k * 4, s, near, n, k,
+                       blkcnt, st);
+    hipLaunchKernelGGL(k_seg_colscan, dim3((k + 3) / 4), dim3(256), 0, s, blkcnt, n_oblk, k,
+                       seg_off + 1, (const DevState *)st);
+    hipLaunchKernelGGL(k_seg_scan<float>, dim3(1), dim3(1024), (size_t)(k + 1) * 4, s, k, n, seg_off,
+                       dn, ds, L, Q, static_cast<ChunkInfo *>(cinfo), st);
+    hipLaunchKernelGGL(k_seg_scatter<float>, dim3(n_oblk), dim3(kObjBlk), 0, s, near, dn, ds, n, k,
+                       (const int32_t *)blkcnt, (const int32_t *)seg_off, srow, sdn, sds,
+                       (const DevState *)st);
+    return hipGetLastError();
+}
+
 // explicit instantiations
 #define PAMX_INST(T)                                                                           \
     template hipError_t run_build<T>(const T *, int64_t, const Layout &, int32_t, int32_t,     \

@@ -18,6 +18,7 @@ PAMX_INPUT_D, PAMX_INPUT_X = 0, 1
 PAMX_L1, PAMX_L2 = 1, 2
 PAMX_FASTPAM1, PAMX_FASTPAM2 = 1, 2
 PAMX_ACC_F64, PAMX_ACC_F32 = 0, 1
+PAMX_DIST_STORED, PAMX_DIST_BF16 = 0, 1
 PAMX_OK, PAMX_WARN_MAXITER = 0, 1
 PAMX_ERR_ARG, PAMX_ERR_WORKSPACE, PAMX_ERR_HIP = -1, -2, -3
 PAMX_ERR_INVALID_MEDOIDS, PAMX_ERR_UNSUPPORTED = -4, -5
@@ -27,7 +28,8 @@ class pamx_options(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("accum", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("build_exclude_self", ctypes.c_int32),
                 ("trace_cap", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("trace", ctypes.c_void_p)]
+                ("profile", ctypes.c_int32), ("dist_mode", ctypes.c_int32),
+                ("trace", ctypes.c_void_p)]
 
 
 class pamx_swap_record(ctypes.Structure):
