@@ -142,36 +142,64 @@ struct RowVals {
     const float *v0, *v1, *v2, *v3;   // per (sorted) position; v3 may be null
 };
 
+// Registers holding one block's staged data in flight (software pipeline:
+// the next block's global loads overlap the current block's MFMA and row loop).
 template <int KS>
-__device__ __forceinline__ void gram_block(const __bf16 *__restrict__ Xs, int KP,
+struct Stage {
+    static constexpr int kPieces = KS * 4;                            // 16-byte pieces per split row
+    static constexpr int kPer = (kRB * kPieces + kRT - 1) / kRT;      // pieces per lane
+    bf16x8 v[kPer];
+    float4 rv;
+};
+
+template <int KS>
+__device__ __forceinline__ void stage_load(Stage<KS> &st, const __bf16 *__restrict__ Xs, int KP,
                                            const int32_t *__restrict__ rows, int64_t j0, int64_t jend,
-                                           const RowVals &rvals, __bf16 *__restrict__ As,
-                                           float4 *__restrict__ Rv, float *__restrict__ Gw,
-                                           const bf16x8 (&bh)[2][KS], const bf16x8 (&bl)[2][KS]) {
-    const int tid = threadIdx.x, lane = tid & 63;
-    constexpr int kPieces = KS * 4;   // 16-byte pieces per split row (hi + lo)
-    for (int e = tid; e < kRB * kPieces; e += kRT) {
-        const int r = e / kPieces, p = e - r * kPieces;
+                                           const RowVals &rvals) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < Stage<KS>::kPer; ++u) {
+        const int e = tid + u * kRT;
+        const int r = e / Stage<KS>::kPieces, p = e - r * Stage<KS>::kPieces;
         const int64_t j = j0 + r;
-        bf16x8 v;
-        if (j < jend) {
+        if (e < kRB * Stage<KS>::kPieces && j < jend) {
             const int64_t o = rows ? rows[j] : j;
-            v = *reinterpret_cast<const bf16x8 *>(Xs + o * 2 * KP + p * 8);
+            st.v[u] = *reinterpret_cast<const bf16x8 *>(Xs + o * 2 * KP + p * 8);
         } else {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = (__bf16)0.0f;
+            for (int q = 0; q < 8; ++q) st.v[u][q] = (__bf16)0.0f;
         }
-        // hi pieces to [0, KP), lo pieces to [kAS, kAS + KP)
-        const int half = (p * 8) / KP, off = (p * 8) % KP;
-        *reinterpret_cast<bf16x8 *>(As + r * 2 * kAS + half * kAS + off) = v;
     }
+    st.rv = make_float4(0.f, 0.f, 0.f, 0.f);
     if (tid < kRB) {
         const int64_t j = j0 + tid;
-        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (j < jend) q = make_float4(rvals.v0[j], rvals.v1[j], rvals.v2[j], rvals.v3 ? rvals.v3[j] : 0.f);
-        Rv[tid] = q;
+        if (j < jend)
+            st.rv = make_float4(rvals.v0[j], rvals.v1[j], rvals.v2[j], rvals.v3 ? rvals.v3[j] : 0.f);
     }
-    __syncthreads();
+}
+
+template <int KS>
+__device__ __forceinline__ void stage_store(const Stage<KS> &st, int KP, __bf16 *__restrict__ As,
+                                            float4 *__restrict__ Rv) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < Stage<KS>::kPer; ++u) {
+        const int e = tid + u * kRT;
+        if (e < kRB * Stage<KS>::kPieces) {
+            const int r = e / Stage<KS>::kPieces, p = e - r * Stage<KS>::kPieces;
+            const int half = (p * 8) / KP, off = (p * 8) % KP;   // hi to [0, KP), lo to [kAS, kAS + KP)
+            *reinterpret_cast<bf16x8 *>(As + r * 2 * kAS + half * kAS + off) = st.v[u];
+        }
+    }
+    if (tid < kRB) Rv[tid] = st.rv;
+}
+
+// The Gram tile of the staged block (after the barrier that publishes it):
+// hi.hi' + hi.lo' + lo.hi' per k step, then the transposed store.
+template <int KS>
+__device__ __forceinline__ void gram_tile(const __bf16 *__restrict__ As, float *__restrict__ Gw,
+                                          const bf16x8 (&bh)[2][KS], const bf16x8 (&bl)[2][KS]) {
+    const int lane = threadIdx.x & 63;
     floatx16 acc0, acc1;
 #pragma unroll
     for (int v = 0; v < 16; ++v) { acc0[v] = 0.0f; acc1[v] = 0.0f; }
@@ -193,7 +221,6 @@ __device__ __forceinline__ void gram_block(const __bf16 *__restrict__ Xs, int KP
         Gw[i * kGS + r] = acc0[v];
         Gw[(32 + i) * kGS + r] = acc1[v];
     }
-    __syncthreads();
 }
 
 // B operands (hi and lo) of a wave's two column blocks for its 64 candidates
@@ -248,9 +275,15 @@ __global__ __launch_bounds__(kRT) void k_rc_build_pass(
     int cf = 0, cn = 0;
     float *Gw = G[w];
     const RowVals rv{nb, dn, thr, nullptr};
+    Stage<KS> stg;
+    stage_load<KS>(stg, Xs, KP, nullptr, a, b, rv);
     for (int64_t j0 = a; j0 < b; j0 += kRB) {
         float4 *Rb = Rv[((j0 - a) / kRB) & 1];
-        gram_block<KS>(Xs, KP, nullptr, j0, b, rv, As, Rb, Gw, bh, bl);
+        stage_store<KS>(stg, KP, As, Rb);
+        __syncthreads();
+        if (j0 + kRB < b) stage_load<KS>(stg, Xs, KP, nullptr, j0 + kRB, b, rv);
+        gram_tile<KS>(As, Gw, bh, bl);
+        __syncthreads();
         const int m = (int)min((int64_t)kRB, b - j0);
         ACC blk = 0;
         for (int r = 0; r < m; ++r) {
@@ -313,9 +346,15 @@ __global__ __launch_bounds__(kRT) void k_rc_swap_pass(
     };
     float *Gw = G[w];
     const RowVals rv{snb, sdn, sds, sthr};
+    Stage<KS> stg;
+    stage_load<KS>(stg, Xs, KP, srow, a, b, rv);
     for (int64_t j0 = a; j0 < b; j0 += kRB) {
         float4 *Rb = Rv[((j0 - a) / kRB) & 1];
-        gram_block<KS>(Xs, KP, srow, j0, b, rv, As, Rb, Gw, bh, bl);
+        stage_store<KS>(stg, KP, As, Rb);
+        __syncthreads();
+        if (j0 + kRB < b) stage_load<KS>(stg, Xs, KP, srow, j0 + kRB, b, rv);
+        gram_tile<KS>(As, Gw, bh, bl);
+        __syncthreads();
         const int m = (int)min((int64_t)kRB, b - j0);
         ACC bblk = 0, sblk = 0;
         for (int r = 0; r < m; ++r) {
