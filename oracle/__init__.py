@@ -66,6 +66,9 @@ def _load():
     lib.orc_build.argtypes = [P, P, i64, i32, i32, i32, i32, P, P, P]
     lib.orc_swap_search.argtypes = [P, P, i64, i32, i32, P, i32, i64, i64, P, P, P]
     lib.orc_swap.argtypes = [P, P, i64, i32, i32, P, i32, i32, i32, P, P, P, i32, P, P, P]
+    lib.orc_dist_rows.argtypes = [P, i64, i32, i32, P, i64, P]
+    lib.orc_swap_list.argtypes = [P, P, i64, i32, i32, P, i32, P, i64, P]
+    lib.orc_build_list.argtypes = [P, P, i64, i32, i32, P, i32, i32, P, i64, P]
     _lib = lib
     return lib
 
@@ -108,6 +111,18 @@ def dist_matrix(X, metric=L2) -> np.ndarray:
     if rc:
         raise ValueError("orc_dist_matrix rc=%d" % rc)
     return D
+
+
+def dist_rows(X, rows, metric=L2) -> np.ndarray:
+    """Rows ``rows`` of the dissimilarity matrix of points X, FP64."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    n, dim = X.shape
+    out = np.empty((len(rows), n), dtype=np.float64)
+    rc = _load().orc_dist_rows(_ptr(X), n, dim, int(metric), _ptr(rows), len(rows), _ptr(out))
+    if rc:
+        raise ValueError("orc_dist_rows rc=%d" % rc)
+    return out
 
 
 def change(d, is_i, dn, ds) -> float:
@@ -167,6 +182,33 @@ def swap_search(med, D=None, X=None, metric=L2, c_begin=0, c_end=None):
     if rc < 0:
         raise ValueError("orc_swap_search rc=%d" % rc)
     return bool(rc), bd.value, bi.value, bc.value
+
+
+def swap_list(med, cand, D=None, X=None, metric=L2) -> np.ndarray:
+    """Delta TD of every (candidate in ``cand``, slot) swap: array (len(cand), k),
+    NaN rows for candidates that are medoids (Alg. 2 inner sum, Eq. change)."""
+    s = _Src(D, X, metric)
+    med = np.ascontiguousarray(med, dtype=np.int32)
+    cand = np.ascontiguousarray(cand, dtype=np.int64)
+    out = np.empty((len(cand), len(med)), np.float64)
+    rc = _load().orc_swap_list(*s.args(), _ptr(med), len(med), _ptr(cand), len(cand), _ptr(out))
+    if rc:
+        raise ValueError("orc_swap_list rc=%d" % rc)
+    return out
+
+
+def build_list(prefix, cand, D=None, X=None, metric=L2, exclude_self=False) -> np.ndarray:
+    """BUILD change (Alg. 1) of taking each of ``cand`` as the next medoid after
+    the medoids ``prefix``; an empty prefix gives the first step's column sums."""
+    s = _Src(D, X, metric)
+    prefix = np.ascontiguousarray(prefix, dtype=np.int32)
+    cand = np.ascontiguousarray(cand, dtype=np.int64)
+    out = np.empty(len(cand), np.float64)
+    rc = _load().orc_build_list(*s.args(), _ptr(prefix) if len(prefix) else None, len(prefix),
+                                int(bool(exclude_self)), _ptr(cand), len(cand), _ptr(out))
+    if rc:
+        raise ValueError("orc_build_list rc=%d" % rc)
+    return out
 
 
 @dataclass

@@ -114,6 +114,21 @@ int orc_dist_matrix(const double *X, int64_t n, int32_t dim, int32_t metric, dou
     return ORC_OK;
 }
 
+/* Selected rows of the dissimilarity matrix: out[j*n + b] = d(x_rows[j], x_b). */
+int orc_dist_rows(const double *X, int64_t n, int32_t dim, int32_t metric,
+                  const int64_t *rows, int64_t m, double *out)
+{
+    src_t s;
+    if (!out || !rows || m < 0 || make_src(&s, NULL, X, n, dim, metric)) return ORC_ERR_ARG;
+    for (int64_t j = 0; j < m; ++j)
+        if (rows[j] < 0 || rows[j] >= n) return ORC_ERR_ARG;
+    #pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < m; ++j)
+        for (int64_t b = 0; b < n; ++b)
+            out[j * n + b] = dist(&s, rows[j], b);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------ */
 /* Nearest / second-nearest medoid of every object (reading R4).        */
 /* ------------------------------------------------------------------ */
@@ -356,6 +371,105 @@ static int td_matches(double running, double fresh)
 {
     double tol = 1e-9 * fabs(fresh) + 1e-9;
     return fabs(running - fresh) <= tol;
+}
+
+/* ------------------------------------------------------------------ */
+/* Changes for a listed set of candidates, so that single steps of a    */
+/* large run can be checked without a full search.                      */
+/* ------------------------------------------------------------------ */
+
+/* SWAP: out[j*k + i] = Delta TD of replacing the medoid in slot i by
+ * cand[j], the sum of Eq. change over the objects of Alg. 2's inner loop
+ * (ascending object order, as in a full search).  NAN where cand[j] is a
+ * medoid. */
+int orc_swap_list(const double *D, const double *X, int64_t n, int32_t dim, int32_t metric,
+                  const int32_t *med, int32_t k, const int64_t *cand, int64_t m, double *out)
+{
+    src_t s;
+    if (make_src(&s, D, X, n, dim, metric) || !med || k < 2 || k > n || !cand || m < 0 || !out)
+        return ORC_ERR_ARG;
+    for (int64_t j = 0; j < m; ++j)
+        if (cand[j] < 0 || cand[j] >= n) return ORC_ERR_ARG;
+    double *dn = (double *)malloc(sizeof(double) * (size_t)n);
+    double *ds = (double *)malloc(sizeof(double) * (size_t)n);
+    int32_t *near = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    unsigned char *is_med = medoid_mask(n, med, k);
+    if (!dn || !ds || !near || !is_med) {
+        free(dn); free(ds); free(near); free(is_med);
+        return ORC_ERR_MEM;
+    }
+    nearest_all(&s, med, k, near, dn, ds);
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < m; ++j) {
+        double *acc = out + j * (int64_t)k;
+        const int64_t c = cand[j];
+        for (int32_t i = 0; i < k; ++i) acc[i] = is_med[c] ? NAN : 0.0;
+        if (is_med[c]) continue;
+        for (int64_t o = 0; o < n; ++o) {
+            const double d = dist(&s, o, c);
+            for (int32_t i = 0; i < k; ++i) {
+                if (is_med[o] && o != med[i]) continue;
+                acc[i] += orc_change(d, near[o] == i, dn[o], ds[o]);
+            }
+        }
+    }
+    free(dn); free(ds); free(near); free(is_med);
+    return ORC_OK;
+}
+
+/* BUILD (Alg. 1): the change of taking cand[j] as the next medoid after
+ * med[0..t-1].  t == 0 gives the first step's sum of distances to all other
+ * objects.  Self-term by reading R1 (exclude_self selects the literal loop
+ * bounds).  NAN where cand[j] is already a medoid. */
+int orc_build_list(const double *D, const double *X, int64_t n, int32_t dim, int32_t metric,
+                   const int32_t *med, int32_t t, int32_t exclude_self, const int64_t *cand,
+                   int64_t m, double *out)
+{
+    src_t s;
+    if (make_src(&s, D, X, n, dim, metric) || t < 0 || t >= n || (t > 0 && !med) || !cand ||
+        m < 0 || !out)
+        return ORC_ERR_ARG;
+    for (int64_t j = 0; j < m; ++j)
+        if (cand[j] < 0 || cand[j] >= n) return ORC_ERR_ARG;
+    unsigned char *is_med = (unsigned char *)calloc((size_t)n, 1);
+    double *dn = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!is_med || !dn) { free(is_med); free(dn); return ORC_ERR_MEM; }
+    for (int32_t i = 0; i < t; ++i) {
+        if (med[i] < 0 || med[i] >= n || is_med[med[i]]) { free(is_med); free(dn); return ORC_ERR_ARG; }
+        is_med[med[i]] = 1;
+    }
+    /* distance of every object to its nearest chosen medoid (0 for medoids) */
+    #pragma omp parallel for schedule(static)
+    for (int64_t o = 0; o < n; ++o) {
+        double best = INFINITY;
+        if (is_med[o]) best = 0.0;
+        else
+            for (int32_t i = 0; i < t; ++i) {
+                double d = dist(&s, o, med[i]);
+                if (d < best) best = d;
+            }
+        dn[o] = best;
+    }
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < m; ++j) {
+        const int64_t c = cand[j];
+        if (is_med[c]) { out[j] = NAN; continue; }
+        double acc = 0.0;
+        if (t == 0) {
+            for (int64_t o = 0; o < n; ++o)
+                if (o != c) acc += dist(&s, o, c);
+        } else {
+            for (int64_t o = 0; o < n; ++o) {
+                if (is_med[o] || o == c) continue;
+                double delta = dist(&s, o, c) - dn[o];
+                if (delta < 0.0) acc += delta;
+            }
+            if (!exclude_self) acc -= dn[c];
+        }
+        out[j] = acc;
+    }
+    free(is_med); free(dn);
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------ */

@@ -131,6 +131,11 @@ def test_dist_matrix_vs_scipy():
                                rtol=1e-13, atol=1e-13)
     Xi = datagen.int_points(50, 2, 0, 1000, seed=1)
     assert np.array_equal(oracle.dist_matrix(Xi, oracle.L1), cdist(Xi, Xi, "cityblock"))
+    rows = np.array([36, 0, 7, 7])
+    np.testing.assert_allclose(oracle.dist_rows(X, rows), cdist(X[rows], X), rtol=1e-13,
+                               atol=1e-13)
+    rows = np.array([49, 0, 7, 7])
+    assert np.array_equal(oracle.dist_rows(Xi, rows, oracle.L1), cdist(Xi[rows], Xi, "cityblock"))
 
 
 # ---------------------------------------------------------------- BUILD
@@ -213,6 +218,77 @@ def test_delta_matches_td_difference():
         assert oracle.delta(med, i, c, D=D) == pytest.approx(want, abs=1e-12)
         # points mode computes the same distances on the fly
         assert oracle.delta(med, i, c, X=X) == pytest.approx(want, abs=1e-12)
+
+
+def test_swap_list_matches_td_difference():
+    """The listed-candidate table equals the TD difference of every swap, on
+    integer distances exactly, NaN for candidates that are medoids."""
+    rng = np.random.default_rng(23)
+    for trial in range(25):
+        n = int(rng.integers(4, 16))
+        k = int(rng.integers(2, n))
+        if trial % 2:
+            X = rng.integers(0, 7, size=(n, 2)).astype(float)
+            D = oracle.dist_matrix(X, oracle.L1)
+            metric, exact = oracle.L1, True
+        else:
+            X = rng.normal(size=(n, 3))
+            D = oracle.dist_matrix(X)
+            metric, exact = oracle.L2, False
+        med = [int(v) for v in rng.choice(n, size=k, replace=False)]
+        cand = rng.permutation(n)
+        tab = oracle.swap_list(med, cand, D=D)
+        tabx = oracle.swap_list(med, cand, X=X, metric=metric)
+        Dl = D.tolist()
+        td0 = brute.td_of(Dl, med)
+        for j, c in enumerate(cand):
+            if c in med:
+                assert np.isnan(tab[j]).all() and np.isnan(tabx[j]).all()
+                continue
+            for i in range(k):
+                m2 = list(med)
+                m2[i] = int(c)
+                want = brute.td_of(Dl, m2) - td0
+                if exact:
+                    assert tab[j, i] == want and tabx[j, i] == want, (trial, i, c)
+                else:
+                    assert tab[j, i] == pytest.approx(want, abs=1e-12)
+                    assert tabx[j, i] == pytest.approx(want, abs=1e-12)
+
+
+@pytest.mark.parametrize("exclude_self", [False, True])
+def test_build_list_matches_td_difference(exclude_self):
+    """BUILD change of each candidate after a prefix: the TD difference of
+    adding it (self-term reading), or that plus its own nearest distance
+    (literal loop bounds); the first step is the sum of distances to all
+    other objects.  Along a BUILD run the chosen medoid is the first minimum."""
+    rng = np.random.default_rng(29)
+    for trial in range(20):
+        n = int(rng.integers(3, 15))
+        X = rng.integers(0, 9, size=(n, 2)).astype(float)
+        D = oracle.dist_matrix(X, oracle.L1)
+        Dl = D.tolist()
+        t = int(rng.integers(0, n))
+        prefix = [int(v) for v in rng.choice(n, size=t, replace=False)]
+        cand = np.arange(n)
+        got = oracle.build_list(prefix, cand, D=D, exclude_self=exclude_self)
+        for c in range(n):
+            if c in prefix:
+                assert np.isnan(got[c])
+                continue
+            if t == 0:
+                want = sum(Dl[o][c] for o in range(n) if o != c)
+            else:
+                want = brute.td_of(Dl, prefix + [c]) - brute.td_of(Dl, prefix)
+                if exclude_self:
+                    want += min(Dl[c][m] for m in prefix)
+            assert got[c] == want, (trial, t, c)
+        k = int(rng.integers(1, n + 1))
+        med, _, steps = oracle.build(k, D=D, exclude_self=exclude_self)
+        for s in range(k):
+            v = oracle.build_list(med[:s], cand, D=D, exclude_self=exclude_self)
+            v = np.where(np.isnan(v), np.inf, v)
+            assert int(np.argmin(v)) == med[s] and v[med[s]] == steps[s]
 
 
 def test_pam_from_build_matches_bruteforce():
