@@ -144,11 +144,15 @@ int pamx_workspace_bytes(int64_t n, int32_t k, int32_t dim, int32_t input_kind,
 
 /* Dissimilarity matrix of n points (Sec. 2: PAM consumes a matrix).
  *   X      device, n x dim row-major; PAMX_I32 with PAMX_L1 (exact), or
- *          PAMX_F32 with PAMX_L2 (Euclidean; the Gram term on MFMA).
+ *          PAMX_F32 with PAMX_L2 (Euclidean of the mean-centred points,
+ *          the Gram term on MFMA; pamx_fit computes the same bits).
  *   D      device, n x ld output of the same element type; ld >= n,
- *          a multiple of 4.  Diagonal written as 0, D symmetric bitwise. */
+ *          a multiple of 4.  Diagonal written as 0, D symmetric bitwise.
+ *   ws     device scratch of at least 4*dim bytes for PAMX_F32 (the
+ *          coordinate means; PAMX_ERR_WORKSPACE otherwise); unused, may
+ *          be NULL, for PAMX_I32. */
 int pamx_dist(const void *X, int32_t dtype, int64_t n, int32_t dim, int32_t metric,
-              void *D, int64_t ld, void *stream);
+              void *D, int64_t ld, void *ws, size_t ws_bytes, void *stream);
 
 /* BUILD (Alg. 1): k initial medoids in slot order (the order picked).
  *   D        device dissimilarities (see conventions)

@@ -3,7 +3,7 @@
 //
 //  * k_dist_l1_i32 : exact Manhattan distances of int32 points (VALU).
 //  * k_dist_l2_f32 : Euclidean distances d = sqrt(max(|x|^2 + |y|^2 - 2 x.y, 0))
-//                    with the Gram term x.y on the FP32 matrix cores
+//                    of mean-centred points, the Gram term x.y on the FP32 matrix cores
 //                    (v_mfma_f32_32x32x2_f32), 64 x 64 tiles staged in LDS and
 //                    written back as full 256-byte row segments.
 //  Both write a zero diagonal and are bitwise symmetric.
@@ -48,7 +48,8 @@ hipError_t launch_dist_l1_i32(const int32_t *X, int64_t n, int32_t dim, int32_t 
 // ---------------------------------------------------------------- centring
 // Subtracting the mean does not change Euclidean distances but shrinks |x|^2,
 // which bounds the cancellation error of the Gram form.  The mean of each
-// coordinate is summed in FP64 in a fixed order (deterministic).
+// coordinate is summed in FP64 in a fixed order (deterministic); the distance
+// kernel subtracts it while staging points into LDS.
 __global__ __launch_bounds__(256) void k_center_mean(const float *__restrict__ X, int64_t n,
                                                      int32_t dim, float *__restrict__ mean) {
     __shared__ double red[256];
@@ -64,25 +65,8 @@ __global__ __launch_bounds__(256) void k_center_mean(const float *__restrict__ X
     if (threadIdx.x == 0) mean[j] = (float)(red[0] / (double)n);
 }
 
-__global__ __launch_bounds__(256) void k_center_sub(const float *__restrict__ X, int64_t total,
-                                                    int32_t dim, const float *__restrict__ mean,
-                                                    float *__restrict__ Xc) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t < total) Xc[t] = X[t] - mean[t % dim];
-}
-
 hipError_t launch_mean_f32(const float *X, int64_t n, int32_t dim, float *mean, hipStream_t s) {
     hipLaunchKernelGGL(k_center_mean, dim3(dim), dim3(256), 0, s, X, n, dim, mean);
-    return hipGetLastError();
-}
-
-hipError_t launch_center_f32(const float *X, int64_t n, int32_t dim, float *Xc, hipStream_t s) {
-    // the mean is parked right after the centred copy (the workspace reserves it)
-    float *mean = Xc + n * dim;
-    hipLaunchKernelGGL(k_center_mean, dim3(dim), dim3(256), 0, s, X, n, dim, mean);
-    const int64_t total = n * dim;
-    hipLaunchKernelGGL(k_center_sub, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, X,
-                       total, dim, (const float *)mean, Xc);
     return hipGetLastError();
 }
 
@@ -97,7 +81,8 @@ constexpr int kLdsK = kKC + 1; // padded row stride of the staged points
 // v_mfma_f32_32x32x2_f32 operand layout (wave64): lane l supplies A[l%32][l/32]
 // and B[l/32][l%32]; accumulator element v of lane l is C[8*(v/4) + 4*(l/32) +
 // v%4][l%32].
-__global__ __launch_bounds__(256) void k_dist_l2_f32(const float *__restrict__ X, int64_t n,
+__global__ __launch_bounds__(256) void k_dist_l2_f32(const float *__restrict__ X,
+                                                     const float *__restrict__ mean, int64_t n,
                                                      int32_t dim, float *__restrict__ D,
                                                      int64_t ld) {
     __shared__ float xa[kT * kLdsK];
@@ -124,8 +109,9 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32(const float *__restrict__ X
             const int r = e / kKC, kk = e % kKC;
             float va = 0.0f, vb = 0.0f;
             if (kk < kc) {
-                if (r0 + r < n) va = X[(r0 + r) * dim + k0 + kk];
-                if (c0 + r < n) vb = X[(c0 + r) * dim + k0 + kk];
+                const float mu = mean[k0 + kk];
+                if (r0 + r < n) va = X[(r0 + r) * dim + k0 + kk] - mu;
+                if (c0 + r < n) vb = X[(c0 + r) * dim + k0 + kk] - mu;
             }
             xa[r * kLdsK + kk] = va;
             xb[r * kLdsK + kk] = vb;
@@ -177,9 +163,10 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32(const float *__restrict__ X
 }
 
 hipError_t launch_dist_l2_f32(const float *X, int64_t n, int32_t dim, float *D, int64_t ld,
-                              hipStream_t s) {
+                              float *mean, hipStream_t s) {
+    hipLaunchKernelGGL(k_center_mean, dim3(dim), dim3(256), 0, s, X, n, dim, mean);
     dim3 grid((unsigned)((n + kT - 1) / kT), (unsigned)((n + kT - 1) / kT));
-    hipLaunchKernelGGL(k_dist_l2_f32, grid, dim3(256), 0, s, X, n, dim, D, ld);
+    hipLaunchKernelGGL(k_dist_l2_f32, grid, dim3(256), 0, s, X, (const float *)mean, n, dim, D, ld);
     return hipGetLastError();
 }
 

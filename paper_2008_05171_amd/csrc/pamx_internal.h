@@ -155,7 +155,7 @@ struct Layout {
     size_t asz;          // accumulator size (8)
     // offsets
     size_t D;            // stored matrix (pamx_fit with points), or SIZE_MAX
-    size_t Xc;           // centred copy of points (L2 fit), or SIZE_MAX
+    size_t mean;         // coordinate means of the points (L2 fit), or SIZE_MAX
     size_t near, sec, dn, ds, is_med;
     size_t srow, sdn, sds;
     size_t blkcnt, blkbase, seg_off, segc;
@@ -176,9 +176,10 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
 // launchers (one per kernel family); each returns hipSuccess or an error.
 hipError_t launch_dist_l1_i32(const int32_t *X, int64_t n, int32_t dim, int32_t *D, int64_t ld,
                               hipStream_t s);
-hipError_t launch_center_f32(const float *X, int64_t n, int32_t dim, float *Xc, hipStream_t s);
+// mean[dim] (device scratch) receives the coordinate means; the distances are
+// those of the centred points
 hipError_t launch_dist_l2_f32(const float *X, int64_t n, int32_t dim, float *D, int64_t ld,
-                              hipStream_t s);
+                              float *mean, hipStream_t s);
 
 // Workspace layout of the mixed-precision (BF16 Gram, FP32 sums, FP64
 // re-score) form for points.

@@ -84,7 +84,7 @@ def load(path: str = LIB_PATH):
     lib.pamx_default_options.argtypes = [opt_p]
     lib.pamx_default_options.restype = None
     lib.pamx_workspace_bytes.argtypes = [i64, i32, i32, i32, i32, opt_p, ctypes.POINTER(sz)]
-    lib.pamx_dist.argtypes = [P, i32, i64, i32, i32, P, i64, P]
+    lib.pamx_dist.argtypes = [P, i32, i64, i32, i32, P, i64, P, sz, P]
     lib.pamx_build.argtypes = [P, i32, i64, i64, i32, opt_p, P, dbl_p, P, sz, P]
     lib.pamx_swap.argtypes = [P, i32, i64, i64, i32, opt_p, P, P, dbl_p, st_p, P, sz, P]
     lib.pamx_fit.argtypes = [P, i32, i32, i64, i32, i32, i32, opt_p, P, P, dbl_p, st_p, P, sz, P]
@@ -140,11 +140,15 @@ def pamx_workspace_bytes(n, k, dim, input_kind, dtype, opt=None) -> int:
     return int(out.value)
 
 
-def pamx_dist(X, metric, D, ld=None, stream=None):
+def pamx_dist(X, metric, D, ws=None, ld=None, stream=None):
+    """ws: device scratch of >= 4*dim bytes for float32 points (allocated here if None)."""
+    import torch
     n, dim = X.shape
     ld = D.stride(0) if ld is None else ld
+    if ws is None:
+        ws = torch.empty(max(4 * dim, 256), dtype=torch.uint8, device=X.device)
     return _check(load().pamx_dist(_ptr(X), _dtype_code(X), n, dim, int(metric), _ptr(D), int(ld),
-                                   _stream(stream)))
+                                   _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def pamx_build(D, k, medoids, ws, opt=None, n=None, ld=None, stream=None):

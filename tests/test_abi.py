@@ -102,14 +102,18 @@ def test_host_argument_errors_before_device_work(lib):
 
 def test_points_metric_rules(lib):
     fake = ctypes.c_void_p(0x100000)
-    rc = lib.pamx_dist(fake, abi.PAMX_I32, 10, 2, abi.PAMX_L2, fake, 12, None)
+    rc = lib.pamx_dist(fake, abi.PAMX_I32, 10, 2, abi.PAMX_L2, fake, 12, None, 0, None)
     assert rc == abi.PAMX_ERR_UNSUPPORTED
-    rc = lib.pamx_dist(fake, abi.PAMX_F32, 10, 2, abi.PAMX_L1, fake, 12, None)
+    rc = lib.pamx_dist(fake, abi.PAMX_F32, 10, 2, abi.PAMX_L1, fake, 12, fake, 256, None)
     assert rc == abi.PAMX_ERR_UNSUPPORTED
-    rc = lib.pamx_dist(fake, abi.PAMX_F32, 10, 2, abi.PAMX_L2, fake, 10, None)
+    rc = lib.pamx_dist(fake, abi.PAMX_F32, 10, 2, abi.PAMX_L2, fake, 10, fake, 256, None)
     assert rc == abi.PAMX_ERR_ARG          # ld not a multiple of 4
-    rc = lib.pamx_dist(fake, abi.PAMX_F32, 10, 0, abi.PAMX_L2, fake, 12, None)
+    rc = lib.pamx_dist(fake, abi.PAMX_F32, 10, 0, abi.PAMX_L2, fake, 12, fake, 256, None)
     assert rc == abi.PAMX_ERR_ARG
+    rc = lib.pamx_dist(fake, abi.PAMX_F32, 10, 8, abi.PAMX_L2, fake, 12, fake, 31, None)
+    assert rc == abi.PAMX_ERR_WORKSPACE    # the 8 coordinate means need 32 bytes
+    rc = lib.pamx_dist(fake, abi.PAMX_F32, 10, 8, abi.PAMX_L2, fake, 12, None, 0, None)
+    assert rc == abi.PAMX_ERR_WORKSPACE
 
 
 def test_no_oracle_in_product_path():
