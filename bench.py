@@ -41,19 +41,60 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "swap_pass_gmm16_traffic.json")
+# the SWAP pass kernel, its launch shape (chunking) and the shared header
+KERNEL_SOURCES = ("swap.hip", "pamx_api.hip", "pamx_internal.h")
+
+
+def kernel_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2008_05171_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_from_profiles(n, k):
     """HBM bytes per SWAP pass from committed rocprofv3 counter runs, or None
-    when the kernel source changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "swap_pass_gmm16_traffic.json")
-    if not os.path.exists(path):
+    when the kernel sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_JSON):
         return None
-    rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_2008_05171_amd", "csrc", "swap.hip"), "rb").read()
-    if rec.get("src_sha256") != hashlib.sha256(src).hexdigest():
-        return None
-    if rec.get("n") != n or rec.get("k") != k:
+    rec = json.load(open(TRAFFIC_JSON))
+    if rec.get("src_sha256") != kernel_sha256() or rec.get("n") != n or rec.get("k") != k:
         return None
     return float(rec["bytes_per_launch"])
+
+
+def write_traffic(fetch_csv, write_csv, probe_mib):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
+    dispatch) of `bench.py --copy-probe-mib M` into the traffic record read by
+    traffic_from_profiles.  Each counter is scaled by what it reads for the
+    probe's plain copy of M MiB (M MiB read, M MiB written).  SWAP passes
+    enqueued after convergence, which return at once, are left out."""
+    import csv
+    import re
+
+    def per_kernel(path):
+        out = {}
+        for r in csv.DictReader(open(path)):
+            name = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "").strip()
+            out.setdefault(name, []).append(float(r["Counter_Value"]))
+        return out
+
+    f, w = per_kernel(fetch_csv), per_kernel(write_csv)
+    fetch_scale = probe_mib * 1024.0 / max(f["__amd_rocclr_copyBuffer"])
+    write_scale = probe_mib * 1024.0 / max(w["__amd_rocclr_copyBuffer"])
+    key = "pamx::k_swap_pass<float, 4, false>"
+    pairs = [(a, b) for a, b in zip(f[key], w[key]) if a > 1024.0]
+    fetch_kib = sum(a for a, _ in pairs) / len(pairs)
+    write_kib = sum(b for _, b in pairs) / len(pairs)
+    rec = {"kernel": key, "n": N, "k": K, "src_sha256": kernel_sha256(),
+           "launches": len(pairs), "fetch_kib": fetch_kib, "write_kib": write_kib,
+           "fetch_scale": fetch_scale, "write_scale": write_scale,
+           "bytes_per_launch": (fetch_kib * fetch_scale + write_kib * write_scale) * 1024.0,
+           "algorithmic_bytes_per_launch": 4.0 * N * (N - K)}
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
 
 
 def cpu_baseline(X, k, target_s):
@@ -90,7 +131,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fastpam2", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy a device buffer of this many MiB three times (a plain copy "
+                         "kernel of known size that calibrates HBM byte counters)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the SWAP pass traffic record from two rocprofv3 --pmc runs of "
+                         "this script with --copy-probe-mib (no GPU work)")
     args = ap.parse_args()
+    if args.write_traffic:
+        if args.copy_probe_mib <= 0:
+            sys.exit("--write-traffic needs the --copy-probe-mib size of the profiled runs")
+        print(json.dumps(write_traffic(*args.write_traffic, args.copy_probe_mib)))
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported "
               "(the multi-GPU design is described in DESIGN.md)" % args.gpus, file=sys.stderr)
@@ -102,6 +154,15 @@ def main():
     from paper_2008_05171_amd import pamx as abi
 
     dev = torch.device("cuda:0")
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 3 copies of %d MiB (read %d + write %d bytes each)" % (
+            args.copy_probe_mib, src.numel() * 4, src.numel() * 4))
+        del src, dst
     X_np = datagen.gaussian_mixture(N, DIM, COMPONENTS, seed=SEED, sigma=1.0)
     X = torch.from_numpy(X_np).to(dev)
 
