@@ -259,7 +259,12 @@ def main():
         "iterations": last["iterations"], "swaps": last["swaps"], "td": stats[-1][1],
         "td_build": last["td_build"],
         "build_pass": {"avg_launch_ms": avg_bpass_ms, "achieved_gbs": build_gbs,
-                       "bytes_per_launch": 4.0 * N * N},
+                       "bytes_per_launch": 4.0 * N * N, "launches_per_fit": last["n_build_pass"]},
+        "build_incremental": {"launches_per_fit": last["n_build_delta"],
+                              "rows_read_per_fit": last["build_rows"],
+                              "ms_per_fit": round(last["ms_build_delta"], 3),
+                              "achieved_gbs": (4.0 * N * last["build_rows"] /
+                                               max(last["ms_build_delta"], 1e-9) / 1e6)},
         "swap_pass_pairs_per_s": N * (N - K) / (avg_pass_ms / 1e3),
     }
     out.update(extra)

@@ -128,9 +128,16 @@ typedef struct pamx_stats {
     int64_t pass_pairs; /* candidate-object pairs read by SWAP passes */
     int64_t build_pairs;/* candidate-object pairs read by BUILD passes */
     double ms_swap_pass;   /* profile=1: summed duration of the SWAP pass kernels */
-    double ms_build_pass;  /* profile=1: summed duration of the BUILD pass kernels */
+    double ms_build_pass;  /* profile=1: summed duration of the full BUILD passes
+                              (every step of the BUILD-from-scratch form; the
+                              first two steps of the stored-matrix form) */
     int32_t n_swap_pass;   /* profile=1: SWAP pass launches that did work */
-    int32_t n_build_pass;  /* profile=1: BUILD pass launches */
+    int32_t n_build_pass;  /* profile=1: full BUILD pass launches */
+    double ms_build_delta; /* profile=1: summed duration of the incremental BUILD
+                              passes (stored matrix, steps 3..k) */
+    int64_t build_rows;    /* matrix rows read by the incremental BUILD passes */
+    int32_t n_build_delta; /* profile=1: incremental BUILD pass launches */
+    int32_t reserved;
 } pamx_stats;
 
 /* Fills `opt` with the defaults listed above. */

@@ -363,9 +363,11 @@ struct EventPool {
         return true;
     }
     // summed duration of the first `pairs` (begin, end) pairs
-    double sum(int pairs) const {
+    double sum(int pairs) const { return sum(0, pairs); }
+    // summed duration of (begin, end) pairs j0 .. j1-1
+    double sum(int j0, int j1) const {
         double t = 0.0;
-        for (int j = 0; j < pairs; ++j) {
+        for (int j = j0; j < j1; ++j) {
             float v = 0.f;
             if (hipEventElapsedTime(&v, ev[2 * j], ev[2 * j + 1]) == hipSuccess) t += v;
         }
@@ -395,9 +397,16 @@ int build_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const pamx_op
     if (rc) return rc;
     if (st.bad_medoids) return fail(PAMX_ERR_HIP, "BUILD found no candidate");
     if (td) *td = st.td;
-    if (stats && pool) {
-        stats->ms_build_pass = pool->sum(k);
-        stats->n_build_pass = k;
+    if (stats) {
+        const int full = k < 2 ? k : 2;
+        stats->build_rows = st.build_rows;
+        stats->build_pairs = (int64_t)full * L.n * L.n + st.build_rows * L.n;
+        if (pool) {
+            stats->ms_build_pass = pool->sum(0, full);
+            stats->n_build_pass = full;
+            stats->ms_build_delta = pool->sum(full, k);
+            stats->n_build_delta = k - full;
+        }
     }
     return PAMX_OK;
 }
@@ -695,9 +704,12 @@ extern "C" int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int
         stats->ms_build = tm.ms(1, 2);
         stats->ms_swap = tm.ms(2, 3);
         stats->ms_total = tm.ms(0, 4);
-        stats->build_pairs = (int64_t)k * n * n;
+        stats->build_pairs = bst.build_pairs;
+        stats->build_rows = bst.build_rows;
         stats->ms_build_pass = bst.ms_build_pass;
         stats->n_build_pass = bst.n_build_pass;
+        stats->ms_build_delta = bst.ms_build_delta;
+        stats->n_build_delta = bst.n_build_delta;
     }
     return rc;
 }

@@ -59,6 +59,8 @@ struct alignas(64) DevState {
     long long td_i;      // running TD (int path)
     double margin;       // FP32 error bound used for re-scoring
     double f32_best;     // FP32 best change before re-scoring
+    long long n_chg;     // BUILD: objects whose nearest distance dropped this step
+    long long build_rows;// BUILD: rows read by the incremental passes
 };
 
 // Lexicographic "a is better than b" on (value, slot, candidate).

@@ -60,6 +60,13 @@ static void fill(X *p, int64_t cnt, X v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill<X>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, p, cnt, v);
 }
 
+template <typename X>
+__global__ __launch_bounds__(256) void k_copy(const X *__restrict__ src, X *__restrict__ dst,
+                                              int64_t cnt) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < cnt) dst[t] = src[t];
+}
+
 __global__ void k_state_init(DevState *st, int32_t max_iter, int32_t trace_cap) {
     if (threadIdx.x == 0) {
         DevState z{};
@@ -116,43 +123,6 @@ __global__ __launch_bounds__(kWG) void k_build_pass(const T *__restrict__ D, int
     for (int e = 0; e < VEC; ++e) dst[e] = acc[e];
 }
 
-// Sum the chunk partials of each candidate (chunk order) and reduce the
-// work-group's best (value, candidate) among non-medoids.
-template <typename T>
-__global__ __launch_bounds__(kWG) void k_build_merge(const AccT<T> *__restrict__ part, int32_t Q,
-                                                     int64_t ncp, int64_t n,
-                                                     const T *__restrict__ dn,
-                                                     const uint8_t *__restrict__ is_med,
-                                                     int32_t add_self, AccT<T> *__restrict__ wg_v,
-                                                     int32_t *__restrict__ wg_c) {
-    using A = AccT<T>;
-    const int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    A v = VT<T>::acc_inf();
-    int ci = INT_MAX;
-    if (c < n && !is_med[c]) {
-        A s = 0;
-        const A *pc = part + c;
-        int q = 0;
-        for (; q + 8 <= Q; q += 8) {           // loads first, then the adds in chunk order
-            A x[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = pc[(int64_t)(q + u) * ncp];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) s += x[u];
-        }
-        for (; q < Q; ++q) s += pc[(int64_t)q * ncp];
-        if (add_self) s += (A)dn[c];   // literal Alg. 1: x_c's own gain not counted
-        v = s;
-        ci = (int)c;
-    }
-    int dummy = 0;
-    block_argmin3<A, kWG>(v, dummy, ci);
-    if (threadIdx.x == 0) {
-        wg_v[blockIdx.x] = v;
-        wg_c[blockIdx.x] = ci;
-    }
-}
-
 // Pick the step's medoid: the smallest change, smallest index on ties.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_build_select(const AccT<T> *__restrict__ wg_v,
@@ -190,6 +160,167 @@ __global__ __launch_bounds__(256) void k_build_update(const T *__restrict__ D, i
     dn[o] = first ? d : vmin(dn[o], d);
 }
 
+// ---- incremental BUILD.  Adding m_t lowers dn only for the objects closer
+// to m_t than to every earlier medoid, and
+//   A_t(c) - A_{t-1}(c) = sum over those objects of min(d, dn_new) - min(d, dn_old),
+// so after the first two steps each step reads only the rows of the objects
+// whose dn dropped (about n / t of them) instead of the whole matrix.  The
+// sums are exact for int32 matrices; for FP32 the per-object differences are
+// exact in FP64 and only their sum rounds.
+
+// dn2 = min(dn, row m_t) and, per block of kObjBlk objects, how many dropped.
+template <typename T>
+__global__ __launch_bounds__(kObjBlk) void k_build_update2(const T *__restrict__ D, int64_t ld,
+                                                           int64_t n, const T *__restrict__ dn,
+                                                           T *__restrict__ dn2,
+                                                           const DevState *__restrict__ st,
+                                                           int32_t *__restrict__ blkcnt) {
+    const int64_t o = (int64_t)blockIdx.x * kObjBlk + threadIdx.x;
+    const int c = st->best_c;
+    int chg = 0;
+    if (o < n) {
+        const T old = dn[o];
+        T nw = old;
+        if (c != INT_MAX) nw = vmin(old, D[(int64_t)c * ld + o]);
+        dn2[o] = nw;
+        chg = nw < old;
+    }
+    const int cnt = __syncthreads_count(chg);
+    if (threadIdx.x == 0) blkcnt[blockIdx.x] = cnt;
+}
+
+// Stable list of the objects whose dn dropped (ascending object order), with
+// their old and new dn; the total goes to the device state.
+template <typename T>
+__global__ __launch_bounds__(kObjBlk) void k_build_compact(const T *__restrict__ dn,
+                                                           const T *__restrict__ dn2, int64_t n,
+                                                           const int32_t *__restrict__ blkcnt,
+                                                           int32_t nblk, int32_t *__restrict__ chg_o,
+                                                           T *__restrict__ chg_old,
+                                                           T *__restrict__ chg_new,
+                                                           DevState *__restrict__ st) {
+    __shared__ int wcnt[kObjBlk / 64];
+    int pre = 0, tot = 0;
+    for (int b = threadIdx.x; b < nblk; b += kObjBlk) {
+        const int v = blkcnt[b];
+        tot += v;
+        if (b < (int)blockIdx.x) pre += v;
+    }
+    pre = block_sum<int, kObjBlk>(pre);
+    tot = block_sum<int, kObjBlk>(tot);
+    const int64_t o = (int64_t)blockIdx.x * kObjBlk + threadIdx.x;
+    T old = 0, nw = 0;
+    bool chg = false;
+    if (o < n) {
+        old = dn[o];
+        nw = dn2[o];
+        chg = nw < old;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long m = __ballot(chg);
+    if (lane == 0) wcnt[wv] = __popcll(m);
+    __syncthreads();
+    int rank = __popcll(m & ((1ull << lane) - 1ull));
+    for (int w = 0; w < wv; ++w) rank += wcnt[w];
+    if (chg) {
+        const int pos = pre + rank;
+        chg_o[pos] = (int32_t)o;
+        chg_old[pos] = old;
+        chg_new[pos] = nw;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->n_chg = tot;
+        st->build_rows += tot;
+    }
+}
+
+// Per candidate and chunk of the list: sum of min(d, new) - min(d, old).
+template <typename T, int VEC>
+__global__ __launch_bounds__(kWG) void k_build_delta(const T *__restrict__ D, int64_t ld, int64_t n,
+                                                     const int32_t *__restrict__ chg_o,
+                                                     const T *__restrict__ chg_old,
+                                                     const T *__restrict__ chg_new,
+                                                     const DevState *__restrict__ st, int64_t ncp,
+                                                     AccT<T> *__restrict__ part) {
+    using A = AccT<T>;
+    constexpr int U = 4;
+    const int64_t m = st->n_chg;
+    const int Qd = gridDim.y, q = blockIdx.y;
+    const int64_t Ld = (m + Qd - 1) / Qd;
+    const int64_t a = min((int64_t)q * Ld, m), b = min(a + Ld, m);
+    const int64_t c0 = ((int64_t)blockIdx.x * kWG + threadIdx.x) * VEC;
+    A acc[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[e] = 0;
+    if (c0 < n) {
+        int64_t j = a;
+        for (; j + U <= b; j += U) {
+            T v[U][VEC];
+            T lo[U], hi[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                load_vec<T, VEC>(D + (int64_t)chg_o[j + u] * ld + c0, v[u]);
+                lo[u] = chg_old[j + u];
+                hi[u] = chg_new[j + u];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    acc[e] += (A)vmin(v[u][e], hi[u]) - (A)vmin(v[u][e], lo[u]);
+        }
+        for (; j < b; ++j) {
+            T v[VEC];
+            load_vec<T, VEC>(D + (int64_t)chg_o[j] * ld + c0, v);
+            const T lo = chg_old[j], hi = chg_new[j];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[e] += (A)vmin(v[e], hi) - (A)vmin(v[e], lo);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) part[(int64_t)q * ncp + c0 + e] = acc[e];
+}
+
+// A(c) <- A(c) + sum of the chunk deltas (chunk order), then the work-group's
+// best (value, candidate) among non-medoids, as k_build_merge.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_build_dmerge(const AccT<T> *__restrict__ part, int32_t Q,
+                                                      int64_t ncp, int64_t n, AccT<T> *__restrict__ acur,
+                                                      const T *__restrict__ dn,
+                                                      const uint8_t *__restrict__ is_med,
+                                                      int32_t add_self, AccT<T> *__restrict__ wg_v,
+                                                      int32_t *__restrict__ wg_c) {
+    using A = AccT<T>;
+    const int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    A v = VT<T>::acc_inf();
+    int ci = INT_MAX;
+    if (c < n) {
+        A s = 0;
+        const A *pc = part + c;
+        int q = 0;
+        for (; q + 8 <= Q; q += 8) {
+            A x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = pc[(int64_t)(q + u) * ncp];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += x[u];
+        }
+        for (; q < Q; ++q) s += pc[(int64_t)q * ncp];
+        const A a = acur[c] + s;
+        acur[c] = a;
+        if (!is_med[c]) {
+            v = add_self ? a + (A)dn[c] : a;
+            ci = (int)c;
+        }
+    }
+    int dummy = 0;
+    block_argmin3<A, kWG>(v, dummy, ci);
+    if (threadIdx.x == 0) {
+        wg_v[blockIdx.x] = v;
+        wg_c[blockIdx.x] = ci;
+    }
+}
+
 // TD = sum_o dn(o) in a fixed order (single work-group).
 template <typename T>
 __global__ __launch_bounds__(1024) void k_td_sum(const T *__restrict__ dn, int64_t n,
@@ -204,41 +335,80 @@ __global__ __launch_bounds__(1024) void k_td_sum(const T *__restrict__ dn, int64
     }
 }
 
+// BUILD: the first two steps read the whole matrix (column sums, then A for
+// the first medoid's dn); every later step is incremental.  The SWAP-only
+// buffers of the workspace serve as scratch: ds is the second dn buffer,
+// srow/sdn/sds the list of changed objects, cand_a the running A(c).
 template <typename T>
 hipError_t run_build(const T *D, int64_t ld, const Layout &L, int32_t k, int32_t exclude_self,
                      int32_t *medoids, void *ws, hipStream_t s, hipEvent_t *ev) {
     using A = AccT<T>;
     char *w = static_cast<char *>(ws);
     const int64_t n = L.n;
-    T *dn = reinterpret_cast<T *>(w + L.dn);
+    T *dnb[2] = {reinterpret_cast<T *>(w + L.dn), reinterpret_cast<T *>(w + L.ds)};
     uint8_t *is_med = reinterpret_cast<uint8_t *>(w + L.is_med);
     A *part = reinterpret_cast<A *>(w + L.part);
+    A *acur = reinterpret_cast<A *>(w + L.cand_a);
     A *wg_v = reinterpret_cast<A *>(w + L.wg_v);
     int32_t *wg_c = reinterpret_cast<int32_t *>(w + L.wg_c);
+    int32_t *blkcnt = reinterpret_cast<int32_t *>(w + L.blkcnt);
+    int32_t *chg_o = reinterpret_cast<int32_t *>(w + L.srow);
+    T *chg_old = reinterpret_cast<T *>(w + L.sdn);
+    T *chg_new = reinterpret_cast<T *>(w + L.sds);
     DevState *st = reinterpret_cast<DevState *>(w + L.state);
+    const unsigned nblk = (unsigned)L.n_oblk;
 
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, 0, 0);
     fill<uint8_t>(is_med, n, 0, s);
-    fill<T>(dn, n, VT<T>::inf(), s);
+    fill<T>(dnb[0], n, VT<T>::inf(), s);
     const dim3 pgrid(L.n_ctiles, L.Q);
+    int cur = 0;   // dnb[cur] holds dn for the medoids chosen so far
     for (int32_t t = 0; t < k; ++t) {
-        if (ev) (void)hipEventRecord(ev[2 * t], s);
-        if (L.vec == 4)
-            hipLaunchKernelGGL((k_build_pass<T, 4>), pgrid, dim3(kWG), 0, s, D, ld, n,
-                               (const T *)dn, L.L, L.ncp, part);
-        else
-            hipLaunchKernelGGL((k_build_pass<T, 1>), pgrid, dim3(kWG), 0, s, D, ld, n,
-                               (const T *)dn, L.L, L.ncp, part);
-        if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
-        hipLaunchKernelGGL(k_build_merge<T>, dim3(L.n_mwg), dim3(kWG), 0, s, (const A *)part, L.Q,
-                           L.ncp, n, (const T *)dn, (const uint8_t *)is_med,
+        const T *dn = dnb[cur];
+        if (t < 2) {
+            if (ev) (void)hipEventRecord(ev[2 * t], s);
+            if (L.vec == 4)
+                hipLaunchKernelGGL((k_build_pass<T, 4>), pgrid, dim3(kWG), 0, s, D, ld, n, dn, L.L,
+                                   L.ncp, part);
+            else
+                hipLaunchKernelGGL((k_build_pass<T, 1>), pgrid, dim3(kWG), 0, s, D, ld, n, dn, L.L,
+                                   L.ncp, part);
+            if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
+            // a zeroed running sum turns the delta merge into a plain merge
+            fill<A>(acur, n, (A)0, s);
+        } else {
+            hipLaunchKernelGGL(k_build_compact<T>, dim3(nblk), dim3(kObjBlk), 0, s,
+                               (const T *)dnb[cur ^ 1], dn, n, (const int32_t *)blkcnt,
+                               (int32_t)nblk, chg_o, chg_old, chg_new, st);
+            if (ev) (void)hipEventRecord(ev[2 * t], s);
+            if (L.vec == 4)
+                hipLaunchKernelGGL((k_build_delta<T, 4>), pgrid, dim3(kWG), 0, s, D, ld, n,
+                                   (const int32_t *)chg_o, (const T *)chg_old, (const T *)chg_new,
+                                   (const DevState *)st, L.ncp, part);
+            else
+                hipLaunchKernelGGL((k_build_delta<T, 1>), pgrid, dim3(kWG), 0, s, D, ld, n,
+                                   (const int32_t *)chg_o, (const T *)chg_old, (const T *)chg_new,
+                                   (const DevState *)st, L.ncp, part);
+            if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
+        }
+        hipLaunchKernelGGL(k_build_dmerge<T>, dim3(L.n_mwg), dim3(kWG), 0, s, (const A *)part,
+                           L.Q, L.ncp, n, acur, dn, (const uint8_t *)is_med,
                            (int32_t)(exclude_self && t > 0), wg_v, wg_c);
         hipLaunchKernelGGL(k_build_select<T>, dim3(1), dim3(1024), 0, s, (const A *)wg_v,
                            (const int32_t *)wg_c, L.n_mwg, t, medoids, is_med, st);
-        hipLaunchKernelGGL(k_build_update<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                           D, ld, n, dn, (const DevState *)st, (int32_t)(t == 0));
+        if (t == 0) {
+            hipLaunchKernelGGL(k_build_update<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                               D, ld, n, dnb[cur], (const DevState *)st, (int32_t)1);
+        } else {
+            hipLaunchKernelGGL(k_build_update2<T>, dim3(nblk), dim3(kObjBlk), 0, s, D, ld, n, dn,
+                               dnb[cur ^ 1], (const DevState *)st, blkcnt);
+            cur ^= 1;
+        }
     }
-    hipLaunchKernelGGL(k_td_sum<T>, dim3(1), dim3(1024), 0, s, (const T *)dn, n, st);
+    if (cur == 1)   // leave the final dn where the caches expect it
+        hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           (const T *)dnb[1], dnb[0], n);
+    hipLaunchKernelGGL(k_td_sum<T>, dim3(1), dim3(1024), 0, s, (const T *)dnb[0], n, st);
     return hipGetLastError();
 }
 

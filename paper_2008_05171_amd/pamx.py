@@ -44,7 +44,9 @@ class pamx_stats(ctypes.Structure):
                 ("ms_swap", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("pass_pairs", ctypes.c_int64), ("build_pairs", ctypes.c_int64),
                 ("ms_swap_pass", ctypes.c_double), ("ms_build_pass", ctypes.c_double),
-                ("n_swap_pass", ctypes.c_int32), ("n_build_pass", ctypes.c_int32)]
+                ("n_swap_pass", ctypes.c_int32), ("n_build_pass", ctypes.c_int32),
+                ("ms_build_delta", ctypes.c_double), ("build_rows", ctypes.c_int64),
+                ("n_build_delta", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class pamx_batch_stats(ctypes.Structure):
