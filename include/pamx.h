@@ -197,7 +197,9 @@ typedef struct pamx_batch_stats {
     double ms_pam;        /* device time of the batched BUILD + SWAP launch */
     double ms_assign;     /* device time of the full-data TD kernels */
     double ms_total;
-    int64_t pairs;        /* candidate-object pairs evaluated (BUILD + SWAP passes) */
+    int64_t pairs;        /* candidate-object pairs evaluated: two full BUILD steps, the
+                             rows of changed objects in later BUILD steps, and every
+                             non-medoid candidate against every object per SWAP search */
 } pamx_batch_stats;
 
 /* Workspace bytes of pamx_fit_batched for n_inst instances. */

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
     const int64_t *__restrict__ moff, const int32_t *__restrict__ order, int32_t n_inst,
     int32_t max_iter, int32_t excl, int32_t n_max, int32_t k_max, int32_t *__restrict__ med_out,
     double *__restrict__ td_out, double *__restrict__ tdb_out, int32_t *__restrict__ it_out,
-    int32_t *__restrict__ sw_out, int32_t *__restrict__ queue) {
+    int32_t *__restrict__ sw_out, int32_t *__restrict__ rows_out, int32_t *__restrict__ queue) {
     using A = AccT<T>;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ A rv[kBW];
@@ -177,7 +177,14 @@ __global__ __launch_bounds__(kBT) void k_clara(
         for (int o = tid; o < n; o += kBT) { L.dn[o] = VT<T>::inf(); L.is_med[o] = 0; }
         __syncthreads();
 
-        // ---- BUILD (Alg. 1): A(c) = sum_o min(d(o,c), dn(o)); step 0 has dn = inf
+        // ---- BUILD (Alg. 1): A(c) = sum_o min(d(o,c), dn(o)); step 0 has dn = inf.
+        // Each lane keeps A of its candidates across steps.  After the first two
+        // steps only objects whose dn dropped change A:
+        //   A(c) += sum over them of min(d, dn_new) - min(d, dn_old),
+        // taken from a stable list (ascending object) of those objects in LDS
+        // (srow: object, sdn: old dn, sds: new dn; free until SWAP).
+        A acand[kBR];
+        int nchg = 0, rows = 0;
         for (int step = 0; step < k; ++step) {
             A bv = VT<T>::acc_inf();
             int bc = INT_MAX, zero = 0;
@@ -186,9 +193,19 @@ __global__ __launch_bounds__(kBT) void k_clara(
                 if (c >= n || L.is_med[c]) continue;
                 T b[MD];
                 load_pt<T, MD>(L.P + (size_t)c * dim, dim, b);
-                A acc = 0;
-                for (int o = 0; o < n; ++o)
-                    acc += (A)vmin(pdist<MD>(L.P + (size_t)o * dim, b, dim), L.dn[o]);
+                A acc;
+                if (step < 2) {
+                    acc = 0;
+                    for (int o = 0; o < n; ++o)
+                        acc += (A)vmin(pdist<MD>(L.P + (size_t)o * dim, b, dim), L.dn[o]);
+                } else {
+                    acc = acand[r];
+                    for (int q = 0; q < nchg; ++q) {
+                        const T d = pdist<MD>(L.P + (size_t)L.srow[q] * dim, b, dim);
+                        acc += (A)vmin(d, L.sds[q]) - (A)vmin(d, L.sdn[q]);
+                    }
+                }
+                acand[r] = acc;
                 if (excl && step > 0) acc += (A)L.dn[c];
                 if (acc < bv) { bv = acc; bc = c; }
             }
@@ -197,11 +214,37 @@ __global__ __launch_bounds__(kBT) void k_clara(
             if (tid == 0) { L.med[step] = m; L.is_med[m] = 1; }
             T b[MD];
             load_pt<T, MD>(L.P + (size_t)m * dim, dim, b);
-            for (int o = tid; o < n; o += kBT) {
-                const T d = pdist<MD>(L.P + (size_t)o * dim, b, dim);
-                L.dn[o] = (step == 0) ? d : vmin(L.dn[o], d);
+            // dn update and the list of objects whose dn dropped
+            int base = 0;
+            for (int b0 = 0; b0 < n; b0 += kBT) {
+                const int o = b0 + tid;
+                bool chg = false;
+                T old = 0, nw = 0;
+                if (o < n) {
+                    const T d = pdist<MD>(L.P + (size_t)o * dim, b, dim);
+                    old = L.dn[o];
+                    nw = (step == 0) ? d : vmin(old, d);
+                    chg = nw < old;
+                    L.dn[o] = nw;
+                }
+                const unsigned long long msk = __ballot(chg);
+                if (lane == 0) L.wcnt[wv] = __popcll(msk);
+                __syncthreads();
+                int pre = 0, tot = 0;
+                for (int u = 0; u < kBW; ++u) {
+                    const int c = L.wcnt[u];
+                    if (u < wv) pre += c;
+                    tot += c;
+                }
+                if (chg) {
+                    const int p = base + pre + __popcll(msk & ((1ull << lane) - 1ull));
+                    L.srow[p] = o; L.sdn[p] = old; L.sds[p] = nw;
+                }
+                base += tot;
+                __syncthreads();
             }
-            __syncthreads();
+            nchg = base;
+            if (step >= 1 && step + 1 < k) rows += nchg;   // read by the next step
         }
         A tdb = 0;
         for (int o = tid; o < n; o += kBT) tdb += (A)L.dn[o];
@@ -325,6 +368,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
             td_out[j] = (double)td;
             tdb_out[j] = (double)tdb;
             it_out[j] = iters;
+            rows_out[j] = rows;
             sw_out[j] = swaps;
         }
         __syncthreads();
@@ -411,7 +455,7 @@ static hipError_t launch_clara_md(const T *X, int64_t N, int32_t dim, const Batc
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_clara<T, MD>), dim3(a.grid), dim3(kBT), lds, s, X, N, dim, a.soff, a.sidx,
                        a.kin, a.moff, a.order, a.n_inst, a.max_iter, a.excl, a.n_max, a.k_max,
-                       a.med_out, a.td_out, a.tdb_out, a.it_out, a.sw_out, a.queue);
+                       a.med_out, a.td_out, a.tdb_out, a.it_out, a.sw_out, a.rows_out, a.queue);
     return hipGetLastError();
 }
 

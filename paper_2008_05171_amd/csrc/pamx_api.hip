@@ -189,6 +189,15 @@ int make_rc_layout(int64_t n, int32_t k, int32_t dim, const pamx_options *opt, R
     R->bnd = take(4 * 8);
     R->mean = take((size_t)dim * 4);
     R->state = take(sizeof(DevState));
+    // incremental BUILD: running A~(c) and its bound, list of changed objects
+    R->acur = take((size_t)R->ncp * 8);
+    R->ecur = take((size_t)R->ncp * 8);
+    R->lold = take((size_t)n * 8);
+    R->lnew = take((size_t)n * 8);
+    R->lnb = take((size_t)n * 4);
+    R->llo = take((size_t)n * 4);
+    R->lhi = take((size_t)n * 4);
+    R->res_a = take((size_t)n * 8);
     R->total = off;
     return PAMX_OK;
 }
@@ -719,7 +728,7 @@ namespace {
 constexpr int kFullBlocks = 256;   // blocks per instance in the full-data TD
 
 struct BatchLayout {
-    size_t soff, kin, moff, order, td, tdb, it, sw, ctr, part, tdf, total;
+    size_t soff, kin, moff, order, td, tdb, it, sw, rows, ctr, part, tdf, total;
 };
 
 BatchLayout batch_layout(int32_t n_inst) {
@@ -734,6 +743,7 @@ BatchLayout batch_layout(int32_t n_inst) {
     b.tdb = take((size_t)n_inst * 8);
     b.it = take((size_t)n_inst * 4);
     b.sw = take((size_t)n_inst * 4);
+    b.rows = take((size_t)n_inst * 4);
     b.ctr = take(2 * 4);
     b.part = take((size_t)n_inst * kFullBlocks * 8);
     b.tdf = take((size_t)n_inst * 8);
@@ -840,6 +850,7 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
     a.td_full = reinterpret_cast<double *>(w + B.tdf);
     a.it_out = reinterpret_cast<int32_t *>(w + B.it);
     a.sw_out = reinterpret_cast<int32_t *>(w + B.sw);
+    a.rows_out = reinterpret_cast<int32_t *>(w + B.rows);
     a.queue = ctr;
     a.err = ctr + 1;
 
@@ -862,12 +873,13 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
     }
     tm.rec(2, s);
     int32_t err = 0;
-    std::vector<int32_t> it(n_inst), sw(n_inst);
+    std::vector<int32_t> it(n_inst), sw(n_inst), rows(n_inst);
     HIP_TRY(hipMemcpyAsync(&err, ctr + 1, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(td_sample, a.td_out, (size_t)n_inst * 8, hipMemcpyDeviceToHost, s));
     if (td_full) HIP_TRY(hipMemcpyAsync(td_full, a.td_full, (size_t)n_inst * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(it.data(), a.it_out, (size_t)n_inst * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(sw.data(), a.sw_out, (size_t)n_inst * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(rows.data(), a.rows_out, (size_t)n_inst * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (err) return fail(PAMX_ERR_HIP, "a medoid index outside [0, N) reached the full-data TD");
     if (stats) {
@@ -877,7 +889,10 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
             stats->iterations += it[j];
             stats->swaps += sw[j];
             const int64_t nj = sample_off[j + 1] - sample_off[j];
-            pairs += ((int64_t)k_inst[j] + it[j]) * nj * nj;
+            const int64_t kj = k_inst[j];
+            // BUILD: two full steps, then the rows of the changed objects;
+            // SWAP: every non-medoid candidate against every object
+            pairs += (kj < 2 ? kj : 2) * nj * nj + (int64_t)rows[j] * nj + it[j] * nj * (nj - kj);
         }
         stats->pairs = pairs;
         stats->best_inst = -1;

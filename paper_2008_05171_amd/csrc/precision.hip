@@ -35,13 +35,30 @@ constexpr int kAS = 72;        // padded row stride (bf16) of the staged object 
 // ---------------------------------------------------------------- FP64 distance
 // The reference distance of this form: Euclidean, FP64, from the original
 // FP32 coordinates (differences of two floats are exact in FP64).
+// Coordinates are loaded in unrolled groups of 16 from clamped (always
+// valid) indices, with no branch between the loads, so a group's loads are in
+// flight together; coordinates past dim add an exact 0.  The FMA order is
+// k = 0 .. dim-1.
 __device__ __forceinline__ double d64(const float *__restrict__ X, int dim, int64_t a, int64_t b) {
     const float *x = X + a * dim;
     const float *y = X + b * dim;
     double s = 0.0;
-    for (int k = 0; k < dim; ++k) {
-        const double t = (double)x[k] - (double)y[k];
-        s = fma(t, t, s);
+#pragma unroll
+    for (int k0 = 0; k0 < kRcMaxDim; k0 += 16) {
+        if (k0 < dim) {
+            float xv[16], yv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int kk = min(k0 + u, dim - 1);
+                xv[u] = x[kk];
+                yv[u] = y[kk];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const double t = (k0 + u < dim) ? (double)xv[u] - (double)yv[u] : 0.0;
+                s = fma(t, t, s);
+            }
+        }
     }
     return sqrt(s);
 }
@@ -258,10 +275,12 @@ template <int KS, typename ACC>
 __global__ __launch_bounds__(kRT) void k_rc_build_pass(
     const __bf16 *__restrict__ Xs, int32_t KP, const float *__restrict__ nb, int64_t n,
     const float *__restrict__ dn, const float *__restrict__ thr, const double *__restrict__ eps0,
-    int32_t L, int64_t ncp, ACC *__restrict__ part, int32_t *__restrict__ part_i) {
+    int32_t L, int64_t ncp, ACC *__restrict__ part, int32_t *__restrict__ part_i,
+    const DevState *__restrict__ gate) {
     __shared__ __align__(16) __bf16 As[kRB * 2 * kAS];
     __shared__ float4 Rv[2][kRB];   // by block parity: a wave is at most one block ahead
     __shared__ float G[4][64 * kGS];
+    if (gate && !gate->refresh) return;   // incremental step instead
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int q = blockIdx.y;
     const int64_t a = (int64_t)q * L, b = min(a + (int64_t)L, n);
@@ -394,8 +413,11 @@ __global__ __launch_bounds__(256) void k_rc_build_merge(
     const ACC *__restrict__ part, const int32_t *__restrict__ part_i, int32_t Q, int64_t ncp,
     int64_t n, const double *__restrict__ dn64, const uint8_t *__restrict__ is_med, int32_t add_self,
     const double *__restrict__ bnd, double *__restrict__ cand_v, double *__restrict__ cand_b,
-    double *__restrict__ wg_u) {
+    double *__restrict__ wg_u, double *__restrict__ acur, double *__restrict__ ecur,
+    DevState *__restrict__ gate) {
     __shared__ double red[256];
+    if (gate && !gate->refresh) return;
+    if (gate && blockIdx.x == 0 && threadIdx.x == 0) gate->n_full += 1;
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double up = __builtin_huge_val();
     if (c < n && !is_med[c]) {
@@ -408,6 +430,7 @@ __global__ __launch_bounds__(256) void k_rc_build_merge(
         }
         double v = (double)s;
         double b = (double)cf * bnd[0] + (double)cn * bnd[1] + bnd[2] * v;
+        if (acur) { acur[c] = v; ecur[c] = b; }   // start of the incremental steps
         if (add_self) v += dn64[c];
         b = b * 1.0001 + 1e-300;
         cand_v[c] = v;
@@ -523,40 +546,40 @@ __global__ __launch_bounds__(256) void k_rc_mark(const double *__restrict__ cand
 }
 
 // ---------------------------------------------------------------- FP64 re-score
-// BUILD: A64(c) = sum_o min(d64(o,c), dn64(o)) (+ dn64(c)), one work-group per
-// listed candidate, fixed summation order.
+// One work-group per listed candidate, fixed summation order.
+// BUILD: A64(c) = sum_o min(d64(o,c), dn64(o)) (+ dn64(c)).
+template <int KS>
 __global__ __launch_bounds__(256) void k_rc_build_rescore(
     const float *__restrict__ X, int32_t dim, int64_t n, const double *__restrict__ dn64,
     int32_t add_self, const int32_t *__restrict__ list, const DevState *__restrict__ st,
-    double *__restrict__ res_v) {
-    __shared__ double red[256];
+    double *__restrict__ res_v, double *__restrict__ res_a) {
     const int m = st->n_list;
     for (int idx = blockIdx.x; idx < m; idx += gridDim.x) {
         const int64_t c = list[idx];
         double s = 0.0;
         for (int64_t o = threadIdx.x; o < n; o += 256) s += fmin(d64(X, dim, o, c), dn64[o]);
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
+        s = block_sum<double, 256>(s);
+        if (threadIdx.x == 0) {
+            res_v[idx] = s + (add_self ? dn64[c] : 0.0);
+            res_a[idx] = s;
         }
-        if (threadIdx.x == 0) res_v[idx] = red[0] + (add_self ? dn64[c] : 0.0);
         __syncthreads();
     }
 }
 
-// SWAP: exact Delta(i,c) = R_i + B(c) + S_i(c) for every slot i, one
-// work-group per listed candidate.  Lane t walks a contiguous range of the
-// sorted objects; segments complete in its range go to LDS directly, the
-// partial first/last ones are combined afterwards in lane order.
+// SWAP: exact Delta(i,c) = R_i + B(c) + S_i(c) for every slot i.  Thread t
+// walks a contiguous range of the sorted objects; segments complete in its
+// range go to LDS directly, the partial first/last ones are combined
+// afterwards in thread order.
+template <int KS>
 __global__ __launch_bounds__(256) void k_rc_swap_rescore(
     const float *__restrict__ X, int32_t dim, int64_t n, int32_t k, const int32_t *__restrict__ srow,
     const double *__restrict__ dn64, const double *__restrict__ ds64,
-    const int32_t *__restrict__ near, const int32_t *__restrict__ seg_off,
-    const double *__restrict__ R64, const int32_t *__restrict__ list, const DevState *__restrict__ st,
+    const int32_t *__restrict__ near, const double *__restrict__ R64,
+    const int32_t *__restrict__ list, const DevState *__restrict__ st,
     double *__restrict__ res_v, int32_t *__restrict__ res_i) {
-    extern __shared__ double sarr[];          // k per-slot sums
+    extern __shared__ __align__(16) unsigned char rs_raw[];
+    double *sarr = reinterpret_cast<double *>(rs_raw);          // k per-slot sums
     __shared__ double hv[256], tv[256], red[256];
     __shared__ int hs[256], ts[256], ri[256];
     const int t = threadIdx.x;
@@ -571,13 +594,13 @@ __global__ __launch_bounds__(256) void k_rc_swap_rescore(
         int cur = -1, fs = -1;
         for (int64_t j = j0; j < j1; ++j) {
             const int64_t o = srow[j];
-            const int s = near[o];
-            if (s != cur) {
+            const int sl = near[o];
+            if (sl != cur) {
                 if (cur >= 0) {
                     if (fs < 0) { fs = cur; first = S; }   // first segment of the range
                     else sarr[cur] = S;                    // complete inside the range
                 }
-                cur = s;
+                cur = sl;
                 S = 0.0;
             }
             const double d = d64(X, dim, o, c), lo = dn64[o], hi = ds64[o];
@@ -625,7 +648,38 @@ __global__ __launch_bounds__(256) void k_rc_swap_rescore(
         }
         if (t == 0) { res_v[idx] = hv[0] + red[0]; res_i[idx] = ri[0]; }
         __syncthreads();
-        (void)seg_off;
+    }
+}
+
+template <int KS>
+static hipError_t rc_rescore_launch(bool swap_mode, const float *X, int32_t dim, int64_t n, int32_t k,
+                                    const int32_t *srow, const double *dn64, const double *ds64,
+                                    const int32_t *near, const double *R64, int32_t add_self,
+                                    const int32_t *list, const DevState *st, double *res_v,
+                                    double *res_a, int32_t *res_i, hipStream_t s) {
+    if (swap_mode)
+        hipLaunchKernelGGL((k_rc_swap_rescore<KS>), dim3(1024), dim3(256), (size_t)k * 8, s, X, dim, n,
+                           k, srow, dn64, ds64, near, R64, list, st, res_v, res_i);
+    else
+        hipLaunchKernelGGL((k_rc_build_rescore<KS>), dim3(1024), dim3(256), 0, s, X, dim, n, dn64,
+                           add_self, list, st, res_v, res_a);
+    return hipGetLastError();
+}
+
+static hipError_t rc_rescore(int KP, bool swap_mode, const float *X, int32_t dim, int64_t n, int32_t k,
+                             const int32_t *srow, const double *dn64, const double *ds64,
+                             const int32_t *near, const double *R64, int32_t add_self,
+                             const int32_t *list, const DevState *st, double *res_v, double *res_a,
+                             int32_t *res_i, hipStream_t s) {
+    switch (KP / 16) {
+        case 1: return rc_rescore_launch<1>(swap_mode, X, dim, n, k, srow, dn64, ds64, near, R64,
+                                            add_self, list, st, res_v, res_a, res_i, s);
+        case 2: return rc_rescore_launch<2>(swap_mode, X, dim, n, k, srow, dn64, ds64, near, R64,
+                                            add_self, list, st, res_v, res_a, res_i, s);
+        case 3: return rc_rescore_launch<3>(swap_mode, X, dim, n, k, srow, dn64, ds64, near, R64,
+                                            add_self, list, st, res_v, res_a, res_i, s);
+        default: return rc_rescore_launch<4>(swap_mode, X, dim, n, k, srow, dn64, ds64, near, R64,
+                                             add_self, list, st, res_v, res_a, res_i, s);
     }
 }
 
@@ -650,6 +704,9 @@ __global__ __launch_bounds__(1024) void k_rc_pick(const double *__restrict__ res
     if (threadIdx.x != 0) return;
     st->rescored += m;
     if (!swap_mode) {
+        // a long re-score list means the running bounds have grown: the next
+        // step recomputes every candidate from scratch
+        st->refresh = m > kRcRefreshList;
         st->best_c = c;
         if (c != INT_MAX) { med[t_step] = c; is_med[c] = 1; }
         else st->bad_medoids = 1;
@@ -863,7 +920,9 @@ __global__ __launch_bounds__(1024) void k_rc_iter_bounds(const double *__restric
 // BUILD step thresholds: dn + e_near (FP32), +inf before the first medoid.
 __global__ __launch_bounds__(256) void k_rc_build_thr(const float *__restrict__ dn32, int64_t n,
                                                       const double *__restrict__ eps0,
-                                                      float *__restrict__ thr) {
+                                                      float *__restrict__ thr,
+                                                      const DevState *__restrict__ gate) {
+    if (gate && !gate->refresh) return;
     const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (o >= n) return;
     const double lo = (double)dn32[o];
@@ -876,8 +935,11 @@ __global__ __launch_bounds__(256) void k_rc_build_thr(const float *__restrict__ 
 __global__ __launch_bounds__(1024) void k_rc_build_bounds(const double *__restrict__ dn64, int64_t n,
                                                           int32_t L, int32_t Q, int32_t first,
                                                           int32_t acc64, const double *__restrict__ eps0,
-                                                          double *__restrict__ bnd) {
+                                                          double *__restrict__ bnd,
+                                                          const DevState *__restrict__ gate,
+                                                          int32_t want) {
     __shared__ double r[1024];
+    if (gate && gate->refresh != want) return;
     double mx = 0.0;
     if (!first)
         for (int64_t o = threadIdx.x; o < n; o += 1024) mx = fmax(mx, dn64[o]);
@@ -895,12 +957,218 @@ __global__ __launch_bounds__(1024) void k_rc_build_bounds(const double *__restri
         bnd[1] = eps0[0] + small;
         bnd[2] = acc64 ? ((double)L + Q + 64.0) * 0x1p-52
                        : (32.0 + (L + 31) / 32 + Q + 10.0) * 0x1p-24 * 1.02;
+        bnd[3] = r[0];
     }
 }
 
 __global__ void k_rc_reset_list(DevState *st) {
     if (threadIdx.x == 0 && !st->done) st->n_list = 0;
 }
+
+// ---------------------------------------------------------------- incremental BUILD
+// After the first two steps, adding medoid m_t changes A(c) only through the
+// objects whose dn dropped (new < old):
+//   A(c) += sum over them of min(d, new) - min(d, old),
+// and a term depends on d only while new < d < old.  With d~ within e of d,
+// an object whose d~ is below new - e or above old + e contributes its exact
+// term, so the running bound E(c) grows by e per object counted inside
+// [new - e, old + e] (near/far classes as in the full pass) plus the FP64
+// rounding of the sums.  A candidate re-scored exactly restarts from its FP64
+// value with a rounding-only bound.
+
+__global__ __launch_bounds__(kObjBlk) void k_rc_build_update2(
+    const float *__restrict__ X, int32_t dim, int64_t n, const double *__restrict__ dn64,
+    double *__restrict__ dn64n, float *__restrict__ dn32n, const DevState *__restrict__ st,
+    int32_t *__restrict__ blkcnt) {
+    const int64_t o = (int64_t)blockIdx.x * kObjBlk + threadIdx.x;
+    const int c = st->best_c;
+    int chg = 0;
+    if (o < n) {
+        const double old = dn64[o];
+        double nw = old;
+        if (c != INT_MAX) nw = fmin(old, d64(X, dim, o, c));
+        dn64n[o] = nw;
+        dn32n[o] = (float)nw;
+        chg = nw < old;
+    }
+    const int cnt = __syncthreads_count(chg);
+    if (threadIdx.x == 0) blkcnt[blockIdx.x] = cnt;
+}
+
+// Stable list (ascending object) of the objects whose dn dropped, with their
+// old and new dn, norm and counting interval [lo, hi] (rounded outward).
+__global__ __launch_bounds__(kObjBlk) void k_rc_build_compact(
+    const double *__restrict__ dn_old, const double *__restrict__ dn_new, const float *__restrict__ nb,
+    int64_t n, const int32_t *__restrict__ blkcnt, int32_t nblk, const double *__restrict__ eps0,
+    int32_t *__restrict__ lobj, double *__restrict__ lold, double *__restrict__ lnew,
+    float *__restrict__ lnb, float *__restrict__ llo, float *__restrict__ lhi,
+    DevState *__restrict__ st) {
+    __shared__ int wcnt[kObjBlk / 64];
+    if (st->refresh) return;
+    int pre = 0, tot = 0;
+    for (int b = threadIdx.x; b < nblk; b += kObjBlk) {
+        const int v = blkcnt[b];
+        tot += v;
+        if (b < (int)blockIdx.x) pre += v;
+    }
+    pre = block_sum<int, kObjBlk>(pre);
+    tot = block_sum<int, kObjBlk>(tot);
+    const int64_t o = (int64_t)blockIdx.x * kObjBlk + threadIdx.x;
+    double old = 0.0, nw = 0.0;
+    bool chg = false;
+    if (o < n) {
+        old = dn_old[o];
+        nw = dn_new[o];
+        chg = nw < old;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long m = __ballot(chg);
+    if (lane == 0) wcnt[wv] = __popcll(m);
+    __syncthreads();
+    int rank = __popcll(m & ((1ull << lane) - 1ull));
+    for (int w = 0; w < wv; ++w) rank += wcnt[w];
+    if (chg) {
+        const int pos = pre + rank;
+        const double e = eps0[0];
+        lobj[pos] = (int32_t)o;
+        lold[pos] = old;
+        lnew[pos] = nw;
+        lnb[pos] = nb[o];
+        llo[pos] = (float)((nw - e) - 0x1p-20 * (nw + e) - 1e-30);
+        lhi[pos] = (float)((old + e) + 0x1p-20 * (old + e) + 1e-30);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->n_chg = tot;
+}
+
+// Per candidate and chunk of the list: sum of min(d~, new) - min(d~, old) in
+// FP64 and the far / near counts of d~ inside [lo, hi].
+template <int KS>
+__global__ __launch_bounds__(kRT) void k_rc_build_delta(
+    const __bf16 *__restrict__ Xs, int32_t KP, const float *__restrict__ nb, int64_t n,
+    const int32_t *__restrict__ lobj, const float *__restrict__ lnb, const float *__restrict__ llo,
+    const float *__restrict__ lhi, const double *__restrict__ lold, const double *__restrict__ lnew,
+    const double *__restrict__ eps0, const DevState *__restrict__ st, int64_t ncp,
+    double *__restrict__ part, int32_t *__restrict__ part_i) {
+    __shared__ __align__(16) __bf16 As[kRB * 2 * kAS];
+    __shared__ float4 Rv[2][kRB];    // by block parity, as in the full pass
+    __shared__ double2 Rd[2][kRB];
+    __shared__ float G[4][64 * kGS];
+    if (st->refresh) return;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int64_t m = st->n_chg;
+    const int Qd = gridDim.y, q = blockIdx.y;
+    const int64_t Ld = (m + Qd - 1) / Qd;
+    const int64_t a = min((int64_t)q * Ld, m), b = min(a + Ld, m);
+    const int64_t cbase = (int64_t)blockIdx.x * kRT + w * 64;
+    const int64_t c = cbase + lane;
+    bf16x8 bh[2][KS], bl[2][KS];
+    load_bq<KS>(Xs, KP, n, cbase, bh, bl);
+    const float nc = (c < n) ? nb[c] : 0.0f;
+    const float d0 = (float)eps0[2];
+    double acc = 0.0;
+    int cf = 0, cn = 0;
+    float *Gw = G[w];
+    const RowVals rv{lnb, llo, lhi, nullptr};
+    Stage<KS> stg;
+    if (a < b) stage_load<KS>(stg, Xs, KP, lobj, a, b, rv);
+    for (int64_t j0 = a; j0 < b; j0 += kRB) {
+        const int par = (int)(((j0 - a) / kRB) & 1);
+        float4 *Rb = Rv[par];
+        double2 *Rdb = Rd[par];
+        stage_store<KS>(stg, KP, As, Rb);
+        if (tid < kRB) {
+            const int64_t j = j0 + tid;
+            Rdb[tid] = (j < b) ? make_double2(lold[j], lnew[j]) : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        if (j0 + kRB < b) stage_load<KS>(stg, Xs, KP, lobj, j0 + kRB, b, rv);
+        gram_tile<KS>(As, Gw, bh, bl);
+        __syncthreads();
+        const int mm = (int)min((int64_t)kRB, b - j0);
+        double blk = 0.0;
+        for (int r = 0; r < mm; ++r) {
+            const float4 q4 = Rb[r];      // norm, lo, hi
+            const double2 od = Rdb[r];    // old, new
+            const float d = rc_dist(Gw[lane * kGS + r], q4.x, nc);
+            const double dd = (double)d;
+            blk += fmin(dd, od.y) - fmin(dd, od.x);
+            const bool cnt = d >= q4.y && d <= q4.z;
+            cf += (cnt && d >= d0) ? 1 : 0;
+            cn += (cnt && d < d0) ? 1 : 0;
+        }
+        acc += blk;
+    }
+    part[(int64_t)q * ncp + c] = acc;
+    part_i[(int64_t)q * 2 * ncp + c] = cf;
+    part_i[(int64_t)q * 2 * ncp + ncp + c] = cn;
+}
+
+// A~(c) += chunk sums (chunk order), E(c) += counted errors + rounding; then
+// the step's value, bound and work-group upper minimum as k_rc_build_merge.
+// bnd[0] = e_far, bnd[1] = e_near, bnd[2] = FP64 summation factor,
+// bnd[3] = largest old dn (bounds every |term|).
+__global__ __launch_bounds__(256) void k_rc_build_dmerge(
+    const double *__restrict__ part, const int32_t *__restrict__ part_i, int32_t Q, int64_t ncp,
+    int64_t n, const double *__restrict__ dn64, const uint8_t *__restrict__ is_med, int32_t add_self,
+    const double *__restrict__ bnd, const DevState *__restrict__ st, double *__restrict__ acur,
+    double *__restrict__ ecur, double *__restrict__ cand_v, double *__restrict__ cand_b,
+    double *__restrict__ wg_u) {
+    __shared__ double red[256];
+    if (st->refresh) return;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double up = __builtin_huge_val();
+    if (c < n && !is_med[c]) {
+        double s = 0.0;
+        int64_t cf = 0, cn = 0;
+        for (int q = 0; q < Q; ++q) {
+            s += part[(int64_t)q * ncp + c];
+            cf += part_i[(int64_t)q * 2 * ncp + c];
+            cn += part_i[(int64_t)q * 2 * ncp + ncp + c];
+        }
+        const double a = acur[c] + s;
+        const double e = ecur[c] + (double)cf * bnd[0] + (double)cn * bnd[1] +
+                         bnd[2] * (double)st->n_chg * bnd[3] + 0x1p-52 * fabs(a);
+        acur[c] = a;
+        ecur[c] = e;
+        const double v = add_self ? a + dn64[c] : a;
+        const double b = e * 1.0001 + 1e-300;
+        cand_v[c] = v;
+        cand_b[c] = b;
+        up = v + b;
+    } else if (c < n) {
+        cand_v[c] = __builtin_huge_val();
+        cand_b[c] = 0.0;
+    }
+    red[threadIdx.x] = up;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) wg_u[blockIdx.x] = red[0];
+}
+
+// Re-scored candidates restart from their FP64 sums.
+__global__ __launch_bounds__(256) void k_rc_reanchor(const int32_t *__restrict__ list,
+                                                     const double *__restrict__ res_a,
+                                                     const DevState *__restrict__ st, int64_t n,
+                                                     double *__restrict__ acur,
+                                                     double *__restrict__ ecur) {
+    const int m = st->n_list;
+    for (int idx = blockIdx.x * 256 + threadIdx.x; idx < m; idx += gridDim.x * 256) {
+        const int64_t c = list[idx];
+        acur[c] = res_a[idx];
+        ecur[c] = ((double)n + 64.0) * 0x1p-52 * res_a[idx];
+    }
+}
+
+template <typename X>
+__global__ __launch_bounds__(256) void k_rc_copy(const X *__restrict__ src, X *__restrict__ dst,
+                                                 int64_t cnt) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < cnt) dst[t] = src[t];
+}
+
 
 // ================================================================ host side
 struct RcPtrs {
@@ -911,14 +1179,17 @@ struct RcPtrs {
     int32_t *near, *sec, *srow, *blkcnt, *seg_off, *cinfo3, *part_i, *list, *res_i, *rlist;
     uint8_t *is_med;
     DevState *st;
+    double *acur, *ecur, *lold, *lnew, *res_a;
+    float *lnb, *llo, *lhi;
 };
 
 template <int KS, typename ACC>
-static void rc_build_pass_launch(const RcPtrs &p, const RcLayout &R, int64_t n, hipStream_t s) {
+static void rc_build_pass_launch(const RcPtrs &p, const RcLayout &R, int64_t n, const float *dn32,
+                                 const DevState *gate, hipStream_t s) {
     hipLaunchKernelGGL((k_rc_build_pass<KS, ACC>), dim3(R.n_ctiles, R.Q), dim3(kRT), 0, s,
-                       (const __bf16 *)p.Xs, R.KP, (const float *)p.nb, n, (const float *)p.dn32,
+                       (const __bf16 *)p.Xs, R.KP, (const float *)p.nb, n, dn32,
                        (const float *)p.thr, (const double *)p.eps0, R.L, R.ncp,
-                       static_cast<ACC *>(p.part), p.part_i);
+                       static_cast<ACC *>(p.part), p.part_i, gate);
 }
 
 template <int KS, typename ACC>
@@ -932,12 +1203,13 @@ static void rc_swap_pass_launch(const RcPtrs &p, const RcLayout &R, int64_t n, i
 }
 
 template <typename ACC>
-static void rc_build_pass_any(const RcPtrs &p, const RcLayout &R, int64_t n, hipStream_t s) {
+static void rc_build_pass_any(const RcPtrs &p, const RcLayout &R, int64_t n, const float *dn32,
+                              const DevState *gate, hipStream_t s) {
     switch (R.KP / 16) {
-        case 1: rc_build_pass_launch<1, ACC>(p, R, n, s); break;
-        case 2: rc_build_pass_launch<2, ACC>(p, R, n, s); break;
-        case 3: rc_build_pass_launch<3, ACC>(p, R, n, s); break;
-        default: rc_build_pass_launch<4, ACC>(p, R, n, s); break;
+        case 1: rc_build_pass_launch<1, ACC>(p, R, n, dn32, gate, s); break;
+        case 2: rc_build_pass_launch<2, ACC>(p, R, n, dn32, gate, s); break;
+        case 3: rc_build_pass_launch<3, ACC>(p, R, n, dn32, gate, s); break;
+        default: rc_build_pass_launch<4, ACC>(p, R, n, dn32, gate, s); break;
     }
 }
 
@@ -948,6 +1220,24 @@ static void rc_swap_pass_any(const RcPtrs &p, const RcLayout &R, int64_t n, int 
         case 2: rc_swap_pass_launch<2, ACC>(p, R, n, k, s); break;
         case 3: rc_swap_pass_launch<3, ACC>(p, R, n, k, s); break;
         default: rc_swap_pass_launch<4, ACC>(p, R, n, k, s); break;
+    }
+}
+
+template <int KS>
+static void rc_build_delta_launch(const RcPtrs &p, const RcLayout &R, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL((k_rc_build_delta<KS>), dim3(R.n_ctiles, R.Q), dim3(kRT), 0, s,
+                       (const __bf16 *)p.Xs, R.KP, (const float *)p.nb, n, (const int32_t *)p.srow,
+                       (const float *)p.lnb, (const float *)p.llo, (const float *)p.lhi,
+                       (const double *)p.lold, (const double *)p.lnew, (const double *)p.eps0,
+                       (const DevState *)p.st, R.ncp, static_cast<double *>(p.part), p.part_i);
+}
+
+static void rc_build_delta_any(const RcPtrs &p, const RcLayout &R, int64_t n, hipStream_t s) {
+    switch (R.KP / 16) {
+        case 1: rc_build_delta_launch<1>(p, R, n, s); break;
+        case 2: rc_build_delta_launch<2>(p, R, n, s); break;
+        case 3: rc_build_delta_launch<3>(p, R, n, s); break;
+        default: rc_build_delta_launch<4>(p, R, n, s); break;
     }
 }
 
@@ -987,6 +1277,14 @@ static RcPtrs rc_ptrs(const RcLayout &R, void *ws) {
     p.eps0 = reinterpret_cast<double *>(w + R.eps0);
     p.bnd = reinterpret_cast<double *>(w + R.bnd);
     p.st = reinterpret_cast<DevState *>(w + R.state);
+    p.acur = reinterpret_cast<double *>(w + R.acur);
+    p.ecur = reinterpret_cast<double *>(w + R.ecur);
+    p.lold = reinterpret_cast<double *>(w + R.lold);
+    p.lnew = reinterpret_cast<double *>(w + R.lnew);
+    p.res_a = reinterpret_cast<double *>(w + R.res_a);
+    p.lnb = reinterpret_cast<float *>(w + R.lnb);
+    p.llo = reinterpret_cast<float *>(w + R.llo);
+    p.lhi = reinterpret_cast<float *>(w + R.lhi);
     return p;
 }
 
@@ -1027,40 +1325,91 @@ hipError_t rc_prep_build(const float *X, int32_t dim, const RcLayout &R, int32_t
     rc_fill<double>(p.dn64, n, __builtin_huge_val(), s);
     rc_fill<float>(p.dn32, n, __builtin_huge_valf(), s);
     const int nmwg = (int)((n + 255) / 256);
-    for (int32_t t = 0; t < k; ++t) {
-        hipLaunchKernelGGL(k_rc_build_thr, dim3(ob), dim3(256), 0, s, (const float *)p.dn32, n,
-                           (const double *)p.eps0, p.thr);
-        hipLaunchKernelGGL(k_rc_build_bounds, dim3(1), dim3(1024), 0, s, (const double *)p.dn64, n,
-                           R.L, R.Q, (int32_t)(t == 0), (int32_t)acc64, (const double *)p.eps0, p.bnd);
-        const int add_self = (opt.build_exclude_self && t > 0) ? 1 : 0;
+    // FP64 sums: the first two steps are full passes, later steps incremental
+    // (dn ping-pongs between the dn and ds buffers, free until SWAP)
+    double *d64b[2] = {p.dn64, p.ds64};
+    float *d32b[2] = {p.dn32, p.ds32};
+    int cur = 0;
+    // full pass from scratch: thresholds, bounds, pass, merge (gate = run only
+    // when the device state asks for a refresh; nullptr = always)
+    auto full_step = [&](int32_t t, int add_self, DevState *gate) {
+        hipLaunchKernelGGL(k_rc_build_thr, dim3(ob), dim3(256), 0, s, (const float *)d32b[cur], n,
+                           (const double *)p.eps0, p.thr, (const DevState *)gate);
+        hipLaunchKernelGGL(k_rc_build_bounds, dim3(1), dim3(1024), 0, s, (const double *)d64b[cur],
+                           n, R.L, R.Q, (int32_t)(t == 0), (int32_t)acc64, (const double *)p.eps0,
+                           p.bnd, (const DevState *)gate, (int32_t)1);
         if (acc64) {
-            rc_build_pass_any<double>(p, R, n, s);
+            rc_build_pass_any<double>(p, R, n, d32b[cur], gate, s);
             hipLaunchKernelGGL(k_rc_build_merge<double>, dim3(nmwg), dim3(256), 0, s,
                                (const double *)p.part, (const int32_t *)p.part_i, R.Q, R.ncp, n,
-                               (const double *)p.dn64, (const uint8_t *)p.is_med, add_self,
-                               (const double *)p.bnd, p.cand_v, p.cand_b, p.wg_u);
+                               (const double *)d64b[cur], (const uint8_t *)p.is_med, add_self,
+                               (const double *)p.bnd, p.cand_v, p.cand_b, p.wg_u, p.acur, p.ecur,
+                               gate);
         } else {
-            rc_build_pass_any<float>(p, R, n, s);
+            rc_build_pass_any<float>(p, R, n, d32b[cur], gate, s);
             hipLaunchKernelGGL(k_rc_build_merge<float>, dim3(nmwg), dim3(256), 0, s,
                                (const float *)p.part, (const int32_t *)p.part_i, R.Q, R.ncp, n,
-                               (const double *)p.dn64, (const uint8_t *)p.is_med, add_self,
-                               (const double *)p.bnd, p.cand_v, p.cand_b, p.wg_u);
+                               (const double *)d64b[cur], (const uint8_t *)p.is_med, add_self,
+                               (const double *)p.bnd, p.cand_v, p.cand_b, p.wg_u,
+                               (double *)nullptr, (double *)nullptr, gate);
+        }
+    };
+    for (int32_t t = 0; t < k; ++t) {
+        const int add_self = (opt.build_exclude_self && t > 0) ? 1 : 0;
+        if (!acc64 || t < 2) {
+            full_step(t, add_self, nullptr);
+        } else {
+            // incremental step (skipped on the device when a refresh was asked for) ...
+            hipLaunchKernelGGL(k_rc_build_bounds, dim3(1), dim3(1024), 0, s,
+                               (const double *)d64b[cur ^ 1], n, R.L, R.Q, (int32_t)0, (int32_t)1,
+                               (const double *)p.eps0, p.bnd, (const DevState *)p.st, (int32_t)0);
+            hipLaunchKernelGGL(k_rc_build_compact, dim3((unsigned)R.n_oblk), dim3(kObjBlk), 0, s,
+                               (const double *)d64b[cur ^ 1], (const double *)d64b[cur],
+                               (const float *)p.nb, n, (const int32_t *)p.blkcnt, R.n_oblk,
+                               (const double *)p.eps0, p.srow, p.lold, p.lnew, p.lnb, p.llo, p.lhi,
+                               p.st);
+            rc_build_delta_any(p, R, n, s);
+            hipLaunchKernelGGL(k_rc_build_dmerge, dim3(nmwg), dim3(256), 0, s,
+                               (const double *)p.part, (const int32_t *)p.part_i, R.Q, R.ncp, n,
+                               (const double *)d64b[cur], (const uint8_t *)p.is_med, add_self,
+                               (const double *)p.bnd, (const DevState *)p.st, p.acur, p.ecur,
+                               p.cand_v, p.cand_b, p.wg_u);
+            // ... or the full pass that resets every running bound
+            full_step(t, add_self, p.st);
         }
         hipLaunchKernelGGL(k_rc_upper, dim3(1), dim3(1024), 0, s, (const double *)p.wg_u, nmwg, p.st);
         hipLaunchKernelGGL(k_rc_mark, dim3(nmwg), dim3(256), 0, s, (const double *)p.cand_v,
                            (const double *)p.cand_b, n, 0, p.list, p.st);
-        hipLaunchKernelGGL(k_rc_build_rescore, dim3(1024), dim3(256), 0, s, X, dim, n,
-                           (const double *)p.dn64, add_self, (const int32_t *)p.list,
-                           (const DevState *)p.st, p.res_v);
+        {
+            const hipError_t e = rc_rescore(R.KP, false, X, dim, n, k, nullptr, (const double *)d64b[cur],
+                                            nullptr, nullptr, nullptr, add_self, (const int32_t *)p.list,
+                                            (const DevState *)p.st, p.res_v, p.res_a, nullptr, s);
+            if (e != hipSuccess) return e;
+        }
         hipLaunchKernelGGL(k_rc_pick, dim3(1), dim3(1024), 0, s, (const double *)p.res_v,
                            (const int32_t *)p.res_i, (const int32_t *)p.list, 0, t, medoids, p.is_med,
                            p.st, (pamx_swap_record *)nullptr);
-        if (t == 0)
+        if (acc64)
+            hipLaunchKernelGGL(k_rc_reanchor, dim3(64), dim3(256), 0, s, (const int32_t *)p.list,
+                               (const double *)p.res_a, (const DevState *)p.st, n, p.acur, p.ecur);
+        if (t == 0) {
             hipLaunchKernelGGL(k_rc_build_update<true>, dim3(ob), dim3(256), 0, s, X, dim, n, p.dn64,
                                p.dn32, (const DevState *)p.st);
-        else
+        } else if (acc64) {
+            hipLaunchKernelGGL(k_rc_build_update2, dim3((unsigned)R.n_oblk), dim3(kObjBlk), 0, s, X,
+                               dim, n, (const double *)d64b[cur], d64b[cur ^ 1], d32b[cur ^ 1],
+                               (const DevState *)p.st, p.blkcnt);
+            cur ^= 1;
+        } else {
             hipLaunchKernelGGL(k_rc_build_update<false>, dim3(ob), dim3(256), 0, s, X, dim, n, p.dn64,
                                p.dn32, (const DevState *)p.st);
+        }
+    }
+    if (cur == 1) {   // the caller reads dn from the dn buffers
+        hipLaunchKernelGGL(k_rc_copy<double>, dim3(ob), dim3(256), 0, s, (const double *)p.ds64,
+                           p.dn64, n);
+        hipLaunchKernelGGL(k_rc_copy<float>, dim3(ob), dim3(256), 0, s, (const float *)p.ds32,
+                           p.dn32, n);
     }
     return hipGetLastError();
 }
@@ -1134,10 +1483,14 @@ hipError_t rc_swap_iteration(const float *X, int32_t dim, const RcLayout &R, int
     hipLaunchKernelGGL(k_rc_upper, dim3(1), dim3(1024), 0, s, (const double *)p.wg_u, nmwg, p.st);
     hipLaunchKernelGGL(k_rc_mark, dim3(nmwg), dim3(256), 0, s, (const double *)p.cand_v,
                        (const double *)p.cand_b, n, 1, p.list, p.st);
-    hipLaunchKernelGGL(k_rc_swap_rescore, dim3(1024), dim3(256), (size_t)k * 8, s, X, dim, n, k,
-                       (const int32_t *)p.srow, (const double *)p.dn64, (const double *)p.ds64,
-                       (const int32_t *)p.near, (const int32_t *)p.seg_off, (const double *)p.R64,
-                       (const int32_t *)p.list, (const DevState *)p.st, p.res_v, p.res_i);
+    {
+        const hipError_t e = rc_rescore(R.KP, true, X, dim, n, k, (const int32_t *)p.srow,
+                                        (const double *)p.dn64, (const double *)p.ds64,
+                                        (const int32_t *)p.near, (const double *)p.R64, 0,
+                                        (const int32_t *)p.list, (const DevState *)p.st, p.res_v,
+                                        nullptr, p.res_i, s);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_rc_pick, dim3(1), dim3(1024), 0, s, (const double *)p.res_v,
                        (const int32_t *)p.res_i, (const int32_t *)p.list, 1, 0, medoids, p.is_med, p.st,
                        static_cast<pamx_swap_record *>(opt.trace));
