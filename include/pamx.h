@@ -77,12 +77,13 @@ extern "C" {
 #define PAMX_DIST_STORED 0 /* the n x n FP32 matrix is computed once into the
                               workspace (Gram term on FP32 MFMA)              */
 #define PAMX_DIST_BF16 1   /* mixed-precision form: no matrix; every pass
-                              recomputes distances of BF16-rounded centred
+                              recomputes distances of split-BF16 centred
                               points on the BF16 matrix cores, sums loss
-                              changes in FP32, and re-scores in FP64 (from the
-                              FP32 points) every candidate whose rigorous error
-                              bound reaches the best one, so BUILD and SWAP
-                              take the decisions of FP64 arithmetic.
+                              changes in FP64 (or FP32 with PAMX_ACC_F32),
+                              and re-scores in FP64 (from the FP32 points)
+                              every candidate whose rigorous error bound
+                              reaches the best one, so BUILD and SWAP take
+                              the decisions of FP64 arithmetic.
                               FastPAM1 only; dim <= 64, k <= 4096.            */
 
 /* return codes */
