@@ -110,7 +110,7 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->blkcnt = take((size_t)L->n_oblk * k * 4);
     L->blkbase = take((size_t)L->Q * 16);            // chunk carry map
     L->seg_off = take((size_t)(k + 1) * 4);
-    L->segc = take((size_t)k * 8);
+    L->cdn = take((size_t)L->Q * 2 * 8);              // DN parts of carried segments
     L->part = take((size_t)L->Q * 4 * L->ncp * 8);
     L->part_i = take((size_t)L->Q * L->ncp * 4);
     L->cand_v = take(8);

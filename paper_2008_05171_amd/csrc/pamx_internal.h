@@ -162,7 +162,7 @@ struct Layout {
     size_t mean;         // coordinate means of the points (L2 fit), or SIZE_MAX
     size_t near, sec, dn, ds, is_med;
     size_t srow, sdn, sds;
-    size_t blkcnt, blkbase, seg_off, segc;
+    size_t blkcnt, blkbase, seg_off, cdn;
     size_t part, part_i;
     size_t cand_v, cand_i, cand_a;
     size_t wg_v, wg_i, wg_c;

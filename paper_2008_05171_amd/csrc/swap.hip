@@ -526,26 +526,6 @@ __device__ __forceinline__ bool cache_update_o1(int slot, T dnew, int32_t &nr, i
     return false;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_cache_update(const T *__restrict__ D, int64_t ld, int64_t n,
-                                                      int32_t *__restrict__ near,
-                                                      int32_t *__restrict__ sec, T *__restrict__ dn,
-                                                      T *__restrict__ ds, int32_t *__restrict__ rlist,
-                                                      DevState *__restrict__ st) {
-    if (st->done || !st->swapped) return;
-    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (o >= n) return;
-    const int slot = st->new_slot;
-    const T dnew = D[(int64_t)st->new_med * ld + o];
-    int32_t nr = near[o], sc = sec[o];
-    T a = dn[o], b = ds[o];
-    if (cache_update_o1<T>(slot, dnew, nr, sc, a, b)) {
-        rlist[atomicAdd(&st->n_list, 1)] = (int32_t)o;
-    } else {
-        near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b;
-    }
-}
-
 // One wave per listed object (the list order varies, each result does not).
 template <typename T>
 __global__ __launch_bounds__(256) void k_cache_rescan(const T *__restrict__ D, int64_t ld, int32_t k,
@@ -719,22 +699,6 @@ __global__ __launch_bounds__(kObjBlk) void k_seg_scatter(const int32_t *__restri
 }
 
 // DN_i = sum over segment i of dn, one wave per segment, fixed order.
-template <typename T>
-__global__ __launch_bounds__(256) void k_seg_const(const T *__restrict__ sdn,
-                                                   const int32_t *__restrict__ seg_off, int32_t k,
-                                                   AccT<T> *__restrict__ segc,
-                                                   const DevState *__restrict__ st) {
-    using A = AccT<T>;
-    if (st->done) return;
-    const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= k) return;
-    A s = 0;
-    for (int64_t j = seg_off[i] + lane; j < seg_off[i + 1]; j += 64) s += (A)sdn[j];
-    for (int w = 32; w > 0; w >>= 1) s += __shfl_xor(s, w);
-    if (lane == 0) segc[i] = s;
-}
-
 // ---- the hot pass.  See the file header for the arithmetic.
 // Output per candidate and chunk: part[q][0] = A partial, [1] head carry,
 // [2] tail carry, [3] best value over segments complete in the chunk, and
@@ -744,7 +708,7 @@ template <typename T, int VEC, bool P2>
 __global__ __launch_bounds__(kWG) void k_swap_pass(
     const T *__restrict__ D, int64_t ld, int64_t n, int32_t k, const int32_t *__restrict__ srow,
     const T *__restrict__ sdn, const T *__restrict__ sds, const int32_t *__restrict__ seg_off,
-    const AccT<T> *__restrict__ segc, const ChunkInfo *__restrict__ cinfo, int32_t L, int64_t ncp,
+    AccT<T> *__restrict__ cdn, const ChunkInfo *__restrict__ cinfo, int32_t L, int64_t ncp,
     AccT<T> *__restrict__ part, int32_t *__restrict__ part_i, AccT<T> *__restrict__ P,
     const DevState *__restrict__ st) {
     using A = AccT<T>;
@@ -772,6 +736,7 @@ __global__ __launch_bounds__(kWG) void k_swap_pass(
         A M[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) M[e] = 0;
+        A dns = 0;   // DN of the segment's objects in this chunk (same in every lane)
         if (active) {
             int64_t j = p0;
             for (; j + U <= p1; j += U) {
@@ -785,18 +750,21 @@ __global__ __launch_bounds__(kWG) void k_swap_pass(
                     hi[u] = sds[j + u];
                 }
 #pragma unroll
-                for (int u = 0; u < U; ++u)
+                for (int u = 0; u < U; ++u) {
+                    dns += (A)lo[u];
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
                         accA[e] += (A)vmin(v[u][e], lo[u]);
                         M[e] += (A)vmed3(v[u][e], lo[u], hi[u]);
                     }
+                }
             }
             for (; j < p1; ++j) {
                 const int64_t o = srow[j];
                 T v[VEC];
                 load_vec<T, VEC>(D + o * ld + c0, v);
                 const T lo = sdn[j], hi = sds[j];
+                dns += (A)lo;
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
                     accA[e] += (A)vmin(v[e], lo);
@@ -804,14 +772,18 @@ __global__ __launch_bounds__(kWG) void k_swap_pass(
                 }
             }
         }
+        // the first lane of the first tile (always a real candidate) records
+        // the chunk's part of DN for segments carried across chunks
+        const bool rec = blockIdx.x == 0 && threadIdx.x == 0;
         if (s == ci.sa && (ci.flags & kHead)) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) pq[1 * ncp + e] = M[e];
+            if (rec) cdn[2 * q] = dns;
         } else if (s == ci.sb && (ci.flags & kTail)) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) pq[2 * ncp + e] = M[e];
+            if (rec) cdn[2 * q + 1] = dns;
         } else {
-            const A dns = segc[s];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 const A v = M[e] - dns;
@@ -838,7 +810,7 @@ template <typename T, bool P2>
 __global__ __launch_bounds__(kWG) void k_swap_merge(
     const AccT<T> *__restrict__ part, const int32_t *__restrict__ part_i,
     const ChunkInfo *__restrict__ cinfo, int32_t Q, int64_t n, int32_t k, int64_t ncp,
-    const AccT<T> *__restrict__ segc, const uint8_t *__restrict__ is_med,
+    const AccT<T> *__restrict__ cdn, const uint8_t *__restrict__ is_med,
     const DevState *__restrict__ st, AccT<T> *__restrict__ P, AccT<T> *__restrict__ cand_a,
     AccT<T> *__restrict__ wg_v, int32_t *__restrict__ wg_i, int32_t *__restrict__ wg_c) {
     using A = AccT<T>;
@@ -850,10 +822,10 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
     if (c < n) {
         A accA = 0;
         int run_s = -1;
-        A run_m = 0;
+        A run_m = 0, run_dn = 0;
         auto flush = [&]() {
             if (run_s >= 0) {
-                const A v = run_m - segc[run_s];
+                const A v = run_m - run_dn;
                 if (lt2(v, run_s, bestv, besti)) { bestv = v; besti = run_s; }
                 if constexpr (P2) P[(int64_t)run_s * ncp + c] = v;
             }
@@ -880,12 +852,14 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
                 accA += xa[u];
                 if (xi[u] != INT_MAX && lt2(xv[u], xi[u], bestv, besti)) { bestv = xv[u]; besti = xi[u]; }
                 if (ci.flags & kHead) {
-                    if (ci.sa == run_s) run_m += xh[u];
-                    else { flush(); run_s = ci.sa; run_m = xh[u]; }
+                    const A dh = cdn[2 * (q0 + u)];
+                    if (ci.sa == run_s) { run_m += xh[u]; run_dn += dh; }
+                    else { flush(); run_s = ci.sa; run_m = xh[u]; run_dn = dh; }
                 }
                 if (ci.flags & kTail) {
-                    if (ci.sb == run_s) run_m += xt[u];
-                    else { flush(); run_s = ci.sb; run_m = xt[u]; }
+                    const A dt = cdn[2 * (q0 + u) + 1];
+                    if (ci.sb == run_s) { run_m += xt[u]; run_dn += dt; }
+                    else { flush(); run_s = ci.sb; run_m = xt[u]; run_dn = dt; }
                 }
             }
         }
@@ -912,48 +886,63 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
     }
 }
 
-// ---- FastPAM1: global best (value, slot, candidate), then apply it if it
-// lowers TD.  The float path requires the FP64 change to be below -margin,
-// the bound on its rounding, so TD decreases strictly and SWAP cannot cycle.
+// ---- FastPAM1 select fused with the cache update: every block reduces the
+// merge partials to the global best (value, slot, candidate) itself -- the
+// same result in every block -- and, when the swap is taken, updates its
+// objects' caches by the O(1) rule (objects that lost their nearest or second
+// medoid are listed for a rescan).  Block 0 records the swap in the state.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_swap_select(const AccT<T> *__restrict__ wg_v,
-                                                      const int32_t *__restrict__ wg_i,
-                                                      const int32_t *__restrict__ wg_c, int32_t nwg,
-                                                      int32_t *__restrict__ med,
-                                                      uint8_t *__restrict__ is_med,
-                                                      DevState *__restrict__ st,
-                                                      pamx_swap_record *__restrict__ trace) {
+__global__ __launch_bounds__(256) void k_select_update(
+    const AccT<T> *__restrict__ wg_v, const int32_t *__restrict__ wg_i,
+    const int32_t *__restrict__ wg_c, int32_t nwg, const T *__restrict__ D, int64_t ld, int64_t n,
+    int32_t *__restrict__ med, uint8_t *__restrict__ is_med, int32_t *__restrict__ near,
+    int32_t *__restrict__ sec, T *__restrict__ dn, T *__restrict__ ds, int32_t *__restrict__ rlist,
+    DevState *__restrict__ st, pamx_swap_record *__restrict__ trace) {
     using A = AccT<T>;
     if (st->done) return;
     A v = VT<T>::acc_inf();
     int i = INT_MAX, c = INT_MAX;
-    for (int w = threadIdx.x; w < nwg; w += 1024)
+    for (int w = threadIdx.x; w < nwg; w += 256)
         if (lex_less(wg_v[w], wg_i[w], wg_c[w], v, i, c)) { v = wg_v[w]; i = wg_i[w]; c = wg_c[w]; }
-    block_argmin3<A, 1024>(v, i, c);
-    if (threadIdx.x != 0) return;
-    st->iter += 1;
-    st->best_i = i;
-    st->best_c = c;
-    if constexpr (std::is_same<T, float>::value) st->best_v = v; else { st->best_vi = v; st->best_v = (double)v; }
+    block_argmin3<A, 256>(v, i, c);
     bool apply;
     if constexpr (std::is_same<T, float>::value) apply = (c != INT_MAX) && (v < -st->margin);
     else apply = (c != INT_MAX) && (v < 0);
-    if (!apply) {
-        st->done = 1;
-        st->swapped = 0;
-        return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->iter += 1;
+        st->best_i = i;
+        st->best_c = c;
+        if constexpr (std::is_same<T, float>::value) st->best_v = v;
+        else { st->best_vi = v; st->best_v = (double)v; }
+        if (!apply) {
+            st->done = 1;
+            st->swapped = 0;
+        } else {
+            const int old = med[i];
+            is_med[old] = 0;
+            is_med[c] = 1;
+            med[i] = c;
+            st->old_med = old;
+            st->new_slot = i;
+            st->new_med = c;
+            st->swapped = 1;
+            if constexpr (std::is_same<T, float>::value) st->td += v;
+            else { st->td_i += v; st->td = (double)st->td_i; }
+            if (trace && st->swaps < st->trace_cap) trace[st->swaps] = pamx_swap_record{i, c, (double)v};
+            st->swaps += 1;
+        }
     }
-    const int old = med[i];
-    is_med[old] = 0;
-    is_med[c] = 1;
-    med[i] = c;
-    st->old_med = old;
-    st->new_slot = i;
-    st->new_med = c;
-    st->swapped = 1;
-    if constexpr (std::is_same<T, float>::value) st->td += v; else { st->td_i += v; st->td = (double)st->td_i; }
-    if (trace && st->swaps < st->trace_cap) trace[st->swaps] = pamx_swap_record{i, c, (double)v};
-    st->swaps += 1;
+    if (!apply) return;
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= n) return;
+    const T dnew = D[(int64_t)c * ld + o];
+    int32_t nr = near[o], sc = sec[o];
+    T a = dn[o], b = ds[o];
+    if (cache_update_o1<T>(i, dnew, nr, sc, a, b)) {
+        rlist[atomicAdd(&st->n_list, 1)] = (int32_t)o;
+    } else {
+        near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b;
+    }
 }
 
 // ---- FastPAM2: best candidate of every slot, (value, candidate) order.
@@ -1075,7 +1064,7 @@ struct SwapPtrs {
     int32_t *near, *sec, *srow, *blkcnt, *seg_off, *part_i, *wg_i, *wg_c, *slot_c, *order, *rlist;
     T *dn, *ds, *sdn, *sds;
     uint8_t *is_med;
-    AccT<T> *segc, *part, *wg_v, *P, *cand_a, *slot_v;
+    AccT<T> *cdn, *part, *wg_v, *P, *cand_a, *slot_v;
     ChunkInfo *cinfo;
     DevState *st;
 };
@@ -1095,7 +1084,7 @@ static SwapPtrs<T> ptrs(const Layout &L, void *ws) {
     p.blkcnt = reinterpret_cast<int32_t *>(w + L.blkcnt);
     p.seg_off = reinterpret_cast<int32_t *>(w + L.seg_off);
     p.cinfo = reinterpret_cast<ChunkInfo *>(w + L.blkbase);
-    p.segc = reinterpret_cast<AccT<T> *>(w + L.segc);
+    p.cdn = reinterpret_cast<AccT<T> *>(w + L.cdn);
     p.part = reinterpret_cast<AccT<T> *>(w + L.part);
     p.part_i = reinterpret_cast<int32_t *>(w + L.part_i);
     p.cand_a = reinterpret_cast<AccT<T> *>(w + L.cand_a);
@@ -1158,14 +1147,12 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
                        (const int32_t *)p.near, (const T *)p.dn, (const T *)p.ds, n, k,
                        (const int32_t *)p.blkcnt, (const int32_t *)p.seg_off, p.srow, p.sdn,
                        p.sds, (const DevState *)p.st);
-    hipLaunchKernelGGL(k_seg_const<T>, dim3((k + 3) / 4), dim3(256), 0, s, (const T *)p.sdn,
-                       (const int32_t *)p.seg_off, k, p.segc, (const DevState *)p.st);
     const dim3 pgrid(L.n_ctiles, L.Q);
     if (ev0) (void)hipEventRecord(ev0, s);
 #define PAMX_PASS(VEC, P2)                                                                    \
     hipLaunchKernelGGL((k_swap_pass<T, VEC, P2>), pgrid, dim3(kWG), 0, s, D, ld, n, k,       \
                        (const int32_t *)p.srow, (const T *)p.sdn, (const T *)p.sds,           \
-                       (const int32_t *)p.seg_off, (const A *)p.segc,                         \
+                       (const int32_t *)p.seg_off, p.cdn,                                     \
                        (const ChunkInfo *)p.cinfo, L.L, L.ncp, p.part, p.part_i, p.P,         \
                        (const DevState *)p.st)
     if (L.vec == 4) { if (p2) PAMX_PASS(4, true); else PAMX_PASS(4, false); }
@@ -1175,7 +1162,7 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
     if (p2) {
         hipLaunchKernelGGL((k_swap_merge<T, true>), dim3(L.n_mwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
-                           L.Q, n, k, L.ncp, (const A *)p.segc, (const uint8_t *)p.is_med,
+                           L.Q, n, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
                            (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
         hipLaunchKernelGGL(k_slot_best<T>, dim3(k), dim3(256), 0, s, (const A *)p.P,
                            (const A *)p.cand_a, (const int32_t *)p.seg_off, n, L.ncp,
@@ -1186,13 +1173,11 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
     } else {
         hipLaunchKernelGGL((k_swap_merge<T, false>), dim3(L.n_mwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
-                           L.Q, n, k, L.ncp, (const A *)p.segc, (const uint8_t *)p.is_med,
+                           L.Q, n, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
                            (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
-        hipLaunchKernelGGL(k_swap_select<T>, dim3(1), dim3(1024), 0, s, (const A *)p.wg_v,
-                           (const int32_t *)p.wg_i, (const int32_t *)p.wg_c, L.n_mwg, medoids,
-                           p.is_med, p.st, trace);
-        hipLaunchKernelGGL(k_cache_update<T>, dim3(ob), dim3(256), 0, s, D, ld, n, p.near, p.sec,
-                           p.dn, p.ds, p.rlist, p.st);
+        hipLaunchKernelGGL(k_select_update<T>, dim3(ob), dim3(256), 0, s, (const A *)p.wg_v,
+                           (const int32_t *)p.wg_i, (const int32_t *)p.wg_c, L.n_mwg, D, ld, n,
+                           medoids, p.is_med, p.near, p.sec, p.dn, p.ds, p.rlist, p.st, trace);
         hipLaunchKernelGGL(k_cache_rescan<T>, dim3(256), dim3(256), 0, s, D, ld, k,
                            (const int32_t *)medoids, p.near, p.sec, p.dn, p.ds,
                            (const int32_t *)p.rlist, (const DevState *)p.st);
