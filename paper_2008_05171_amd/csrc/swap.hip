@@ -613,35 +613,56 @@ __global__ __launch_bounds__(1024) void k_seg_scan(int32_t k, int64_t n, int32_t
     using A = AccT<T>;
     if (st->done) return;
     extern __shared__ int32_t soff[];    // k + 1 offsets
-    __shared__ int32_t carry;
+    __shared__ int32_t wsum[16];
+    __shared__ A ws1[16], ws2[16];
     __shared__ int32_t empty_min;
-    __shared__ int32_t buf[1024];
-    const int t = threadIdx.x;
-    if (t == 0) { carry = 0; empty_min = k; soff[0] = 0; }
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t == 0) { empty_min = k; soff[0] = 0; }
     __syncthreads();
+    // segment offsets: wave scans of the slot totals, then the wave totals
+    int32_t carry = 0;
     for (int base = 0; base < k; base += 1024) {
         const int i = base + t;
         const int32_t v = (i < k) ? seg_off[i + 1] : 0;
         if (i < k && v == 0) atomicMin(&empty_min, i);
-        buf[t] = v;
-        __syncthreads();
-        for (int w = 1; w < 1024; w <<= 1) {
-            const int32_t x = (t >= w) ? buf[t - w] : 0;
-            __syncthreads();
-            buf[t] += x;
-            __syncthreads();
+        int32_t x = v;   // inclusive wave scan
+        for (int w = 1; w < 64; w <<= 1) {
+            const int32_t y = __shfl_up(x, w);
+            if (lane >= w) x += y;
         }
-        if (i < k) soff[i + 1] = carry + buf[t];   // inclusive
+        if (lane == 63) wsum[wv] = x;
         __syncthreads();
-        if (t == 1023) carry += buf[1023];
+        int32_t off = carry, tot = 0;
+        for (int u = 0; u < 16; ++u) {
+            const int32_t c = wsum[u];
+            if (u < wv) off += c;
+            tot += c;
+        }
+        if (i < k) soff[i + 1] = off + x;
+        carry += tot;
         __syncthreads();
     }
     for (int i = t; i <= k; i += 1024) seg_off[i] = soff[i];
-    // TD and sum of ds, fixed order
+    // TD and sum of ds, fixed order (four loads in flight per thread, wave
+    // butterflies, then the 16 wave sums in order)
     A s1 = 0, s2 = 0;
-    for (int64_t o = t; o < n; o += 1024) { s1 += (A)dn[o]; s2 += (A)ds[o]; }
-    s1 = block_sum<A, 1024>(s1);
-    s2 = block_sum<A, 1024>(s2);
+    int64_t o = t;
+    for (; o + 3 * 1024 < n; o += 4 * 1024) {
+        T a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { a[u] = dn[o + u * 1024]; b[u] = ds[o + u * 1024]; }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { s1 += (A)a[u]; s2 += (A)b[u]; }
+    }
+    for (; o < n; o += 1024) { s1 += (A)dn[o]; s2 += (A)ds[o]; }
+    s1 = wave_sum<A>(s1);
+    s2 = wave_sum<A>(s2);
+    if (lane == 0) { ws1[wv] = s1; ws2[wv] = s2; }
+    __syncthreads();
+    if (t == 0) {
+        s1 = 0; s2 = 0;
+        for (int u = 0; u < 16; ++u) { s1 += ws1[u]; s2 += ws2[u]; }
+    }
     // carry map of each chunk (binary searches in LDS)
     for (int q = t; q < Q; q += 1024) {
         const int64_t a = (int64_t)q * L, b = min(a + (int64_t)L, n);
@@ -830,7 +851,7 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
                 if constexpr (P2) P[(int64_t)run_s * ncp + c] = v;
             }
         };
-        constexpr int UQ = 4;   // chunks whose partials are loaded together
+        constexpr int UQ = 8;   // chunks whose partials are loaded together
         for (int q0 = 0; q0 < Q; q0 += UQ) {
             A xa[UQ], xh[UQ], xt[UQ], xv[UQ];
             int32_t xi[UQ];
