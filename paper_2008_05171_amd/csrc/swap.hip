@@ -123,43 +123,6 @@ __global__ __launch_bounds__(kWG) void k_build_pass(const T *__restrict__ D, int
     for (int e = 0; e < VEC; ++e) dst[e] = acc[e];
 }
 
-// Pick the step's medoid: the smallest change, smallest index on ties.
-template <typename T>
-__global__ __launch_bounds__(1024) void k_build_select(const AccT<T> *__restrict__ wg_v,
-                                                       const int32_t *__restrict__ wg_c, int32_t nwg,
-                                                       int32_t t, int32_t *__restrict__ medoids,
-                                                       uint8_t *__restrict__ is_med,
-                                                       DevState *__restrict__ st) {
-    using A = AccT<T>;
-    A v = VT<T>::acc_inf();
-    int c = INT_MAX, dummy = 0;
-    for (int w = threadIdx.x; w < nwg; w += 1024) {
-        if (lex_less(wg_v[w], 0, wg_c[w], v, 0, c)) { v = wg_v[w]; c = wg_c[w]; }
-    }
-    block_argmin3<A, 1024>(v, dummy, c);
-    if (threadIdx.x == 0) {
-        st->best_c = c;
-        if (c != INT_MAX) {
-            medoids[t] = c;
-            is_med[c] = 1;
-        } else {
-            st->bad_medoids = 1;  // no candidate left (cannot happen for k <= n)
-        }
-    }
-}
-
-// dn(o) <- min(dn(o), d(o, m_t)), reading row m_t (= column m_t).
-template <typename T>
-__global__ __launch_bounds__(256) void k_build_update(const T *__restrict__ D, int64_t ld, int64_t n,
-                                                      T *__restrict__ dn, const DevState *__restrict__ st,
-                                                      int32_t first) {
-    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int c = st->best_c;
-    if (o >= n || c == INT_MAX) return;
-    const T d = D[(int64_t)c * ld + o];
-    dn[o] = first ? d : vmin(dn[o], d);
-}
-
 // ---- incremental BUILD.  Adding m_t lowers dn only for the objects closer
 // to m_t than to every earlier medoid, and
 //   A_t(c) - A_{t-1}(c) = sum over those objects of min(d, dn_new) - min(d, dn_old),
@@ -168,25 +131,47 @@ __global__ __launch_bounds__(256) void k_build_update(const T *__restrict__ D, i
 // sums are exact for int32 matrices; for FP32 the per-object differences are
 // exact in FP64 and only their sum rounds.
 
+// The step's medoid (every block reduces the merge partials itself: the
+// smallest change, smallest index on ties; block 0 records it), then
 // dn2 = min(dn, row m_t) and, per block of kObjBlk objects, how many dropped.
-template <typename T>
-__global__ __launch_bounds__(kObjBlk) void k_build_update2(const T *__restrict__ D, int64_t ld,
-                                                           int64_t n, const T *__restrict__ dn,
-                                                           T *__restrict__ dn2,
-                                                           const DevState *__restrict__ st,
-                                                           int32_t *__restrict__ blkcnt) {
+// FIRST: step 0, dn2 = row m_t (dn is +inf), no counts needed.
+template <typename T, bool FIRST>
+__global__ __launch_bounds__(kObjBlk) void k_build_select_update(
+    const AccT<T> *__restrict__ wg_v, const int32_t *__restrict__ wg_c, int32_t nwg, int32_t t,
+    int32_t *__restrict__ medoids, uint8_t *__restrict__ is_med, const T *__restrict__ D,
+    int64_t ld, int64_t n, const T *__restrict__ dn, T *__restrict__ dn2,
+    DevState *__restrict__ st, int32_t *__restrict__ blkcnt) {
+    using A = AccT<T>;
+    A v = VT<T>::acc_inf();
+    int c = INT_MAX, dummy = 0;
+    for (int w = threadIdx.x; w < nwg; w += kObjBlk)
+        if (lex_less(wg_v[w], 0, wg_c[w], v, 0, c)) { v = wg_v[w]; c = wg_c[w]; }
+    block_argmin3<A, kObjBlk>(v, dummy, c);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->best_c = c;
+        if (c != INT_MAX) {
+            medoids[t] = c;
+            is_med[c] = 1;
+        } else {
+            st->bad_medoids = 1;  // no candidate left (cannot happen for k <= n)
+        }
+    }
     const int64_t o = (int64_t)blockIdx.x * kObjBlk + threadIdx.x;
-    const int c = st->best_c;
     int chg = 0;
     if (o < n) {
         const T old = dn[o];
         T nw = old;
-        if (c != INT_MAX) nw = vmin(old, D[(int64_t)c * ld + o]);
+        if (c != INT_MAX) {
+            const T d = D[(int64_t)c * ld + o];
+            nw = FIRST ? d : vmin(old, d);
+        }
         dn2[o] = nw;
         chg = nw < old;
     }
-    const int cnt = __syncthreads_count(chg);
-    if (threadIdx.x == 0) blkcnt[blockIdx.x] = cnt;
+    if constexpr (!FIRST) {
+        const int cnt = __syncthreads_count(chg);
+        if (threadIdx.x == 0) blkcnt[blockIdx.x] = cnt;
+    }
 }
 
 // Stable list of the objects whose dn dropped (ascending object order), with
@@ -282,7 +267,7 @@ __global__ __launch_bounds__(kWG) void k_build_delta(const T *__restrict__ D, in
 }
 
 // A(c) <- A(c) + sum of the chunk deltas (chunk order), then the work-group's
-// best (value, candidate) among non-medoids, as k_build_merge.
+// best (value, candidate) among non-medoids.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_build_dmerge(const AccT<T> *__restrict__ part, int32_t Q,
                                                       int64_t ncp, int64_t n, AccT<T> *__restrict__ acur,
@@ -394,16 +379,15 @@ hipError_t run_build(const T *D, int64_t ld, const Layout &L, int32_t k, int32_t
         hipLaunchKernelGGL(k_build_dmerge<T>, dim3(L.n_mwg), dim3(kWG), 0, s, (const A *)part,
                            L.Q, L.ncp, n, acur, dn, (const uint8_t *)is_med,
                            (int32_t)(exclude_self && t > 0), wg_v, wg_c);
-        hipLaunchKernelGGL(k_build_select<T>, dim3(1), dim3(1024), 0, s, (const A *)wg_v,
-                           (const int32_t *)wg_c, L.n_mwg, t, medoids, is_med, st);
-        if (t == 0) {
-            hipLaunchKernelGGL(k_build_update<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                               D, ld, n, dnb[cur], (const DevState *)st, (int32_t)1);
-        } else {
-            hipLaunchKernelGGL(k_build_update2<T>, dim3(nblk), dim3(kObjBlk), 0, s, D, ld, n, dn,
-                               dnb[cur ^ 1], (const DevState *)st, blkcnt);
-            cur ^= 1;
-        }
+        if (t == 0)   // dn is +inf: the new dn is the medoid's row
+            hipLaunchKernelGGL((k_build_select_update<T, true>), dim3(nblk), dim3(kObjBlk), 0, s,
+                               (const A *)wg_v, (const int32_t *)wg_c, L.n_mwg, t, medoids, is_med,
+                               D, ld, n, dn, dnb[cur ^ 1], st, blkcnt);
+        else
+            hipLaunchKernelGGL((k_build_select_update<T, false>), dim3(nblk), dim3(kObjBlk), 0, s,
+                               (const A *)wg_v, (const int32_t *)wg_c, L.n_mwg, t, medoids, is_med,
+                               D, ld, n, dn, dnb[cur ^ 1], st, blkcnt);
+        cur ^= 1;
     }
     if (cur == 1)   // leave the final dn where the caches expect it
         hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
