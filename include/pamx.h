@@ -86,6 +86,11 @@ extern "C" {
                               the decisions of FP64 arithmetic.
                               FastPAM1 only; dim <= 64, k <= 4096.            */
 
+/* pamx_options.chunk: time the SWAP pass for several chunk lengths on the
+ * caller's matrix (after BUILD, with its medoids) and keep the fastest; the
+ * workspace must then be sized with the same option. */
+#define PAMX_CHUNK_TUNE (-1)
+
 /* return codes */
 #define PAMX_OK 0
 #define PAMX_WARN_MAXITER 1
@@ -104,7 +109,10 @@ typedef struct pamx_options {
                                    adds the point that lowers TD most; 1: the
                                    literal loop bounds of Alg. 1 (x_c skipped) */
     int32_t trace_cap;          /* capacity of `trace` in records (0: none)   */
-    int32_t chunk;              /* objects per pass work-group; 0 = automatic */
+    int32_t chunk;              /* objects per pass work-group; 0 = automatic,
+                                   PAMX_CHUNK_TUNE = timed on the first call for
+                                   this device and shape (stored matrix), then
+                                   reused for the life of the process         */
     int32_t profile;            /* 1: time every BUILD / SWAP pass kernel with
                                    HIP events on `stream` (pamx_stats)       */
     int32_t dist_mode;          /* PAMX_DIST_STORED (default) or PAMX_DIST_BF16 */
@@ -138,7 +146,7 @@ typedef struct pamx_stats {
                               passes (stored matrix, steps 3..k) */
     int64_t build_rows;    /* matrix rows read by the incremental BUILD passes */
     int32_t n_build_delta; /* profile=1: incremental BUILD pass launches */
-    int32_t reserved;
+    int32_t chunk;         /* object chunk length of the SWAP passes */
 } pamx_stats;
 
 /* Fills `opt` with the defaults listed above. */

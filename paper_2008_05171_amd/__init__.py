@@ -12,12 +12,13 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 
 from . import pamx as _abi
-from .pamx import (PAMX_ACC_F32, PAMX_ACC_F64, PAMX_DIST_BF16, PAMX_DIST_STORED, PAMX_FASTPAM1,
+from .pamx import (PAMX_ACC_F32, PAMX_ACC_F64, PAMX_CHUNK_TUNE, PAMX_DIST_BF16, PAMX_DIST_STORED,
+                   PAMX_FASTPAM1,
                    PAMX_FASTPAM2, PAMX_INPUT_D, PAMX_INPUT_X, PAMX_L1, PAMX_L2, PamxError)
 
 __all__ = ["fit", "build", "swap", "dist", "fit_batched", "FitResult", "BatchResult", "PamxError", "PAMX_FASTPAM1",
            "PAMX_FASTPAM2", "PAMX_L1", "PAMX_L2", "PAMX_ACC_F64", "PAMX_ACC_F32",
-           "PAMX_INPUT_D", "PAMX_INPUT_X"]
+           "PAMX_INPUT_D", "PAMX_INPUT_X", "PAMX_CHUNK_TUNE"]
 
 _VARIANTS = {"fastpam1": PAMX_FASTPAM1, "fastpam2": PAMX_FASTPAM2,
              PAMX_FASTPAM1: PAMX_FASTPAM1, PAMX_FASTPAM2: PAMX_FASTPAM2}
@@ -79,7 +80,9 @@ def fit(data, k, *, input_kind=PAMX_INPUT_X, metric=None, variant="fastpam1",
     data: device tensor, n x dim points (int32 -> L1, float32 -> L2) or an
     n x n dissimilarity matrix with input_kind=PAMX_INPUT_D.
     dist_mode="bf16": the mixed-precision form (no matrix; BF16 Gram
-    distances, FP32 sums, FP64 re-scoring of every possible best swap)."""
+    distances, FP32 sums, FP64 re-scoring of every possible best swap).
+    chunk: objects per pass work-group, 0 = automatic, PAMX_CHUNK_TUNE = timed
+    once per process and shape on this matrix (stats["chunk"] reports it)."""
     import torch
     n = data.shape[0]
     dim = data.shape[1] if input_kind == PAMX_INPUT_X else 0

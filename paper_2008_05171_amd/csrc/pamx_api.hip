@@ -7,7 +7,10 @@
 #include <cstring>
 #include <type_traits>
 #include <algorithm>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "pamx_internal.h"
@@ -108,11 +111,7 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->sdn = take((size_t)n * 4);
     L->sds = take((size_t)n * 4);
     L->blkcnt = take((size_t)L->n_oblk * k * 4);
-    L->blkbase = take((size_t)L->Q * 16);            // chunk carry map
     L->seg_off = take((size_t)(k + 1) * 4);
-    L->cdn = take((size_t)L->Q * 2 * 8);              // DN parts of carried segments
-    L->part = take((size_t)L->Q * 4 * L->ncp * 8);
-    L->part_i = take((size_t)L->Q * L->ncp * 4);
     L->cand_v = take(8);
     L->cand_i = take(8);
     L->cand_a = take((size_t)L->ncp * 8);
@@ -127,8 +126,56 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->list_i = take(8);
     L->rlist = take((size_t)n * 4);
     L->state = take(sizeof(DevState));
-    L->total = off;
+    L->head = off;
+    set_chunk(L, L->L);
     return PAMX_OK;
+}
+
+// The regions whose size depends on the number of object chunks Q come last,
+// so the chunk length can change between BUILD and SWAP (chunk tuning).
+void set_chunk(Layout *L, int32_t Lc) {
+    if (Lc > L->n) Lc = (int32_t)L->n;
+    if (Lc < 1) Lc = 1;
+    L->L = Lc;
+    L->Q = (int32_t)((L->n + Lc - 1) / Lc);
+    size_t off = L->head;
+    auto take = [&](size_t bytes) { size_t o = off; off = up256(off + (bytes ? bytes : 1)); return o; };
+    L->blkbase = take((size_t)L->Q * 16);            // chunk carry map
+    L->cdn = take((size_t)L->Q * 2 * 8);              // DN parts of carried segments
+    L->part = take((size_t)L->Q * 4 * L->ncp * 8);
+    L->part_i = take((size_t)L->Q * L->ncp * 4);
+    L->total = off;
+}
+
+// Chunk lengths tried by the tuner: pass grids at or just below about 1, 1.5,
+// 2, 3, 4, 6 and 8 work-groups per compute unit.
+std::vector<int32_t> tune_chunks(const Layout &L) {
+    static const int grid[] = {256, 384, 512, 768, 1024, 1536, 2048};
+    const int64_t qmax = (L.n + 63) / 64;
+    std::vector<int32_t> out;
+    for (int g : grid) {
+        int64_t Q = g / L.n_ctiles;
+        if (Q > qmax) Q = qmax;
+        if (Q < 1) Q = 1;
+        int64_t Lc = (L.n + Q - 1) / Q;
+        Lc = (Lc + 7) & ~int64_t(7);
+        if (Lc > L.n) Lc = L.n;
+        if (std::find(out.begin(), out.end(), (int32_t)Lc) == out.end()) out.push_back((int32_t)Lc);
+    }
+    return out;
+}
+
+// Workspace bytes for L: with chunk tuning, the largest tail over the chunk
+// lengths the tuner may pick.
+size_t layout_need(const Layout &L, const pamx_options *opt) {
+    if (!opt || opt->chunk >= 0) return L.total;
+    size_t need = L.total;
+    for (int32_t Lc : tune_chunks(L)) {
+        Layout T = L;
+        set_chunk(&T, Lc);
+        if (T.total > need) need = T.total;
+    }
+    return need;
 }
 
 int make_rc_layout(int64_t n, int32_t k, int32_t dim, const pamx_options *opt, RcLayout *R) {
@@ -226,7 +273,8 @@ static int check_common(int64_t n, int32_t k, int32_t dtype, const pamx_options 
             return fail(PAMX_ERR_UNSUPPORTED, "accum PAMX_ACC_F32 is available with PAMX_DIST_BF16 only");
         if (opt->max_iter < 0) return fail(PAMX_ERR_ARG, "max_iter must be >= 0");
         if (opt->trace_cap < 0) return fail(PAMX_ERR_ARG, "trace_cap must be >= 0");
-        if (opt->chunk < 0) return fail(PAMX_ERR_ARG, "chunk must be >= 0");
+        if (opt->chunk < PAMX_CHUNK_TUNE)
+            return fail(PAMX_ERR_ARG, "chunk must be >= 0, or PAMX_CHUNK_TUNE");
         if (opt->build_exclude_self != 0 && opt->build_exclude_self != 1)
             return fail(PAMX_ERR_ARG, "build_exclude_self must be 0 or 1");
         if (opt->dist_mode != PAMX_DIST_STORED && opt->dist_mode != PAMX_DIST_BF16)
@@ -254,12 +302,13 @@ static int check_matrix(const void *D, int64_t n, int64_t ld) {
     return PAMX_OK;
 }
 
-static int check_ws(void *ws, size_t ws_bytes, const Layout &L) {
+static int check_ws(void *ws, size_t ws_bytes, const Layout &L, const pamx_options *opt) {
     if (!ws) return fail(PAMX_ERR_WORKSPACE, "workspace is NULL");
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
         return fail(PAMX_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-    if (ws_bytes < L.total)
-        return fail(PAMX_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    const size_t need = layout_need(L, opt);
+    if (ws_bytes < need)
+        return fail(PAMX_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
     return PAMX_OK;
 }
 
@@ -283,9 +332,10 @@ extern "C" int pamx_workspace_bytes(int64_t n, int32_t k, int32_t dim, int32_t i
     // the pass tiling depends on ld and on the matrix alignment: take the
     // larger of the 16-byte-load and scalar-load layouts
     make_layout(n, k, dim, input_kind, dtype, (n + 3) & ~int64_t(3), opt, &L, nullptr);
-    size_t b4 = L.total;
+    const size_t b4 = layout_need(L, opt);
     make_layout(n, k, dim, input_kind, dtype, (n % 4) ? n : n + 1, opt, &L, nullptr);
-    *bytes = b4 > L.total ? b4 : L.total;
+    const size_t b1 = layout_need(L, opt);
+    *bytes = b4 > b1 ? b4 : b1;
     return PAMX_OK;
 }
 
@@ -420,10 +470,61 @@ int build_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const pamx_op
     return PAMX_OK;
 }
 
+// ---- chunk tuning: the fastest chunk length per (device, shape), timed
+// once per process on the caller's matrix and kept for later calls.
+struct TuneKey {
+    int dev;
+    int64_t n, ld;
+    int32_t k, dtype, vec, variant;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(dev, n, ld, k, dtype, vec, variant) <
+               std::tie(o.dev, o.n, o.ld, o.k, o.dtype, o.vec, o.variant);
+    }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int32_t> g_tuned;
+
 template <typename T>
-int swap_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const pamx_options &opt,
+static int tune_chunk(const T *D, int64_t ld, Layout *L, const pamx_options &opt, void *ws,
+                      hipStream_t s) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    const TuneKey key{dev, L->n, ld, L->k, L->dtype, L->vec, opt.variant};
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) { set_chunk(L, it->second); return PAMX_OK; }
+    }
+    constexpr int kReps = 3;
+    EventPool pool(2 * kReps);
+    if (!pool.ok()) return fail(PAMX_ERR_HIP, "hipEventCreate failed");
+    int32_t best = L->L;
+    double best_ms = 1e300;
+    for (int32_t Lc : tune_chunks(*L)) {
+        Layout Tl = *L;
+        set_chunk(&Tl, Lc);
+        HIP_TRY(enqueue_tune_passes<T>(D, ld, Tl, opt, ws, s, pool.ev.data(), kReps));
+        HIP_TRY(hipStreamSynchronize(s));
+        double t = 1e300;
+        for (int r = 0; r < kReps; ++r) {
+            const double v = pool.sum(r, r + 1);
+            if (v < t) t = v;
+        }
+        if (t < best_ms) { best_ms = t; best = Lc; }
+    }
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tuned[key] = best;
+    }
+    set_chunk(L, best);
+    return PAMX_OK;
+}
+
+template <typename T>
+int swap_impl(const T *D, int64_t ld, const Layout &L_in, int32_t k, const pamx_options &opt,
               int32_t *medoids, int32_t *labels, double *td, pamx_stats *stats, void *ws,
               hipStream_t s, Timer &tm) {
+    Layout L = L_in;
     const int64_t n = L.n;
     HIP_TRY(enqueue_swap_init<T>(D, ld, L, medoids, opt, ws, s));
     DevState st;
@@ -431,18 +532,23 @@ int swap_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const pamx_opt
     if (rc) return rc;
     if (st.bad_medoids)
         return fail(PAMX_ERR_INVALID_MEDOIDS, "medoids must be distinct and in [0, n)");
+    const bool searches = k >= 2 && k < n;
+    if (searches) HIP_TRY(enqueue_swap_caches<T>(D, ld, L, medoids, ws, s));
+    if (searches && opt.chunk == PAMX_CHUNK_TUNE && opt.max_iter > 0) {
+        rc = tune_chunk<T>(D, ld, &L, opt, ws, s);
+        if (rc) return rc;
+    }
     tm.rec(2, s);
     int enq = 0;
     double ms_pass = 0.0;
     int n_pass = 0;
-    if (k >= 2 && k < n) {
+    if (searches) {
         constexpr int kMaxBatch = 32;
         std::unique_ptr<EventPool> pool;
         if (opt.profile) {
             pool.reset(new EventPool(2 * kMaxBatch));
             if (!pool->ok()) return fail(PAMX_ERR_HIP, "hipEventCreate failed");
         }
-        HIP_TRY(enqueue_swap_caches<T>(D, ld, L, medoids, ws, s));
         int batch = 4;
         for (;;) {
             int b = batch;
@@ -480,6 +586,7 @@ int swap_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const pamx_opt
         stats->pass_pairs = (int64_t)st.iter * n * (n - k);
         stats->ms_swap_pass = ms_pass;
         stats->n_swap_pass = n_pass;
+        stats->chunk = L.L;
     }
     return st.capped ? PAMX_WARN_MAXITER : PAMX_OK;
 }
@@ -599,7 +706,7 @@ extern "C" int pamx_build(const void *D, int32_t dtype, int64_t n, int64_t ld, i
     if (rc) return rc;
     Layout L;
     make_layout(n, k, 0, PAMX_INPUT_D, dtype, ld, &opt, &L, D);
-    rc = check_ws(ws, ws_bytes, L);
+    rc = check_ws(ws, ws_bytes, L, &opt);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (dtype == PAMX_F32)
@@ -619,7 +726,7 @@ extern "C" int pamx_swap(const void *D, int32_t dtype, int64_t n, int64_t ld, in
     if (rc) return rc;
     Layout L;
     make_layout(n, k, 0, PAMX_INPUT_D, dtype, ld, &opt, &L, D);
-    rc = check_ws(ws, ws_bytes, L);
+    rc = check_ws(ws, ws_bytes, L, &opt);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (stats) std::memset(stats, 0, sizeof(*stats));
@@ -670,7 +777,7 @@ extern "C" int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int
     Layout L;
     make_layout(n, k, dim, input_kind, dtype, n, &opt, &L,
                 input_kind == PAMX_INPUT_D ? XorD : nullptr);
-    rc = check_ws(ws, ws_bytes, L);
+    rc = check_ws(ws, ws_bytes, L, &opt);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (stats) std::memset(stats, 0, sizeof(*stats));

@@ -169,6 +169,7 @@ struct Layout {
     size_t P, slot_v, slot_c;
     size_t list, list_v, list_i, rlist;
     size_t state;
+    size_t head;         // end of the regions that do not depend on the chunk length
     size_t total;
     int64_t ld_fit;      // row stride of the stored matrix in pamx_fit
 };
@@ -176,6 +177,8 @@ struct Layout {
 // host helpers (pamx_api.cpp)
 int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t dtype,
                 int64_t ld, const pamx_options *opt, Layout *L, const void *D);
+// re-place the chunk-dependent regions (after L->head) for chunk length Lc
+void set_chunk(Layout *L, int32_t Lc);
 
 // launchers (one per kernel family); each returns hipSuccess or an error.
 hipError_t launch_dist_l1_i32(const int32_t *X, int64_t n, int32_t dim, int32_t *D, int64_t ld,
@@ -244,6 +247,9 @@ template <typename T>
 hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32_t *medoids,
                                   const pamx_options &opt, void *ws, hipStream_t s,
                                   hipEvent_t ev0, hipEvent_t ev1);
+template <typename T>
+hipError_t enqueue_tune_passes(const T *D, int64_t ld, const Layout &L, const pamx_options &opt,
+                               void *ws, hipStream_t s, hipEvent_t *ev, int reps);
 template <typename T>
 hipError_t enqueue_finalize(const T *D, int64_t ld, const Layout &L, const int32_t *medoids,
                             int32_t *labels, void *ws, hipStream_t s);

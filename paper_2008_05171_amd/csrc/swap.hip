@@ -1130,6 +1130,55 @@ static hipError_t enqueue_caches(const T *D, int64_t ld, const Layout &L, const 
     return hipGetLastError();
 }
 
+// Objects sorted by nearest slot, segment offsets, chunk map (the chunk
+// map depends on the chunk length of L).
+template <typename T>
+static void enqueue_segments(const Layout &L, const SwapPtrs<T> &p, hipStream_t s) {
+    const int64_t n = L.n;
+    const int32_t k = L.k;
+    hipLaunchKernelGGL(k_seg_count, dim3(L.n_oblk), dim3(kObjBlk), (size_t)k * 4, s,
+                       (const int32_t *)p.near, n, k, p.blkcnt, p.st);
+    hipLaunchKernelGGL(k_seg_colscan, dim3((k + 3) / 4), dim3(256), 0, s, p.blkcnt, L.n_oblk, k,
+                       p.seg_off + 1, (const DevState *)p.st);
+    hipLaunchKernelGGL(k_seg_scan<T>, dim3(1), dim3(1024), (size_t)(k + 1) * 4, s, k, n,
+                       p.seg_off, (const T *)p.dn, (const T *)p.ds, L.L, L.Q, p.cinfo, p.st);
+    hipLaunchKernelGGL(k_seg_scatter<T>, dim3(L.n_oblk), dim3(kObjBlk), 0, s,
+                       (const int32_t *)p.near, (const T *)p.dn, (const T *)p.ds, n, k,
+                       (const int32_t *)p.blkcnt, (const int32_t *)p.seg_off, p.srow, p.sdn,
+                       p.sds, (const DevState *)p.st);
+}
+
+template <typename T>
+static void enqueue_pass(const T *D, int64_t ld, const Layout &L, const SwapPtrs<T> &p, bool p2,
+                         hipStream_t s) {
+    const dim3 pgrid(L.n_ctiles, L.Q);
+#define PAMX_PASS(VEC, P2)                                                                    \
+    hipLaunchKernelGGL((k_swap_pass<T, VEC, P2>), pgrid, dim3(kWG), 0, s, D, ld, L.n, L.k,   \
+                       (const int32_t *)p.srow, (const T *)p.sdn, (const T *)p.sds,           \
+                       (const int32_t *)p.seg_off, p.cdn,                                     \
+                       (const ChunkInfo *)p.cinfo, L.L, L.ncp, p.part, p.part_i, p.P,         \
+                       (const DevState *)p.st)
+    if (L.vec == 4) { if (p2) PAMX_PASS(4, true); else PAMX_PASS(4, false); }
+    else { if (p2) PAMX_PASS(1, true); else PAMX_PASS(1, false); }
+#undef PAMX_PASS
+}
+
+// Chunk tuning: the segments for L's chunk length, then `reps` SWAP passes,
+// each between events ev[2r] and ev[2r+1].  The passes change no state that
+// the next search reads (their partials are recomputed by every search).
+template <typename T>
+hipError_t enqueue_tune_passes(const T *D, int64_t ld, const Layout &L, const pamx_options &opt,
+                               void *ws, hipStream_t s, hipEvent_t *ev, int reps) {
+    auto p = ptrs<T>(L, ws);
+    enqueue_segments<T>(L, p, s);
+    for (int r = 0; r < reps; ++r) {
+        (void)hipEventRecord(ev[2 * r], s);
+        enqueue_pass<T>(D, ld, L, p, opt.variant == PAMX_FASTPAM2, s);
+        (void)hipEventRecord(ev[2 * r + 1], s);
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32_t *medoids,
                                   const pamx_options &opt, void *ws, hipStream_t s,
@@ -1142,27 +1191,9 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
     pamx_swap_record *trace = static_cast<pamx_swap_record *>(opt.trace);
     const unsigned ob = (unsigned)((n + 255) / 256);
 
-    hipLaunchKernelGGL(k_seg_count, dim3(L.n_oblk), dim3(kObjBlk), (size_t)k * 4, s,
-                       (const int32_t *)p.near, n, k, p.blkcnt, p.st);
-    hipLaunchKernelGGL(k_seg_colscan, dim3((k + 3) / 4), dim3(256), 0, s, p.blkcnt, L.n_oblk, k,
-                       p.seg_off + 1, (const DevState *)p.st);
-    hipLaunchKernelGGL(k_seg_scan<T>, dim3(1), dim3(1024), (size_t)(k + 1) * 4, s, k, n,
-                       p.seg_off, (const T *)p.dn, (const T *)p.ds, L.L, L.Q, p.cinfo, p.st);
-    hipLaunchKernelGGL(k_seg_scatter<T>, dim3(L.n_oblk), dim3(kObjBlk), 0, s,
-                       (const int32_t *)p.near, (const T *)p.dn, (const T *)p.ds, n, k,
-                       (const int32_t *)p.blkcnt, (const int32_t *)p.seg_off, p.srow, p.sdn,
-                       p.sds, (const DevState *)p.st);
-    const dim3 pgrid(L.n_ctiles, L.Q);
+    enqueue_segments<T>(L, p, s);
     if (ev0) (void)hipEventRecord(ev0, s);
-#define PAMX_PASS(VEC, P2)                                                                    \
-    hipLaunchKernelGGL((k_swap_pass<T, VEC, P2>), pgrid, dim3(kWG), 0, s, D, ld, n, k,       \
-                       (const int32_t *)p.srow, (const T *)p.sdn, (const T *)p.sds,           \
-                       (const int32_t *)p.seg_off, p.cdn,                                     \
-                       (const ChunkInfo *)p.cinfo, L.L, L.ncp, p.part, p.part_i, p.P,         \
-                       (const DevState *)p.st)
-    if (L.vec == 4) { if (p2) PAMX_PASS(4, true); else PAMX_PASS(4, false); }
-    else { if (p2) PAMX_PASS(1, true); else PAMX_PASS(1, false); }
-#undef PAMX_PASS
+    enqueue_pass<T>(D, ld, L, p, p2, s);
     if (ev1) (void)hipEventRecord(ev1, s);
     if (p2) {
         hipLaunchKernelGGL((k_swap_merge<T, true>), dim3(L.n_mwg), dim3(kWG), 0, s,
@@ -1234,6 +1265,9 @@ hipError_t launch_segments_f32(const int32_t *near, const float *dn, const float
     template hipError_t enqueue_swap_iteration<T>(const T *, int64_t, const Layout &,          \
                                                   int32_t *, const pamx_options &, void *,     \
                                                   hipStream_t, hipEvent_t, hipEvent_t);        \
+    template hipError_t enqueue_tune_passes<T>(const T *, int64_t, const Layout &,             \
+                                               const pamx_options &, void *, hipStream_t,       \
+                                               hipEvent_t *, int);                             \
     template hipError_t enqueue_finalize<T>(const T *, int64_t, const Layout &,                \
                                             const int32_t *, int32_t *, void *, hipStream_t);  \
     template hipError_t enqueue_swap_caches<T>(const T *, int64_t, const Layout &,             \

@@ -19,6 +19,7 @@ PAMX_L1, PAMX_L2 = 1, 2
 PAMX_FASTPAM1, PAMX_FASTPAM2 = 1, 2
 PAMX_ACC_F64, PAMX_ACC_F32 = 0, 1
 PAMX_DIST_STORED, PAMX_DIST_BF16 = 0, 1
+PAMX_CHUNK_TUNE = -1
 PAMX_OK, PAMX_WARN_MAXITER = 0, 1
 PAMX_ERR_ARG, PAMX_ERR_WORKSPACE, PAMX_ERR_HIP = -1, -2, -3
 PAMX_ERR_INVALID_MEDOIDS, PAMX_ERR_UNSUPPORTED = -4, -5
@@ -46,7 +47,7 @@ class pamx_stats(ctypes.Structure):
                 ("ms_swap_pass", ctypes.c_double), ("ms_build_pass", ctypes.c_double),
                 ("n_swap_pass", ctypes.c_int32), ("n_build_pass", ctypes.c_int32),
                 ("ms_build_delta", ctypes.c_double), ("build_rows", ctypes.c_int64),
-                ("n_build_delta", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_build_delta", ctypes.c_int32), ("chunk", ctypes.c_int32)]
 
 
 class pamx_batch_stats(ctypes.Structure):

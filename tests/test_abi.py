@@ -100,6 +100,19 @@ def test_host_argument_errors_before_device_work(lib):
     assert _call_build(lib, fake, abi.PAMX_F32, 1 << 30, 1 << 40, 2, ws, 1 << 62) == abi.PAMX_ERR_ARG
 
 
+def test_chunk_tuning_option(lib):
+    """chunk = PAMX_CHUNK_TUNE is accepted and sizes the workspace for the
+    largest chunk count the tuner may pick; other negative values are errors."""
+    o = abi.pamx_default_options()
+    base = abi.pamx_workspace_bytes(20000, 100, 16, abi.PAMX_INPUT_X, abi.PAMX_F32, o)
+    o.chunk = abi.PAMX_CHUNK_TUNE
+    tuned = abi.pamx_workspace_bytes(20000, 100, 16, abi.PAMX_INPUT_X, abi.PAMX_F32, o)
+    assert tuned >= base
+    o.chunk = -2
+    with pytest.raises(abi.PamxError):
+        abi.pamx_workspace_bytes(20000, 100, 16, abi.PAMX_INPUT_X, abi.PAMX_F32, o)
+
+
 def test_points_metric_rules(lib):
     fake = ctypes.c_void_p(0x100000)
     rc = lib.pamx_dist(fake, abi.PAMX_I32, 10, 2, abi.PAMX_L2, fake, 12, None, 0, None)

@@ -119,6 +119,21 @@ def test_chunk_carries_do_not_change_results(chunk):
     _check_same(res, ref, 9)
 
 
+def test_chunk_tuning_keeps_results():
+    """Chunk tuning times the pass for several chunk lengths and keeps the
+    fastest; on integer distances every chunking gives the same sums, so the
+    run equals the oracle's, and a second call reuses the tuned length."""
+    _say("chunk_tune")
+    X, D = _int_case(4000, 41, hi=300)
+    ref = oracle.pam(12, D=D)
+    a = px().fit(_t(X), 12, trace=True, chunk=px().PAMX_CHUNK_TUNE)
+    _check_same(a, ref, 12)
+    b = px().fit(_t(X), 12, trace=True, chunk=px().PAMX_CHUNK_TUNE)
+    _check_same(b, ref, 12)
+    assert a.stats["chunk"] == b.stats["chunk"] > 0
+    print("tuned chunk", a.stats["chunk"], flush=True)
+
+
 def test_unaligned_leading_dimension():
     """n not a multiple of 4 with ld = n: the scalar-load pass variant."""
     _say("ld_unaligned")
