@@ -42,8 +42,9 @@ def log(*a):
 
 
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "swap_pass_gmm16_traffic.json")
-# the SWAP pass kernel, its launch shape (chunking) and the shared header
-KERNEL_SOURCES = ("swap.hip", "pamx_api.hip", "pamx_internal.h")
+# the SWAP pass kernel and the header it shares (its launch shape, the chunk
+# length, is recorded with the counters and compared with the timed fits')
+KERNEL_SOURCES = ("swap.hip", "pamx_internal.h")
 
 
 def kernel_sha256():
@@ -53,18 +54,20 @@ def kernel_sha256():
     return h.hexdigest()
 
 
-def traffic_from_profiles(n, k):
+def traffic_from_profiles(n, k, chunk):
     """HBM bytes per SWAP pass from committed rocprofv3 counter runs, or None
-    when the kernel sources changed since the counters were taken."""
+    when the kernel sources or the chunk length changed since the counters
+    were taken."""
     if not os.path.exists(TRAFFIC_JSON):
         return None
     rec = json.load(open(TRAFFIC_JSON))
-    if rec.get("src_sha256") != kernel_sha256() or rec.get("n") != n or rec.get("k") != k:
+    if (rec.get("src_sha256") != kernel_sha256() or rec.get("n") != n or rec.get("k") != k
+            or rec.get("chunk") != chunk):
         return None
     return float(rec["bytes_per_launch"])
 
 
-def write_traffic(fetch_csv, write_csv, probe_mib):
+def write_traffic(fetch_csv, write_csv, probe_mib, chunk):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
     dispatch) of `bench.py --copy-probe-mib M` into the traffic record read by
     traffic_from_profiles.  Each counter is scaled by what it reads for the
@@ -87,7 +90,7 @@ def write_traffic(fetch_csv, write_csv, probe_mib):
     pairs = [(a, b) for a, b in zip(f[key], w[key]) if a > 1024.0]
     fetch_kib = sum(a for a, _ in pairs) / len(pairs)
     write_kib = sum(b for _, b in pairs) / len(pairs)
-    rec = {"kernel": key, "n": N, "k": K, "src_sha256": kernel_sha256(),
+    rec = {"kernel": key, "n": N, "k": K, "chunk": chunk, "src_sha256": kernel_sha256(),
            "launches": len(pairs), "fetch_kib": fetch_kib, "write_kib": write_kib,
            "fetch_scale": fetch_scale, "write_scale": write_scale,
            "bytes_per_launch": (fetch_kib * fetch_scale + write_kib * write_scale) * 1024.0,
@@ -134,14 +137,16 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy a device buffer of this many MiB three times (a plain copy "
                          "kernel of known size that calibrates HBM byte counters)")
-    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+    ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "CHUNK"),
                     help="write the SWAP pass traffic record from two rocprofv3 --pmc runs of "
-                         "this script with --copy-probe-mib (no GPU work)")
+                         "this script with --copy-probe-mib, whose fits used chunk length CHUNK "
+                         "(printed as config.chunk; no GPU work)")
     args = ap.parse_args()
     if args.write_traffic:
         if args.copy_probe_mib <= 0:
             sys.exit("--write-traffic needs the --copy-probe-mib size of the profiled runs")
-        print(json.dumps(write_traffic(*args.write_traffic, args.copy_probe_mib)))
+        f_csv, w_csv, chunk = args.write_traffic
+        print(json.dumps(write_traffic(f_csv, w_csv, args.copy_probe_mib, int(chunk))))
         return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported "
@@ -209,7 +214,8 @@ def main():
     alg_bytes = 4.0 * N * (N - K)            # D entries of the non-medoid candidates
     achieved = alg_bytes / (avg_pass_ms / 1e3) / 1e9
     build_gbs = 4.0 * N * N / (avg_bpass_ms / 1e3) / 1e9
-    traffic = traffic_from_profiles(N, K)
+    chunk = int(stats[-1][2]["chunk"])
+    traffic = traffic_from_profiles(N, K, chunk)
     last = stats[-1][2]
 
     extra = {}
@@ -247,7 +253,7 @@ def main():
         "config": {"workload": "gmm16: n=20000 d=16, 50-component Gaussian mixture, stored FP32 "
                                "Euclidean matrix (1.6 GB), k=100, BUILD init, FastPAM1",
                    "n": N, "dim": DIM, "k": K, "components": COMPONENTS, "seed": SEED,
-                   "parallelism": "single GPU"},
+                   "chunk": chunk, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_swap_pass", "bytes_per_launch": alg_bytes,
