@@ -116,6 +116,14 @@ typedef struct pamx_options {
     int32_t profile;            /* 1: time every BUILD / SWAP pass kernel with
                                    HIP events on `stream` (pamx_stats)       */
     int32_t dist_mode;          /* PAMX_DIST_STORED (default) or PAMX_DIST_BF16 */
+    int32_t graph;              /* stored matrix, profile 0: 1 = one SWAP
+                                   search is captured as a HIP graph (kept per
+                                   host thread for the last 4 argument sets) and
+                                   replayed on a library stream ordered after
+                                   and before `stream` by events; 0 (default) =
+                                   every kernel launched directly (measured
+                                   faster: a replay costs more than the launches
+                                   it replaces)                              */
     void *trace;                /* optional DEVICE array of pamx_swap_record:
                                    every applied swap in order               */
 } pamx_options;

@@ -39,8 +39,9 @@ _DIST = {"stored": PAMX_DIST_STORED, "bf16": PAMX_DIST_BF16,
 
 
 def _options(variant="fastpam1", accum=PAMX_ACC_F64, max_iter=10000, exclude_self=False,
-             chunk=0, trace_buf=None, trace_cap=0, dist_mode="stored"):
+             chunk=0, trace_buf=None, trace_cap=0, dist_mode="stored", graph=False):
     o = _abi.pamx_default_options()
+    o.graph = int(bool(graph))
     o.dist_mode = _DIST[dist_mode]
     o.variant = _VARIANTS[variant]
     o.accum = int(accum)
@@ -74,7 +75,7 @@ def _stats_dict(st):
 
 def fit(data, k, *, input_kind=PAMX_INPUT_X, metric=None, variant="fastpam1",
         accum=PAMX_ACC_F64, max_iter=10000, exclude_self=False, trace=False, chunk=0,
-        dist_mode="stored", stream=None) -> FitResult:
+        dist_mode="stored", graph=False, stream=None) -> FitResult:
     """Distances (for points), BUILD, SWAP, labels and TD on the GPU.
 
     data: device tensor, n x dim points (int32 -> L1, float32 -> L2) or an
@@ -91,7 +92,7 @@ def fit(data, k, *, input_kind=PAMX_INPUT_X, metric=None, variant="fastpam1",
         metric = PAMX_L1 if dtype == _abi.PAMX_I32 else PAMX_L2
     cap = (max_iter * (k if variant in ("fastpam2", PAMX_FASTPAM2) else 1) + 16) if trace else 0
     tbuf = torch.empty(cap * 16, dtype=torch.uint8, device=data.device) if trace else None
-    opt = _options(variant, accum, max_iter, exclude_self, chunk, tbuf, cap, dist_mode)
+    opt = _options(variant, accum, max_iter, exclude_self, chunk, tbuf, cap, dist_mode, graph)
     nbytes = _abi.pamx_workspace_bytes(n, k, dim, input_kind, dtype, opt)
     ws = _workspace(nbytes, data.device)
     med = torch.empty(k, dtype=torch.int32, device=data.device)
@@ -114,14 +115,14 @@ def build(D, k, *, exclude_self=False, stream=None):
 
 
 def swap(D, medoids, *, variant="fastpam1", accum=PAMX_ACC_F64, max_iter=10000, trace=False,
-         chunk=0, stream=None) -> FitResult:
+         chunk=0, graph=False, stream=None) -> FitResult:
     """SWAP from the given medoids (device int32 tensor, slot order; copied)."""
     import torch
     n = D.shape[0]
     k = int(medoids.numel())
     cap = (max_iter * (k if variant in ("fastpam2", PAMX_FASTPAM2) else 1) + 16) if trace else 0
     tbuf = torch.empty(cap * 16, dtype=torch.uint8, device=D.device) if trace else None
-    opt = _options(variant, accum, max_iter, False, chunk, tbuf, cap)
+    opt = _options(variant, accum, max_iter, False, chunk, tbuf, cap, graph=graph)
     nbytes = _abi.pamx_workspace_bytes(n, k, 0, PAMX_INPUT_D, _abi._dtype_code(D), opt)
     ws = _workspace(nbytes, D.device)
     med = medoids.to(device=D.device, dtype=torch.int32).clone()

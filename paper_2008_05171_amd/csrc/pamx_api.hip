@@ -470,6 +470,82 @@ int build_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const pamx_op
     return PAMX_OK;
 }
 
+// ---- SWAP searches as a HIP graph.  A library stream per host thread and
+// device (default priority, never destroyed) runs the replays; events order
+// it after the caller's stream and the caller's stream after it.
+static hipStream_t graph_stream() {
+    constexpr int kMaxDev = 64;
+    thread_local hipStream_t streams[kMaxDev] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return nullptr;
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+        streams[dev] = nullptr;
+    return streams[dev];
+}
+
+// An instantiated search graph bakes in every kernel argument: the matrix,
+// the workspace (and the layout in it), the medoid and trace arrays.  Graphs
+// are kept per host thread for the last few argument sets, so repeated calls
+// on the same buffers replay without capturing again.
+struct SearchKey {
+    int dev;
+    const void *D, *ws, *med, *trace;
+    int64_t ld, n;
+    int32_t k, dtype, variant, chunk, vec, trace_cap;
+    bool operator==(const SearchKey &o) const {
+        return std::tie(dev, D, ws, med, trace, ld, n, k, dtype, variant, chunk, vec, trace_cap) ==
+               std::tie(o.dev, o.D, o.ws, o.med, o.trace, o.ld, o.n, o.k, o.dtype, o.variant, o.chunk,
+                        o.vec, o.trace_cap);
+    }
+};
+
+struct SearchGraph {
+    SearchKey key{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    SearchGraph() = default;
+    SearchGraph(const SearchGraph &) = delete;
+    SearchGraph &operator=(const SearchGraph &) = delete;
+    ~SearchGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+    }
+};
+
+// The cached graph for these arguments, captured on xs if not yet there.
+template <typename T>
+static int search_graph(const T *D, int64_t ld, const Layout &L, int32_t *medoids,
+                        const pamx_options &opt, void *ws, hipStream_t xs, SearchGraph **out) {
+    constexpr size_t kKeep = 4;
+    // held until the process ends (not destroyed at exit, when the HIP
+    // runtime may already be gone)
+    thread_local auto *cache_p = new std::vector<std::unique_ptr<SearchGraph>>();
+    auto &cache = *cache_p;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    const SearchKey key{dev, D, ws, medoids, opt.trace, ld, L.n, L.k, L.dtype, opt.variant,
+                        L.L, L.vec, opt.trace_cap};
+    for (auto &g : cache)
+        if (g->key == key) { *out = g.get(); return PAMX_OK; }
+    std::unique_ptr<SearchGraph> g(new SearchGraph);
+    g->key = key;
+    HIP_TRY(hipEventCreateWithFlags(&g->fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&g->join, hipEventDisableTiming));
+    HIP_TRY(hipStreamBeginCapture(xs, hipStreamCaptureModeThreadLocal));
+    const hipError_t ce = enqueue_swap_iteration<T>(D, ld, L, medoids, opt, ws, xs, nullptr, nullptr);
+    const hipError_t ee = hipStreamEndCapture(xs, &g->graph);
+    if (ce != hipSuccess) return fail(PAMX_ERR_HIP, "capture of a search failed: %s", hipGetErrorString(ce));
+    if (ee != hipSuccess) return fail(PAMX_ERR_HIP, "end of capture failed: %s", hipGetErrorString(ee));
+    HIP_TRY(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    if (cache.size() >= kKeep) cache.erase(cache.begin());
+    cache.push_back(std::move(g));
+    *out = cache.back().get();
+    return PAMX_OK;
+}
+
 // ---- chunk tuning: the fastest chunk length per (device, shape), timed
 // once per process on the caller's matrix and kept for later calls.
 struct TuneKey {
@@ -549,18 +625,33 @@ int swap_impl(const T *D, int64_t ld, const Layout &L_in, int32_t k, const pamx_
             pool.reset(new EventPool(2 * kMaxBatch));
             if (!pool->ok()) return fail(PAMX_ERR_HIP, "hipEventCreate failed");
         }
+        SearchGraph *g = nullptr;
+        hipStream_t xs = s;   // stream the searches run on
+        if (opt.graph && !opt.profile) {
+            hipStream_t gs = graph_stream();
+            if (!gs) return fail(PAMX_ERR_HIP, "could not create the library stream");
+            rc = search_graph<T>(D, ld, L, medoids, opt, ws, gs, &g);
+            if (rc) return rc;
+            HIP_TRY(hipEventRecord(g->fork, s));   // after the caller's work on s
+            HIP_TRY(hipStreamWaitEvent(gs, g->fork, 0));
+            xs = gs;
+        }
         int batch = 4;
         for (;;) {
             int b = batch;
             if (b > opt.max_iter + 1 - enq) b = opt.max_iter + 1 - enq;
             if (b < 1) b = 1;
             const int iter0 = st.iter;
-            for (int j = 0; j < b; ++j)
-                HIP_TRY(enqueue_swap_iteration<T>(D, ld, L, medoids, opt, ws, s,
-                                                  pool ? pool->ev[2 * j] : nullptr,
-                                                  pool ? pool->ev[2 * j + 1] : nullptr));
+            for (int j = 0; j < b; ++j) {
+                if (g)
+                    HIP_TRY(hipGraphLaunch(g->exec, xs));
+                else
+                    HIP_TRY(enqueue_swap_iteration<T>(D, ld, L, medoids, opt, ws, s,
+                                                      pool ? pool->ev[2 * j] : nullptr,
+                                                      pool ? pool->ev[2 * j + 1] : nullptr));
+            }
             enq += b;
-            rc = read_state(L, ws, s, &st);
+            rc = read_state(L, ws, xs, &st);
             if (rc) return rc;
             if (pool) {
                 // passes of iterations that ran (later ones returned at once)
@@ -570,6 +661,10 @@ int swap_impl(const T *D, int64_t ld, const Layout &L_in, int32_t k, const pamx_
             }
             if (st.done) break;
             if (batch < kMaxBatch) batch *= 2;
+        }
+        if (g) {   // the caller's stream continues after the replays
+            HIP_TRY(hipEventRecord(g->join, xs));
+            HIP_TRY(hipStreamWaitEvent(s, g->join, 0));
         }
     }
     tm.rec(3, s);

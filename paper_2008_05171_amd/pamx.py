@@ -30,7 +30,7 @@ class pamx_options(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("build_exclude_self", ctypes.c_int32),
                 ("trace_cap", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("dist_mode", ctypes.c_int32),
-                ("trace", ctypes.c_void_p)]
+                ("graph", ctypes.c_int32), ("trace", ctypes.c_void_p)]
 
 
 class pamx_swap_record(ctypes.Structure):

@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_struct_sizes_match_header():
-    assert ctypes.sizeof(abi.pamx_options) == 40
+    assert ctypes.sizeof(abi.pamx_options) == 48
     assert ctypes.sizeof(abi.pamx_swap_record) == 16
     assert ctypes.sizeof(abi.pamx_stats) == 128
 

@@ -134,6 +134,28 @@ def test_chunk_tuning_keeps_results():
     print("tuned chunk", a.stats["chunk"], flush=True)
 
 
+@pytest.mark.parametrize("variant", ["fastpam1", "fastpam2"])
+def test_graph_replays_equal_direct_launches(variant):
+    """The searches replayed from a captured HIP graph (with host polls and
+    the caller's own work between batches) equal directly launched ones, bit
+    for bit, on integer and float matrices, and the integer run is the oracle's."""
+    _say("graph", variant)
+    X, D = _int_case(1500, 51, hi=60)
+    ref = oracle.pam(7, D=D, variant=oracle.FASTPAM2 if variant == "fastpam2" else oracle.PAM)
+    g = px().fit(_t(X), 7, variant=variant, trace=True, graph=True)
+    d = px().fit(_t(X), 7, variant=variant, trace=True, graph=False)
+    _check_same(g, ref, 7)
+    assert g.trace == d.trace and torch.equal(g.medoids, d.medoids)
+    assert torch.equal(g.labels, d.labels) and g.td == d.td
+    Xf = datagen.gaussian_mixture(3000, 8, 12, seed=52)
+    g = px().fit(_t(Xf), 15, variant=variant, trace=True, graph=True)
+    torch.cuda.synchronize()
+    filler = torch.ones(1 << 20, device=DEV).cumsum(0)   # the caller's own work in between
+    d = px().fit(_t(Xf), 15, variant=variant, trace=True, graph=False)
+    assert g.trace == d.trace and torch.equal(g.medoids, d.medoids) and g.td == d.td
+    assert float(filler[-1]) == float(1 << 20)
+
+
 def test_unaligned_leading_dimension():
     """n not a multiple of 4 with ld = n: the scalar-load pass variant."""
     _say("ld_unaligned")
