@@ -212,7 +212,6 @@ int make_rc_layout(int64_t n, int32_t k, int32_t dim, const pamx_options *opt, R
     R->sds = take((size_t)n * 4);
     R->sthr = take((size_t)n * 4);
     R->snb = take((size_t)n * 4);
-    R->thr = take((size_t)n * 4);
     R->R64 = take((size_t)k * 8);
     R->R32 = take((size_t)k * 4);
     R->part = take((size_t)R->Q * 4 * R->ncp * 8);
@@ -236,15 +235,10 @@ int make_rc_layout(int64_t n, int32_t k, int32_t dim, const pamx_options *opt, R
     R->bnd = take(4 * 8);
     R->mean = take((size_t)dim * 4);
     R->state = take(sizeof(DevState));
-    // incremental BUILD: running A~(c) and its bound, list of changed objects
+    // FP64 BUILD: running A(c), list of objects whose dn dropped (old, new)
     R->acur = take((size_t)R->ncp * 8);
-    R->ecur = take((size_t)R->ncp * 8);
     R->lold = take((size_t)n * 8);
     R->lnew = take((size_t)n * 8);
-    R->lnb = take((size_t)n * 4);
-    R->llo = take((size_t)n * 4);
-    R->lhi = take((size_t)n * 4);
-    R->res_a = take((size_t)n * 8);
     R->total = off;
     return PAMX_OK;
 }

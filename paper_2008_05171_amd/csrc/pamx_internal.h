@@ -61,8 +61,6 @@ struct alignas(64) DevState {
     double f32_best;     // FP32 best change before re-scoring
     long long n_chg;     // BUILD: objects whose nearest distance dropped this step
     long long build_rows;// BUILD: rows read by the incremental passes
-    int32_t refresh;     // BUILD (recompute form): next step makes a full pass
-    int32_t n_full;      // BUILD (recompute form): full passes made
 };
 
 // Lexicographic "a is better than b" on (value, slot, candidate).
@@ -194,13 +192,12 @@ struct RcLayout {
     int64_t n;
     int32_t k, KP, n_ctiles, L, Q, n_oblk;
     int64_t ncp;
-    size_t Xb, nb, eo, dn64, ds64, dn32, ds32, sdn, sds, sthr, snb, thr, R64, R32, part, part_i,
+    size_t Xb, nb, eo, dn64, ds64, dn32, ds32, sdn, sds, sthr, snb, R64, R32, part, part_i,
         cand_v, cand_b, wg_u, list, res_v, res_i, rlist, near, sec, srow, blkcnt, seg_off, cinfo,
-        is_med, mx, eps0, bnd, mean, state, acur, ecur, lold, lnew, lnb, llo, lhi, res_a, total;
+        is_med, mx, eps0, bnd, mean, state, acur, lold, lnew, total;
 };
 constexpr int kRcMaxDim = 64;     // precision form: largest point dimension
 constexpr int kRcMaxK = 4096;     // precision form: largest k (per-slot FP64 sums in LDS)
-constexpr int kRcRefreshList = 32;// precision form BUILD: re-score list length that triggers a full pass
 hipError_t rc_prep_build(const float *X, int32_t dim, const RcLayout &R, int32_t k,
                          const pamx_options &opt, int32_t *medoids, void *ws, hipStream_t s,
                          const float *mean);

@@ -1,8 +1,10 @@
-// precision.hip -- the mixed-precision form of BUILD and FastPAM1 SWAP for
-// Euclidean points: distances recomputed per tile from BF16-rounded points on
-// the matrix cores (no n x n matrix), loss changes summed in FP32, and every
+// precision.hip -- the mixed-precision form of FastPAM1 SWAP for Euclidean
+// points: distances recomputed per tile from split-BF16 points on the matrix
+// cores (no n x n matrix), loss changes summed in FP64 or FP32, and every
 // candidate that could still be the best swap re-scored in FP64 from the
 // original FP32 points, so the decisions are those of FP64 arithmetic.
+// BUILD of this form (Alg. 1) runs in FP64 directly, incrementally after its
+// first two steps.
 //
 // Paper: Schubert & Rousseeuw, arXiv 2008.05171 -- Alg. 1 (BUILD), Alg. 3
 // and Eq. better-change3 (FastPAM1).  The paper fixes no precision; this form
@@ -15,7 +17,7 @@
 //     g_max = sqrt((KP + 8) 2^-20 max_o |x~o|^2)   (FP32 norms and Gram)
 //
 // The loss change of an object depends on d(o,c) only while d < ds(o) (the
-// second-nearest distance; dn for BUILD), so for every swap
+// second-nearest distance), so for every swap
 //   |Delta~(i,c) - Delta(i,c)| <= cnt(c) * eps1 + eps_acc
 // where cnt(c) counts objects with d~(o,c) below ds(o) + eps, and eps_acc
 // bounds the FP32 summation.  Candidates whose lower bound reaches the best
@@ -266,60 +268,6 @@ __device__ __forceinline__ float rc_dist(float g, float no, float nc) {
     return sqrtf(fmaxf(fmaf(-2.0f, g, no + nc), 0.0f));
 }
 
-// ---------------------------------------------------------------- BUILD pass
-// A~(c) = sum_o min(d~(o,c), dn(o)) over a chunk of objects (natural order);
-// counts of objects with d~ < thr(o), split at delta0.  ACC: the sum type
-// (double, or float summed pairwise per 32-object block).
-// part[q][c] = A~ (ACC), part_i[q][0|1][c] = far / near counts.
-template <int KS, typename ACC>
-__global__ __launch_bounds__(kRT) void k_rc_build_pass(
-    const __bf16 *__restrict__ Xs, int32_t KP, const float *__restrict__ nb, int64_t n,
-    const float *__restrict__ dn, const float *__restrict__ thr, const double *__restrict__ eps0,
-    int32_t L, int64_t ncp, ACC *__restrict__ part, int32_t *__restrict__ part_i,
-    const DevState *__restrict__ gate) {
-    __shared__ __align__(16) __bf16 As[kRB * 2 * kAS];
-    __shared__ float4 Rv[2][kRB];   // by block parity: a wave is at most one block ahead
-    __shared__ float G[4][64 * kGS];
-    if (gate && !gate->refresh) return;   // incremental step instead
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int q = blockIdx.y;
-    const int64_t a = (int64_t)q * L, b = min(a + (int64_t)L, n);
-    const int64_t cbase = (int64_t)blockIdx.x * kRT + w * 64;
-    const int64_t c = cbase + lane;
-    bf16x8 bh[2][KS], bl[2][KS];
-    load_bq<KS>(Xs, KP, n, cbase, bh, bl);
-    const float nc = (c < n) ? nb[c] : 0.0f;
-    const float d0 = (float)eps0[2];
-    ACC accA = 0;
-    int cf = 0, cn = 0;
-    float *Gw = G[w];
-    const RowVals rv{nb, dn, thr, nullptr};
-    Stage<KS> stg;
-    stage_load<KS>(stg, Xs, KP, nullptr, a, b, rv);
-    for (int64_t j0 = a; j0 < b; j0 += kRB) {
-        float4 *Rb = Rv[((j0 - a) / kRB) & 1];
-        stage_store<KS>(stg, KP, As, Rb);
-        __syncthreads();
-        if (j0 + kRB < b) stage_load<KS>(stg, Xs, KP, nullptr, j0 + kRB, b, rv);
-        gram_tile<KS>(As, Gw, bh, bl);
-        __syncthreads();
-        const int m = (int)min((int64_t)kRB, b - j0);
-        ACC blk = 0;
-        for (int r = 0; r < m; ++r) {
-            const float4 q4 = Rb[r];
-            const float d = rc_dist(Gw[lane * kGS + r], q4.x, nc);
-            blk += (ACC)fminf(d, q4.y);
-            const bool cnt = d < q4.z;
-            cf += (cnt && d >= d0) ? 1 : 0;
-            cn += (cnt && d < d0) ? 1 : 0;
-        }
-        accA += blk;
-    }
-    part[(int64_t)q * ncp + c] = accA;
-    part_i[(int64_t)q * 2 * ncp + c] = cf;
-    part_i[(int64_t)q * 2 * ncp + ncp + c] = cn;
-}
-
 // ---------------------------------------------------------------- SWAP pass
 // The FastPAM1 pass (Eq. better-change3) over a chunk of segment-sorted
 // objects: B(c) += min(d~ - dn, 0); S_i(c) += med3(d~, dn, ds) - ds; at the
@@ -405,50 +353,7 @@ __global__ __launch_bounds__(kRT) void k_rc_swap_pass(
     pi[2 * ncp] = cn;
 }
 
-// ---------------------------------------------------------------- merges
-// BUILD: A~(c) summed over chunks, its bound, per-WG min of the upper bound.
-// bnd[0] = e_far, bnd[1] = e_near, bnd[2] = relative summation factor.
-template <typename ACC>
-__global__ __launch_bounds__(256) void k_rc_build_merge(
-    const ACC *__restrict__ part, const int32_t *__restrict__ part_i, int32_t Q, int64_t ncp,
-    int64_t n, const double *__restrict__ dn64, const uint8_t *__restrict__ is_med, int32_t add_self,
-    const double *__restrict__ bnd, double *__restrict__ cand_v, double *__restrict__ cand_b,
-    double *__restrict__ wg_u, double *__restrict__ acur, double *__restrict__ ecur,
-    DevState *__restrict__ gate) {
-    __shared__ double red[256];
-    if (gate && !gate->refresh) return;
-    if (gate && blockIdx.x == 0 && threadIdx.x == 0) gate->n_full += 1;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double up = __builtin_huge_val();
-    if (c < n && !is_med[c]) {
-        ACC s = 0;
-        int64_t cf = 0, cn = 0;
-        for (int q = 0; q < Q; ++q) {
-            s += part[(int64_t)q * ncp + c];
-            cf += part_i[(int64_t)q * 2 * ncp + c];
-            cn += part_i[(int64_t)q * 2 * ncp + ncp + c];
-        }
-        double v = (double)s;
-        double b = (double)cf * bnd[0] + (double)cn * bnd[1] + bnd[2] * v;
-        if (acur) { acur[c] = v; ecur[c] = b; }   // start of the incremental steps
-        if (add_self) v += dn64[c];
-        b = b * 1.0001 + 1e-300;
-        cand_v[c] = v;
-        cand_b[c] = b;
-        up = v + b;
-    } else if (c < n) {
-        cand_v[c] = __builtin_huge_val();
-        cand_b[c] = 0.0;
-    }
-    red[threadIdx.x] = up;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) wg_u[blockIdx.x] = red[0];
-}
-
+// ---------------------------------------------------------------- merge
 // SWAP: chunk carries and bests -> per candidate Delta~_c and its bound.
 // bnd[0] = e_far, bnd[1] = e_near, bnd[2] = absolute summation bound.
 template <typename ACC>
@@ -547,26 +452,6 @@ __global__ __launch_bounds__(256) void k_rc_mark(const double *__restrict__ cand
 
 // ---------------------------------------------------------------- FP64 re-score
 // One work-group per listed candidate, fixed summation order.
-// BUILD: A64(c) = sum_o min(d64(o,c), dn64(o)) (+ dn64(c)).
-template <int KS>
-__global__ __launch_bounds__(256) void k_rc_build_rescore(
-    const float *__restrict__ X, int32_t dim, int64_t n, const double *__restrict__ dn64,
-    int32_t add_self, const int32_t *__restrict__ list, const DevState *__restrict__ st,
-    double *__restrict__ res_v, double *__restrict__ res_a) {
-    const int m = st->n_list;
-    for (int idx = blockIdx.x; idx < m; idx += gridDim.x) {
-        const int64_t c = list[idx];
-        double s = 0.0;
-        for (int64_t o = threadIdx.x; o < n; o += 256) s += fmin(d64(X, dim, o, c), dn64[o]);
-        s = block_sum<double, 256>(s);
-        if (threadIdx.x == 0) {
-            res_v[idx] = s + (add_self ? dn64[c] : 0.0);
-            res_a[idx] = s;
-        }
-        __syncthreads();
-    }
-}
-
 // SWAP: exact Delta(i,c) = R_i + B(c) + S_i(c) for every slot i.  Thread t
 // walks a contiguous range of the sorted objects; segments complete in its
 // range go to LDS directly, the partial first/last ones are combined
@@ -652,43 +537,34 @@ __global__ __launch_bounds__(256) void k_rc_swap_rescore(
 }
 
 template <int KS>
-static hipError_t rc_rescore_launch(bool swap_mode, const float *X, int32_t dim, int64_t n, int32_t k,
+static hipError_t rc_rescore_launch(const float *X, int32_t dim, int64_t n, int32_t k,
                                     const int32_t *srow, const double *dn64, const double *ds64,
-                                    const int32_t *near, const double *R64, int32_t add_self,
-                                    const int32_t *list, const DevState *st, double *res_v,
-                                    double *res_a, int32_t *res_i, hipStream_t s) {
-    if (swap_mode)
-        hipLaunchKernelGGL((k_rc_swap_rescore<KS>), dim3(1024), dim3(256), (size_t)k * 8, s, X, dim, n,
-                           k, srow, dn64, ds64, near, R64, list, st, res_v, res_i);
-    else
-        hipLaunchKernelGGL((k_rc_build_rescore<KS>), dim3(1024), dim3(256), 0, s, X, dim, n, dn64,
-                           add_self, list, st, res_v, res_a);
+                                    const int32_t *near, const double *R64, const int32_t *list,
+                                    const DevState *st, double *res_v, int32_t *res_i,
+                                    hipStream_t s) {
+    hipLaunchKernelGGL((k_rc_swap_rescore<KS>), dim3(1024), dim3(256), (size_t)k * 8, s, X, dim, n, k,
+                       srow, dn64, ds64, near, R64, list, st, res_v, res_i);
     return hipGetLastError();
 }
 
-static hipError_t rc_rescore(int KP, bool swap_mode, const float *X, int32_t dim, int64_t n, int32_t k,
+static hipError_t rc_rescore(int KP, const float *X, int32_t dim, int64_t n, int32_t k,
                              const int32_t *srow, const double *dn64, const double *ds64,
-                             const int32_t *near, const double *R64, int32_t add_self,
-                             const int32_t *list, const DevState *st, double *res_v, double *res_a,
-                             int32_t *res_i, hipStream_t s) {
+                             const int32_t *near, const double *R64, const int32_t *list,
+                             const DevState *st, double *res_v, int32_t *res_i, hipStream_t s) {
     switch (KP / 16) {
-        case 1: return rc_rescore_launch<1>(swap_mode, X, dim, n, k, srow, dn64, ds64, near, R64,
-                                            add_self, list, st, res_v, res_a, res_i, s);
-        case 2: return rc_rescore_launch<2>(swap_mode, X, dim, n, k, srow, dn64, ds64, near, R64,
-                                            add_self, list, st, res_v, res_a, res_i, s);
-        case 3: return rc_rescore_launch<3>(swap_mode, X, dim, n, k, srow, dn64, ds64, near, R64,
-                                            add_self, list, st, res_v, res_a, res_i, s);
-        default: return rc_rescore_launch<4>(swap_mode, X, dim, n, k, srow, dn64, ds64, near, R64,
-                                             add_self, list, st, res_v, res_a, res_i, s);
+        case 1: return rc_rescore_launch<1>(X, dim, n, k, srow, dn64, ds64, near, R64, list, st, res_v, res_i, s);
+        case 2: return rc_rescore_launch<2>(X, dim, n, k, srow, dn64, ds64, near, R64, list, st, res_v, res_i, s);
+        case 3: return rc_rescore_launch<3>(X, dim, n, k, srow, dn64, ds64, near, R64, list, st, res_v, res_i, s);
+        default: return rc_rescore_launch<4>(X, dim, n, k, srow, dn64, ds64, near, R64, list, st, res_v, res_i, s);
     }
 }
 
-// Lexicographic minimum over the re-scored list; BUILD picks the medoid,
-// SWAP applies the swap if its exact change is below -margin.
+// Lexicographic minimum over the re-scored list; the swap is applied if its
+// exact change is below -margin.
 __global__ __launch_bounds__(1024) void k_rc_pick(const double *__restrict__ res_v,
                                                   const int32_t *__restrict__ res_i,
-                                                  const int32_t *__restrict__ list, int32_t swap_mode,
-                                                  int32_t t_step, int32_t *__restrict__ med,
+                                                  const int32_t *__restrict__ list,
+                                                  int32_t *__restrict__ med,
                                                   uint8_t *__restrict__ is_med, DevState *__restrict__ st,
                                                   pamx_swap_record *__restrict__ trace) {
     if (st->done) return;
@@ -697,21 +573,12 @@ __global__ __launch_bounds__(1024) void k_rc_pick(const double *__restrict__ res
     int i = INT_MAX, c = INT_MAX;
     for (int idx = threadIdx.x; idx < m; idx += 1024) {
         const double vv = res_v[idx];
-        const int ii = swap_mode ? res_i[idx] : 0, cc = list[idx];
+        const int ii = res_i[idx], cc = list[idx];
         if (lex_less(vv, ii, cc, v, i, c)) { v = vv; i = ii; c = cc; }
     }
     block_argmin3<double, 1024>(v, i, c);
     if (threadIdx.x != 0) return;
     st->rescored += m;
-    if (!swap_mode) {
-        // a long re-score list means the running bounds have grown: the next
-        // step recomputes every candidate from scratch
-        st->refresh = m > kRcRefreshList;
-        st->best_c = c;
-        if (c != INT_MAX) { med[t_step] = c; is_med[c] = 1; }
-        else st->bad_medoids = 1;
-        return;
-    }
     st->iter += 1;
     st->best_i = i;
     st->best_c = c;
@@ -735,20 +602,6 @@ __global__ __launch_bounds__(1024) void k_rc_pick(const double *__restrict__ res
 }
 
 // ---------------------------------------------------------------- caches (FP64)
-template <bool FIRST>
-__global__ __launch_bounds__(256) void k_rc_build_update(const float *__restrict__ X, int32_t dim,
-                                                         int64_t n, double *__restrict__ dn64,
-                                                         float *__restrict__ dn32,
-                                                         const DevState *__restrict__ st) {
-    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int c = st->best_c;
-    if (o >= n || c == INT_MAX) return;
-    const double d = d64(X, dim, o, c);
-    const double v = FIRST ? d : fmin(dn64[o], d);
-    dn64[o] = v;
-    dn32[o] = (float)v;
-}
-
 // nearest / second over the k medoids with FP64 distances; FP32 copies
 __device__ __forceinline__ void rc_scan(const float *__restrict__ X, int dim, int k,
                                         const int32_t *__restrict__ med, int64_t o, int lane,
@@ -917,71 +770,125 @@ __global__ __launch_bounds__(1024) void k_rc_iter_bounds(const double *__restric
     }
 }
 
-// BUILD step thresholds: dn + e_near (FP32), +inf before the first medoid.
-__global__ __launch_bounds__(256) void k_rc_build_thr(const float *__restrict__ dn32, int64_t n,
-                                                      const double *__restrict__ eps0,
-                                                      float *__restrict__ thr,
-                                                      const DevState *__restrict__ gate) {
-    if (gate && !gate->refresh) return;
-    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (o >= n) return;
-    const double lo = (double)dn32[o];
-    thr[o] = (lo == __builtin_huge_val()) ? __builtin_huge_valf()
-                                         : (float)((lo + eps0[0]) * (1.0 + 0x1p-20) + 1e-30);
-}
-
-// BUILD step bounds: bnd[0] = e_far, bnd[1] = e_near, bnd[2] = relative
-// summation factor (times A~(c)).
-__global__ __launch_bounds__(1024) void k_rc_build_bounds(const double *__restrict__ dn64, int64_t n,
-                                                          int32_t L, int32_t Q, int32_t first,
-                                                          int32_t acc64, const double *__restrict__ eps0,
-                                                          double *__restrict__ bnd,
-                                                          const DevState *__restrict__ gate,
-                                                          int32_t want) {
-    __shared__ double r[1024];
-    if (gate && gate->refresh != want) return;
-    double mx = 0.0;
-    if (!first)
-        for (int64_t o = threadIdx.x; o < n; o += 1024) mx = fmax(mx, dn64[o]);
-    r[threadIdx.x] = mx;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) r[threadIdx.x] = fmax(r[threadIdx.x], r[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        // step 0 counts every object: its distances are below eps0[3]
-        const double thr = first ? eps0[3] : (r[0] + eps0[0]) * (1.0 + 0x1p-20);
-        const double small = 0x1p-22 * thr + 3.0 * 0x1p-24 * thr;
-        bnd[0] = eps0[1] + small;
-        bnd[1] = eps0[0] + small;
-        bnd[2] = acc64 ? ((double)L + Q + 64.0) * 0x1p-52
-                       : (32.0 + (L + 31) / 32 + Q + 10.0) * 0x1p-24 * 1.02;
-        bnd[3] = r[0];
-    }
-}
-
 __global__ void k_rc_reset_list(DevState *st) {
     if (threadIdx.x == 0 && !st->done) st->n_list = 0;
 }
 
-// ---------------------------------------------------------------- incremental BUILD
-// After the first two steps, adding medoid m_t changes A(c) only through the
-// objects whose dn dropped (new < old):
-//   A(c) += sum over them of min(d, new) - min(d, old),
-// and a term depends on d only while new < d < old.  With d~ within e of d,
-// an object whose d~ is below new - e or above old + e contributes its exact
-// term, so the running bound E(c) grows by e per object counted inside
-// [new - e, old + e] (near/far classes as in the full pass) plus the FP64
-// rounding of the sums.  A candidate re-scored exactly restarts from its FP64
-// value with a rounding-only bound.
+template <typename X>
+__global__ __launch_bounds__(256) void k_rc_copy(const X *__restrict__ src, X *__restrict__ dst,
+                                                 int64_t cnt) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < cnt) dst[t] = src[t];
+}
 
-__global__ __launch_bounds__(kObjBlk) void k_rc_build_update2(
-    const float *__restrict__ X, int32_t dim, int64_t n, const double *__restrict__ dn64,
-    double *__restrict__ dn64n, float *__restrict__ dn32n, const DevState *__restrict__ st,
-    int32_t *__restrict__ blkcnt) {
+
+// ================================================================ BUILD (FP64)
+// BUILD of this form runs in FP64, so its choices need no error bound:
+// A(c) = sum_o min(d64(o,c), dn(o)) over all objects in the first two steps,
+// then, per step, the change sum over the objects whose dn dropped of
+// min(d64, dn_new) - min(d64, dn_old).  One thread per candidate with its
+// point in registers as doubles; objects in tiles of 32 staged in LDS as
+// doubles (every lane reads the same entry); d64 is the same expression as
+// the re-scoring distance (coordinates past dim add an exact 0).
+constexpr int kB64Tile = 32;
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_rc64_build_pass(
+    const float *__restrict__ X, int32_t dim, int64_t n, const int32_t *__restrict__ rows,
+    const double *__restrict__ vold, const double *__restrict__ vnew,
+    const DevState *__restrict__ st, int64_t ncp, double *__restrict__ part) {
+    constexpr int MD = 16 * KS;
+    __shared__ __align__(16) double xs[kB64Tile][MD];
+    __shared__ double vo[kB64Tile], vn[kB64Tile];
+    const int tid = threadIdx.x;
+    const int64_t c = (int64_t)blockIdx.x * 256 + tid;
+    const int64_t m = rows ? (int64_t)st->n_chg : n;
+    const int Qd = gridDim.y, q = blockIdx.y;
+    const int64_t Ld = (m + Qd - 1) / Qd;
+    const int64_t a = min((int64_t)q * Ld, m), b = min(a + Ld, m);
+    double xc[MD];
+#pragma unroll
+    for (int k = 0; k < MD; ++k) xc[k] = (c < n && k < dim) ? (double)X[c * dim + k] : 0.0;
+    for (int e = tid; e < kB64Tile * MD; e += 256) xs[e / MD][e % MD] = 0.0;   // padding stays 0
+    double acc = 0.0;
+    for (int64_t j0 = a; j0 < b; j0 += kB64Tile) {
+        const int cnt = (int)min((int64_t)kB64Tile, b - j0);
+        __syncthreads();
+        for (int e = tid; e < cnt * dim; e += 256) {
+            const int r = e / dim, kk = e - r * dim;
+            const int64_t o = rows ? (int64_t)rows[j0 + r] : j0 + r;
+            xs[r][kk] = (double)X[o * dim + kk];
+        }
+        if (tid < cnt) {
+            vn[tid] = vnew[j0 + tid];
+            vo[tid] = vold ? vold[j0 + tid] : 0.0;
+        }
+        __syncthreads();
+        for (int r = 0; r < cnt; ++r) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < MD; ++k) {
+                const double t = xs[r][k] - xc[k];
+                s2 = fma(t, t, s2);
+            }
+            const double d = sqrt(s2);
+            acc += vold ? fmin(d, vn[r]) - fmin(d, vo[r]) : fmin(d, vn[r]);
+        }
+    }
+    part[(int64_t)q * ncp + c] = acc;
+}
+
+// A(c) <- (full ? 0 : A(c)) + chunk sums in chunk order; the work-group's
+// best (value, candidate) among non-medoids (value + dn(c) for the literal
+// reading of Alg. 1).
+__global__ __launch_bounds__(256) void k_rc64_build_merge(
+    const double *__restrict__ part, int32_t Q, int64_t ncp, int64_t n, int32_t full,
+    double *__restrict__ acur, const double *__restrict__ dn64, const uint8_t *__restrict__ is_med,
+    int32_t add_self, double *__restrict__ wg_v, int32_t *__restrict__ wg_c) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double v = __builtin_huge_val();
+    int ci = INT_MAX;
+    if (c < n) {
+        double s2 = 0.0;
+        for (int q = 0; q < Q; ++q) s2 += part[(int64_t)q * ncp + c];
+        const double a2 = full ? s2 : acur[c] + s2;
+        acur[c] = a2;
+        if (!is_med[c]) {
+            v = add_self ? a2 + dn64[c] : a2;
+            ci = (int)c;
+        }
+    }
+    int dummy = 0;
+    block_argmin3<double, 256>(v, dummy, ci);
+    if (threadIdx.x == 0) {
+        wg_v[blockIdx.x] = v;
+        wg_c[blockIdx.x] = ci;
+    }
+}
+
+// The step's medoid (every block reduces the merge partials: smallest value,
+// smallest index on ties; block 0 records it), then dn' = min(dn, d64(., m))
+// into the other buffer and the per-block count of objects whose dn dropped.
+__global__ __launch_bounds__(kObjBlk) void k_rc64_select_update(
+    const double *__restrict__ wg_v, const int32_t *__restrict__ wg_c, int32_t nwg, int32_t t,
+    int32_t *__restrict__ med, uint8_t *__restrict__ is_med, const float *__restrict__ X,
+    int32_t dim, int64_t n, const double *__restrict__ dn64, double *__restrict__ dn64n,
+    float *__restrict__ dn32n, DevState *__restrict__ st, int32_t *__restrict__ blkcnt) {
+    double v = __builtin_huge_val();
+    int c = INT_MAX, dummy = 0;
+    for (int w = threadIdx.x; w < nwg; w += kObjBlk)
+        if (lex_less(wg_v[w], 0, wg_c[w], v, 0, c)) { v = wg_v[w]; c = wg_c[w]; }
+    block_argmin3<double, kObjBlk>(v, dummy, c);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->best_c = c;
+        if (c != INT_MAX) {
+            med[t] = c;
+            is_med[c] = 1;
+        } else {
+            st->bad_medoids = 1;  // no candidate left (cannot happen for k <= n)
+        }
+    }
     const int64_t o = (int64_t)blockIdx.x * kObjBlk + threadIdx.x;
-    const int c = st->best_c;
     int chg = 0;
     if (o < n) {
         const double old = dn64[o];
@@ -996,15 +903,12 @@ __global__ __launch_bounds__(kObjBlk) void k_rc_build_update2(
 }
 
 // Stable list (ascending object) of the objects whose dn dropped, with their
-// old and new dn, norm and counting interval [lo, hi] (rounded outward).
-__global__ __launch_bounds__(kObjBlk) void k_rc_build_compact(
-    const double *__restrict__ dn_old, const double *__restrict__ dn_new, const float *__restrict__ nb,
-    int64_t n, const int32_t *__restrict__ blkcnt, int32_t nblk, const double *__restrict__ eps0,
-    int32_t *__restrict__ lobj, double *__restrict__ lold, double *__restrict__ lnew,
-    float *__restrict__ lnb, float *__restrict__ llo, float *__restrict__ lhi,
-    DevState *__restrict__ st) {
+// old and new dn; the total goes to the device state.
+__global__ __launch_bounds__(kObjBlk) void k_rc64_compact(
+    const double *__restrict__ dn_old, const double *__restrict__ dn_new, int64_t n,
+    const int32_t *__restrict__ blkcnt, int32_t nblk, int32_t *__restrict__ lobj,
+    double *__restrict__ lold, double *__restrict__ lnew, DevState *__restrict__ st) {
     __shared__ int wcnt[kObjBlk / 64];
-    if (st->refresh) return;
     int pre = 0, tot = 0;
     for (int b = threadIdx.x; b < nblk; b += kObjBlk) {
         const int v = blkcnt[b];
@@ -1022,175 +926,34 @@ __global__ __launch_bounds__(kObjBlk) void k_rc_build_compact(
         chg = nw < old;
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const unsigned long long m = __ballot(chg);
-    if (lane == 0) wcnt[wv] = __popcll(m);
+    const unsigned long long msk = __ballot(chg);
+    if (lane == 0) wcnt[wv] = __popcll(msk);
     __syncthreads();
-    int rank = __popcll(m & ((1ull << lane) - 1ull));
+    int rank = __popcll(msk & ((1ull << lane) - 1ull));
     for (int w = 0; w < wv; ++w) rank += wcnt[w];
     if (chg) {
         const int pos = pre + rank;
-        const double e = eps0[0];
         lobj[pos] = (int32_t)o;
         lold[pos] = old;
         lnew[pos] = nw;
-        lnb[pos] = nb[o];
-        llo[pos] = (float)((nw - e) - 0x1p-20 * (nw + e) - 1e-30);
-        lhi[pos] = (float)((old + e) + 0x1p-20 * (old + e) + 1e-30);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->n_chg = tot;
-}
-
-// Per candidate and chunk of the list: sum of min(d~, new) - min(d~, old) in
-// FP64 and the far / near counts of d~ inside [lo, hi].
-template <int KS>
-__global__ __launch_bounds__(kRT) void k_rc_build_delta(
-    const __bf16 *__restrict__ Xs, int32_t KP, const float *__restrict__ nb, int64_t n,
-    const int32_t *__restrict__ lobj, const float *__restrict__ lnb, const float *__restrict__ llo,
-    const float *__restrict__ lhi, const double *__restrict__ lold, const double *__restrict__ lnew,
-    const double *__restrict__ eps0, const DevState *__restrict__ st, int64_t ncp,
-    double *__restrict__ part, int32_t *__restrict__ part_i) {
-    __shared__ __align__(16) __bf16 As[kRB * 2 * kAS];
-    __shared__ float4 Rv[2][kRB];    // by block parity, as in the full pass
-    __shared__ double2 Rd[2][kRB];
-    __shared__ float G[4][64 * kGS];
-    if (st->refresh) return;
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int64_t m = st->n_chg;
-    const int Qd = gridDim.y, q = blockIdx.y;
-    const int64_t Ld = (m + Qd - 1) / Qd;
-    const int64_t a = min((int64_t)q * Ld, m), b = min(a + Ld, m);
-    const int64_t cbase = (int64_t)blockIdx.x * kRT + w * 64;
-    const int64_t c = cbase + lane;
-    bf16x8 bh[2][KS], bl[2][KS];
-    load_bq<KS>(Xs, KP, n, cbase, bh, bl);
-    const float nc = (c < n) ? nb[c] : 0.0f;
-    const float d0 = (float)eps0[2];
-    double acc = 0.0;
-    int cf = 0, cn = 0;
-    float *Gw = G[w];
-    const RowVals rv{lnb, llo, lhi, nullptr};
-    Stage<KS> stg;
-    if (a < b) stage_load<KS>(stg, Xs, KP, lobj, a, b, rv);
-    for (int64_t j0 = a; j0 < b; j0 += kRB) {
-        const int par = (int)(((j0 - a) / kRB) & 1);
-        float4 *Rb = Rv[par];
-        double2 *Rdb = Rd[par];
-        stage_store<KS>(stg, KP, As, Rb);
-        if (tid < kRB) {
-            const int64_t j = j0 + tid;
-            Rdb[tid] = (j < b) ? make_double2(lold[j], lnew[j]) : make_double2(0.0, 0.0);
-        }
-        __syncthreads();
-        if (j0 + kRB < b) stage_load<KS>(stg, Xs, KP, lobj, j0 + kRB, b, rv);
-        gram_tile<KS>(As, Gw, bh, bl);
-        __syncthreads();
-        const int mm = (int)min((int64_t)kRB, b - j0);
-        double blk = 0.0;
-        for (int r = 0; r < mm; ++r) {
-            const float4 q4 = Rb[r];      // norm, lo, hi
-            const double2 od = Rdb[r];    // old, new
-            const float d = rc_dist(Gw[lane * kGS + r], q4.x, nc);
-            const double dd = (double)d;
-            blk += fmin(dd, od.y) - fmin(dd, od.x);
-            const bool cnt = d >= q4.y && d <= q4.z;
-            cf += (cnt && d >= d0) ? 1 : 0;
-            cn += (cnt && d < d0) ? 1 : 0;
-        }
-        acc += blk;
-    }
-    part[(int64_t)q * ncp + c] = acc;
-    part_i[(int64_t)q * 2 * ncp + c] = cf;
-    part_i[(int64_t)q * 2 * ncp + ncp + c] = cn;
-}
-
-// A~(c) += chunk sums (chunk order), E(c) += counted errors + rounding; then
-// the step's value, bound and work-group upper minimum as k_rc_build_merge.
-// bnd[0] = e_far, bnd[1] = e_near, bnd[2] = FP64 summation factor,
-// bnd[3] = largest old dn (bounds every |term|).
-__global__ __launch_bounds__(256) void k_rc_build_dmerge(
-    const double *__restrict__ part, const int32_t *__restrict__ part_i, int32_t Q, int64_t ncp,
-    int64_t n, const double *__restrict__ dn64, const uint8_t *__restrict__ is_med, int32_t add_self,
-    const double *__restrict__ bnd, const DevState *__restrict__ st, double *__restrict__ acur,
-    double *__restrict__ ecur, double *__restrict__ cand_v, double *__restrict__ cand_b,
-    double *__restrict__ wg_u) {
-    __shared__ double red[256];
-    if (st->refresh) return;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double up = __builtin_huge_val();
-    if (c < n && !is_med[c]) {
-        double s = 0.0;
-        int64_t cf = 0, cn = 0;
-        for (int q = 0; q < Q; ++q) {
-            s += part[(int64_t)q * ncp + c];
-            cf += part_i[(int64_t)q * 2 * ncp + c];
-            cn += part_i[(int64_t)q * 2 * ncp + ncp + c];
-        }
-        const double a = acur[c] + s;
-        const double e = ecur[c] + (double)cf * bnd[0] + (double)cn * bnd[1] +
-                         bnd[2] * (double)st->n_chg * bnd[3] + 0x1p-52 * fabs(a);
-        acur[c] = a;
-        ecur[c] = e;
-        const double v = add_self ? a + dn64[c] : a;
-        const double b = e * 1.0001 + 1e-300;
-        cand_v[c] = v;
-        cand_b[c] = b;
-        up = v + b;
-    } else if (c < n) {
-        cand_v[c] = __builtin_huge_val();
-        cand_b[c] = 0.0;
-    }
-    red[threadIdx.x] = up;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) wg_u[blockIdx.x] = red[0];
-}
-
-// Re-scored candidates restart from their FP64 sums.
-__global__ __launch_bounds__(256) void k_rc_reanchor(const int32_t *__restrict__ list,
-                                                     const double *__restrict__ res_a,
-                                                     const DevState *__restrict__ st, int64_t n,
-                                                     double *__restrict__ acur,
-                                                     double *__restrict__ ecur) {
-    const int m = st->n_list;
-    for (int idx = blockIdx.x * 256 + threadIdx.x; idx < m; idx += gridDim.x * 256) {
-        const int64_t c = list[idx];
-        acur[c] = res_a[idx];
-        ecur[c] = ((double)n + 64.0) * 0x1p-52 * res_a[idx];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->n_chg = tot;
+        st->build_rows += tot;
     }
 }
-
-template <typename X>
-__global__ __launch_bounds__(256) void k_rc_copy(const X *__restrict__ src, X *__restrict__ dst,
-                                                 int64_t cnt) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t < cnt) dst[t] = src[t];
-}
-
 
 // ================================================================ host side
 struct RcPtrs {
     __bf16 *Xs;
-    float *nb, *dn32, *ds32, *sdn, *sds, *sthr, *snb, *thr;
+    float *nb, *dn32, *ds32, *sdn, *sds, *sthr, *snb;
     void *part;
     double *eo, *dn64, *ds64, *R64, *mx, *eps0, *bnd, *wg_u, *res_v, *cand_v, *cand_b;
     int32_t *near, *sec, *srow, *blkcnt, *seg_off, *cinfo3, *part_i, *list, *res_i, *rlist;
     uint8_t *is_med;
     DevState *st;
-    double *acur, *ecur, *lold, *lnew, *res_a;
-    float *lnb, *llo, *lhi;
+    double *acur, *lold, *lnew;
 };
-
-template <int KS, typename ACC>
-static void rc_build_pass_launch(const RcPtrs &p, const RcLayout &R, int64_t n, const float *dn32,
-                                 const DevState *gate, hipStream_t s) {
-    hipLaunchKernelGGL((k_rc_build_pass<KS, ACC>), dim3(R.n_ctiles, R.Q), dim3(kRT), 0, s,
-                       (const __bf16 *)p.Xs, R.KP, (const float *)p.nb, n, dn32,
-                       (const float *)p.thr, (const double *)p.eps0, R.L, R.ncp,
-                       static_cast<ACC *>(p.part), p.part_i, gate);
-}
 
 template <int KS, typename ACC>
 static void rc_swap_pass_launch(const RcPtrs &p, const RcLayout &R, int64_t n, int k, hipStream_t s) {
@@ -1203,17 +966,6 @@ static void rc_swap_pass_launch(const RcPtrs &p, const RcLayout &R, int64_t n, i
 }
 
 template <typename ACC>
-static void rc_build_pass_any(const RcPtrs &p, const RcLayout &R, int64_t n, const float *dn32,
-                              const DevState *gate, hipStream_t s) {
-    switch (R.KP / 16) {
-        case 1: rc_build_pass_launch<1, ACC>(p, R, n, dn32, gate, s); break;
-        case 2: rc_build_pass_launch<2, ACC>(p, R, n, dn32, gate, s); break;
-        case 3: rc_build_pass_launch<3, ACC>(p, R, n, dn32, gate, s); break;
-        default: rc_build_pass_launch<4, ACC>(p, R, n, dn32, gate, s); break;
-    }
-}
-
-template <typename ACC>
 static void rc_swap_pass_any(const RcPtrs &p, const RcLayout &R, int64_t n, int k, hipStream_t s) {
     switch (R.KP / 16) {
         case 1: rc_swap_pass_launch<1, ACC>(p, R, n, k, s); break;
@@ -1223,22 +975,20 @@ static void rc_swap_pass_any(const RcPtrs &p, const RcLayout &R, int64_t n, int 
     }
 }
 
-template <int KS>
-static void rc_build_delta_launch(const RcPtrs &p, const RcLayout &R, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL((k_rc_build_delta<KS>), dim3(R.n_ctiles, R.Q), dim3(kRT), 0, s,
-                       (const __bf16 *)p.Xs, R.KP, (const float *)p.nb, n, (const int32_t *)p.srow,
-                       (const float *)p.lnb, (const float *)p.llo, (const float *)p.lhi,
-                       (const double *)p.lold, (const double *)p.lnew, (const double *)p.eps0,
-                       (const DevState *)p.st, R.ncp, static_cast<double *>(p.part), p.part_i);
-}
-
-static void rc_build_delta_any(const RcPtrs &p, const RcLayout &R, int64_t n, hipStream_t s) {
+static void rc64_build_pass(const RcPtrs &p, const RcLayout &R, const float *X, int32_t dim,
+                            int64_t n, const int32_t *rows, const double *vold, const double *vnew,
+                            int32_t Q, hipStream_t s) {
+    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)Q);
+#define PAMX_B64(KS)                                                                            \
+    hipLaunchKernelGGL((k_rc64_build_pass<KS>), grid, dim3(256), 0, s, X, dim, n, rows, vold, vnew, \
+                       (const DevState *)p.st, R.ncp, static_cast<double *>(p.part))
     switch (R.KP / 16) {
-        case 1: rc_build_delta_launch<1>(p, R, n, s); break;
-        case 2: rc_build_delta_launch<2>(p, R, n, s); break;
-        case 3: rc_build_delta_launch<3>(p, R, n, s); break;
-        default: rc_build_delta_launch<4>(p, R, n, s); break;
+        case 1: PAMX_B64(1); break;
+        case 2: PAMX_B64(2); break;
+        case 3: PAMX_B64(3); break;
+        default: PAMX_B64(4); break;
     }
+#undef PAMX_B64
 }
 
 static RcPtrs rc_ptrs(const RcLayout &R, void *ws) {
@@ -1255,7 +1005,6 @@ static RcPtrs rc_ptrs(const RcLayout &R, void *ws) {
     p.sds = reinterpret_cast<float *>(w + R.sds);
     p.sthr = reinterpret_cast<float *>(w + R.sthr);
     p.snb = reinterpret_cast<float *>(w + R.snb);
-    p.thr = reinterpret_cast<float *>(w + R.thr);
     p.R64 = reinterpret_cast<double *>(w + R.R64);
     p.part = w + R.part;
     p.part_i = reinterpret_cast<int32_t *>(w + R.part_i);
@@ -1278,13 +1027,8 @@ static RcPtrs rc_ptrs(const RcLayout &R, void *ws) {
     p.bnd = reinterpret_cast<double *>(w + R.bnd);
     p.st = reinterpret_cast<DevState *>(w + R.state);
     p.acur = reinterpret_cast<double *>(w + R.acur);
-    p.ecur = reinterpret_cast<double *>(w + R.ecur);
     p.lold = reinterpret_cast<double *>(w + R.lold);
     p.lnew = reinterpret_cast<double *>(w + R.lnew);
-    p.res_a = reinterpret_cast<double *>(w + R.res_a);
-    p.lnb = reinterpret_cast<float *>(w + R.lnb);
-    p.llo = reinterpret_cast<float *>(w + R.llo);
-    p.lhi = reinterpret_cast<float *>(w + R.lhi);
     return p;
 }
 
@@ -1325,85 +1069,38 @@ hipError_t rc_prep_build(const float *X, int32_t dim, const RcLayout &R, int32_t
     rc_fill<double>(p.dn64, n, __builtin_huge_val(), s);
     rc_fill<float>(p.dn32, n, __builtin_huge_valf(), s);
     const int nmwg = (int)((n + 255) / 256);
-    // FP64 sums: the first two steps are full passes, later steps incremental
-    // (dn ping-pongs between the dn and ds buffers, free until SWAP)
+    const unsigned nblk = (unsigned)R.n_oblk;
+    // object chunks of the FP64 passes: about two work-groups per CU for the
+    // full steps, four chunks for the short lists of later steps
+    const int64_t nct = (n + 255) / 256;
+    int32_t qf = (int32_t)(512 / nct);
+    if (qf < 1) qf = 1;
+    if (qf > R.Q * 4) qf = R.Q * 4;   // the partial buffer holds 4 Q rows
+    const int32_t qd = 4 <= R.Q * 4 ? 4 : 1;
+    // dn ping-pongs between the dn and ds buffers (free until SWAP)
     double *d64b[2] = {p.dn64, p.ds64};
     float *d32b[2] = {p.dn32, p.ds32};
     int cur = 0;
-    // full pass from scratch: thresholds, bounds, pass, merge (gate = run only
-    // when the device state asks for a refresh; nullptr = always)
-    auto full_step = [&](int32_t t, int add_self, DevState *gate) {
-        hipLaunchKernelGGL(k_rc_build_thr, dim3(ob), dim3(256), 0, s, (const float *)d32b[cur], n,
-                           (const double *)p.eps0, p.thr, (const DevState *)gate);
-        hipLaunchKernelGGL(k_rc_build_bounds, dim3(1), dim3(1024), 0, s, (const double *)d64b[cur],
-                           n, R.L, R.Q, (int32_t)(t == 0), (int32_t)acc64, (const double *)p.eps0,
-                           p.bnd, (const DevState *)gate, (int32_t)1);
-        if (acc64) {
-            rc_build_pass_any<double>(p, R, n, d32b[cur], gate, s);
-            hipLaunchKernelGGL(k_rc_build_merge<double>, dim3(nmwg), dim3(256), 0, s,
-                               (const double *)p.part, (const int32_t *)p.part_i, R.Q, R.ncp, n,
-                               (const double *)d64b[cur], (const uint8_t *)p.is_med, add_self,
-                               (const double *)p.bnd, p.cand_v, p.cand_b, p.wg_u, p.acur, p.ecur,
-                               gate);
-        } else {
-            rc_build_pass_any<float>(p, R, n, d32b[cur], gate, s);
-            hipLaunchKernelGGL(k_rc_build_merge<float>, dim3(nmwg), dim3(256), 0, s,
-                               (const float *)p.part, (const int32_t *)p.part_i, R.Q, R.ncp, n,
-                               (const double *)d64b[cur], (const uint8_t *)p.is_med, add_self,
-                               (const double *)p.bnd, p.cand_v, p.cand_b, p.wg_u,
-                               (double *)nullptr, (double *)nullptr, gate);
-        }
-    };
     for (int32_t t = 0; t < k; ++t) {
         const int add_self = (opt.build_exclude_self && t > 0) ? 1 : 0;
-        if (!acc64 || t < 2) {
-            full_step(t, add_self, nullptr);
+        const bool full = t < 2;
+        if (full) {
+            rc64_build_pass(p, R, X, dim, n, nullptr, nullptr, d64b[cur], qf, s);
         } else {
-            // incremental step (skipped on the device when a refresh was asked for) ...
-            hipLaunchKernelGGL(k_rc_build_bounds, dim3(1), dim3(1024), 0, s,
-                               (const double *)d64b[cur ^ 1], n, R.L, R.Q, (int32_t)0, (int32_t)1,
-                               (const double *)p.eps0, p.bnd, (const DevState *)p.st, (int32_t)0);
-            hipLaunchKernelGGL(k_rc_build_compact, dim3((unsigned)R.n_oblk), dim3(kObjBlk), 0, s,
-                               (const double *)d64b[cur ^ 1], (const double *)d64b[cur],
-                               (const float *)p.nb, n, (const int32_t *)p.blkcnt, R.n_oblk,
-                               (const double *)p.eps0, p.srow, p.lold, p.lnew, p.lnb, p.llo, p.lhi,
-                               p.st);
-            rc_build_delta_any(p, R, n, s);
-            hipLaunchKernelGGL(k_rc_build_dmerge, dim3(nmwg), dim3(256), 0, s,
-                               (const double *)p.part, (const int32_t *)p.part_i, R.Q, R.ncp, n,
-                               (const double *)d64b[cur], (const uint8_t *)p.is_med, add_self,
-                               (const double *)p.bnd, (const DevState *)p.st, p.acur, p.ecur,
-                               p.cand_v, p.cand_b, p.wg_u);
-            // ... or the full pass that resets every running bound
-            full_step(t, add_self, p.st);
+            hipLaunchKernelGGL(k_rc64_compact, dim3(nblk), dim3(kObjBlk), 0, s,
+                               (const double *)d64b[cur ^ 1], (const double *)d64b[cur], n,
+                               (const int32_t *)p.blkcnt, R.n_oblk, p.srow, p.lold, p.lnew, p.st);
+            rc64_build_pass(p, R, X, dim, n, p.srow, p.lold, p.lnew, qd, s);
         }
-        hipLaunchKernelGGL(k_rc_upper, dim3(1), dim3(1024), 0, s, (const double *)p.wg_u, nmwg, p.st);
-        hipLaunchKernelGGL(k_rc_mark, dim3(nmwg), dim3(256), 0, s, (const double *)p.cand_v,
-                           (const double *)p.cand_b, n, 0, p.list, p.st);
-        {
-            const hipError_t e = rc_rescore(R.KP, false, X, dim, n, k, nullptr, (const double *)d64b[cur],
-                                            nullptr, nullptr, nullptr, add_self, (const int32_t *)p.list,
-                                            (const DevState *)p.st, p.res_v, p.res_a, nullptr, s);
-            if (e != hipSuccess) return e;
-        }
-        hipLaunchKernelGGL(k_rc_pick, dim3(1), dim3(1024), 0, s, (const double *)p.res_v,
-                           (const int32_t *)p.res_i, (const int32_t *)p.list, 0, t, medoids, p.is_med,
-                           p.st, (pamx_swap_record *)nullptr);
-        if (acc64)
-            hipLaunchKernelGGL(k_rc_reanchor, dim3(64), dim3(256), 0, s, (const int32_t *)p.list,
-                               (const double *)p.res_a, (const DevState *)p.st, n, p.acur, p.ecur);
-        if (t == 0) {
-            hipLaunchKernelGGL(k_rc_build_update<true>, dim3(ob), dim3(256), 0, s, X, dim, n, p.dn64,
-                               p.dn32, (const DevState *)p.st);
-        } else if (acc64) {
-            hipLaunchKernelGGL(k_rc_build_update2, dim3((unsigned)R.n_oblk), dim3(kObjBlk), 0, s, X,
-                               dim, n, (const double *)d64b[cur], d64b[cur ^ 1], d32b[cur ^ 1],
-                               (const DevState *)p.st, p.blkcnt);
-            cur ^= 1;
-        } else {
-            hipLaunchKernelGGL(k_rc_build_update<false>, dim3(ob), dim3(256), 0, s, X, dim, n, p.dn64,
-                               p.dn32, (const DevState *)p.st);
-        }
+        hipLaunchKernelGGL(k_rc64_build_merge, dim3(nmwg), dim3(256), 0, s,
+                           (const double *)p.part, full ? qf : qd, R.ncp, n, (int32_t)full, p.acur,
+                           (const double *)d64b[cur], (const uint8_t *)p.is_med, add_self, p.wg_u,
+                           p.res_i);
+        hipLaunchKernelGGL(k_rc64_select_update, dim3(nblk), dim3(kObjBlk), 0, s,
+                           (const double *)p.wg_u, (const int32_t *)p.res_i, nmwg, t, medoids,
+                           p.is_med, X, dim, n, (const double *)d64b[cur], d64b[cur ^ 1],
+                           d32b[cur ^ 1], p.st, p.blkcnt);
+        cur ^= 1;
     }
     if (cur == 1) {   // the caller reads dn from the dn buffers
         hipLaunchKernelGGL(k_rc_copy<double>, dim3(ob), dim3(256), 0, s, (const double *)p.ds64,
@@ -1484,15 +1181,15 @@ hipError_t rc_swap_iteration(const float *X, int32_t dim, const RcLayout &R, int
     hipLaunchKernelGGL(k_rc_mark, dim3(nmwg), dim3(256), 0, s, (const double *)p.cand_v,
                        (const double *)p.cand_b, n, 1, p.list, p.st);
     {
-        const hipError_t e = rc_rescore(R.KP, true, X, dim, n, k, (const int32_t *)p.srow,
+        const hipError_t e = rc_rescore(R.KP, X, dim, n, k, (const int32_t *)p.srow,
                                         (const double *)p.dn64, (const double *)p.ds64,
-                                        (const int32_t *)p.near, (const double *)p.R64, 0,
+                                        (const int32_t *)p.near, (const double *)p.R64,
                                         (const int32_t *)p.list, (const DevState *)p.st, p.res_v,
-                                        nullptr, p.res_i, s);
+                                        p.res_i, s);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_rc_pick, dim3(1), dim3(1024), 0, s, (const double *)p.res_v,
-                       (const int32_t *)p.res_i, (const int32_t *)p.list, 1, 0, medoids, p.is_med, p.st,
+                       (const int32_t *)p.res_i, (const int32_t *)p.list, medoids, p.is_med, p.st,
                        static_cast<pamx_swap_record *>(opt.trace));
     hipLaunchKernelGGL(k_rc_reset_list, dim3(1), dim3(1), 0, s, p.st);
     hipLaunchKernelGGL(k_rc_cache_update, dim3(ob), dim3(256), 0, s, X, dim, n, p.near, p.sec, p.dn64,
