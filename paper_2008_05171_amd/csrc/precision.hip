@@ -45,6 +45,37 @@ __device__ __forceinline__ double d64(const float *__restrict__ X, int dim, int6
     const float *x = X + a * dim;
     const float *y = X + b * dim;
     double s = 0.0;
+    if ((dim & 3) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0) {
+        // rows are 16-byte aligned: 16-byte loads, same FMA order
+        const float4 *x4 = reinterpret_cast<const float4 *>(x);
+        const float4 *y4 = reinterpret_cast<const float4 *>(y);
+        const int d4 = dim >> 2;
+#pragma unroll
+        for (int k0 = 0; k0 < kRcMaxDim / 4; k0 += 4) {
+            if (k0 < d4) {
+                float4 xv[4], yv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int kk = min(k0 + u, d4 - 1);
+                    xv[u] = x4[kk];
+                    yv[u] = y4[kk];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool in = k0 + u < d4;
+                    const double t0 = in ? (double)xv[u].x - (double)yv[u].x : 0.0;
+                    const double t1 = in ? (double)xv[u].y - (double)yv[u].y : 0.0;
+                    const double t2 = in ? (double)xv[u].z - (double)yv[u].z : 0.0;
+                    const double t3 = in ? (double)xv[u].w - (double)yv[u].w : 0.0;
+                    s = fma(t0, t0, s);
+                    s = fma(t1, t1, s);
+                    s = fma(t2, t2, s);
+                    s = fma(t3, t3, s);
+                }
+            }
+        }
+        return sqrt(s);
+    }
 #pragma unroll
     for (int k0 = 0; k0 < kRcMaxDim; k0 += 16) {
         if (k0 < dim) {
@@ -456,8 +487,10 @@ __global__ __launch_bounds__(256) void k_rc_mark(const double *__restrict__ cand
 // walks a contiguous range of the sorted objects; segments complete in its
 // range go to LDS directly, the partial first/last ones are combined
 // afterwards in thread order.
+constexpr int kRsT = 256;    // threads per re-scored candidate
+
 template <int KS>
-__global__ __launch_bounds__(256) void k_rc_swap_rescore(
+__global__ __launch_bounds__(kRsT) void k_rc_swap_rescore(
     const float *__restrict__ X, int32_t dim, int64_t n, int32_t k, const int32_t *__restrict__ srow,
     const double *__restrict__ dn64, const double *__restrict__ ds64,
     const int32_t *__restrict__ near, const double *__restrict__ R64,
@@ -465,14 +498,14 @@ __global__ __launch_bounds__(256) void k_rc_swap_rescore(
     double *__restrict__ res_v, int32_t *__restrict__ res_i) {
     extern __shared__ __align__(16) unsigned char rs_raw[];
     double *sarr = reinterpret_cast<double *>(rs_raw);          // k per-slot sums
-    __shared__ double hv[256], tv[256], red[256];
-    __shared__ int hs[256], ts[256], ri[256];
+    __shared__ double hv[kRsT], tv[kRsT], red[kRsT];
+    __shared__ int hs[kRsT], ts[kRsT], ri[kRsT];
     const int t = threadIdx.x;
     const int m = st->n_list;
-    const int64_t per = (n + 255) / 256;
+    const int64_t per = (n + kRsT - 1) / kRsT;
     for (int idx = blockIdx.x; idx < m; idx += gridDim.x) {
         const int64_t c = list[idx];
-        for (int i = t; i < k; i += 256) sarr[i] = 0.0;
+        for (int i = t; i < k; i += kRsT) sarr[i] = 0.0;
         __syncthreads();
         const int64_t j0 = min(n, (int64_t)t * per), j1 = min(n, j0 + per);
         double B = 0.0, S = 0.0, first = 0.0;
@@ -501,7 +534,7 @@ __global__ __launch_bounds__(256) void k_rc_swap_rescore(
         if (t == 0) {
             int rs = -1;
             double rm = 0.0;
-            for (int u = 0; u < 256; ++u) {
+            for (int u = 0; u < kRsT; ++u) {
                 if (hs[u] >= 0) {
                     if (hs[u] == rs) rm += hv[u];
                     else { if (rs >= 0) sarr[rs] += rm; rs = hs[u]; rm = hv[u]; }
@@ -513,7 +546,7 @@ __global__ __launch_bounds__(256) void k_rc_swap_rescore(
             }
             if (rs >= 0) sarr[rs] += rm;
         }
-        for (int w = 128; w > 0; w >>= 1) {
+        for (int w = kRsT / 2; w > 0; w >>= 1) {
             __syncthreads();
             if (t < w) red[t] += red[t + w];
         }
@@ -521,13 +554,13 @@ __global__ __launch_bounds__(256) void k_rc_swap_rescore(
         // best slot: smallest R_i + S_i, smallest i on ties
         double bv = __builtin_huge_val();
         int bi = INT_MAX;
-        for (int i = t; i < k; i += 256) {
+        for (int i = t; i < k; i += kRsT) {
             const double v = R64[i] + sarr[i];
             if (v < bv) { bv = v; bi = i; }
         }
         hv[t] = bv; ri[t] = bi;
         __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
+        for (int w = kRsT / 2; w > 0; w >>= 1) {
             if (t < w && lt2(hv[t + w], ri[t + w], hv[t], ri[t])) { hv[t] = hv[t + w]; ri[t] = ri[t + w]; }
             __syncthreads();
         }
@@ -542,7 +575,13 @@ static hipError_t rc_rescore_launch(const float *X, int32_t dim, int64_t n, int3
                                     const int32_t *near, const double *R64, const int32_t *list,
                                     const DevState *st, double *res_v, int32_t *res_i,
                                     hipStream_t s) {
-    hipLaunchKernelGGL((k_rc_swap_rescore<KS>), dim3(1024), dim3(256), (size_t)k * 8, s, X, dim, n, k,
+    const size_t lds = (size_t)k * 8;   // the per-slot sums, beside 9 KB of fixed LDS
+    if (lds > 49152) {
+        const hipError_t e = hipFuncSetAttribute((const void *)k_rc_swap_rescore<KS>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_rc_swap_rescore<KS>), dim3(1024), dim3(kRsT), lds, s, X, dim, n, k,
                        srow, dn64, ds64, near, R64, list, st, res_v, res_i);
     return hipGetLastError();
 }
