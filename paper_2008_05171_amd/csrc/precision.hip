@@ -853,10 +853,24 @@ __global__ __launch_bounds__(256) void k_rc64_build_pass(
     for (int64_t j0 = a; j0 < b; j0 += kB64Tile) {
         const int cnt = (int)min((int64_t)kB64Tile, b - j0);
         __syncthreads();
-        for (int e = tid; e < cnt * dim; e += 256) {
+        // all loads of the tile first (clamped, always valid), then the stores
+        constexpr int kIt = (kB64Tile * MD + 255) / 256;
+        float v[kIt];
+        const int tot = cnt * dim;
+#pragma unroll
+        for (int u = 0; u < kIt; ++u) {
+            const int e = min(tid + u * 256, tot - 1);
             const int r = e / dim, kk = e - r * dim;
             const int64_t o = rows ? (int64_t)rows[j0 + r] : j0 + r;
-            xs[r][kk] = (double)X[o * dim + kk];
+            v[u] = X[o * dim + kk];
+        }
+#pragma unroll
+        for (int u = 0; u < kIt; ++u) {
+            const int e = tid + u * 256;
+            if (e < tot) {
+                const int r = e / dim, kk = e - r * dim;
+                xs[r][kk] = (double)v[u];
+            }
         }
         if (tid < cnt) {
             vn[tid] = vnew[j0 + tid];
