@@ -794,7 +794,7 @@ __global__ __launch_bounds__(kWG) void k_swap_pass(
                 const A v = M[e] - dns;
                 if (v < bv[e]) { bv[e] = v; bi[e] = s; }
                 if constexpr (P2) {
-                    if (active) P[(int64_t)s * ncp + c0 + e] = v;
+                    if (active) __builtin_nontemporal_store(v, &P[(int64_t)s * ncp + c0 + e]);
                 }
             }
         }
