@@ -66,6 +66,18 @@ extern "C" {
 /* SWAP variants */
 #define PAMX_FASTPAM1 1 /* best swap per iteration (Alg. 3)               */
 #define PAMX_FASTPAM2 2 /* best swap per medoid, applied eagerly (Sec. 3.2) */
+#define PAMX_FASTERPAM 3 /* FasterPAM (Alg. 4, Sec. 3.3): the candidates are
+                            visited in index order, cyclically; each takes its
+                            best slot (smallest on ties) and is swapped in at
+                            once when that lowers TD; the run ends after a
+                            full cycle of n positions without a swap.  The
+                            device scores a window of consecutive candidates
+                            in one pass and applies the first improving one,
+                            which is the swap the sequential scan makes, so
+                            the swaps are Alg. 4's exactly (PAMX_I32) or
+                            with FP64 sums of the FP32 matrix (PAMX_F32, a
+                            swap taken when its change is below minus the
+                            summation bound).  max_iter caps the passes. */
 
 /* accumulation of the loss changes for PAMX_F32 dissimilarities */
 #define PAMX_ACC_F64 0 /* FP64 sums (default)                              */
@@ -103,7 +115,8 @@ extern "C" {
 typedef struct pamx_options {
     int32_t variant;            /* PAMX_FASTPAM1 (default) or PAMX_FASTPAM2   */
     int32_t accum;              /* PAMX_ACC_F64 (default) or PAMX_ACC_F32     */
-    int32_t max_iter;           /* SWAP iterations (searches) cap; default 10000 */
+    int32_t max_iter;           /* SWAP iterations (searches; FasterPAM: passes
+                                   over the candidates) cap; default 10000  */
     int32_t build_exclude_self; /* 0 (default): a BUILD candidate's own drop to
                                    distance 0 counts in its change, so each step
                                    adds the point that lowers TD most; 1: the
@@ -124,6 +137,9 @@ typedef struct pamx_options {
                                    every kernel launched directly (measured
                                    faster: a replay costs more than the launches
                                    it replaces)                              */
+    int32_t window;             /* PAMX_FASTERPAM: candidates scored per pass
+                                   (rounded up to whole 1024- or 256-candidate
+                                   tiles); 0 (default) = automatic           */
     void *trace;                /* optional DEVICE array of pamx_swap_record:
                                    every applied swap in order               */
 } pamx_options;
@@ -135,7 +151,8 @@ typedef struct pamx_swap_record {
 } pamx_swap_record;
 
 typedef struct pamx_stats {
-    int32_t iterations; /* SWAP searches performed (PAM: swaps + 1 when converged) */
+    int32_t iterations; /* SWAP searches performed (PAM: swaps + 1 when converged;
+                           FasterPAM: passes over the candidates begun) */
     int32_t swaps;      /* swaps applied */
     int32_t converged;  /* 1 if the last search found no improving swap */
     int32_t rescored;   /* candidates scored again in FP64 (PAMX_ACC_F32) */
@@ -155,6 +172,10 @@ typedef struct pamx_stats {
     int64_t build_rows;    /* matrix rows read by the incremental BUILD passes */
     int32_t n_build_delta; /* profile=1: incremental BUILD pass launches */
     int32_t chunk;         /* object chunk length of the SWAP passes */
+    int64_t scan_positions;/* PAMX_FASTERPAM: candidate positions visited
+                              (iterations = passes begun = ceil(positions / n)) */
+    int32_t windows;       /* PAMX_FASTERPAM: window passes run */
+    int32_t window;        /* PAMX_FASTERPAM: candidates per window pass */
 } pamx_stats;
 
 /* Fills `opt` with the defaults listed above. */

@@ -12,8 +12,10 @@ only builds it (gcc) and marshals numpy arrays.  Paper references
 * ``nearest``/``td``-- nearest/second-nearest caches and Eq. td.
 * ``change``        -- Eq. change, the per-object loss change of a swap.
 * ``delta``         -- Delta TD of one swap, Eq. td2 summed with Eq. change.
-* ``swap``          -- PAM SWAP, Alg. 2 (variant 1), or the FastPAM2 reading
-                       (variant 2: best swap per medoid, applied eagerly).
+* ``swap``          -- PAM SWAP, Alg. 2 (variant 1), the FastPAM2 reading
+                       (variant 2: best swap per medoid, applied eagerly), or
+                       FasterPAM, Alg. 4 (variant 3: the first candidate in scan
+                       order with an improving swap, applied at once).
 * ``pam``           -- BUILD followed by SWAP, with labels.
 """
 from __future__ import annotations
@@ -33,6 +35,7 @@ L1 = 1
 L2 = 2
 PAM = 1          # best swap per iteration (PAM == FastPAM1 result)
 FASTPAM2 = 2     # best swap per medoid, applied eagerly
+FASTERPAM = 3    # Alg. 4: eager swap of each improving candidate in scan order
 
 _lib = None
 
@@ -254,7 +257,7 @@ class PamResult:
 
 
 def pam(k, D=None, X=None, metric=L2, variant=PAM, exclude_self=False, max_iter=10000):
-    """BUILD (Alg. 1) then SWAP (Alg. 2 or the FastPAM2 reading)."""
+    """BUILD (Alg. 1) then SWAP (Alg. 2, the FastPAM2 reading or Alg. 4)."""
     bm, td_b, _ = build(k, D=D, X=X, metric=metric, exclude_self=exclude_self)
     r = swap(bm, D=D, X=X, metric=metric, variant=variant, max_iter=max_iter)
     tdv, labels = td(r.medoids, D=D, X=X, metric=metric)

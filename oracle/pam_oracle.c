@@ -41,6 +41,18 @@
  *      negative change.
  *   R6 k == 1: SWAP is not run (the second-nearest distance does not exist);
  *      BUILD's first medoid is the medoid of the whole set (Eq. def-medoid).
+ *   R7 FasterPAM (Alg. 4), with the misprints of its listing read as fixed:
+ *      the candidate that was swapped in is the one remembered as the last
+ *      swap, and a scan that has made no swap at all ends after one full
+ *      pass.  Candidates are visited in ascending index order, cyclically,
+ *      current medoids skipped.  For the visited candidate c every slot's
+ *      change Delta(i, c) is evaluated against the current medoids (the sum
+ *      of Eq. change, which Alg. 4 computes as the removal loss plus the
+ *      shared accumulator); i* is the smallest slot with the minimum, and the
+ *      swap (i*, c) is applied at once when its change is negative.  The run
+ *      ends when n consecutive positions have been visited without a swap
+ *      (the scan is back at the last swap's position).  Iterations count the
+ *      passes begun: ceil(positions visited / n).
  */
 #include <math.h>
 #include <stdint.h>
@@ -473,9 +485,11 @@ int orc_build_list(const double *D, const double *X, int64_t n, int32_t dim, int
 }
 
 /* ------------------------------------------------------------------ */
-/* PAM SWAP (Alg. 2), and the FastPAM2 reading R5.                      */
+/* PAM SWAP (Alg. 2), the FastPAM2 reading R5 and FasterPAM (R7).     */
 /*   variant 1 = best swap per iteration (PAM; FastPAM1 gives the same) */
 /*   variant 2 = best swap per medoid, applied eagerly (reading R5)     */
+/*   variant 3 = FasterPAM, Alg. 4: first improving candidate in scan   */
+/*               order, its best slot, applied at once (reading R7)     */
 /* med is read (slot order) and overwritten with the result.            */
 /* trace_* (optional, capacity trace_cap) receive every applied swap.   */
 /* ------------------------------------------------------------------ */
@@ -486,7 +500,7 @@ int orc_swap(const double *D, const double *X, int64_t n, int32_t dim, int32_t m
 {
     src_t s;
     if (make_src(&s, D, X, n, dim, metric) || !med || k < 1 || k > n ||
-        (variant != 1 && variant != 2) || max_iter < 0)
+        variant < 1 || variant > 3 || max_iter < 0)
         return ORC_ERR_ARG;
     unsigned char *is_med = (unsigned char *)calloc((size_t)n, 1);
     if (!is_med) return ORC_ERR_MEM;
@@ -512,7 +526,43 @@ int orc_swap(const double *D, const double *X, int64_t n, int32_t dim, int32_t m
     double td = 0.0;
     for (int64_t o = 0; o < n; ++o) td += dn[o];
 
-    while (k >= 2 && k < n) {
+    if (variant == 3 && k >= 2 && k < n) {
+        /* reading R7: one candidate at a time, in scan order */
+        int64_t pos = 0, visited = 0, quiet = 0;
+        while (quiet < n) {
+            if (visited == (int64_t)max_iter * n) { rc = ORC_WARN_MAXITER; break; }
+            const int64_t c = pos;
+            pos = (pos + 1 == n) ? 0 : pos + 1;
+            ++visited;
+            ++quiet;
+            if (is_med[c]) continue;
+            #pragma omp parallel for schedule(static) if (k >= 8)
+            for (int32_t i = 0; i < k; ++i)
+                bdel[i] = delta_swap(&s, med, k, is_med, near, dn, ds, i, c);
+            int32_t bi = 0;
+            for (int32_t i = 1; i < k; ++i)
+                if (bdel[i] < bdel[bi]) bi = i;
+            const double bd = bdel[bi];
+            if (!(bd < 0.0)) continue;
+            is_med[med[bi]] = 0;
+            med[bi] = (int32_t)c;
+            is_med[c] = 1;
+            td += bd;
+            if (trace_slot && swaps < trace_cap) {
+                trace_slot[swaps] = bi; trace_c[swaps] = c; trace_delta[swaps] = bd;
+            }
+            ++swaps;
+            quiet = 0;
+            nearest_all(&s, med, k, near, dn, ds);
+            double fresh = 0.0;
+            for (int64_t o = 0; o < n; ++o) fresh += dn[o];
+            if (!td_matches(td, fresh)) { rc = ORC_ERR_TD; break; }
+            td = fresh;
+        }
+        iters = (int32_t)((visited + n - 1) / n);
+    }
+
+    while (variant != 3 && k >= 2 && k < n) {
         if (iters >= max_iter) { rc = ORC_WARN_MAXITER; break; }
         ++iters;
         swap_table(&s, med, k, is_med, near, dn, ds, 0, n, tab);

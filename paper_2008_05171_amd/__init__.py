@@ -1,4 +1,5 @@
-"""MI355X-native k-medoids: PAM BUILD with FastPAM1 / eager FastPAM2 SWAP.
+"""MI355X-native k-medoids: PAM BUILD with FastPAM1 / eager FastPAM2 /
+FasterPAM SWAP.
 
 Schubert & Rousseeuw, "Fast and Eager k-Medoids Clustering: O(k) Runtime
 Improvement of the PAM, CLARA, and CLARANS Algorithms", arXiv 2008.05171.
@@ -13,15 +14,25 @@ from dataclasses import dataclass, field
 
 from . import pamx as _abi
 from .pamx import (PAMX_ACC_F32, PAMX_ACC_F64, PAMX_CHUNK_TUNE, PAMX_DIST_BF16, PAMX_DIST_STORED,
-                   PAMX_FASTPAM1,
+                   PAMX_FASTERPAM, PAMX_FASTPAM1,
                    PAMX_FASTPAM2, PAMX_INPUT_D, PAMX_INPUT_X, PAMX_L1, PAMX_L2, PamxError)
 
 __all__ = ["fit", "build", "swap", "dist", "fit_batched", "FitResult", "BatchResult", "PamxError", "PAMX_FASTPAM1",
-           "PAMX_FASTPAM2", "PAMX_L1", "PAMX_L2", "PAMX_ACC_F64", "PAMX_ACC_F32",
+           "PAMX_FASTPAM2", "PAMX_FASTERPAM", "PAMX_L1", "PAMX_L2", "PAMX_ACC_F64", "PAMX_ACC_F32",
            "PAMX_INPUT_D", "PAMX_INPUT_X", "PAMX_CHUNK_TUNE"]
 
-_VARIANTS = {"fastpam1": PAMX_FASTPAM1, "fastpam2": PAMX_FASTPAM2,
-             PAMX_FASTPAM1: PAMX_FASTPAM1, PAMX_FASTPAM2: PAMX_FASTPAM2}
+_VARIANTS = {"fastpam1": PAMX_FASTPAM1, "fastpam2": PAMX_FASTPAM2, "fasterpam": PAMX_FASTERPAM,
+             PAMX_FASTPAM1: PAMX_FASTPAM1, PAMX_FASTPAM2: PAMX_FASTPAM2,
+             PAMX_FASTERPAM: PAMX_FASTERPAM}
+
+
+def _trace_cap(variant, max_iter, n, k):
+    """Swap records to reserve: one per search (FastPAM1), k per search
+    (FastPAM2), for FasterPAM up to four per object."""
+    v = _VARIANTS[variant]
+    if v == PAMX_FASTERPAM:
+        return 4 * n + 16
+    return max_iter * (k if v == PAMX_FASTPAM2 else 1) + 16
 
 
 @dataclass
@@ -39,9 +50,10 @@ _DIST = {"stored": PAMX_DIST_STORED, "bf16": PAMX_DIST_BF16,
 
 
 def _options(variant="fastpam1", accum=PAMX_ACC_F64, max_iter=10000, exclude_self=False,
-             chunk=0, trace_buf=None, trace_cap=0, dist_mode="stored", graph=False):
+             chunk=0, trace_buf=None, trace_cap=0, dist_mode="stored", graph=False, window=0):
     o = _abi.pamx_default_options()
     o.graph = int(bool(graph))
+    o.window = int(window)
     o.dist_mode = _DIST[dist_mode]
     o.variant = _VARIANTS[variant]
     o.accum = int(accum)
@@ -75,7 +87,7 @@ def _stats_dict(st):
 
 def fit(data, k, *, input_kind=PAMX_INPUT_X, metric=None, variant="fastpam1",
         accum=PAMX_ACC_F64, max_iter=10000, exclude_self=False, trace=False, chunk=0,
-        dist_mode="stored", graph=False, stream=None) -> FitResult:
+        dist_mode="stored", graph=False, window=0, stream=None) -> FitResult:
     """Distances (for points), BUILD, SWAP, labels and TD on the GPU.
 
     data: device tensor, n x dim points (int32 -> L1, float32 -> L2) or an
@@ -83,16 +95,19 @@ def fit(data, k, *, input_kind=PAMX_INPUT_X, metric=None, variant="fastpam1",
     dist_mode="bf16": the mixed-precision form (no matrix; BF16 Gram
     distances, FP32 sums, FP64 re-scoring of every possible best swap).
     chunk: objects per pass work-group, 0 = automatic, PAMX_CHUNK_TUNE = timed
-    once per process and shape on this matrix (stats["chunk"] reports it)."""
+    once per process and shape on this matrix (stats["chunk"] reports it).
+    variant="fasterpam": Alg. 4; window = candidates scored per pass (0 =
+    automatic)."""
     import torch
     n = data.shape[0]
     dim = data.shape[1] if input_kind == PAMX_INPUT_X else 0
     dtype = _abi._dtype_code(data)
     if metric is None:
         metric = PAMX_L1 if dtype == _abi.PAMX_I32 else PAMX_L2
-    cap = (max_iter * (k if variant in ("fastpam2", PAMX_FASTPAM2) else 1) + 16) if trace else 0
+    cap = _trace_cap(variant, max_iter, n, k) if trace else 0
     tbuf = torch.empty(cap * 16, dtype=torch.uint8, device=data.device) if trace else None
-    opt = _options(variant, accum, max_iter, exclude_self, chunk, tbuf, cap, dist_mode, graph)
+    opt = _options(variant, accum, max_iter, exclude_self, chunk, tbuf, cap, dist_mode, graph,
+                   window)
     nbytes = _abi.pamx_workspace_bytes(n, k, dim, input_kind, dtype, opt)
     ws = _workspace(nbytes, data.device)
     med = torch.empty(k, dtype=torch.int32, device=data.device)
@@ -115,14 +130,14 @@ def build(D, k, *, exclude_self=False, stream=None):
 
 
 def swap(D, medoids, *, variant="fastpam1", accum=PAMX_ACC_F64, max_iter=10000, trace=False,
-         chunk=0, graph=False, stream=None) -> FitResult:
+         chunk=0, graph=False, window=0, stream=None) -> FitResult:
     """SWAP from the given medoids (device int32 tensor, slot order; copied)."""
     import torch
     n = D.shape[0]
     k = int(medoids.numel())
-    cap = (max_iter * (k if variant in ("fastpam2", PAMX_FASTPAM2) else 1) + 16) if trace else 0
+    cap = _trace_cap(variant, max_iter, n, k) if trace else 0
     tbuf = torch.empty(cap * 16, dtype=torch.uint8, device=D.device) if trace else None
-    opt = _options(variant, accum, max_iter, False, chunk, tbuf, cap, graph=graph)
+    opt = _options(variant, accum, max_iter, False, chunk, tbuf, cap, graph=graph, window=window)
     nbytes = _abi.pamx_workspace_bytes(n, k, 0, PAMX_INPUT_D, _abi._dtype_code(D), opt)
     ws = _workspace(nbytes, D.device)
     med = medoids.to(device=D.device, dtype=torch.int32).clone()

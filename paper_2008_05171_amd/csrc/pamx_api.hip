@@ -93,6 +93,25 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->n_oblk = (int32_t)((n + kObjBlk - 1) / kObjBlk);
     L->n_mwg = (int32_t)((n + kWG - 1) / kWG);
     const bool p2 = opt && opt->variant == PAMX_FASTPAM2;
+    if (opt && opt->variant == PAMX_FASTERPAM) {
+        // window: the requested width rounded up to whole tiles, else about a
+        // sixteenth of the candidates; its pass is chunked to about two
+        // work-groups per compute unit
+        int64_t m = (opt->window > 0) ? (opt->window + L->tile - 1) / L->tile : L->n_ctiles / 16;
+        if (m < 1) m = 1;
+        if (m > L->n_ctiles) m = L->n_ctiles;
+        if (m > 256) m = 256;
+        L->fw = (int32_t)(m * L->tile);
+        int64_t Q = 512 / m;
+        const int64_t qmax = (n + 63) / 64;
+        if (Q > qmax) Q = qmax;
+        if (Q < 1) Q = 1;
+        int64_t Lw = (n + Q - 1) / Q;
+        Lw = (Lw + 7) & ~int64_t(7);
+        if (Lw > n) Lw = n;
+        L->fwL = (int32_t)Lw;
+        L->fwQ = (int32_t)((n + Lw - 1) / Lw);
+    }
 
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = up256(off + (bytes ? bytes : 1)); return o; };
@@ -115,9 +134,10 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->cand_v = take(8);
     L->cand_i = take(8);
     L->cand_a = take((size_t)L->ncp * 8);
-    L->wg_v = take((size_t)L->n_mwg * 8);
-    L->wg_i = take((size_t)L->n_mwg * 4);
-    L->wg_c = take((size_t)L->n_mwg * 4);
+    const size_t nwg = (size_t)(L->ncp / kWG);   // >= n_mwg; a window's merge blocks
+    L->wg_v = take(nwg * 8);
+    L->wg_i = take(nwg * 4);
+    L->wg_c = take(nwg * 4);
     L->P = p2 ? take((size_t)k * L->ncp * 8) : SIZE_MAX;
     L->slot_v = take((size_t)k * 8);
     L->slot_c = take((size_t)k * 4);
@@ -133,7 +153,7 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
 
 // The regions whose size depends on the number of object chunks Q come last,
 // so the chunk length can change between BUILD and SWAP (chunk tuning).
-void set_chunk(Layout *L, int32_t Lc) {
+static void place_tail(Layout *L, int32_t Lc, int64_t cols) {
     if (Lc > L->n) Lc = (int32_t)L->n;
     if (Lc < 1) Lc = 1;
     L->L = Lc;
@@ -142,10 +162,12 @@ void set_chunk(Layout *L, int32_t Lc) {
     auto take = [&](size_t bytes) { size_t o = off; off = up256(off + (bytes ? bytes : 1)); return o; };
     L->blkbase = take((size_t)L->Q * 16);            // chunk carry map
     L->cdn = take((size_t)L->Q * 2 * 8);              // DN parts of carried segments
-    L->part = take((size_t)L->Q * 4 * L->ncp * 8);
-    L->part_i = take((size_t)L->Q * L->ncp * 4);
+    L->part = take((size_t)L->Q * 4 * cols * 8);
+    L->part_i = take((size_t)L->Q * cols * 4);
     L->total = off;
 }
+void set_chunk(Layout *L, int32_t Lc) { place_tail(L, Lc, L->ncp); }
+void set_window(Layout *L) { place_tail(L, L->fwL, L->fw); }
 
 // Chunk lengths tried by the tuner: pass grids at or just below about 1, 1.5,
 // 2, 3, 4, 6 and 8 work-groups per compute unit.
@@ -168,6 +190,11 @@ std::vector<int32_t> tune_chunks(const Layout &L) {
 // Workspace bytes for L: with chunk tuning, the largest tail over the chunk
 // lengths the tuner may pick.
 size_t layout_need(const Layout &L, const pamx_options *opt) {
+    if (L.fw > 0) {
+        Layout T = L;
+        set_window(&T);
+        return T.total > L.total ? T.total : L.total;
+    }
     if (!opt || opt->chunk >= 0) return L.total;
     size_t need = L.total;
     for (int32_t Lc : tune_chunks(L)) {
@@ -255,8 +282,10 @@ static int check_common(int64_t n, int32_t k, int32_t dtype, const pamx_options 
     if (dtype != PAMX_I32 && dtype != PAMX_F32)
         return fail(PAMX_ERR_ARG, "unknown dtype %d", dtype);
     if (opt) {
-        if (opt->variant != PAMX_FASTPAM1 && opt->variant != PAMX_FASTPAM2)
+        if (opt->variant != PAMX_FASTPAM1 && opt->variant != PAMX_FASTPAM2 &&
+            opt->variant != PAMX_FASTERPAM)
             return fail(PAMX_ERR_ARG, "unknown variant %d", opt->variant);
+        if (opt->window < 0) return fail(PAMX_ERR_ARG, "window must be >= 0");
         if (opt->accum != PAMX_ACC_F64 && opt->accum != PAMX_ACC_F32)
             return fail(PAMX_ERR_ARG, "unknown accum %d", opt->accum);
         if (opt->dist_mode != PAMX_DIST_STORED && opt->dist_mode != PAMX_DIST_BF16)
@@ -485,11 +514,11 @@ struct SearchKey {
     int dev;
     const void *D, *ws, *med, *trace;
     int64_t ld, n;
-    int32_t k, dtype, variant, chunk, vec, trace_cap;
+    int32_t k, dtype, variant, chunk, vec, trace_cap, fw;
     bool operator==(const SearchKey &o) const {
-        return std::tie(dev, D, ws, med, trace, ld, n, k, dtype, variant, chunk, vec, trace_cap) ==
+        return std::tie(dev, D, ws, med, trace, ld, n, k, dtype, variant, chunk, vec, trace_cap, fw) ==
                std::tie(o.dev, o.D, o.ws, o.med, o.trace, o.ld, o.n, o.k, o.dtype, o.variant, o.chunk,
-                        o.vec, o.trace_cap);
+                        o.vec, o.trace_cap, o.fw);
     }
 };
 
@@ -521,7 +550,7 @@ static int search_graph(const T *D, int64_t ld, const Layout &L, int32_t *medoid
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     const SearchKey key{dev, D, ws, medoids, opt.trace, ld, L.n, L.k, L.dtype, opt.variant,
-                        L.L, L.vec, opt.trace_cap};
+                        L.L, L.vec, opt.trace_cap, L.fw};
     for (auto &g : cache)
         if (g->key == key) { *out = g.get(); return PAMX_OK; }
     std::unique_ptr<SearchGraph> g(new SearchGraph);
@@ -603,8 +632,10 @@ int swap_impl(const T *D, int64_t ld, const Layout &L_in, int32_t k, const pamx_
     if (st.bad_medoids)
         return fail(PAMX_ERR_INVALID_MEDOIDS, "medoids must be distinct and in [0, n)");
     const bool searches = k >= 2 && k < n;
+    const bool scan = opt.variant == PAMX_FASTERPAM;
+    if (scan) set_window(&L);   // the window passes have their own chunking
     if (searches) HIP_TRY(enqueue_swap_caches<T>(D, ld, L, medoids, ws, s));
-    if (searches && opt.chunk == PAMX_CHUNK_TUNE && opt.max_iter > 0) {
+    if (searches && !scan && opt.chunk == PAMX_CHUNK_TUNE && opt.max_iter > 0) {
         rc = tune_chunk<T>(D, ld, &L, opt, ws, s);
         if (rc) return rc;
     }
@@ -633,7 +664,9 @@ int swap_impl(const T *D, int64_t ld, const Layout &L_in, int32_t k, const pamx_
         int batch = 4;
         for (;;) {
             int b = batch;
-            if (b > opt.max_iter + 1 - enq) b = opt.max_iter + 1 - enq;
+            // a FasterPAM scan takes an unknown number of windows (its
+            // cap counts passes and is applied on the device)
+            if (!scan && b > opt.max_iter + 1 - enq) b = opt.max_iter + 1 - enq;
             if (b < 1) b = 1;
             const int iter0 = st.iter;
             for (int j = 0; j < b; ++j) {
@@ -676,6 +709,15 @@ int swap_impl(const T *D, int64_t ld, const Layout &L_in, int32_t k, const pamx_
         stats->ms_swap_pass = ms_pass;
         stats->n_swap_pass = n_pass;
         stats->chunk = L.L;
+        if (scan) {
+            // passes begun over the candidates; every window pass reads all n
+            // objects for its candidates
+            stats->iterations = searches ? (int32_t)((st.fp_visited + n - 1) / n) : 0;
+            stats->windows = searches ? st.iter : 0;
+            stats->window = L.fw;
+            stats->scan_positions = searches ? st.fp_visited : 0;
+            stats->pass_pairs = (int64_t)(searches ? st.iter : 0) * L.fw * n;
+        }
     }
     return st.capped ? PAMX_WARN_MAXITER : PAMX_OK;
 }

@@ -61,6 +61,15 @@ struct alignas(64) DevState {
     double f32_best;     // FP32 best change before re-scoring
     long long n_chg;     // BUILD: objects whose nearest distance dropped this step
     long long build_rows;// BUILD: rows read by the incremental passes
+    // FasterPAM scan (Alg. 4)
+    int32_t fp;          // 1: the run is a FasterPAM scan (max_iter caps passes)
+    int32_t seg_skip;    // 1: no swap since the segments were built
+    long long fp_pos;    // next scan position
+    long long fp_visited;// positions visited
+    long long fp_quiet;  // positions visited since the last swap
+    long long fp_limit;  // max_iter * n
+    long long fw_base;   // window of the next pass: [fw_base, fw_end)
+    long long fw_end;
 };
 
 // Lexicographic "a is better than b" on (value, slot, candidate).
@@ -153,6 +162,8 @@ struct Layout {
     int64_t ncp;         // padded candidate count = n_ctiles * tile
     int32_t n_oblk;      // object blocks of kObjBlk
     int32_t n_mwg;       // merge work-groups = ceil(n / kWG)
+    int32_t fw;          // FasterPAM: candidates per window (a multiple of tile), or 0
+    int32_t fwL, fwQ;    // FasterPAM: object chunk length and count of the window pass
     size_t esz;          // element size of D (4)
     size_t asz;          // accumulator size (8)
     // offsets
@@ -177,6 +188,8 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
                 int64_t ld, const pamx_options *opt, Layout *L, const void *D);
 // re-place the chunk-dependent regions (after L->head) for chunk length Lc
 void set_chunk(Layout *L, int32_t Lc);
+// FasterPAM: place them for the window pass (chunk fwL, fw partial columns)
+void set_window(Layout *L);
 
 // launchers (one per kernel family); each returns hipSuccess or an error.
 hipError_t launch_dist_l1_i32(const int32_t *X, int64_t n, int32_t dim, int32_t *D, int64_t ld,

@@ -535,7 +535,7 @@ __global__ __launch_bounds__(256) void k_cache_rescan(const T *__restrict__ D, i
 __device__ __forceinline__ void iter_begin(DevState *st) {
     st->swapped = 0;
     st->n_list = 0;
-    if (st->iter >= st->max_iter) {
+    if (!st->fp && st->iter >= st->max_iter) {
         st->done = 1;
         st->capped = 1;
     }
@@ -547,6 +547,7 @@ __global__ __launch_bounds__(kObjBlk) void k_seg_count(const int32_t *__restrict
                                                        DevState *__restrict__ st) {
     if (st->done) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) iter_begin(st);
+    if (st->seg_skip) return;
     extern __shared__ int32_t hist[];
     for (int i = threadIdx.x; i < k; i += kObjBlk) hist[i] = 0;
     __syncthreads();
@@ -562,7 +563,7 @@ __global__ __launch_bounds__(kObjBlk) void k_seg_count(const int32_t *__restrict
 __global__ __launch_bounds__(256) void k_seg_colscan(int32_t *__restrict__ blkcnt, int32_t nblk,
                                                      int32_t k, int32_t *__restrict__ seg_size,
                                                      const DevState *__restrict__ st) {
-    if (st->done) return;
+    if (st->done || st->seg_skip) return;
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= k) return;
@@ -595,7 +596,7 @@ __global__ __launch_bounds__(1024) void k_seg_scan(int32_t k, int64_t n, int32_t
                                                    int32_t L, int32_t Q, ChunkInfo *__restrict__ cinfo,
                                                    DevState *__restrict__ st) {
     using A = AccT<T>;
-    if (st->done) return;
+    if (st->done || st->seg_skip) return;
     extern __shared__ int32_t soff[];    // k + 1 offsets
     __shared__ int32_t wsum[16];
     __shared__ A ws1[16], ws2[16];
@@ -687,7 +688,7 @@ __global__ __launch_bounds__(kObjBlk) void k_seg_scatter(const int32_t *__restri
                                                          int32_t *__restrict__ srow,
                                                          T *__restrict__ sdn, T *__restrict__ sds,
                                                          const DevState *__restrict__ st) {
-    if (st->done) return;
+    if (st->done || st->seg_skip) return;
     __shared__ int32_t ln[kObjBlk];
     const int t = threadIdx.x;
     const int64_t o = (int64_t)blockIdx.x * kObjBlk + t;
@@ -708,8 +709,10 @@ __global__ __launch_bounds__(kObjBlk) void k_seg_scatter(const int32_t *__restri
 // Output per candidate and chunk: part[q][0] = A partial, [1] head carry,
 // [2] tail carry, [3] best value over segments complete in the chunk, and
 // part_i = its slot.  P2 (FastPAM2) also stores M_i - DN_i of complete
-// segments into P[i][c].
-template <typename T, int VEC, bool P2>
+// segments into P[i][c].  WIN (FasterPAM) evaluates the candidate window
+// [fw_base, fw_end) of the state; the partials are indexed relative to
+// fw_base (ncp is then the window width).
+template <typename T, int VEC, bool P2, bool WIN>
 __global__ __launch_bounds__(kWG) void k_swap_pass(
     const T *__restrict__ D, int64_t ld, int64_t n, int32_t k, const int32_t *__restrict__ srow,
     const T *__restrict__ sdn, const T *__restrict__ sds, const int32_t *__restrict__ seg_off,
@@ -724,15 +727,18 @@ __global__ __launch_bounds__(kWG) void k_swap_pass(
     const int q = blockIdx.y;
     const int64_t a = (int64_t)q * L;
     const int64_t b = min(a + (int64_t)L, n);
-    const int64_t c0 = ((int64_t)blockIdx.x * kWG + threadIdx.x) * VEC;
-    const bool active = c0 < n;
+    const int64_t cr = ((int64_t)blockIdx.x * kWG + threadIdx.x) * VEC;   // partial column
+    int64_t cb = 0, ce = n;
+    if constexpr (WIN) { cb = st->fw_base; ce = st->fw_end; }
+    const int64_t c0 = cb + cr;
+    const bool active = c0 < ce;
     const ChunkInfo ci = cinfo[q];
 
     A accA[VEC], bv[VEC];
     int32_t bi[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) { accA[e] = 0; bv[e] = VT<T>::acc_inf(); bi[e] = INT_MAX; }
-    A *pq = part + (int64_t)q * 4 * ncp + c0;
+    A *pq = part + (int64_t)q * 4 * ncp + cr;
 
     for (int s = ci.sa; s <= ci.sb; ++s) {
         const int64_t so = seg_off[s], se = seg_off[s + 1];
@@ -777,8 +783,9 @@ __global__ __launch_bounds__(kWG) void k_swap_pass(
                 }
             }
         }
-        // the first lane of the first tile (always a real candidate) records
-        // the chunk's part of DN for segments carried across chunks
+        // the first lane of the first tile (always a real candidate: windows
+        // are never empty) records the chunk's part of DN for segments
+        // carried across chunks
         const bool rec = blockIdx.x == 0 && threadIdx.x == 0;
         if (s == ci.sa && (ci.flags & kHead)) {
 #pragma unroll
@@ -803,15 +810,18 @@ __global__ __launch_bounds__(kWG) void k_swap_pass(
     for (int e = 0; e < VEC; ++e) {
         pq[0 * ncp + e] = accA[e];
         pq[3 * ncp + e] = bv[e];
-        part_i[(int64_t)q * ncp + c0 + e] = bi[e];
+        part_i[(int64_t)q * ncp + cr + e] = bi[e];
     }
 }
 
 // ---- merge chunk partials per candidate (fixed chunk order).
 // Writes, per candidate, its best change over slots (FastPAM1) and the
 // work-group's best (value, slot, candidate); for FastPAM2 it completes
-// P[i][c] for carried segments and stores B(c) = A(c) - TD.
-template <typename T, bool P2>
+// P[i][c] for carried segments and stores B(c) = A(c) - TD.  WIN
+// (FasterPAM): the candidates of the window; the work-group reports its
+// first candidate at or after the scan position whose best change is below
+// the threshold (wg_c = INT_MAX if none).
+template <typename T, bool P2, bool WIN>
 __global__ __launch_bounds__(kWG) void k_swap_merge(
     const AccT<T> *__restrict__ part, const int32_t *__restrict__ part_i,
     const ChunkInfo *__restrict__ cinfo, int32_t Q, int64_t n, int32_t k, int64_t ncp,
@@ -820,11 +830,13 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
     AccT<T> *__restrict__ wg_v, int32_t *__restrict__ wg_i, int32_t *__restrict__ wg_c) {
     using A = AccT<T>;
     if (st->done) return;
-    const int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    const int64_t cr = (int64_t)blockIdx.x * kWG + threadIdx.x;   // partial column
+    int64_t c = cr, ce = n;
+    if constexpr (WIN) { c = st->fw_base + cr; ce = st->fw_end; }
     A bestv = VT<T>::acc_inf();
     int besti = INT_MAX;
     int cc = INT_MAX;
-    if (c < n) {
+    if (c < ce) {
         A accA = 0;
         int run_s = -1;
         A run_m = 0, run_dn = 0;
@@ -832,7 +844,7 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
             if (run_s >= 0) {
                 const A v = run_m - run_dn;
                 if (lt2(v, run_s, bestv, besti)) { bestv = v; besti = run_s; }
-                if constexpr (P2) P[(int64_t)run_s * ncp + c] = v;
+                if constexpr (P2) P[(int64_t)run_s * ncp + cr] = v;
             }
         };
         constexpr int UQ = 8;   // chunks whose partials are loaded together
@@ -842,12 +854,12 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
 #pragma unroll
             for (int u = 0; u < UQ; ++u) {
                 if (q0 + u < Q) {
-                    const A *pq = part + (int64_t)(q0 + u) * 4 * ncp + c;
+                    const A *pq = part + (int64_t)(q0 + u) * 4 * ncp + cr;
                     xa[u] = pq[0];
                     xh[u] = pq[1 * ncp];   // read even when unused (never written then)
                     xt[u] = pq[2 * ncp];
                     xv[u] = pq[3 * ncp];
-                    xi[u] = part_i[(int64_t)(q0 + u) * ncp + c];
+                    xi[u] = part_i[(int64_t)(q0 + u) * ncp + cr];
                 }
             }
 #pragma unroll
@@ -882,6 +894,24 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
             bestv = VT<T>::acc_inf();
             besti = INT_MAX;
         }
+    }
+    if constexpr (WIN) {
+        A thr;
+        if constexpr (std::is_same<T, float>::value) thr = -st->margin; else thr = 0;
+        const bool neg = cc != INT_MAX && c >= st->fp_pos && bestv < thr;
+        __shared__ int first;
+        if (threadIdx.x == 0) first = INT_MAX;
+        __syncthreads();
+        if (neg) atomicMin(&first, cc);
+        __syncthreads();
+        if (neg && cc == first) {
+            wg_v[blockIdx.x] = bestv;
+            wg_i[blockIdx.x] = besti;
+            wg_c[blockIdx.x] = cc;
+        } else if (threadIdx.x == 0 && first == INT_MAX) {
+            wg_c[blockIdx.x] = INT_MAX;
+        }
+        return;
     }
     block_argmin3<A, kWG>(bestv, besti, cc);
     if (threadIdx.x == 0) {
@@ -935,6 +965,121 @@ __global__ __launch_bounds__(256) void k_select_update(
             else { st->td_i += v; st->td = (double)st->td_i; }
             if (trace && st->swaps < st->trace_cap) trace[st->swaps] = pamx_swap_record{i, c, (double)v};
             st->swaps += 1;
+        }
+    }
+    if (!apply) return;
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= n) return;
+    const T dnew = D[(int64_t)c * ld + o];
+    int32_t nr = near[o], sc = sec[o];
+    T a = dn[o], b = ds[o];
+    if (cache_update_o1<T>(i, dnew, nr, sc, a, b)) {
+        rlist[atomicAdd(&st->n_list, 1)] = (int32_t)o;
+    } else {
+        near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b;
+    }
+}
+
+// ---- FasterPAM (Alg. 4): candidates are visited one at a time in index
+// order, cyclically; each takes its best slot and is swapped in at once when
+// that lowers TD.  On the device the scan is evaluated a window at a time:
+// every candidate of [fw_base, fw_end) is scored against the current medoids
+// in one pass, and the first one at or after the scan position fp_pos with
+// an improving swap is exactly the candidate at which the sequential scan
+// swaps next (nothing changes between the position and that candidate).  The
+// swap is applied and the next window starts right after it; without one the
+// scan moves to the window's end.  The scan ends once n consecutive
+// positions went by without a swap, or after max_iter passes.
+
+// Next window: starts at the scan position (rounded down to the load width;
+// the positions before it are masked), at most fw wide, not past n, the stop
+// position or the pass cap.
+__device__ __forceinline__ void fp_window(DevState *st, int64_t n, int64_t fw, int32_t vec) {
+    const long long pos = st->fp_pos;
+    const long long base = pos - pos % vec;
+    long long end = base + fw;
+    if (end > n) end = n;
+    const long long rest = (long long)n - st->fp_quiet;
+    if (end > pos + rest) end = pos + rest;
+    const long long left = st->fp_limit - st->fp_visited;
+    if (end > pos + left) end = pos + left;
+    st->fw_base = base;
+    st->fw_end = end;
+}
+
+__global__ void k_fp_init(DevState *st, int64_t n, int64_t fw, int32_t vec, long long limit) {
+    st->fp = 1;
+    st->fp_pos = 0;
+    st->fp_visited = 0;
+    st->fp_quiet = 0;
+    st->fp_limit = limit;
+    st->seg_skip = 0;
+    if (limit <= 0) {
+        st->done = 1;
+        st->capped = 1;
+    } else {
+        fp_window(st, n, fw, vec);
+    }
+}
+
+// Every block finds the window's first improving candidate from the merge
+// results (work-groups in candidate order) -- the same in every block -- and,
+// when there is one, updates its objects' caches by the O(1) rule.  Block 0
+// applies the swap or advances the scan, and places the next window.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fp_select_update(
+    const AccT<T> *__restrict__ wg_v, const int32_t *__restrict__ wg_i,
+    const int32_t *__restrict__ wg_c, int32_t nwg, const T *__restrict__ D, int64_t ld,
+    int64_t n, int64_t fw, int32_t vec, int32_t *__restrict__ med, uint8_t *__restrict__ is_med,
+    int32_t *__restrict__ near, int32_t *__restrict__ sec, T *__restrict__ dn, T *__restrict__ ds,
+    int32_t *__restrict__ rlist, DevState *__restrict__ st, pamx_swap_record *__restrict__ trace) {
+    using A = AccT<T>;
+    if (st->done) return;
+    __shared__ int wfirst;
+    if (threadIdx.x == 0) wfirst = INT_MAX;
+    __syncthreads();
+    for (int w = threadIdx.x; w < nwg; w += 256)
+        if (wg_c[w] != INT_MAX) atomicMin(&wfirst, w);
+    __syncthreads();
+    const int wb = wfirst;
+    const bool apply = wb != INT_MAX;
+    A v = 0;
+    int i = 0, c = 0;
+    if (apply) { v = wg_v[wb]; i = wg_i[wb]; c = wg_c[wb]; }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->iter += 1;
+        const long long pos = st->fp_pos, end = st->fw_end;
+        if (apply) {
+            st->best_i = i;
+            st->best_c = c;
+            const int old = med[i];
+            is_med[old] = 0;
+            is_med[c] = 1;
+            med[i] = c;
+            st->old_med = old;
+            st->new_slot = i;
+            st->new_med = c;
+            if constexpr (std::is_same<T, float>::value) { st->best_v = v; st->td += v; }
+            else { st->best_vi = v; st->best_v = (double)v; st->td_i += v; st->td = (double)st->td_i; }
+            if (trace && st->swaps < st->trace_cap) trace[st->swaps] = pamx_swap_record{i, c, (double)v};
+            st->swaps += 1;
+            st->fp_visited += (long long)c - pos + 1;
+            st->fp_quiet = 0;
+            st->fp_pos = (c + 1 == n) ? 0 : c + 1;
+        } else {
+            st->fp_visited += end - pos;
+            st->fp_quiet += end - pos;
+            st->fp_pos = (end == n) ? 0 : end;
+        }
+        st->swapped = apply ? 1 : 0;
+        st->seg_skip = apply ? 0 : 1;
+        if (st->fp_quiet >= n) {
+            st->done = 1;
+        } else if (st->fp_visited >= st->fp_limit) {
+            st->done = 1;
+            st->capped = 1;
+        } else {
+            fp_window(st, n, fw, vec);
         }
     }
     if (!apply) return;
@@ -1117,6 +1262,9 @@ hipError_t enqueue_swap_init(const T *D, int64_t ld, const Layout &L, const int3
     fill<int32_t>(p.near, n, 0, s);
     hipLaunchKernelGGL(k_check_medoids, dim3((k + 255) / 256), dim3(256), 0, s, medoids, k, n,
                        p.near, p.is_med, p.st);
+    if (opt.variant == PAMX_FASTERPAM)
+        hipLaunchKernelGGL(k_fp_init, dim3(1), dim3(1), 0, s, p.st, n, (int64_t)L.fw, L.vec,
+                           (long long)opt.max_iter * (long long)n);
     return hipGetLastError();
 }
 
@@ -1148,18 +1296,26 @@ static void enqueue_segments(const Layout &L, const SwapPtrs<T> &p, hipStream_t 
                        p.sds, (const DevState *)p.st);
 }
 
+// win: FasterPAM window pass (L placed by set_window: L.L, L.Q are the
+// window chunking, the partials have L.fw columns)
 template <typename T>
 static void enqueue_pass(const T *D, int64_t ld, const Layout &L, const SwapPtrs<T> &p, bool p2,
-                         hipStream_t s) {
-    const dim3 pgrid(L.n_ctiles, L.Q);
-#define PAMX_PASS(VEC, P2)                                                                    \
-    hipLaunchKernelGGL((k_swap_pass<T, VEC, P2>), pgrid, dim3(kWG), 0, s, D, ld, L.n, L.k,   \
-                       (const int32_t *)p.srow, (const T *)p.sdn, (const T *)p.sds,           \
+                         hipStream_t s, bool win = false) {
+    const dim3 pgrid(win ? L.fw / L.tile : L.n_ctiles, L.Q);
+    const int64_t cols = win ? L.fw : L.ncp;
+#define PAMX_PASS(VEC, P2, WIN)                                                               \
+    hipLaunchKernelGGL((k_swap_pass<T, VEC, P2, WIN>), pgrid, dim3(kWG), 0, s, D, ld, L.n,   \
+                       L.k, (const int32_t *)p.srow, (const T *)p.sdn, (const T *)p.sds,      \
                        (const int32_t *)p.seg_off, p.cdn,                                     \
-                       (const ChunkInfo *)p.cinfo, L.L, L.ncp, p.part, p.part_i, p.P,         \
+                       (const ChunkInfo *)p.cinfo, L.L, cols, p.part, p.part_i, p.P,          \
                        (const DevState *)p.st)
-    if (L.vec == 4) { if (p2) PAMX_PASS(4, true); else PAMX_PASS(4, false); }
-    else { if (p2) PAMX_PASS(1, true); else PAMX_PASS(1, false); }
+    if (win) {
+        if (L.vec == 4) PAMX_PASS(4, false, true); else PAMX_PASS(1, false, true);
+    } else if (L.vec == 4) {
+        if (p2) PAMX_PASS(4, true, false); else PAMX_PASS(4, false, false);
+    } else {
+        if (p2) PAMX_PASS(1, true, false); else PAMX_PASS(1, false, false);
+    }
 #undef PAMX_PASS
 }
 
@@ -1191,12 +1347,32 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
     pamx_swap_record *trace = static_cast<pamx_swap_record *>(opt.trace);
     const unsigned ob = (unsigned)((n + 255) / 256);
 
+    if (opt.variant == PAMX_FASTERPAM) {
+        // one window of the scan (segments are rebuilt only after a swap)
+        const int nwg = L.fw / kWG;
+        enqueue_segments<T>(L, p, s);
+        if (ev0) (void)hipEventRecord(ev0, s);
+        enqueue_pass<T>(D, ld, L, p, false, s, true);
+        if (ev1) (void)hipEventRecord(ev1, s);
+        hipLaunchKernelGGL((k_swap_merge<T, false, true>), dim3(nwg), dim3(kWG), 0, s,
+                           (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
+                           L.Q, n, k, (int64_t)L.fw, (const A *)p.cdn, (const uint8_t *)p.is_med,
+                           (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
+        hipLaunchKernelGGL(k_fp_select_update<T>, dim3(ob), dim3(256), 0, s, (const A *)p.wg_v,
+                           (const int32_t *)p.wg_i, (const int32_t *)p.wg_c, nwg, D, ld, n,
+                           (int64_t)L.fw, L.vec, medoids, p.is_med, p.near, p.sec, p.dn, p.ds,
+                           p.rlist, p.st, trace);
+        hipLaunchKernelGGL(k_cache_rescan<T>, dim3(256), dim3(256), 0, s, D, ld, k,
+                           (const int32_t *)medoids, p.near, p.sec, p.dn, p.ds,
+                           (const int32_t *)p.rlist, (const DevState *)p.st);
+        return hipGetLastError();
+    }
     enqueue_segments<T>(L, p, s);
     if (ev0) (void)hipEventRecord(ev0, s);
     enqueue_pass<T>(D, ld, L, p, p2, s);
     if (ev1) (void)hipEventRecord(ev1, s);
     if (p2) {
-        hipLaunchKernelGGL((k_swap_merge<T, true>), dim3(L.n_mwg), dim3(kWG), 0, s,
+        hipLaunchKernelGGL((k_swap_merge<T, true, false>), dim3(L.n_mwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
                            L.Q, n, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
                            (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
@@ -1207,7 +1383,7 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
                            p.is_med, p.near, p.sec, p.dn, p.ds, (const A *)p.slot_v,
                            (const int32_t *)p.slot_c, p.order, p.rlist, p.st, trace);
     } else {
-        hipLaunchKernelGGL((k_swap_merge<T, false>), dim3(L.n_mwg), dim3(kWG), 0, s,
+        hipLaunchKernelGGL((k_swap_merge<T, false, false>), dim3(L.n_mwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
                            L.Q, n, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
                            (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);

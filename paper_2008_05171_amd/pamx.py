@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(PKG, "libpamx.so")
 PAMX_I32, PAMX_F32 = 1, 2
 PAMX_INPUT_D, PAMX_INPUT_X = 0, 1
 PAMX_L1, PAMX_L2 = 1, 2
-PAMX_FASTPAM1, PAMX_FASTPAM2 = 1, 2
+PAMX_FASTPAM1, PAMX_FASTPAM2, PAMX_FASTERPAM = 1, 2, 3
 PAMX_ACC_F64, PAMX_ACC_F32 = 0, 1
 PAMX_DIST_STORED, PAMX_DIST_BF16 = 0, 1
 PAMX_CHUNK_TUNE = -1
@@ -30,7 +30,8 @@ class pamx_options(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("build_exclude_self", ctypes.c_int32),
                 ("trace_cap", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("dist_mode", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("trace", ctypes.c_void_p)]
+                ("graph", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("trace", ctypes.c_void_p)]
 
 
 class pamx_swap_record(ctypes.Structure):
@@ -47,7 +48,9 @@ class pamx_stats(ctypes.Structure):
                 ("ms_swap_pass", ctypes.c_double), ("ms_build_pass", ctypes.c_double),
                 ("n_swap_pass", ctypes.c_int32), ("n_build_pass", ctypes.c_int32),
                 ("ms_build_delta", ctypes.c_double), ("build_rows", ctypes.c_int64),
-                ("n_build_delta", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+                ("n_build_delta", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("scan_positions", ctypes.c_int64), ("windows", ctypes.c_int32),
+                ("window", ctypes.c_int32)]
 
 
 class pamx_batch_stats(ctypes.Structure):

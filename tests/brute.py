@@ -116,3 +116,36 @@ def global_optimum(D, k):
 
 def is_local_optimum(D, med):
     return all(v >= 0 for v in all_swaps(D, med).values())
+
+
+def fasterpam_swap(D, med, max_passes=1000):
+    """Alg. 4's scan with every change taken as a full TD recomputation.
+
+    Positions 0, 1, ..., n-1, 0, ... are visited in turn; at a non-medoid c
+    the TD change of putting c into each slot is computed and the smallest
+    slot with the smallest change is swapped in at once if that change is
+    negative.  The scan ends once n consecutive positions passed without a
+    swap.  Returns (medoids, trace [(slot, cand, change)], passes begun)."""
+    n = len(D)
+    med = list(med)
+    trace = []
+    pos = visited = quiet = 0
+    while quiet < n and visited < max_passes * n:
+        c = pos
+        pos = (pos + 1) % n
+        visited += 1
+        quiet += 1
+        if c in med:
+            continue
+        base = td_of(D, med)
+        ch = []
+        for i in range(len(med)):
+            m2 = list(med)
+            m2[i] = c
+            ch.append(td_of(D, m2) - base)
+        i = min(range(len(med)), key=lambda j: (ch[j], j))
+        if ch[i] < 0:
+            med[i] = c
+            trace.append((i, c, ch[i]))
+            quiet = 0
+    return med, trace, (visited + n - 1) // n

@@ -35,7 +35,7 @@ def test_exports_every_declared_symbol(lib):
 def test_struct_sizes_match_header():
     assert ctypes.sizeof(abi.pamx_options) == 48
     assert ctypes.sizeof(abi.pamx_swap_record) == 16
-    assert ctypes.sizeof(abi.pamx_stats) == 128
+    assert ctypes.sizeof(abi.pamx_stats) == 144
 
 
 def test_default_options(lib):
@@ -86,8 +86,13 @@ def test_host_argument_errors_before_device_work(lib):
                        1 << 30) == abi.PAMX_ERR_WORKSPACE
     assert _call_build(lib, fake, abi.PAMX_F32, 10, 10, 2, None, 1 << 30) == abi.PAMX_ERR_WORKSPACE
     o = abi.pamx_default_options()
-    o.variant = 3
+    o.variant = 4
     assert _call_build(lib, fake, abi.PAMX_F32, 10, 10, 2, ws, 1 << 30, o) == abi.PAMX_ERR_ARG
+    o = abi.pamx_default_options()
+    o.variant = abi.PAMX_FASTERPAM
+    o.window = -1
+    assert _call_build(lib, fake, abi.PAMX_F32, 10, 10, 2, ws, 1 << 30, o) == abi.PAMX_ERR_ARG
+    assert "window" in abi.pamx_last_error()
     o = abi.pamx_default_options()
     o.accum = abi.PAMX_ACC_F32
     assert _call_build(lib, fake, abi.PAMX_I32, 10, 10, 2, ws, 1 << 30, o) == abi.PAMX_ERR_ARG
@@ -111,6 +116,22 @@ def test_chunk_tuning_option(lib):
     o.chunk = -2
     with pytest.raises(abi.PamxError):
         abi.pamx_workspace_bytes(20000, 100, 16, abi.PAMX_INPUT_X, abi.PAMX_F32, o)
+
+
+def test_fasterpam_window_option(lib):
+    """FasterPAM sizes the workspace for its window passes; a wider window
+    needs more partials; BF16 distances run FastPAM1 only."""
+    o = abi.pamx_default_options()
+    o.variant = abi.PAMX_FASTERPAM
+    a = abi.pamx_workspace_bytes(20000, 100, 0, abi.PAMX_INPUT_D, abi.PAMX_F32, o)
+    o.window = 8192
+    b = abi.pamx_workspace_bytes(20000, 100, 0, abi.PAMX_INPUT_D, abi.PAMX_F32, o)
+    assert 0 < a <= b
+    o.window = 0
+    o.dist_mode = abi.PAMX_DIST_BF16
+    with pytest.raises(abi.PamxError) as e:
+        abi.pamx_workspace_bytes(2000, 10, 8, abi.PAMX_INPUT_X, abi.PAMX_F32, o)
+    assert e.value.code == abi.PAMX_ERR_UNSUPPORTED
 
 
 def test_points_metric_rules(lib):

@@ -336,6 +336,89 @@ def test_fastpam2_first_swap_equals_pam_first_swap():
             assert b.trace[0] == a.trace[0]
 
 
+# ---------------------------------------------------------------- FasterPAM (Alg. 4)
+@pytest.mark.parametrize("variant", ["printed", "drawn"])
+def test_fig1_fasterpam(variant):
+    """The hand-worked FasterPAM run on Fig. 1's points (fixture derived from
+    Alg. 4, not printed by the paper) and the losses the figure prints."""
+    g = _read_golden("fig1_fasterpam.txt")
+    pts = g["points"] if variant == "printed" else g["points_drawn"]
+    swaps = g["swaps"] if variant == "printed" else g["swaps_drawn"]
+    losses = g["losses"] if variant == "printed" else g["losses_drawn"]
+    names = [p.split("=")[0] for p in pts]
+    X = np.array([[float(p.split("=")[1])] for p in pts])
+    D = oracle.dist_matrix(X, oracle.L1)
+    start = [names.index(s) for s in g["start"]]
+    r = oracle.swap(start, D=D, variant=oracle.FASTERPAM)
+    want = [(int(s.split(":")[0]), names.index(s.split(":")[1]), float(s.split(":")[2]))
+            for s in swaps]
+    assert r.trace == want
+    tds = [oracle.td(start, D=D)[0]]
+    for _, _, dl in r.trace:
+        tds.append(tds[-1] + dl)
+    assert tds == [float(v) for v in losses]
+    assert [names[m] for m in r.medoids] == g["final"]
+    assert r.iterations == int(g["passes"][0]) and r.rc == 0
+
+
+def test_fasterpam_matches_bruteforce():
+    """Trajectory, passes and result equal the scan with full TD recomputation
+    for every change, on tie-heavy integer matrices; the result is a local
+    optimum (no single swap lowers TD)."""
+    rng = np.random.default_rng(47)
+    for trial in range(40):
+        n = int(rng.integers(5, 13))
+        k = int(rng.integers(2, min(5, n - 1) + 1))
+        D, _ = _tiny_int_D(rng, n, hi=6 if trial % 2 else 20)
+        start = [int(v) for v in rng.choice(n, size=k, replace=False)]
+        r = oracle.swap(start, D=D, variant=oracle.FASTERPAM)
+        med_b, trace_b, passes_b = brute.fasterpam_swap(D.tolist(), start)
+        assert list(r.medoids) == med_b, trial
+        assert r.trace == [(i, c, float(v)) for i, c, v in trace_b], trial
+        assert r.iterations == passes_b and r.swaps == len(trace_b) and r.rc == 0
+        assert brute.is_local_optimum(D.tolist(), med_b)
+        assert r.td == brute.td_of(D.tolist(), med_b)
+
+
+def test_fasterpam_max_iter_and_no_swap():
+    """A start that is already a local optimum ends after one pass with no
+    swap; a pass cap ends an unconverged run with the warning code."""
+    rng = np.random.default_rng(53)
+    D, _ = _tiny_int_D(rng, 40, hi=50)
+    r = oracle.pam(4, D=D)
+    again = oracle.swap(r.medoids, D=D, variant=oracle.FASTERPAM)
+    assert again.swaps == 0 and again.iterations == 1 and again.rc == 0
+    start = [0, 1, 2, 3]
+    full = oracle.swap(start, D=D, variant=oracle.FASTERPAM)
+    assert full.iterations >= 2 and full.rc == 0
+    capped = oracle.swap(start, D=D, variant=oracle.FASTERPAM, max_iter=1)
+    assert capped.rc == 1 and capped.iterations == 1
+    assert capped.trace == full.trace[:capped.swaps]
+
+
+def test_fasterpam_bookkeeping_on_int_workload():
+    """n = 300 integer workload: TD strictly decreasing, TD_start + sum of the
+    changes equals the final TD exactly, every change equals the swap's
+    Eq. td difference, and the search finds no improving swap at the end."""
+    rng = np.random.default_rng(59)
+    X = rng.integers(0, 100, size=(300, 2)).astype(np.float64)
+    D = oracle.dist_matrix(X, oracle.L1)
+    start = [int(v) for v in rng.choice(300, 7, replace=False)]
+    r = oracle.swap(start, D=D, variant=oracle.FASTERPAM)
+    med = list(start)
+    td0 = oracle.td(med, D=D)[0]
+    run = td0
+    for i, c, dl in r.trace:
+        assert dl < 0
+        before = oracle.td(med, D=D)[0]
+        med[i] = c
+        assert oracle.td(med, D=D)[0] - before == dl
+        run += dl
+    assert med == list(r.medoids) and run == r.td
+    found, _, _, _ = oracle.swap_search(r.medoids, D=D)
+    assert not found
+
+
 # ---------------------------------------------------------------- degenerate cases
 def test_k_equals_n_and_duplicates():
     X = np.array([[0.0], [0.0], [1.0], [1.0], [5.0]])
