@@ -817,11 +817,8 @@ __global__ __launch_bounds__(kWG) void k_swap_pass(
 // ---- merge chunk partials per candidate (fixed chunk order).
 // Writes, per candidate, its best change over slots (FastPAM1) and the
 // work-group's best (value, slot, candidate); for FastPAM2 it completes
-// P[i][c] for carried segments and stores B(c) = A(c) - TD.  WIN
-// (FasterPAM): the candidates of the window; the work-group reports its
-// first candidate at or after the scan position whose best change is below
-// the threshold (wg_c = INT_MAX if none).
-template <typename T, bool P2, bool WIN>
+// P[i][c] for carried segments and stores B(c) = A(c) - TD.
+template <typename T, bool P2>
 __global__ __launch_bounds__(kWG) void k_swap_merge(
     const AccT<T> *__restrict__ part, const int32_t *__restrict__ part_i,
     const ChunkInfo *__restrict__ cinfo, int32_t Q, int64_t n, int32_t k, int64_t ncp,
@@ -830,13 +827,11 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
     AccT<T> *__restrict__ wg_v, int32_t *__restrict__ wg_i, int32_t *__restrict__ wg_c) {
     using A = AccT<T>;
     if (st->done) return;
-    const int64_t cr = (int64_t)blockIdx.x * kWG + threadIdx.x;   // partial column
-    int64_t c = cr, ce = n;
-    if constexpr (WIN) { c = st->fw_base + cr; ce = st->fw_end; }
+    const int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x;
     A bestv = VT<T>::acc_inf();
     int besti = INT_MAX;
     int cc = INT_MAX;
-    if (c < ce) {
+    if (c < n) {
         A accA = 0;
         int run_s = -1;
         A run_m = 0, run_dn = 0;
@@ -844,7 +839,7 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
             if (run_s >= 0) {
                 const A v = run_m - run_dn;
                 if (lt2(v, run_s, bestv, besti)) { bestv = v; besti = run_s; }
-                if constexpr (P2) P[(int64_t)run_s * ncp + cr] = v;
+                if constexpr (P2) P[(int64_t)run_s * ncp + c] = v;
             }
         };
         constexpr int UQ = 8;   // chunks whose partials are loaded together
@@ -854,12 +849,12 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
 #pragma unroll
             for (int u = 0; u < UQ; ++u) {
                 if (q0 + u < Q) {
-                    const A *pq = part + (int64_t)(q0 + u) * 4 * ncp + cr;
+                    const A *pq = part + (int64_t)(q0 + u) * 4 * ncp + c;
                     xa[u] = pq[0];
                     xh[u] = pq[1 * ncp];   // read even when unused (never written then)
                     xt[u] = pq[2 * ncp];
                     xv[u] = pq[3 * ncp];
-                    xi[u] = part_i[(int64_t)(q0 + u) * ncp + cr];
+                    xi[u] = part_i[(int64_t)(q0 + u) * ncp + c];
                 }
             }
 #pragma unroll
@@ -894,24 +889,6 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
             bestv = VT<T>::acc_inf();
             besti = INT_MAX;
         }
-    }
-    if constexpr (WIN) {
-        A thr;
-        if constexpr (std::is_same<T, float>::value) thr = -st->margin; else thr = 0;
-        const bool neg = cc != INT_MAX && c >= st->fp_pos && bestv < thr;
-        __shared__ int first;
-        if (threadIdx.x == 0) first = INT_MAX;
-        __syncthreads();
-        if (neg) atomicMin(&first, cc);
-        __syncthreads();
-        if (neg && cc == first) {
-            wg_v[blockIdx.x] = bestv;
-            wg_i[blockIdx.x] = besti;
-            wg_c[blockIdx.x] = cc;
-        } else if (threadIdx.x == 0 && first == INT_MAX) {
-            wg_c[blockIdx.x] = INT_MAX;
-        }
-        return;
     }
     block_argmin3<A, kWG>(bestv, besti, cc);
     if (threadIdx.x == 0) {
@@ -1019,6 +996,113 @@ __global__ void k_fp_init(DevState *st, int64_t n, int64_t fw, int32_t vec, long
         st->capped = 1;
     } else {
         fp_window(st, n, fw, vec);
+    }
+}
+
+// Merge of a window pass's chunk partials.  A window has few candidates and
+// many chunks, so 16 threads share a candidate: each merges a contiguous
+// group of chunks into a summary (sum of A, best complete segment, first and
+// last segment run, which may continue into the neighbouring groups), and
+// the candidate's first thread combines the 16 summaries in chunk order.
+// The work-group (16 candidates) reports its first candidate at or after the
+// scan position whose best change is below the acceptance threshold.
+template <typename A>
+struct RunSum {
+    A accA, bv, fm, fdn, lm, ldn;
+    int32_t bi, nr, fs, ls;   // nr: runs seen (0, 1, 2 = more than one)
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fp_merge(
+    const AccT<T> *__restrict__ part, const int32_t *__restrict__ part_i,
+    const ChunkInfo *__restrict__ cinfo, int32_t Q, int64_t cols, int32_t k,
+    const AccT<T> *__restrict__ cdn, const uint8_t *__restrict__ is_med,
+    const DevState *__restrict__ st, AccT<T> *__restrict__ wg_v, int32_t *__restrict__ wg_i,
+    int32_t *__restrict__ wg_c) {
+    using A = AccT<T>;
+    constexpr int CPB = 16, G = 16;
+    if (st->done) return;
+    __shared__ RunSum<A> sm[G][CPB];
+    __shared__ int first;
+    const int j = threadIdx.x % CPB, g = threadIdx.x / CPB;
+    const int64_t cr = (int64_t)blockIdx.x * CPB + j;   // partial column
+    const int64_t c = st->fw_base + cr;
+    const bool live = c < st->fw_end;
+    RunSum<A> r;
+    r.accA = 0; r.bv = VT<T>::acc_inf(); r.bi = INT_MAX; r.nr = 0;
+    r.fs = -1; r.fm = 0; r.fdn = 0; r.ls = -1; r.lm = 0; r.ldn = 0;
+    if (live) {
+        const int per = (Q + G - 1) / G;
+        const int q0 = g * per, q1 = min(Q, q0 + per);
+        // the open run is (fs, fm, fdn) while nr == 1, else (ls, lm, ldn)
+        auto add = [&](int s, A m, A dn) {
+            if (r.nr == 0) { r.nr = 1; r.fs = s; r.fm = m; r.fdn = dn; return; }
+            if (r.nr == 1) {
+                if (s == r.fs) { r.fm += m; r.fdn += dn; }
+                else { r.nr = 2; r.ls = s; r.lm = m; r.ldn = dn; }
+                return;
+            }
+            if (s == r.ls) { r.lm += m; r.ldn += dn; return; }
+            const A v = r.lm - r.ldn;   // a run between the first and the last: complete
+            if (lt2(v, r.ls, r.bv, r.bi)) { r.bv = v; r.bi = r.ls; }
+            r.ls = s; r.lm = m; r.ldn = dn;
+        };
+        for (int q = q0; q < q1; ++q) {
+            const A *pq = part + (int64_t)q * 4 * cols + cr;
+            const A xa = pq[0], xh = pq[1 * cols], xt = pq[2 * cols], xv = pq[3 * cols];
+            const int32_t xi = part_i[(int64_t)q * cols + cr];
+            const ChunkInfo ci = cinfo[q];
+            r.accA += xa;
+            if (xi != INT_MAX && lt2(xv, xi, r.bv, r.bi)) { r.bv = xv; r.bi = xi; }
+            if (ci.flags & kHead) add(ci.sa, xh, cdn[2 * q]);
+            if (ci.flags & kTail) add(ci.sb, xt, cdn[2 * q + 1]);
+        }
+    }
+    sm[g][j] = r;
+    if (threadIdx.x == 0) first = INT_MAX;
+    __syncthreads();
+    A bestv = VT<T>::acc_inf();
+    int besti = INT_MAX;
+    bool neg = false;
+    if (g == 0 && live) {
+        A accA = 0, bv = VT<T>::acc_inf(), rm = 0, rdn = 0;
+        int bi = INT_MAX, rs = -1;
+        auto flush = [&](int s, A m, A dn) {
+            if (s < 0) return;
+            const A v = m - dn;
+            if (lt2(v, s, bv, bi)) { bv = v; bi = s; }
+        };
+        for (int h = 0; h < G; ++h) {
+            const RunSum<A> &x = sm[h][j];
+            accA += x.accA;
+            if (x.bi != INT_MAX && lt2(x.bv, x.bi, bv, bi)) { bv = x.bv; bi = x.bi; }
+            if (x.nr == 0) continue;
+            if (x.fs == rs) { rm += x.fm; rdn += x.fdn; }
+            else { flush(rs, rm, rdn); rs = x.fs; rm = x.fm; rdn = x.fdn; }
+            if (x.nr == 2) {   // the first run ended inside the group
+                flush(rs, rm, rdn);
+                rs = x.ls; rm = x.lm; rdn = x.ldn;
+            }
+        }
+        flush(rs, rm, rdn);
+        const int e = st->empty_slot;   // an empty slot changes by 0 + B(c)
+        if (e < k && lt2((A)0, e, bv, bi)) { bv = 0; bi = e; }
+        A td;
+        if constexpr (std::is_same<T, float>::value) td = st->td; else td = st->td_i;
+        A thr;
+        if constexpr (std::is_same<T, float>::value) thr = -st->margin; else thr = 0;
+        bestv = bv + (accA - td);
+        besti = bi;
+        neg = !is_med[c] && c >= st->fp_pos && bestv < thr;
+        if (neg) atomicMin(&first, (int)c);
+    }
+    __syncthreads();
+    if (neg && (int)c == first) {
+        wg_v[blockIdx.x] = bestv;
+        wg_i[blockIdx.x] = besti;
+        wg_c[blockIdx.x] = (int)c;
+    } else if (threadIdx.x == 0 && first == INT_MAX) {
+        wg_c[blockIdx.x] = INT_MAX;
     }
 }
 
@@ -1349,15 +1433,15 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
 
     if (opt.variant == PAMX_FASTERPAM) {
         // one window of the scan (segments are rebuilt only after a swap)
-        const int nwg = L.fw / kWG;
+        const int nwg = L.fw / 16;   // merge work-groups (16 candidates each)
         enqueue_segments<T>(L, p, s);
         if (ev0) (void)hipEventRecord(ev0, s);
         enqueue_pass<T>(D, ld, L, p, false, s, true);
         if (ev1) (void)hipEventRecord(ev1, s);
-        hipLaunchKernelGGL((k_swap_merge<T, false, true>), dim3(nwg), dim3(kWG), 0, s,
-                           (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
-                           L.Q, n, k, (int64_t)L.fw, (const A *)p.cdn, (const uint8_t *)p.is_med,
-                           (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
+        hipLaunchKernelGGL(k_fp_merge<T>, dim3(nwg), dim3(256), 0, s, (const A *)p.part,
+                           (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo, L.Q,
+                           (int64_t)L.fw, k, (const A *)p.cdn, (const uint8_t *)p.is_med,
+                           (const DevState *)p.st, p.wg_v, p.wg_i, p.wg_c);
         hipLaunchKernelGGL(k_fp_select_update<T>, dim3(ob), dim3(256), 0, s, (const A *)p.wg_v,
                            (const int32_t *)p.wg_i, (const int32_t *)p.wg_c, nwg, D, ld, n,
                            (int64_t)L.fw, L.vec, medoids, p.is_med, p.near, p.sec, p.dn, p.ds,
@@ -1372,7 +1456,7 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
     enqueue_pass<T>(D, ld, L, p, p2, s);
     if (ev1) (void)hipEventRecord(ev1, s);
     if (p2) {
-        hipLaunchKernelGGL((k_swap_merge<T, true, false>), dim3(L.n_mwg), dim3(kWG), 0, s,
+        hipLaunchKernelGGL((k_swap_merge<T, true>), dim3(L.n_mwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
                            L.Q, n, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
                            (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
@@ -1383,7 +1467,7 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
                            p.is_med, p.near, p.sec, p.dn, p.ds, (const A *)p.slot_v,
                            (const int32_t *)p.slot_c, p.order, p.rlist, p.st, trace);
     } else {
-        hipLaunchKernelGGL((k_swap_merge<T, false, false>), dim3(L.n_mwg), dim3(kWG), 0, s,
+        hipLaunchKernelGGL((k_swap_merge<T, false>), dim3(L.n_mwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
                            L.Q, n, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
                            (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
