@@ -226,6 +226,40 @@ int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int64_t n, int
              int32_t *labels, double *td, pamx_stats *stats, void *ws, size_t ws_bytes,
              void *stream);
 
+/* ---- Faster initialisations (Sec. 3.4).  Both write k object indices in
+ * slot order to `medoids` (DEVICE int32[k]) for pamx_swap, and take their
+ * random draws as inputs.  D, dtype, n, ld as for pamx_build (symmetric).
+ * The work is enqueued on `stream` (pamx_init_lab first synchronizes once
+ * to check its sample indices).  Host-detectable argument errors return
+ * before any device work.  Integer matrices give the same medoids as the
+ * plain definition; FP32 ones sum in FP64 in a fixed order.
+ *
+ * Workspace (256-byte aligned): pamx_init_workspace_bytes(n, m); m = the
+ * subsample size for pamx_init_lab, 0 for pamx_init_dw. */
+int pamx_init_workspace_bytes(int64_t n, int32_t m, size_t *bytes);
+
+/* Distance-weighted seeding (the k-means++ idea with the distance to the
+ * nearest seed as weight, the "distance weighted" initialisation of
+ * Sec. 3.4).  u: DEVICE double[k], uniforms in [0, 1).  The first seed is
+ * floor(u[0] n); seed t is the first object, in index order, whose running
+ * sum of weights exceeds u[t] W (W the sum of all weights); seeds weigh 0.
+ * When W = 0 (every object coincides with a seed) the smallest-index
+ * non-seed is taken. */
+int pamx_init_dw(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                 const double *u, int32_t *medoids, void *ws, size_t ws_bytes, void *stream);
+
+/* LAB, linear approximative BUILD (Sec. 3.4): BUILD whose step t looks only
+ * at samples[t*m .. t*m+m-1] (DEVICE int32, distinct indices in [0, n); the
+ * paper draws 10 + ceil(sqrt(n)) non-medoid points per step).  The
+ * non-medoid members are the candidates, in listed order (first strict
+ * minimum wins), the members are the objects of the change; exclude_self as
+ * pamx_options.build_exclude_self.  If every member is a medoid the
+ * smallest-index non-medoid is taken.  An index outside [0, n) returns
+ * PAMX_ERR_ARG (checked on the device before the first step). */
+int pamx_init_lab(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                  const int32_t *samples, int32_t m, int32_t exclude_self, int32_t *medoids,
+                  void *ws, size_t ws_bytes, void *stream);
+
 typedef struct pamx_batch_stats {
     int32_t iterations;   /* SWAP searches over all instances */
     int32_t swaps;        /* swaps over all instances */

@@ -17,6 +17,8 @@ only builds it (gcc) and marshals numpy arrays.  Paper references
                        FasterPAM, Alg. 4 (variant 3: the first candidate in scan
                        order with an improving swap, applied at once).
 * ``pam``           -- BUILD followed by SWAP, with labels.
+* ``init_dw``       -- distance-weighted seeding (Sec. 3.4, reading R8).
+* ``init_lab``      -- LAB, BUILD on per-step subsamples (Sec. 3.4, reading R9).
 """
 from __future__ import annotations
 
@@ -72,6 +74,8 @@ def _load():
     lib.orc_dist_rows.argtypes = [P, i64, i32, i32, P, i64, P]
     lib.orc_swap_list.argtypes = [P, P, i64, i32, i32, P, i32, P, i64, P]
     lib.orc_build_list.argtypes = [P, P, i64, i32, i32, P, i32, i32, P, i64, P]
+    lib.orc_init_dw.argtypes = [P, P, i64, i32, i32, i32, P, P]
+    lib.orc_init_lab.argtypes = [P, P, i64, i32, i32, i32, P, i32, i32, P]
     _lib = lib
     return lib
 
@@ -262,3 +266,30 @@ def pam(k, D=None, X=None, metric=L2, variant=PAM, exclude_self=False, max_iter=
     r = swap(bm, D=D, X=X, metric=metric, variant=variant, max_iter=max_iter)
     tdv, labels = td(r.medoids, D=D, X=X, metric=metric)
     return PamResult(r.medoids, labels, tdv, td_b, bm, r.iterations, r.swaps, r.rc, r.trace)
+
+
+def init_dw(k, u, D=None, X=None, metric=L2) -> np.ndarray:
+    """Distance-weighted seeds (reading R8) from the uniforms u[0..k-1]."""
+    s = _Src(D, X, metric)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    if len(u) < k:
+        raise ValueError("need k uniforms")
+    med = np.empty(k, np.int32)
+    rc = _load().orc_init_dw(*s.args(), int(k), _ptr(u), _ptr(med))
+    if rc:
+        raise ValueError("orc_init_dw rc=%d" % rc)
+    return med
+
+
+def init_lab(k, samples, D=None, X=None, metric=L2, exclude_self=False) -> np.ndarray:
+    """LAB (reading R9): samples is a (k, m) array, row t = step t's subsample."""
+    s = _Src(D, X, metric)
+    samples = np.ascontiguousarray(samples, dtype=np.int32)
+    if samples.ndim != 2 or samples.shape[0] != k:
+        raise ValueError("samples must be (k, m)")
+    med = np.empty(k, np.int32)
+    rc = _load().orc_init_lab(*s.args(), int(k), _ptr(samples), int(samples.shape[1]),
+                              int(bool(exclude_self)), _ptr(med))
+    if rc:
+        raise ValueError("orc_init_lab rc=%d" % rc)
+    return med

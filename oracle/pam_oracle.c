@@ -53,6 +53,20 @@
  *      ends when n consecutive positions have been visited without a swap
  *      (the scan is back at the last swap's position).  Iterations count the
  *      passes begun: ceil(positions visited / n).
+ *   R8 Distance-weighted seeding (Sec. 3.4, the k-means++ idea with the
+ *      distance to the nearest seed as weight, the k-medoids loss term):
+ *      the first seed is floor(u_0 n); seed t is the first object, in index
+ *      order, whose running weight sum exceeds u_t W (W = sum of weights,
+ *      summed in index order); seeds weigh 0 and are never picked again.
+ *      If W = 0 the smallest-index non-seed is taken.  The uniforms u_t in
+ *      [0, 1) are inputs.
+ *   R9 LAB (Sec. 3.4): each BUILD step is restricted to a subsample supplied
+ *      by the caller (10 + ceil(sqrt n) points, distinct): its non-medoid
+ *      members are the candidates, in the order listed, and its members the
+ *      objects of the change (self-term as in R1); the first strict minimum
+ *      is taken.  If every member is a medoid the smallest-index non-medoid
+ *      is taken.  With the whole data set listed in index order every step
+ *      equals BUILD's.
  */
 #include <math.h>
 #include <stdint.h>
@@ -644,4 +658,91 @@ int orc_swap(const double *D, const double *X, int64_t n, int32_t dim, int32_t m
     }
     free(is_med); free(dn); free(ds); free(near); free(tab); free(order); free(bdel); free(bcand);
     return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Faster initialisations (Sec. 3.4): distance-weighted seeding (R8)    */
+/* and LAB (R9).  med receives k object indices in slot order.          */
+/* ------------------------------------------------------------------ */
+int orc_init_dw(const double *D, const double *X, int64_t n, int32_t dim, int32_t metric,
+                int32_t k, const double *u, int32_t *med)
+{
+    src_t s;
+    if (make_src(&s, D, X, n, dim, metric) || k < 1 || k > n || !u || !med) return ORC_ERR_ARG;
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    unsigned char *is_med = (unsigned char *)calloc((size_t)n, 1);
+    if (!w || !is_med) { free(w); free(is_med); return ORC_ERR_MEM; }
+    int64_t c = (int64_t)floor(u[0] * (double)n);
+    if (c < 0) c = 0;
+    if (c >= n) c = n - 1;
+    med[0] = (int32_t)c;
+    is_med[c] = 1;
+    for (int64_t o = 0; o < n; ++o) w[o] = dist(&s, o, c);
+    for (int32_t t = 1; t < k; ++t) {
+        double W = 0.0;
+        for (int64_t o = 0; o < n; ++o) W += w[o];
+        const double target = u[t] * W;
+        int64_t pick = -1;
+        double run = 0.0;
+        for (int64_t o = 0; o < n; ++o) {
+            run += w[o];
+            if (run > target) { pick = o; break; }
+        }
+        if (pick < 0)
+            for (int64_t o = 0; o < n; ++o)
+                if (!is_med[o]) { pick = o; break; }
+        med[t] = (int32_t)pick;
+        is_med[pick] = 1;
+        for (int64_t o = 0; o < n; ++o) {
+            const double d = dist(&s, o, pick);
+            if (d < w[o]) w[o] = d;
+        }
+    }
+    free(w); free(is_med);
+    return ORC_OK;
+}
+
+int orc_init_lab(const double *D, const double *X, int64_t n, int32_t dim, int32_t metric,
+                 int32_t k, const int32_t *samp, int32_t m, int32_t exclude_self, int32_t *med)
+{
+    src_t s;
+    if (make_src(&s, D, X, n, dim, metric) || k < 1 || k > n || !samp || m < 1 || !med)
+        return ORC_ERR_ARG;
+    for (int64_t j = 0; j < (int64_t)k * m; ++j)
+        if (samp[j] < 0 || samp[j] >= n) return ORC_ERR_ARG;
+    double *dn = (double *)malloc(sizeof(double) * (size_t)n);
+    unsigned char *is_med = (unsigned char *)calloc((size_t)n, 1);
+    if (!dn || !is_med) { free(dn); free(is_med); return ORC_ERR_MEM; }
+    for (int64_t o = 0; o < n; ++o) dn[o] = INFINITY;
+    for (int32_t t = 0; t < k; ++t) {
+        const int32_t *S = samp + (int64_t)t * m;
+        double best = INFINITY;
+        int64_t bc = -1;
+        for (int32_t j = 0; j < m; ++j) {
+            const int64_t c = S[j];
+            if (is_med[c]) continue;
+            double acc = 0.0;
+            for (int32_t jj = 0; jj < m; ++jj) {
+                const int64_t o = S[jj];
+                if (o == c) continue;
+                if (t == 0) { acc += dist(&s, o, c); continue; }
+                if (is_med[o]) continue;
+                const double delta = dist(&s, o, c) - dn[o];
+                if (delta < 0.0) acc += delta;
+            }
+            if (t > 0 && !exclude_self) acc -= dn[c];
+            if (acc < best) { best = acc; bc = c; }
+        }
+        if (bc < 0)
+            for (int64_t o = 0; o < n; ++o)
+                if (!is_med[o]) { bc = o; break; }
+        med[t] = (int32_t)bc;
+        is_med[bc] = 1;
+        for (int64_t o = 0; o < n; ++o) {
+            const double d = dist(&s, o, bc);
+            if (d < dn[o]) dn[o] = d;
+        }
+    }
+    free(dn); free(is_med);
+    return ORC_OK;
 }

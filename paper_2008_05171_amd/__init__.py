@@ -17,7 +17,7 @@ from .pamx import (PAMX_ACC_F32, PAMX_ACC_F64, PAMX_CHUNK_TUNE, PAMX_DIST_BF16, 
                    PAMX_FASTERPAM, PAMX_FASTPAM1,
                    PAMX_FASTPAM2, PAMX_INPUT_D, PAMX_INPUT_X, PAMX_L1, PAMX_L2, PamxError)
 
-__all__ = ["fit", "build", "swap", "dist", "fit_batched", "FitResult", "BatchResult", "PamxError", "PAMX_FASTPAM1",
+__all__ = ["fit", "build", "swap", "dist", "init_dw", "init_lab", "fit_batched", "FitResult", "BatchResult", "PamxError", "PAMX_FASTPAM1",
            "PAMX_FASTPAM2", "PAMX_FASTERPAM", "PAMX_L1", "PAMX_L2", "PAMX_ACC_F64", "PAMX_ACC_F32",
            "PAMX_INPUT_D", "PAMX_INPUT_X", "PAMX_CHUNK_TUNE"]
 
@@ -87,7 +87,8 @@ def _stats_dict(st):
 
 def fit(data, k, *, input_kind=PAMX_INPUT_X, metric=None, variant="fastpam1",
         accum=PAMX_ACC_F64, max_iter=10000, exclude_self=False, trace=False, chunk=0,
-        dist_mode="stored", graph=False, window=0, stream=None) -> FitResult:
+        dist_mode="stored", graph=False, window=0, init="build", seed=0,
+        stream=None) -> FitResult:
     """Distances (for points), BUILD, SWAP, labels and TD on the GPU.
 
     data: device tensor, n x dim points (int32 -> L1, float32 -> L2) or an
@@ -97,8 +98,16 @@ def fit(data, k, *, input_kind=PAMX_INPUT_X, metric=None, variant="fastpam1",
     chunk: objects per pass work-group, 0 = automatic, PAMX_CHUNK_TUNE = timed
     once per process and shape on this matrix (stats["chunk"] reports it).
     variant="fasterpam": Alg. 4; window = candidates scored per pass (0 =
-    automatic)."""
+    automatic).
+    init: "build" (PAM BUILD, default), or one of the initialisations of
+    Sec. 3.4 drawn from `seed`: "random" (k uniform distinct objects), "dw"
+    (distance-weighted seeding), "lab" (linear approximative BUILD); these
+    run on the stored matrix (computed first for points), then SWAP."""
     import torch
+    if init != "build":
+        return _fit_init(data, k, input_kind=input_kind, metric=metric, variant=variant,
+                         max_iter=max_iter, exclude_self=exclude_self, trace=trace, chunk=chunk,
+                         graph=graph, window=window, init=init, seed=seed, stream=stream)
     n = data.shape[0]
     dim = data.shape[1] if input_kind == PAMX_INPUT_X else 0
     dtype = _abi._dtype_code(data)
@@ -115,6 +124,37 @@ def fit(data, k, *, input_kind=PAMX_INPUT_X, metric=None, variant="fastpam1",
     rc, td, st = _abi.pamx_fit(data, input_kind, k, med, lab, ws, metric=metric, opt=opt,
                                stream=stream)
     return FitResult(med, lab, td, rc, _stats_dict(st), _trace_list(tbuf, min(st.swaps, cap)))
+
+
+def _fit_init(data, k, *, input_kind, metric, variant, max_iter, exclude_self, trace, chunk,
+              graph, window, init, seed, stream):
+    import time
+    import torch
+    from . import datagen
+    n = data.shape[0]
+    torch.cuda.synchronize(data.device)
+    t0 = time.perf_counter()
+    D = dist(data, metric=metric, stream=stream) if input_kind == PAMX_INPUT_X else data
+    torch.cuda.synchronize(data.device)
+    t1 = time.perf_counter()
+    if init == "random":
+        med = torch.from_numpy(datagen.random_subset(n, k, seed)).to(data.device)
+    elif init == "dw":
+        med = init_dw(D, k, seed=seed, stream=stream)
+    elif init == "lab":
+        med = init_lab(D, k, seed=seed, exclude_self=exclude_self, stream=stream)
+    else:
+        raise ValueError("unknown init %r" % (init,))
+    torch.cuda.synchronize(data.device)
+    t2 = time.perf_counter()
+    r = swap(D, med, variant=variant, max_iter=max_iter, trace=trace, chunk=chunk, graph=graph,
+             window=window, stream=stream)
+    r.stats["init"] = init
+    r.stats["init_medoids"] = med
+    r.stats["ms_dist"] = (t1 - t0) * 1e3
+    r.stats["ms_build"] = (t2 - t1) * 1e3
+    r.stats["ms_total"] = r.stats["ms_dist"] + r.stats["ms_build"] + r.stats["ms_swap"]
+    return r
 
 
 def build(D, k, *, exclude_self=False, stream=None):
@@ -144,6 +184,43 @@ def swap(D, medoids, *, variant="fastpam1", accum=PAMX_ACC_F64, max_iter=10000, 
     lab = torch.empty(n, dtype=torch.int32, device=D.device)
     rc, td, st = _abi.pamx_swap(D, k, med, ws, labels=lab, opt=opt, stream=stream)
     return FitResult(med, lab, td, rc, _stats_dict(st), _trace_list(tbuf, min(st.swaps, cap)))
+
+
+def init_dw(D, k, *, seed=0, u=None, stream=None):
+    """Distance-weighted seeds (Sec. 3.4) from k uniforms (drawn from `seed`
+    unless given): device int32 [k]."""
+    import torch
+    from . import datagen
+    n = D.shape[0]
+    if u is None:
+        u = datagen.uniforms(k, seed)
+    ud = torch.as_tensor(u, dtype=torch.float64).to(D.device)
+    ws = _workspace(_abi.pamx_init_workspace_bytes(n, 0), D.device)
+    med = torch.empty(k, dtype=torch.int32, device=D.device)
+    _abi.pamx_init_dw(D, k, ud, med, ws, stream=stream)
+    return med
+
+
+def lab_sample_size(n):
+    """LAB's per-step subsample, 10 + ceil(sqrt(n)) points (Sec. 3.4), at most n."""
+    import math
+    return min(n, 10 + math.isqrt(n - 1) + 1 if n > 1 else 1)
+
+
+def init_lab(D, k, *, seed=0, m=None, samples=None, exclude_self=False, stream=None):
+    """LAB seeds (Sec. 3.4): BUILD on a fresh subsample of m points per step
+    (default 10 + ceil(sqrt(n)); rows of `samples` if given).  Device int32 [k]."""
+    import torch
+    from . import datagen
+    n = D.shape[0]
+    if samples is None:
+        m = lab_sample_size(n) if m is None else int(m)
+        samples = datagen.subsamples(n, k, m, seed)
+    sd = torch.as_tensor(samples, dtype=torch.int32).to(D.device).contiguous()
+    ws = _workspace(_abi.pamx_init_workspace_bytes(n, sd.shape[1]), D.device)
+    med = torch.empty(k, dtype=torch.int32, device=D.device)
+    _abi.pamx_init_lab(D, k, sd, med, ws, exclude_self=exclude_self, stream=stream)
+    return med
 
 
 def dist(X, *, metric=None, ld=None, stream=None):

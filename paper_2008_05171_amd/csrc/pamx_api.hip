@@ -879,6 +879,74 @@ extern "C" int pamx_swap(const void *D, int32_t dtype, int64_t n, int64_t ld, in
     return rc;
 }
 
+// ---------------------------------------------------------------- faster initialisations
+extern "C" int pamx_init_workspace_bytes(int64_t n, int32_t m, size_t *bytes) {
+    if (!bytes) return fail(PAMX_ERR_ARG, "bytes is NULL");
+    if (n < 1 || n > (int64_t)INT32_MAX - 1) return fail(PAMX_ERR_ARG, "n out of range");
+    if (m < 0 || m > n) return fail(PAMX_ERR_ARG, "m must be in [0, n]");
+    *bytes = make_init_layout(n, m).total;
+    return PAMX_OK;
+}
+
+static int init_args(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                     const int32_t *medoids, const void *ws, size_t ws_bytes, int32_t m) {
+    if (n < 1 || n > (int64_t)INT32_MAX - 1) return fail(PAMX_ERR_ARG, "n out of range");
+    if (k < 1 || k > n) return fail(PAMX_ERR_ARG, "k must be in [1, n]");
+    if (dtype != PAMX_I32 && dtype != PAMX_F32) return fail(PAMX_ERR_ARG, "unknown dtype %d", dtype);
+    int rc = check_matrix(D, n, ld);
+    if (rc) return rc;
+    if (!medoids) return fail(PAMX_ERR_ARG, "medoids is NULL");
+    if (!ws) return fail(PAMX_ERR_WORKSPACE, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return fail(PAMX_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    const size_t need = make_init_layout(n, m).total;
+    if (ws_bytes < need)
+        return fail(PAMX_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return PAMX_OK;
+}
+
+extern "C" int pamx_init_dw(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                            const double *u, int32_t *medoids, void *ws, size_t ws_bytes,
+                            void *stream) {
+    int rc = init_args(D, dtype, n, ld, k, medoids, ws, ws_bytes, 0);
+    if (rc) return rc;
+    if (!u) return fail(PAMX_ERR_ARG, "u is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == PAMX_F32)
+        HIP_TRY(launch_init_dw<float>(static_cast<const float *>(D), ld, n, k, u, medoids, ws, s));
+    else
+        HIP_TRY(launch_init_dw<int32_t>(static_cast<const int32_t *>(D), ld, n, k, u, medoids, ws, s));
+    return PAMX_OK;
+}
+
+extern "C" int pamx_init_lab(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                             const int32_t *samples, int32_t m, int32_t exclude_self,
+                             int32_t *medoids, void *ws, size_t ws_bytes, void *stream) {
+    if (m < 1 || m > n) return fail(PAMX_ERR_ARG, "m must be in [1, n]");
+    int rc = init_args(D, dtype, n, ld, k, medoids, ws, ws_bytes, m);
+    if (rc) return rc;
+    if (!samples) return fail(PAMX_ERR_ARG, "samples is NULL");
+    if (exclude_self != 0 && exclude_self != 1) return fail(PAMX_ERR_ARG, "exclude_self must be 0 or 1");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // every listed index in [0, n) before any step runs
+    {
+        int32_t *err = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + make_init_layout(n, m).err);
+        int32_t e0 = 0;
+        HIP_TRY(launch_init_zero(err, s));
+        HIP_TRY(launch_check_sidx(samples, (int64_t)k * m, n, err, s));
+        HIP_TRY(hipMemcpyAsync(&e0, err, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (e0) return fail(PAMX_ERR_ARG, "samples holds an index outside [0, n)");
+    }
+    if (dtype == PAMX_F32)
+        HIP_TRY(launch_init_lab<float>(static_cast<const float *>(D), ld, n, k, samples, m,
+                                       exclude_self, medoids, ws, s));
+    else
+        HIP_TRY(launch_init_lab<int32_t>(static_cast<const int32_t *>(D), ld, n, k, samples, m,
+                                         exclude_self, medoids, ws, s));
+    return PAMX_OK;
+}
+
 extern "C" int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int64_t n, int32_t dim,
                         int32_t metric, int32_t k, const pamx_options *opt_in, int32_t *medoids,
                         int32_t *labels, double *td, pamx_stats *stats, void *ws, size_t ws_bytes,

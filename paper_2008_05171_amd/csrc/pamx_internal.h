@@ -246,6 +246,22 @@ hipError_t launch_clara(const T *X, int64_t N, int32_t dim, const BatchArgs &a, 
 template <typename T>
 hipError_t launch_full_assign(const T *X, int64_t N, int32_t dim, const BatchArgs &a, hipStream_t s);
 
+// Workspace of the faster initialisations (init.hip): weights / nearest
+// distances (two buffers), block sums (two buffers), medoid flags, the
+// subsample changes and an error flag.
+struct InitLayout {
+    int32_t nblk;
+    size_t dn0, dn1, bs0, bs1, is_med, vals, err, total;
+};
+InitLayout make_init_layout(int64_t n, int32_t m);
+template <typename T>
+hipError_t launch_init_dw(const T *D, int64_t ld, int64_t n, int32_t k, const double *u,
+                          int32_t *med, void *ws, hipStream_t s);
+hipError_t launch_init_zero(int32_t *p, hipStream_t s);
+template <typename T>
+hipError_t launch_init_lab(const T *D, int64_t ld, int64_t n, int32_t k, const int32_t *S,
+                           int32_t m, int32_t excl, int32_t *med, void *ws, hipStream_t s);
+
 template <typename T>
 hipError_t run_build(const T *D, int64_t ld, const Layout &L, int32_t k, int32_t exclude_self,
                      int32_t *medoids, void *ws, hipStream_t s, hipEvent_t *ev);

@@ -79,6 +79,24 @@ def clara_samples(N: int, n_inst: int, k_lo: int, k_hi: int, n_hi: int, seed: in
 
 
 # Named workloads (shapes and distributions of the measured configurations).
+def uniforms(count: int, seed: int = 0) -> np.ndarray:
+    """count float64 uniforms in [0, 1)."""
+    return _rng(seed).random(count)
+
+
+def random_subset(n: int, size: int, seed: int = 0) -> np.ndarray:
+    """size distinct indices of [0, n), drawn uniformly, int32."""
+    return _rng(seed).choice(n, size=size, replace=False).astype(np.int32)
+
+
+def subsamples(n: int, rows: int, size: int, seed: int = 0) -> np.ndarray:
+    """(rows, size) int32: each row `size` distinct indices of [0, n) drawn
+    uniformly, listed in ascending order."""
+    g = _rng(seed)
+    return np.stack([np.sort(g.choice(n, size=size, replace=False))
+                     for _ in range(rows)]).astype(np.int32)
+
+
 def workload_l1_int(n=1000, dim=2, seed=1001, hi=1000):
     """Integer coordinates uniform in [0, hi), Manhattan dissimilarity."""
     return int_points(n, dim, 0, hi, seed)

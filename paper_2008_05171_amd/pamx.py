@@ -62,7 +62,7 @@ class pamx_batch_stats(ctypes.Structure):
 
 EXPORTS = ("pamx_default_options", "pamx_workspace_bytes", "pamx_dist", "pamx_build",
            "pamx_swap", "pamx_fit", "pamx_batched_workspace_bytes", "pamx_fit_batched",
-           "pamx_last_error")
+           "pamx_init_workspace_bytes", "pamx_init_dw", "pamx_init_lab", "pamx_last_error")
 
 
 class PamxError(RuntimeError):
@@ -97,10 +97,14 @@ def load(path: str = LIB_PATH):
     lib.pamx_batched_workspace_bytes.argtypes = [i32, i64, ctypes.POINTER(sz)]
     lib.pamx_fit_batched.argtypes = [P, i32, i64, i32, i32, i32, P, P, P, opt_p, P, P, P,
                                      ctypes.POINTER(pamx_batch_stats), P, sz, P]
+    lib.pamx_init_workspace_bytes.argtypes = [i64, i32, ctypes.POINTER(sz)]
+    lib.pamx_init_dw.argtypes = [P, i32, i64, i64, i32, P, P, P, sz, P]
+    lib.pamx_init_lab.argtypes = [P, i32, i64, i64, i32, P, i32, i32, P, P, sz, P]
     lib.pamx_last_error.argtypes = []
     lib.pamx_last_error.restype = ctypes.c_char_p
     for name in ("pamx_workspace_bytes", "pamx_dist", "pamx_build", "pamx_swap", "pamx_fit",
-                 "pamx_batched_workspace_bytes", "pamx_fit_batched"):
+                 "pamx_batched_workspace_bytes", "pamx_fit_batched", "pamx_init_workspace_bytes",
+                 "pamx_init_dw", "pamx_init_lab"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -224,3 +228,28 @@ def pamx_fit_batched(X, metric, sample_off, sample_idx, k_inst, medoids, ws, opt
 
 def pamx_last_error() -> str:
     return load().pamx_last_error().decode()
+
+
+def pamx_init_workspace_bytes(n, m=0) -> int:
+    out = ctypes.c_size_t()
+    _check(load().pamx_init_workspace_bytes(int(n), int(m), ctypes.byref(out)))
+    return int(out.value)
+
+
+def pamx_init_dw(D, k, u, medoids, ws, n=None, ld=None, stream=None):
+    """u: device float64 [k] uniforms in [0, 1)."""
+    n = D.shape[0] if n is None else n
+    ld = D.stride(0) if ld is None else ld
+    return _check(load().pamx_init_dw(_ptr(D), _dtype_code(D), int(n), int(ld), int(k), _ptr(u),
+                                      _ptr(medoids), _ptr(ws), ws.numel() * ws.element_size(),
+                                      _stream(stream)))
+
+
+def pamx_init_lab(D, k, samples, medoids, ws, exclude_self=False, n=None, ld=None, stream=None):
+    """samples: device int32 (k, m), row t = step t's subsample."""
+    n = D.shape[0] if n is None else n
+    ld = D.stride(0) if ld is None else ld
+    m = int(samples.shape[1])
+    return _check(load().pamx_init_lab(_ptr(D), _dtype_code(D), int(n), int(ld), int(k),
+                                       _ptr(samples), m, int(bool(exclude_self)), _ptr(medoids),
+                                       _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))

@@ -149,3 +149,32 @@ def fasterpam_swap(D, med, max_passes=1000):
             trace.append((i, c, ch[i]))
             quiet = 0
     return med, trace, (visited + n - 1) // n
+
+
+def lab_greedy(D, k, samples, exclude_self=False):
+    """LAB by full recomputation: at step t the candidate of samples[t] (in
+    listed order, medoids skipped, first strict minimum) that minimises the
+    TD of the subsample, TD_S(M + [c]); step 0 uses TD_S([c]) (the first BUILD
+    step on the subsample).  With exclude_self the candidate's own drop to
+    distance zero is not counted."""
+    n = len(D)
+    med = []
+    for t in range(k):
+        S = list(samples[t])
+        best, bc = None, None
+        for c in S:
+            if c in med:
+                continue
+            if t == 0:
+                ch = sum(D[o][c] for o in S if o != c)
+            else:
+                dn = {o: min(D[o][m] for m in med) for o in S}
+                ch = sum(min(dn[o], D[o][c]) for o in S) - sum(dn[o] for o in S)
+                if exclude_self and c in dn:
+                    ch += dn[c]
+            if best is None or ch < best:
+                best, bc = ch, c
+        if bc is None:
+            bc = min(o for o in range(n) if o not in med)
+        med.append(bc)
+    return med

@@ -134,6 +134,34 @@ def test_fasterpam_window_option(lib):
     assert e.value.code == abi.PAMX_ERR_UNSUPPORTED
 
 
+def test_init_argument_errors(lib):
+    """The initialisation entry points reject bad arguments before any
+    device work."""
+    fake = ctypes.c_void_p(0x100000)
+    ws = ctypes.c_void_p(0x200000)
+    need = abi.pamx_init_workspace_bytes(1000, 42)
+    assert need >= abi.pamx_init_workspace_bytes(1000, 0) > 1000 * 8
+    with pytest.raises(abi.PamxError):
+        abi.pamx_init_workspace_bytes(1000, 1001)
+    dw = lib.pamx_init_dw
+    assert dw(None, abi.PAMX_F32, 1000, 1000, 5, fake, fake, ws, 1 << 30, None) == abi.PAMX_ERR_ARG
+    assert dw(fake, abi.PAMX_F32, 1000, 1000, 1001, fake, fake, ws, 1 << 30, None) == abi.PAMX_ERR_ARG
+    assert dw(fake, abi.PAMX_F32, 1000, 1000, 0, fake, fake, ws, 1 << 30, None) == abi.PAMX_ERR_ARG
+    assert dw(fake, 9, 1000, 1000, 5, fake, fake, ws, 1 << 30, None) == abi.PAMX_ERR_ARG
+    assert dw(fake, abi.PAMX_F32, 1000, 999, 5, fake, fake, ws, 1 << 30, None) == abi.PAMX_ERR_ARG
+    assert dw(fake, abi.PAMX_F32, 1000, 1000, 5, None, fake, ws, 1 << 30, None) == abi.PAMX_ERR_ARG
+    assert dw(fake, abi.PAMX_F32, 1000, 1000, 5, fake, None, ws, 1 << 30, None) == abi.PAMX_ERR_ARG
+    assert dw(fake, abi.PAMX_F32, 1000, 1000, 5, fake, fake, ws, 64, None) == abi.PAMX_ERR_WORKSPACE
+    assert dw(fake, abi.PAMX_F32, 1000, 1000, 5, fake, fake, ctypes.c_void_p(0x200010), 1 << 30,
+              None) == abi.PAMX_ERR_WORKSPACE
+    lab = lib.pamx_init_lab
+    assert lab(fake, abi.PAMX_I32, 1000, 1000, 5, fake, 0, 0, fake, ws, 1 << 30, None) == abi.PAMX_ERR_ARG
+    assert lab(fake, abi.PAMX_I32, 1000, 1000, 5, fake, 1001, 0, fake, ws, 1 << 30, None) == abi.PAMX_ERR_ARG
+    assert lab(fake, abi.PAMX_I32, 1000, 1000, 5, None, 42, 0, fake, ws, 1 << 30, None) == abi.PAMX_ERR_ARG
+    assert lab(fake, abi.PAMX_I32, 1000, 1000, 5, fake, 42, 2, fake, ws, 1 << 30, None) == abi.PAMX_ERR_ARG
+    assert lab(fake, abi.PAMX_I32, 1000, 1000, 5, fake, 42, 0, fake, ws, 100, None) == abi.PAMX_ERR_WORKSPACE
+
+
 def test_points_metric_rules(lib):
     fake = ctypes.c_void_p(0x100000)
     rc = lib.pamx_dist(fake, abi.PAMX_I32, 10, 2, abi.PAMX_L2, fake, 12, None, 0, None)

@@ -419,6 +419,79 @@ def test_fasterpam_bookkeeping_on_int_workload():
     assert not found
 
 
+# ---------------------------------------------------------------- faster initialisations
+def test_init_dw_pick_frequencies_follow_distances():
+    """With one seed placed, the second seed is drawn with probability
+    proportional to the distance to that seed: empirical frequencies over
+    many uniforms match the column of D (chi-square far below the 0.1% point),
+    the seed itself (weight 0) is never drawn, and the pick is monotone in u."""
+    rng = np.random.default_rng(61)
+    D, _ = _tiny_int_D(rng, 12, hi=30)
+    u0 = 5.5 / 12                       # first seed: floor(u0 n) = 5
+    draws = 20000
+    us = np.sort(rng.random(draws))
+    picks = np.array([oracle.init_dw(2, [u0, u], D=D)[1] for u in us])
+    assert np.all(np.diff(picks) >= 0)
+    assert np.all(picks != 5)
+    w = D[:, 5]
+    p = w / w.sum()
+    cnt = np.bincount(picks, minlength=12)
+    keep = p > 0
+    chi2 = float((((cnt - draws * p) ** 2)[keep] / (draws * p[keep])).sum())
+    assert chi2 < 31.3                  # chi-square, 10 degrees of freedom, 0.1%
+    assert oracle.init_dw(2, [u0, 0.0], D=D)[1] == int(np.flatnonzero(w > 0)[0])
+    assert oracle.init_dw(2, [u0, 1 - 1e-12], D=D)[1] == int(np.flatnonzero(w > 0)[-1])
+
+
+def test_init_dw_distinct_and_duplicates_never_drawn():
+    """Points that coincide with a seed have weight 0: the seeds are distinct
+    points; when every point coincides with a seed the smallest free index is
+    taken."""
+    rng = np.random.default_rng(67)
+    X = np.repeat(rng.integers(0, 100, size=(8, 2)), 5, axis=0).astype(np.float64)
+    D = oracle.dist_matrix(X, oracle.L1)
+    for trial in range(30):
+        med = oracle.init_dw(8, rng.random(8), D=D)
+        assert len(set(med)) == 8
+        assert len({tuple(X[m]) for m in med}) == 8
+    med = oracle.init_dw(10, rng.random(10), D=D)
+    assert len(set(med)) == 10
+    rest = [m for m in med[8:]]
+    free = [o for o in range(40) if o not in med[:8]]
+    assert rest[0] == free[0] and rest[1] == [o for o in free if o != rest[0]][0]
+
+
+@pytest.mark.parametrize("exclude_self", [False, True])
+def test_init_lab_full_sample_is_build(exclude_self):
+    """LAB with the whole data set (index order) as every step's sample is
+    BUILD, and both equal the brute-force greedy TD recomputation."""
+    rng = np.random.default_rng(71)
+    for _ in range(10):
+        n = int(rng.integers(6, 25))
+        k = int(rng.integers(1, 5))
+        D, _ = _tiny_int_D(rng, n, hi=15)
+        S = np.tile(np.arange(n), (k, 1))
+        lab = oracle.init_lab(k, S, D=D, exclude_self=exclude_self)
+        assert list(lab) == list(oracle.build(k, D=D, exclude_self=exclude_self)[0])
+        assert list(lab) == brute.build_greedy(D.tolist(), k, exclude_self=exclude_self)
+
+
+@pytest.mark.parametrize("exclude_self", [False, True])
+def test_init_lab_matches_subsample_bruteforce(exclude_self):
+    """Random subsamples of 10 + ceil(sqrt n) points per step: each step picks
+    the candidate with the smallest recomputed TD of its subsample."""
+    rng = np.random.default_rng(73)
+    for _ in range(15):
+        n = int(rng.integers(20, 60))
+        k = int(rng.integers(2, 7))
+        m = 10 + int(np.ceil(np.sqrt(n)))
+        D, _ = _tiny_int_D(rng, n, hi=25)
+        S = np.array([np.sort(rng.choice(n, size=m, replace=False)) for _ in range(k)])
+        lab = oracle.init_lab(k, S, D=D, exclude_self=exclude_self)
+        assert list(lab) == brute.lab_greedy(D.tolist(), k, S.tolist(), exclude_self)
+        assert len(set(lab)) == k
+
+
 # ---------------------------------------------------------------- degenerate cases
 def test_k_equals_n_and_duplicates():
     X = np.array([[0.0], [0.0], [1.0], [1.0], [5.0]])
