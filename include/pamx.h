@@ -137,9 +137,12 @@ typedef struct pamx_options {
                                    every kernel launched directly (measured
                                    faster: a replay costs more than the launches
                                    it replaces)                              */
-    int32_t window;             /* PAMX_FASTERPAM: candidates scored per pass
-                                   (rounded up to whole 1024- or 256-candidate
-                                   tiles); 0 (default) = automatic           */
+    int32_t window;             /* PAMX_FASTERPAM: largest number of candidates
+                                   scored per pass (rounded up to whole 1024-
+                                   or 256-candidate tiles; a pass after a swap
+                                   scores one tile, each pass without a swap
+                                   doubles the width up to this); 0 (default)
+                                   = 16 tiles                                */
     void *trace;                /* optional DEVICE array of pamx_swap_record:
                                    every applied swap in order               */
 } pamx_options;
@@ -175,7 +178,7 @@ typedef struct pamx_stats {
     int64_t scan_positions;/* PAMX_FASTERPAM: candidate positions visited
                               (iterations = passes begun = ceil(positions / n)) */
     int32_t windows;       /* PAMX_FASTERPAM: window passes run */
-    int32_t window;        /* PAMX_FASTERPAM: candidates per window pass */
+    int32_t window;        /* PAMX_FASTERPAM: largest window (candidates) */
 } pamx_stats;
 
 /* Fills `opt` with the defaults listed above. */

@@ -94,15 +94,15 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->n_mwg = (int32_t)((n + kWG - 1) / kWG);
     const bool p2 = opt && opt->variant == PAMX_FASTPAM2;
     if (opt && opt->variant == PAMX_FASTERPAM) {
-        // window: the requested width rounded up to whole tiles, else about a
-        // sixteenth of the candidates; its pass is chunked to about two
-        // work-groups per compute unit
-        int64_t m = (opt->window > 0) ? (opt->window + L->tile - 1) / L->tile : L->n_ctiles / 16;
+        // largest window: the requested width rounded up to whole tiles, else
+        // 16 tiles; the pass is chunked for about two work-groups per compute
+        // unit on a one-tile window (the width after a swap)
+        int64_t m = (opt->window > 0) ? (opt->window + L->tile - 1) / L->tile : 16;
         if (m < 1) m = 1;
         if (m > L->n_ctiles) m = L->n_ctiles;
         if (m > 256) m = 256;
         L->fw = (int32_t)(m * L->tile);
-        int64_t Q = 512 / m;
+        int64_t Q = 512;
         const int64_t qmax = (n + 63) / 64;
         if (Q > qmax) Q = qmax;
         if (Q < 1) Q = 1;
@@ -716,7 +716,7 @@ int swap_impl(const T *D, int64_t ld, const Layout &L_in, int32_t k, const pamx_
             stats->windows = searches ? st.iter : 0;
             stats->window = L.fw;
             stats->scan_positions = searches ? st.fp_visited : 0;
-            stats->pass_pairs = (int64_t)(searches ? st.iter : 0) * L.fw * n;
+            stats->pass_pairs = searches ? st.fp_cols * n : 0;
         }
     }
     return st.capped ? PAMX_WARN_MAXITER : PAMX_OK;

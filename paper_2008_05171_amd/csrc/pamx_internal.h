@@ -70,6 +70,8 @@ struct alignas(64) DevState {
     long long fp_limit;  // max_iter * n
     long long fw_base;   // window of the next pass: [fw_base, fw_end)
     long long fw_end;
+    int32_t fw_tiles;    // its width in candidate tiles
+    long long fp_cols;   // candidate columns scored by the window passes
 };
 
 // Lexicographic "a is better than b" on (value, slot, candidate).
@@ -162,7 +164,7 @@ struct Layout {
     int64_t ncp;         // padded candidate count = n_ctiles * tile
     int32_t n_oblk;      // object blocks of kObjBlk
     int32_t n_mwg;       // merge work-groups = ceil(n / kWG)
-    int32_t fw;          // FasterPAM: candidates per window (a multiple of tile), or 0
+    int32_t fw;          // FasterPAM: largest window (a multiple of tile), or 0
     int32_t fwL, fwQ;    // FasterPAM: object chunk length and count of the window pass
     size_t esz;          // element size of D (4)
     size_t asz;          // accumulator size (8)

@@ -712,24 +712,20 @@ __global__ __launch_bounds__(kObjBlk) void k_seg_scatter(const int32_t *__restri
 // segments into P[i][c].  WIN (FasterPAM) evaluates the candidate window
 // [fw_base, fw_end) of the state; the partials are indexed relative to
 // fw_base (ncp is then the window width).
-template <typename T, int VEC, bool P2, bool WIN>
-__global__ __launch_bounds__(kWG) void k_swap_pass(
-    const T *__restrict__ D, int64_t ld, int64_t n, int32_t k, const int32_t *__restrict__ srow,
-    const T *__restrict__ sdn, const T *__restrict__ sds, const int32_t *__restrict__ seg_off,
-    AccT<T> *__restrict__ cdn, const ChunkInfo *__restrict__ cinfo, int32_t L, int64_t ncp,
-    AccT<T> *__restrict__ part, int32_t *__restrict__ part_i, AccT<T> *__restrict__ P,
-    const DevState *__restrict__ st) {
+template <typename T, int VEC, bool P2>
+__device__ __forceinline__ void pass_tile(
+    int tile, int q, int64_t cb, int64_t ce, const T *__restrict__ D, int64_t ld, int64_t n,
+    const int32_t *__restrict__ srow, const T *__restrict__ sdn, const T *__restrict__ sds,
+    const int32_t *__restrict__ seg_off, AccT<T> *__restrict__ cdn,
+    const ChunkInfo *__restrict__ cinfo, int32_t L, int64_t ncp, AccT<T> *__restrict__ part,
+    int32_t *__restrict__ part_i, AccT<T> *__restrict__ P) {
     using A = AccT<T>;
     // four rows in flight per lane: measured faster than eight or sixteen
     // for a 20000 x 20000 FP32 matrix (fewer VGPRs, more waves per SIMD)
     constexpr int U = 4;
-    if (st->done) return;
-    const int q = blockIdx.y;
     const int64_t a = (int64_t)q * L;
     const int64_t b = min(a + (int64_t)L, n);
-    const int64_t cr = ((int64_t)blockIdx.x * kWG + threadIdx.x) * VEC;   // partial column
-    int64_t cb = 0, ce = n;
-    if constexpr (WIN) { cb = st->fw_base; ce = st->fw_end; }
+    const int64_t cr = ((int64_t)tile * kWG + threadIdx.x) * VEC;   // partial column
     const int64_t c0 = cb + cr;
     const bool active = c0 < ce;
     const ChunkInfo ci = cinfo[q];
@@ -786,7 +782,7 @@ __global__ __launch_bounds__(kWG) void k_swap_pass(
         // the first lane of the first tile (always a real candidate: windows
         // are never empty) records the chunk's part of DN for segments
         // carried across chunks
-        const bool rec = blockIdx.x == 0 && threadIdx.x == 0;
+        const bool rec = tile == 0 && threadIdx.x == 0;
         if (s == ci.sa && (ci.flags & kHead)) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) pq[1 * ncp + e] = M[e];
@@ -811,6 +807,27 @@ __global__ __launch_bounds__(kWG) void k_swap_pass(
         pq[0 * ncp + e] = accA[e];
         pq[3 * ncp + e] = bv[e];
         part_i[(int64_t)q * ncp + cr + e] = bi[e];
+    }
+}
+
+template <typename T, int VEC, bool P2, bool WIN>
+__global__ __launch_bounds__(kWG) void k_swap_pass(
+    const T *__restrict__ D, int64_t ld, int64_t n, int32_t k, const int32_t *__restrict__ srow,
+    const T *__restrict__ sdn, const T *__restrict__ sds, const int32_t *__restrict__ seg_off,
+    AccT<T> *__restrict__ cdn, const ChunkInfo *__restrict__ cinfo, int32_t L, int64_t ncp,
+    AccT<T> *__restrict__ part, int32_t *__restrict__ part_i, AccT<T> *__restrict__ P,
+    const DevState *__restrict__ st) {
+    if (st->done) return;
+    if constexpr (WIN) {
+        // one work-group per object chunk, over every tile of the window
+        const int64_t cb = st->fw_base, ce = st->fw_end;
+        const int nt = (int)((ce - cb + kWG * VEC - 1) / (kWG * VEC));
+        for (int t = 0; t < nt; ++t)
+            pass_tile<T, VEC, false>(t, blockIdx.y, cb, ce, D, ld, n, srow, sdn, sds, seg_off, cdn,
+                                     cinfo, L, ncp, part, part_i, P);
+    } else {
+        pass_tile<T, VEC, P2>(blockIdx.x, blockIdx.y, 0, n, D, ld, n, srow, sdn, sds, seg_off, cdn,
+                              cinfo, L, ncp, part, part_i, P);
     }
 }
 
@@ -969,12 +986,14 @@ __global__ __launch_bounds__(256) void k_select_update(
 // positions went by without a swap, or after max_iter passes.
 
 // Next window: starts at the scan position (rounded down to the load width;
-// the positions before it are masked), at most fw wide, not past n, the stop
-// position or the pass cap.
-__device__ __forceinline__ void fp_window(DevState *st, int64_t n, int64_t fw, int32_t vec) {
+// the positions before it are masked), fw_tiles tiles wide, not past n, the
+// stop position or the pass cap.  The width adapts to the spacing of the
+// swaps: one tile after a swap, doubled (up to the launch grid's max_tiles)
+// after each window without one; results do not depend on it.
+__device__ __forceinline__ void fp_window(DevState *st, int64_t n, int64_t tile, int32_t vec) {
     const long long pos = st->fp_pos;
     const long long base = pos - pos % vec;
-    long long end = base + fw;
+    long long end = base + (long long)st->fw_tiles * tile;
     if (end > n) end = n;
     const long long rest = (long long)n - st->fp_quiet;
     if (end > pos + rest) end = pos + rest;
@@ -984,8 +1003,9 @@ __device__ __forceinline__ void fp_window(DevState *st, int64_t n, int64_t fw, i
     st->fw_end = end;
 }
 
-__global__ void k_fp_init(DevState *st, int64_t n, int64_t fw, int32_t vec, long long limit) {
+__global__ void k_fp_init(DevState *st, int64_t n, int64_t tile, int32_t vec, long long limit) {
     st->fp = 1;
+    st->fw_tiles = 1;
     st->fp_pos = 0;
     st->fp_visited = 0;
     st->fp_quiet = 0;
@@ -995,7 +1015,7 @@ __global__ void k_fp_init(DevState *st, int64_t n, int64_t fw, int32_t vec, long
         st->done = 1;
         st->capped = 1;
     } else {
-        fp_window(st, n, fw, vec);
+        fp_window(st, n, tile, vec);
     }
 }
 
@@ -1024,115 +1044,129 @@ __global__ __launch_bounds__(256) void k_fp_merge(
     if (st->done) return;
     __shared__ RunSum<A> sm[G][CPB];
     __shared__ int first;
+    __shared__ A resv;
+    __shared__ int resi;
     const int j = threadIdx.x % CPB, g = threadIdx.x / CPB;
-    const int64_t cr = (int64_t)blockIdx.x * CPB + j;   // partial column
-    const int64_t c = st->fw_base + cr;
-    const bool live = c < st->fw_end;
-    RunSum<A> r;
-    r.accA = 0; r.bv = VT<T>::acc_inf(); r.bi = INT_MAX; r.nr = 0;
-    r.fs = -1; r.fm = 0; r.fdn = 0; r.ls = -1; r.lm = 0; r.ldn = 0;
-    if (live) {
-        const int per = (Q + G - 1) / G;
-        const int q0 = g * per, q1 = min(Q, q0 + per);
-        // the open run is (fs, fm, fdn) while nr == 1, else (ls, lm, ldn)
-        auto add = [&](int s, A m, A dn) {
-            if (r.nr == 0) { r.nr = 1; r.fs = s; r.fm = m; r.fdn = dn; return; }
-            if (r.nr == 1) {
-                if (s == r.fs) { r.fm += m; r.fdn += dn; }
-                else { r.nr = 2; r.ls = s; r.lm = m; r.ldn = dn; }
-                return;
-            }
-            if (s == r.ls) { r.lm += m; r.ldn += dn; return; }
-            const A v = r.lm - r.ldn;   // a run between the first and the last: complete
-            if (lt2(v, r.ls, r.bv, r.bi)) { r.bv = v; r.bi = r.ls; }
-            r.ls = s; r.lm = m; r.ldn = dn;
-        };
-        for (int q = q0; q < q1; ++q) {
-            const A *pq = part + (int64_t)q * 4 * cols + cr;
-            const A xa = pq[0], xh = pq[1 * cols], xt = pq[2 * cols], xv = pq[3 * cols];
-            const int32_t xi = part_i[(int64_t)q * cols + cr];
-            const ChunkInfo ci = cinfo[q];
-            r.accA += xa;
-            if (xi != INT_MAX && lt2(xv, xi, r.bv, r.bi)) { r.bv = xv; r.bi = xi; }
-            if (ci.flags & kHead) add(ci.sa, xh, cdn[2 * q]);
-            if (ci.flags & kTail) add(ci.sb, xt, cdn[2 * q + 1]);
-        }
-    }
-    sm[g][j] = r;
-    if (threadIdx.x == 0) first = INT_MAX;
-    __syncthreads();
-    A bestv = VT<T>::acc_inf();
-    int besti = INT_MAX;
-    bool neg = false;
-    if (g == 0 && live) {
-        A accA = 0, bv = VT<T>::acc_inf(), rm = 0, rdn = 0;
-        int bi = INT_MAX, rs = -1;
-        auto flush = [&](int s, A m, A dn) {
-            if (s < 0) return;
-            const A v = m - dn;
-            if (lt2(v, s, bv, bi)) { bv = v; bi = s; }
-        };
-        for (int h = 0; h < G; ++h) {
-            const RunSum<A> &x = sm[h][j];
-            accA += x.accA;
-            if (x.bi != INT_MAX && lt2(x.bv, x.bi, bv, bi)) { bv = x.bv; bi = x.bi; }
-            if (x.nr == 0) continue;
-            if (x.fs == rs) { rm += x.fm; rdn += x.fdn; }
-            else { flush(rs, rm, rdn); rs = x.fs; rm = x.fm; rdn = x.fdn; }
-            if (x.nr == 2) {   // the first run ended inside the group
-                flush(rs, rm, rdn);
-                rs = x.ls; rm = x.lm; rdn = x.ldn;
+    const int64_t cb = st->fw_base, ce = st->fw_end;
+    const int64_t ngrp = (ce - cb + CPB - 1) / CPB;
+    int found = INT_MAX;
+    // groups of 16 candidates, in increasing order per work-group: the first
+    // improving candidate found ends the work-group's search
+    for (int64_t grp = blockIdx.x; grp < ngrp && found == INT_MAX; grp += gridDim.x) {
+        const int64_t cr = grp * CPB + j;   // partial column
+        const int64_t c = cb + cr;
+        const bool live = c < ce;
+        RunSum<A> r;
+        r.accA = 0; r.bv = VT<T>::acc_inf(); r.bi = INT_MAX; r.nr = 0;
+        r.fs = -1; r.fm = 0; r.fdn = 0; r.ls = -1; r.lm = 0; r.ldn = 0;
+        if (live) {
+            const int per = (Q + G - 1) / G;
+            const int q0 = g * per, q1 = min(Q, q0 + per);
+            // the open run is (fs, fm, fdn) while nr == 1, else (ls, lm, ldn)
+            auto add = [&](int s, A m, A dn) {
+                if (r.nr == 0) { r.nr = 1; r.fs = s; r.fm = m; r.fdn = dn; return; }
+                if (r.nr == 1) {
+                    if (s == r.fs) { r.fm += m; r.fdn += dn; }
+                    else { r.nr = 2; r.ls = s; r.lm = m; r.ldn = dn; }
+                    return;
+                }
+                if (s == r.ls) { r.lm += m; r.ldn += dn; return; }
+                const A v = r.lm - r.ldn;   // a run between the first and the last: complete
+                if (lt2(v, r.ls, r.bv, r.bi)) { r.bv = v; r.bi = r.ls; }
+                r.ls = s; r.lm = m; r.ldn = dn;
+            };
+            for (int q = q0; q < q1; ++q) {
+                const A *pq = part + (int64_t)q * 4 * cols + cr;
+                const A xa = pq[0], xh = pq[1 * cols], xt = pq[2 * cols], xv = pq[3 * cols];
+                const int32_t xi = part_i[(int64_t)q * cols + cr];
+                const ChunkInfo ci = cinfo[q];
+                r.accA += xa;
+                if (xi != INT_MAX && lt2(xv, xi, r.bv, r.bi)) { r.bv = xv; r.bi = xi; }
+                if (ci.flags & kHead) add(ci.sa, xh, cdn[2 * q]);
+                if (ci.flags & kTail) add(ci.sb, xt, cdn[2 * q + 1]);
             }
         }
-        flush(rs, rm, rdn);
-        const int e = st->empty_slot;   // an empty slot changes by 0 + B(c)
-        if (e < k && lt2((A)0, e, bv, bi)) { bv = 0; bi = e; }
-        A td;
-        if constexpr (std::is_same<T, float>::value) td = st->td; else td = st->td_i;
-        A thr;
-        if constexpr (std::is_same<T, float>::value) thr = -st->margin; else thr = 0;
-        bestv = bv + (accA - td);
-        besti = bi;
-        neg = !is_med[c] && c >= st->fp_pos && bestv < thr;
-        if (neg) atomicMin(&first, (int)c);
+        sm[g][j] = r;
+        if (threadIdx.x == 0) first = INT_MAX;
+        __syncthreads();
+        A bestv = VT<T>::acc_inf();
+        int besti = INT_MAX;
+        bool neg = false;
+        if (g == 0 && live) {
+            A accA = 0, bv = VT<T>::acc_inf(), rm = 0, rdn = 0;
+            int bi = INT_MAX, rs = -1;
+            auto flush = [&](int s, A m, A dn) {
+                if (s < 0) return;
+                const A v = m - dn;
+                if (lt2(v, s, bv, bi)) { bv = v; bi = s; }
+            };
+            for (int h = 0; h < G; ++h) {
+                const RunSum<A> &x = sm[h][j];
+                accA += x.accA;
+                if (x.bi != INT_MAX && lt2(x.bv, x.bi, bv, bi)) { bv = x.bv; bi = x.bi; }
+                if (x.nr == 0) continue;
+                if (x.fs == rs) { rm += x.fm; rdn += x.fdn; }
+                else { flush(rs, rm, rdn); rs = x.fs; rm = x.fm; rdn = x.fdn; }
+                if (x.nr == 2) {   // the first run ended inside the group
+                    flush(rs, rm, rdn);
+                    rs = x.ls; rm = x.lm; rdn = x.ldn;
+                }
+            }
+            flush(rs, rm, rdn);
+            const int e = st->empty_slot;   // an empty slot changes by 0 + B(c)
+            if (e < k && lt2((A)0, e, bv, bi)) { bv = 0; bi = e; }
+            A td;
+            if constexpr (std::is_same<T, float>::value) td = st->td; else td = st->td_i;
+            A thr;
+            if constexpr (std::is_same<T, float>::value) thr = -st->margin; else thr = 0;
+            bestv = bv + (accA - td);
+            besti = bi;
+            neg = !is_med[c] && c >= st->fp_pos && bestv < thr;
+            if (neg) atomicMin(&first, (int)c);
+        }
+        __syncthreads();
+        if (neg && (int)c == first) { resv = bestv; resi = besti; }
+        __syncthreads();
+        found = first;
+        __syncthreads();
     }
-    __syncthreads();
-    if (neg && (int)c == first) {
-        wg_v[blockIdx.x] = bestv;
-        wg_i[blockIdx.x] = besti;
-        wg_c[blockIdx.x] = (int)c;
-    } else if (threadIdx.x == 0 && first == INT_MAX) {
-        wg_c[blockIdx.x] = INT_MAX;
+    if (threadIdx.x == 0) {
+        wg_c[blockIdx.x] = found;
+        if (found != INT_MAX) { wg_v[blockIdx.x] = resv; wg_i[blockIdx.x] = resi; }
     }
 }
 
-// Every block finds the window's first improving candidate from the merge
-// results (work-groups in candidate order) -- the same in every block -- and,
+// Every block finds the window's first improving candidate (the smallest
+// one any merge work-group reported) -- the same in every block -- and,
 // when there is one, updates its objects' caches by the O(1) rule.  Block 0
 // applies the swap or advances the scan, and places the next window.
 template <typename T>
 __global__ __launch_bounds__(256) void k_fp_select_update(
     const AccT<T> *__restrict__ wg_v, const int32_t *__restrict__ wg_i,
     const int32_t *__restrict__ wg_c, int32_t nwg, const T *__restrict__ D, int64_t ld,
-    int64_t n, int64_t fw, int32_t vec, int32_t *__restrict__ med, uint8_t *__restrict__ is_med,
+    int64_t n, int64_t tile, int32_t max_tiles, int32_t vec, int32_t *__restrict__ med,
+    uint8_t *__restrict__ is_med,
     int32_t *__restrict__ near, int32_t *__restrict__ sec, T *__restrict__ dn, T *__restrict__ ds,
     int32_t *__restrict__ rlist, DevState *__restrict__ st, pamx_swap_record *__restrict__ trace) {
     using A = AccT<T>;
     if (st->done) return;
-    __shared__ int wfirst;
-    if (threadIdx.x == 0) wfirst = INT_MAX;
+    __shared__ long long wfirst;   // (candidate << 32) | merge work-group
+    if (threadIdx.x == 0) wfirst = LLONG_MAX;
     __syncthreads();
-    for (int w = threadIdx.x; w < nwg; w += 256)
-        if (wg_c[w] != INT_MAX) atomicMin(&wfirst, w);
+    for (int w = threadIdx.x; w < nwg; w += 256) {
+        const int32_t c = wg_c[w];
+        if (c != INT_MAX) atomicMin(&wfirst, ((long long)c << 32) | w);
+    }
     __syncthreads();
-    const int wb = wfirst;
-    const bool apply = wb != INT_MAX;
+    const bool apply = wfirst != LLONG_MAX;
+    const int wb = apply ? (int)(wfirst & 0xffffffffLL) : 0;
     A v = 0;
     int i = 0, c = 0;
     if (apply) { v = wg_v[wb]; i = wg_i[wb]; c = wg_c[wb]; }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->iter += 1;
         const long long pos = st->fp_pos, end = st->fw_end;
+        st->fp_cols += end - st->fw_base;
         if (apply) {
             st->best_i = i;
             st->best_c = c;
@@ -1157,13 +1191,14 @@ __global__ __launch_bounds__(256) void k_fp_select_update(
         }
         st->swapped = apply ? 1 : 0;
         st->seg_skip = apply ? 0 : 1;
+        st->fw_tiles = apply ? 1 : min(2 * st->fw_tiles, max_tiles);
         if (st->fp_quiet >= n) {
             st->done = 1;
         } else if (st->fp_visited >= st->fp_limit) {
             st->done = 1;
             st->capped = 1;
         } else {
-            fp_window(st, n, fw, vec);
+            fp_window(st, n, tile, vec);
         }
     }
     if (!apply) return;
@@ -1347,7 +1382,7 @@ hipError_t enqueue_swap_init(const T *D, int64_t ld, const Layout &L, const int3
     hipLaunchKernelGGL(k_check_medoids, dim3((k + 255) / 256), dim3(256), 0, s, medoids, k, n,
                        p.near, p.is_med, p.st);
     if (opt.variant == PAMX_FASTERPAM)
-        hipLaunchKernelGGL(k_fp_init, dim3(1), dim3(1), 0, s, p.st, n, (int64_t)L.fw, L.vec,
+        hipLaunchKernelGGL(k_fp_init, dim3(1), dim3(1), 0, s, p.st, n, (int64_t)L.tile, L.vec,
                            (long long)opt.max_iter * (long long)n);
     return hipGetLastError();
 }
@@ -1385,7 +1420,7 @@ static void enqueue_segments(const Layout &L, const SwapPtrs<T> &p, hipStream_t 
 template <typename T>
 static void enqueue_pass(const T *D, int64_t ld, const Layout &L, const SwapPtrs<T> &p, bool p2,
                          hipStream_t s, bool win = false) {
-    const dim3 pgrid(win ? L.fw / L.tile : L.n_ctiles, L.Q);
+    const dim3 pgrid(win ? 1 : L.n_ctiles, L.Q);
     const int64_t cols = win ? L.fw : L.ncp;
 #define PAMX_PASS(VEC, P2, WIN)                                                               \
     hipLaunchKernelGGL((k_swap_pass<T, VEC, P2, WIN>), pgrid, dim3(kWG), 0, s, D, ld, L.n,   \
@@ -1433,7 +1468,7 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
 
     if (opt.variant == PAMX_FASTERPAM) {
         // one window of the scan (segments are rebuilt only after a swap)
-        const int nwg = L.fw / 16;   // merge work-groups (16 candidates each)
+        const int nwg = (L.fw / 16 < 64) ? L.fw / 16 : 64;   // merge work-groups
         enqueue_segments<T>(L, p, s);
         if (ev0) (void)hipEventRecord(ev0, s);
         enqueue_pass<T>(D, ld, L, p, false, s, true);
@@ -1444,7 +1479,8 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
                            (const DevState *)p.st, p.wg_v, p.wg_i, p.wg_c);
         hipLaunchKernelGGL(k_fp_select_update<T>, dim3(ob), dim3(256), 0, s, (const A *)p.wg_v,
                            (const int32_t *)p.wg_i, (const int32_t *)p.wg_c, nwg, D, ld, n,
-                           (int64_t)L.fw, L.vec, medoids, p.is_med, p.near, p.sec, p.dn, p.ds,
+                           (int64_t)L.tile, L.fw / L.tile, L.vec, medoids, p.is_med, p.near,
+                           p.sec, p.dn, p.ds,
                            p.rlist, p.st, trace);
         hipLaunchKernelGGL(k_cache_rescan<T>, dim3(256), dim3(256), 0, s, D, ld, k,
                            (const int32_t *)medoids, p.near, p.sec, p.dn, p.ds,
