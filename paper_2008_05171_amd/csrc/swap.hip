@@ -1075,15 +1075,32 @@ __global__ __launch_bounds__(256) void k_fp_merge(
                 if (lt2(v, r.ls, r.bv, r.bi)) { r.bv = v; r.bi = r.ls; }
                 r.ls = s; r.lm = m; r.ldn = dn;
             };
-            for (int q = q0; q < q1; ++q) {
-                const A *pq = part + (int64_t)q * 4 * cols + cr;
-                const A xa = pq[0], xh = pq[1 * cols], xt = pq[2 * cols], xv = pq[3 * cols];
-                const int32_t xi = part_i[(int64_t)q * cols + cr];
-                const ChunkInfo ci = cinfo[q];
-                r.accA += xa;
-                if (xi != INT_MAX && lt2(xv, xi, r.bv, r.bi)) { r.bv = xv; r.bi = xi; }
-                if (ci.flags & kHead) add(ci.sa, xh, cdn[2 * q]);
-                if (ci.flags & kTail) add(ci.sb, xt, cdn[2 * q + 1]);
+            constexpr int UQ = 8;   // chunks whose partials are loaded together
+            for (int qa = q0; qa < q1; qa += UQ) {
+                A xa[UQ], xh[UQ], xt[UQ], xv[UQ], dh[UQ], dt[UQ];
+                int32_t xi[UQ];
+                ChunkInfo ci[UQ];
+#pragma unroll
+                for (int u = 0; u < UQ; ++u) {
+                    const int q = min(qa + u, q1 - 1);   // clamped: every load in bounds
+                    const A *pq = part + (int64_t)q * 4 * cols + cr;
+                    xa[u] = pq[0];
+                    xh[u] = pq[1 * cols];   // read even when unused (never written then)
+                    xt[u] = pq[2 * cols];
+                    xv[u] = pq[3 * cols];
+                    xi[u] = part_i[(int64_t)q * cols + cr];
+                    ci[u] = cinfo[q];
+                    dh[u] = cdn[2 * q];
+                    dt[u] = cdn[2 * q + 1];
+                }
+#pragma unroll
+                for (int u = 0; u < UQ; ++u) {
+                    if (qa + u >= q1) break;
+                    r.accA += xa[u];
+                    if (xi[u] != INT_MAX && lt2(xv[u], xi[u], r.bv, r.bi)) { r.bv = xv[u]; r.bi = xi[u]; }
+                    if (ci[u].flags & kHead) add(ci[u].sa, xh[u], dh[u]);
+                    if (ci[u].flags & kTail) add(ci[u].sb, xt[u], dt[u]);
+                }
             }
         }
         sm[g][j] = r;
