@@ -229,6 +229,27 @@ int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int64_t n, int
              int32_t *labels, double *td, pamx_stats *stats, void *ws, size_t ws_bytes,
              void *stream);
 
+/* FastCLARANS (Sec. 3.5): one randomized local search from `medoids`
+ * (DEVICE int32[k], slot order; read, then overwritten with the result).
+ * draws: DEVICE int32[len], random object indices chosen by the caller,
+ * taken in order.  A draw that is a current medoid is skipped; any other is
+ * a candidate scored against all k slots at once (its best slot, smallest on
+ * ties) and swapped in when that lowers TD (PAMX_F32: below minus the FP64
+ * summation bound).  Draws that do not improve count as failures, a swap
+ * resets the count; the search ends after `maxneighbor` failures in a row
+ * (the paper uses 2.5% of n - k) -> PAMX_OK, or when the list runs out ->
+ * PAMX_WARN_MAXITER.  Restarts ("numlocal") are separate calls.  The device
+ * scores a window of draws per pass and applies the first improving one, so
+ * the swaps are those of the sequential search (exactly for PAMX_I32).
+ * labels, td, stats as for pamx_swap (stats: swaps, converged; windows =
+ * passes; scan_positions = draws evaluated).  Workspace:
+ * pamx_workspace_bytes(n, k, 0, PAMX_INPUT_D, dtype, opt, ...).  A draw
+ * outside [0, n) returns PAMX_ERR_ARG (checked on the device first). */
+int pamx_clarans(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                 const int32_t *draws, int64_t len, int64_t maxneighbor,
+                 const pamx_options *opt, int32_t *medoids, int32_t *labels, double *td,
+                 pamx_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- Faster initialisations (Sec. 3.4).  Both write k object indices in
  * slot order to `medoids` (DEVICE int32[k]) for pamx_swap, and take their
  * random draws as inputs.  D, dtype, n, ld as for pamx_build (symmetric).

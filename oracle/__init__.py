@@ -19,6 +19,8 @@ only builds it (gcc) and marshals numpy arrays.  Paper references
 * ``pam``           -- BUILD followed by SWAP, with labels.
 * ``init_dw``       -- distance-weighted seeding (Sec. 3.4, reading R8).
 * ``init_lab``      -- LAB, BUILD on per-step subsamples (Sec. 3.4, reading R9).
+* ``clarans``       -- one FastCLARANS local search over given draws (Sec. 3.5,
+                       reading R10).
 """
 from __future__ import annotations
 
@@ -76,6 +78,7 @@ def _load():
     lib.orc_build_list.argtypes = [P, P, i64, i32, i32, P, i32, i32, P, i64, P]
     lib.orc_init_dw.argtypes = [P, P, i64, i32, i32, i32, P, P]
     lib.orc_init_lab.argtypes = [P, P, i64, i32, i32, i32, P, i32, i32, P]
+    lib.orc_clarans.argtypes = [P, P, i64, i32, i32, P, i32, P, i64, i64, P, P, P, i32, P, P, P]
     _lib = lib
     return lib
 
@@ -293,3 +296,35 @@ def init_lab(k, samples, D=None, X=None, metric=L2, exclude_self=False) -> np.nd
     if rc:
         raise ValueError("orc_init_lab rc=%d" % rc)
     return med
+
+
+@dataclass
+class ClaransResult:
+    medoids: np.ndarray
+    td: float
+    evaluations: int
+    swaps: int
+    rc: int
+    trace: list = field(default_factory=list)
+
+
+def clarans(med, draws, maxneighbor, D=None, X=None, metric=L2, trace_cap=100000):
+    """One FastCLARANS local search (reading R10) from medoids `med` over the
+    random draws `draws` (object indices, in order)."""
+    s = _Src(D, X, metric)
+    med = np.array(med, dtype=np.int32, copy=True)
+    draws = np.ascontiguousarray(draws, dtype=np.int32)
+    ts = np.empty(trace_cap, np.int32)
+    tc = np.empty(trace_cap, np.int64)
+    tdl = np.empty(trace_cap, np.float64)
+    ev = ctypes.c_int64()
+    sw = ctypes.c_int32()
+    tdv = ctypes.c_double()
+    rc = _load().orc_clarans(*s.args(), _ptr(med), len(med), _ptr(draws), len(draws),
+                             int(maxneighbor), _ptr(ts), _ptr(tc), _ptr(tdl), int(trace_cap),
+                             ctypes.byref(ev), ctypes.byref(sw), ctypes.byref(tdv))
+    if rc < 0:
+        raise ValueError("orc_clarans rc=%d" % rc)
+    m = min(sw.value, trace_cap)
+    trace = [(int(ts[j]), int(tc[j]), float(tdl[j])) for j in range(m)]
+    return ClaransResult(med, tdv.value, ev.value, sw.value, rc, trace)

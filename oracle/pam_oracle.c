@@ -67,6 +67,14 @@
  *      is taken.  If every member is a medoid the smallest-index non-medoid
  *      is taken.  With the whole data set listed in index order every step
  *      equals BUILD's.
+ *  R10 FastCLARANS (Sec. 3.5): one local search from given medoids over a
+ *      list of random draws supplied by the caller.  A draw that is a medoid
+ *      is skipped; otherwise it is a candidate like in Alg. 4 (best slot,
+ *      smallest on ties, swapped in when its change is negative).  Draws
+ *      that do not improve count as failures; a swap resets the count.  The
+ *      search ends when maxneighbor failures follow each other (a local
+ *      optimum for the sampled neighbourhood) or when the list runs out
+ *      (reported as not converged).  Restarts are separate searches.
  */
 #include <math.h>
 #include <stdint.h>
@@ -745,4 +753,79 @@ int orc_init_lab(const double *D, const double *X, int64_t n, int32_t dim, int32
     }
     free(dn); free(is_med);
     return ORC_OK;
+}
+
+/* FastCLARANS local search (R10).  med (slot order) is read and
+ * overwritten; trace_* (optional) receive the swaps; n_eval = draws
+ * evaluated (non-medoid draws up to the end of the search). */
+int orc_clarans(const double *D, const double *X, int64_t n, int32_t dim, int32_t metric,
+                int32_t *med, int32_t k, const int32_t *draws, int64_t len, int64_t maxneighbor,
+                int32_t *trace_slot, int64_t *trace_c, double *trace_delta, int32_t trace_cap,
+                int64_t *n_eval, int32_t *n_swaps, double *td_out)
+{
+    src_t s;
+    if (make_src(&s, D, X, n, dim, metric) || !med || k < 1 || k > n || !draws || len < 0 ||
+        maxneighbor < 1)
+        return ORC_ERR_ARG;
+    for (int64_t j = 0; j < len; ++j)
+        if (draws[j] < 0 || draws[j] >= n) return ORC_ERR_ARG;
+    unsigned char *is_med = (unsigned char *)calloc((size_t)n, 1);
+    double *dn = (double *)malloc(sizeof(double) * (size_t)n);
+    double *ds = (double *)malloc(sizeof(double) * (size_t)n);
+    int32_t *near = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    double *chg = (double *)malloc(sizeof(double) * (size_t)k);
+    if (!is_med || !dn || !ds || !near || !chg) {
+        free(is_med); free(dn); free(ds); free(near); free(chg);
+        return ORC_ERR_MEM;
+    }
+    int rc = ORC_OK;
+    for (int32_t i = 0; i < k; ++i) {
+        if (med[i] < 0 || med[i] >= n || is_med[med[i]]) { rc = ORC_ERR_ARG; break; }
+        is_med[med[i]] = 1;
+    }
+    int64_t evals = 0, fails = 0;
+    int32_t swaps = 0;
+    if (rc == ORC_OK && k >= 2 && k < n) {
+        nearest_all(&s, med, k, near, dn, ds);
+        double td = 0.0;
+        for (int64_t o = 0; o < n; ++o) td += dn[o];
+        int64_t j = 0;
+        while (fails < maxneighbor) {
+            if (j == len) { rc = ORC_WARN_MAXITER; break; }
+            const int64_t c = draws[j++];
+            if (is_med[c]) continue;
+            ++evals;
+            #pragma omp parallel for schedule(static) if (k >= 8)
+            for (int32_t i = 0; i < k; ++i)
+                chg[i] = delta_swap(&s, med, k, is_med, near, dn, ds, i, c);
+            int32_t bi = 0;
+            for (int32_t i = 1; i < k; ++i)
+                if (chg[i] < chg[bi]) bi = i;
+            if (!(chg[bi] < 0.0)) { ++fails; continue; }
+            is_med[med[bi]] = 0;
+            med[bi] = (int32_t)c;
+            is_med[c] = 1;
+            td += chg[bi];
+            if (trace_slot && swaps < trace_cap) {
+                trace_slot[swaps] = bi; trace_c[swaps] = c; trace_delta[swaps] = chg[bi];
+            }
+            ++swaps;
+            fails = 0;
+            nearest_all(&s, med, k, near, dn, ds);
+            double fresh = 0.0;
+            for (int64_t o = 0; o < n; ++o) fresh += dn[o];
+            if (!td_matches(td, fresh)) { rc = ORC_ERR_TD; break; }
+            td = fresh;
+        }
+    }
+    if (n_eval) *n_eval = evals;
+    if (n_swaps) *n_swaps = swaps;
+    if (td_out && rc >= 0) {
+        nearest_all(&s, med, k, near, dn, ds);
+        double fresh = 0.0;
+        for (int64_t o = 0; o < n; ++o) fresh += dn[o];
+        *td_out = fresh;
+    }
+    free(is_med); free(dn); free(ds); free(near); free(chg);
+    return rc;
 }

@@ -17,7 +17,7 @@ from .pamx import (PAMX_ACC_F32, PAMX_ACC_F64, PAMX_CHUNK_TUNE, PAMX_DIST_BF16, 
                    PAMX_FASTERPAM, PAMX_FASTPAM1,
                    PAMX_FASTPAM2, PAMX_INPUT_D, PAMX_INPUT_X, PAMX_L1, PAMX_L2, PamxError)
 
-__all__ = ["fit", "build", "swap", "dist", "init_dw", "init_lab", "fit_batched", "FitResult", "BatchResult", "PamxError", "PAMX_FASTPAM1",
+__all__ = ["fit", "build", "swap", "dist", "init_dw", "init_lab", "clarans", "fit_batched", "FitResult", "BatchResult", "PamxError", "PAMX_FASTPAM1",
            "PAMX_FASTPAM2", "PAMX_FASTERPAM", "PAMX_L1", "PAMX_L2", "PAMX_ACC_F64", "PAMX_ACC_F32",
            "PAMX_INPUT_D", "PAMX_INPUT_X", "PAMX_CHUNK_TUNE"]
 
@@ -221,6 +221,50 @@ def init_lab(D, k, *, seed=0, m=None, samples=None, exclude_self=False, stream=N
     med = torch.empty(k, dtype=torch.int32, device=D.device)
     _abi.pamx_init_lab(D, k, sd, med, ws, exclude_self=exclude_self, stream=stream)
     return med
+
+
+def clarans_maxneighbor(n, k):
+    """Failures that end a FastCLARANS search: 2.5% of the non-medoids
+    (the paper's setting, Sec. 3.5), at least 1."""
+    return max(1, int(round(0.025 * (n - k))))
+
+
+def clarans(D, k, *, numlocal=2, seed=0, maxneighbor=None, draws_per_search=None, trace=False,
+            stream=None) -> FitResult:
+    """FastCLARANS (Sec. 3.5) on a stored matrix: `numlocal` local searches,
+    each from k uniform random medoids over its own list of random draws
+    (seeded), keeping the smallest TD (the first on ties).  stats gain
+    "searches": [(td, swaps, draws evaluated, rc)]."""
+    import numpy as np
+    import torch
+    from . import datagen
+    n = D.shape[0]
+    if maxneighbor is None:
+        maxneighbor = clarans_maxneighbor(n, k)
+    length = draws_per_search or (64 * maxneighbor + 4 * n)
+    opt = _options()
+    cap = 4 * n + 16 if trace else 0
+    nbytes = _abi.pamx_workspace_bytes(n, k, 0, PAMX_INPUT_D, _abi._dtype_code(D), opt)
+    ws = _workspace(nbytes, D.device)
+    best, runs = None, []
+    for r in range(numlocal):
+        start = datagen.random_subset(n, k, seed * 1000 + 2 * r)
+        dr = datagen.int_points(length, 1, 0, n, seed=seed * 1000 + 2 * r + 1).reshape(-1)
+        tbuf = torch.empty(cap * 16, dtype=torch.uint8, device=D.device) if trace else None
+        o = _options(trace_buf=tbuf, trace_cap=cap)
+        med = torch.from_numpy(start).to(D.device)
+        lab = torch.empty(n, dtype=torch.int32, device=D.device)
+        rc, td, st = _abi.pamx_clarans(D, k, torch.from_numpy(dr).to(D.device), maxneighbor, med,
+                                       ws, labels=lab, opt=o, stream=stream)
+        res = FitResult(med, lab, td, rc, _stats_dict(st), _trace_list(tbuf, min(st.swaps, cap)))
+        res.stats["start"] = start
+        res.stats["draws"] = dr
+        runs.append((td, st.swaps, st.scan_positions, rc))
+        if best is None or td < best.td:
+            best = res
+    best.stats["searches"] = runs
+    best.stats["maxneighbor"] = maxneighbor
+    return best
 
 
 def dist(X, *, metric=None, ld=None, stream=None):

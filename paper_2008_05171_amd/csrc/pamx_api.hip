@@ -145,6 +145,8 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->list_v = take(8);
     L->list_i = take(8);
     L->rlist = take((size_t)n * 4);
+    L->cl_v = take(1024 * 8);
+    L->cl_i = take(1024 * 4);
     L->state = take(sizeof(DevState));
     L->head = off;
     set_chunk(L, L->L);
@@ -722,6 +724,63 @@ int swap_impl(const T *D, int64_t ld, const Layout &L_in, int32_t k, const pamx_
     return st.capped ? PAMX_WARN_MAXITER : PAMX_OK;
 }
 
+// One FastCLARANS local search (Sec. 3.5) over the caller's draws.
+template <typename T>
+int clarans_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const int32_t *draws,
+                 int64_t len, int64_t maxneighbor, const pamx_options &opt, int32_t *medoids,
+                 int32_t *labels, double *td, pamx_stats *stats, void *ws, hipStream_t s,
+                 Timer &tm) {
+    const int64_t n = L.n;
+    HIP_TRY(enqueue_swap_init<T>(D, ld, L, medoids, opt, ws, s));
+    DevState st;
+    int rc = read_state(L, ws, s, &st);
+    if (rc) return rc;
+    if (st.bad_medoids)
+        return fail(PAMX_ERR_INVALID_MEDOIDS, "medoids must be distinct and in [0, n)");
+    const bool searches = k >= 2 && k < n;
+    if (searches) {
+        // every draw in [0, n) before the search starts
+        int32_t *err = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + L.cl_i);
+        int32_t e0 = 0;
+        HIP_TRY(launch_init_zero(err, s));
+        HIP_TRY(launch_check_sidx(draws, len, n, err, s));
+        HIP_TRY(hipMemcpyAsync(&e0, err, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (e0) return fail(PAMX_ERR_ARG, "draws holds an index outside [0, n)");
+        HIP_TRY(enqueue_swap_caches<T>(D, ld, L, medoids, ws, s));
+        HIP_TRY(enqueue_cl_init<T>(L, len, maxneighbor, ws, s));
+    }
+    tm.rec(2, s);
+    if (searches) {
+        int batch = 4;
+        for (;;) {
+            for (int j = 0; j < batch; ++j)
+                HIP_TRY(enqueue_cl_step<T>(D, ld, L, draws, medoids, opt, ws, s));
+            rc = read_state(L, ws, s, &st);
+            if (rc) return rc;
+            if (st.done) break;
+            if (batch < 32) batch *= 2;
+        }
+    }
+    tm.rec(3, s);
+    HIP_TRY(enqueue_finalize<T>(D, ld, L, medoids, labels, ws, s));
+    DevState fin;
+    rc = read_state(L, ws, s, &fin);
+    if (rc) return rc;
+    if (td) *td = fin.td;
+    if (stats) {
+        stats->iterations = searches ? st.iter : 0;
+        stats->windows = searches ? st.iter : 0;
+        stats->swaps = searches ? st.swaps : 0;
+        stats->converged = searches ? (st.done && !st.capped) : 1;
+        stats->td = fin.td;
+        stats->scan_positions = searches ? st.fp_cols : 0;
+        stats->pass_pairs = searches ? st.fp_cols * n : 0;
+        stats->window = 1024;
+    }
+    return (searches && st.capped) ? PAMX_WARN_MAXITER : PAMX_OK;
+}
+
 }  // namespace
 
 // The mixed-precision form: BUILD and FastPAM1 on recomputed BF16-Gram
@@ -869,6 +928,46 @@ extern "C" int pamx_swap(const void *D, int32_t dtype, int64_t n, int64_t ld, in
     else
         rc = swap_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, opt, medoids, labels, td,
                                 stats, ws, s, tm);
+    if (rc < 0) return rc;
+    tm.rec(4, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(PAMX_ERR_HIP, "stream synchronize failed");
+    if (stats) {
+        stats->ms_swap = tm.ms(2, 3);
+        stats->ms_total = tm.ms(0, 4);
+    }
+    return rc;
+}
+
+extern "C" int pamx_clarans(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                            const int32_t *draws, int64_t len, int64_t maxneighbor,
+                            const pamx_options *opt_in, int32_t *medoids, int32_t *labels,
+                            double *td, pamx_stats *stats, void *ws, size_t ws_bytes,
+                            void *stream) {
+    pamx_options opt;
+    pamx_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    int rc = swap_args(D, dtype, n, ld, k, &opt, medoids);
+    if (rc) return rc;
+    if (len < 0) return fail(PAMX_ERR_ARG, "len must be >= 0");
+    if (len > 0 && !draws) return fail(PAMX_ERR_ARG, "draws is NULL");
+    if (maxneighbor < 1) return fail(PAMX_ERR_ARG, "maxneighbor must be >= 1");
+    if (opt.variant != PAMX_FASTPAM1)
+        return fail(PAMX_ERR_ARG, "pamx_clarans takes no SWAP variant (leave PAMX_FASTPAM1)");
+    Layout L;
+    make_layout(n, k, 0, PAMX_INPUT_D, dtype, ld, &opt, &L, D);
+    rc = check_ws(ws, ws_bytes, L, &opt);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    Timer tm;
+    tm.rec(0, s);
+    tm.rec(1, s);
+    if (dtype == PAMX_F32)
+        rc = clarans_impl<float>(static_cast<const float *>(D), ld, L, k, draws, len, maxneighbor,
+                                 opt, medoids, labels, td, stats, ws, s, tm);
+    else
+        rc = clarans_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, draws, len,
+                                   maxneighbor, opt, medoids, labels, td, stats, ws, s, tm);
     if (rc < 0) return rc;
     tm.rec(4, s);
     if (hipStreamSynchronize(s) != hipSuccess) return fail(PAMX_ERR_HIP, "stream synchronize failed");

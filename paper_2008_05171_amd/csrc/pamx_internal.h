@@ -179,6 +179,7 @@ struct Layout {
     size_t wg_v, wg_i, wg_c;
     size_t P, slot_v, slot_c;
     size_t list, list_v, list_i, rlist;
+    size_t cl_v, cl_i;   // FastCLARANS: changes and slots of a window of draws
     size_t state;
     size_t head;         // end of the regions that do not depend on the chunk length
     size_t total;
@@ -278,6 +279,13 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
 template <typename T>
 hipError_t enqueue_tune_passes(const T *D, int64_t ld, const Layout &L, const pamx_options &opt,
                                void *ws, hipStream_t s, hipEvent_t *ev, int reps);
+// FastCLARANS: state for a search over `len` draws, and one window step
+template <typename T>
+hipError_t enqueue_cl_init(const Layout &L, int64_t len, int64_t maxneighbor, void *ws,
+                           hipStream_t s);
+template <typename T>
+hipError_t enqueue_cl_step(const T *D, int64_t ld, const Layout &L, const int32_t *draws,
+                           int32_t *medoids, const pamx_options &opt, void *ws, hipStream_t s);
 template <typename T>
 hipError_t enqueue_finalize(const T *D, int64_t ld, const Layout &L, const int32_t *medoids,
                             int32_t *labels, void *ws, hipStream_t s);

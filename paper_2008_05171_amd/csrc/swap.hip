@@ -1231,6 +1231,223 @@ __global__ __launch_bounds__(256) void k_fp_select_update(
     }
 }
 
+// ---- FastCLARANS (Sec. 3.5): one local search over a list of random draws.
+// A draw that is a medoid is skipped; any other is a candidate as in Alg. 4
+// (best slot, smallest on ties, swapped in when the change is below the
+// acceptance threshold).  Draws that do not improve count as failures, a swap
+// resets the count, and maxneighbor failures in a row end the search; so does
+// the end of the list (not converged).  The device scores a window of draws
+// against the current medoids at once and takes the first improving one
+// unless the failures before it already end the search -- exactly the
+// sequential order.  State: fp_pos = list position, fp_quiet = failures,
+// fp_limit = list length, fp_cols = draws evaluated; the window [fw_base,
+// fw_end) is in list positions, its width kClUnit << (fw_tiles - 1) draws.
+constexpr int kClUnit = 64;      // draws in the window after a swap
+constexpr int kClMax = 1024;     // widest window (draws)
+constexpr int kClGrid = 256;     // work-groups of the scoring kernel
+
+__device__ __forceinline__ void cl_window(DevState *st) {
+    const long long base = st->fp_pos;
+    long long end = base + ((long long)kClUnit << (st->fw_tiles - 1));
+    if (end > st->fp_limit) end = st->fp_limit;
+    st->fw_base = base;
+    st->fw_end = end;
+}
+
+__global__ void k_cl_init(DevState *st, long long len, long long maxneighbor) {
+    st->fp = 1;
+    st->fp_pos = 0;
+    st->fp_quiet = 0;
+    st->fp_limit = len;
+    st->fp_cols = 0;
+    st->fp_visited = maxneighbor;   // the failure limit
+    st->seg_skip = 0;
+    st->fw_tiles = 1;
+    if (len <= 0) {
+        st->done = 1;
+        st->capped = 1;
+    } else {
+        cl_window(st);
+    }
+}
+
+// Change of every draw of the window: one work-group per draw; its waves
+// take the segments in turn (lanes over the segment's objects, reading the
+// candidate's row of D at the sorted objects: D symmetric), each segment
+// summed by a wave butterfly, so every sum has a fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_eval(
+    const T *__restrict__ D, int64_t ld, int32_t k, const int32_t *__restrict__ draws,
+    const int32_t *__restrict__ srow, const T *__restrict__ sdn, const T *__restrict__ sds,
+    const int32_t *__restrict__ seg_off, const uint8_t *__restrict__ is_med,
+    const DevState *__restrict__ st, AccT<T> *__restrict__ out_v, int32_t *__restrict__ out_i) {
+    using A = AccT<T>;
+    constexpr int U = 4;
+    if (st->done) return;
+    __shared__ A wv[4], wa[4];
+    __shared__ int wi[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const long long base = st->fw_base, end = st->fw_end;
+    for (long long j = base + blockIdx.x; j < end; j += gridDim.x) {
+        const int64_t c = draws[j];
+        const int64_t r = j - base;
+        if (is_med[c]) {
+            if (threadIdx.x == 0) { out_v[r] = VT<T>::acc_inf(); out_i[r] = -1; }
+            continue;
+        }
+        const T *row = D + c * ld;
+        A accA = 0, bv = VT<T>::acc_inf();
+        int bi = INT_MAX;
+        for (int sg = w; sg < k; sg += 4) {
+            const int32_t so = seg_off[sg], se = seg_off[sg + 1];
+            if (so == se) continue;
+            A M = 0, DN = 0;
+            int32_t p = so + lane;
+            for (; p + (U - 1) * 64 < se; p += U * 64) {
+                T d[U], lo[U], hi[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    d[u] = row[srow[p + u * 64]];
+                    lo[u] = sdn[p + u * 64];
+                    hi[u] = sds[p + u * 64];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    accA += (A)vmin(d[u], lo[u]);
+                    M += (A)vmed3(d[u], lo[u], hi[u]);
+                    DN += (A)lo[u];
+                }
+            }
+            for (; p < se; p += 64) {
+                const T d = row[srow[p]], lo = sdn[p], hi = sds[p];
+                accA += (A)vmin(d, lo);
+                M += (A)vmed3(d, lo, hi);
+                DN += (A)lo;
+            }
+            const A v = wave_sum<A>(M) - wave_sum<A>(DN);
+            if (lt2(v, sg, bv, bi)) { bv = v; bi = sg; }
+        }
+        accA = wave_sum<A>(accA);
+        if (lane == 0) { wv[w] = bv; wi[w] = bi; wa[w] = accA; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            A v = wv[0];
+            int i = wi[0];
+            for (int u = 1; u < 4; ++u)
+                if (lt2(wv[u], wi[u], v, i)) { v = wv[u]; i = wi[u]; }
+            const int e = st->empty_slot;   // an empty slot changes by 0 + B(c)
+            if (e < k && lt2((A)0, e, v, i)) { v = 0; i = e; }
+            A td;
+            if constexpr (std::is_same<T, float>::value) td = st->td; else td = st->td_i;
+            const A atot = ((wa[0] + wa[1]) + wa[2]) + wa[3];
+            out_v[r] = v + (atot - td);
+            out_i[r] = i;
+        }
+        __syncthreads();
+    }
+}
+
+// Every block finds, in list order, the first improving draw that comes
+// before the failure limit (the same in every block), and updates its
+// objects' caches when that draw is swapped in.  Block 0 applies the swap or
+// ends / advances the search and places the next window.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_select_update(
+    const AccT<T> *__restrict__ out_v, const int32_t *__restrict__ out_i,
+    const int32_t *__restrict__ draws, const T *__restrict__ D, int64_t ld, int64_t n,
+    int32_t *__restrict__ med, uint8_t *__restrict__ is_med, int32_t *__restrict__ near,
+    int32_t *__restrict__ sec, T *__restrict__ dn, T *__restrict__ ds, int32_t *__restrict__ rlist,
+    DevState *__restrict__ st, pamx_swap_record *__restrict__ trace) {
+    using A = AccT<T>;
+    if (st->done) return;
+    __shared__ int32_t ecnt[256];
+    __shared__ int first;
+    const int t = threadIdx.x;
+    const long long base = st->fw_base, end = st->fw_end;
+    const int W = (int)(end - base);
+    const long long fails = st->fp_quiet, maxn = st->fp_visited;
+    A thr;
+    if constexpr (std::is_same<T, float>::value) thr = -st->margin; else thr = 0;
+    // evaluated draws per thread (4 consecutive entries each), exclusive scan
+    int cnt = 0;
+    for (int u = 0; u < 4; ++u) {
+        const int r = 4 * t + u;
+        if (r < W && out_i[r] >= 0) ++cnt;
+    }
+    ecnt[t] = cnt;
+    if (t == 0) first = INT_MAX;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int u = 0; u < 256; ++u) {
+        if (u < t) before += ecnt[u];
+        total += ecnt[u];
+    }
+    for (int u = 0; u < 4; ++u) {
+        const int r = 4 * t + u;
+        if (r >= W || out_i[r] < 0) continue;
+        if (fails + before < maxn && out_v[r] < thr) { atomicMin(&first, r); break; }
+        ++before;
+    }
+    __syncthreads();
+    const bool apply = first != INT_MAX;
+    A v = 0;
+    int i = 0, c = 0;
+    if (apply) { v = out_v[first]; i = out_i[first]; c = draws[base + first]; }
+    if (blockIdx.x == 0 && t == 0) {
+        st->iter += 1;
+        if (apply) {
+            int ev = 0;   // evaluated draws up to and including the swap
+            for (int r = 0; r <= first; ++r) ev += (out_i[r] >= 0);
+            st->fp_cols += ev;
+            st->best_i = i;
+            st->best_c = c;
+            const int old = med[i];
+            is_med[old] = 0;
+            is_med[c] = 1;
+            med[i] = c;
+            st->old_med = old;
+            st->new_slot = i;
+            st->new_med = c;
+            if constexpr (std::is_same<T, float>::value) { st->best_v = v; st->td += v; }
+            else { st->best_vi = v; st->best_v = (double)v; st->td_i += v; st->td = (double)st->td_i; }
+            if (trace && st->swaps < st->trace_cap) trace[st->swaps] = pamx_swap_record{i, c, (double)v};
+            st->swaps += 1;
+            st->fp_quiet = 0;
+            st->fp_pos = base + first + 1;
+            st->fw_tiles = 1;
+        } else if (fails + total >= maxn) {
+            st->fp_cols += maxn - fails;   // the search ends at the limit
+            st->fp_quiet = maxn;
+        } else {
+            st->fp_cols += total;
+            st->fp_quiet = fails + total;
+            st->fp_pos = end;
+            if ((kClUnit << st->fw_tiles) <= kClMax) st->fw_tiles += 1;
+        }
+        st->swapped = apply ? 1 : 0;
+        st->seg_skip = apply ? 0 : 1;
+        if (st->fp_quiet >= maxn) {
+            st->done = 1;
+        } else if (st->fp_pos >= st->fp_limit) {
+            st->done = 1;
+            st->capped = 1;
+        } else {
+            cl_window(st);
+        }
+    }
+    if (!apply) return;
+    const int64_t o = (int64_t)blockIdx.x * 256 + t;
+    if (o >= n) return;
+    const T dnew = D[(int64_t)c * ld + o];
+    int32_t nr = near[o], sc = sec[o];
+    T a = dn[o], b = ds[o];
+    if (cache_update_o1<T>(i, dnew, nr, sc, a, b)) {
+        rlist[atomicAdd(&st->n_list, 1)] = (int32_t)o;
+    } else {
+        near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b;
+    }
+}
+
 // ---- FastPAM2: best candidate of every slot, (value, candidate) order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_slot_best(const AccT<T> *__restrict__ P,
@@ -1535,6 +1752,40 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
 }
 
 template <typename T>
+hipError_t enqueue_cl_init(const Layout &L, int64_t len, int64_t maxneighbor, void *ws,
+                           hipStream_t s) {
+    auto p = ptrs<T>(L, ws);
+    hipLaunchKernelGGL(k_cl_init, dim3(1), dim3(1), 0, s, p.st, (long long)len,
+                       (long long)maxneighbor);
+    return hipGetLastError();
+}
+
+// one window of a FastCLARANS search (segments are rebuilt only after a swap)
+template <typename T>
+hipError_t enqueue_cl_step(const T *D, int64_t ld, const Layout &L, const int32_t *draws,
+                           int32_t *medoids, const pamx_options &opt, void *ws, hipStream_t s) {
+    using A = AccT<T>;
+    auto p = ptrs<T>(L, ws);
+    char *w = static_cast<char *>(ws);
+    A *clv = reinterpret_cast<A *>(w + L.cl_v);
+    int32_t *cli = reinterpret_cast<int32_t *>(w + L.cl_i);
+    pamx_swap_record *trace = static_cast<pamx_swap_record *>(opt.trace);
+    const unsigned ob = (unsigned)((L.n + 255) / 256);
+    enqueue_segments<T>(L, p, s);
+    hipLaunchKernelGGL(k_cl_eval<T>, dim3(kClGrid), dim3(256), 0, s, D, ld, L.k, draws,
+                       (const int32_t *)p.srow, (const T *)p.sdn, (const T *)p.sds,
+                       (const int32_t *)p.seg_off, (const uint8_t *)p.is_med,
+                       (const DevState *)p.st, clv, cli);
+    hipLaunchKernelGGL(k_cl_select_update<T>, dim3(ob), dim3(256), 0, s, (const A *)clv,
+                       (const int32_t *)cli, draws, D, ld, L.n, medoids, p.is_med, p.near, p.sec,
+                       p.dn, p.ds, p.rlist, p.st, trace);
+    hipLaunchKernelGGL(k_cache_rescan<T>, dim3(256), dim3(256), 0, s, D, ld, L.k,
+                       (const int32_t *)medoids, p.near, p.sec, p.dn, p.ds,
+                       (const int32_t *)p.rlist, (const DevState *)p.st);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t enqueue_finalize(const T *D, int64_t ld, const Layout &L, const int32_t *medoids,
                             int32_t *labels, void *ws, hipStream_t s) {
     auto p = ptrs<T>(L, ws);
@@ -1584,7 +1835,11 @@ hipError_t launch_segments_f32(const int32_t *near, const float *dn, const float
     template hipError_t enqueue_finalize<T>(const T *, int64_t, const Layout &,                \
                                             const int32_t *, int32_t *, void *, hipStream_t);  \
     template hipError_t enqueue_swap_caches<T>(const T *, int64_t, const Layout &,             \
-                                               const int32_t *, void *, hipStream_t);
+                                               const int32_t *, void *, hipStream_t);          \
+    template hipError_t enqueue_cl_init<T>(const Layout &, int64_t, int64_t, void *,           \
+                                           hipStream_t);                                       \
+    template hipError_t enqueue_cl_step<T>(const T *, int64_t, const Layout &, const int32_t *, \
+                                           int32_t *, const pamx_options &, void *, hipStream_t);
 PAMX_INST(float)
 PAMX_INST(int32_t)
 #undef PAMX_INST

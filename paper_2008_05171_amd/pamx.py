@@ -62,7 +62,8 @@ class pamx_batch_stats(ctypes.Structure):
 
 EXPORTS = ("pamx_default_options", "pamx_workspace_bytes", "pamx_dist", "pamx_build",
            "pamx_swap", "pamx_fit", "pamx_batched_workspace_bytes", "pamx_fit_batched",
-           "pamx_init_workspace_bytes", "pamx_init_dw", "pamx_init_lab", "pamx_last_error")
+           "pamx_init_workspace_bytes", "pamx_init_dw", "pamx_init_lab", "pamx_clarans",
+           "pamx_last_error")
 
 
 class PamxError(RuntimeError):
@@ -100,11 +101,13 @@ def load(path: str = LIB_PATH):
     lib.pamx_init_workspace_bytes.argtypes = [i64, i32, ctypes.POINTER(sz)]
     lib.pamx_init_dw.argtypes = [P, i32, i64, i64, i32, P, P, P, sz, P]
     lib.pamx_init_lab.argtypes = [P, i32, i64, i64, i32, P, i32, i32, P, P, sz, P]
+    lib.pamx_clarans.argtypes = [P, i32, i64, i64, i32, P, i64, i64, opt_p, P, P, dbl_p, st_p, P,
+                                 sz, P]
     lib.pamx_last_error.argtypes = []
     lib.pamx_last_error.restype = ctypes.c_char_p
     for name in ("pamx_workspace_bytes", "pamx_dist", "pamx_build", "pamx_swap", "pamx_fit",
                  "pamx_batched_workspace_bytes", "pamx_fit_batched", "pamx_init_workspace_bytes",
-                 "pamx_init_dw", "pamx_init_lab"):
+                 "pamx_init_dw", "pamx_init_lab", "pamx_clarans"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -253,3 +256,18 @@ def pamx_init_lab(D, k, samples, medoids, ws, exclude_self=False, n=None, ld=Non
     return _check(load().pamx_init_lab(_ptr(D), _dtype_code(D), int(n), int(ld), int(k),
                                        _ptr(samples), m, int(bool(exclude_self)), _ptr(medoids),
                                        _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def pamx_clarans(D, k, draws, maxneighbor, medoids, ws, labels=None, opt=None, n=None, ld=None,
+                 stream=None):
+    """draws: device int32 [len]; medoids: device int32 [k], read and overwritten."""
+    n = D.shape[0] if n is None else n
+    ld = D.stride(0) if ld is None else ld
+    td = ctypes.c_double()
+    st = pamx_stats()
+    rc = _check(load().pamx_clarans(_ptr(D), _dtype_code(D), int(n), int(ld), int(k), _ptr(draws),
+                                    int(draws.numel()), int(maxneighbor),
+                                    ctypes.byref(opt) if opt is not None else None, _ptr(medoids),
+                                    _ptr(labels), ctypes.byref(td), ctypes.byref(st), _ptr(ws),
+                                    ws.numel() * ws.element_size(), _stream(stream)))
+    return rc, td.value, st

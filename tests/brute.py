@@ -178,3 +178,33 @@ def lab_greedy(D, k, samples, exclude_self=False):
             bc = min(o for o in range(n) if o not in med)
         med.append(bc)
     return med
+
+
+def clarans_search(D, med, draws, maxneighbor):
+    """One FastCLARANS local search by full TD recomputation: draws that are
+    medoids are skipped; a drawn non-medoid takes its best slot (smallest on
+    ties) and is swapped in when TD drops; maxneighbor consecutive failures
+    end the search.  Returns (medoids, trace, evaluations, list exhausted)."""
+    med = list(med)
+    trace = []
+    fails = evals = 0
+    for c in draws:
+        if fails >= maxneighbor:
+            return med, trace, evals, False
+        if c in med:
+            continue
+        evals += 1
+        base = td_of(D, med)
+        ch = []
+        for i in range(len(med)):
+            m2 = list(med)
+            m2[i] = c
+            ch.append(td_of(D, m2) - base)
+        i = min(range(len(med)), key=lambda j: (ch[j], j))
+        if ch[i] < 0:
+            med[i] = c
+            trace.append((i, c, ch[i]))
+            fails = 0
+        else:
+            fails += 1
+    return med, trace, evals, fails < maxneighbor

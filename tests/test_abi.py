@@ -123,6 +123,7 @@ def test_fasterpam_window_option(lib):
     needs more partials; BF16 distances run FastPAM1 only."""
     o = abi.pamx_default_options()
     o.variant = abi.PAMX_FASTERPAM
+    o.window = 1024
     a = abi.pamx_workspace_bytes(20000, 100, 0, abi.PAMX_INPUT_D, abi.PAMX_F32, o)
     o.window = 8192
     b = abi.pamx_workspace_bytes(20000, 100, 0, abi.PAMX_INPUT_D, abi.PAMX_F32, o)
@@ -160,6 +161,27 @@ def test_init_argument_errors(lib):
     assert lab(fake, abi.PAMX_I32, 1000, 1000, 5, None, 42, 0, fake, ws, 1 << 30, None) == abi.PAMX_ERR_ARG
     assert lab(fake, abi.PAMX_I32, 1000, 1000, 5, fake, 42, 2, fake, ws, 1 << 30, None) == abi.PAMX_ERR_ARG
     assert lab(fake, abi.PAMX_I32, 1000, 1000, 5, fake, 42, 0, fake, ws, 100, None) == abi.PAMX_ERR_WORKSPACE
+
+
+def test_clarans_argument_errors(lib):
+    fake = ctypes.c_void_p(0x100000)
+    ws = ctypes.c_void_p(0x200000)
+    cl = lib.pamx_clarans
+
+    def call(D=fake, dtype=abi.PAMX_F32, n=1000, ld=1000, k=5, draws=fake, ln=100, mx=10, opt=None,
+             med=fake, wsb=1 << 30):
+        return cl(D, dtype, n, ld, k, draws, ln, mx, ctypes.byref(opt) if opt else None, med, None,
+                  None, None, ws, wsb, None)
+    assert call(D=None) == abi.PAMX_ERR_ARG
+    assert call(k=1001) == abi.PAMX_ERR_ARG
+    assert call(draws=None) == abi.PAMX_ERR_ARG
+    assert call(ln=-1) == abi.PAMX_ERR_ARG
+    assert call(mx=0) == abi.PAMX_ERR_ARG
+    assert call(med=None) == abi.PAMX_ERR_ARG
+    o = abi.pamx_default_options()
+    o.variant = abi.PAMX_FASTERPAM
+    assert call(opt=o) == abi.PAMX_ERR_ARG
+    assert call(wsb=64) == abi.PAMX_ERR_WORKSPACE
 
 
 def test_points_metric_rules(lib):

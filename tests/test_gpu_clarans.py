@@ -1,0 +1,167 @@
+"""GPU parity of FastCLARANS (Sec. 3.5): the window search against the oracle.
+
+Integer dissimilarities: bit-exact trajectory (slot, candidate, change),
+evaluation count, medoids, labels and TD for the same starting medoids and
+random draws.  Float dissimilarities: the GPU's swaps are replayed on the
+oracle (changes within the FP64 summation bound; every evaluated draw
+between swaps and in the final run of failures non-improving up to that
+bound).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_05171_amd import datagen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def px():
+    import paper_2008_05171_amd as m
+    return m
+
+
+def abi():
+    from paper_2008_05171_amd import pamx
+    return pamx
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _int_case(n, seed, hi=1000, dim=2):
+    X = datagen.int_points(n, dim, 0, hi, seed=seed)
+    return X, oracle.dist_matrix(X, oracle.L1)
+
+
+def _run(D, start, draws, maxn, trace=True):
+    """One search through the C ABI: (rc, medoids, labels, td, stats, trace)."""
+    n = D.shape[0]
+    k = len(start)
+    cap = 4 * n + 16
+    tbuf = torch.empty(cap * 16, dtype=torch.uint8, device=DEV) if trace else None
+    o = px()._options(trace_buf=tbuf, trace_cap=cap if trace else 0)
+    nbytes = abi().pamx_workspace_bytes(n, k, 0, abi().PAMX_INPUT_D, abi()._dtype_code(D), o)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=DEV)
+    med = _t(np.asarray(start, np.int32))
+    lab = torch.empty(n, dtype=torch.int32, device=DEV)
+    rc, td, st = abi().pamx_clarans(D, k, _t(np.asarray(draws, np.int32)), maxn, med, ws,
+                                    labels=lab, opt=o)
+    tr = px()._trace_list(tbuf, min(st.swaps, cap)) if trace else []
+    return rc, med.cpu().numpy(), lab.cpu().numpy(), td, st, tr
+
+
+@pytest.mark.parametrize("n,k,hi,maxn,seed", [
+    (1000, 5, 1000, 25, 1), (1000, 10, 1000, 3, 2), (1000, 30, 10, 25, 3), (600, 12, 30, 60, 4),
+    (5000, 20, 500, 124, 5), (257, 40, 6, 8, 6)])
+def test_int_bitexact(n, k, hi, maxn, seed):
+    _say("clarans_int", n, k, hi, maxn, seed)
+    X, D = _int_case(n, seed, hi=hi)
+    start = datagen.random_subset(n, k, seed)
+    draws = datagen.int_points(40 * maxn + 3 * n, 1, 0, n, seed=seed + 100).reshape(-1)
+    ref = oracle.clarans(start, draws, maxn, D=D)
+    rc, med, lab, td, st, tr = _run(_t(D.astype(np.int32)), start, draws, maxn)
+    assert rc == ref.rc == 0
+    assert tr == ref.trace
+    assert list(med) == list(ref.medoids) and td == ref.td
+    assert st.swaps == ref.swaps and st.scan_positions == ref.evaluations
+    assert st.converged == 1
+    assert np.array_equal(lab, oracle.td(ref.medoids, D=D)[1])
+
+
+def test_exhausted_list_and_prefix():
+    _say("clarans_exhausted")
+    X, D = _int_case(1500, 11, hi=300)
+    start = datagen.random_subset(1500, 15, 11)
+    draws = datagen.int_points(20000, 1, 0, 1500, seed=12).reshape(-1)
+    Di = _t(D.astype(np.int32))
+    full = oracle.clarans(start, draws, 37, D=D)
+    assert full.rc == 0 and full.swaps > 5
+    short = draws[:100]
+    ref = oracle.clarans(start, short, 37, D=D)
+    rc, med, _, td, st, tr = _run(Di, start, short, 37)
+    assert rc == ref.rc == 1 and st.converged == 0
+    assert tr == ref.trace == full.trace[:len(tr)]
+    assert list(med) == list(ref.medoids) and td == ref.td
+
+
+def test_cyclic_draws_give_fasterpam():
+    """Draws 0..n-1 repeated with maxneighbor = n - k: FasterPAM's swaps."""
+    _say("clarans_cyclic")
+    X, D = _int_case(900, 21, hi=200)
+    start = datagen.random_subset(900, 9, 21)
+    Di = _t(D.astype(np.int32))
+    rc, med, _, td, st, tr = _run(Di, start, np.tile(np.arange(900), 12), 900 - 9)
+    f = px().swap(Di, _t(start), variant="fasterpam", trace=True)
+    assert rc == 0 and tr == f.trace and list(med) == list(f.medoids.cpu().numpy())
+    assert td == f.td
+
+
+def test_float_replayed_on_oracle():
+    _say("clarans_float")
+    X = datagen.gaussian_mixture(2000, 8, 15, seed=31)
+    Dg = px().dist(_t(X))
+    D64 = Dg.cpu().numpy().astype(np.float64)
+    n, k, maxn = 2000, 15, 50
+    start = datagen.random_subset(n, k, 31)
+    draws = datagen.int_points(30000, 1, 0, n, seed=32).reshape(-1)
+    rc, med, lab, td, st, tr = _run(Dg, start, draws, maxn)
+    assert rc == 0 and st.swaps > 3
+    cur = [int(v) for v in start]
+    pos = 0
+    evals = 0
+
+    def tol_of(m):
+        _, dn, ds = oracle.nearest(m, D=D64)
+        return 16 * n * 2.0 ** -53 * float((dn + ds).sum())
+
+    for (i, c, dl) in tr:
+        tol = tol_of(cur)
+        # draws up to this swap: the evaluated ones before it do not improve
+        j = pos
+        fails = []
+        while draws[j] != c or c in cur:
+            if draws[j] not in cur:
+                fails.append(int(draws[j]))
+            j += 1
+        assert len(fails) < maxn
+        if fails:
+            assert np.nanmin(oracle.swap_list(cur, fails, D=D64)) >= -tol
+        ch = oracle.swap_list(cur, [c], D=D64)[0]
+        assert abs(ch[i] - dl) <= tol and ch[i] <= np.nanmin(ch) + 2 * tol and dl < 0
+        evals += len(fails) + 1
+        cur[i] = c
+        pos = j + 1
+    # the final run of maxneighbor failures
+    tol = tol_of(cur)
+    fails = []
+    j = pos
+    while len(fails) < maxn:
+        if draws[j] not in cur:
+            fails.append(int(draws[j]))
+        j += 1
+    assert np.nanmin(oracle.swap_list(cur, fails, D=D64)) >= -tol
+    assert st.scan_positions == evals + maxn
+    assert list(med) == cur
+    tdo, labo = oracle.td(cur, D=D64)
+    assert abs(td - tdo) <= 8 * n * 2.0 ** -53 * tdo and np.array_equal(lab, labo)
+
+
+def test_numlocal_keeps_the_best_search():
+    _say("clarans_numlocal")
+    X, D = _int_case(1200, 41, hi=400)
+    Di = _t(D.astype(np.int32))
+    r = px().clarans(Di, 10, numlocal=3, seed=5, trace=True)
+    tds = [s[0] for s in r.stats["searches"]]
+    assert r.td == min(tds) and len(tds) == 3
+    ref = oracle.clarans(r.stats["start"], r.stats["draws"], r.stats["maxneighbor"], D=D)
+    assert list(r.medoids.cpu().numpy()) == list(ref.medoids) and r.td == ref.td
+    assert r.trace == ref.trace

@@ -492,6 +492,54 @@ def test_init_lab_matches_subsample_bruteforce(exclude_self):
         assert len(set(lab)) == k
 
 
+# ---------------------------------------------------------------- FastCLARANS (Sec. 3.5)
+def test_clarans_matches_bruteforce():
+    """Random draws (medoids among them), tie-heavy integer matrices: the
+    trajectory, evaluation count and result equal the search by full TD
+    recomputation."""
+    rng = np.random.default_rng(83)
+    for trial in range(40):
+        n = int(rng.integers(5, 14))
+        k = int(rng.integers(2, min(5, n - 1) + 1))
+        D, _ = _tiny_int_D(rng, n, hi=6 if trial % 2 else 25)
+        start = [int(v) for v in rng.choice(n, size=k, replace=False)]
+        draws = rng.integers(0, n, size=400)
+        mx = int(rng.integers(1, 8))
+        r = oracle.clarans(start, draws, mx, D=D)
+        med_b, trace_b, ev_b, exhausted = brute.clarans_search(D.tolist(), start, draws.tolist(), mx)
+        assert list(r.medoids) == med_b, trial
+        assert r.trace == [(i, c, float(v)) for i, c, v in trace_b], trial
+        assert r.evaluations == ev_b and r.rc == (1 if exhausted else 0)
+        assert r.td == brute.td_of(D.tolist(), med_b)
+
+
+def test_clarans_cyclic_draws_are_fasterpam():
+    """Draws in index order, repeated, with maxneighbor = n - k: the search
+    stops where Alg. 4's scan completes a cycle without a swap, so it makes
+    FasterPAM's swaps."""
+    rng = np.random.default_rng(89)
+    for _ in range(10):
+        n = int(rng.integers(20, 80))
+        k = int(rng.integers(2, 8))
+        D, _ = _tiny_int_D(rng, n, hi=40)
+        start = [int(v) for v in rng.choice(n, size=k, replace=False)]
+        r = oracle.clarans(start, np.tile(np.arange(n), 50), n - k, D=D)
+        f = oracle.swap(start, D=D, variant=oracle.FASTERPAM)
+        assert r.rc == 0 and r.trace == f.trace and list(r.medoids) == list(f.medoids)
+
+
+def test_clarans_exhausted_list_is_a_prefix():
+    rng = np.random.default_rng(97)
+    D, _ = _tiny_int_D(rng, 60, hi=100)
+    start = [0, 1, 2, 3, 4]
+    draws = rng.integers(0, 60, size=3000)
+    full = oracle.clarans(start, draws, 40, D=D)
+    assert full.rc == 0 and full.swaps > 2
+    short = oracle.clarans(start, draws[:30], 40, D=D)
+    assert short.rc == 1
+    assert short.trace == full.trace[:short.swaps]
+
+
 # ---------------------------------------------------------------- degenerate cases
 def test_k_equals_n_and_duplicates():
     X = np.array([[0.0], [0.0], [1.0], [1.0], [5.0]])
