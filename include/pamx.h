@@ -66,7 +66,7 @@ extern "C" {
 /* SWAP variants */
 #define PAMX_FASTPAM1 1 /* best swap per iteration (Alg. 3)               */
 #define PAMX_FASTPAM2 2 /* best swap per medoid, applied eagerly (Sec. 3.2) */
-#define PAMX_FASTERPAM 3 /* FasterPAM (Alg. 4, Sec. 3.3): the candidates are
+#define PAMX_FASTERPAM 3 /* FasterPAM (Alg. 4, Sec. 3.2): the candidates are
                             visited in index order, cyclically; each takes its
                             best slot (smallest on ties) and is swapped in at
                             once when that lowers TD; the run ends after a
@@ -229,7 +229,7 @@ int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int64_t n, int
              int32_t *labels, double *td, pamx_stats *stats, void *ws, size_t ws_bytes,
              void *stream);
 
-/* FastCLARANS (Sec. 3.5): one randomized local search from `medoids`
+/* FastCLARANS (Sec. 3.4): one randomized local search from `medoids`
  * (DEVICE int32[k], slot order; read, then overwritten with the result).
  * draws: DEVICE int32[len], random object indices chosen by the caller,
  * taken in order.  A draw that is a current medoid is skipped; any other is
@@ -250,7 +250,7 @@ int pamx_clarans(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
                  const pamx_options *opt, int32_t *medoids, int32_t *labels, double *td,
                  pamx_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
-/* ---- Faster initialisations (Sec. 3.4).  Both write k object indices in
+/* ---- Faster initialisations (Sec. 3.3).  Both write k object indices in
  * slot order to `medoids` (DEVICE int32[k]) for pamx_swap, and take their
  * random draws as inputs.  D, dtype, n, ld as for pamx_build (symmetric).
  * The work is enqueued on `stream` (pamx_init_lab first synchronizes once
@@ -264,7 +264,7 @@ int pamx_init_workspace_bytes(int64_t n, int32_t m, size_t *bytes);
 
 /* Distance-weighted seeding (the k-means++ idea with the distance to the
  * nearest seed as weight, the "distance weighted" initialisation of
- * Sec. 3.4).  u: DEVICE double[k], uniforms in [0, 1).  The first seed is
+ * Sec. 3.3).  u: DEVICE double[k], uniforms in [0, 1).  The first seed is
  * floor(u[0] n); seed t is the first object, in index order, whose running
  * sum of weights exceeds u[t] W (W the sum of all weights); seeds weigh 0.
  * When W = 0 (every object coincides with a seed) the smallest-index
@@ -272,7 +272,7 @@ int pamx_init_workspace_bytes(int64_t n, int32_t m, size_t *bytes);
 int pamx_init_dw(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
                  const double *u, int32_t *medoids, void *ws, size_t ws_bytes, void *stream);
 
-/* LAB, linear approximative BUILD (Sec. 3.4): BUILD whose step t looks only
+/* LAB, linear approximative BUILD (Sec. 3.3): BUILD whose step t looks only
  * at samples[t*m .. t*m+m-1] (DEVICE int32, distinct indices in [0, n); the
  * paper draws 10 + ceil(sqrt(n)) non-medoid points per step).  The
  * non-medoid members are the candidates, in listed order (first strict

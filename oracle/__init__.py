@@ -17,10 +17,10 @@ only builds it (gcc) and marshals numpy arrays.  Paper references
                        FasterPAM, Alg. 4 (variant 3: the first candidate in scan
                        order with an improving swap, applied at once).
 * ``pam``           -- BUILD followed by SWAP, with labels.
-* ``init_dw``       -- distance-weighted seeding (Sec. 3.4, reading R8).
-* ``init_lab``      -- LAB, BUILD on per-step subsamples (Sec. 3.4, reading R9).
-* ``clarans``       -- one FastCLARANS local search over given draws (Sec. 3.5,
-                       reading R10).
+* ``init_dw``       -- distance-weighted seeding (Sec. 3.3, reading R14).
+* ``init_lab``      -- LAB, BUILD on per-step subsamples (Sec. 3.3, reading R15).
+* ``clarans``       -- one FastCLARANS local search over given draws (Sec. 3.4,
+                       reading R16).
 """
 from __future__ import annotations
 
@@ -272,7 +272,7 @@ def pam(k, D=None, X=None, metric=L2, variant=PAM, exclude_self=False, max_iter=
 
 
 def init_dw(k, u, D=None, X=None, metric=L2) -> np.ndarray:
-    """Distance-weighted seeds (reading R8) from the uniforms u[0..k-1]."""
+    """Distance-weighted seeds (reading R14) from the uniforms u[0..k-1]."""
     s = _Src(D, X, metric)
     u = np.ascontiguousarray(u, dtype=np.float64)
     if len(u) < k:
@@ -285,7 +285,7 @@ def init_dw(k, u, D=None, X=None, metric=L2) -> np.ndarray:
 
 
 def init_lab(k, samples, D=None, X=None, metric=L2, exclude_self=False) -> np.ndarray:
-    """LAB (reading R9): samples is a (k, m) array, row t = step t's subsample."""
+    """LAB (reading R15): samples is a (k, m) array, row t = step t's subsample."""
     s = _Src(D, X, metric)
     samples = np.ascontiguousarray(samples, dtype=np.int32)
     if samples.ndim != 2 or samples.shape[0] != k:
@@ -309,7 +309,7 @@ class ClaransResult:
 
 
 def clarans(med, draws, maxneighbor, D=None, X=None, metric=L2, trace_cap=100000):
-    """One FastCLARANS local search (reading R10) from medoids `med` over the
+    """One FastCLARANS local search (reading R16) from medoids `med` over the
     random draws `draws` (object indices, in order)."""
     s = _Src(D, X, metric)
     med = np.array(med, dtype=np.int32, copy=True)

@@ -13,7 +13,10 @@
  *   - the per-object loss change of a swap           (Sec. 3, Eq. change)
  *   - PAM SWAP, best-swap steepest descent           (Sec. 2, Alg. 2)
  *   - the best-swap-per-medoid eager variant that the paper calls FastPAM2
- *     (Sec. 3.2, one sentence, no pseudocode), in the reading stated below.
+ *     (Sec. 3.2, one sentence, no pseudocode), in the reading stated below
+ *   - FasterPAM, eager swapping of each improving candidate   (Sec. 3.2, Alg. 4)
+ *   - distance-weighted seeding and LAB                        (Sec. 3.3)
+ *   - one FastCLARANS local search over given random draws     (Sec. 3.4).
  *
  * FastPAM1 (Alg. 3) performs exactly the swaps of PAM (Sec. 3.1), so the
  * plain definition -- original PAM with Eq. change -- is the reference for it.
@@ -27,21 +30,21 @@
  *      to its change, so each BUILD step picks the candidate that lowers TD
  *      most (Sec. 2 text and the TD update of Alg. 1).  exclude_self=1 gives
  *      the literal loop bounds of Alg. 1, which skip x_c.
- *   R2 Ties: every argmin keeps the first minimum in ascending order
+ *   R2, R3 Ties: every argmin keeps the first minimum in ascending order
  *      (strict "<"), BUILD over c, SWAP over (slot i, then c) as in Alg. 2.
- *   R3 A swap keeps the slot: the new medoid takes the removed one's slot.
- *   R4 nearest(o) is the smallest slot at the minimum distance; ds(o) is the
+ *   R4 A swap keeps the slot: the new medoid takes the removed one's slot.
+ *   R5 nearest(o) is the smallest slot at the minimum distance; ds(o) is the
  *      minimum over all other slots (it equals dn(o) on ties).
- *   R5 FastPAM2: one search gives, per slot i, the best candidate c*_i
+ *   R6 FastPAM2: one search gives, per slot i, the best candidate c*_i
  *      (first minimum over ascending c).  Slots with a negative best are
  *      visited in order of (delta, i); a visit is skipped when c*_i has become
  *      a medoid meanwhile, otherwise the change of swapping (i, c*_i) is
  *      evaluated again against the current medoids and the swap is applied
  *      when that change is negative.  Converged when a search finds no
  *      negative change.
- *   R6 k == 1: SWAP is not run (the second-nearest distance does not exist);
+ *   R8 k == 1: SWAP is not run (the second-nearest distance does not exist);
  *      BUILD's first medoid is the medoid of the whole set (Eq. def-medoid).
- *   R7 FasterPAM (Alg. 4), with the misprints of its listing read as fixed:
+ *   R13 FasterPAM (Alg. 4), with the misprints of its listing read as fixed:
  *      the candidate that was swapped in is the one remembered as the last
  *      swap, and a scan that has made no swap at all ends after one full
  *      pass.  Candidates are visited in ascending index order, cyclically,
@@ -53,21 +56,21 @@
  *      ends when n consecutive positions have been visited without a swap
  *      (the scan is back at the last swap's position).  Iterations count the
  *      passes begun: ceil(positions visited / n).
- *   R8 Distance-weighted seeding (Sec. 3.4, the k-means++ idea with the
+ *   R14 Distance-weighted seeding (Sec. 3.3, the k-means++ idea with the
  *      distance to the nearest seed as weight, the k-medoids loss term):
  *      the first seed is floor(u_0 n); seed t is the first object, in index
  *      order, whose running weight sum exceeds u_t W (W = sum of weights,
  *      summed in index order); seeds weigh 0 and are never picked again.
  *      If W = 0 the smallest-index non-seed is taken.  The uniforms u_t in
  *      [0, 1) are inputs.
- *   R9 LAB (Sec. 3.4): each BUILD step is restricted to a subsample supplied
+ *   R15 LAB (Sec. 3.3): each BUILD step is restricted to a subsample supplied
  *      by the caller (10 + ceil(sqrt n) points, distinct): its non-medoid
  *      members are the candidates, in the order listed, and its members the
  *      objects of the change (self-term as in R1); the first strict minimum
  *      is taken.  If every member is a medoid the smallest-index non-medoid
  *      is taken.  With the whole data set listed in index order every step
  *      equals BUILD's.
- *  R10 FastCLARANS (Sec. 3.5): one local search from given medoids over a
+ *   R16 FastCLARANS (Sec. 3.4): one local search from given medoids over a
  *      list of random draws supplied by the caller.  A draw that is a medoid
  *      is skipped; otherwise it is a candidate like in Alg. 4 (best slot,
  *      smallest on ties, swapped in when its change is negative).  Draws
@@ -164,7 +167,7 @@ int orc_dist_rows(const double *X, int64_t n, int32_t dim, int32_t metric,
 }
 
 /* ------------------------------------------------------------------ */
-/* Nearest / second-nearest medoid of every object (reading R4).        */
+/* Nearest / second-nearest medoid of every object (reading R5).        */
 /* ------------------------------------------------------------------ */
 static void nearest_all(const src_t *s, const int32_t *med, int32_t k,
                         int32_t *near, double *dn, double *ds)
@@ -507,11 +510,11 @@ int orc_build_list(const double *D, const double *X, int64_t n, int32_t dim, int
 }
 
 /* ------------------------------------------------------------------ */
-/* PAM SWAP (Alg. 2), the FastPAM2 reading R5 and FasterPAM (R7).     */
+/* PAM SWAP (Alg. 2), the FastPAM2 reading R6 and FasterPAM (R13).     */
 /*   variant 1 = best swap per iteration (PAM; FastPAM1 gives the same) */
-/*   variant 2 = best swap per medoid, applied eagerly (reading R5)     */
+/*   variant 2 = best swap per medoid, applied eagerly (reading R6)     */
 /*   variant 3 = FasterPAM, Alg. 4: first improving candidate in scan   */
-/*               order, its best slot, applied at once (reading R7)     */
+/*               order, its best slot, applied at once (reading R13)     */
 /* med is read (slot order) and overwritten with the result.            */
 /* trace_* (optional, capacity trace_cap) receive every applied swap.   */
 /* ------------------------------------------------------------------ */
@@ -549,7 +552,7 @@ int orc_swap(const double *D, const double *X, int64_t n, int32_t dim, int32_t m
     for (int64_t o = 0; o < n; ++o) td += dn[o];
 
     if (variant == 3 && k >= 2 && k < n) {
-        /* reading R7: one candidate at a time, in scan order */
+        /* reading R13: one candidate at a time, in scan order */
         int64_t pos = 0, visited = 0, quiet = 0;
         while (quiet < n) {
             if (visited == (int64_t)max_iter * n) { rc = ORC_WARN_MAXITER; break; }
@@ -669,8 +672,8 @@ int orc_swap(const double *D, const double *X, int64_t n, int32_t dim, int32_t m
 }
 
 /* ------------------------------------------------------------------ */
-/* Faster initialisations (Sec. 3.4): distance-weighted seeding (R8)    */
-/* and LAB (R9).  med receives k object indices in slot order.          */
+/* Faster initialisations (Sec. 3.3): distance-weighted seeding (R14)    */
+/* and LAB (R15).  med receives k object indices in slot order.          */
 /* ------------------------------------------------------------------ */
 int orc_init_dw(const double *D, const double *X, int64_t n, int32_t dim, int32_t metric,
                 int32_t k, const double *u, int32_t *med)
@@ -755,7 +758,7 @@ int orc_init_lab(const double *D, const double *X, int64_t n, int32_t dim, int32
     return ORC_OK;
 }
 
-/* FastCLARANS local search (R10).  med (slot order) is read and
+/* FastCLARANS local search (R16).  med (slot order) is read and
  * overwritten; trace_* (optional) receive the swaps; n_eval = draws
  * evaluated (non-medoid draws up to the end of the search). */
 int orc_clarans(const double *D, const double *X, int64_t n, int32_t dim, int32_t metric,

@@ -100,7 +100,7 @@ def fit(data, k, *, input_kind=PAMX_INPUT_X, metric=None, variant="fastpam1",
     variant="fasterpam": Alg. 4; window = candidates scored per pass (0 =
     automatic).
     init: "build" (PAM BUILD, default), or one of the initialisations of
-    Sec. 3.4 drawn from `seed`: "random" (k uniform distinct objects), "dw"
+    Sec. 3.3 drawn from `seed`: "random" (k uniform distinct objects), "dw"
     (distance-weighted seeding), "lab" (linear approximative BUILD); these
     run on the stored matrix (computed first for points), then SWAP."""
     import torch
@@ -187,7 +187,7 @@ def swap(D, medoids, *, variant="fastpam1", accum=PAMX_ACC_F64, max_iter=10000, 
 
 
 def init_dw(D, k, *, seed=0, u=None, stream=None):
-    """Distance-weighted seeds (Sec. 3.4) from k uniforms (drawn from `seed`
+    """Distance-weighted seeds (Sec. 3.3) from k uniforms (drawn from `seed`
     unless given): device int32 [k]."""
     import torch
     from . import datagen
@@ -202,13 +202,13 @@ def init_dw(D, k, *, seed=0, u=None, stream=None):
 
 
 def lab_sample_size(n):
-    """LAB's per-step subsample, 10 + ceil(sqrt(n)) points (Sec. 3.4), at most n."""
+    """LAB's per-step subsample, 10 + ceil(sqrt(n)) points (Sec. 3.3), at most n."""
     import math
     return min(n, 10 + math.isqrt(n - 1) + 1 if n > 1 else 1)
 
 
 def init_lab(D, k, *, seed=0, m=None, samples=None, exclude_self=False, stream=None):
-    """LAB seeds (Sec. 3.4): BUILD on a fresh subsample of m points per step
+    """LAB seeds (Sec. 3.3): BUILD on a fresh subsample of m points per step
     (default 10 + ceil(sqrt(n)); rows of `samples` if given).  Device int32 [k]."""
     import torch
     from . import datagen
@@ -225,13 +225,13 @@ def init_lab(D, k, *, seed=0, m=None, samples=None, exclude_self=False, stream=N
 
 def clarans_maxneighbor(n, k):
     """Failures that end a FastCLARANS search: 2.5% of the non-medoids
-    (the paper's setting, Sec. 3.5), at least 1."""
+    (the paper's setting, Sec. 3.4), at least 1."""
     return max(1, int(round(0.025 * (n - k))))
 
 
 def clarans(D, k, *, numlocal=2, seed=0, maxneighbor=None, draws_per_search=None, trace=False,
             stream=None) -> FitResult:
-    """FastCLARANS (Sec. 3.5) on a stored matrix: `numlocal` local searches,
+    """FastCLARANS (Sec. 3.4) on a stored matrix: `numlocal` local searches,
     each from k uniform random medoids over its own list of random draws
     (seeded), keeping the smallest TD (the first on ties).  stats gain
     "searches": [(td, swaps, draws evaluated, rc)]."""

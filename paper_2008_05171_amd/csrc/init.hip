@@ -1,4 +1,4 @@
-// init.hip -- the faster initialisations of Sec. 3.4 on gfx950.
+// init.hip -- the faster initialisations of Sec. 3.3 on gfx950.
 //
 // Distance-weighted seeding: the k-means++ idea with the distance to the
 // nearest seed (the k-medoids loss term) as weight.  The first seed is

@@ -724,7 +724,7 @@ int swap_impl(const T *D, int64_t ld, const Layout &L_in, int32_t k, const pamx_
     return st.capped ? PAMX_WARN_MAXITER : PAMX_OK;
 }
 
-// One FastCLARANS local search (Sec. 3.5) over the caller's draws.
+// One FastCLARANS local search (Sec. 3.4) over the caller's draws.
 template <typename T>
 int clarans_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const int32_t *draws,
                  int64_t len, int64_t maxneighbor, const pamx_options &opt, int32_t *medoids,

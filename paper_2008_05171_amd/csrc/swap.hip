@@ -1231,7 +1231,7 @@ __global__ __launch_bounds__(256) void k_fp_select_update(
     }
 }
 
-// ---- FastCLARANS (Sec. 3.5): one local search over a list of random draws.
+// ---- FastCLARANS (Sec. 3.4): one local search over a list of random draws.
 // A draw that is a medoid is skipped; any other is a candidate as in Alg. 4
 // (best slot, smallest on ties, swapped in when the change is below the
 // acceptance threshold).  Draws that do not improve count as failures, a swap

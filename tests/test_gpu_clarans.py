@@ -1,4 +1,4 @@
-"""GPU parity of FastCLARANS (Sec. 3.5): the window search against the oracle.
+"""GPU parity of FastCLARANS (Sec. 3.4): the window search against the oracle.
 
 Integer dissimilarities: bit-exact trajectory (slot, candidate, change),
 evaluation count, medoids, labels and TD for the same starting medoids and

@@ -2,7 +2,7 @@
 
 Integer dissimilarities: bit-exact medoids, labels, TD, the whole swap
 trajectory (slot, candidate, change) and the number of passes, against the
-oracle's sequential scan (reading R7), for several window widths (one
+oracle's sequential scan (reading R13), for several window widths (one
 window per pass, many windows per pass with wrap-around, the 1-wide load
 path).  Float dissimilarities: the same FP32 matrix on both sides; the GPU's
 swaps are replayed on the oracle: each change agrees within the FP64

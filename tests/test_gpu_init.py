@@ -1,4 +1,4 @@
-"""GPU parity of the faster initialisations (Sec. 3.4) against the oracle.
+"""GPU parity of the faster initialisations (Sec. 3.3) against the oracle.
 
 Integer dissimilarities: the seeds of distance-weighted seeding and of LAB
 equal the oracle's bit for bit (weights and changes are exact integers on

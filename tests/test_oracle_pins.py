@@ -492,7 +492,7 @@ def test_init_lab_matches_subsample_bruteforce(exclude_self):
         assert len(set(lab)) == k
 
 
-# ---------------------------------------------------------------- FastCLARANS (Sec. 3.5)
+# ---------------------------------------------------------------- FastCLARANS (Sec. 3.4)
 def test_clarans_matches_bruteforce():
     """Random draws (medoids among them), tie-heavy integer matrices: the
     trajectory, evaluation count and result equal the search by full TD
