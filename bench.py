@@ -20,6 +20,11 @@ Reported (one JSON line):
                    library's stream), against 8 TB/s HBM
   cpu_baseline     the CPU oracle (original PAM SWAP, FP64, OpenMP) on a
                    bounded sample of candidates of the same workload
+
+--next fasterpam|init|clarans [--large] times a row beyond the headline
+instead (FasterPAM from BUILD; distance-weighted and LAB seeding; one
+FastCLARANS search) on this workload, or with --large on the 1e5 x 32 Zipf
+mixture (k = 500, 40 GB matrix), and prints one JSON line of its timings.
 """
 from __future__ import annotations
 
@@ -126,6 +131,47 @@ def cpu_baseline(X, k, target_s):
                       "candidates 0..%d of the same %d-point workload, %.1f s" % (k, m - 1, n, dt)}
 
 
+def run_next(which, large, reps):
+    """Time one of the rows beyond the headline (see the module docstring)."""
+    import torch
+    import paper_2008_05171_amd as px
+    from paper_2008_05171_amd import datagen
+    if large:
+        X = torch.from_numpy(datagen.workload_gmm32_zipf()).cuda()
+        k, name = 500, "gmm32 zipf: n=100000 d=32, 500 Zipf(1.1)-weighted components, k=500"
+    else:
+        X = torch.from_numpy(datagen.gaussian_mixture(N, DIM, COMPONENTS, seed=SEED)).cuda()
+        k, name = K, "gmm16: n=20000 d=16, 50 components, k=100"
+    out = {"next": which, "workload": name, "runs": []}
+    D = px.dist(X) if which in ("init", "clarans") else None
+    for r in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        if which == "fasterpam":
+            res = px.fit(X, k, variant="fasterpam")
+            torch.cuda.synchronize()
+            s = res.stats
+            run = {"fit_ms": s["ms_total"], "swap_ms": s["ms_swap"], "windows": s["windows"],
+                   "swaps": s["swaps"], "passes": s["iterations"], "td": res.td}
+        elif which == "init":
+            px.init_dw(D, k, seed=1)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            px.init_lab(D, k, seed=1)
+            torch.cuda.synchronize()
+            run = {"dw_ms": (a - t) * 1e3, "lab_ms": (time.perf_counter() - a) * 1e3}
+        else:
+            res = px.clarans(D, k, numlocal=1, seed=1)
+            torch.cuda.synchronize()
+            s = res.stats
+            run = {"search_ms": s["ms_swap"], "windows": s["windows"], "swaps": s["swaps"],
+                   "draws_evaluated": s["scan_positions"], "td": res.td}
+        run["wall_ms"] = (time.perf_counter() - t) * 1e3
+        out["runs"].append(run)
+        log("%s run %d: %s" % (which, r, run))
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,7 +187,14 @@ def main():
                     help="write the SWAP pass traffic record from two rocprofv3 --pmc runs of "
                          "this script with --copy-probe-mib, whose fits used chunk length CHUNK "
                          "(printed as config.chunk; no GPU work)")
+    ap.add_argument("--next", choices=("fasterpam", "init", "clarans"),
+                    help="time a row beyond the headline instead (one JSON line)")
+    ap.add_argument("--large", action="store_true",
+                    help="with --next: the 1e5-point, k=500 workload")
     args = ap.parse_args()
+    if args.next:
+        run_next(args.next, args.large, max(args.steps, 1))
+        return
     if args.write_traffic:
         if args.copy_probe_mib <= 0:
             sys.exit("--write-traffic needs the --copy-probe-mib size of the profiled runs")

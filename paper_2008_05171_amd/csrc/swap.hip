@@ -1026,6 +1026,11 @@ __global__ void k_fp_init(DevState *st, int64_t n, int64_t tile, int32_t vec, lo
 // the candidate's first thread combines the 16 summaries in chunk order.
 // The work-group (16 candidates) reports its first candidate at or after the
 // scan position whose best change is below the acceptance threshold.
+// candidates per window-merge work-group and the merge grid: 16 candidates
+// (64-byte column segments) on 64 work-groups measured faster than 4 on 256
+constexpr int kFmCPB = 16;
+constexpr int kFmGrid = 64;
+
 template <typename A>
 struct RunSum {
     A accA, bv, fm, fdn, lm, ldn;
@@ -1040,7 +1045,7 @@ __global__ __launch_bounds__(256) void k_fp_merge(
     const DevState *__restrict__ st, AccT<T> *__restrict__ wg_v, int32_t *__restrict__ wg_i,
     int32_t *__restrict__ wg_c) {
     using A = AccT<T>;
-    constexpr int CPB = 16, G = 16;
+    constexpr int CPB = kFmCPB, G = 256 / kFmCPB;
     if (st->done) return;
     __shared__ RunSum<A> sm[G][CPB];
     __shared__ int first;
@@ -1702,7 +1707,7 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
 
     if (opt.variant == PAMX_FASTERPAM) {
         // one window of the scan (segments are rebuilt only after a swap)
-        const int nwg = (L.fw / 16 < 64) ? L.fw / 16 : 64;   // merge work-groups
+        const int nwg = (L.fw / kFmCPB < kFmGrid) ? L.fw / kFmCPB : kFmGrid;   // merge work-groups
         enqueue_segments<T>(L, p, s);
         if (ev0) (void)hipEventRecord(ev0, s);
         enqueue_pass<T>(D, ld, L, p, false, s, true);
