@@ -21,6 +21,9 @@ only builds it (gcc) and marshals numpy arrays.  Paper references
 * ``init_lab``      -- LAB, BUILD on per-step subsamples (Sec. 3.3, reading R15).
 * ``clarans``       -- one FastCLARANS local search over given draws (Sec. 3.4,
                        reading R16).
+* ``rect_build``, ``rect_swap``, ``rect_td``, ``rect_pam`` -- BUILD and PAM SWAP
+                       for bichromatic medoids: consumers x locations matrix
+                       (Sec. 5, reading R17).
 """
 from __future__ import annotations
 
@@ -79,6 +82,10 @@ def _load():
     lib.orc_init_dw.argtypes = [P, P, i64, i32, i32, i32, P, P]
     lib.orc_init_lab.argtypes = [P, P, i64, i32, i32, i32, P, i32, i32, P]
     lib.orc_clarans.argtypes = [P, P, i64, i32, i32, P, i32, P, i64, i64, P, P, P, i32, P, P, P]
+    lib.orc_rect_td.argtypes = [P, i64, i64, P, i32, P]
+    lib.orc_rect_td.restype = f64
+    lib.orc_rect_build.argtypes = [P, i64, i64, i32, P, P]
+    lib.orc_rect_swap.argtypes = [P, i64, i64, P, i32, i32, P, P, P, i32, P, P, P]
     _lib = lib
     return lib
 
@@ -328,3 +335,58 @@ def clarans(med, draws, maxneighbor, D=None, X=None, metric=L2, trace_cap=100000
     m = min(sw.value, trace_cap)
     trace = [(int(ts[j]), int(tc[j]), float(tdl[j])) for j in range(m)]
     return ClaransResult(med, tdv.value, ev.value, sw.value, rc, trace)
+
+
+def _rect(D):
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    if D.ndim != 2:
+        raise ValueError("D must be consumers x locations")
+    return D, D.shape[0], D.shape[1]
+
+
+def rect_td(med, D):
+    """(TD, labels) of location medoids `med` for the consumers x locations D."""
+    D, nc, nl = _rect(D)
+    med = np.ascontiguousarray(med, dtype=np.int32)
+    labels = np.empty(nc, np.int32)
+    v = _load().orc_rect_td(_ptr(D), nc, nl, _ptr(med), len(med), _ptr(labels))
+    return float(v), labels
+
+
+def rect_build(k, D):
+    """BUILD over locations (reading R17): (medoids, TD)."""
+    D, nc, nl = _rect(D)
+    med = np.empty(k, np.int32)
+    tdv = np.zeros(1, np.float64)
+    rc = _load().orc_rect_build(_ptr(D), nc, nl, int(k), _ptr(med), _ptr(tdv))
+    if rc:
+        raise ValueError("orc_rect_build rc=%d" % rc)
+    return med, float(tdv[0])
+
+
+def rect_swap(med, D, max_iter=10000, trace_cap=100000):
+    """PAM SWAP over locations (reading R17)."""
+    D, nc, nl = _rect(D)
+    med = np.array(med, dtype=np.int32, copy=True)
+    ts = np.empty(trace_cap, np.int32)
+    tc = np.empty(trace_cap, np.int64)
+    tdl = np.empty(trace_cap, np.float64)
+    it = ctypes.c_int32()
+    sw = ctypes.c_int32()
+    tdv = ctypes.c_double()
+    rc = _load().orc_rect_swap(_ptr(D), nc, nl, _ptr(med), len(med), int(max_iter), _ptr(ts),
+                               _ptr(tc), _ptr(tdl), int(trace_cap), ctypes.byref(it),
+                               ctypes.byref(sw), ctypes.byref(tdv))
+    if rc < 0:
+        raise ValueError("orc_rect_swap rc=%d" % rc)
+    m = min(sw.value, trace_cap)
+    trace = [(int(ts[j]), int(tc[j]), float(tdl[j])) for j in range(m)]
+    return SwapResult(med, tdv.value, it.value, sw.value, rc, trace)
+
+
+def rect_pam(k, D, max_iter=10000):
+    """Bichromatic BUILD then SWAP: PamResult with location medoids."""
+    bm, td_b = rect_build(k, D)
+    r = rect_swap(bm, D, max_iter=max_iter)
+    tdv, labels = rect_td(r.medoids, D)
+    return PamResult(r.medoids, labels, tdv, td_b, bm, r.iterations, r.swaps, r.rc, r.trace)

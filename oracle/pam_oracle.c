@@ -16,7 +16,9 @@
  *     (Sec. 3.2, one sentence, no pseudocode), in the reading stated below
  *   - FasterPAM, eager swapping of each improving candidate   (Sec. 3.2, Alg. 4)
  *   - distance-weighted seeding and LAB                        (Sec. 3.3)
- *   - one FastCLARANS local search over given random draws     (Sec. 3.4).
+ *   - one FastCLARANS local search over given random draws     (Sec. 3.4)
+ *   - BUILD and PAM SWAP for bichromatic medoids, separate consumers and
+ *     locations                                                (Sec. 5).
  *
  * FastPAM1 (Alg. 3) performs exactly the swaps of PAM (Sec. 3.1), so the
  * plain definition -- original PAM with Eq. change -- is the reference for it.
@@ -78,6 +80,14 @@
  *      search ends when maxneighbor failures follow each other (a local
  *      optimum for the sampled neighbourhood) or when the list runs out
  *      (reported as not converged).  Restarts are separate searches.
+ *   R17 Bichromatic medoids (Sec. 5): consumers C (the objects) and
+ *      possible locations L (the candidates) are separate sets; D is the
+ *      |C| x |L| matrix of consumer-location distances; the k medoids are
+ *      locations and TD sums each consumer's distance to its nearest
+ *      medoid.  BUILD and SWAP keep their steps (Alg. 1, Alg. 2, Eq. change)
+ *      with objects = consumers and candidates = locations; no object is a
+ *      candidate, so there is no self-term (with C = L and a symmetric D
+ *      this is the one-set method with the self-term of R1).
  */
 #include <math.h>
 #include <stdint.h>
@@ -830,5 +840,158 @@ int orc_clarans(const double *D, const double *X, int64_t n, int32_t dim, int32_
         *td_out = fresh;
     }
     free(is_med); free(dn); free(ds); free(near); free(chg);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Bichromatic medoids (R17): D is nc x nl, row-major (consumers x      */
+/* locations); medoids are location indices.                           */
+/* ------------------------------------------------------------------ */
+static void rect_nearest(const double *D, int64_t nc, int64_t nl, const int32_t *med, int32_t k,
+                         int32_t *near, double *dn, double *ds)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t o = 0; o < nc; ++o) {
+        double b1 = INFINITY, b2 = INFINITY;
+        int32_t i1 = -1;
+        for (int32_t i = 0; i < k; ++i) {
+            const double d = D[o * nl + med[i]];
+            if (d < b1) { b2 = b1; b1 = d; i1 = i; }
+            else if (d < b2) b2 = d;
+        }
+        near[o] = i1; dn[o] = b1; ds[o] = b2;
+    }
+}
+
+double orc_rect_td(const double *D, int64_t nc, int64_t nl, const int32_t *med, int32_t k,
+                   int32_t *labels)
+{
+    if (!D || nc < 1 || nl < 1 || !med || k < 1) return NAN;
+    double td = 0.0;
+    for (int64_t o = 0; o < nc; ++o) {
+        double b = INFINITY;
+        int32_t bi = -1;
+        for (int32_t i = 0; i < k; ++i) {
+            const double d = D[o * nl + med[i]];
+            if (d < b) { b = d; bi = i; }
+        }
+        td += b;
+        if (labels) labels[o] = bi;
+    }
+    return td;
+}
+
+/* BUILD (Alg. 1) over locations: step 0 takes the location with the
+ * smallest sum of distances to all consumers (the bichromatic medoid);
+ * step t the location whose addition lowers TD most (first minimum). */
+int orc_rect_build(const double *D, int64_t nc, int64_t nl, int32_t k, int32_t *med, double *td_out)
+{
+    if (!D || nc < 1 || nl < 1 || k < 1 || k > nl || !med) return ORC_ERR_ARG;
+    double *dn = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *chg = (double *)malloc(sizeof(double) * (size_t)nl);
+    unsigned char *is_med = (unsigned char *)calloc((size_t)nl, 1);
+    if (!dn || !chg || !is_med) { free(dn); free(chg); free(is_med); return ORC_ERR_MEM; }
+    for (int64_t o = 0; o < nc; ++o) dn[o] = INFINITY;
+    for (int32_t t = 0; t < k; ++t) {
+        #pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < nl; ++c) {
+            if (is_med[c]) { chg[c] = NAN; continue; }
+            double acc = 0.0;
+            for (int64_t o = 0; o < nc; ++o) {
+                const double d = D[o * nl + c];
+                if (t == 0) acc += d;
+                else if (d < dn[o]) acc += d - dn[o];
+            }
+            chg[c] = acc;
+        }
+        double best = INFINITY;
+        int64_t bc = -1;
+        for (int64_t c = 0; c < nl; ++c)
+            if (!is_med[c] && chg[c] < best) { best = chg[c]; bc = c; }
+        med[t] = (int32_t)bc;
+        is_med[bc] = 1;
+        for (int64_t o = 0; o < nc; ++o) {
+            const double d = D[o * nl + bc];
+            if (d < dn[o]) dn[o] = d;
+        }
+    }
+    if (td_out) {
+        double td = 0.0;
+        for (int64_t o = 0; o < nc; ++o) td += dn[o];
+        *td_out = td;
+    }
+    free(dn); free(chg); free(is_med);
+    return ORC_OK;
+}
+
+/* PAM SWAP (Alg. 2) over locations: per search the best (change, slot,
+ * location) with strict "<" in slot-outer, location-inner order; each
+ * change the sum of Eq. change over all consumers. */
+int orc_rect_swap(const double *D, int64_t nc, int64_t nl, int32_t *med, int32_t k,
+                  int32_t max_iter, int32_t *trace_slot, int64_t *trace_c, double *trace_delta,
+                  int32_t trace_cap, int32_t *n_iter, int32_t *n_swaps, double *td_out)
+{
+    if (!D || nc < 1 || nl < 1 || !med || k < 1 || k > nl || max_iter < 0) return ORC_ERR_ARG;
+    unsigned char *is_med = (unsigned char *)calloc((size_t)nl, 1);
+    if (!is_med) return ORC_ERR_MEM;
+    for (int32_t i = 0; i < k; ++i) {
+        if (med[i] < 0 || med[i] >= nl || is_med[med[i]]) { free(is_med); return ORC_ERR_ARG; }
+        is_med[med[i]] = 1;
+    }
+    double *dn = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *ds = (double *)malloc(sizeof(double) * (size_t)nc);
+    int32_t *near = (int32_t *)malloc(sizeof(int32_t) * (size_t)nc);
+    double *tab = (double *)malloc(sizeof(double) * (size_t)nl * (size_t)k);
+    if (!dn || !ds || !near || !tab) {
+        free(is_med); free(dn); free(ds); free(near); free(tab);
+        return ORC_ERR_MEM;
+    }
+    int rc = ORC_OK;
+    int32_t iters = 0, swaps = 0;
+    rect_nearest(D, nc, nl, med, k, near, dn, ds);
+    double td = 0.0;
+    for (int64_t o = 0; o < nc; ++o) td += dn[o];
+    while (k >= 2 && k < nl) {
+        if (iters >= max_iter) { rc = ORC_WARN_MAXITER; break; }
+        ++iters;
+        #pragma omp parallel for collapse(2) schedule(dynamic, 16)
+        for (int32_t i = 0; i < k; ++i)
+            for (int64_t c = 0; c < nl; ++c) {
+                double acc = NAN;
+                if (!is_med[c]) {
+                    acc = 0.0;
+                    for (int64_t o = 0; o < nc; ++o)
+                        acc += orc_change(D[o * nl + c], near[o] == i, dn[o], ds[o]);
+                }
+                tab[(int64_t)i * nl + c] = acc;
+            }
+        double bd = 0.0;
+        int32_t bi = -1;
+        int64_t bc = -1;
+        for (int32_t i = 0; i < k; ++i)
+            for (int64_t c = 0; c < nl; ++c) {
+                if (is_med[c]) continue;
+                const double v = tab[(int64_t)i * nl + c];
+                if (v < bd) { bd = v; bi = i; bc = c; }
+            }
+        if (bi < 0) break;
+        is_med[med[bi]] = 0;
+        med[bi] = (int32_t)bc;
+        is_med[bc] = 1;
+        td += bd;
+        if (trace_slot && swaps < trace_cap) {
+            trace_slot[swaps] = bi; trace_c[swaps] = bc; trace_delta[swaps] = bd;
+        }
+        ++swaps;
+        rect_nearest(D, nc, nl, med, k, near, dn, ds);
+        double fresh = 0.0;
+        for (int64_t o = 0; o < nc; ++o) fresh += dn[o];
+        if (!td_matches(td, fresh)) { rc = ORC_ERR_TD; break; }
+        td = fresh;
+    }
+    if (n_iter) *n_iter = iters;
+    if (n_swaps) *n_swaps = swaps;
+    if (td_out) *td_out = orc_rect_td(D, nc, nl, med, k, NULL);
+    free(is_med); free(dn); free(ds); free(near); free(tab);
     return rc;
 }

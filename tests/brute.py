@@ -208,3 +208,51 @@ def clarans_search(D, med, draws, maxneighbor):
         else:
             fails += 1
     return med, trace, evals, fails < maxneighbor
+
+
+# ---- bichromatic medoids: D[consumer][location], medoids are locations
+def rect_td_of(D, med):
+    return sum(min(row[m] for m in med) for row in D)
+
+
+def rect_build_greedy(D, k):
+    """Location with the smallest distance sum to all consumers, then the
+    location lowering TD most (first on ties), by full recomputation."""
+    nl = len(D[0])
+    med = []
+    for _ in range(k):
+        best, bc = None, None
+        for c in range(nl):
+            if c in med:
+                continue
+            v = rect_td_of(D, med + [c])
+            if best is None or v < best:
+                best, bc = v, c
+        med.append(bc)
+    return med
+
+
+def rect_pam_swap(D, med, max_iter=1000):
+    """Best-swap steepest descent over (change, slot, location) by full TD
+    recomputation."""
+    nl = len(D[0])
+    med = list(med)
+    trace = []
+    for _ in range(max_iter):
+        base = rect_td_of(D, med)
+        best = None
+        for i in range(len(med)):
+            for c in range(nl):
+                if c in med:
+                    continue
+                m2 = list(med)
+                m2[i] = c
+                v = rect_td_of(D, m2) - base
+                if v < 0 and (best is None or (v, i, c) < best):
+                    best = (v, i, c)
+        if best is None:
+            break
+        v, i, c = best
+        med[i] = c
+        trace.append((i, c, v))
+    return med, trace

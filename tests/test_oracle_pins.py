@@ -540,6 +540,57 @@ def test_clarans_exhausted_list_is_a_prefix():
     assert short.trace == full.trace[:short.swaps]
 
 
+# ---------------------------------------------------------------- bichromatic medoids (Sec. 5)
+def test_rect_square_symmetric_is_the_one_set_method():
+    """Consumers = locations with a symmetric zero-diagonal matrix: the same
+    BUILD, swap trajectory, medoids and TD as the one-set method (R1)."""
+    rng = np.random.default_rng(101)
+    for _ in range(10):
+        n = int(rng.integers(8, 60))
+        k = int(rng.integers(1, 6))
+        D, _ = _tiny_int_D(rng, n, hi=25)
+        a = oracle.rect_pam(k, D)
+        b = oracle.pam(k, D=D)
+        assert list(a.medoids) == list(b.medoids) and a.td == b.td
+        assert list(a.build_medoids) == list(b.build_medoids) and a.td_build == b.td_build
+        assert a.trace == b.trace and np.array_equal(a.labels, b.labels)
+
+
+def test_rect_matches_bruteforce():
+    """Rectangular consumer x location matrices (more, fewer or as many
+    locations as consumers, tie-heavy): BUILD = greedy by full recomputation,
+    SWAP = steepest descent by full recomputation, a local optimum, no better
+    than the global optimum over all k-subsets of locations."""
+    from itertools import combinations
+    rng = np.random.default_rng(103)
+    for trial in range(30):
+        nc = int(rng.integers(3, 16))
+        nl = int(rng.integers(3, 11))
+        k = int(rng.integers(1, min(4, nl) + 1))
+        D = rng.integers(0, 6 if trial % 2 else 30, size=(nc, nl)).astype(np.float64)
+        Dl = D.tolist()
+        bm, tdb = oracle.rect_build(k, D)
+        assert list(bm) == brute.rect_build_greedy(Dl, k), trial
+        assert tdb == brute.rect_td_of(Dl, list(bm))
+        r = oracle.rect_swap(bm, D)
+        med_b, trace_b = brute.rect_pam_swap(Dl, list(bm))
+        assert list(r.medoids) == med_b and r.trace == [(i, c, float(v)) for i, c, v in trace_b]
+        assert r.td == brute.rect_td_of(Dl, med_b)
+        opt = min(brute.rect_td_of(Dl, list(m)) for m in combinations(range(nl), k))
+        assert opt <= r.td
+
+
+def test_rect_k1_is_the_bichromatic_medoid():
+    """k = 1: the location minimising the summed distance to all consumers
+    (the bichromatic medoid definition of Sec. 5), first on ties."""
+    rng = np.random.default_rng(107)
+    for _ in range(20):
+        D = rng.integers(0, 50, size=(int(rng.integers(1, 30)), int(rng.integers(1, 20))))
+        D = D.astype(np.float64)
+        r = oracle.rect_pam(1, D)
+        assert list(r.medoids) == [int(np.argmin(D.sum(0)))]
+
+
 # ---------------------------------------------------------------- degenerate cases
 def test_k_equals_n_and_duplicates():
     X = np.array([[0.0], [0.0], [1.0], [1.0], [5.0]])
