@@ -250,6 +250,32 @@ int pamx_clarans(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
                  const pamx_options *opt, int32_t *medoids, int32_t *labels, double *td,
                  pamx_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Bichromatic medoids (facility location, Sec. 5): consumers and
+ * possible locations are separate sets.  D: DEVICE n_cons x n_loc matrix
+ * (row-major, row stride ld >= n_loc) of consumer-to-location
+ * dissimilarities (finite, non-negative, no symmetry needed).  The k
+ * medoids are location indices in slot order; TD sums each consumer's
+ * distance to its nearest medoid; labels (DEVICE int32[n_cons] or NULL)
+ * hold slots.  pamx_fit_rect runs BUILD (Alg. 1: first the location with
+ * the smallest summed distance to all consumers -- the bichromatic medoid
+ * of Sec. 5 -- then each step the location that lowers TD most; no
+ * self-term, as no location is a consumer) and FastPAM1 SWAP with the
+ * arithmetic and tie rules of pamx_fit; pamx_swap_rect starts from the
+ * medoids given (DEVICE int32[k], read and overwritten).  The workspace
+ * (pamx_rect_workspace_bytes) also holds the transposed matrix (each
+ * location's distances to all consumers).  opt: FastPAM1 with a stored
+ * matrix only (else PAMX_ERR_UNSUPPORTED); build_exclude_self does not
+ * apply.  With n_cons = n_loc and a symmetric zero-diagonal D the results
+ * equal pamx_fit / pamx_swap on that matrix. */
+int pamx_rect_workspace_bytes(int64_t n_cons, int64_t n_loc, int32_t k, int32_t dtype,
+                              const pamx_options *opt, size_t *bytes);
+int pamx_fit_rect(const void *D, int32_t dtype, int64_t n_cons, int64_t n_loc, int64_t ld,
+                  int32_t k, const pamx_options *opt, int32_t *medoids, int32_t *labels,
+                  double *td, pamx_stats *stats, void *ws, size_t ws_bytes, void *stream);
+int pamx_swap_rect(const void *D, int32_t dtype, int64_t n_cons, int64_t n_loc, int64_t ld,
+                   int32_t k, const pamx_options *opt, int32_t *medoids, int32_t *labels,
+                   double *td, pamx_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- Faster initialisations (Sec. 3.3).  Both write k object indices in
  * slot order to `medoids` (DEVICE int32[k]) for pamx_swap, and take their
  * random draws as inputs.  D, dtype, n, ld as for pamx_build (symmetric).

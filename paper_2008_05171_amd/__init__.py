@@ -17,7 +17,8 @@ from .pamx import (PAMX_ACC_F32, PAMX_ACC_F64, PAMX_CHUNK_TUNE, PAMX_DIST_BF16, 
                    PAMX_FASTERPAM, PAMX_FASTPAM1,
                    PAMX_FASTPAM2, PAMX_INPUT_D, PAMX_INPUT_X, PAMX_L1, PAMX_L2, PamxError)
 
-__all__ = ["fit", "build", "swap", "dist", "init_dw", "init_lab", "clarans", "fit_batched", "FitResult", "BatchResult", "PamxError", "PAMX_FASTPAM1",
+__all__ = ["fit", "build", "swap", "dist", "init_dw", "init_lab", "clarans", "fit_rect",
+           "fit_batched", "FitResult", "BatchResult", "PamxError", "PAMX_FASTPAM1",
            "PAMX_FASTPAM2", "PAMX_FASTERPAM", "PAMX_L1", "PAMX_L2", "PAMX_ACC_F64", "PAMX_ACC_F32",
            "PAMX_INPUT_D", "PAMX_INPUT_X", "PAMX_CHUNK_TUNE"]
 
@@ -265,6 +266,27 @@ def clarans(D, k, *, numlocal=2, seed=0, maxneighbor=None, draws_per_search=None
     best.stats["searches"] = runs
     best.stats["maxneighbor"] = maxneighbor
     return best
+
+
+def fit_rect(D, k, *, medoids=None, max_iter=10000, trace=False, stream=None) -> FitResult:
+    """Bichromatic medoids (Sec. 5) on a consumers x locations matrix D
+    (device, int32 or float32): BUILD then FastPAM1, or FastPAM1 from the
+    location `medoids` given.  Medoids are location indices, labels slots."""
+    import torch
+    nco, nl = D.shape
+    cap = max_iter + 16 if trace else 0
+    tbuf = torch.empty(cap * 16, dtype=torch.uint8, device=D.device) if trace else None
+    opt = _options(max_iter=max_iter, trace_buf=tbuf, trace_cap=cap)
+    nbytes = _abi.pamx_rect_workspace_bytes(nco, nl, k, _abi._dtype_code(D), opt)
+    ws = _workspace(nbytes, D.device)
+    if medoids is None:
+        med = torch.empty(k, dtype=torch.int32, device=D.device)
+    else:
+        med = medoids.to(device=D.device, dtype=torch.int32).clone()
+    lab = torch.empty(nco, dtype=torch.int32, device=D.device)
+    rc, td, st = _abi.pamx_rect(D, k, med, ws, labels=lab, opt=opt, build=medoids is None,
+                                stream=stream)
+    return FitResult(med, lab, td, rc, _stats_dict(st), _trace_list(tbuf, min(st.swaps, cap)))
 
 
 def dist(X, *, metric=None, ld=None, stream=None):

@@ -170,4 +170,32 @@ hipError_t launch_dist_l2_f32(const float *X, int64_t n, int32_t dim, float *D, 
     return hipGetLastError();
 }
 
+// ---- transpose of a rows x cols matrix of 4-byte elements (DT[c][r] =
+// D[r][c]) through 64 x 64 tiles in LDS (one padding column against bank
+// conflicts), both sides read and written along rows.
+__global__ __launch_bounds__(256) void k_transpose(const uint32_t *__restrict__ D, int64_t ld,
+                                                   int64_t rows, int64_t cols,
+                                                   uint32_t *__restrict__ DT, int64_t ldt) {
+    __shared__ uint32_t tile[64][65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t r = r0 + i, c = c0 + tx;
+        if (r < rows && c < cols) tile[i][tx] = D[r * ld + c];
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t c = c0 + i, r = r0 + tx;
+        if (c < cols && r < rows) DT[c * ldt + r] = tile[tx][i];
+    }
+}
+
+hipError_t launch_transpose(const void *D, int64_t ld, int64_t rows, int64_t cols, void *DT,
+                            int64_t ldt, hipStream_t s) {
+    const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64));
+    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, s, static_cast<const uint32_t *>(D), ld,
+                       rows, cols, static_cast<uint32_t *>(DT), ldt);
+    return hipGetLastError();
+}
+
 }  // namespace pamx

@@ -70,9 +70,12 @@ static int32_t auto_chunk(int64_t n, int32_t n_ctiles) {
 }
 
 int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t dtype,
-                int64_t ld, const pamx_options *opt, Layout *L, const void *D) {
+                int64_t ld, const pamx_options *opt, Layout *L, const void *D, int64_t ncand) {
     std::memset(L, 0, sizeof(*L));
+    const bool rect = ncand >= 0;
+    const int64_t nc = rect ? ncand : n;
     L->n = n;
+    L->nc = nc;
     L->k = k;
     L->dtype = dtype;
     L->esz = 4;
@@ -84,14 +87,14 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
                          (reinterpret_cast<uintptr_t>(D) & 15) == 0;
     L->vec = (ldx % 4 == 0 && aligned) ? 4 : 1;
     L->tile = kWG * L->vec;
-    L->n_ctiles = (int32_t)((n + L->tile - 1) / L->tile);
+    L->n_ctiles = (int32_t)((nc + L->tile - 1) / L->tile);
     L->ncp = (int64_t)L->n_ctiles * L->tile;
     int32_t Lc = (opt && opt->chunk > 0) ? opt->chunk : auto_chunk(n, L->n_ctiles);
     if (Lc > n) Lc = (int32_t)n;
     L->L = Lc;
     L->Q = (int32_t)((n + Lc - 1) / Lc);
     L->n_oblk = (int32_t)((n + kObjBlk - 1) / kObjBlk);
-    L->n_mwg = (int32_t)((n + kWG - 1) / kWG);
+    L->n_mwg = (int32_t)((nc + kWG - 1) / kWG);
     const bool p2 = opt && opt->variant == PAMX_FASTPAM2;
     if (opt && opt->variant == PAMX_FASTERPAM) {
         // largest window: the requested width rounded up to whole tiles, else
@@ -117,6 +120,11 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     auto take = [&](size_t bytes) { size_t o = off; off = up256(off + (bytes ? bytes : 1)); return o; };
     L->D = SIZE_MAX;
     L->mean = SIZE_MAX;
+    L->DT = SIZE_MAX;
+    if (rect) {
+        L->ldt = (n + 63) & ~int64_t(63);
+        L->DT = take((size_t)nc * (size_t)L->ldt * 4);
+    }
     if (input_kind == PAMX_INPUT_X) {
         L->D = take((size_t)n * (size_t)L->ld_fit * 4);
         if (dtype == PAMX_F32) L->mean = take((size_t)dim * 4);
@@ -125,7 +133,8 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->sec = take((size_t)n * 4);
     L->dn = take((size_t)n * 4);
     L->ds = take((size_t)n * 4);
-    L->is_med = take((size_t)n);
+    L->is_med = take((size_t)nc);
+    L->mark = take((size_t)nc * 4);
     L->srow = take((size_t)n * 4);
     L->sdn = take((size_t)n * 4);
     L->sds = take((size_t)n * 4);
@@ -485,7 +494,7 @@ int build_impl(const T *D, int64_t ld, const Layout &L, int32_t k, const pamx_op
     if (stats) {
         const int full = k < 2 ? k : 2;
         stats->build_rows = st.build_rows;
-        stats->build_pairs = (int64_t)full * L.n * L.n + st.build_rows * L.n;
+        stats->build_pairs = (int64_t)full * L.n * L.nc + st.build_rows * L.nc;
         if (pool) {
             stats->ms_build_pass = pool->sum(0, full);
             stats->n_build_pass = full;
@@ -634,7 +643,7 @@ int swap_impl(const T *D, int64_t ld, const Layout &L_in, int32_t k, const pamx_
     if (rc) return rc;
     if (st.bad_medoids)
         return fail(PAMX_ERR_INVALID_MEDOIDS, "medoids must be distinct and in [0, n)");
-    const bool searches = k >= 2 && k < n;
+    const bool searches = k >= 2 && k < L.nc;
     const bool scan = opt.variant == PAMX_FASTERPAM;
     if (scan) set_window(&L);   // the window passes have their own chunking
     if (searches) HIP_TRY(enqueue_swap_caches<T>(D, ld, L, medoids, ws, s));
@@ -705,10 +714,10 @@ int swap_impl(const T *D, int64_t ld, const Layout &L_in, int32_t k, const pamx_
     if (stats) {
         stats->iterations = st.iter;
         stats->swaps = st.swaps;
-        stats->converged = (k >= 2 && k < n) ? (st.done && !st.capped) : 1;
+        stats->converged = searches ? (st.done && !st.capped) : 1;
         stats->rescored = st.rescored;
         stats->td = st.td;
-        stats->pass_pairs = (int64_t)st.iter * n * (n - k);
+        stats->pass_pairs = (int64_t)st.iter * n * (L.nc - k);
         stats->ms_swap_pass = ms_pass;
         stats->n_swap_pass = n_pass;
         stats->chunk = L.L;
@@ -977,6 +986,119 @@ extern "C" int pamx_clarans(const void *D, int32_t dtype, int64_t n, int64_t ld,
         stats->ms_total = tm.ms(0, 4);
     }
     return rc;
+}
+
+// ---------------------------------------------------------------- bichromatic medoids
+static int rect_args(const void *D, int32_t dtype, int64_t nco, int64_t nl, int64_t ld, int32_t k,
+                     const pamx_options *opt, const int32_t *medoids) {
+    if (nco < 1 || nco > (int64_t)INT32_MAX - 1) return fail(PAMX_ERR_ARG, "n_cons out of range");
+    if (nl < 1 || nl > (int64_t)INT32_MAX - 1) return fail(PAMX_ERR_ARG, "n_loc out of range");
+    int rc = check_common(nl, k, dtype, opt);
+    if (rc) return rc;
+    rc = check_matrix(D, nl, ld);
+    if (rc) return rc;
+    if (nco > ((int64_t)1 << 62) / ld) return fail(PAMX_ERR_ARG, "n_cons * ld overflows");
+    if (!medoids) return fail(PAMX_ERR_ARG, "medoids is NULL");
+    if (opt) {
+        if (opt->variant != PAMX_FASTPAM1)
+            return fail(PAMX_ERR_UNSUPPORTED, "a consumers x locations matrix runs FastPAM1 only");
+        if (opt->dist_mode != PAMX_DIST_STORED || opt->chunk == PAMX_CHUNK_TUNE)
+            return fail(PAMX_ERR_UNSUPPORTED, "no BF16 form or chunk tuning for a rectangular matrix");
+        if (opt->trace_cap > 0 && !opt->trace) return fail(PAMX_ERR_ARG, "trace_cap > 0 needs a trace array");
+    }
+    return PAMX_OK;
+}
+
+extern "C" int pamx_rect_workspace_bytes(int64_t n_cons, int64_t n_loc, int32_t k, int32_t dtype,
+                                         const pamx_options *opt, size_t *bytes) {
+    if (!bytes) return fail(PAMX_ERR_ARG, "bytes is NULL");
+    int32_t dummy = 0;
+    int rc = rect_args(reinterpret_cast<const void *>(256), dtype, n_cons, n_loc, n_loc, k, opt,
+                       &dummy);
+    if (rc) return rc;
+    Layout L;
+    make_layout(n_cons, k, 0, PAMX_INPUT_D, dtype, (n_loc + 3) & ~int64_t(3), opt, &L, nullptr,
+                n_loc);
+    const size_t b4 = layout_need(L, opt);
+    make_layout(n_cons, k, 0, PAMX_INPUT_D, dtype, (n_loc % 4) ? n_loc : n_loc + 1, opt, &L,
+                nullptr, n_loc);
+    const size_t b1 = layout_need(L, opt);
+    *bytes = b4 > b1 ? b4 : b1;
+    return PAMX_OK;
+}
+
+// BUILD (if `build`) and FastPAM1 SWAP on an n_cons x n_loc matrix.
+static int rect_impl(const void *D, int32_t dtype, int64_t nco, int64_t nl, int64_t ld, int32_t k,
+                     const pamx_options *opt_in, bool build, int32_t *medoids, int32_t *labels,
+                     double *td, pamx_stats *stats, void *ws, size_t ws_bytes, void *stream) {
+    pamx_options opt;
+    pamx_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    int rc = rect_args(D, dtype, nco, nl, ld, k, &opt, medoids);
+    if (rc) return rc;
+    opt.build_exclude_self = 0;   // no candidate is an object
+    Layout L;
+    make_layout(nco, k, 0, PAMX_INPUT_D, dtype, ld, &opt, &L, D, nl);
+    rc = check_ws(ws, ws_bytes, L, &opt);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    Timer tm;
+    tm.rec(0, s);
+    // the locations' distances to all consumers, one row per location
+    HIP_TRY(launch_transpose(D, ld, nco, nl, static_cast<char *>(ws) + L.DT, L.ldt, s));
+    tm.rec(1, s);
+    double td_build = 0.0;
+    pamx_stats bst;
+    std::memset(&bst, 0, sizeof(bst));
+    if (build) {
+        if (dtype == PAMX_F32)
+            rc = build_impl<float>(static_cast<const float *>(D), ld, L, k, opt, medoids, &td_build,
+                                   ws, s, &bst);
+        else
+            rc = build_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, opt, medoids,
+                                     &td_build, ws, s, &bst);
+        if (rc) return rc;
+    }
+    if (dtype == PAMX_F32)
+        rc = swap_impl<float>(static_cast<const float *>(D), ld, L, k, opt, medoids, labels, td,
+                              stats, ws, s, tm);
+    else
+        rc = swap_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, opt, medoids, labels, td,
+                                stats, ws, s, tm);
+    if (rc < 0) return rc;
+    tm.rec(4, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(PAMX_ERR_HIP, "stream synchronize failed");
+    if (stats) {
+        stats->td_build = td_build;
+        stats->ms_dist = tm.ms(0, 1);
+        stats->ms_build = tm.ms(1, 2);
+        stats->ms_swap = tm.ms(2, 3);
+        stats->ms_total = tm.ms(0, 4);
+        stats->build_pairs = bst.build_pairs;
+        stats->build_rows = bst.build_rows;
+        stats->ms_build_pass = bst.ms_build_pass;
+        stats->n_build_pass = bst.n_build_pass;
+        stats->ms_build_delta = bst.ms_build_delta;
+        stats->n_build_delta = bst.n_build_delta;
+    }
+    return rc;
+}
+
+extern "C" int pamx_fit_rect(const void *D, int32_t dtype, int64_t n_cons, int64_t n_loc,
+                             int64_t ld, int32_t k, const pamx_options *opt, int32_t *medoids,
+                             int32_t *labels, double *td, pamx_stats *stats, void *ws,
+                             size_t ws_bytes, void *stream) {
+    return rect_impl(D, dtype, n_cons, n_loc, ld, k, opt, true, medoids, labels, td, stats, ws,
+                     ws_bytes, stream);
+}
+
+extern "C" int pamx_swap_rect(const void *D, int32_t dtype, int64_t n_cons, int64_t n_loc,
+                              int64_t ld, int32_t k, const pamx_options *opt, int32_t *medoids,
+                              int32_t *labels, double *td, pamx_stats *stats, void *ws,
+                              size_t ws_bytes, void *stream) {
+    return rect_impl(D, dtype, n_cons, n_loc, ld, k, opt, false, medoids, labels, td, stats, ws,
+                     ws_bytes, stream);
 }
 
 // ---------------------------------------------------------------- faster initialisations

@@ -153,7 +153,8 @@ __device__ __forceinline__ A wave_sum(A x) {
 
 // Workspace layout (byte offsets, 256-aligned) for one (n, k, dtype) run.
 struct Layout {
-    int64_t n;
+    int64_t n;           // objects (consumers of a rectangular matrix)
+    int64_t nc;          // candidates (locations); = n for a square matrix
     int32_t k;
     int32_t dtype;
     int32_t vec;         // candidates per lane in pass kernels (4, or 1 if ld % 4)
@@ -180,6 +181,9 @@ struct Layout {
     size_t P, slot_v, slot_c;
     size_t list, list_v, list_i, rlist;
     size_t cl_v, cl_i;   // FastCLARANS: changes and slots of a window of draws
+    size_t mark;         // medoid check: one counter per candidate
+    size_t DT;           // rectangular matrix: its transpose (candidate rows), or SIZE_MAX
+    int64_t ldt;         // row stride of DT
     size_t state;
     size_t head;         // end of the regions that do not depend on the chunk length
     size_t total;
@@ -187,8 +191,13 @@ struct Layout {
 };
 
 // host helpers (pamx_api.cpp)
+// ncand >= 0: a rectangular n x ncand matrix (objects x candidates), whose
+// transpose the workspace holds; else square (ncand = n)
 int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t dtype,
-                int64_t ld, const pamx_options *opt, Layout *L, const void *D);
+                int64_t ld, const pamx_options *opt, Layout *L, const void *D,
+                int64_t ncand = -1);
+hipError_t launch_transpose(const void *D, int64_t ld, int64_t rows, int64_t cols, void *DT,
+                            int64_t ldt, hipStream_t s);
 // re-place the chunk-dependent regions (after L->head) for chunk length Lc
 void set_chunk(Layout *L, int32_t Lc);
 // FasterPAM: place them for the window pass (chunk fwL, fw partial columns)

@@ -85,7 +85,7 @@ __global__ void k_state_init(DevState *st, int32_t max_iter, int32_t trace_cap) 
 // TD change of adding c (self-term included); medoids have dn = 0 and add 0.
 template <typename T, int VEC>
 __global__ __launch_bounds__(kWG) void k_build_pass(const T *__restrict__ D, int64_t ld, int64_t n,
-                                                    const T *__restrict__ dn, int32_t L,
+                                                    int64_t nc, const T *__restrict__ dn, int32_t L,
                                                     int64_t ncp, AccT<T> *__restrict__ part) {
     using A = AccT<T>;
     constexpr int U = 8;
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kWG) void k_build_pass(const T *__restrict__ D, int
     A acc[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) acc[e] = 0;
-    if (c0 < n) {
+    if (c0 < nc) {
         int64_t o = a;
         for (; o + U <= b; o += U) {
             T v[U][VEC];
@@ -133,13 +133,15 @@ __global__ __launch_bounds__(kWG) void k_build_pass(const T *__restrict__ D, int
 
 // The step's medoid (every block reduces the merge partials itself: the
 // smallest change, smallest index on ties; block 0 records it), then
-// dn2 = min(dn, row m_t) and, per block of kObjBlk objects, how many dropped.
+// dn2 = min(dn, row m_t of Dl) and, per block of kObjBlk objects, how many
+// dropped.  Dl holds a candidate's distances to all objects in a row: D
+// itself when D is symmetric, else its transpose.
 // FIRST: step 0, dn2 = row m_t (dn is +inf), no counts needed.
 template <typename T, bool FIRST>
 __global__ __launch_bounds__(kObjBlk) void k_build_select_update(
     const AccT<T> *__restrict__ wg_v, const int32_t *__restrict__ wg_c, int32_t nwg, int32_t t,
-    int32_t *__restrict__ medoids, uint8_t *__restrict__ is_med, const T *__restrict__ D,
-    int64_t ld, int64_t n, const T *__restrict__ dn, T *__restrict__ dn2,
+    int32_t *__restrict__ medoids, uint8_t *__restrict__ is_med, const T *__restrict__ Dl,
+    int64_t ldl, int64_t n, const T *__restrict__ dn, T *__restrict__ dn2,
     DevState *__restrict__ st, int32_t *__restrict__ blkcnt) {
     using A = AccT<T>;
     A v = VT<T>::acc_inf();
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(kObjBlk) void k_build_select_update(
         const T old = dn[o];
         T nw = old;
         if (c != INT_MAX) {
-            const T d = D[(int64_t)c * ld + o];
+            const T d = Dl[(int64_t)c * ldl + o];
             nw = FIRST ? d : vmin(old, d);
         }
         dn2[o] = nw;
@@ -221,7 +223,7 @@ __global__ __launch_bounds__(kObjBlk) void k_build_compact(const T *__restrict__
 
 // Per candidate and chunk of the list: sum of min(d, new) - min(d, old).
 template <typename T, int VEC>
-__global__ __launch_bounds__(kWG) void k_build_delta(const T *__restrict__ D, int64_t ld, int64_t n,
+__global__ __launch_bounds__(kWG) void k_build_delta(const T *__restrict__ D, int64_t ld, int64_t nc,
                                                      const int32_t *__restrict__ chg_o,
                                                      const T *__restrict__ chg_old,
                                                      const T *__restrict__ chg_new,
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(kWG) void k_build_delta(const T *__restrict__ D, in
     A acc[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) acc[e] = 0;
-    if (c0 < n) {
+    if (c0 < nc) {
         int64_t j = a;
         for (; j + U <= b; j += U) {
             T v[U][VEC];
@@ -270,7 +272,7 @@ __global__ __launch_bounds__(kWG) void k_build_delta(const T *__restrict__ D, in
 // best (value, candidate) among non-medoids.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_build_dmerge(const AccT<T> *__restrict__ part, int32_t Q,
-                                                      int64_t ncp, int64_t n, AccT<T> *__restrict__ acur,
+                                                      int64_t ncp, int64_t nc, AccT<T> *__restrict__ acur,
                                                       const T *__restrict__ dn,
                                                       const uint8_t *__restrict__ is_med,
                                                       int32_t add_self, AccT<T> *__restrict__ wg_v,
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(kWG) void k_build_dmerge(const AccT<T> *__restrict_
     const int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x;
     A v = VT<T>::acc_inf();
     int ci = INT_MAX;
-    if (c < n) {
+    if (c < nc) {
         A s = 0;
         const A *pc = part + c;
         int q = 0;
@@ -320,6 +322,15 @@ __global__ __launch_bounds__(1024) void k_td_sum(const T *__restrict__ dn, int64
     }
 }
 
+// Rows of the candidates' distances to all objects: the transposed copy in
+// the workspace for a rectangular (bichromatic) matrix, else D (symmetric).
+template <typename T>
+static const T *loc_rows(const T *D, int64_t ld, const Layout &L, void *ws, int64_t *ldl) {
+    if (L.DT == SIZE_MAX) { *ldl = ld; return D; }
+    *ldl = L.ldt;
+    return reinterpret_cast<const T *>(static_cast<char *>(ws) + L.DT);
+}
+
 // BUILD: the first two steps read the whole matrix (column sums, then A for
 // the first medoid's dn); every later step is incremental.  The SWAP-only
 // buffers of the workspace serve as scratch: ds is the second dn buffer,
@@ -329,7 +340,9 @@ hipError_t run_build(const T *D, int64_t ld, const Layout &L, int32_t k, int32_t
                      int32_t *medoids, void *ws, hipStream_t s, hipEvent_t *ev) {
     using A = AccT<T>;
     char *w = static_cast<char *>(ws);
-    const int64_t n = L.n;
+    const int64_t n = L.n, nc = L.nc;
+    int64_t ldl;
+    const T *Dl = loc_rows<T>(D, ld, L, ws, &ldl);
     T *dnb[2] = {reinterpret_cast<T *>(w + L.dn), reinterpret_cast<T *>(w + L.ds)};
     uint8_t *is_med = reinterpret_cast<uint8_t *>(w + L.is_med);
     A *part = reinterpret_cast<A *>(w + L.part);
@@ -344,7 +357,7 @@ hipError_t run_build(const T *D, int64_t ld, const Layout &L, int32_t k, int32_t
     const unsigned nblk = (unsigned)L.n_oblk;
 
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, 0, 0);
-    fill<uint8_t>(is_med, n, 0, s);
+    fill<uint8_t>(is_med, nc, 0, s);
     fill<T>(dnb[0], n, VT<T>::inf(), s);
     const dim3 pgrid(L.n_ctiles, L.Q);
     int cur = 0;   // dnb[cur] holds dn for the medoids chosen so far
@@ -353,40 +366,40 @@ hipError_t run_build(const T *D, int64_t ld, const Layout &L, int32_t k, int32_t
         if (t < 2) {
             if (ev) (void)hipEventRecord(ev[2 * t], s);
             if (L.vec == 4)
-                hipLaunchKernelGGL((k_build_pass<T, 4>), pgrid, dim3(kWG), 0, s, D, ld, n, dn, L.L,
-                                   L.ncp, part);
+                hipLaunchKernelGGL((k_build_pass<T, 4>), pgrid, dim3(kWG), 0, s, D, ld, n, nc, dn,
+                                   L.L, L.ncp, part);
             else
-                hipLaunchKernelGGL((k_build_pass<T, 1>), pgrid, dim3(kWG), 0, s, D, ld, n, dn, L.L,
-                                   L.ncp, part);
+                hipLaunchKernelGGL((k_build_pass<T, 1>), pgrid, dim3(kWG), 0, s, D, ld, n, nc, dn,
+                                   L.L, L.ncp, part);
             if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
             // a zeroed running sum turns the delta merge into a plain merge
-            fill<A>(acur, n, (A)0, s);
+            fill<A>(acur, nc, (A)0, s);
         } else {
             hipLaunchKernelGGL(k_build_compact<T>, dim3(nblk), dim3(kObjBlk), 0, s,
                                (const T *)dnb[cur ^ 1], dn, n, (const int32_t *)blkcnt,
                                (int32_t)nblk, chg_o, chg_old, chg_new, st);
             if (ev) (void)hipEventRecord(ev[2 * t], s);
             if (L.vec == 4)
-                hipLaunchKernelGGL((k_build_delta<T, 4>), pgrid, dim3(kWG), 0, s, D, ld, n,
+                hipLaunchKernelGGL((k_build_delta<T, 4>), pgrid, dim3(kWG), 0, s, D, ld, nc,
                                    (const int32_t *)chg_o, (const T *)chg_old, (const T *)chg_new,
                                    (const DevState *)st, L.ncp, part);
             else
-                hipLaunchKernelGGL((k_build_delta<T, 1>), pgrid, dim3(kWG), 0, s, D, ld, n,
+                hipLaunchKernelGGL((k_build_delta<T, 1>), pgrid, dim3(kWG), 0, s, D, ld, nc,
                                    (const int32_t *)chg_o, (const T *)chg_old, (const T *)chg_new,
                                    (const DevState *)st, L.ncp, part);
             if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
         }
         hipLaunchKernelGGL(k_build_dmerge<T>, dim3(L.n_mwg), dim3(kWG), 0, s, (const A *)part,
-                           L.Q, L.ncp, n, acur, dn, (const uint8_t *)is_med,
-                           (int32_t)(exclude_self && t > 0), wg_v, wg_c);
+                           L.Q, L.ncp, nc, acur, dn, (const uint8_t *)is_med,
+                           (int32_t)(exclude_self && t > 0 && L.DT == SIZE_MAX), wg_v, wg_c);
         if (t == 0)   // dn is +inf: the new dn is the medoid's row
             hipLaunchKernelGGL((k_build_select_update<T, true>), dim3(nblk), dim3(kObjBlk), 0, s,
                                (const A *)wg_v, (const int32_t *)wg_c, L.n_mwg, t, medoids, is_med,
-                               D, ld, n, dn, dnb[cur ^ 1], st, blkcnt);
+                               Dl, ldl, n, dn, dnb[cur ^ 1], st, blkcnt);
         else
             hipLaunchKernelGGL((k_build_select_update<T, false>), dim3(nblk), dim3(kObjBlk), 0, s,
                                (const A *)wg_v, (const int32_t *)wg_c, L.n_mwg, t, medoids, is_med,
-                               D, ld, n, dn, dnb[cur ^ 1], st, blkcnt);
+                               Dl, ldl, n, dn, dnb[cur ^ 1], st, blkcnt);
         cur ^= 1;
     }
     if (cur == 1)   // leave the final dn where the caches expect it
@@ -812,7 +825,8 @@ __device__ __forceinline__ void pass_tile(
 
 template <typename T, int VEC, bool P2, bool WIN>
 __global__ __launch_bounds__(kWG) void k_swap_pass(
-    const T *__restrict__ D, int64_t ld, int64_t n, int32_t k, const int32_t *__restrict__ srow,
+    const T *__restrict__ D, int64_t ld, int64_t n, int64_t nc, int32_t k,
+    const int32_t *__restrict__ srow,
     const T *__restrict__ sdn, const T *__restrict__ sds, const int32_t *__restrict__ seg_off,
     AccT<T> *__restrict__ cdn, const ChunkInfo *__restrict__ cinfo, int32_t L, int64_t ncp,
     AccT<T> *__restrict__ part, int32_t *__restrict__ part_i, AccT<T> *__restrict__ P,
@@ -826,7 +840,7 @@ __global__ __launch_bounds__(kWG) void k_swap_pass(
             pass_tile<T, VEC, false>(t, blockIdx.y, cb, ce, D, ld, n, srow, sdn, sds, seg_off, cdn,
                                      cinfo, L, ncp, part, part_i, P);
     } else {
-        pass_tile<T, VEC, P2>(blockIdx.x, blockIdx.y, 0, n, D, ld, n, srow, sdn, sds, seg_off, cdn,
+        pass_tile<T, VEC, P2>(blockIdx.x, blockIdx.y, 0, nc, D, ld, n, srow, sdn, sds, seg_off, cdn,
                               cinfo, L, ncp, part, part_i, P);
     }
 }
@@ -838,7 +852,7 @@ __global__ __launch_bounds__(kWG) void k_swap_pass(
 template <typename T, bool P2>
 __global__ __launch_bounds__(kWG) void k_swap_merge(
     const AccT<T> *__restrict__ part, const int32_t *__restrict__ part_i,
-    const ChunkInfo *__restrict__ cinfo, int32_t Q, int64_t n, int32_t k, int64_t ncp,
+    const ChunkInfo *__restrict__ cinfo, int32_t Q, int64_t nc, int32_t k, int64_t ncp,
     const AccT<T> *__restrict__ cdn, const uint8_t *__restrict__ is_med,
     const DevState *__restrict__ st, AccT<T> *__restrict__ P, AccT<T> *__restrict__ cand_a,
     AccT<T> *__restrict__ wg_v, int32_t *__restrict__ wg_i, int32_t *__restrict__ wg_c) {
@@ -848,7 +862,7 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
     A bestv = VT<T>::acc_inf();
     int besti = INT_MAX;
     int cc = INT_MAX;
-    if (c < n) {
+    if (c < nc) {
         A accA = 0;
         int run_s = -1;
         A run_m = 0, run_dn = 0;
@@ -1616,10 +1630,11 @@ hipError_t enqueue_swap_init(const T *D, int64_t ld, const Layout &L, const int3
     const int32_t k = L.k;
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, p.st, opt.max_iter,
                        opt.trace ? opt.trace_cap : 0);
-    fill<uint8_t>(p.is_med, n, 0, s);
-    fill<int32_t>(p.near, n, 0, s);
-    hipLaunchKernelGGL(k_check_medoids, dim3((k + 255) / 256), dim3(256), 0, s, medoids, k, n,
-                       p.near, p.is_med, p.st);
+    int32_t *mark = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + L.mark);
+    fill<uint8_t>(p.is_med, L.nc, 0, s);
+    fill<int32_t>(mark, L.nc, 0, s);
+    hipLaunchKernelGGL(k_check_medoids, dim3((k + 255) / 256), dim3(256), 0, s, medoids, k, L.nc,
+                       mark, p.is_med, p.st);
     if (opt.variant == PAMX_FASTERPAM)
         hipLaunchKernelGGL(k_fp_init, dim3(1), dim3(1), 0, s, p.st, n, (int64_t)L.tile, L.vec,
                            (long long)opt.max_iter * (long long)n);
@@ -1631,8 +1646,10 @@ static hipError_t enqueue_caches(const T *D, int64_t ld, const Layout &L, const 
                                  int32_t *labels, void *ws, hipStream_t s) {
     auto p = ptrs<T>(L, ws);
     const int64_t n = L.n;
-    hipLaunchKernelGGL(k_cache_init<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, D, ld,
-                       n, L.k, medoids, p.near, p.sec, p.dn, p.ds, labels);
+    int64_t ldl;
+    const T *Dl = loc_rows<T>(D, ld, L, ws, &ldl);
+    hipLaunchKernelGGL(k_cache_init<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Dl,
+                       ldl, n, L.k, medoids, p.near, p.sec, p.dn, p.ds, labels);
     return hipGetLastError();
 }
 
@@ -1663,7 +1680,7 @@ static void enqueue_pass(const T *D, int64_t ld, const Layout &L, const SwapPtrs
     const int64_t cols = win ? L.fw : L.ncp;
 #define PAMX_PASS(VEC, P2, WIN)                                                               \
     hipLaunchKernelGGL((k_swap_pass<T, VEC, P2, WIN>), pgrid, dim3(kWG), 0, s, D, ld, L.n,   \
-                       L.k, (const int32_t *)p.srow, (const T *)p.sdn, (const T *)p.sds,      \
+                       L.nc, L.k, (const int32_t *)p.srow, (const T *)p.sdn, (const T *)p.sds, \
                        (const int32_t *)p.seg_off, p.cdn,                                     \
                        (const ChunkInfo *)p.cinfo, L.L, cols, p.part, p.part_i, p.P,          \
                        (const DevState *)p.st)
@@ -1733,7 +1750,7 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
     if (p2) {
         hipLaunchKernelGGL((k_swap_merge<T, true>), dim3(L.n_mwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
-                           L.Q, n, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
+                           L.Q, L.nc, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
                            (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
         hipLaunchKernelGGL(k_slot_best<T>, dim3(k), dim3(256), 0, s, (const A *)p.P,
                            (const A *)p.cand_a, (const int32_t *)p.seg_off, n, L.ncp,
@@ -1744,11 +1761,14 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
     } else {
         hipLaunchKernelGGL((k_swap_merge<T, false>), dim3(L.n_mwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
-                           L.Q, n, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
+                           L.Q, L.nc, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
                            (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
+        int64_t ldl;
+        const T *Dl = loc_rows<T>(D, ld, L, ws, &ldl);
         hipLaunchKernelGGL(k_select_update<T>, dim3(ob), dim3(256), 0, s, (const A *)p.wg_v,
-                           (const int32_t *)p.wg_i, (const int32_t *)p.wg_c, L.n_mwg, D, ld, n,
+                           (const int32_t *)p.wg_i, (const int32_t *)p.wg_c, L.n_mwg, Dl, ldl, n,
                            medoids, p.is_med, p.near, p.sec, p.dn, p.ds, p.rlist, p.st, trace);
+        // the rescan reads row o of D at the medoid columns (consumer rows)
         hipLaunchKernelGGL(k_cache_rescan<T>, dim3(256), dim3(256), 0, s, D, ld, k,
                            (const int32_t *)medoids, p.near, p.sec, p.dn, p.ds,
                            (const int32_t *)p.rlist, (const DevState *)p.st);

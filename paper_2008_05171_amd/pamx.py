@@ -63,7 +63,7 @@ class pamx_batch_stats(ctypes.Structure):
 EXPORTS = ("pamx_default_options", "pamx_workspace_bytes", "pamx_dist", "pamx_build",
            "pamx_swap", "pamx_fit", "pamx_batched_workspace_bytes", "pamx_fit_batched",
            "pamx_init_workspace_bytes", "pamx_init_dw", "pamx_init_lab", "pamx_clarans",
-           "pamx_last_error")
+           "pamx_rect_workspace_bytes", "pamx_fit_rect", "pamx_swap_rect", "pamx_last_error")
 
 
 class PamxError(RuntimeError):
@@ -103,11 +103,15 @@ def load(path: str = LIB_PATH):
     lib.pamx_init_lab.argtypes = [P, i32, i64, i64, i32, P, i32, i32, P, P, sz, P]
     lib.pamx_clarans.argtypes = [P, i32, i64, i64, i32, P, i64, i64, opt_p, P, P, dbl_p, st_p, P,
                                  sz, P]
+    lib.pamx_rect_workspace_bytes.argtypes = [i64, i64, i32, i32, opt_p, ctypes.POINTER(sz)]
+    lib.pamx_fit_rect.argtypes = [P, i32, i64, i64, i64, i32, opt_p, P, P, dbl_p, st_p, P, sz, P]
+    lib.pamx_swap_rect.argtypes = [P, i32, i64, i64, i64, i32, opt_p, P, P, dbl_p, st_p, P, sz, P]
     lib.pamx_last_error.argtypes = []
     lib.pamx_last_error.restype = ctypes.c_char_p
     for name in ("pamx_workspace_bytes", "pamx_dist", "pamx_build", "pamx_swap", "pamx_fit",
                  "pamx_batched_workspace_bytes", "pamx_fit_batched", "pamx_init_workspace_bytes",
-                 "pamx_init_dw", "pamx_init_lab", "pamx_clarans"):
+                 "pamx_init_dw", "pamx_init_lab", "pamx_clarans", "pamx_rect_workspace_bytes",
+                 "pamx_fit_rect", "pamx_swap_rect"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -270,4 +274,27 @@ def pamx_clarans(D, k, draws, maxneighbor, medoids, ws, labels=None, opt=None, n
                                     ctypes.byref(opt) if opt is not None else None, _ptr(medoids),
                                     _ptr(labels), ctypes.byref(td), ctypes.byref(st), _ptr(ws),
                                     ws.numel() * ws.element_size(), _stream(stream)))
+    return rc, td.value, st
+
+
+def pamx_rect_workspace_bytes(n_cons, n_loc, k, dtype, opt=None) -> int:
+    out = ctypes.c_size_t()
+    _check(load().pamx_rect_workspace_bytes(int(n_cons), int(n_loc), int(k), int(dtype),
+                                            ctypes.byref(opt) if opt is not None else None,
+                                            ctypes.byref(out)))
+    return int(out.value)
+
+
+def pamx_rect(D, k, medoids, ws, labels=None, opt=None, build=True, ld=None, stream=None):
+    """D: device (n_cons, n_loc) matrix (row stride ld); build=False starts
+    from `medoids` (pamx_swap_rect), else pamx_fit_rect."""
+    nco, nl = D.shape
+    ld = D.stride(0) if ld is None else ld
+    td = ctypes.c_double()
+    st = pamx_stats()
+    f = load().pamx_fit_rect if build else load().pamx_swap_rect
+    rc = _check(f(_ptr(D), _dtype_code(D), int(nco), int(nl), int(ld), int(k),
+                  ctypes.byref(opt) if opt is not None else None, _ptr(medoids), _ptr(labels),
+                  ctypes.byref(td), ctypes.byref(st), _ptr(ws), ws.numel() * ws.element_size(),
+                  _stream(stream)))
     return rc, td.value, st

@@ -184,6 +184,30 @@ def test_clarans_argument_errors(lib):
     assert call(wsb=64) == abi.PAMX_ERR_WORKSPACE
 
 
+def test_rect_argument_errors(lib):
+    fake = ctypes.c_void_p(0x100000)
+    ws = ctypes.c_void_p(0x200000)
+
+    def call(f, D=fake, nco=500, nl=300, ld=300, k=5, opt=None, med=fake, wsb=1 << 30):
+        return f(D, abi.PAMX_F32, nco, nl, ld, k, ctypes.byref(opt) if opt else None, med, None,
+                 None, None, ws, wsb, None)
+    for f in (lib.pamx_fit_rect, lib.pamx_swap_rect):
+        assert call(f, D=None) == abi.PAMX_ERR_ARG
+        assert call(f, nco=0) == abi.PAMX_ERR_ARG
+        assert call(f, k=301) == abi.PAMX_ERR_ARG
+        assert call(f, ld=299) == abi.PAMX_ERR_ARG
+        assert call(f, med=None) == abi.PAMX_ERR_ARG
+        for v in (abi.PAMX_FASTPAM2, abi.PAMX_FASTERPAM):
+            o = abi.pamx_default_options()
+            o.variant = v
+            assert call(f, opt=o) == abi.PAMX_ERR_UNSUPPORTED
+        assert call(f, wsb=64) == abi.PAMX_ERR_WORKSPACE
+    a = abi.pamx_rect_workspace_bytes(20000, 500, 50, abi.PAMX_F32)
+    assert a > 500 * 20032 * 4                 # holds the transposed matrix
+    with pytest.raises(abi.PamxError):
+        abi.pamx_rect_workspace_bytes(20000, 500, 501, abi.PAMX_F32)
+
+
 def test_points_metric_rules(lib):
     fake = ctypes.c_void_p(0x100000)
     rc = lib.pamx_dist(fake, abi.PAMX_I32, 10, 2, abi.PAMX_L2, fake, 12, None, 0, None)

@@ -1,0 +1,131 @@
+"""GPU parity of bichromatic medoids (Sec. 5): consumers x locations matrices.
+
+Integer matrices: BUILD + FastPAM1 on the GPU equal the oracle's BUILD + PAM
+(reading R17) bit for bit -- medoids, labels, TD, BUILD TD and the swap
+trajectory -- for more or fewer locations than consumers, an unaligned row
+stride, tie-heavy values and degenerate sizes; on a square symmetric matrix
+they equal the one-set path.  Float matrices: BUILD and the trajectory equal
+the oracle's on the same FP32 values, and the result is certified a local
+optimum by an FP64 numpy check of every swap.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_05171_amd import datagen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def px():
+    import paper_2008_05171_amd as m
+    return m
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _two_sets(nc, nl, seed, hi=1000, dim=2, metric=oracle.L1, float_pts=False):
+    """Consumers and locations drawn separately; D[c][l] by the oracle's metric."""
+    if float_pts:
+        C = datagen.gaussian_mixture(nc, dim, 8, seed=seed)
+        Lp = datagen.gaussian_mixture(nl, dim, 8, seed=seed + 1)
+    else:
+        C = datagen.int_points(nc, dim, 0, hi, seed=seed)
+        Lp = datagen.int_points(nl, dim, 0, hi, seed=seed + 1)
+    Z = np.concatenate([C, Lp]).astype(np.float64)
+    return oracle.dist_matrix(Z, metric)[:nc, nc:]
+
+
+def _check_same(res, ref):
+    assert list(res.medoids.cpu().numpy()) == list(ref.medoids)
+    assert np.array_equal(res.labels.cpu().numpy(), ref.labels)
+    assert res.td == ref.td
+    assert res.trace == ref.trace
+
+
+@pytest.mark.parametrize("nc,nl,k,hi,seed", [(1500, 700, 8, 1000, 1), (600, 2000, 12, 1000, 2),
+                                             (1000, 1000, 5, 300, 3), (900, 333, 20, 8, 4),
+                                             (257, 1025, 30, 40, 5), (3000, 1500, 50, 2000, 6)])
+def test_int_fit_bitexact(nc, nl, k, hi, seed):
+    _say("rect_int", nc, nl, k, hi, seed)
+    D = _two_sets(nc, nl, seed, hi=hi)
+    ref = oracle.rect_pam(k, D)
+    res = px().fit_rect(_t(D.astype(np.int32)), k, trace=True)
+    assert res.rc == 0 and res.stats["converged"] == 1
+    assert res.stats["td_build"] == ref.td_build
+    assert res.stats["iterations"] == ref.iterations
+    _check_same(res, ref)
+
+
+def test_unaligned_row_stride():
+    """n_loc = 701 with the rows padded to 703: the 1-wide load path."""
+    _say("rect_unaligned")
+    D = _two_sets(800, 701, 11, hi=500)
+    Dp = np.zeros((800, 703), np.int32)
+    Dp[:, :701] = D
+    ref = oracle.rect_pam(9, D)
+    res = px().fit_rect(_t(Dp)[:, :701], 9, trace=True)
+    _check_same(res, ref)
+
+
+def test_swap_from_given_locations():
+    _say("rect_swap")
+    D = _two_sets(1200, 500, 21, hi=300)
+    start = datagen.random_subset(500, 10, 21)
+    ref = oracle.rect_swap(start, D)
+    res = px().fit_rect(_t(D.astype(np.int32)), 10, medoids=_t(start), trace=True)
+    assert list(res.medoids.cpu().numpy()) == list(ref.medoids) and res.td == ref.td
+    assert res.trace == ref.trace and res.stats["iterations"] == ref.iterations
+
+
+def test_square_symmetric_equals_one_set_path():
+    _say("rect_square")
+    X = datagen.int_points(1000, 2, 0, 1000, seed=31)
+    D = oracle.dist_matrix(X, oracle.L1).astype(np.int32)
+    a = px().fit_rect(_t(D), 6, trace=True)
+    b = px().fit(_t(D), 6, input_kind=px().PAMX_INPUT_D, trace=True)
+    assert torch.equal(a.medoids, b.medoids) and torch.equal(a.labels, b.labels)
+    assert a.td == b.td and a.trace == b.trace and a.stats["td_build"] == b.stats["td_build"]
+
+
+@pytest.mark.parametrize("nc,nl,k", [(1, 40, 1), (1, 40, 3), (50, 7, 7), (50, 7, 1), (300, 2, 2)])
+def test_degenerate_sizes(nc, nl, k):
+    _say("rect_degenerate", nc, nl, k)
+    D = _two_sets(nc, nl, 41 + nc + nl, hi=50)
+    ref = oracle.rect_pam(k, D)
+    res = px().fit_rect(_t(D.astype(np.int32)), k, trace=True)
+    _check_same(res, ref)
+    if k == 1:
+        assert int(res.medoids[0]) == int(np.argmin(D.sum(0)))
+
+
+def test_float_matrix_and_certificate():
+    """FP32 matrix shared by both sides; the final medoids pass an FP64
+    local-optimality check over every (slot, location) swap."""
+    _say("rect_float")
+    nc, nl, k = 2000, 600, 10
+    D = _two_sets(nc, nl, 51, dim=4, metric=oracle.L2, float_pts=True).astype(np.float32)
+    D64 = D.astype(np.float64)
+    ref = oracle.rect_pam(k, D64)
+    res = px().fit_rect(_t(D), k, trace=True)
+    assert list(res.medoids.cpu().numpy()) == list(ref.medoids)
+    assert [(s, c) for s, c, _ in res.trace] == [(s, c) for s, c, _ in ref.trace]
+    assert abs(res.td - ref.td) <= 8 * nc * 2.0 ** -53 * ref.td
+    med = [int(v) for v in res.medoids.cpu().numpy()]
+    dm = D64[:, med]
+    base = dm.min(1).sum()
+    tol = 16 * nc * 2.0 ** -53 * base
+    for i in range(k):
+        other = np.delete(dm, i, axis=1).min(1)
+        new = np.minimum(other[:, None], D64).sum(0)
+        new[med] = np.inf
+        assert new.min() - base >= -tol
