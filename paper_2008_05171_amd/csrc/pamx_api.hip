@@ -278,6 +278,7 @@ int make_rc_layout(int64_t n, int32_t k, int32_t dim, const pamx_options *opt, R
     R->acur = take((size_t)R->ncp * 8);
     R->lold = take((size_t)n * 8);
     R->lnew = take((size_t)n * 8);
+    R->rs_part = take((size_t)4096 * (k + 1) * 8);   // FP64 re-score partials
     R->total = off;
     return PAMX_OK;
 }

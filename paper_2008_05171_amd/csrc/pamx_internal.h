@@ -219,7 +219,7 @@ struct RcLayout {
     int64_t ncp;
     size_t Xb, nb, eo, dn64, ds64, dn32, ds32, sdn, sds, sthr, snb, R64, R32, part, part_i,
         cand_v, cand_b, wg_u, list, res_v, res_i, rlist, near, sec, srow, blkcnt, seg_off, cinfo,
-        is_med, mx, eps0, bnd, mean, state, acur, lold, lnew, total;
+        is_med, mx, eps0, bnd, mean, state, acur, lold, lnew, rs_part, total;
 };
 constexpr int kRcMaxDim = 64;     // precision form: largest point dimension
 constexpr int kRcMaxK = 4096;     // precision form: largest k (per-slot FP64 sums in LDS)

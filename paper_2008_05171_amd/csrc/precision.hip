@@ -487,7 +487,20 @@ __global__ __launch_bounds__(256) void k_rc_mark(const double *__restrict__ cand
 // walks a contiguous range of the sorted objects; segments complete in its
 // range go to LDS directly, the partial first/last ones are combined
 // afterwards in thread order.
-constexpr int kRsT = 256;    // threads per re-scored candidate
+constexpr int kRsT = 256;    // threads per (candidate, object group)
+// A listed candidate's sorted objects are split into G contiguous groups,
+// one work-group each, so that a short list still fills the chip; each group
+// writes its per-slot partial sums and its part of B, and a second kernel
+// adds the groups in order.  At most kRsParts (candidate, group) partials are
+// held at once: G = min(kRsGmax, kRsParts / m), and G = 1 (no partials, the
+// work-group finishes the candidate) for lists longer than kRsParts.
+constexpr int kRsParts = 4096;
+constexpr int kRsGmax = 16;
+
+__device__ __forceinline__ int rs_groups(int m) {
+    const int g = kRsParts / (m > 0 ? m : 1);
+    return g < 1 ? 1 : (g > kRsGmax ? kRsGmax : g);
+}
 
 template <int KS>
 __global__ __launch_bounds__(kRsT) void k_rc_swap_rescore(
@@ -495,19 +508,23 @@ __global__ __launch_bounds__(kRsT) void k_rc_swap_rescore(
     const double *__restrict__ dn64, const double *__restrict__ ds64,
     const int32_t *__restrict__ near, const double *__restrict__ R64,
     const int32_t *__restrict__ list, const DevState *__restrict__ st,
-    double *__restrict__ res_v, int32_t *__restrict__ res_i) {
+    double *__restrict__ res_v, int32_t *__restrict__ res_i, double *__restrict__ rs_part) {
     extern __shared__ __align__(16) unsigned char rs_raw[];
     double *sarr = reinterpret_cast<double *>(rs_raw);          // k per-slot sums
     __shared__ double hv[kRsT], tv[kRsT], red[kRsT];
     __shared__ int hs[kRsT], ts[kRsT], ri[kRsT];
     const int t = threadIdx.x;
     const int m = st->n_list;
-    const int64_t per = (n + kRsT - 1) / kRsT;
-    for (int idx = blockIdx.x; idx < m; idx += gridDim.x) {
+    const int G = rs_groups(m);
+    for (int b = blockIdx.x; b < m * G; b += gridDim.x) {
+        const int idx = b / G, g = b - idx * G;
         const int64_t c = list[idx];
         for (int i = t; i < k; i += kRsT) sarr[i] = 0.0;
         __syncthreads();
-        const int64_t j0 = min(n, (int64_t)t * per), j1 = min(n, j0 + per);
+        // this group's sorted positions, then this thread's part of them
+        const int64_t g0 = n * g / G, g1 = n * (g + 1) / G;
+        const int64_t per = (g1 - g0 + kRsT - 1) / kRsT;
+        const int64_t j0 = min(g1, g0 + (int64_t)t * per), j1 = min(g1, j0 + per);
         double B = 0.0, S = 0.0, first = 0.0;
         int cur = -1, fs = -1;
         for (int64_t j = j0; j < j1; ++j) {
@@ -551,6 +568,13 @@ __global__ __launch_bounds__(kRsT) void k_rc_swap_rescore(
             if (t < w) red[t] += red[t + w];
         }
         __syncthreads();
+        if (G > 1) {   // partial sums of this group; k_rc_rescore_combine finishes
+            double *pp = rs_part + (int64_t)b * (k + 1);
+            for (int i = t; i < k; i += kRsT) pp[i] = sarr[i];
+            if (t == 0) pp[k] = red[0];
+            __syncthreads();
+            continue;
+        }
         // best slot: smallest R_i + S_i, smallest i on ties
         double bv = __builtin_huge_val();
         int bi = INT_MAX;
@@ -569,12 +593,48 @@ __global__ __launch_bounds__(kRsT) void k_rc_swap_rescore(
     }
 }
 
+// Sum of a candidate's group partials in group order, then its best slot.
+__global__ __launch_bounds__(kRsT) void k_rc_rescore_combine(
+    const double *__restrict__ rs_part, int32_t k, const double *__restrict__ R64,
+    const DevState *__restrict__ st, double *__restrict__ res_v, int32_t *__restrict__ res_i) {
+    __shared__ double hv[kRsT];
+    __shared__ int ri[kRsT];
+    const int t = threadIdx.x;
+    const int m = st->n_list;
+    const int G = rs_groups(m);
+    if (G == 1) return;
+    for (int idx = blockIdx.x; idx < m; idx += gridDim.x) {
+        const double *pp = rs_part + (int64_t)idx * G * (k + 1);
+        double bv = __builtin_huge_val();
+        int bi = INT_MAX;
+        for (int i = t; i < k; i += kRsT) {
+            double S = 0.0;
+            for (int g = 0; g < G; ++g) S += pp[(int64_t)g * (k + 1) + i];
+            const double v = R64[i] + S;
+            if (v < bv) { bv = v; bi = i; }
+        }
+        hv[t] = bv; ri[t] = bi;
+        __syncthreads();
+        for (int w = kRsT / 2; w > 0; w >>= 1) {
+            if (t < w && lt2(hv[t + w], ri[t + w], hv[t], ri[t])) { hv[t] = hv[t + w]; ri[t] = ri[t + w]; }
+            __syncthreads();
+        }
+        if (t == 0) {
+            double B = 0.0;
+            for (int g = 0; g < G; ++g) B += pp[(int64_t)g * (k + 1) + k];
+            res_v[idx] = hv[0] + B;
+            res_i[idx] = ri[0];
+        }
+        __syncthreads();
+    }
+}
+
 template <int KS>
 static hipError_t rc_rescore_launch(const float *X, int32_t dim, int64_t n, int32_t k,
                                     const int32_t *srow, const double *dn64, const double *ds64,
                                     const int32_t *near, const double *R64, const int32_t *list,
                                     const DevState *st, double *res_v, int32_t *res_i,
-                                    hipStream_t s) {
+                                    double *rs_part, hipStream_t s) {
     const size_t lds = (size_t)k * 8;   // the per-slot sums, beside 9 KB of fixed LDS
     if (lds > 49152) {
         const hipError_t e = hipFuncSetAttribute((const void *)k_rc_swap_rescore<KS>,
@@ -582,19 +642,22 @@ static hipError_t rc_rescore_launch(const float *X, int32_t dim, int64_t n, int3
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_rc_swap_rescore<KS>), dim3(1024), dim3(kRsT), lds, s, X, dim, n, k,
-                       srow, dn64, ds64, near, R64, list, st, res_v, res_i);
+                       srow, dn64, ds64, near, R64, list, st, res_v, res_i, rs_part);
+    hipLaunchKernelGGL(k_rc_rescore_combine, dim3(1024), dim3(kRsT), 0, s, (const double *)rs_part,
+                       k, R64, st, res_v, res_i);
     return hipGetLastError();
 }
 
 static hipError_t rc_rescore(int KP, const float *X, int32_t dim, int64_t n, int32_t k,
                              const int32_t *srow, const double *dn64, const double *ds64,
                              const int32_t *near, const double *R64, const int32_t *list,
-                             const DevState *st, double *res_v, int32_t *res_i, hipStream_t s) {
+                             const DevState *st, double *res_v, int32_t *res_i, double *rs_part,
+                             hipStream_t s) {
     switch (KP / 16) {
-        case 1: return rc_rescore_launch<1>(X, dim, n, k, srow, dn64, ds64, near, R64, list, st, res_v, res_i, s);
-        case 2: return rc_rescore_launch<2>(X, dim, n, k, srow, dn64, ds64, near, R64, list, st, res_v, res_i, s);
-        case 3: return rc_rescore_launch<3>(X, dim, n, k, srow, dn64, ds64, near, R64, list, st, res_v, res_i, s);
-        default: return rc_rescore_launch<4>(X, dim, n, k, srow, dn64, ds64, near, R64, list, st, res_v, res_i, s);
+        case 1: return rc_rescore_launch<1>(X, dim, n, k, srow, dn64, ds64, near, R64, list, st, res_v, res_i, rs_part, s);
+        case 2: return rc_rescore_launch<2>(X, dim, n, k, srow, dn64, ds64, near, R64, list, st, res_v, res_i, rs_part, s);
+        case 3: return rc_rescore_launch<3>(X, dim, n, k, srow, dn64, ds64, near, R64, list, st, res_v, res_i, rs_part, s);
+        default: return rc_rescore_launch<4>(X, dim, n, k, srow, dn64, ds64, near, R64, list, st, res_v, res_i, rs_part, s);
     }
 }
 
@@ -1006,6 +1069,7 @@ struct RcPtrs {
     uint8_t *is_med;
     DevState *st;
     double *acur, *lold, *lnew;
+    double *rs_part;   // re-score partials of (candidate, object group)
 };
 
 template <int KS, typename ACC>
@@ -1067,6 +1131,7 @@ static RcPtrs rc_ptrs(const RcLayout &R, void *ws) {
     p.list = reinterpret_cast<int32_t *>(w + R.list);
     p.res_v = reinterpret_cast<double *>(w + R.res_v);
     p.res_i = reinterpret_cast<int32_t *>(w + R.res_i);
+    p.rs_part = reinterpret_cast<double *>(w + R.rs_part);
     p.rlist = reinterpret_cast<int32_t *>(w + R.rlist);
     p.near = reinterpret_cast<int32_t *>(w + R.near);
     p.sec = reinterpret_cast<int32_t *>(w + R.sec);
@@ -1238,7 +1303,7 @@ hipError_t rc_swap_iteration(const float *X, int32_t dim, const RcLayout &R, int
                                         (const double *)p.dn64, (const double *)p.ds64,
                                         (const int32_t *)p.near, (const double *)p.R64,
                                         (const int32_t *)p.list, (const DevState *)p.st, p.res_v,
-                                        p.res_i, s);
+                                        p.res_i, p.rs_part, s);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_rc_pick, dim3(1), dim3(1024), 0, s, (const double *)p.res_v,
