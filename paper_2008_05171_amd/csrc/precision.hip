@@ -295,8 +295,11 @@ __device__ __forceinline__ void load_bq(const __bf16 *__restrict__ Xs, int KP, i
     }
 }
 
+// The hardware square root (v_sqrt_f32): within 1 ulp of the exact root for
+// normal arguments and 0 for subnormal ones -- one instruction instead of the
+// correctly rounded sequence; the per-pair bound covers both (k_rc_iter_bounds).
 __device__ __forceinline__ float rc_dist(float g, float no, float nc) {
-    return sqrtf(fmaxf(fmaf(-2.0f, g, no + nc), 0.0f));
+    return __builtin_amdgcn_sqrtf(fmaxf(fmaf(-2.0f, g, no + nc), 0.0f));
 }
 
 // ---------------------------------------------------------------- SWAP pass
@@ -861,7 +864,9 @@ __global__ __launch_bounds__(1024) void k_rc_iter_bounds(const double *__restric
     if (t == 0) {
         const double rm = r1[0];
         const double thr = (dsmax + eps0[0]) * (1.0 + 0x1p-20);
-        const double small = 0x1p-22 * thr + 3.0 * 0x1p-24 * thr;   // sqrt rounding, FP32 terms
+        // FP32 terms and the hardware square root: 2 ulp of the root, plus
+        // 2^-62 for a subnormal argument, whose root is returned as 0
+        const double small = 0x1p-22 * thr + 3.0 * 0x1p-24 * thr + 0x1p-62;
         bnd[0] = eps0[1] + small;
         bnd[1] = eps0[0] + small;
         const double chain = acc64 ? ((double)L + Q + 64.0) * 0x1p-52
