@@ -4,8 +4,9 @@
 //  * k_dist_l1_i32 : exact Manhattan distances of int32 points (VALU).
 //  * k_dist_l2_f32 : Euclidean distances d = sqrt(max(|x|^2 + |y|^2 - 2 x.y, 0))
 //                    of mean-centred points, the Gram term x.y on the FP32 matrix cores
-//                    (v_mfma_f32_32x32x2_f32), 64 x 64 tiles staged in LDS and
-//                    written back as full 256-byte row segments.
+//                    (v_mfma_f32_32x32x2_f32), the root by the hardware instruction
+//                    (within 1 ulp; its error is small beside the Gram term's), 64 x 64
+//                    tiles staged in LDS and written back as full 256-byte row segments.
 //  Both write a zero diagonal and are bitwise symmetric.
 #include "pamx_internal.h"
 
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32(const float *__restrict__ X
             const int r = wr + 8 * (v >> 2) + 4 * h + (v & 3);
             const int c = wc + j;
             const float s = (na[r] + nb[c]) - 2.0f * acc[v];
-            float d = sqrtf(fmaxf(s, 0.0f));
+            float d = __builtin_amdgcn_sqrtf(fmaxf(s, 0.0f));   // within 1 ulp; subnormals to 0
             if (r0 + r == c0 + c) d = 0.0f;
             tile[r * (kT + 4) + c] = d;
         }
