@@ -157,6 +157,7 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->rlist = take((size_t)n * 4);
     L->cl_v = take(1024 * 8);
     L->cl_i = take(1024 * 4);
+    L->egred = p2 ? take(2 * 1024 * 8) : SIZE_MAX;
     L->state = take(sizeof(DevState));
     L->head = off;
     set_chunk(L, L->L);
@@ -638,6 +639,9 @@ int swap_impl(const T *D, int64_t ld, const Layout &L_in, int32_t k, const pamx_
               hipStream_t s, Timer &tm) {
     Layout L = L_in;
     const int64_t n = L.n;
+    // FastPAM2: the eager apply runs over the whole chip where the device
+    // has cooperative launch (such searches are not captured in a graph)
+    if (opt.variant == PAMX_FASTPAM2 && L.egred != SIZE_MAX) L.eg = eager_grid(n, L.dtype);
     HIP_TRY(enqueue_swap_init<T>(D, ld, L, medoids, opt, ws, s));
     DevState st;
     int rc = read_state(L, ws, s, &st);
@@ -665,7 +669,7 @@ int swap_impl(const T *D, int64_t ld, const Layout &L_in, int32_t k, const pamx_
         }
         SearchGraph *g = nullptr;
         hipStream_t xs = s;   // stream the searches run on
-        if (opt.graph && !opt.profile) {
+        if (opt.graph && !opt.profile && L.eg == 0) {
             hipStream_t gs = graph_stream();
             if (!gs) return fail(PAMX_ERR_HIP, "could not create the library stream");
             rc = search_graph<T>(D, ld, L, medoids, opt, ws, gs, &g);

@@ -167,6 +167,7 @@ struct Layout {
     int32_t n_mwg;       // merge work-groups = ceil(n / kWG)
     int32_t fw;          // FasterPAM: largest window (a multiple of tile), or 0
     int32_t fwL, fwQ;    // FasterPAM: object chunk length and count of the window pass
+    int32_t eg;          // FastPAM2: grid of the cooperative eager apply, 0 = one work-group
     size_t esz;          // element size of D (4)
     size_t asz;          // accumulator size (8)
     // offsets
@@ -182,6 +183,7 @@ struct Layout {
     size_t list, list_v, list_i, rlist;
     size_t cl_v, cl_i;   // FastCLARANS: changes and slots of a window of draws
     size_t mark;         // medoid check: one counter per candidate
+    size_t egred;        // FastPAM2: per-work-group re-score sums of the eager apply
     size_t DT;           // rectangular matrix: its transpose (candidate rows), or SIZE_MAX
     int64_t ldt;         // row stride of DT
     size_t state;
@@ -196,6 +198,9 @@ struct Layout {
 int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t dtype,
                 int64_t ld, const pamx_options *opt, Layout *L, const void *D,
                 int64_t ncand = -1);
+// Grid for the cooperative FastPAM2 eager apply over n objects on the
+// current device (0: the device has no cooperative launch).
+int32_t eager_grid(int64_t n, int32_t dtype);
 hipError_t launch_transpose(const void *D, int64_t ld, int64_t rows, int64_t cols, void *DT,
                             int64_t ldt, hipStream_t s);
 // re-place the chunk-dependent regions (after L->head) for chunk length Lc

@@ -26,6 +26,8 @@
 // uniform.  Segments cut by a chunk edge leave partial sums ("carries") that
 // a merge kernel adds in chunk order: every sum is formed in a fixed order,
 // so results are deterministic.
+#include <hip/hip_cooperative_groups.h>
+
 #include "pamx_internal.h"
 
 namespace pamx {
@@ -1580,6 +1582,151 @@ __global__ __launch_bounds__(1024) void k_eager_apply(
     }
 }
 
+// ---- FastPAM2 eager application over the whole chip (cooperative launch).
+// The same visits, re-scores and decisions as k_eager_apply, with the
+// objects spread over the grid: thread (b, t) owns objects b*256 + t +
+// j*256*G, so an object's caches are read and written by one thread (its
+// rescan by a wave of the same work-group) and need no exchange.  Per visit:
+//   1. every work-group sums Eq. change over its objects (fixed tree order)
+//      and writes the sum to red[parity][b];
+//   2. grid barrier; every work-group adds red[parity][0..G) in one fixed
+//      order, so all take the same decision on the same value;
+//   3. if the swap is applied, work-group 0 records it (medoids, TD, trace),
+//      grid barrier, then every work-group updates its objects (O(1) rule,
+//      wave rescans of those that lost their nearest or second medoid).
+// The partials alternate between two halves of red, so a work-group still
+// reading one visit's sums is never overtaken by the next visit's writes
+// (a barrier lies between).  Loops and branches are uniform over the grid:
+// every work-group reaches every barrier.
+constexpr int kEgT = 256;       // threads (and objects per round) of a work-group
+constexpr int kEgMax = 1024;    // largest grid (red holds 2 * kEgMax sums)
+template <typename T>
+__global__ __launch_bounds__(kEgT) void k_eager_grid(
+    const T *__restrict__ D, int64_t ld, int64_t n, int32_t k, int32_t *__restrict__ med,
+    uint8_t *__restrict__ is_med, int32_t *__restrict__ near, int32_t *__restrict__ sec,
+    T *__restrict__ dn, T *__restrict__ ds, const AccT<T> *__restrict__ slot_v,
+    const int32_t *__restrict__ slot_c, int32_t *__restrict__ order, AccT<T> *__restrict__ red,
+    DevState *__restrict__ st, pamx_swap_record *__restrict__ trace) {
+    using A = AccT<T>;
+    namespace cg = cooperative_groups;
+    cg::grid_group grid = cg::this_grid();
+    // read by every work-group before its first barrier; written only after
+    // the last one
+    if (st->done) return;
+    __shared__ int32_t rl[kEgT];
+    __shared__ int32_t nres;
+    __shared__ A tot_s;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int G = gridDim.x;
+    A thr;
+    if constexpr (std::is_same<T, float>::value) thr = -st->margin; else thr = 0;
+    // rank the negative slots by (value, slot), spread over the grid; every
+    // work-group counts them itself
+    int cnt = 0;
+    for (int i = blockIdx.x * kEgT + t; i < k; i += G * kEgT) {
+        const A vi = slot_v[i];
+        if (!(slot_c[i] != INT_MAX && vi < thr)) continue;
+        int r = 0;
+        for (int j = 0; j < k; ++j) {
+            const A vj = slot_v[j];
+            if (slot_c[j] != INT_MAX && vj < thr && lt2(vj, j, vi, i)) ++r;
+        }
+        order[r] = i;
+    }
+    for (int i = t; i < k; i += kEgT) cnt += (slot_c[i] != INT_MAX && slot_v[i] < thr) ? 1 : 0;
+    const int m = block_sum<int, kEgT>(cnt);
+    grid.sync();
+    const int64_t stride = (int64_t)G * kEgT;
+    const int64_t o0 = (int64_t)blockIdx.x * kEgT + t;
+    int applied = 0, par = 0;
+    for (int r = 0; r < m; ++r) {
+        const int i = order[r];
+        const int c = slot_c[i];
+        if (is_med[c]) continue;   // same byte for every thread of the grid
+        const T *rowc = D + (int64_t)c * ld;
+        A s = 0;
+        for (int64_t o = o0; o < n; o += stride) {
+            const T d = rowc[o];
+            const T a = dn[o];
+            if (near[o] == i) s += (A)vmin(d, ds[o]) - (A)a;   // cases (b1), (b2)
+            else s += (A)vmin(d, a) - (A)a;                    // cases (a), (c)
+        }
+        s = block_sum<A, kEgT>(s);
+        A *rb = red + (int64_t)par * kEgMax;
+        par ^= 1;
+        if (t == 0) rb[blockIdx.x] = s;
+        grid.sync();
+        if (wv == 0) {
+            A x = 0;
+            for (int j = lane; j < G; j += 64) x += rb[j];
+            for (int w = 32; w >= 1; w >>= 1) x += __shfl_xor(x, w);   // same sum in every lane
+            if (lane == 0) tot_s = x;
+        }
+        __syncthreads();
+        const A tot = tot_s;
+        if (!(tot < thr)) continue;
+        if (blockIdx.x == 0 && t == 0) {
+            const int old = med[i];
+            is_med[old] = 0;
+            is_med[c] = 1;
+            med[i] = c;
+            if constexpr (std::is_same<T, float>::value) st->td += tot; else { st->td_i += tot; st->td = (double)st->td_i; }
+            if (trace && st->swaps < st->trace_cap) trace[st->swaps] = pamx_swap_record{i, c, (double)tot};
+            st->swaps += 1;
+        }
+        grid.sync();
+        for (int64_t b0 = (int64_t)blockIdx.x * kEgT; b0 < n; b0 += stride) {
+            if (t == 0) nres = 0;
+            __syncthreads();
+            const int64_t o = b0 + t;
+            if (o < n) {
+                int32_t nr = near[o], sc = sec[o];
+                T a = dn[o], b2 = ds[o];
+                if (cache_update_o1<T>(i, rowc[o], nr, sc, a, b2)) {
+                    rl[atomicAdd(&nres, 1)] = (int32_t)o;
+                } else {
+                    near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b2;
+                }
+            }
+            __syncthreads();
+            const int mr = nres;
+            for (int idx = wv; idx < mr; idx += kEgT / 64) {
+                const int64_t q = rl[idx];
+                const Top2<T> tt = wave_scan_medoids<T>(D, ld, k, med, q, lane);
+                if (lane == 0) store_top2<T>(tt, q, near, sec, dn, ds);
+            }
+            __syncthreads();
+        }
+        ++applied;
+    }
+    if (blockIdx.x == 0 && t == 0) {
+        st->iter += 1;
+        if (applied == 0) st->done = 1;
+    }
+}
+
+// Grid of k_eager_grid for n objects on the current device: one work-group
+// per 256 objects, at most what can be resident at once (a cooperative
+// launch requires it) and kEgMax; 0 if the device has no cooperative launch.
+template <typename T>
+static int32_t eager_grid_t(int64_t n) {
+    int dev = 0, coop = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
+        return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_eager_grid<T>, kEgT, 0) != hipSuccess)
+        return 0;
+    int64_t g = (n + kEgT - 1) / kEgT;
+    const int64_t cap = (int64_t)cus * per;
+    if (g > cap) g = cap;
+    if (g > kEgMax) g = kEgMax;
+    return (int32_t)(g < 1 ? 0 : g);
+}
+int32_t eager_grid(int64_t n, int32_t dtype) {
+    return dtype == PAMX_I32 ? eager_grid_t<int32_t>(n) : eager_grid_t<float>(n);
+}
+
 // ================================================================ host side
 template <typename T>
 struct SwapPtrs {
@@ -1755,9 +1902,28 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
         hipLaunchKernelGGL(k_slot_best<T>, dim3(k), dim3(256), 0, s, (const A *)p.P,
                            (const A *)p.cand_a, (const int32_t *)p.seg_off, n, L.ncp,
                            (const uint8_t *)p.is_med, p.slot_v, p.slot_c, (const DevState *)p.st);
-        hipLaunchKernelGGL(k_eager_apply<T>, dim3(1), dim3(1024), 0, s, D, ld, n, k, medoids,
-                           p.is_med, p.near, p.sec, p.dn, p.ds, (const A *)p.slot_v,
-                           (const int32_t *)p.slot_c, p.order, p.rlist, p.st, trace);
+        if (L.eg > 0) {
+            const T *a_D = D;
+            int64_t a_ld = ld, a_n = n;
+            int32_t a_k = k;
+            int32_t *a_med = medoids, *a_near = p.near, *a_sec = p.sec, *a_order = p.order;
+            uint8_t *a_is_med = p.is_med;
+            T *a_dn = p.dn, *a_ds = p.ds;
+            const A *a_sv = p.slot_v;
+            const int32_t *a_sc = p.slot_c;
+            A *a_red = reinterpret_cast<A *>(static_cast<char *>(ws) + L.egred);
+            DevState *a_st = p.st;
+            pamx_swap_record *a_tr = trace;
+            void *args[] = {&a_D, &a_ld, &a_n, &a_k, &a_med, &a_is_med, &a_near, &a_sec,
+                            &a_dn, &a_ds, &a_sv, &a_sc, &a_order, &a_red, &a_st, &a_tr};
+            const hipError_t e = hipLaunchCooperativeKernel(
+                reinterpret_cast<const void *>(k_eager_grid<T>), dim3(L.eg), dim3(kEgT), args, 0, s);
+            if (e != hipSuccess) return e;
+        } else {
+            hipLaunchKernelGGL(k_eager_apply<T>, dim3(1), dim3(1024), 0, s, D, ld, n, k, medoids,
+                               p.is_med, p.near, p.sec, p.dn, p.ds, (const A *)p.slot_v,
+                               (const int32_t *)p.slot_c, p.order, p.rlist, p.st, trace);
+        }
     } else {
         hipLaunchKernelGGL((k_swap_merge<T, false>), dim3(L.n_mwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
