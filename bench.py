@@ -274,8 +274,9 @@ def main():
     extra = {}
     if not args.no_fastpam2:
         opt2, ws2, med2, lab2 = make(abi.PAMX_FASTPAM2)
-        rc2, td2, st2 = abi.pamx_fit(X, abi.PAMX_INPUT_X, K, med2, lab2, ws2,
-                                     metric=abi.PAMX_L2, opt=opt2, stream=stream)
+        for _ in range(2):   # the second fit is reported (the first loads its kernels)
+            rc2, td2, st2 = abi.pamx_fit(X, abi.PAMX_INPUT_X, K, med2, lab2, ws2,
+                                         metric=abi.PAMX_L2, opt=opt2, stream=stream)
         extra = {"fastpam2_eager": {
             "fit_ms": round(st2.ms_total, 3), "swap_ms": round(st2.ms_swap, 3),
             "iterations": st2.iterations, "swaps": st2.swaps, "td": td2,

@@ -158,6 +158,18 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->cl_v = take(1024 * 8);
     L->cl_i = take(1024 * 4);
     L->egred = p2 ? take(2 * 1024 * 8) : SIZE_MAX;
+    // best-candidate scan: about 4096 work-groups in all, at least 1024
+    // candidates each, at most 32 ranges per slot
+    {
+        int64_t S = 4096 / k;
+        const int64_t smax = (nc + 1023) / 1024;
+        if (S > smax) S = smax;
+        if (S > 32) S = 32;
+        if (S < 1) S = 1;
+        L->sbS = (int32_t)S;
+    }
+    L->sb_v = p2 ? take((size_t)k * L->sbS * 8) : SIZE_MAX;
+    L->sb_c = p2 ? take((size_t)k * L->sbS * 4) : SIZE_MAX;
     L->state = take(sizeof(DevState));
     L->head = off;
     set_chunk(L, L->L);

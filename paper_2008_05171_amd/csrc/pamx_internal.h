@@ -168,6 +168,7 @@ struct Layout {
     int32_t fw;          // FasterPAM: largest window (a multiple of tile), or 0
     int32_t fwL, fwQ;    // FasterPAM: object chunk length and count of the window pass
     int32_t eg;          // FastPAM2: grid of the cooperative eager apply, 0 = one work-group
+    int32_t sbS;         // FastPAM2: candidate ranges per slot in the best-candidate scan
     size_t esz;          // element size of D (4)
     size_t asz;          // accumulator size (8)
     // offsets
@@ -184,6 +185,7 @@ struct Layout {
     size_t cl_v, cl_i;   // FastCLARANS: changes and slots of a window of draws
     size_t mark;         // medoid check: one counter per candidate
     size_t egred;        // FastPAM2: per-work-group re-score sums of the eager apply
+    size_t sb_v, sb_c;   // FastPAM2: per-range best candidates of every slot
     size_t DT;           // rectangular matrix: its transpose (candidate rows), or SIZE_MAX
     int64_t ldt;         // row stride of DT
     size_t state;

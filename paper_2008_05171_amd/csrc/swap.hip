@@ -807,12 +807,19 @@ __device__ __forceinline__ void pass_tile(
             for (int e = 0; e < VEC; ++e) pq[2 * ncp + e] = M[e];
             if (rec) cdn[2 * q + 1] = dns;
         } else {
+            A v[VEC];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
-                const A v = M[e] - dns;
-                if (v < bv[e]) { bv[e] = v; bi[e] = s; }
-                if constexpr (P2) {
-                    if (active) __builtin_nontemporal_store(v, &P[(int64_t)s * ncp + c0 + e]);
+                v[e] = M[e] - dns;
+                if (v[e] < bv[e]) { bv[e] = v[e]; bi[e] = s; }
+            }
+            if constexpr (P2) {
+                // streaming stores (P is read once, by the best-candidate
+                // scan); measured faster than 16-byte or cached stores
+                if (active) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        __builtin_nontemporal_store(v[e], &P[(int64_t)s * ncp + c0 + e]);
                 }
             }
         }
@@ -1470,27 +1477,52 @@ __global__ __launch_bounds__(256) void k_cl_select_update(
 }
 
 // ---- FastPAM2: best candidate of every slot, (value, candidate) order.
+// Work-group (i, j) scans the j-th of S equal candidate ranges of slot i and
+// leaves its (value, candidate) minimum in part_v/part_c[i * S + j];
+// k_slot_reduce takes the lexicographic minimum of the S parts.
 template <typename T>
 __global__ __launch_bounds__(256) void k_slot_best(const AccT<T> *__restrict__ P,
                                                    const AccT<T> *__restrict__ cand_a,
                                                    const int32_t *__restrict__ seg_off, int64_t n,
                                                    int64_t ncp, const uint8_t *__restrict__ is_med,
-                                                   AccT<T> *__restrict__ slot_v,
-                                                   int32_t *__restrict__ slot_c,
+                                                   AccT<T> *__restrict__ part_v,
+                                                   int32_t *__restrict__ part_c, int64_t span,
                                                    const DevState *__restrict__ st) {
     using A = AccT<T>;
     if (st->done) return;
-    const int i = blockIdx.x;
+    const int i = blockIdx.x, j = blockIdx.y, S = gridDim.y;
     const bool empty = seg_off[i] == seg_off[i + 1];
+    const int64_t x0 = (int64_t)j * span, x1 = min(x0 + span, n);
+    const A *Pi = P + (int64_t)i * ncp;
     A v = VT<T>::acc_inf();
     int c = INT_MAX, dummy = 0;
-    for (int64_t x = threadIdx.x; x < n; x += 256) {
-        if (is_med[x]) continue;
-        const A d = (empty ? (A)0 : P[(int64_t)i * ncp + x]) + cand_a[x];
-        if (d < v) { v = d; c = (int)x; }   // ascending x: first minimum per thread
+    for (int64_t x = x0 + threadIdx.x; x < x1; x += 256) {
+        const A d = (empty ? (A)0 : Pi[x]) + cand_a[x];
+        if (!is_med[x] && d < v) { v = d; c = (int)x; }   // ascending x: first minimum per thread
     }
     block_argmin3<A, 256>(v, dummy, c);
-    if (threadIdx.x == 0) { slot_v[i] = v; slot_c[i] = c; }
+    if (threadIdx.x == 0) { part_v[(int64_t)i * S + j] = v; part_c[(int64_t)i * S + j] = c; }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_slot_reduce(const AccT<T> *__restrict__ part_v,
+                                                     const int32_t *__restrict__ part_c, int S,
+                                                     int32_t k, AccT<T> *__restrict__ slot_v,
+                                                     int32_t *__restrict__ slot_c,
+                                                     const DevState *__restrict__ st) {
+    using A = AccT<T>;
+    if (st->done) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= k) return;
+    A v = VT<T>::acc_inf();
+    int c = INT_MAX;
+    for (int j = 0; j < S; ++j) {
+        const A pv = part_v[(int64_t)i * S + j];
+        const int pc = part_c[(int64_t)i * S + j];
+        if (lt2(pv, pc, v, c)) { v = pv; c = pc; }
+    }
+    slot_v[i] = v;
+    slot_c[i] = c;
 }
 
 // ---- FastPAM2 eager application (one work-group).  Slots with a negative
@@ -1899,9 +1931,17 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
                            L.Q, L.nc, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
                            (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
-        hipLaunchKernelGGL(k_slot_best<T>, dim3(k), dim3(256), 0, s, (const A *)p.P,
-                           (const A *)p.cand_a, (const int32_t *)p.seg_off, n, L.ncp,
-                           (const uint8_t *)p.is_med, p.slot_v, p.slot_c, (const DevState *)p.st);
+        {
+            A *sb_v = reinterpret_cast<A *>(static_cast<char *>(ws) + L.sb_v);
+            int32_t *sb_c = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + L.sb_c);
+            const int64_t span = (L.nc + L.sbS - 1) / L.sbS;
+            hipLaunchKernelGGL(k_slot_best<T>, dim3(k, L.sbS), dim3(256), 0, s, (const A *)p.P,
+                               (const A *)p.cand_a, (const int32_t *)p.seg_off, L.nc, L.ncp,
+                               (const uint8_t *)p.is_med, sb_v, sb_c, span, (const DevState *)p.st);
+            hipLaunchKernelGGL(k_slot_reduce<T>, dim3((k + 255) / 256), dim3(256), 0, s,
+                               (const A *)sb_v, (const int32_t *)sb_c, L.sbS, k, p.slot_v,
+                               p.slot_c, (const DevState *)p.st);
+        }
         if (L.eg > 0) {
             const T *a_D = D;
             int64_t a_ld = ld, a_n = n;
