@@ -308,9 +308,10 @@ __device__ __forceinline__ float rc_dist(float g, float no, float nc) {
 // end of a segment complete in the chunk, v = R_i + S_i and the running best
 // (v, i); head and tail carries as in the stored-matrix pass.  Outputs per
 // candidate and chunk: part[q][0..3] = B, head, tail, best value (ACC);
-// part_i[q][0..3] = best slot, far count, near count.
+// part_i[q][0..3] = best slot, far count, near count.  Register use is held
+// to three waves per SIMD (the LDS of three work-groups per CU).
 template <int KS, typename ACC>
-__global__ __launch_bounds__(kRT) void k_rc_swap_pass(
+__global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(3))) void k_rc_swap_pass(
     const __bf16 *__restrict__ Xs, int32_t KP, const float *__restrict__ nb, int64_t n, int32_t k,
     const int32_t *__restrict__ srow, const float *__restrict__ sdn, const float *__restrict__ sds,
     const float *__restrict__ sthr, const float *__restrict__ snb, const double *__restrict__ eps0,
@@ -358,22 +359,46 @@ __global__ __launch_bounds__(kRT) void k_rc_swap_pass(
         __syncthreads();
         const int m = (int)min((int64_t)kRB, b - j0);
         ACC bblk = 0, sblk = 0;
-        for (int r = 0; r < m; ++r) {
-            const int64_t j = j0 + r;
-            if (j == ce) {             // uniform: segment boundary
+        const float *Gl = Gw + lane * kGS;
+        // one pair: loss-change terms and the bound's counts
+        auto pair = [&](float g, float4 q4) {   // q4 = no, dn, ds, thr
+            const float d = rc_dist(g, q4.x, nc);
+            bblk += (ACC)fminf(d - q4.y, 0.0f);
+            sblk += (ACC)(__builtin_amdgcn_fmed3f(d, q4.y, q4.z) - q4.z);
+            const bool cnt = d < q4.w;
+            cf += (cnt && d >= d0) ? 1 : 0;
+            cn += (cnt && d < d0) ? 1 : 0;
+        };
+        int r = 0;
+        while (r < m) {
+            if (j0 + r == ce) {        // uniform: segment boundary
                 S += sblk;
                 sblk = 0;
                 finish(cs);
                 do { ++cs; } while (seg_off[cs + 1] == seg_off[cs]);
                 ce = seg_off[cs + 1];
             }
-            const float4 q4 = Rb[r];   // no, dn, ds, thr
-            const float d = rc_dist(Gw[lane * kGS + r], q4.x, nc);
-            bblk += (ACC)fminf(d - q4.y, 0.0f);
-            sblk += (ACC)(__builtin_amdgcn_fmed3f(d, q4.y, q4.z) - q4.z);
-            const bool cnt = d < q4.w;
-            cf += (cnt && d >= d0) ? 1 : 0;
-            cn += (cnt && d < d0) ? 1 : 0;
+            // the objects up to the next boundary, eight (then four) at a time
+            // with their LDS reads issued together, so LDS latency overlaps
+            // arithmetic (same order of additions as one at a time)
+            const int re = (int)min((int64_t)m, ce - j0);
+            for (; r + 8 <= re; r += 8) {
+                float4 q[8];
+                float g[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) { q[u] = Rb[r + u]; g[u] = Gl[r + u]; }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) pair(g[u], q[u]);
+            }
+            for (; r + 4 <= re; r += 4) {
+                float4 q[4];
+                float g[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) { q[u] = Rb[r + u]; g[u] = Gl[r + u]; }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) pair(g[u], q[u]);
+            }
+            for (; r < re; ++r) pair(Gl[r], Rb[r]);
         }
         accB += bblk;
         S += sblk;
