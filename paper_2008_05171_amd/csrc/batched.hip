@@ -200,7 +200,22 @@ __global__ __launch_bounds__(kBT) void k_clara(
                         acc += (A)vmin(pdist<MD>(L.P + (size_t)o * dim, b, dim), L.dn[o]);
                 } else {
                     acc = acand[r];
-                    for (int q = 0; q < nchg; ++q) {
+                    // four listed objects at a time, their LDS reads issued
+                    // together (same order of additions)
+                    int q = 0;
+                    for (; q + 4 <= nchg; q += 4) {
+                        int32_t ob[4];
+                        T d[4], lo[4], hi[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            ob[u] = L.srow[q + u]; lo[u] = L.sdn[q + u]; hi[u] = L.sds[q + u];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) d[u] = pdist<MD>(L.P + (size_t)ob[u] * dim, b, dim);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) acc += (A)vmin(d[u], hi[u]) - (A)vmin(d[u], lo[u]);
+                    }
+                    for (; q < nchg; ++q) {
                         const T d = pdist<MD>(L.P + (size_t)L.srow[q] * dim, b, dim);
                         acc += (A)vmin(d, L.sds[q]) - (A)vmin(d, L.sdn[q]);
                     }
@@ -322,7 +337,25 @@ __global__ __launch_bounds__(kBT) void k_clara(
                         const int q0 = L.seg[s], q1 = L.seg[s + 1];
                         if (q0 == q1) continue;
                         A M = 0;
-                        for (int q = q0; q < q1; ++q) {
+                        // four objects of the segment at a time, their LDS
+                        // reads issued together (same order of additions)
+                        int q = q0;
+                        for (; q + 4 <= q1; q += 4) {
+                            int32_t ob[4];
+                            T d[4], lo[4], hi[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                ob[u] = L.srow[q + u]; lo[u] = L.sdn[q + u]; hi[u] = L.sds[q + u];
+                            }
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) d[u] = pdist<MD>(L.P + (size_t)ob[u] * dim, cb, dim);
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                accA += (A)vmin(d[u], lo[u]);
+                                M += (A)vmed3(d[u], lo[u], hi[u]);
+                            }
+                        }
+                        for (; q < q1; ++q) {
                             const T d = pdist<MD>(L.P + (size_t)L.srow[q] * dim, cb, dim);
                             const T lo = L.sdn[q], hi = L.sds[q];
                             accA += (A)vmin(d, lo);
