@@ -6,12 +6,23 @@
 // and O(n'^2) per SWAP iteration (Sec. 3.4).
 //
 // k_clara: a persistent kernel.  Each work-group (1024 lanes, one per CU: its
-// LDS holds one instance) takes instances from an atomic work queue (largest
+// LDS holds one instance) takes tickets from an atomic work queue (largest
 // estimated cost first) and runs BUILD (Alg. 1) and FastPAM1 SWAP (Alg. 3)
-// for that instance entirely in LDS: the sample's points, the caches and the
-// segment-sorted object order.  Distances are recomputed from the points in
-// LDS (Euclidean FP32 or Manhattan int32), so nothing of size n'^2 is stored.
-// Sums are FP64 (int64 for integer points) in a fixed order.
+// for the ticket's instance entirely in LDS: the sample's points, the caches
+// and the segment-sorted object order.  Distances are recomputed from the
+// points in LDS (Euclidean FP32 or Manhattan int32), so nothing of size n'^2
+// is stored.  Sums are FP64 (int64 for integer points) in a fixed order.
+//
+// A large instance is run by a team of T work-groups (T consecutive tickets)
+// so that it does not set the length of the whole launch: member m evaluates
+// the candidates m*1024 + lane + r*T*1024, every member keeps its own full
+// copy of the points and caches (the same values: the same code on the same
+// data), and the only exchange is the (value, slot, candidate) minimum of
+// each BUILD step and SWAP iteration, through global memory and a team
+// barrier.  The minimum of a total order does not depend on how the
+// candidates are split, so a team's results equal one work-group's.  Teams
+// need every member resident at once: they are formed only under a
+// cooperative launch.
 //
 // k_full_assign + k_full_reduce: TD of every instance's medoids over all N
 // points (FP32 distances, FP64 sums in a fixed order).
@@ -68,6 +79,61 @@ __device__ __forceinline__ void wg_argmin3(A &v, int &i, int &c, A *rv, int *ri,
     for (int u = 1; u < kBW; ++u)
         if (lex_less(rv[u], ri[u], rc[u], v, i, c)) { v = rv[u]; i = ri[u]; c = rc[u]; }
     __syncthreads();
+}
+
+// Team-wide (value, slot, candidate) minimum for instance j: member m posts
+// its work-group result in the exchange slots of this step's parity, arrives
+// at the team's counter and waits until all T members have arrived at this
+// step; every member then takes the minimum over the T posts.  Two parities:
+// a member can post step g+1 while a slower one still reads step g, never
+// step g+2 (that needs the slower one's arrival at g+1).  The wait is bounded
+// (a count no correct run reaches): past it the kernel reports err |= 4 and
+// the work-group leaves (returns false).
+constexpr long long kSpinMax = 1ll << 24;
+template <typename E>
+__device__ bool team_argmin3(AccT<E> &v, int &i, int &c, int T, int m, int j, int &gen,
+                             int32_t *__restrict__ bar, unsigned long long *__restrict__ xch,
+                             int32_t *__restrict__ err, AccT<E> *rv, int *ri, int *rc) {
+    using A = AccT<E>;
+    if (T == 1) return true;
+    __shared__ int ok_s;
+    unsigned long long *slot = xch + ((size_t)(2 * j + (gen & 1)) * kBTeamMax) * 2;
+    if (threadIdx.x == 0) {
+        slot[2 * m] = __builtin_bit_cast(unsigned long long, v);
+        slot[2 * m + 1] = ((unsigned long long)(uint32_t)i << 32) | (uint32_t)c;
+        __threadfence();   // the post before the arrival
+        atomicAdd(&bar[j], 1);
+        const int want = (gen + 1) * T;
+        long long spins = 0;
+        int ok = 1;
+        while (__hip_atomic_load(&bar[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < want) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > kSpinMax) { ok = 0; break; }
+        }
+        if (ok) {
+            A bv = VT<E>::acc_inf();
+            int bi = INT_MAX, bc = INT_MAX;
+            for (int u = 0; u < T; ++u) {
+                const unsigned long long a0 =
+                    __hip_atomic_load(&slot[2 * u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long a1 =
+                    __hip_atomic_load(&slot[2 * u + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const A uv = __builtin_bit_cast(A, a0);
+                const int ui = (int)(uint32_t)(a1 >> 32), uc = (int)(uint32_t)a1;
+                if (lex_less(uv, ui, uc, bv, bi, bc)) { bv = uv; bi = ui; bc = uc; }
+            }
+            rv[0] = bv; ri[0] = bi; rc[0] = bc;
+        } else {
+            atomicOr(err, 4);
+        }
+        ok_s = ok;
+    }
+    __syncthreads();
+    const bool ok = ok_s != 0;
+    if (ok) { v = rv[0]; i = ri[0]; c = rc[0]; }
+    __syncthreads();
+    ++gen;
+    return ok;
 }
 
 template <typename A>
@@ -146,10 +212,12 @@ template <typename T, int MD>
 __global__ __launch_bounds__(kBT) void k_clara(
     const T *__restrict__ X, int64_t N, int32_t dim, const int64_t *__restrict__ soff,
     const int32_t *__restrict__ sidx, const int32_t *__restrict__ kin,
-    const int64_t *__restrict__ moff, const int32_t *__restrict__ order, int32_t n_inst,
+    const int64_t *__restrict__ moff, const int32_t *__restrict__ tk_inst,
+    const int32_t *__restrict__ tk_mem, const int32_t *__restrict__ tsz, int32_t n_tick,
     int32_t max_iter, int32_t excl, int32_t n_max, int32_t k_max, int32_t *__restrict__ med_out,
     double *__restrict__ td_out, double *__restrict__ tdb_out, int32_t *__restrict__ it_out,
-    int32_t *__restrict__ sw_out, int32_t *__restrict__ rows_out, int32_t *__restrict__ queue) {
+    int32_t *__restrict__ sw_out, int32_t *__restrict__ rows_out, int32_t *__restrict__ queue,
+    int32_t *__restrict__ bar, unsigned long long *__restrict__ xch, int32_t *__restrict__ err) {
     using A = AccT<T>;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ A rv[kBW];
@@ -163,8 +231,12 @@ __global__ __launch_bounds__(kBT) void k_clara(
         __syncthreads();
         const int job = __builtin_amdgcn_readfirstlane(job_s);
         __syncthreads();   // everyone has read job_s before thread 0 writes it again
-        if (job >= n_inst) break;
-        const int j = order[job];
+        if (job >= n_tick) break;
+        const int j = tk_inst[job];
+        const int mem = tk_mem[job];      // member of the instance's team
+        const int tsize = tsz[j];         // team size
+        const int cb0 = mem * kBT, cstr = tsize * kBT;   // this member's candidates
+        int gen = 0;                      // team steps so far
         const int64_t base = soff[j];
         const int n = (int)(soff[j + 1] - base);
         const int k = kin[j];
@@ -189,7 +261,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
             A bv = VT<T>::acc_inf();
             int bc = INT_MAX, zero = 0;
             for (int r = 0; r < kBR; ++r) {
-                const int c = tid + r * kBT;
+                const int c = cb0 + tid + r * cstr;
                 if (c >= n || L.is_med[c]) continue;
                 T b[MD];
                 load_pt<T, MD>(L.P + (size_t)c * dim, dim, b);
@@ -225,6 +297,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
                 if (acc < bv) { bv = acc; bc = c; }
             }
             wg_argmin3<A>(bv, zero, bc, rv, ri, rc);
+            if (!team_argmin3<T>(bv, zero, bc, tsize, mem, j, gen, bar, xch, err, rv, ri, rc)) return;
             const int m = bc;
             if (tid == 0) { L.med[step] = m; L.is_med[m] = 1; }
             T b[MD];
@@ -327,7 +400,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
                 A bestv = VT<T>::acc_inf();
                 int besti = INT_MAX, bestc = INT_MAX;
                 for (int r = 0; r < kBR; ++r) {
-                    const int c = tid + r * kBT;
+                    const int c = cb0 + tid + r * cstr;
                     if (c >= n || L.is_med[c]) continue;
                     T cb[MD];
                     load_pt<T, MD>(L.P + (size_t)c * dim, dim, cb);
@@ -369,6 +442,8 @@ __global__ __launch_bounds__(kBT) void k_clara(
                     if (lex_less(dl, bi, c, bestv, besti, bestc)) { bestv = dl; besti = bi; bestc = c; }
                 }
                 wg_argmin3<A>(bestv, besti, bestc, rv, ri, rc);
+                if (!team_argmin3<T>(bestv, besti, bestc, tsize, mem, j, gen, bar, xch, err, rv, ri, rc))
+                    return;
                 A thr;
                 if constexpr (std::is_same<T, float>::value)
                     thr = -4.0 * ((double)n + 68.0) * 0x1p-53 * (double)sds_sum;
@@ -396,8 +471,10 @@ __global__ __launch_bounds__(kBT) void k_clara(
         A td = 0;
         for (int o = tid; o < n; o += kBT) td += (A)L.dn[o];
         td = wg_sum<A>(td, rv);
-        for (int s = tid; s < k; s += kBT) med_out[moff[j] + s] = sidx[base + L.med[s]];
-        if (tid == 0) {
+        if (mem == 0) {   // one member writes the instance's results
+            for (int s = tid; s < k; s += kBT) med_out[moff[j] + s] = sidx[base + L.med[s]];
+        }
+        if (tid == 0 && mem == 0) {
             td_out[j] = (double)td;
             tdb_out[j] = (double)tdb;
             it_out[j] = iters;
@@ -483,13 +560,63 @@ template <typename T, int MD>
 static hipError_t launch_clara_md(const T *X, int64_t N, int32_t dim, const BatchArgs &a,
                                   hipStream_t s) {
     const size_t lds = batched_lds_bytes(a.n_max, a.k_max, dim, sizeof(T));
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_clara<T, MD>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void *fn = reinterpret_cast<const void *>(&k_clara<T, MD>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_clara<T, MD>), dim3(a.grid), dim3(kBT), lds, s, X, N, dim, a.soff, a.sidx,
-                       a.kin, a.moff, a.order, a.n_inst, a.max_iter, a.excl, a.n_max, a.k_max,
-                       a.med_out, a.td_out, a.tdb_out, a.it_out, a.sw_out, a.rows_out, a.queue);
-    return hipGetLastError();
+    if (!a.coop) {
+        hipLaunchKernelGGL((k_clara<T, MD>), dim3(a.grid), dim3(kBT), lds, s, X, N, dim, a.soff,
+                           a.sidx, a.kin, a.moff, a.tk_inst, a.tk_mem, a.tsz, a.n_tick, a.max_iter,
+                           a.excl, a.n_max, a.k_max, a.med_out, a.td_out, a.tdb_out, a.it_out,
+                           a.sw_out, a.rows_out, a.queue, a.bar, a.xch, a.err);
+        return hipGetLastError();
+    }
+    // teams: every work-group resident at once
+    const T *p_X = X;
+    int64_t p_N = N;
+    int32_t p_dim = dim;
+    const int64_t *p_soff = a.soff;
+    const int32_t *p_sidx = a.sidx, *p_kin = a.kin;
+    const int64_t *p_moff = a.moff;
+    const int32_t *p_tki = a.tk_inst, *p_tkm = a.tk_mem, *p_tsz = a.tsz;
+    int32_t p_ntick = a.n_tick, p_maxit = a.max_iter, p_excl = a.excl, p_nmax = a.n_max,
+            p_kmax = a.k_max;
+    int32_t *p_med = a.med_out;
+    double *p_td = a.td_out, *p_tdb = a.tdb_out;
+    int32_t *p_it = a.it_out, *p_sw = a.sw_out, *p_rows = a.rows_out, *p_queue = a.queue,
+            *p_bar = a.bar, *p_err = a.err;
+    unsigned long long *p_xch = a.xch;
+    void *args[] = {&p_X,    &p_N,    &p_dim,  &p_soff, &p_sidx,  &p_kin,  &p_moff, &p_tki,
+                    &p_tkm,  &p_tsz,  &p_ntick, &p_maxit, &p_excl, &p_nmax, &p_kmax, &p_med,
+                    &p_td,   &p_tdb,  &p_it,   &p_sw,   &p_rows,  &p_queue, &p_bar, &p_xch,
+                    &p_err};
+    return hipLaunchCooperativeKernel(fn, dim3(a.grid), dim3(kBT), args, (unsigned)lds, s);
+}
+
+template <typename T, int MD>
+static int resident_md(size_t lds) {
+    const void *fn = reinterpret_cast<const void *>(&k_clara<T, MD>);
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_clara<T, MD>, kBT, lds) != hipSuccess)
+        return 0;
+    return per;
+}
+
+int batched_resident(int32_t dim, size_t lds, int32_t dtype, int *coop) {
+    int dev = 0, cus = 0, c = 0;
+    *coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess) *coop = c;
+    int per;
+    if (dtype == PAMX_F32)
+        per = dim <= 4 ? resident_md<float, 4>(lds)
+                       : (dim <= 8 ? resident_md<float, 8>(lds) : resident_md<float, kBMaxDim>(lds));
+    else
+        per = dim <= 4 ? resident_md<int32_t, 4>(lds)
+                       : (dim <= 8 ? resident_md<int32_t, 8>(lds) : resident_md<int32_t, kBMaxDim>(lds));
+    return per * cus;
 }
 
 template <typename T>

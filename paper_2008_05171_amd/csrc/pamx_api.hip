@@ -1273,7 +1273,8 @@ namespace {
 constexpr int kFullBlocks = 256;   // blocks per instance in the full-data TD
 
 struct BatchLayout {
-    size_t soff, kin, moff, order, td, tdb, it, sw, rows, ctr, part, tdf, total;
+    size_t soff, kin, moff, tk_inst, tk_mem, tsz, bar, xch, td, tdb, it, sw, rows, ctr, part, tdf,
+        total;
 };
 
 BatchLayout batch_layout(int32_t n_inst) {
@@ -1283,7 +1284,11 @@ BatchLayout batch_layout(int32_t n_inst) {
     b.soff = take((size_t)(n_inst + 1) * 8);
     b.kin = take((size_t)n_inst * 4);
     b.moff = take((size_t)(n_inst + 1) * 8);
-    b.order = take((size_t)n_inst * 4);
+    b.tk_inst = take((size_t)n_inst * kBTeamMax * 4);
+    b.tk_mem = take((size_t)n_inst * kBTeamMax * 4);
+    b.tsz = take((size_t)n_inst * 4);
+    b.bar = take((size_t)n_inst * 4);
+    b.xch = take((size_t)n_inst * kBTeamSlots * 8);
     b.td = take((size_t)n_inst * 8);
     b.tdb = take((size_t)n_inst * 8);
     b.it = take((size_t)n_inst * 4);
@@ -1353,14 +1358,41 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
     if (lds > 150 * 1024)
         return fail(PAMX_ERR_UNSUPPORTED, "instance too large for one work-group's LDS (%zu B)", lds);
     std::sort(cost.begin(), cost.end());
-    std::vector<int32_t> order(n_inst);
-    for (int32_t j = 0; j < n_inst; ++j) order[j] = cost[j].second;
     const BatchLayout B = batch_layout(n_inst);
     if (!ws) return fail(PAMX_ERR_WORKSPACE, "workspace is NULL");
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
         return fail(PAMX_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     if (ws_bytes < B.total) return fail(PAMX_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes",
                                         ws_bytes, B.total);
+    // Teams: with cooperative launch, an instance whose estimated cost is a
+    // multiple of the balanced share (total / resident work-groups) gets that
+    // many work-groups (at most kBTeamMax, and at least 256 candidates each),
+    // so the largest instances do not set the length of the launch.
+    int coop = 0;
+    const int resident = batched_resident(dim, lds, dtype, &coop);
+    if (resident < 1) return fail(PAMX_ERR_UNSUPPORTED, "the batched kernel does not fit a compute unit");
+    std::vector<int32_t> tsz(n_inst, 1);
+    if (coop && resident >= 2) {
+        double total = 0.0;
+        for (const auto &cj : cost) total += -cj.first;
+        const double share = total / resident;
+        for (const auto &cj : cost) {
+            const int32_t j = cj.second;
+            const int64_t nj = sample_off[j + 1] - sample_off[j];
+            int lim = (int)std::min<int64_t>(kBTeamMax, std::max<int64_t>(1, nj / 256));
+            if (lim > resident) lim = resident;
+            const int t = (int)std::llround(-cj.first / share);
+            tsz[j] = t < 1 ? 1 : (t > lim ? lim : t);
+        }
+    }
+    std::vector<int32_t> tk_inst, tk_mem;   // queue tickets, largest estimated cost first
+    int32_t max_team = 1;
+    for (const auto &cj : cost) {
+        const int32_t j = cj.second;
+        for (int32_t m = 0; m < tsz[j]; ++m) { tk_inst.push_back(j); tk_mem.push_back(m); }
+        max_team = tsz[j] > max_team ? tsz[j] : max_team;
+    }
+    const int32_t n_tick = (int32_t)tk_inst.size();
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *w = static_cast<char *>(ws);
@@ -1370,9 +1402,13 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
     HIP_TRY(hipMemcpyAsync(w + B.soff, sample_off, (size_t)(n_inst + 1) * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(w + B.kin, k_inst, (size_t)n_inst * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(w + B.moff, moff.data(), (size_t)(n_inst + 1) * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w + B.order, order.data(), (size_t)n_inst * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w + B.tk_inst, tk_inst.data(), (size_t)n_tick * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w + B.tk_mem, tk_mem.data(), (size_t)n_tick * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w + B.tsz, tsz.data(), (size_t)n_inst * 4, hipMemcpyHostToDevice, s));
     int32_t *ctr = reinterpret_cast<int32_t *>(w + B.ctr);
     hipLaunchKernelGGL(k_fill_batch<int32_t>, dim3(1), dim3(256), 0, s, ctr, (int64_t)2, 0);
+    hipLaunchKernelGGL(k_fill_batch<int32_t>, dim3((n_inst + 255) / 256), dim3(256), 0, s,
+                       reinterpret_cast<int32_t *>(w + B.bar), (int64_t)n_inst, 0);
     HIP_TRY(hipGetLastError());
 
     BatchArgs a;
@@ -1380,13 +1416,20 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
     a.sidx = sample_idx;
     a.kin = reinterpret_cast<const int32_t *>(w + B.kin);
     a.moff = reinterpret_cast<const int64_t *>(w + B.moff);
-    a.order = reinterpret_cast<const int32_t *>(w + B.order);
+    a.tk_inst = reinterpret_cast<const int32_t *>(w + B.tk_inst);
+    a.tk_mem = reinterpret_cast<const int32_t *>(w + B.tk_mem);
+    a.tsz = reinterpret_cast<const int32_t *>(w + B.tsz);
+    a.bar = reinterpret_cast<int32_t *>(w + B.bar);
+    a.xch = reinterpret_cast<unsigned long long *>(w + B.xch);
     a.n_inst = n_inst;
+    a.n_tick = n_tick;
+    a.coop = max_team > 1 ? 1 : 0;
     a.max_iter = opt.max_iter;
     a.excl = opt.build_exclude_self;
     a.n_max = n_max;
     a.k_max = k_max;
-    a.grid = cus < n_inst ? cus : n_inst;
+    if (a.coop) a.grid = resident < n_tick ? resident : n_tick;   // all resident at once
+    else a.grid = cus < n_inst ? cus : n_inst;
     a.nblk = kFullBlocks;
     a.med_out = medoids;
     a.td_out = reinterpret_cast<double *>(w + B.td);
@@ -1426,6 +1469,7 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
     HIP_TRY(hipMemcpyAsync(sw.data(), a.sw_out, (size_t)n_inst * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(rows.data(), a.rows_out, (size_t)n_inst * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (err & 4) return fail(PAMX_ERR_HIP, "a team of the batched kernel did not meet (wait bound reached)");
     if (err) return fail(PAMX_ERR_HIP, "a medoid index outside [0, N) reached the full-data TD");
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));

@@ -17,6 +17,7 @@ constexpr int kMaxK = 16000;      // largest k accepted (slot histogram and offs
 constexpr int kBMaxDim = 16;      // batched instances: largest point dimension
 constexpr int kBMaxK = 256;       // batched instances: largest k
 constexpr int kBMaxN = 2048;      // batched instances: largest sample (2 candidates per lane)
+constexpr int kBTeamMax = 8;      // batched instances: largest team of work-groups per instance
 
 // Accumulator and "infinity" per element type.  Integer dissimilarities are
 // summed exactly in int64; float32 ones in FP64 (or FP32 with re-scoring).
@@ -250,14 +251,23 @@ struct BatchArgs {
     const int32_t *sidx;    // sample point indices
     const int32_t *kin;     // [n_inst] k per instance
     const int64_t *moff;    // [n_inst+1] medoid offsets
-    const int32_t *order;   // instance ids, largest estimated cost first
-    int32_t n_inst, max_iter, excl, n_max, k_max, grid, nblk;
+    const int32_t *tk_inst; // [n_tick] instance of each queue ticket, largest estimated cost first
+    const int32_t *tk_mem;  // [n_tick] team member of the ticket
+    const int32_t *tsz;     // [n_inst] team size (work-groups) of each instance
+    int32_t *bar;           // [n_inst] team arrival counters, zero before the launch
+    unsigned long long *xch;   // [n_inst][2][kBTeamMax][2] team exchange slots
+    int32_t n_inst, n_tick, max_iter, excl, n_max, k_max, grid, nblk;
+    int32_t coop;           // teams present: cooperative launch
     int32_t *med_out;       // global indices of the medoids, instance-major
     double *td_out, *tdb_out, *part, *td_full;
     int32_t *it_out, *sw_out, *queue, *err;
     int32_t *rows_out;      // rows read by the incremental BUILD steps
 };
 size_t batched_lds_bytes_host(int n_max, int k_max, int dim, size_t esz);
+// Work-groups of k_clara resident at once on the current device for this
+// LDS size, and whether it has cooperative launch (teams need both).
+int batched_resident(int32_t dim, size_t lds, int32_t dtype, int *coop);
+constexpr int kBTeamSlots = kBTeamMax * 2 * 2;   // exchange words per instance (members x 2 parities x 2)
 hipError_t launch_check_sidx(const int32_t *sidx, int64_t total, int64_t N, int32_t *err,
                              hipStream_t s);
 template <typename T>

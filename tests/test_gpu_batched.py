@@ -72,6 +72,31 @@ def test_batched_float_close():
     assert sum(agree) >= len(agree) - 1
 
 
+def test_batched_teams_int_bitexact():
+    """Samples of 1500, 900 and 520 points run as teams of several work-groups
+    (candidates split, one exchange per step); with the small instances beside
+    them every result is bit-exact against the oracle, instance by instance."""
+    _say("batched_teams_int")
+    X = datagen.int_points(20000, 3, 0, 1000, seed=11)
+    sizes = [1500, 900, 520, 300, 100, 40]
+    ks = np.array([9, 6, 3, 5, 4, 2], np.int32)
+    rng = np.random.default_rng(11)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    idx = np.concatenate([np.sort(rng.choice(20000, size=m, replace=False))
+                          for m in sizes]).astype(np.int32)
+    res = _run(X, off, idx, ks)
+    assert res.rc == 0
+    for j in range(len(ks)):
+        sample = idx[off[j]:off[j + 1]]
+        D = oracle.dist_matrix(X[sample], oracle.L1)
+        ref = oracle.pam(int(ks[j]), D=D)
+        assert list(res.medoids[j].cpu().numpy()) == list(sample[ref.medoids]), j
+        assert res.td_sample[j] == ref.td, j
+        assert res.stats["iterations"] > 0
+        tdf, _ = oracle.td(sample[ref.medoids], X=X.astype(np.float64), metric=oracle.L1)
+        assert res.td_full[j] == tdf, j
+
+
 def test_batched_edge_cases():
     _say("batched_edges")
     X = datagen.int_points(3000, 3, 0, 50, seed=9)
