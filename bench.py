@@ -91,7 +91,7 @@ def write_traffic(fetch_csv, write_csv, probe_mib, chunk):
     f, w = per_kernel(fetch_csv), per_kernel(write_csv)
     fetch_scale = probe_mib * 1024.0 / max(f["__amd_rocclr_copyBuffer"])
     write_scale = probe_mib * 1024.0 / max(w["__amd_rocclr_copyBuffer"])
-    key = "pamx::k_swap_pass<float, 4, false>"
+    key = "pamx::k_swap_pass<float, 4, false, false>"   # FastPAM1, full candidate range
     pairs = [(a, b) for a, b in zip(f[key], w[key]) if a > 1024.0]
     fetch_kib = sum(a for a, _ in pairs) / len(pairs)
     write_kib = sum(b for _, b in pairs) / len(pairs)
