@@ -21,10 +21,17 @@ Reported (one JSON line):
   cpu_baseline     the CPU oracle (original PAM SWAP, FP64, OpenMP) on a
                    bounded sample of candidates of the same workload
 
---next fasterpam|init|clarans [--large] times a row beyond the headline
-instead (FasterPAM from BUILD; distance-weighted and LAB seeding; one
-FastCLARANS search) on this workload, or with --large on the 1e5 x 32 Zipf
-mixture (k = 500, 40 GB matrix), and prints one JSON line of its timings.
+--next fasterpam|init|clarans|starts [--large] times a row beyond the
+headline instead (FasterPAM from BUILD; distance-weighted and LAB seeding;
+one FastCLARANS search; whole fits for every start x SWAP variant) on this
+workload, or with --large on the 1e5 x 32 Zipf mixture (k = 500, 40 GB
+matrix), and prints one JSON line of its timings.
+
+--form bf16|clara|eager-large times one of the other forms on its own
+workload and prints one JSON line: the mixed-precision form (n = 50000,
+d = 64, 200 components, k = 200, no stored matrix), 256 batched CLARA
+instances drawn from 1e6 points in 8 dimensions, or eager FastPAM2 on the
+1e5 x 32 Zipf mixture (k = 500, 40 GB matrix).
 """
 from __future__ import annotations
 
@@ -143,6 +150,28 @@ def run_next(which, large, reps):
         X = torch.from_numpy(datagen.gaussian_mixture(N, DIM, COMPONENTS, seed=SEED)).cuda()
         k, name = K, "gmm16: n=20000 d=16, 50 components, k=100"
     out = {"next": which, "workload": name, "runs": []}
+    if which == "starts":
+        # whole fits from the points; the second of two runs is reported
+        # (one run each at 1e5 points, where a slow combination takes seconds)
+        variants = ("fastpam1", "fastpam2", "fasterpam")
+        combos = [(i, v) for i in ("build", "random", "dw", "lab") for v in variants]
+        if large:
+            combos = [c for c in combos if c not in (("random", "fastpam1"), ("dw", "fastpam1"),
+                                                     ("lab", "fastpam1"), ("lab", "fastpam2"))]
+        for init, v in combos:
+            for _ in range(1 if large else 2):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                res = px.fit(X, k, init=init, variant=v, seed=3)
+                torch.cuda.synchronize()
+                wall = (time.perf_counter() - t) * 1e3
+            s = res.stats
+            run = {"start": init, "variant": v, "wall_ms": wall, "start_ms": s["ms_build"],
+                   "swap_ms": s["ms_swap"], "swaps": s["swaps"], "td": res.td}
+            out["runs"].append(run)
+            log("starts: %s" % run)
+        print(json.dumps(out))
+        return
     D = px.dist(X) if which in ("init", "clarans") else None
     for r in range(reps):
         torch.cuda.synchronize()
@@ -172,6 +201,58 @@ def run_next(which, large, reps):
     print(json.dumps(out))
 
 
+def run_form(which, reps):
+    """Time one of the other forms on its workload (see the module docstring)."""
+    import torch
+    import paper_2008_05171_amd as px
+    from paper_2008_05171_amd import datagen
+    from paper_2008_05171_amd import pamx as abi
+    out = {"form": which, "runs": []}
+    if which == "clara":
+        Xh = datagen.workload_gmm8_pool()
+        off, idx, ks = datagen.clara_samples(Xh.shape[0], 256, 10, 50, 2000, seed=1004)
+        X = torch.from_numpy(Xh).cuda()
+        idxd = torch.from_numpy(idx).cuda()
+        out["workload"] = ("gmm8 pool: 1e6 points d=8, 100 components; 256 CLARA instances, "
+                           "k ~ U{10..50}, n' ~ U{40+2k..2000}")
+        for r in range(reps):
+            res = px.fit_batched(X, off, idxd, ks)
+            s = res.stats
+            run = {"pam_ms": s["ms_pam"], "full_td_ms": s["ms_assign"], "pairs": s["pairs"],
+                   "pair_evals_per_s": s["pairs"] / (s["ms_pam"] / 1e3),
+                   "iterations": s["iterations"], "swaps": s["swaps"], "best": res.best,
+                   "td_full_best": res.td_full[res.best]}
+            out["runs"].append(run)
+            log("clara run %d: %s" % (r, run))
+        print(json.dumps(out))
+        return
+    if which == "bf16":
+        X = torch.from_numpy(datagen.workload_gmm64()).cuda()
+        k, kw = 200, dict(dist_mode="bf16")
+        out["workload"] = "gmm64: n=50000 d=64, 200 components, k=200, BF16 form (no stored matrix)"
+    else:
+        X = torch.from_numpy(datagen.workload_gmm32_zipf()).cuda()
+        k, kw = 500, dict(variant="fastpam2")
+        out["workload"] = ("gmm32 zipf: n=100000 d=32, 500 Zipf(1.1)-weighted components, k=500, "
+                           "eager FastPAM2 (40 GB matrix)")
+    n, dim = X.shape
+    opt = px._options(**kw)
+    opt.profile = 1
+    ws = torch.empty(abi.pamx_workspace_bytes(n, k, dim, abi.PAMX_INPUT_X, abi.PAMX_F32, opt),
+                     dtype=torch.uint8, device="cuda")
+    med = torch.empty(k, dtype=torch.int32, device="cuda")
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    for r in range(reps):
+        rc, td, st = abi.pamx_fit(X, abi.PAMX_INPUT_X, k, med, lab, ws, opt=opt)
+        run = {"rc": rc, "fit_ms": st.ms_total, "dist_ms": st.ms_dist, "build_ms": st.ms_build,
+               "swap_ms": st.ms_swap, "searches": st.iterations, "swaps": st.swaps,
+               "rescored": st.rescored,
+               "swap_pass_ms": st.ms_swap_pass / max(st.n_swap_pass, 1), "td": td}
+        out["runs"].append(run)
+        log("%s run %d: %s" % (which, r, run))
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,11 +268,16 @@ def main():
                     help="write the SWAP pass traffic record from two rocprofv3 --pmc runs of "
                          "this script with --copy-probe-mib, whose fits used chunk length CHUNK "
                          "(printed as config.chunk; no GPU work)")
-    ap.add_argument("--next", choices=("fasterpam", "init", "clarans"),
+    ap.add_argument("--next", choices=("fasterpam", "init", "clarans", "starts"),
                     help="time a row beyond the headline instead (one JSON line)")
     ap.add_argument("--large", action="store_true",
                     help="with --next: the 1e5-point, k=500 workload")
+    ap.add_argument("--form", choices=("bf16", "clara", "eager-large"),
+                    help="time another form on its own workload instead (one JSON line)")
     args = ap.parse_args()
+    if args.form:
+        run_form(args.form, max(args.steps, 1))
+        return
     if args.next:
         run_next(args.next, args.large, max(args.steps, 1))
         return
