@@ -7,7 +7,10 @@
 //                    (v_mfma_f32_32x32x2_f32), the root by the hardware instruction
 //                    (within 1 ulp; its error is small beside the Gram term's), 64 x 64
 //                    tiles staged in LDS and written back as full 256-byte row segments.
-//  Both write a zero diagonal and are bitwise symmetric.
+//  * k_dist_l2_f32_strip : the same entries for dim <= 64: a work-group keeps its
+//                    rows' points and walks four column tiles, loading the next
+//                    tile's points behind the current MFMA loop.
+//  All write a zero diagonal and are bitwise symmetric.
 #include "pamx_internal.h"
 
 namespace pamx {
@@ -163,11 +166,116 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32(const float *__restrict__ X
     }
 }
 
+// Strip form for dim <= kSD: a work-group keeps its 64 rows' points in LDS
+// and walks kCT column tiles of 64; the next tile's points are loaded into
+// registers before the current tile's MFMA loop (the load latency hides
+// behind it), and results go from the accumulators straight to D (per store
+// instruction each half-wave writes 32 consecutive floats of one row).  The
+// arithmetic of every entry, and its order, is the tiled kernel's: the same
+// centred values, the same MFMA sequence over coordinates, norms summed in
+// coordinate order, so D is again bitwise symmetric with a zero diagonal.
+// DP = the dimension padded to 16, 32 or 64 with zeros (0 x 0 products leave
+// every sum unchanged).
+constexpr int kSD = 64;       // largest dimension of the strip form
+constexpr int kCT = 4;        // column tiles per work-group
+template <int DP>
+__global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restrict__ X,
+                                                           const float *__restrict__ mean,
+                                                           int64_t n, int32_t dim,
+                                                           float *__restrict__ D, int64_t ld) {
+    constexpr int kSLd = DP + 1;           // padded row stride of the staged points
+    __shared__ float xa[kT * kSLd];
+    __shared__ float xb[kT * kSLd];
+    __shared__ float na[kT], nb[kT];
+    constexpr int kPer = kT * DP / 256;    // staged values per thread
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.y * kT;
+    const int64_t cb = (int64_t)blockIdx.x * (kT * kCT);
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+
+    // centred coordinates of 64 points (rows p0..p0+63) into registers
+    auto load = [&](int64_t p0, float (&v)[kPer]) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + u * 256;
+            const int r = e / DP, kk = e % DP;
+            v[u] = (kk < dim && p0 + r < n) ? X[(p0 + r) * dim + kk] - mean[kk] : 0.0f;
+        }
+    };
+    auto store = [&](float *x, const float (&v)[kPer]) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + u * 256;
+            x[(e / DP) * kSLd + e % DP] = v[u];
+        }
+    };
+    float va[kPer], vb[kPer];
+    load(r0, va);
+    load(cb, vb);
+    store(xa, va);
+    __syncthreads();
+    if (tid < 64) {
+        float s2 = 0.0f;
+        for (int kk = 0; kk < dim; ++kk) s2 = fmaf(xa[tid * kSLd + kk], xa[tid * kSLd + kk], s2);
+        na[tid] = s2;
+    }
+    const int i = lane & 31, h = lane >> 5;
+    for (int t = 0; t < kCT; ++t) {
+        const int64_t c0 = cb + (int64_t)t * kT;
+        if (c0 >= n) break;   // uniform
+        __syncthreads();      // the previous tile's reads of xb are done
+        store(xb, vb);
+        __syncthreads();
+        if (t + 1 < kCT && c0 + kT < n) load(c0 + kT, vb);   // next tile, in flight
+        if (tid >= 64 && tid < 128) {
+            const int c = tid - 64;
+            float s2 = 0.0f;
+            for (int kk = 0; kk < dim; ++kk) s2 = fmaf(xb[c * kSLd + kk], xb[c * kSLd + kk], s2);
+            nb[c] = s2;
+        }
+        floatx16 acc;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+#pragma unroll 8
+        for (int kk = 0; kk < DP; kk += 2) {
+            const float a = xa[(wr + i) * kSLd + kk + h];
+            const float b = xb[(wc + i) * kSLd + kk + h];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();      // nb complete
+        const int64_t c = c0 + wc + i;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int r = wr + 8 * (v >> 2) + 4 * h + (v & 3);
+            const float s = (na[r] + nb[wc + i]) - 2.0f * acc[v];
+            float d = __builtin_amdgcn_sqrtf(fmaxf(s, 0.0f));   // within 1 ulp; subnormals to 0
+            if (r0 + r == c) d = 0.0f;
+            if (r0 + r < n && c < n) D[(r0 + r) * ld + c] = d;
+        }
+    }
+}
+
 hipError_t launch_dist_l2_f32(const float *X, int64_t n, int32_t dim, float *D, int64_t ld,
                               float *mean, hipStream_t s) {
     hipLaunchKernelGGL(k_center_mean, dim3(dim), dim3(256), 0, s, X, n, dim, mean);
-    dim3 grid((unsigned)((n + kT - 1) / kT), (unsigned)((n + kT - 1) / kT));
-    hipLaunchKernelGGL(k_dist_l2_f32, grid, dim3(256), 0, s, X, (const float *)mean, n, dim, D, ld);
+    if (dim <= kSD) {
+        dim3 grid((unsigned)((n + kT * kCT - 1) / (kT * kCT)), (unsigned)((n + kT - 1) / kT));
+        if (dim <= 16)
+            hipLaunchKernelGGL(k_dist_l2_f32_strip<16>, grid, dim3(256), 0, s, X,
+                               (const float *)mean, n, dim, D, ld);
+        else if (dim <= 32)
+            hipLaunchKernelGGL(k_dist_l2_f32_strip<32>, grid, dim3(256), 0, s, X,
+                               (const float *)mean, n, dim, D, ld);
+        else
+            hipLaunchKernelGGL(k_dist_l2_f32_strip<64>, grid, dim3(256), 0, s, X,
+                               (const float *)mean, n, dim, D, ld);
+    } else {
+        dim3 grid((unsigned)((n + kT - 1) / kT), (unsigned)((n + kT - 1) / kT));
+        hipLaunchKernelGGL(k_dist_l2_f32, grid, dim3(256), 0, s, X, (const float *)mean, n, dim, D,
+                           ld);
+    }
     return hipGetLastError();
 }
 
