@@ -8,7 +8,7 @@
 //                    (within 1 ulp; its error is small beside the Gram term's), 64 x 64
 //                    tiles staged in LDS and written back as full 256-byte row segments.
 //  * k_dist_l2_f32_strip : the same entries for dim <= 64: a work-group keeps its
-//                    rows' points and walks four column tiles, loading the next
+//                    rows' points and walks two column tiles, loading the next
 //                    tile's points behind the current MFMA loop.
 //  All write a zero diagonal and are bitwise symmetric.
 #include "pamx_internal.h"
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32(const float *__restrict__ X
 // DP = the dimension padded to 16, 32 or 64 with zeros (0 x 0 products leave
 // every sum unchanged).
 constexpr int kSD = 64;       // largest dimension of the strip form
-constexpr int kCT = 4;        // column tiles per work-group
+constexpr int kCT = 2;        // column tiles per work-group (measured: 2 beats 4 and 8)
 template <int DP>
 __global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restrict__ X,
                                                            const float *__restrict__ mean,
