@@ -27,11 +27,13 @@ one FastCLARANS search; whole fits for every start x SWAP variant) on this
 workload, or with --large on the 1e5 x 32 Zipf mixture (k = 500, 40 GB
 matrix), and prints one JSON line of its timings.
 
---form bf16|clara|eager-large times one of the other forms on its own
+--form bf16|clara|eager-large|l1int times one of the other forms on its own
 workload and prints one JSON line: the mixed-precision form (n = 50000,
 d = 64, 200 components, k = 200, no stored matrix), 256 batched CLARA
-instances drawn from 1e6 points in 8 dimensions, or eager FastPAM2 on the
-1e5 x 32 Zipf mixture (k = 500, 40 GB matrix).
+instances drawn from 1e6 points in 8 dimensions (also run as 256 separate
+single-instance fits, for comparison), eager FastPAM2 on the 1e5 x 32 Zipf
+mixture (k = 500, 40 GB matrix), or exact Manhattan distances of n = 1000
+integer points (coordinates uniform on {0..999}^2, k = 5).
 """
 from __future__ import annotations
 
@@ -224,6 +226,40 @@ def run_form(which, reps):
                    "td_full_best": res.td_full[res.best]}
             out["runs"].append(run)
             log("clara run %d: %s" % (r, run))
+        # the same instances as separate fits (one pamx_fit per instance, the
+        # stored-matrix path on the sample's points)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        same = 0
+        for j in range(len(ks)):
+            sample = idxd[int(off[j]):int(off[j + 1])].long()
+            fr = px.fit(X[sample].contiguous(), int(ks[j]))
+            same += int(set(sample[fr.medoids.long()].tolist()) == set(res.medoids[j].tolist()))
+        torch.cuda.synchronize()
+        out["separate_fits"] = {"ms": (time.perf_counter() - t) * 1e3,
+                                "same_medoid_sets": same, "instances": len(ks)}
+        log("separate fits: %s" % out["separate_fits"])
+        print(json.dumps(out))
+        return
+    if which == "l1int":
+        out["workload"] = "l1 int: n=1000 d=2, coordinates uniform on {0..999}, k=5, exact Manhattan"
+        for seed in range(1001, 1001 + reps):
+            Xi = torch.from_numpy(datagen.int_points(1000, 2, 0, 1000, seed=seed)).cuda()
+            opt = px._options()
+            opt.profile = 1
+            ws = torch.empty(abi.pamx_workspace_bytes(1000, 5, 2, abi.PAMX_INPUT_X, abi.PAMX_I32,
+                                                      opt), dtype=torch.uint8, device="cuda")
+            med = torch.empty(5, dtype=torch.int32, device="cuda")
+            lab = torch.empty(1000, dtype=torch.int32, device="cuda")
+            for _ in range(2):   # the second fit is reported
+                rc, td, st = abi.pamx_fit(Xi, abi.PAMX_INPUT_X, 5, med, lab, ws,
+                                          metric=abi.PAMX_L1, opt=opt)
+            us = 1e3 * st.ms_swap_pass / max(st.n_swap_pass, 1)
+            run = {"seed": seed, "rc": rc, "fit_ms": st.ms_total, "searches": st.iterations,
+                   "swaps": st.swaps, "us_per_pass": us,
+                   "pair_evals_per_s": 1000 * 995 / (us * 1e-6), "td": td}
+            out["runs"].append(run)
+            log("l1int: %s" % run)
         print(json.dumps(out))
         return
     if which == "bf16":
@@ -272,7 +308,7 @@ def main():
                     help="time a row beyond the headline instead (one JSON line)")
     ap.add_argument("--large", action="store_true",
                     help="with --next: the 1e5-point, k=500 workload")
-    ap.add_argument("--form", choices=("bf16", "clara", "eager-large"),
+    ap.add_argument("--form", choices=("bf16", "clara", "eager-large", "l1int"),
                     help="time another form on its own workload instead (one JSON line)")
     args = ap.parse_args()
     if args.form:
