@@ -1050,9 +1050,10 @@ __global__ void k_fp_init(DevState *st, int64_t n, int64_t tile, int32_t vec, lo
 // The work-group (16 candidates) reports its first candidate at or after the
 // scan position whose best change is below the acceptance threshold.
 // candidates per window-merge work-group and the merge grid: 16 candidates
-// (64-byte column segments) on 64 work-groups measured faster than 4 on 256
+// (64-byte column segments) on 128 work-groups measured faster than 16 on 64,
+// 8 on 128 or 256, and 4 on 256
 constexpr int kFmCPB = 16;
-constexpr int kFmGrid = 64;
+constexpr int kFmGrid = 128;
 
 template <typename A>
 struct RunSum {
