@@ -45,7 +45,8 @@ def test_dist_l1_int_exact(n):
     assert np.array_equal(D.astype(np.float64), Dref)
 
 
-@pytest.mark.parametrize("n,dim", [(500, 16), (1001, 3), (130, 70), (65, 1)])
+@pytest.mark.parametrize("n,dim", [(500, 16), (1001, 3), (130, 70), (65, 1), (300, 17), (257, 33),
+                                   (200, 64), (129, 65)])
 def test_dist_l2_f32(n, dim):
     _say("dist_l2", n, dim)
     X = datagen.gaussian_mixture(n, dim, 5, seed=n + dim)
