@@ -457,7 +457,15 @@ __device__ __forceinline__ Top2<T> wave_scan_medoids(const T *__restrict__ D, in
                                                      int lane) {
     Top2<T> t{VT<T>::inf(), VT<T>::inf(), INT_MAX, INT_MAX};
     const T *row = D + o * ld;
-    for (int j = lane; j < k; j += 64) top2_insert(t, row[med[j]], j);
+    int j = lane;
+    for (; j + 192 < k; j += 256) {   // four loads in flight per lane
+        T d[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) d[u] = row[med[j + 64 * u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) top2_insert(t, d[u], j + 64 * u);
+    }
+    for (; j < k; j += 64) top2_insert(t, row[med[j]], j);
     for (int w = 32; w >= 1; w >>= 1) {
         const T e1 = __shfl_xor(t.d1, w), e2 = __shfl_xor(t.d2, w);
         const int32_t f1 = __shfl_xor(t.j1, w), f2 = __shfl_xor(t.j2, w);
@@ -526,6 +534,9 @@ __device__ __forceinline__ bool cache_update_o1(int slot, T dnew, int32_t &nr, i
 }
 
 // One wave per listed object (the list order varies, each result does not).
+// Up to kRsMed medoids, the list of medoids is staged in LDS first, so each
+// step of a rescan waits on one global load (the row entry), not two.
+constexpr int kRsMed = 4096;
 template <typename T>
 __global__ __launch_bounds__(256) void k_cache_rescan(const T *__restrict__ D, int64_t ld, int32_t k,
                                                       const int32_t *__restrict__ med,
@@ -535,13 +546,25 @@ __global__ __launch_bounds__(256) void k_cache_rescan(const T *__restrict__ D, i
                                                       const int32_t *__restrict__ rlist,
                                                       const DevState *__restrict__ st) {
     if (st->done || !st->swapped) return;
+    __shared__ int32_t smed[kRsMed];
     const int lane = threadIdx.x & 63;
     const int nw = gridDim.x * 4;
     const int m = st->n_list;
-    for (int idx = blockIdx.x * 4 + (threadIdx.x >> 6); idx < m; idx += nw) {
-        const int64_t o = rlist[idx];
-        const Top2<T> t = wave_scan_medoids<T>(D, ld, k, med, o, lane);
-        if (lane == 0) store_top2<T>(t, o, near, sec, dn, ds);
+    if (blockIdx.x * 4 >= m) return;   // no listed object for this work-group
+    if (k <= kRsMed) {
+        for (int j = threadIdx.x; j < k; j += 256) smed[j] = med[j];
+        __syncthreads();
+        for (int idx = blockIdx.x * 4 + (threadIdx.x >> 6); idx < m; idx += nw) {
+            const int64_t o = rlist[idx];
+            const Top2<T> t = wave_scan_medoids<T>(D, ld, k, smed, o, lane);
+            if (lane == 0) store_top2<T>(t, o, near, sec, dn, ds);
+        }
+    } else {
+        for (int idx = blockIdx.x * 4 + (threadIdx.x >> 6); idx < m; idx += nw) {
+            const int64_t o = rlist[idx];
+            const Top2<T> t = wave_scan_medoids<T>(D, ld, k, med, o, lane);
+            if (lane == 0) store_top2<T>(t, o, near, sec, dn, ds);
+        }
     }
 }
 
@@ -1649,8 +1672,12 @@ __global__ __launch_bounds__(kEgT) void k_eager_grid(
     __shared__ int32_t rl[kEgT];
     __shared__ int32_t nres;
     __shared__ A tot_s;
+    __shared__ int32_t smed[kRsMed];   // this work-group's copy of the medoids (k <= kRsMed)
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int G = gridDim.x;
+    const bool lmed = k <= kRsMed;
+    if (lmed)
+        for (int j = t; j < k; j += kEgT) smed[j] = med[j];   // published by the barrier below
     A thr;
     if constexpr (std::is_same<T, float>::value) thr = -st->margin; else thr = 0;
     // rank the negative slots by (value, slot), spread over the grid; every
@@ -1707,6 +1734,7 @@ __global__ __launch_bounds__(kEgT) void k_eager_grid(
             if (trace && st->swaps < st->trace_cap) trace[st->swaps] = pamx_swap_record{i, c, (double)tot};
             st->swaps += 1;
         }
+        if (lmed && t == 0) smed[i] = c;   // before the barriers below
         grid.sync();
         for (int64_t b0 = (int64_t)blockIdx.x * kEgT; b0 < n; b0 += stride) {
             if (t == 0) nres = 0;
@@ -1725,7 +1753,8 @@ __global__ __launch_bounds__(kEgT) void k_eager_grid(
             const int mr = nres;
             for (int idx = wv; idx < mr; idx += kEgT / 64) {
                 const int64_t q = rl[idx];
-                const Top2<T> tt = wave_scan_medoids<T>(D, ld, k, med, q, lane);
+                const Top2<T> tt = lmed ? wave_scan_medoids<T>(D, ld, k, smed, q, lane)
+                                        : wave_scan_medoids<T>(D, ld, k, med, q, lane);
                 if (lane == 0) store_top2<T>(tt, q, near, sec, dn, ds);
             }
             __syncthreads();
