@@ -34,37 +34,39 @@ constexpr int kBT = 1024;      // lanes per instance work-group
 constexpr int kBR = 2;         // candidates per lane: n' <= kBT * kBR
 constexpr int kBW = kBT / 64;  // waves per work-group
 
-// Point distances (MD = compile-time bound on the dimension): Euclidean in
-// FP32 for float points, exact Manhattan for int32 points.  The same
-// function serves every distance of an instance, so d(o,c) = d(c,o) and
-// d(o,o) = 0 exactly.
-template <int MD>
+// Point distances (MD = compile-time bound on the dimension; FULL: the
+// dimension equals MD, so no coordinate is tested and the loads go out
+// together): Euclidean in FP32 for float points, the root by the hardware
+// instruction (within 1 ulp; subnormals to 0), exact Manhattan for int32
+// points.  The same function serves every distance of an instance, so
+// d(o,c) = d(c,o) and d(o,o) = 0 exactly.
+template <int MD, bool FULL>
 __device__ __forceinline__ float pdist(const float *__restrict__ a, const float (&b)[MD], int dim) {
     float acc = 0.0f;
 #pragma unroll
     for (int d = 0; d < MD; ++d) {
-        if (d < dim) {
+        if (FULL || d < dim) {
             const float t = a[d] - b[d];
             acc = fmaf(t, t, acc);
         }
     }
-    return sqrtf(acc);
+    return __builtin_amdgcn_sqrtf(acc);
 }
 
-template <int MD>
+template <int MD, bool FULL>
 __device__ __forceinline__ int32_t pdist(const int32_t *__restrict__ a, const int32_t (&b)[MD],
                                          int dim) {
     int32_t acc = 0;
 #pragma unroll
     for (int d = 0; d < MD; ++d)
-        if (d < dim) acc += abs(a[d] - b[d]);
+        if (FULL || d < dim) acc += abs(a[d] - b[d]);
     return acc;
 }
 
-template <typename T, int MD>
+template <typename T, int MD, bool FULL>
 __device__ __forceinline__ void load_pt(const T *__restrict__ src, int dim, T (&b)[MD]) {
 #pragma unroll
-    for (int d = 0; d < MD; ++d) b[d] = (d < dim) ? src[d] : T(0);
+    for (int d = 0; d < MD; ++d) b[d] = (FULL || d < dim) ? src[d] : T(0);
 }
 
 // Work-group lexicographic argmin over (v, i, c): waves by butterfly, then
@@ -192,15 +194,15 @@ __device__ BLds<T> carve(unsigned char *base, int n_max, int k_max, int dim) {
 }
 
 // Nearest / second nearest of every object over the k medoids (fresh scan).
-template <typename T, int MD>
+template <typename T, int MD, bool FULL>
 __device__ void b_caches(const BLds<T> &L, int n, int k, int dim) {
     for (int o = threadIdx.x; o < n; o += kBT) {
         T b[MD];
-        load_pt<T, MD>(L.P + (size_t)o * dim, dim, b);
+        load_pt<T, MD, FULL>(L.P + (size_t)o * dim, dim, b);
         T d1 = VT<T>::inf(), d2 = VT<T>::inf();
         int j1 = INT_MAX;
         for (int j = 0; j < k; ++j) {
-            const T d = pdist<MD>(L.P + (size_t)L.med[j] * dim, b, dim);
+            const T d = pdist<MD, FULL>(L.P + (size_t)L.med[j] * dim, b, dim);
             if (d < d1) { d2 = d1; d1 = d; j1 = j; }
             else if (d < d2) { d2 = d; }
         }
@@ -208,7 +210,7 @@ __device__ void b_caches(const BLds<T> &L, int n, int k, int dim) {
     }
 }
 
-template <typename T, int MD>
+template <typename T, int MD, bool FULL>
 __global__ __launch_bounds__(kBT) void k_clara(
     const T *__restrict__ X, int64_t N, int32_t dim, const int64_t *__restrict__ soff,
     const int32_t *__restrict__ sidx, const int32_t *__restrict__ kin,
@@ -264,12 +266,12 @@ __global__ __launch_bounds__(kBT) void k_clara(
                 const int c = cb0 + tid + r * cstr;
                 if (c >= n || L.is_med[c]) continue;
                 T b[MD];
-                load_pt<T, MD>(L.P + (size_t)c * dim, dim, b);
+                load_pt<T, MD, FULL>(L.P + (size_t)c * dim, dim, b);
                 A acc;
                 if (step < 2) {
                     acc = 0;
                     for (int o = 0; o < n; ++o)
-                        acc += (A)vmin(pdist<MD>(L.P + (size_t)o * dim, b, dim), L.dn[o]);
+                        acc += (A)vmin(pdist<MD, FULL>(L.P + (size_t)o * dim, b, dim), L.dn[o]);
                 } else {
                     acc = acand[r];
                     // four listed objects at a time, their LDS reads issued
@@ -283,12 +285,12 @@ __global__ __launch_bounds__(kBT) void k_clara(
                             ob[u] = L.srow[q + u]; lo[u] = L.sdn[q + u]; hi[u] = L.sds[q + u];
                         }
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) d[u] = pdist<MD>(L.P + (size_t)ob[u] * dim, b, dim);
+                        for (int u = 0; u < 4; ++u) d[u] = pdist<MD, FULL>(L.P + (size_t)ob[u] * dim, b, dim);
 #pragma unroll
                         for (int u = 0; u < 4; ++u) acc += (A)vmin(d[u], hi[u]) - (A)vmin(d[u], lo[u]);
                     }
                     for (; q < nchg; ++q) {
-                        const T d = pdist<MD>(L.P + (size_t)L.srow[q] * dim, b, dim);
+                        const T d = pdist<MD, FULL>(L.P + (size_t)L.srow[q] * dim, b, dim);
                         acc += (A)vmin(d, L.sds[q]) - (A)vmin(d, L.sdn[q]);
                     }
                 }
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
             const int m = bc;
             if (tid == 0) { L.med[step] = m; L.is_med[m] = 1; }
             T b[MD];
-            load_pt<T, MD>(L.P + (size_t)m * dim, dim, b);
+            load_pt<T, MD, FULL>(L.P + (size_t)m * dim, dim, b);
             // dn update and the list of objects whose dn dropped
             int base = 0;
             for (int b0 = 0; b0 < n; b0 += kBT) {
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
                 bool chg = false;
                 T old = 0, nw = 0;
                 if (o < n) {
-                    const T d = pdist<MD>(L.P + (size_t)o * dim, b, dim);
+                    const T d = pdist<MD, FULL>(L.P + (size_t)o * dim, b, dim);
                     old = L.dn[o];
                     nw = (step == 0) ? d : vmin(old, d);
                     chg = nw < old;
@@ -341,7 +343,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
         // ---- FastPAM1 SWAP (Alg. 3)
         int iters = 0, swaps = 0;
         if (k >= 2 && k < n) {
-            b_caches<T, MD>(L, n, k, dim);
+            b_caches<T, MD, FULL>(L, n, k, dim);
             __syncthreads();
             while (iters < max_iter) {
                 ++iters;
@@ -403,7 +405,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
                     const int c = cb0 + tid + r * cstr;
                     if (c >= n || L.is_med[c]) continue;
                     T cb[MD];
-                    load_pt<T, MD>(L.P + (size_t)c * dim, dim, cb);
+                    load_pt<T, MD, FULL>(L.P + (size_t)c * dim, dim, cb);
                     A accA = 0, bv = VT<T>::acc_inf();
                     int bi = INT_MAX;
                     for (int s = 0; s < k; ++s) {
@@ -421,7 +423,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
                                 ob[u] = L.srow[q + u]; lo[u] = L.sdn[q + u]; hi[u] = L.sds[q + u];
                             }
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) d[u] = pdist<MD>(L.P + (size_t)ob[u] * dim, cb, dim);
+                            for (int u = 0; u < 4; ++u) d[u] = pdist<MD, FULL>(L.P + (size_t)ob[u] * dim, cb, dim);
 #pragma unroll
                             for (int u = 0; u < 4; ++u) {
                                 accA += (A)vmin(d[u], lo[u]);
@@ -429,7 +431,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
                             }
                         }
                         for (; q < q1; ++q) {
-                            const T d = pdist<MD>(L.P + (size_t)L.srow[q] * dim, cb, dim);
+                            const T d = pdist<MD, FULL>(L.P + (size_t)L.srow[q] * dim, cb, dim);
                             const T lo = L.sdn[q], hi = L.sds[q];
                             accA += (A)vmin(d, lo);
                             M += (A)vmed3(d, lo, hi);
@@ -457,7 +459,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
                 }
                 ++swaps;
                 __syncthreads();
-                b_caches<T, MD>(L, n, k, dim);
+                b_caches<T, MD, FULL>(L, n, k, dim);
                 __syncthreads();
             }
         }
@@ -465,7 +467,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
         if (k >= 2 && k < n) {
             // caches are current after the last swap
         } else {
-            b_caches<T, MD>(L, n, k, dim);
+            b_caches<T, MD, FULL>(L, n, k, dim);
         }
         __syncthreads();
         A td = 0;
@@ -498,7 +500,7 @@ __global__ __launch_bounds__(256) void k_check_sidx(const int32_t *__restrict__ 
 // Runs after k_clara: if that kernel flagged a bad sample index, some
 // instances wrote no medoids, so nothing is read; every medoid index is also
 // checked against [0, N) before it addresses X.
-template <typename T, int MD>
+template <typename T, int MD, bool FULL>
 __global__ __launch_bounds__(256) void k_full_assign(const T *__restrict__ X, int64_t N,
                                                      int32_t dim,
                                                      const int32_t *__restrict__ med_out,
@@ -529,9 +531,9 @@ __global__ __launch_bounds__(256) void k_full_assign(const T *__restrict__ X, in
     A s = 0;
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (int64_t)nblk * 256) {
         T b[MD];
-        load_pt<T, MD>(X + p * dim, dim, b);
+        load_pt<T, MD, FULL>(X + p * dim, dim, b);
         T best = VT<T>::inf();
-        for (int m = 0; m < k; ++m) best = vmin(best, pdist<MD>(mc + m * dim, b, dim));
+        for (int m = 0; m < k; ++m) best = vmin(best, pdist<MD, FULL>(mc + m * dim, b, dim));
         s += (A)best;
     }
     red[threadIdx.x] = s;
@@ -556,15 +558,15 @@ size_t batched_lds_bytes_host(int n_max, int k_max, int dim, size_t esz) {
     return batched_lds_bytes(n_max, k_max, dim, esz);
 }
 
-template <typename T, int MD>
+template <typename T, int MD, bool FULL>
 static hipError_t launch_clara_md(const T *X, int64_t N, int32_t dim, const BatchArgs &a,
                                   hipStream_t s) {
     const size_t lds = batched_lds_bytes(a.n_max, a.k_max, dim, sizeof(T));
-    const void *fn = reinterpret_cast<const void *>(&k_clara<T, MD>);
+    const void *fn = reinterpret_cast<const void *>(&k_clara<T, MD, FULL>);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (!a.coop) {
-        hipLaunchKernelGGL((k_clara<T, MD>), dim3(a.grid), dim3(kBT), lds, s, X, N, dim, a.soff,
+        hipLaunchKernelGGL((k_clara<T, MD, FULL>), dim3(a.grid), dim3(kBT), lds, s, X, N, dim, a.soff,
                            a.sidx, a.kin, a.moff, a.tk_inst, a.tk_mem, a.tsz, a.n_tick, a.max_iter,
                            a.excl, a.n_max, a.k_max, a.med_out, a.td_out, a.tdb_out, a.it_out,
                            a.sw_out, a.rows_out, a.queue, a.bar, a.xch, a.err);
@@ -592,15 +594,21 @@ static hipError_t launch_clara_md(const T *X, int64_t N, int32_t dim, const Batc
     return hipLaunchCooperativeKernel(fn, dim3(a.grid), dim3(kBT), args, (unsigned)lds, s);
 }
 
-template <typename T, int MD>
-static int resident_md(size_t lds) {
-    const void *fn = reinterpret_cast<const void *>(&k_clara<T, MD>);
+template <typename T, int MD, bool FULL>
+static int resident_md1(size_t lds) {
+    const void *fn = reinterpret_cast<const void *>(&k_clara<T, MD, FULL>);
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_clara<T, MD>, kBT, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_clara<T, MD, FULL>, kBT, lds) !=
+        hipSuccess)
         return 0;
     return per;
+}
+// the variant launch_clara picks for this dimension
+template <typename T, int MD>
+static int resident_md(int32_t dim, size_t lds) {
+    return dim == MD ? resident_md1<T, MD, true>(lds) : resident_md1<T, MD, false>(lds);
 }
 
 int batched_resident(int32_t dim, size_t lds, int32_t dtype, int *coop) {
@@ -611,25 +619,34 @@ int batched_resident(int32_t dim, size_t lds, int32_t dtype, int *coop) {
     if (hipDeviceGetAttribute(&c, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess) *coop = c;
     int per;
     if (dtype == PAMX_F32)
-        per = dim <= 4 ? resident_md<float, 4>(lds)
-                       : (dim <= 8 ? resident_md<float, 8>(lds) : resident_md<float, kBMaxDim>(lds));
+        per = dim <= 4 ? resident_md<float, 4>(dim, lds)
+                       : (dim <= 8 ? resident_md<float, 8>(dim, lds)
+                                   : resident_md<float, kBMaxDim>(dim, lds));
     else
-        per = dim <= 4 ? resident_md<int32_t, 4>(lds)
-                       : (dim <= 8 ? resident_md<int32_t, 8>(lds) : resident_md<int32_t, kBMaxDim>(lds));
+        per = dim <= 4 ? resident_md<int32_t, 4>(dim, lds)
+                       : (dim <= 8 ? resident_md<int32_t, 8>(dim, lds)
+                                   : resident_md<int32_t, kBMaxDim>(dim, lds));
     return per * cus;
 }
 
 template <typename T>
 hipError_t launch_clara(const T *X, int64_t N, int32_t dim, const BatchArgs &a, hipStream_t s) {
-    if (dim <= 4) return launch_clara_md<T, 4>(X, N, dim, a, s);
-    if (dim <= 8) return launch_clara_md<T, 8>(X, N, dim, a, s);
-    return launch_clara_md<T, kBMaxDim>(X, N, dim, a, s);
+    if (dim == 4) return launch_clara_md<T, 4, true>(X, N, dim, a, s);
+    if (dim < 4) return launch_clara_md<T, 4, false>(X, N, dim, a, s);
+    if (dim == 8) return launch_clara_md<T, 8, true>(X, N, dim, a, s);
+    if (dim < 8) return launch_clara_md<T, 8, false>(X, N, dim, a, s);
+    if (dim == kBMaxDim) return launch_clara_md<T, kBMaxDim, true>(X, N, dim, a, s);
+    return launch_clara_md<T, kBMaxDim, false>(X, N, dim, a, s);
 }
 
 template <typename T, int MD>
 static void launch_full_md(const T *X, int64_t N, int32_t dim, const BatchArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_full_assign<T, MD>), dim3(a.nblk, a.n_inst), dim3(256), 0, s, X, N, dim,
-                       (const int32_t *)a.med_out, a.moff, a.nblk, a.part, a.err);
+    if (dim == MD)
+        hipLaunchKernelGGL((k_full_assign<T, MD, true>), dim3(a.nblk, a.n_inst), dim3(256), 0, s, X,
+                           N, dim, (const int32_t *)a.med_out, a.moff, a.nblk, a.part, a.err);
+    else
+        hipLaunchKernelGGL((k_full_assign<T, MD, false>), dim3(a.nblk, a.n_inst), dim3(256), 0, s,
+                           X, N, dim, (const int32_t *)a.med_out, a.moff, a.nblk, a.part, a.err);
 }
 
 template <typename T>
