@@ -65,7 +65,11 @@ extern "C" {
 
 /* SWAP variants */
 #define PAMX_FASTPAM1 1 /* best swap per iteration (Alg. 3)               */
-#define PAMX_FASTPAM2 2 /* best swap per medoid, applied eagerly (Sec. 3.2) */
+#define PAMX_FASTPAM2 2 /* best swap per medoid, applied eagerly (Sec. 3.2); the
+                           eager application runs over the whole device under a
+                           cooperative launch, or in one work-group when the
+                           device has none or the environment sets
+                           PAMX_COOPERATIVE=0 (equal results either way) */
 #define PAMX_FASTERPAM 3 /* FasterPAM (Alg. 4, Sec. 3.2): the candidates are
                             visited in index order, cyclically; each takes its
                             best slot (smallest on ties) and is swapped in at
@@ -343,7 +347,11 @@ int pamx_batched_workspace_bytes(int32_t n_inst, int64_t N, size_t *bytes);
  *               indices, slot order) start at sum_{j'<j} k_j'
  *   td_sample   HOST double[n_inst]: TD of each run on its own sample
  *   td_full     HOST double[n_inst] or NULL: TD over all N points; when
- *               given, stats->best_inst is the CLARA result */
+ *               given, stats->best_inst is the CLARA result
+ * Large instances run as teams of up to 8 work-groups under a cooperative
+ * launch (same results as one work-group each); setting the environment
+ * variable PAMX_COOPERATIVE=0 (read on every call) turns teams off.  A team
+ * that fails to meet within its bounded wait returns PAMX_ERR_HIP. */
 int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t dim, int32_t metric,
                      int32_t n_inst, const int64_t *sample_off, const int32_t *sample_idx,
                      const int32_t *k_inst, const pamx_options *opt, int32_t *medoids,

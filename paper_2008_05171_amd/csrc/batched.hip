@@ -616,7 +616,9 @@ int batched_resident(int32_t dim, size_t lds, int32_t dtype, int *coop) {
     *coop = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&c, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess) *coop = c;
+    if (cooperative_allowed() &&
+        hipDeviceGetAttribute(&c, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess)
+        *coop = c;
     int per;
     if (dtype == PAMX_F32)
         per = dim <= 4 ? resident_md<float, 4>(dim, lds)

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <cstdlib>
 #include <stdint.h>
 #include <climits>
 #include <cmath>
@@ -204,6 +205,13 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
 // Grid for the cooperative FastPAM2 eager apply over n objects on the
 // current device (0: the device has no cooperative launch).
 int32_t eager_grid(int64_t n, int32_t dtype);
+// Cooperative launches (the FastPAM2 eager apply over the whole chip, teams
+// of batched instances) unless the environment sets PAMX_COOPERATIVE=0,
+// read on every call: the one-work-group forms then run, with equal results.
+inline bool cooperative_allowed() {
+    const char *e = std::getenv("PAMX_COOPERATIVE");
+    return !(e && e[0] == '0');
+}
 hipError_t launch_transpose(const void *D, int64_t ld, int64_t rows, int64_t cols, void *DT,
                             int64_t ldt, hipStream_t s);
 // re-place the chunk-dependent regions (after L->head) for chunk length Lc

@@ -1773,6 +1773,7 @@ __global__ __launch_bounds__(kEgT) void k_eager_grid(
 template <typename T>
 static int32_t eager_grid_t(int64_t n) {
     int dev = 0, coop = 0, cus = 0, per = 0;
+    if (!cooperative_allowed()) return 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
         return 0;

@@ -97,6 +97,27 @@ def test_batched_teams_int_bitexact():
         assert res.td_full[j] == tdf, j
 
 
+def test_batched_teams_off_equal(monkeypatch):
+    """PAMX_COOPERATIVE=0 turns the teams off: every instance on one
+    work-group, with the same results as the teams."""
+    _say("batched_teams_off")
+    X = datagen.int_points(20000, 3, 0, 1000, seed=12)
+    sizes = [1800, 700, 260, 90]
+    ks = np.array([12, 7, 4, 3], np.int32)
+    rng = np.random.default_rng(12)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    idx = np.concatenate([np.sort(rng.choice(20000, size=m, replace=False))
+                          for m in sizes]).astype(np.int32)
+    teams = _run(X, off, idx, ks)
+    monkeypatch.setenv("PAMX_COOPERATIVE", "0")
+    single = _run(X, off, idx, ks)
+    for j in range(len(ks)):
+        assert torch.equal(teams.medoids[j], single.medoids[j]), j
+        assert teams.td_sample[j] == single.td_sample[j] and teams.td_full[j] == single.td_full[j]
+    assert teams.stats["iterations"] == single.stats["iterations"]
+    assert teams.stats["swaps"] == single.stats["swaps"]
+
+
 def test_batched_edge_cases():
     _say("batched_edges")
     X = datagen.int_points(3000, 3, 0, 50, seed=9)

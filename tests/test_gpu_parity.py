@@ -177,6 +177,35 @@ def test_fastpam2_int_bitexact(seed, n, k, hi):
     assert res.stats["iterations"] == ref.iterations
 
 
+@pytest.mark.parametrize("seed,n,k,hi", [(24, 900, 20, 100), (25, 2000, 40, 1000)])
+def test_fastpam2_one_workgroup_apply_equals_grid(seed, n, k, hi, monkeypatch):
+    """The eager apply over the whole chip (cooperative launch) and the
+    one-work-group form (PAMX_COOPERATIVE=0) perform the same visits and
+    swaps: both bit-exact against the oracle on integer distances."""
+    _say("fastpam2_coop", seed, n, k)
+    X, D = _int_case(n, seed, hi=hi)
+    ref = oracle.pam(k, D=D, variant=oracle.FASTPAM2)
+    grid = px().fit(_t(X), k, variant="fastpam2", trace=True)
+    monkeypatch.setenv("PAMX_COOPERATIVE", "0")
+    one = px().fit(_t(X), k, variant="fastpam2", trace=True)
+    _check_same(grid, ref, k)
+    _check_same(one, ref, k)
+
+
+def test_fastpam2_one_workgroup_apply_float(monkeypatch):
+    """FP32 matrix: the two forms add the re-score sums in different orders,
+    so only rounding may differ; the swaps are the same."""
+    _say("fastpam2_coop_float")
+    X = datagen.gaussian_mixture(3000, 8, 30, seed=26)
+    D32 = oracle.dist_matrix(X.astype(np.float64), oracle.L2).astype(np.float32)
+    grid = px().fit(_t(D32), 30, input_kind=px().PAMX_INPUT_D, variant="fastpam2", trace=True)
+    monkeypatch.setenv("PAMX_COOPERATIVE", "0")
+    one = px().fit(_t(D32), 30, input_kind=px().PAMX_INPUT_D, variant="fastpam2", trace=True)
+    assert [(s, c) for s, c, _ in grid.trace] == [(s, c) for s, c, _ in one.trace]
+    assert torch.equal(grid.medoids, one.medoids) and torch.equal(grid.labels, one.labels)
+    assert abs(grid.td - one.td) <= 1e-12 * one.td
+
+
 # ------------------------------------------------------------------ float matrices
 @pytest.mark.parametrize("variant", ["fastpam1", "fastpam2"])
 def test_float_matrix_matches_oracle(variant):
