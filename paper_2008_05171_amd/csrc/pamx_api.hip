@@ -143,7 +143,7 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->cand_v = take(8);
     L->cand_i = take(8);
     L->cand_a = take((size_t)L->ncp * 8);
-    // >= n_mwg, and >= the window-merge grid (256)
+    // >= n_mwg, >= the SWAP merge grid (ncp / 64) and >= the window-merge grid (256)
     const size_t nwg = (size_t)(L->ncp / 16) > 256 ? (size_t)(L->ncp / 16) : 256;
     L->wg_v = take(nwg * 8);
     L->wg_i = take(nwg * 4);

@@ -877,10 +877,21 @@ __global__ __launch_bounds__(kWG) void k_swap_pass(
     }
 }
 
-// ---- merge chunk partials per candidate (fixed chunk order).
-// Writes, per candidate, its best change over slots (FastPAM1) and the
-// work-group's best (value, slot, candidate); for FastPAM2 it completes
-// P[i][c] for carried segments and stores B(c) = A(c) - TD.
+// ---- merge chunk partials per candidate (fixed order).
+// A work-group takes kSmC candidates; each candidate's chunks are split into
+// kSmG consecutive groups, one thread each, which reduce their chunks to a
+// run summary (A, the best segment complete in the group, the first and the
+// last segment run); the candidate's first thread combines the kSmG
+// summaries in chunk order (as the window merge of FasterPAM does).  Writes,
+// per candidate, its best change over slots and the work-group's best
+// (value, slot, candidate); for FastPAM2 it completes P[i][c] for segments
+// carried across chunks and stores B(c) = A(c) - TD.
+constexpr int kSmC = 64, kSmG = kWG / kSmC;
+template <typename A>
+struct RunSum {
+    A accA, bv, fm, fdn, lm, ldn;
+    int32_t bi, nr, fs, ls;   // nr: runs seen (0, 1, 2 = more than one)
+};
 template <typename T, bool P2>
 __global__ __launch_bounds__(kWG) void k_swap_merge(
     const AccT<T> *__restrict__ part, const int32_t *__restrict__ part_i,
@@ -890,67 +901,94 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
     AccT<T> *__restrict__ wg_v, int32_t *__restrict__ wg_i, int32_t *__restrict__ wg_c) {
     using A = AccT<T>;
     if (st->done) return;
-    const int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    A bestv = VT<T>::acc_inf();
-    int besti = INT_MAX;
-    int cc = INT_MAX;
-    if (c < nc) {
-        A accA = 0;
-        int run_s = -1;
-        A run_m = 0, run_dn = 0;
-        auto flush = [&]() {
-            if (run_s >= 0) {
-                const A v = run_m - run_dn;
-                if (lt2(v, run_s, bestv, besti)) { bestv = v; besti = run_s; }
-                if constexpr (P2) P[(int64_t)run_s * ncp + c] = v;
+    __shared__ RunSum<A> sm[kSmG][kSmC];
+    const int j = threadIdx.x % kSmC, g = threadIdx.x / kSmC;
+    const int64_t c = (int64_t)blockIdx.x * kSmC + j;
+    const bool live = c < nc;
+    RunSum<A> r;
+    r.accA = 0; r.bv = VT<T>::acc_inf(); r.bi = INT_MAX; r.nr = 0;
+    r.fs = -1; r.fm = 0; r.fdn = 0; r.ls = -1; r.lm = 0; r.ldn = 0;
+    if (live) {
+        const int per = (Q + kSmG - 1) / kSmG;
+        const int q0 = g * per, q1 = min(Q, q0 + per);
+        // the open run is (fs, fm, fdn) while nr == 1, else (ls, lm, ldn)
+        auto add = [&](int s, A m, A dn) {
+            if (r.nr == 0) { r.nr = 1; r.fs = s; r.fm = m; r.fdn = dn; return; }
+            if (r.nr == 1) {
+                if (s == r.fs) { r.fm += m; r.fdn += dn; }
+                else { r.nr = 2; r.ls = s; r.lm = m; r.ldn = dn; }
+                return;
             }
+            if (s == r.ls) { r.lm += m; r.ldn += dn; return; }
+            const A v = r.lm - r.ldn;   // a run between the first and the last: complete
+            if (lt2(v, r.ls, r.bv, r.bi)) { r.bv = v; r.bi = r.ls; }
+            if constexpr (P2) P[(int64_t)r.ls * ncp + c] = v;
+            r.ls = s; r.lm = m; r.ldn = dn;
         };
         constexpr int UQ = 8;   // chunks whose partials are loaded together
-        for (int q0 = 0; q0 < Q; q0 += UQ) {
-            A xa[UQ], xh[UQ], xt[UQ], xv[UQ];
+        for (int qa = q0; qa < q1; qa += UQ) {
+            A xa[UQ], xh[UQ], xt[UQ], xv[UQ], dh[UQ], dt[UQ];
             int32_t xi[UQ];
+            ChunkInfo ci[UQ];
 #pragma unroll
             for (int u = 0; u < UQ; ++u) {
-                if (q0 + u < Q) {
-                    const A *pq = part + (int64_t)(q0 + u) * 4 * ncp + c;
-                    xa[u] = pq[0];
-                    xh[u] = pq[1 * ncp];   // read even when unused (never written then)
-                    xt[u] = pq[2 * ncp];
-                    xv[u] = pq[3 * ncp];
-                    xi[u] = part_i[(int64_t)(q0 + u) * ncp + c];
-                }
+                const int q = min(qa + u, q1 - 1);   // clamped: every load in bounds
+                const A *pq = part + (int64_t)q * 4 * ncp + c;
+                xa[u] = pq[0];
+                xh[u] = pq[1 * ncp];   // read even when unused (never written then)
+                xt[u] = pq[2 * ncp];
+                xv[u] = pq[3 * ncp];
+                xi[u] = part_i[(int64_t)q * ncp + c];
+                ci[u] = cinfo[q];
+                dh[u] = cdn[2 * q];
+                dt[u] = cdn[2 * q + 1];
             }
 #pragma unroll
             for (int u = 0; u < UQ; ++u) {
-                if (q0 + u >= Q) break;
-                const ChunkInfo ci = cinfo[q0 + u];
-                accA += xa[u];
-                if (xi[u] != INT_MAX && lt2(xv[u], xi[u], bestv, besti)) { bestv = xv[u]; besti = xi[u]; }
-                if (ci.flags & kHead) {
-                    const A dh = cdn[2 * (q0 + u)];
-                    if (ci.sa == run_s) { run_m += xh[u]; run_dn += dh; }
-                    else { flush(); run_s = ci.sa; run_m = xh[u]; run_dn = dh; }
-                }
-                if (ci.flags & kTail) {
-                    const A dt = cdn[2 * (q0 + u) + 1];
-                    if (ci.sb == run_s) { run_m += xt[u]; run_dn += dt; }
-                    else { flush(); run_s = ci.sb; run_m = xt[u]; run_dn = dt; }
-                }
+                if (qa + u >= q1) break;
+                r.accA += xa[u];
+                if (xi[u] != INT_MAX && lt2(xv[u], xi[u], r.bv, r.bi)) { r.bv = xv[u]; r.bi = xi[u]; }
+                if (ci[u].flags & kHead) add(ci[u].sa, xh[u], dh[u]);
+                if (ci[u].flags & kTail) add(ci[u].sb, xt[u], dt[u]);
             }
         }
-        flush();
+    }
+    sm[g][j] = r;
+    __syncthreads();
+    A bestv = VT<T>::acc_inf();
+    int besti = INT_MAX, cc = INT_MAX;
+    if (g == 0 && live) {
+        A accA = 0, bv = VT<T>::acc_inf(), rm = 0, rdn = 0;
+        int bi = INT_MAX, rs = -1;
+        auto flush = [&](int s, A m, A dn) {
+            if (s < 0) return;
+            const A v = m - dn;
+            if (lt2(v, s, bv, bi)) { bv = v; bi = s; }
+            if constexpr (P2) P[(int64_t)s * ncp + c] = v;
+        };
+        for (int h = 0; h < kSmG; ++h) {
+            const RunSum<A> &x = sm[h][j];
+            accA += x.accA;
+            if (x.bi != INT_MAX && lt2(x.bv, x.bi, bv, bi)) { bv = x.bv; bi = x.bi; }
+            if (x.nr == 0) continue;
+            if (x.fs == rs) { rm += x.fm; rdn += x.fdn; }
+            else { flush(rs, rm, rdn); rs = x.fs; rm = x.fm; rdn = x.fdn; }
+            if (x.nr == 2) {   // the first run ended inside the group
+                flush(rs, rm, rdn);
+                rs = x.ls; rm = x.lm; rdn = x.ldn;
+            }
+        }
+        flush(rs, rm, rdn);
         const int e = st->empty_slot;   // an empty slot changes by 0 + B(c)
-        if (e < k && lt2((A)0, e, bestv, besti)) { bestv = 0; besti = e; }
+        if (e < k && lt2((A)0, e, bv, bi)) { bv = 0; bi = e; }
         A td;
         if constexpr (std::is_same<T, float>::value) td = st->td; else td = st->td_i;
         const A bsh = accA - td;
         if constexpr (P2) cand_a[c] = bsh;
         if (!is_med[c]) {
-            bestv = bestv + bsh;
+            bestv = bv + bsh;
+            besti = bi;
             cc = (int)c;
-        } else {
-            bestv = VT<T>::acc_inf();
-            besti = INT_MAX;
         }
     }
     block_argmin3<A, kWG>(bestv, besti, cc);
@@ -1078,11 +1116,6 @@ __global__ void k_fp_init(DevState *st, int64_t n, int64_t tile, int32_t vec, lo
 constexpr int kFmCPB = 16;
 constexpr int kFmGrid = 128;
 
-template <typename A>
-struct RunSum {
-    A accA, bv, fm, fdn, lm, ldn;
-    int32_t bi, nr, fs, ls;   // nr: runs seen (0, 1, 2 = more than one)
-};
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_fp_merge(
@@ -1931,6 +1964,7 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
     const bool p2 = opt.variant == PAMX_FASTPAM2;
     pamx_swap_record *trace = static_cast<pamx_swap_record *>(opt.trace);
     const unsigned ob = (unsigned)((n + 255) / 256);
+    const int32_t smwg = (int32_t)((L.nc + kSmC - 1) / kSmC);   // SWAP merge work-groups
 
     if (opt.variant == PAMX_FASTERPAM) {
         // one window of the scan (segments are rebuilt only after a swap)
@@ -1958,7 +1992,7 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
     enqueue_pass<T>(D, ld, L, p, p2, s);
     if (ev1) (void)hipEventRecord(ev1, s);
     if (p2) {
-        hipLaunchKernelGGL((k_swap_merge<T, true>), dim3(L.n_mwg), dim3(kWG), 0, s,
+        hipLaunchKernelGGL((k_swap_merge<T, true>), dim3(smwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
                            L.Q, L.nc, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
                            (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
@@ -1996,14 +2030,14 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
                                (const int32_t *)p.slot_c, p.order, p.rlist, p.st, trace);
         }
     } else {
-        hipLaunchKernelGGL((k_swap_merge<T, false>), dim3(L.n_mwg), dim3(kWG), 0, s,
+        hipLaunchKernelGGL((k_swap_merge<T, false>), dim3(smwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
                            L.Q, L.nc, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
                            (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
         int64_t ldl;
         const T *Dl = loc_rows<T>(D, ld, L, ws, &ldl);
         hipLaunchKernelGGL(k_select_update<T>, dim3(ob), dim3(256), 0, s, (const A *)p.wg_v,
-                           (const int32_t *)p.wg_i, (const int32_t *)p.wg_c, L.n_mwg, Dl, ldl, n,
+                           (const int32_t *)p.wg_i, (const int32_t *)p.wg_c, smwg, Dl, ldl, n,
                            medoids, p.is_med, p.near, p.sec, p.dn, p.ds, p.rlist, p.st, trace);
         // the rescan reads row o of D at the medoid columns (consumer rows)
         hipLaunchKernelGGL(k_cache_rescan<T>, dim3(256), dim3(256), 0, s, D, ld, k,
