@@ -1680,13 +1680,16 @@ __global__ __launch_bounds__(1024) void k_eager_apply(
 //      and writes the sum to red[parity][b];
 //   2. grid barrier; every work-group adds red[parity][0..G) in one fixed
 //      order, so all take the same decision on the same value;
-//   3. if the swap is applied, work-group 0 records it (medoids, TD, trace),
-//      grid barrier, then every work-group updates its objects (O(1) rule,
-//      wave rescans of those that lost their nearest or second medoid).
-// The partials alternate between two halves of red, so a work-group still
-// reading one visit's sums is never overtaken by the next visit's writes
-// (a barrier lies between).  Loops and branches are uniform over the grid:
-// every work-group reaches every barrier.
+//   3. if the swap is applied, work-group 0 records it (medoids, TD, trace)
+//      and every work-group updates its objects (O(1) rule, wave rescans of
+//      those that lost their nearest or second medoid).
+// Up to kRsMed medoids, every work-group keeps its own copy of the medoids
+// in LDS (it answers "is c a medoid now" and serves the rescans), so a visit
+// needs one grid barrier; above that, a second barrier publishes work-group
+// 0's medoid arrays before the rescans.  The partials alternate between two
+// halves of red, so a work-group still reading one visit's sums is never
+// overtaken by the next visit's writes (a barrier lies between).  Loops and
+// branches are uniform over the grid: every work-group reaches every barrier.
 constexpr int kEgT = 256;       // threads (and objects per round) of a work-group
 constexpr int kEgMax = 1024;    // largest grid (red holds 2 * kEgMax sums)
 template <typename T>
@@ -1735,7 +1738,15 @@ __global__ __launch_bounds__(kEgT) void k_eager_grid(
     for (int r = 0; r < m; ++r) {
         const int i = order[r];
         const int c = slot_c[i];
-        if (is_med[c]) continue;   // same byte for every thread of the grid
+        bool taken;   // c is a medoid now: the same answer in every work-group
+        if (lmed) {
+            int hit = 0;
+            for (int jj = t; jj < k; jj += kEgT) hit |= (smed[jj] == c);
+            taken = __syncthreads_or(hit) != 0;
+        } else {
+            taken = is_med[c] != 0;
+        }
+        if (taken) continue;
         const T *rowc = D + (int64_t)c * ld;
         A s = 0;
         for (int64_t o = o0; o < n; o += stride) {
@@ -1767,8 +1778,14 @@ __global__ __launch_bounds__(kEgT) void k_eager_grid(
             if (trace && st->swaps < st->trace_cap) trace[st->swaps] = pamx_swap_record{i, c, (double)tot};
             st->swaps += 1;
         }
-        if (lmed && t == 0) smed[i] = c;   // before the barriers below
-        grid.sync();
+        if (lmed) {
+            // every work-group updates its own copy of the medoids, so no
+            // work-group reads what work-group 0 just wrote: no barrier
+            if (t == 0) smed[i] = c;
+            __syncthreads();
+        } else {
+            grid.sync();   // med and is_med from work-group 0 before the rescans
+        }
         for (int64_t b0 = (int64_t)blockIdx.x * kEgT; b0 < n; b0 += stride) {
             if (t == 0) nres = 0;
             __syncthreads();
