@@ -171,9 +171,10 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32(const float *__restrict__ X
 // registers before the current tile's MFMA loop (the load latency hides
 // behind it), and results go from the accumulators straight to D (per store
 // instruction each half-wave writes 32 consecutive floats of one row).  The
-// arithmetic of every entry, and its order, is the tiled kernel's: the same
-// centred values, the same MFMA sequence over coordinates, norms summed in
-// coordinate order, so D is again bitwise symmetric with a zero diagonal.
+// Gram term of every entry is the tiled kernel's (the same centred values and
+// MFMA sequence over coordinates); squared norms are summed by four threads per
+// point in a fixed order, the same for rows and columns, so D is again bitwise
+// symmetric with a zero diagonal.
 // DP = the dimension padded to 16, 32 or 64 with zeros (0 x 0 products leave
 // every sum unchanged).
 constexpr int kSD = 64;       // largest dimension of the strip form
@@ -211,16 +212,24 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restri
             x[(e / DP) * kSLd + e % DP] = v[u];
         }
     };
+    // squared norms of the 64 staged points: four threads per point, each
+    // over a quarter of the (padded) coordinates, then a fixed butterfly
+    auto norms = [&](const float *x, float *nrm) {
+        const int pnt = tid >> 2, part = tid & 3;
+        float s2 = 0.0f;
+#pragma unroll
+        for (int kk = part * (DP / 4); kk < (part + 1) * (DP / 4); ++kk)
+            s2 = fmaf(x[pnt * kSLd + kk], x[pnt * kSLd + kk], s2);
+        s2 += __shfl_xor(s2, 1);
+        s2 += __shfl_xor(s2, 2);
+        if (part == 0) nrm[pnt] = s2;
+    };
     float va[kPer], vb[kPer];
     load(r0, va);
     load(cb, vb);
     store(xa, va);
     __syncthreads();
-    if (tid < 64) {
-        float s2 = 0.0f;
-        for (int kk = 0; kk < dim; ++kk) s2 = fmaf(xa[tid * kSLd + kk], xa[tid * kSLd + kk], s2);
-        na[tid] = s2;
-    }
+    norms(xa, na);
     const int i = lane & 31, h = lane >> 5;
     for (int t = 0; t < kCT; ++t) {
         const int64_t c0 = cb + (int64_t)t * kT;
@@ -229,12 +238,7 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restri
         store(xb, vb);
         __syncthreads();
         if (t + 1 < kCT && c0 + kT < n) load(c0 + kT, vb);   // next tile, in flight
-        if (tid >= 64 && tid < 128) {
-            const int c = tid - 64;
-            float s2 = 0.0f;
-            for (int kk = 0; kk < dim; ++kk) s2 = fmaf(xb[c * kSLd + kk], xb[c * kSLd + kk], s2);
-            nb[c] = s2;
-        }
+        norms(xb, nb);
         floatx16 acc;
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
