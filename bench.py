@@ -324,8 +324,9 @@ def main():
         print(json.dumps(write_traffic(f_csv, w_csv, args.copy_probe_mib, int(chunk))))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
-              "(the multi-GPU design is described in DESIGN.md)" % args.gpus, file=sys.stderr)
+        print("bench.py: one GPU only; --gpus %d is not supported (the path runs on a "
+              "single GPU; sharding across GPUs is a design, not built)" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
