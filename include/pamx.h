@@ -358,6 +358,23 @@ int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t dim, int32
                      double *td_sample, double *td_full, pamx_batch_stats *stats,
                      void *ws, size_t ws_bytes, void *stream);
 
+/* Validation of a dissimilarity matrix.  PAM's arithmetic (Sec. 2) and the
+ * shortcuts of FastPAM assume D symmetric with a zero diagonal, finite and
+ * non-negative; pamx_build / pamx_swap / pamx_fit do not check this.
+ *   D       device, n x ld, PAMX_I32 or PAMX_F32
+ *   ws      device scratch of at least 8 bytes (two counters, overwritten)
+ *   flags   HOST out: bitwise OR of the PAMX_DIS_* bits found (0: valid)
+ *   count   HOST out, may be NULL: number of offending unordered pairs
+ *           {i, j}, i <= j (a diagonal entry is the pair {i, i})
+ * Reads every entry once; returns 0, PAMX_ERR_ARG / PAMX_ERR_WORKSPACE for
+ * bad arguments (before any device work), PAMX_ERR_HIP. */
+#define PAMX_DIS_ASYMMETRIC 1   /* D[i][j] != D[j][i] as values (a NaN never equals its mirror) */
+#define PAMX_DIS_DIAGONAL   2   /* D[i][i] != 0 */
+#define PAMX_DIS_NEGATIVE   4   /* an entry below 0 */
+#define PAMX_DIS_NONFINITE  8   /* a NaN or infinite entry (PAMX_F32) */
+int pamx_check_dissimilarity(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t *flags,
+                             int64_t *count, void *ws, size_t ws_bytes, void *stream);
+
 /* Message for the last non-zero return on this thread ("" if none). */
 const char *pamx_last_error(void);
 

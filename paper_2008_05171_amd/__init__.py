@@ -17,7 +17,8 @@ from .pamx import (PAMX_ACC_F32, PAMX_ACC_F64, PAMX_CHUNK_TUNE, PAMX_DIST_BF16, 
                    PAMX_FASTERPAM, PAMX_FASTPAM1,
                    PAMX_FASTPAM2, PAMX_INPUT_D, PAMX_INPUT_X, PAMX_L1, PAMX_L2, PamxError)
 
-__all__ = ["fit", "build", "swap", "dist", "init_dw", "init_lab", "clarans", "fit_rect",
+__all__ = ["fit", "build", "swap", "dist", "check_dissimilarity", "init_dw", "init_lab",
+           "clarans", "fit_rect",
            "fit_batched", "FitResult", "BatchResult", "PamxError", "PAMX_FASTPAM1",
            "PAMX_FASTPAM2", "PAMX_FASTERPAM", "PAMX_L1", "PAMX_L2", "PAMX_ACC_F64", "PAMX_ACC_F32",
            "PAMX_INPUT_D", "PAMX_INPUT_X", "PAMX_CHUNK_TUNE"]
@@ -287,6 +288,18 @@ def fit_rect(D, k, *, medoids=None, max_iter=10000, trace=False, stream=None) ->
     rc, td, st = _abi.pamx_rect(D, k, med, ws, labels=lab, opt=opt, build=medoids is None,
                                 stream=stream)
     return FitResult(med, lab, td, rc, _stats_dict(st), _trace_list(tbuf, min(st.swaps, cap)))
+
+
+def check_dissimilarity(D, *, stream=None) -> dict:
+    """Validate an n x n device matrix: {"valid", "asymmetric", "diagonal",
+    "negative", "nonfinite", "pairs"} (pairs = offending pairs {i, j}, i <= j)."""
+    flags, count = _abi.pamx_check_dissimilarity(D, stream=stream)
+    return {"valid": flags == 0,
+            "asymmetric": bool(flags & _abi.PAMX_DIS_ASYMMETRIC),
+            "diagonal": bool(flags & _abi.PAMX_DIS_DIAGONAL),
+            "negative": bool(flags & _abi.PAMX_DIS_NEGATIVE),
+            "nonfinite": bool(flags & _abi.PAMX_DIS_NONFINITE),
+            "pairs": count}
 
 
 def dist(X, *, metric=None, ld=None, stream=None):

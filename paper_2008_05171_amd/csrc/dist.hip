@@ -11,6 +11,8 @@
 //                    rows' points and walks two column tiles, loading the next
 //                    tile's points behind the current MFMA loop.
 //  All write a zero diagonal and are bitwise symmetric.
+#include <type_traits>
+
 #include "pamx_internal.h"
 
 namespace pamx {
@@ -301,6 +303,70 @@ __global__ __launch_bounds__(256) void k_transpose(const uint32_t *__restrict__ 
         const int64_t c = c0 + i, r = r0 + tx;
         if (c < cols && r < rows) DT[c * ldt + r] = tile[tx][i];
     }
+}
+
+// ---- validation of a dissimilarity matrix (the properties PAM's arithmetic
+// relies on, Sec. 2): symmetric, zero diagonal, finite and non-negative.
+// Work-group (bi, bj) with bi <= bj compares tile (bi, bj) with the transpose
+// of tile (bj, bi) through LDS, so every entry is read once; an offending
+// pair {i, j} (i <= j) sets bits of flags[0] (vector atomic) and adds one to
+// flags[1].
+template <typename T>
+__device__ __forceinline__ int entry_flags(T v) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (!(v == v) || v == __builtin_huge_valf() || v == -__builtin_huge_valf())
+            return PAMX_DIS_NONFINITE;
+        return v < 0.0f ? PAMX_DIS_NEGATIVE : 0;
+    } else {
+        return v < 0 ? PAMX_DIS_NEGATIVE : 0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_check_dis(const T *__restrict__ D, int64_t n, int64_t ld,
+                                                   int32_t *__restrict__ flags) {
+    __shared__ T tile[64][65];
+    const int64_t bi = blockIdx.y, bj = blockIdx.x;
+    if (bi > bj) return;   // lower tiles are compared from their upper partners
+    const int64_t r0 = bi * 64, c0 = bj * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    // tile (bj, bi) into LDS, transposed on the way out
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t r = c0 + i, c = r0 + tx;
+        if (r < n && c < n) tile[i][tx] = D[r * ld + c];
+    }
+    __syncthreads();
+    // positions r <= c only: each unordered pair {r, c} once, with both entries
+    int f = 0, cnt = 0;
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t r = r0 + i, c = c0 + tx;
+        if (r >= n || c >= n || r > c) continue;
+        const T v = D[r * ld + c];
+        int e = entry_flags<T>(v);
+        if (r == c) {
+            if (v != T(0)) e |= PAMX_DIS_DIAGONAL;
+        } else {
+            const T w = tile[tx][i];   // D[c][r]
+            if (!(v == w)) e |= PAMX_DIS_ASYMMETRIC;
+            e |= entry_flags<T>(w);
+        }
+        f |= e;
+        cnt += (e != 0);
+    }
+    if (f) atomicOr(&flags[0], f);
+    if (cnt) atomicAdd(&flags[1], cnt);
+}
+
+hipError_t launch_check_dis(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t *flags,
+                            hipStream_t s) {
+    const unsigned nt = (unsigned)((n + 63) / 64);
+    if (dtype == PAMX_F32)
+        hipLaunchKernelGGL(k_check_dis<float>, dim3(nt, nt), dim3(256), 0, s,
+                           static_cast<const float *>(D), n, ld, flags);
+    else
+        hipLaunchKernelGGL(k_check_dis<int32_t>, dim3(nt, nt), dim3(256), 0, s,
+                           static_cast<const int32_t *>(D), n, ld, flags);
+    return hipGetLastError();
 }
 
 hipError_t launch_transpose(const void *D, int64_t ld, int64_t rows, int64_t cols, void *DT,

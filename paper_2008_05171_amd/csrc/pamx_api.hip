@@ -430,6 +430,30 @@ extern "C" int pamx_dist(const void *X, int32_t dtype, int64_t n, int32_t dim, i
     return PAMX_OK;
 }
 
+extern "C" int pamx_check_dissimilarity(const void *D, int32_t dtype, int64_t n, int64_t ld,
+                                        int32_t *flags, int64_t *count, void *ws,
+                                        size_t ws_bytes, void *stream) {
+    if (n < 1) return fail(PAMX_ERR_ARG, "n must be >= 1");
+    if (dtype != PAMX_I32 && dtype != PAMX_F32) return fail(PAMX_ERR_ARG, "unknown dtype %d", dtype);
+    int rc = check_matrix(D, n, ld);
+    if (rc) return rc;
+    if (!flags) return fail(PAMX_ERR_ARG, "flags is NULL");
+    if (n > (int64_t)65535 * 64) return fail(PAMX_ERR_ARG, "n too large for the check grid");
+    if (!ws || ws_bytes < 8) return fail(PAMX_ERR_WORKSPACE, "the check needs a workspace of 8 bytes");
+    if ((reinterpret_cast<uintptr_t>(ws) & 3) != 0)
+        return fail(PAMX_ERR_WORKSPACE, "workspace must be 4-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t *dflags = static_cast<int32_t *>(ws);
+    HIP_TRY(hipMemsetAsync(dflags, 0, 2 * sizeof(int32_t), s));   // never captured in a graph
+    HIP_TRY(launch_check_dis(D, dtype, n, ld, dflags, s));
+    int32_t h[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(h, dflags, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *flags = h[0];
+    if (count) *count = h[1];
+    return PAMX_OK;
+}
+
 // ---------------------------------------------------------------- BUILD / SWAP
 namespace {
 

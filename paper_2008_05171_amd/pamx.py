@@ -23,6 +23,7 @@ PAMX_CHUNK_TUNE = -1
 PAMX_OK, PAMX_WARN_MAXITER = 0, 1
 PAMX_ERR_ARG, PAMX_ERR_WORKSPACE, PAMX_ERR_HIP = -1, -2, -3
 PAMX_ERR_INVALID_MEDOIDS, PAMX_ERR_UNSUPPORTED = -4, -5
+PAMX_DIS_ASYMMETRIC, PAMX_DIS_DIAGONAL, PAMX_DIS_NEGATIVE, PAMX_DIS_NONFINITE = 1, 2, 4, 8
 
 
 class pamx_options(ctypes.Structure):
@@ -63,7 +64,8 @@ class pamx_batch_stats(ctypes.Structure):
 EXPORTS = ("pamx_default_options", "pamx_workspace_bytes", "pamx_dist", "pamx_build",
            "pamx_swap", "pamx_fit", "pamx_batched_workspace_bytes", "pamx_fit_batched",
            "pamx_init_workspace_bytes", "pamx_init_dw", "pamx_init_lab", "pamx_clarans",
-           "pamx_rect_workspace_bytes", "pamx_fit_rect", "pamx_swap_rect", "pamx_last_error")
+           "pamx_rect_workspace_bytes", "pamx_fit_rect", "pamx_swap_rect",
+           "pamx_check_dissimilarity", "pamx_last_error")
 
 
 class PamxError(RuntimeError):
@@ -106,12 +108,14 @@ def load(path: str = LIB_PATH):
     lib.pamx_rect_workspace_bytes.argtypes = [i64, i64, i32, i32, opt_p, ctypes.POINTER(sz)]
     lib.pamx_fit_rect.argtypes = [P, i32, i64, i64, i64, i32, opt_p, P, P, dbl_p, st_p, P, sz, P]
     lib.pamx_swap_rect.argtypes = [P, i32, i64, i64, i64, i32, opt_p, P, P, dbl_p, st_p, P, sz, P]
+    lib.pamx_check_dissimilarity.argtypes = [P, i32, i64, i64, ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_int64), P, sz, P]
     lib.pamx_last_error.argtypes = []
     lib.pamx_last_error.restype = ctypes.c_char_p
     for name in ("pamx_workspace_bytes", "pamx_dist", "pamx_build", "pamx_swap", "pamx_fit",
                  "pamx_batched_workspace_bytes", "pamx_fit_batched", "pamx_init_workspace_bytes",
                  "pamx_init_dw", "pamx_init_lab", "pamx_clarans", "pamx_rect_workspace_bytes",
-                 "pamx_fit_rect", "pamx_swap_rect"):
+                 "pamx_fit_rect", "pamx_swap_rect", "pamx_check_dissimilarity"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -166,6 +170,22 @@ def pamx_dist(X, metric, D, ws=None, ld=None, stream=None):
         ws = torch.empty(max(4 * dim, 256), dtype=torch.uint8, device=X.device)
     return _check(load().pamx_dist(_ptr(X), _dtype_code(X), n, dim, int(metric), _ptr(D), int(ld),
                                    _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def pamx_check_dissimilarity(D, ws=None, n=None, ld=None, stream=None):
+    """(flags, count): PAMX_DIS_* bits found in the n x n matrix D and the
+    number of offending pairs; ws: >= 8 bytes of device scratch."""
+    import torch
+    n = D.shape[0] if n is None else n
+    ld = D.stride(0) if ld is None else ld
+    if ws is None:
+        ws = torch.empty(256, dtype=torch.uint8, device=D.device)
+    flags = ctypes.c_int32()
+    count = ctypes.c_int64()
+    _check(load().pamx_check_dissimilarity(_ptr(D), _dtype_code(D), int(n), int(ld),
+                                           ctypes.byref(flags), ctypes.byref(count), _ptr(ws),
+                                           ws.numel() * ws.element_size(), _stream(stream)))
+    return flags.value, count.value
 
 
 def pamx_build(D, k, medoids, ws, opt=None, n=None, ld=None, stream=None):

@@ -257,3 +257,21 @@ def test_batched_host_argument_errors(lib):
     assert call([0, 100], [5], dim=17) == abi.PAMX_ERR_UNSUPPORTED
     assert call([0, 100], [5], dtype=abi.PAMX_I32) == abi.PAMX_ERR_UNSUPPORTED  # int + L2
     assert abi.pamx_batched_workspace_bytes(256, 10 ** 6) > 256 * 256 * 8
+
+
+def test_check_dissimilarity_argument_errors(lib):
+    fake = ctypes.c_void_p(0x100000)
+    ws = ctypes.c_void_p(0x200000)
+    flags = ctypes.c_int32(-7)
+
+    def call(D=fake, dtype=abi.PAMX_F32, n=100, ld=100, fl=True, w=ws, wsb=256):
+        return lib.pamx_check_dissimilarity(D, dtype, n, ld, ctypes.byref(flags) if fl else None,
+                                            None, w, wsb, None)
+    assert call(D=None) == abi.PAMX_ERR_ARG
+    assert call(dtype=7) == abi.PAMX_ERR_ARG
+    assert call(n=0) == abi.PAMX_ERR_ARG
+    assert call(ld=99) == abi.PAMX_ERR_ARG
+    assert call(fl=False) == abi.PAMX_ERR_ARG
+    assert call(w=None) == abi.PAMX_ERR_WORKSPACE
+    assert call(wsb=4) == abi.PAMX_ERR_WORKSPACE
+    assert flags.value == -7   # nothing written on an argument error
