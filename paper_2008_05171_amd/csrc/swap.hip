@@ -1387,27 +1387,30 @@ __global__ __launch_bounds__(256) void k_cl_eval(
             const int32_t so = seg_off[sg], se = seg_off[sg + 1];
             if (so == se) continue;
             A M = 0, DN = 0;
-            int32_t p = so + lane;
-            for (; p + (U - 1) * 64 < se; p += U * 64) {
+            // U slots per lane at a time, masked past the segment's end: the
+            // object indices, then their row entries, go out together (each
+            // lane still adds its objects in order)
+            for (int32_t p0 = so + lane; p0 < se; p0 += U * 64) {
+                int32_t ob[U];
                 T d[U], lo[U], hi[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    d[u] = row[srow[p + u * 64]];
-                    lo[u] = sdn[p + u * 64];
-                    hi[u] = sds[p + u * 64];
+                    const int32_t p = p0 + u * 64;
+                    const int32_t q = p < se ? p : so;   // in bounds; unused when masked
+                    ob[u] = srow[q];
+                    lo[u] = sdn[q];
+                    hi[u] = sds[q];
                 }
 #pragma unroll
+                for (int u = 0; u < U; ++u) d[u] = row[ob[u]];
+#pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    accA += (A)vmin(d[u], lo[u]);
-                    M += (A)vmed3(d[u], lo[u], hi[u]);
-                    DN += (A)lo[u];
+                    if (p0 + u * 64 < se) {
+                        accA += (A)vmin(d[u], lo[u]);
+                        M += (A)vmed3(d[u], lo[u], hi[u]);
+                        DN += (A)lo[u];
+                    }
                 }
-            }
-            for (; p < se; p += 64) {
-                const T d = row[srow[p]], lo = sdn[p], hi = sds[p];
-                accA += (A)vmin(d, lo);
-                M += (A)vmed3(d, lo, hi);
-                DN += (A)lo;
             }
             const A v = wave_sum<A>(M) - wave_sum<A>(DN);
             if (lt2(v, sg, bv, bi)) { bv = v; bi = sg; }
