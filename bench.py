@@ -17,7 +17,9 @@ Reported (one JSON line):
   ms_per_step      wall time of one whole fit
   roofline         SWAP pass kernel: algorithmic bytes 4 * n * (n - k) per
                    launch over its average duration (HIP events on the
-                   library's stream), against 8 TB/s HBM
+                   library's stream), against 8 TB/s HBM; read_probe is a
+                   plain read of an n x n FP32 matrix in the pass's launch
+                   shape (pamx_read_probe), the rate the access can reach
   cpu_baseline     the CPU oracle (original PAM SWAP, FP64, OpenMP) on a
                    bounded sample of candidates of the same workload
 
@@ -394,6 +396,26 @@ def main():
     traffic = traffic_from_profiles(N, K, chunk)
     last = stats[-1][2]
 
+    # the reference read: the same bytes in the pass's launch shape, no arithmetic
+    ld_fit = (N + 63) // 64 * 64
+    Dp = torch.rand(N, ld_fit, dtype=torch.float32, device=dev)
+    tiles, nq = (N + 1023) // 1024, (N + chunk - 1) // chunk
+    psums = torch.empty(tiles * nq, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        abi.pamx_read_probe(Dp, chunk, psums, n=N, ld=ld_fit, stream=stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    probe_ms = []
+    for _ in range(20):
+        ev0.record(stream)
+        abi.pamx_read_probe(Dp, chunk, psums, n=N, ld=ld_fit, stream=stream)
+        ev1.record(stream)
+        ev1.synchronize()
+        probe_ms.append(ev0.elapsed_time(ev1))
+    del Dp, psums
+    probe_avg = sum(probe_ms) / len(probe_ms)
+    probe_gbs = 4.0 * N * N / (probe_avg / 1e3) / 1e9
+    log("read probe: %.1f us per launch, %.0f GB/s" % (probe_avg * 1e3, probe_gbs))
+
     extra = {}
     if not args.no_fastpam2:
         opt2, ws2, med2, lab2 = make(abi.PAMX_FASTPAM2)
@@ -434,7 +456,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_swap_pass", "bytes_per_launch": alg_bytes,
-                     "avg_launch_ms": avg_pass_ms, "launches": n_pass},
+                     "avg_launch_ms": avg_pass_ms, "launches": n_pass,
+                     "read_probe": {"avg_launch_ms": probe_avg, "achieved": probe_gbs,
+                                    "frac": probe_gbs / HBM_PEAK_GBS,
+                                    "bytes_per_launch": 4.0 * N * N, "launches": len(probe_ms)},
+                     "frac_of_read_probe": achieved / probe_gbs},
         "cpu_baseline": cpu,
         "fit_ms": round(last["ms_total"], 3),
         "phase_ms": {"dist": round(last["ms_dist"], 3), "build": round(last["ms_build"], 3),

@@ -375,6 +375,21 @@ int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t dim, int32
 int pamx_check_dissimilarity(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t *flags,
                              int64_t *count, void *ws, size_t ws_bytes, void *stream);
 
+/* Measurement (not part of the method): the read rate the SWAP pass's access
+ * pattern can reach.  A plain streaming read of rows [0, n) of a row-major
+ * matrix of 4-byte elements in the pass's launch shape: work-groups of 256
+ * lanes over 1024-column tiles, one 16-byte non-temporal load per lane and
+ * row with four rows in flight, rows in chunks of `chunk`.  Columns
+ * [0, n rounded up to a multiple of 4) are read; 4 n^2 bytes over the time
+ * of one call is the reference the pass's own rate is compared with.
+ *   D      device, ld % 4 == 0, 16-byte aligned, read as FP32
+ *   sums   device float[sums_len], sums_len >= ceil(n / 1024) * ceil(n / chunk):
+ *          per work-group sums of what it read (overwritten)
+ * Asynchronous on stream.  Returns 0, PAMX_ERR_ARG for bad arguments
+ * (before any device work), PAMX_ERR_HIP. */
+int pamx_read_probe(const void *D, int64_t n, int64_t ld, int32_t chunk, float *sums,
+                    int64_t sums_len, void *stream);
+
 /* Message for the last non-zero return on this thread ("" if none). */
 const char *pamx_last_error(void);
 

@@ -369,6 +369,48 @@ hipError_t launch_check_dis(const void *D, int32_t dtype, int64_t n, int64_t ld,
     return hipGetLastError();
 }
 
+// ---- reference read: the SWAP pass's access with none of its arithmetic.
+// Work-group (tile, chunk) reads rows [chunk * L, +L) of columns
+// [tile * 1024, +1024), one 16-byte non-temporal load per lane and row, four
+// rows in flight (as the pass), and writes the sum of what it read.
+__global__ __launch_bounds__(256) void k_read_probe(const float *__restrict__ D, int64_t ld, int64_t n,
+                                                   int32_t L, float *__restrict__ sums) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    constexpr int U = 4;
+    const int64_t a = (int64_t)blockIdx.y * L;
+    const int64_t b = min(a + (int64_t)L, n);
+    const int64_t c0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    float acc = 0.f;
+    if (c0 < n) {   // c0 + 3 < ld: ld is a multiple of 4
+        int64_t o = a;
+        for (; o + U <= b; o += U) {
+            f4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                v[u] = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(D + (o + u) * ld + c0));
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += (v[u][0] + v[u][1]) + (v[u][2] + v[u][3]);
+        }
+        for (; o < b; ++o) {
+            const f4 v = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(D + o * ld + c0));
+            acc += (v[0] + v[1]) + (v[2] + v[3]);
+        }
+    }
+    __shared__ float wsum[4];
+    for (int w = 32; w >= 1; w >>= 1) acc += __shfl_xor(acc, w);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        sums[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+}
+
+hipError_t launch_read_probe(const float *D, int64_t n, int64_t ld, int32_t L, float *sums,
+                             hipStream_t s) {
+    const dim3 grid((unsigned)((n + 1023) / 1024), (unsigned)((n + L - 1) / L));
+    hipLaunchKernelGGL(k_read_probe, grid, dim3(256), 0, s, D, ld, n, L, sums);
+    return hipGetLastError();
+}
+
 hipError_t launch_transpose(const void *D, int64_t ld, int64_t rows, int64_t cols, void *DT,
                             int64_t ldt, hipStream_t s) {
     const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64));

@@ -454,6 +454,25 @@ extern "C" int pamx_check_dissimilarity(const void *D, int32_t dtype, int64_t n,
     return PAMX_OK;
 }
 
+extern "C" int pamx_read_probe(const void *D, int64_t n, int64_t ld, int32_t chunk, float *sums,
+                               int64_t sums_len, void *stream) {
+    if (n < 1) return fail(PAMX_ERR_ARG, "n must be >= 1");
+    int rc = check_matrix(D, n, ld);
+    if (rc) return rc;
+    if (ld % 4 != 0 || (reinterpret_cast<uintptr_t>(D) & 15) != 0)
+        return fail(PAMX_ERR_ARG, "the probe needs ld %% 4 == 0 and a 16-byte aligned matrix");
+    if (chunk < 1) return fail(PAMX_ERR_ARG, "chunk must be >= 1");
+    const int64_t tiles = (n + 1023) / 1024, q = (n + chunk - 1) / chunk;
+    if (q > 65535) return fail(PAMX_ERR_ARG, "chunk too small: %lld row chunks", (long long)q);
+    if (!sums) return fail(PAMX_ERR_ARG, "sums is NULL");
+    if (sums_len < tiles * q)
+        return fail(PAMX_ERR_ARG, "sums holds %lld floats, the probe writes %lld",
+                    (long long)sums_len, (long long)(tiles * q));
+    HIP_TRY(launch_read_probe(static_cast<const float *>(D), n, ld, chunk, sums,
+                              static_cast<hipStream_t>(stream)));
+    return PAMX_OK;
+}
+
 // ---------------------------------------------------------------- BUILD / SWAP
 namespace {
 

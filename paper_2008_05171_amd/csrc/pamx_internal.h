@@ -215,6 +215,8 @@ inline bool cooperative_allowed() {
 // flags[0] |= PAMX_DIS_* bits, flags[1] += offending entries (zeroed by the caller)
 hipError_t launch_check_dis(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t *flags,
                             hipStream_t s);
+hipError_t launch_read_probe(const float *D, int64_t n, int64_t ld, int32_t L, float *sums,
+                             hipStream_t s);
 hipError_t launch_transpose(const void *D, int64_t ld, int64_t rows, int64_t cols, void *DT,
                             int64_t ldt, hipStream_t s);
 // re-place the chunk-dependent regions (after L->head) for chunk length Lc

@@ -758,8 +758,9 @@ __device__ __forceinline__ void pass_tile(
     const ChunkInfo *__restrict__ cinfo, int32_t L, int64_t ncp, AccT<T> *__restrict__ part,
     int32_t *__restrict__ part_i, AccT<T> *__restrict__ P) {
     using A = AccT<T>;
-    // four rows in flight per lane: measured faster than eight or sixteen
-    // for a 20000 x 20000 FP32 matrix (fewer VGPRs, more waves per SIMD)
+    // four rows in flight per lane: measured faster than eight or sixteen,
+    // and than issuing the next rows before the current ones are summed,
+    // for a 20000 x 20000 FP32 matrix
     constexpr int U = 4;
     const int64_t a = (int64_t)q * L;
     const int64_t b = min(a + (int64_t)L, n);
@@ -773,79 +774,94 @@ __device__ __forceinline__ void pass_tile(
 #pragma unroll
     for (int e = 0; e < VEC; ++e) { accA[e] = 0; bv[e] = VT<T>::acc_inf(); bi[e] = INT_MAX; }
     A *pq = part + (int64_t)q * 4 * ncp + cr;
+    // the first lane of the first tile (always a real candidate: windows are
+    // never empty) records the chunk's part of DN for segments carried
+    // across chunks
+    const bool rec = tile == 0 && threadIdx.x == 0;
 
-    for (int s = ci.sa; s <= ci.sb; ++s) {
-        const int64_t so = seg_off[s], se = seg_off[s + 1];
-        if (so == se) continue;
-        const int64_t p0 = max(a, so), p1 = min(b, se);
+    if (active) {
+        // The chunk's rows are one stream of blocks of U rows; a segment edge
+        // inside a block closes the segment there (a wave-uniform branch), so
+        // loads are never cut short at segment edges.
+        int s = ci.sa;                                   // segment of the current row
+        int64_t se = min((int64_t)seg_off[s + 1], b);    // its end within the chunk
         A M[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) M[e] = 0;
-        A dns = 0;   // DN of the segment's objects in this chunk (same in every lane)
-        if (active) {
-            int64_t j = p0;
-            for (; j + U <= p1; j += U) {
-                T v[U][VEC];
-                T lo[U], hi[U];
+        A dns = 0;   // DN of the segment's rows in this chunk (same in every lane)
+        auto close_seg = [&]() {
+            if (s == ci.sa && (ci.flags & kHead)) {
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t o = srow[j + u];
-                    load_vec<T, VEC>(D + o * ld + c0, v[u]);
-                    lo[u] = sdn[j + u];
-                    hi[u] = sds[j + u];
-                }
+                for (int e = 0; e < VEC; ++e) pq[1 * ncp + e] = M[e];
+                if (rec) cdn[2 * q] = dns;
+            } else if (s == ci.sb && (ci.flags & kTail)) {
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    dns += (A)lo[u];
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) {
-                        accA[e] += (A)vmin(v[u][e], lo[u]);
-                        M[e] += (A)vmed3(v[u][e], lo[u], hi[u]);
-                    }
-                }
-            }
-            for (; j < p1; ++j) {
-                const int64_t o = srow[j];
-                T v[VEC];
-                load_vec<T, VEC>(D + o * ld + c0, v);
-                const T lo = sdn[j], hi = sds[j];
-                dns += (A)lo;
+                for (int e = 0; e < VEC; ++e) pq[2 * ncp + e] = M[e];
+                if (rec) cdn[2 * q + 1] = dns;
+            } else {
+                A v[VEC];
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
-                    accA[e] += (A)vmin(v[e], lo);
-                    M[e] += (A)vmed3(v[e], lo, hi);
+                    v[e] = M[e] - dns;
+                    if (v[e] < bv[e]) { bv[e] = v[e]; bi[e] = s; }
                 }
-            }
-        }
-        // the first lane of the first tile (always a real candidate: windows
-        // are never empty) records the chunk's part of DN for segments
-        // carried across chunks
-        const bool rec = tile == 0 && threadIdx.x == 0;
-        if (s == ci.sa && (ci.flags & kHead)) {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) pq[1 * ncp + e] = M[e];
-            if (rec) cdn[2 * q] = dns;
-        } else if (s == ci.sb && (ci.flags & kTail)) {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) pq[2 * ncp + e] = M[e];
-            if (rec) cdn[2 * q + 1] = dns;
-        } else {
-            A v[VEC];
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                v[e] = M[e] - dns;
-                if (v[e] < bv[e]) { bv[e] = v[e]; bi[e] = s; }
-            }
-            if constexpr (P2) {
-                // streaming stores (P is read once, by the best-candidate
-                // scan); measured faster than 16-byte or cached stores
-                if (active) {
+                if constexpr (P2) {
+                    // streaming stores (P is read once, by the best-candidate
+                    // scan); measured faster than 16-byte or cached stores
 #pragma unroll
                     for (int e = 0; e < VEC; ++e)
                         __builtin_nontemporal_store(v[e], &P[(int64_t)s * ncp + c0 + e]);
                 }
             }
+        };
+        // row j starts a new segment: close the current one, move to the
+        // next non-empty segment
+        auto next_seg = [&](int64_t j) {
+            close_seg();
+            do { ++s; } while (seg_off[s + 1] <= j);
+            se = min((int64_t)seg_off[s + 1], b);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) M[e] = 0;
+            dns = 0;
+        };
+        auto add_row = [&](const T (&v)[VEC], T lo, T hi) {
+            dns += (A)lo;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                accA[e] += (A)vmin(v[e], lo);
+                M[e] += (A)vmed3(v[e], lo, hi);
+            }
+        };
+        int64_t j = a;
+        for (; j + U <= b; j += U) {
+            T v[U][VEC];
+            T lo[U], hi[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t o = srow[j + u];
+                load_vec<T, VEC>(D + o * ld + c0, v[u]);
+                lo[u] = sdn[j + u];
+                hi[u] = sds[j + u];
+            }
+            if (j + U <= se) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) add_row(v[u], lo[u], hi[u]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (j + u == se) next_seg(j + u);
+                    add_row(v[u], lo[u], hi[u]);
+                }
+            }
         }
+        for (; j < b; ++j) {
+            if (j == se) next_seg(j);
+            const int64_t o = srow[j];
+            T v[VEC];
+            load_vec<T, VEC>(D + o * ld + c0, v);
+            add_row(v, sdn[j], sds[j]);
+        }
+        close_seg();
     }
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {

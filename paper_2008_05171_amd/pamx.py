@@ -65,7 +65,7 @@ EXPORTS = ("pamx_default_options", "pamx_workspace_bytes", "pamx_dist", "pamx_bu
            "pamx_swap", "pamx_fit", "pamx_batched_workspace_bytes", "pamx_fit_batched",
            "pamx_init_workspace_bytes", "pamx_init_dw", "pamx_init_lab", "pamx_clarans",
            "pamx_rect_workspace_bytes", "pamx_fit_rect", "pamx_swap_rect",
-           "pamx_check_dissimilarity", "pamx_last_error")
+           "pamx_check_dissimilarity", "pamx_read_probe", "pamx_last_error")
 
 
 class PamxError(RuntimeError):
@@ -110,12 +110,13 @@ def load(path: str = LIB_PATH):
     lib.pamx_swap_rect.argtypes = [P, i32, i64, i64, i64, i32, opt_p, P, P, dbl_p, st_p, P, sz, P]
     lib.pamx_check_dissimilarity.argtypes = [P, i32, i64, i64, ctypes.POINTER(ctypes.c_int32),
                                              ctypes.POINTER(ctypes.c_int64), P, sz, P]
+    lib.pamx_read_probe.argtypes = [P, i64, i64, i32, P, i64, P]
     lib.pamx_last_error.argtypes = []
     lib.pamx_last_error.restype = ctypes.c_char_p
     for name in ("pamx_workspace_bytes", "pamx_dist", "pamx_build", "pamx_swap", "pamx_fit",
                  "pamx_batched_workspace_bytes", "pamx_fit_batched", "pamx_init_workspace_bytes",
                  "pamx_init_dw", "pamx_init_lab", "pamx_clarans", "pamx_rect_workspace_bytes",
-                 "pamx_fit_rect", "pamx_swap_rect", "pamx_check_dissimilarity"):
+                 "pamx_fit_rect", "pamx_swap_rect", "pamx_check_dissimilarity", "pamx_read_probe"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -186,6 +187,15 @@ def pamx_check_dissimilarity(D, ws=None, n=None, ld=None, stream=None):
                                            ctypes.byref(flags), ctypes.byref(count), _ptr(ws),
                                            ws.numel() * ws.element_size(), _stream(stream)))
     return flags.value, count.value
+
+
+def pamx_read_probe(D, chunk, sums, n=None, ld=None, stream=None):
+    """Plain read of the n x n FP32 matrix D in the SWAP pass's launch shape
+    (rows in chunks of `chunk`); sums: device float32, one per work-group."""
+    n = D.shape[0] if n is None else n
+    ld = D.stride(0) if ld is None else ld
+    return _check(load().pamx_read_probe(_ptr(D), int(n), int(ld), int(chunk), _ptr(sums),
+                                         sums.numel(), _stream(stream)))
 
 
 def pamx_build(D, k, medoids, ws, opt=None, n=None, ld=None, stream=None):

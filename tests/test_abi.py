@@ -275,3 +275,20 @@ def test_check_dissimilarity_argument_errors(lib):
     assert call(w=None) == abi.PAMX_ERR_WORKSPACE
     assert call(wsb=4) == abi.PAMX_ERR_WORKSPACE
     assert flags.value == -7   # nothing written on an argument error
+
+
+def test_read_probe_argument_errors(lib):
+    fake = ctypes.c_void_p(0x100000)
+    sums = ctypes.c_void_p(0x200000)
+
+    def call(D=fake, n=2000, ld=2000, chunk=100, s=sums, slen=40):
+        return lib.pamx_read_probe(D, n, ld, chunk, s, slen, None)
+    assert call(D=None) == abi.PAMX_ERR_ARG
+    assert call(n=0) == abi.PAMX_ERR_ARG
+    assert call(ld=1999) == abi.PAMX_ERR_ARG
+    assert call(ld=2002) == abi.PAMX_ERR_ARG                    # ld % 4 != 0
+    assert call(D=ctypes.c_void_p(0x100004)) == abi.PAMX_ERR_ARG  # not 16-byte aligned
+    assert call(chunk=0) == abi.PAMX_ERR_ARG
+    assert call(n=100000, ld=100000, chunk=1, slen=10 ** 9) == abi.PAMX_ERR_ARG  # > 65535 chunks
+    assert call(s=None) == abi.PAMX_ERR_ARG
+    assert call(slen=39) == abi.PAMX_ERR_ARG   # 2 tiles x 20 chunks = 40 sums
