@@ -579,21 +579,43 @@ __device__ __forceinline__ void iter_begin(DevState *st) {
     }
 }
 
-// ---- stable counting sort of objects by nearest slot
-__global__ __launch_bounds__(kObjBlk) void k_seg_count(const int32_t *__restrict__ near, int64_t n,
+// ---- stable counting sort of objects by nearest slot.  Each block also
+// sums its objects' dn and ds (TD and the rounding bound's sum of ds), in a
+// fixed order: wave butterflies, then the four waves in order.
+template <typename T>
+__global__ __launch_bounds__(kObjBlk) void k_seg_count(const int32_t *__restrict__ near,
+                                                       const T *__restrict__ dn,
+                                                       const T *__restrict__ ds, int64_t n,
                                                        int32_t k, int32_t *__restrict__ blkcnt,
+                                                       AccT<T> *__restrict__ tdp,
                                                        DevState *__restrict__ st) {
+    using A = AccT<T>;
     if (st->done) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) iter_begin(st);
     if (st->seg_skip) return;
     extern __shared__ int32_t hist[];
+    __shared__ A w1[kObjBlk / 64], w2[kObjBlk / 64];
     for (int i = threadIdx.x; i < k; i += kObjBlk) hist[i] = 0;
     __syncthreads();
     const int64_t o = (int64_t)blockIdx.x * kObjBlk + threadIdx.x;
-    if (o < n) atomicAdd(&hist[near[o]], 1);
+    A s1 = 0, s2 = 0;
+    if (o < n) {
+        atomicAdd(&hist[near[o]], 1);
+        s1 = (A)dn[o];
+        s2 = (A)ds[o];
+    }
+    s1 = wave_sum<A>(s1);
+    s2 = wave_sum<A>(s2);
+    if ((threadIdx.x & 63) == 0) { w1[threadIdx.x >> 6] = s1; w2[threadIdx.x >> 6] = s2; }
     __syncthreads();
     int32_t *dst = blkcnt + (int64_t)blockIdx.x * k;
     for (int i = threadIdx.x; i < k; i += kObjBlk) dst[i] = hist[i];
+    if (threadIdx.x == 0) {
+        A t1 = 0, t2 = 0;
+        for (int u = 0; u < kObjBlk / 64; ++u) { t1 += w1[u]; t2 += w2[u]; }
+        tdp[2 * blockIdx.x] = t1;
+        tdp[2 * blockIdx.x + 1] = t2;
+    }
 }
 
 // Exclusive prefix over blocks of each slot's counts (in place), one wave per
@@ -626,11 +648,12 @@ struct ChunkInfo {
 constexpr int kHead = 1, kTail = 2;
 
 // Segment offsets (scan of the slot totals), the smallest empty slot, TD and
-// sum of ds (for the rounding bound), and the carry map of every chunk.
-// seg_off[1..k] holds the slot totals on entry.
+// sum of ds (for the rounding bound) from the nblk block sums of
+// k_seg_count, and the carry map of every chunk.  seg_off[1..k] holds the
+// slot totals on entry.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_seg_scan(int32_t k, int64_t n, int32_t *__restrict__ seg_off,
-                                                   const T *__restrict__ dn, const T *__restrict__ ds,
+                                                   const AccT<T> *__restrict__ tdp, int32_t nblk,
                                                    int32_t L, int32_t Q, ChunkInfo *__restrict__ cinfo,
                                                    DevState *__restrict__ st) {
     using A = AccT<T>;
@@ -666,18 +689,10 @@ __global__ __launch_bounds__(1024) void k_seg_scan(int32_t k, int64_t n, int32_t
         __syncthreads();
     }
     for (int i = t; i <= k; i += 1024) seg_off[i] = soff[i];
-    // TD and sum of ds, fixed order (four loads in flight per thread, wave
-    // butterflies, then the 16 wave sums in order)
+    // TD and sum of ds over the block sums, fixed order (blocks t, t + 1024,
+    // ... per thread, wave butterflies, then the 16 wave sums in order)
     A s1 = 0, s2 = 0;
-    int64_t o = t;
-    for (; o + 3 * 1024 < n; o += 4 * 1024) {
-        T a[4], b[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) { a[u] = dn[o + u * 1024]; b[u] = ds[o + u * 1024]; }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) { s1 += (A)a[u]; s2 += (A)b[u]; }
-    }
-    for (; o < n; o += 1024) { s1 += (A)dn[o]; s2 += (A)ds[o]; }
+    for (int b = t; b < nblk; b += 1024) { s1 += tdp[2 * b]; s2 += tdp[2 * b + 1]; }
     s1 = wave_sum<A>(s1);
     s2 = wave_sum<A>(s2);
     if (lane == 0) { ws1[wv] = s1; ws2[wv] = s2; }
@@ -1865,7 +1880,7 @@ struct SwapPtrs {
     int32_t *near, *sec, *srow, *blkcnt, *seg_off, *part_i, *wg_i, *wg_c, *slot_c, *order, *rlist;
     T *dn, *ds, *sdn, *sds;
     uint8_t *is_med;
-    AccT<T> *cdn, *part, *wg_v, *P, *cand_a, *slot_v;
+    AccT<T> *cdn, *part, *wg_v, *P, *cand_a, *slot_v, *tdp;
     ChunkInfo *cinfo;
     DevState *st;
 };
@@ -1883,6 +1898,7 @@ static SwapPtrs<T> ptrs(const Layout &L, void *ws) {
     p.sdn = reinterpret_cast<T *>(w + L.sdn);
     p.sds = reinterpret_cast<T *>(w + L.sds);
     p.blkcnt = reinterpret_cast<int32_t *>(w + L.blkcnt);
+    p.tdp = reinterpret_cast<AccT<T> *>(w + L.tdp);
     p.seg_off = reinterpret_cast<int32_t *>(w + L.seg_off);
     p.cinfo = reinterpret_cast<ChunkInfo *>(w + L.blkbase);
     p.cdn = reinterpret_cast<AccT<T> *>(w + L.cdn);
@@ -1938,12 +1954,13 @@ template <typename T>
 static void enqueue_segments(const Layout &L, const SwapPtrs<T> &p, hipStream_t s) {
     const int64_t n = L.n;
     const int32_t k = L.k;
-    hipLaunchKernelGGL(k_seg_count, dim3(L.n_oblk), dim3(kObjBlk), (size_t)k * 4, s,
-                       (const int32_t *)p.near, n, k, p.blkcnt, p.st);
+    hipLaunchKernelGGL(k_seg_count<T>, dim3(L.n_oblk), dim3(kObjBlk), (size_t)k * 4, s,
+                       (const int32_t *)p.near, (const T *)p.dn, (const T *)p.ds, n, k, p.blkcnt,
+                       p.tdp, p.st);
     hipLaunchKernelGGL(k_seg_colscan, dim3((k + 3) / 4), dim3(256), 0, s, p.blkcnt, L.n_oblk, k,
                        p.seg_off + 1, (const DevState *)p.st);
     hipLaunchKernelGGL(k_seg_scan<T>, dim3(1), dim3(1024), (size_t)(k + 1) * 4, s, k, n,
-                       p.seg_off, (const T *)p.dn, (const T *)p.ds, L.L, L.Q, p.cinfo, p.st);
+                       p.seg_off, (const AccT<T> *)p.tdp, L.n_oblk, L.L, L.Q, p.cinfo, p.st);
     hipLaunchKernelGGL(k_seg_scatter<T>, dim3(L.n_oblk), dim3(kObjBlk), 0, s,
                        (const int32_t *)p.near, (const T *)p.dn, (const T *)p.ds, n, k,
                        (const int32_t *)p.blkcnt, (const int32_t *)p.seg_off, p.srow, p.sdn,
@@ -2136,15 +2153,15 @@ hipError_t enqueue_swap_caches(const T *D, int64_t ld, const Layout &L, const in
 
 // The segment kernels on FP32 caches, for the mixed-precision form.
 hipError_t launch_segments_f32(const int32_t *near, const float *dn, const float *ds, int64_t n,
-                               int32_t k, int32_t n_oblk, int32_t *blkcnt, int32_t *seg_off,
-                               int32_t L, int32_t Q, void *cinfo, int32_t *srow, float *sdn, float *sds,
-                               DevState *st, hipStream_t s) {
-    hipLaunchKernelGGL(k_seg_count, dim3(n_oblk), dim3(kObjBlk), (size_t)k * 4, s, near, n, k,
-                       blkcnt, st);
+                               int32_t k, int32_t n_oblk, int32_t *blkcnt, double *tdp,
+                               int32_t *seg_off, int32_t L, int32_t Q, void *cinfo, int32_t *srow,
+                               float *sdn, float *sds, DevState *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_count<float>, dim3(n_oblk), dim3(kObjBlk), (size_t)k * 4, s, near, dn,
+                       ds, n, k, blkcnt, tdp, st);
     hipLaunchKernelGGL(k_seg_colscan, dim3((k + 3) / 4), dim3(256), 0, s, blkcnt, n_oblk, k,
                        seg_off + 1, (const DevState *)st);
     hipLaunchKernelGGL(k_seg_scan<float>, dim3(1), dim3(1024), (size_t)(k + 1) * 4, s, k, n, seg_off,
-                       dn, ds, L, Q, static_cast<ChunkInfo *>(cinfo), st);
+                       (const double *)tdp, n_oblk, L, Q, static_cast<ChunkInfo *>(cinfo), st);
     hipLaunchKernelGGL(k_seg_scatter<float>, dim3(n_oblk), dim3(kObjBlk), 0, s, near, dn, ds, n, k,
                        (const int32_t *)blkcnt, (const int32_t *)seg_off, srow, sdn, sds,
                        (const DevState *)st);
