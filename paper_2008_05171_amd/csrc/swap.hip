@@ -793,6 +793,29 @@ __device__ __forceinline__ void pass_tile(
     // never empty) records the chunk's part of DN for segments carried
     // across chunks
     const bool rec = tile == 0 && threadIdx.x == 0;
+    // FastPAM2: each wave stages the P values of up to kPStage complete
+    // segments in LDS and writes them out together, four 512-byte stores per
+    // segment.  A store is counted with the loads the wave waits for, so one
+    // store per segment close stalled the stream each time (measured 8 %
+    // slower at n = 20000).  Waves with inactive lanes store directly.
+    constexpr int kPStage = 8;
+    __shared__ A pst[4 * kPStage * 256];
+    __shared__ int32_t pseg[4 * kPStage];
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int64_t wc0 = cb + ((int64_t)tile * kWG + (threadIdx.x & ~63)) * VEC;   // wave's first column
+    const bool wfull = VEC == 4 && wc0 + 64 * VEC <= ce;
+    int nst = 0;   // staged segments (wave-uniform)
+    auto flush_p = [&]() {
+        __builtin_amdgcn_wave_barrier();
+        for (int t = 0; t < nst; ++t) {
+            A *dst = P + (int64_t)pseg[wv * kPStage + t] * ncp + wc0;
+            const A *src = pst + (wv * kPStage + t) * 256;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) __builtin_nontemporal_store(src[64 * e + ln], dst + 64 * e + ln);
+        }
+        __builtin_amdgcn_wave_barrier();
+        nst = 0;
+    };
 
     if (active) {
         // The chunk's rows are one stream of blocks of U rows; a segment edge
@@ -822,10 +845,17 @@ __device__ __forceinline__ void pass_tile(
                 }
                 if constexpr (P2) {
                     // streaming stores (P is read once, by the best-candidate
-                    // scan); measured faster than 16-byte or cached stores
+                    // scan); measured faster than cached stores
+                    if (wfull) {
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e)
-                        __builtin_nontemporal_store(v[e], &P[(int64_t)s * ncp + c0 + e]);
+                        for (int e = 0; e < VEC; ++e) pst[(wv * kPStage + nst) * 256 + ln * VEC + e] = v[e];
+                        if (ln == 0) pseg[wv * kPStage + nst] = s;
+                        if (++nst == kPStage) flush_p();
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e)
+                            __builtin_nontemporal_store(v[e], &P[(int64_t)s * ncp + c0 + e]);
+                    }
                 }
             }
         };
@@ -877,6 +907,9 @@ __device__ __forceinline__ void pass_tile(
             add_row(v, sdn[j], sds[j]);
         }
         close_seg();
+        if constexpr (P2) {
+            if (nst > 0) flush_p();
+        }
     }
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
