@@ -140,6 +140,7 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->sds = take((size_t)n * 4);
     L->blkcnt = take((size_t)L->n_oblk * k * 4);
     L->tdp = take((size_t)L->n_oblk * 2 * 8);
+    L->segtot = take((size_t)k * 4);
     L->seg_off = take((size_t)(k + 1) * 4);
     L->cand_v = take(8);
     L->cand_i = take(8);
@@ -281,6 +282,7 @@ int make_rc_layout(int64_t n, int32_t k, int32_t dim, const pamx_options *opt, R
     R->srow = take((size_t)n * 4);
     R->blkcnt = take((size_t)R->n_oblk * k * 4);
     R->tdp = take((size_t)R->n_oblk * 2 * 8);
+    R->segtot = take((size_t)k * 4);
     R->seg_off = take((size_t)(k + 1) * 4);
     R->cinfo = take((size_t)R->Q * 12);
     R->is_med = take((size_t)n);

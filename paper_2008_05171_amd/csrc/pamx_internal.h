@@ -180,6 +180,7 @@ struct Layout {
     size_t srow, sdn, sds;
     size_t blkcnt, blkbase, seg_off, cdn;
     size_t tdp;          // per-block sums of dn and ds (2 per block of kObjBlk objects)
+    size_t segtot;       // objects per slot (k)
     size_t part, part_i;
     size_t cand_v, cand_i, cand_a;
     size_t wg_v, wg_i, wg_c;
@@ -240,7 +241,7 @@ struct RcLayout {
     int32_t k, KP, n_ctiles, L, Q, n_oblk;
     int64_t ncp;
     size_t Xb, nb, eo, dn64, ds64, dn32, ds32, sdn, sds, sthr, snb, R64, R32, part, part_i,
-        cand_v, cand_b, wg_u, list, res_v, res_i, rlist, near, sec, srow, blkcnt, tdp, seg_off, cinfo,
+        cand_v, cand_b, wg_u, list, res_v, res_i, rlist, near, sec, srow, blkcnt, tdp, segtot, seg_off, cinfo,
         is_med, mx, eps0, bnd, mean, state, acur, lold, lnew, rs_part, total;
 };
 constexpr int kRcMaxDim = 64;     // precision form: largest point dimension

@@ -1095,7 +1095,7 @@ struct RcPtrs {
     float *nb, *dn32, *ds32, *sdn, *sds, *sthr, *snb;
     void *part;
     double *eo, *dn64, *ds64, *R64, *mx, *eps0, *bnd, *wg_u, *res_v, *cand_v, *cand_b, *tdp;
-    int32_t *near, *sec, *srow, *blkcnt, *seg_off, *cinfo3, *part_i, *list, *res_i, *rlist;
+    int32_t *near, *sec, *srow, *blkcnt, *segtot, *seg_off, *cinfo3, *part_i, *list, *res_i, *rlist;
     uint8_t *is_med;
     DevState *st;
     double *acur, *lold, *lnew;
@@ -1168,6 +1168,7 @@ static RcPtrs rc_ptrs(const RcLayout &R, void *ws) {
     p.srow = reinterpret_cast<int32_t *>(w + R.srow);
     p.blkcnt = reinterpret_cast<int32_t *>(w + R.blkcnt);
     p.tdp = reinterpret_cast<double *>(w + R.tdp);
+    p.segtot = reinterpret_cast<int32_t *>(w + R.segtot);
     p.seg_off = reinterpret_cast<int32_t *>(w + R.seg_off);
     p.cinfo3 = reinterpret_cast<int32_t *>(w + R.cinfo);
     p.is_med = reinterpret_cast<uint8_t *>(w + R.is_med);
@@ -1288,8 +1289,8 @@ hipError_t rc_swap_init(const float *X, int32_t dim, const RcLayout &R, const in
 // segment kernels of swap.hip, reused on the FP32 cache copies
 hipError_t launch_segments_f32(const int32_t *near, const float *dn, const float *ds, int64_t n,
                                int32_t k, int32_t n_oblk, int32_t *blkcnt, double *tdp,
-                               int32_t *seg_off, int32_t L, int32_t Q, void *cinfo, int32_t *srow,
-                               float *sdn, float *sds, DevState *st, hipStream_t s);
+                               int32_t *segtot, int32_t *seg_off, int32_t L, int32_t Q, void *cinfo,
+                               int32_t *srow, float *sdn, float *sds, DevState *st, hipStream_t s);
 
 hipError_t rc_swap_iteration(const float *X, int32_t dim, const RcLayout &R, int32_t *medoids,
                              const pamx_options &opt, void *ws, hipStream_t s, hipEvent_t ev0,
@@ -1301,7 +1302,8 @@ hipError_t rc_swap_iteration(const float *X, int32_t dim, const RcLayout &R, int
     const unsigned ob = (unsigned)((n + 255) / 256);
     const int nmwg = (int)((n + 255) / 256);
     hipError_t e = launch_segments_f32(p.near, p.dn32, p.ds32, n, k, R.n_oblk, p.blkcnt, p.tdp,
-                                       p.seg_off, R.L, R.Q, p.cinfo3, p.srow, p.sdn, p.sds, p.st, s);
+                                       p.segtot, p.seg_off, R.L, R.Q, p.cinfo3, p.srow, p.sdn, p.sds,
+                                       p.st, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rc_seg_const, dim3((k + 3) / 4), dim3(256), 0, s, (const int32_t *)p.srow,
                        (const int32_t *)p.seg_off, k, (const double *)p.dn64, (const double *)p.ds64,

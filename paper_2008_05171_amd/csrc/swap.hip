@@ -647,111 +647,101 @@ struct ChunkInfo {
 };
 constexpr int kHead = 1, kTail = 2;
 
-// Segment offsets (scan of the slot totals), the smallest empty slot, TD and
-// sum of ds (for the rounding bound) from the nblk block sums of
-// k_seg_count, and the carry map of every chunk.  seg_off[1..k] holds the
-// slot totals on entry.
+// Segment offsets and the stable scatter in one launch.  Every block scans
+// the k slot totals (seg_tot) into LDS offsets and places its objects at
+// segment start + block base + rank among the block's objects of the same
+// slot.  Block 0 also publishes seg_off[0..k], the smallest empty slot, TD
+// and the sum of ds (for the rounding bound) from the nblk block sums of
+// k_seg_count, and the carry map of every chunk.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_seg_scan(int32_t k, int64_t n, int32_t *__restrict__ seg_off,
-                                                   const AccT<T> *__restrict__ tdp, int32_t nblk,
-                                                   int32_t L, int32_t Q, ChunkInfo *__restrict__ cinfo,
-                                                   DevState *__restrict__ st) {
+__global__ __launch_bounds__(kObjBlk) void k_seg_scatter(
+    const int32_t *__restrict__ near, const T *__restrict__ dn, const T *__restrict__ ds, int64_t n,
+    int32_t k, const int32_t *__restrict__ blkbase, const int32_t *__restrict__ seg_tot,
+    int32_t *__restrict__ seg_off, const AccT<T> *__restrict__ tdp, int32_t nblk, int32_t L,
+    int32_t Q, ChunkInfo *__restrict__ cinfo, int32_t *__restrict__ srow, T *__restrict__ sdn,
+    T *__restrict__ sds, DevState *__restrict__ st) {
     using A = AccT<T>;
     if (st->done || st->seg_skip) return;
-    extern __shared__ int32_t soff[];    // k + 1 offsets
-    __shared__ int32_t wsum[16];
-    __shared__ A ws1[16], ws2[16];
+    extern __shared__ int32_t soff[];   // k + 1 offsets
+    __shared__ int32_t ln[kObjBlk];
+    __shared__ int32_t wsum[kObjBlk / 64];
+    __shared__ A ws1[kObjBlk / 64], ws2[kObjBlk / 64];
     __shared__ int32_t empty_min;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    if (t == 0) { empty_min = k; soff[0] = 0; }
+    const bool lead = blockIdx.x == 0;
+    // offsets: each thread takes a run of consecutive slots; a block scan of
+    // the run totals gives each run's start
+    if (t == 0) empty_min = k;
+    const int per = (k + kObjBlk - 1) / kObjBlk;
+    const int i0 = min(k, t * per), i1 = min(k, i0 + per);
+    int32_t run = 0;
+    for (int i = i0; i < i1; ++i) run += seg_tot[i];
+    int32_t x = run;   // inclusive wave scan
+    for (int w = 1; w < 64; w <<= 1) {
+        const int32_t y = __shfl_up(x, w);
+        if (lane >= w) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
     __syncthreads();
-    // segment offsets: wave scans of the slot totals, then the wave totals
-    int32_t carry = 0;
-    for (int base = 0; base < k; base += 1024) {
-        const int i = base + t;
-        const int32_t v = (i < k) ? seg_off[i + 1] : 0;
-        if (i < k && v == 0) atomicMin(&empty_min, i);
-        int32_t x = v;   // inclusive wave scan
-        for (int w = 1; w < 64; w <<= 1) {
-            const int32_t y = __shfl_up(x, w);
-            if (lane >= w) x += y;
-        }
-        if (lane == 63) wsum[wv] = x;
-        __syncthreads();
-        int32_t off = carry, tot = 0;
-        for (int u = 0; u < 16; ++u) {
-            const int32_t c = wsum[u];
-            if (u < wv) off += c;
-            tot += c;
-        }
-        if (i < k) soff[i + 1] = off + x;
-        carry += tot;
-        __syncthreads();
+    int32_t off = x - run;
+    for (int u = 0; u < wv; ++u) off += wsum[u];
+    for (int i = i0; i < i1; ++i) {
+        const int32_t c = seg_tot[i];
+        if (lead && c == 0) atomicMin(&empty_min, i);
+        soff[i] = off;
+        off += c;
     }
-    for (int i = t; i <= k; i += 1024) seg_off[i] = soff[i];
-    // TD and sum of ds over the block sums, fixed order (blocks t, t + 1024,
-    // ... per thread, wave butterflies, then the 16 wave sums in order)
-    A s1 = 0, s2 = 0;
-    for (int b = t; b < nblk; b += 1024) { s1 += tdp[2 * b]; s2 += tdp[2 * b + 1]; }
-    s1 = wave_sum<A>(s1);
-    s2 = wave_sum<A>(s2);
-    if (lane == 0) { ws1[wv] = s1; ws2[wv] = s2; }
+    if (t == 0) soff[k] = (int32_t)n;
     __syncthreads();
-    if (t == 0) {
-        s1 = 0; s2 = 0;
-        for (int u = 0; u < 16; ++u) { s1 += ws1[u]; s2 += ws2[u]; }
-    }
-    // carry map of each chunk (binary searches in LDS)
-    for (int q = t; q < Q; q += 1024) {
-        const int64_t a = (int64_t)q * L, b = min(a + (int64_t)L, n);
-        int lo = 0, hi = k;
-        while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (soff[m] <= a) lo = m; else hi = m; }
-        const int sa = lo;
-        lo = 0; hi = k;
-        while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (soff[m] <= b - 1) lo = m; else hi = m; }
-        const int sb = lo;
-        int f = 0;
-        if (soff[sa] < a || soff[sa + 1] > b) f |= kHead;
-        if (sb != sa && soff[sb + 1] > b) f |= kTail;
-        cinfo[q] = ChunkInfo{sa, sb, f};
-    }
-    if (t == 0) {
-        st->empty_slot = empty_min;
-        if constexpr (std::is_same<T, float>::value) {
-            st->td = s1;
-            // bound on the FP64 rounding of a computed change: every partial
-            // sum is <= sum(ds), chains are at most n + Q + 64 additions long
-            st->margin = 4.0 * ((double)n + Q + 68) * 0x1p-53 * (double)s2;
-        } else {
-            st->td_i = s1;
-            st->td = (double)s1;
-            st->margin = 0.0;
+    if (lead) {
+        for (int i = t; i <= k; i += kObjBlk) seg_off[i] = soff[i];
+        // TD and sum of ds over the block sums, fixed order (blocks t, t +
+        // kObjBlk, ... per thread, wave butterflies, then the wave sums in order)
+        A s1 = 0, s2 = 0;
+        for (int bb = t; bb < nblk; bb += kObjBlk) { s1 += tdp[2 * bb]; s2 += tdp[2 * bb + 1]; }
+        s1 = wave_sum<A>(s1);
+        s2 = wave_sum<A>(s2);
+        if (lane == 0) { ws1[wv] = s1; ws2[wv] = s2; }
+        // carry map of each chunk (binary searches in LDS)
+        for (int q = t; q < Q; q += kObjBlk) {
+            const int64_t qa = (int64_t)q * L, qb = min(qa + (int64_t)L, n);
+            int lo = 0, hi = k;
+            while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (soff[m] <= qa) lo = m; else hi = m; }
+            const int sa = lo;
+            lo = 0; hi = k;
+            while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (soff[m] <= qb - 1) lo = m; else hi = m; }
+            const int sb = lo;
+            int f = 0;
+            if (soff[sa] < qa || soff[sa + 1] > qb) f |= kHead;
+            if (sb != sa && soff[sb + 1] > qb) f |= kTail;
+            cinfo[q] = ChunkInfo{sa, sb, f};
+        }
+        __syncthreads();
+        if (t == 0) {
+            s1 = 0; s2 = 0;
+            for (int u = 0; u < kObjBlk / 64; ++u) { s1 += ws1[u]; s2 += ws2[u]; }
+            st->empty_slot = empty_min;
+            if constexpr (std::is_same<T, float>::value) {
+                st->td = s1;
+                // bound on the FP64 rounding of a computed change: every partial
+                // sum is <= sum(ds), chains are at most n + Q + 64 additions long
+                st->margin = 4.0 * ((double)n + Q + 68) * 0x1p-53 * (double)s2;
+            } else {
+                st->td_i = s1;
+                st->td = (double)s1;
+                st->margin = 0.0;
+            }
         }
     }
-}
-
-// Scatter objects to their sorted position: segment start + block base +
-// rank among the block's objects of the same slot (stable).
-template <typename T>
-__global__ __launch_bounds__(kObjBlk) void k_seg_scatter(const int32_t *__restrict__ near,
-                                                         const T *__restrict__ dn,
-                                                         const T *__restrict__ ds, int64_t n,
-                                                         int32_t k, const int32_t *__restrict__ blkbase,
-                                                         const int32_t *__restrict__ seg_off,
-                                                         int32_t *__restrict__ srow,
-                                                         T *__restrict__ sdn, T *__restrict__ sds,
-                                                         const DevState *__restrict__ st) {
-    if (st->done || st->seg_skip) return;
-    __shared__ int32_t ln[kObjBlk];
-    const int t = threadIdx.x;
+    // the stable scatter
     const int64_t o = (int64_t)blockIdx.x * kObjBlk + t;
-    const int32_t s = (o < n) ? near[o] : -1;
-    ln[t] = s;
+    const int32_t sl = (o < n) ? near[o] : -1;
+    ln[t] = sl;
     __syncthreads();
     if (o >= n) return;
     int rank = 0;
-    for (int u = 0; u < t; ++u) rank += (ln[u] == s);
-    const int32_t pos = seg_off[s] + blkbase[(int64_t)blockIdx.x * k + s] + rank;
+    for (int u = 0; u < t; ++u) rank += (ln[u] == sl);
+    const int32_t pos = soff[sl] + blkbase[(int64_t)blockIdx.x * k + sl] + rank;
     srow[pos] = (int32_t)o;
     sdn[pos] = dn[o];
     sds[pos] = ds[o];
@@ -1914,6 +1904,7 @@ struct SwapPtrs {
     T *dn, *ds, *sdn, *sds;
     uint8_t *is_med;
     AccT<T> *cdn, *part, *wg_v, *P, *cand_a, *slot_v, *tdp;
+    int32_t *segtot;
     ChunkInfo *cinfo;
     DevState *st;
 };
@@ -1932,6 +1923,7 @@ static SwapPtrs<T> ptrs(const Layout &L, void *ws) {
     p.sds = reinterpret_cast<T *>(w + L.sds);
     p.blkcnt = reinterpret_cast<int32_t *>(w + L.blkcnt);
     p.tdp = reinterpret_cast<AccT<T> *>(w + L.tdp);
+    p.segtot = reinterpret_cast<int32_t *>(w + L.segtot);
     p.seg_off = reinterpret_cast<int32_t *>(w + L.seg_off);
     p.cinfo = reinterpret_cast<ChunkInfo *>(w + L.blkbase);
     p.cdn = reinterpret_cast<AccT<T> *>(w + L.cdn);
@@ -1991,13 +1983,12 @@ static void enqueue_segments(const Layout &L, const SwapPtrs<T> &p, hipStream_t 
                        (const int32_t *)p.near, (const T *)p.dn, (const T *)p.ds, n, k, p.blkcnt,
                        p.tdp, p.st);
     hipLaunchKernelGGL(k_seg_colscan, dim3((k + 3) / 4), dim3(256), 0, s, p.blkcnt, L.n_oblk, k,
-                       p.seg_off + 1, (const DevState *)p.st);
-    hipLaunchKernelGGL(k_seg_scan<T>, dim3(1), dim3(1024), (size_t)(k + 1) * 4, s, k, n,
-                       p.seg_off, (const AccT<T> *)p.tdp, L.n_oblk, L.L, L.Q, p.cinfo, p.st);
-    hipLaunchKernelGGL(k_seg_scatter<T>, dim3(L.n_oblk), dim3(kObjBlk), 0, s,
+                       p.segtot, (const DevState *)p.st);
+    hipLaunchKernelGGL(k_seg_scatter<T>, dim3(L.n_oblk), dim3(kObjBlk), (size_t)(k + 1) * 4, s,
                        (const int32_t *)p.near, (const T *)p.dn, (const T *)p.ds, n, k,
-                       (const int32_t *)p.blkcnt, (const int32_t *)p.seg_off, p.srow, p.sdn,
-                       p.sds, (const DevState *)p.st);
+                       (const int32_t *)p.blkcnt, (const int32_t *)p.segtot, p.seg_off,
+                       (const AccT<T> *)p.tdp, L.n_oblk, L.L, L.Q, p.cinfo, p.srow, p.sdn, p.sds,
+                       p.st);
 }
 
 // win: FasterPAM window pass (L placed by set_window: L.L, L.Q are the
@@ -2187,17 +2178,16 @@ hipError_t enqueue_swap_caches(const T *D, int64_t ld, const Layout &L, const in
 // The segment kernels on FP32 caches, for the mixed-precision form.
 hipError_t launch_segments_f32(const int32_t *near, const float *dn, const float *ds, int64_t n,
                                int32_t k, int32_t n_oblk, int32_t *blkcnt, double *tdp,
-                               int32_t *seg_off, int32_t L, int32_t Q, void *cinfo, int32_t *srow,
-                               float *sdn, float *sds, DevState *st, hipStream_t s) {
+                               int32_t *segtot, int32_t *seg_off, int32_t L, int32_t Q, void *cinfo,
+                               int32_t *srow, float *sdn, float *sds, DevState *st, hipStream_t s) {
     hipLaunchKernelGGL(k_seg_count<float>, dim3(n_oblk), dim3(kObjBlk), (size_t)k * 4, s, near, dn,
                        ds, n, k, blkcnt, tdp, st);
     hipLaunchKernelGGL(k_seg_colscan, dim3((k + 3) / 4), dim3(256), 0, s, blkcnt, n_oblk, k,
-                       seg_off + 1, (const DevState *)st);
-    hipLaunchKernelGGL(k_seg_scan<float>, dim3(1), dim3(1024), (size_t)(k + 1) * 4, s, k, n, seg_off,
-                       (const double *)tdp, n_oblk, L, Q, static_cast<ChunkInfo *>(cinfo), st);
-    hipLaunchKernelGGL(k_seg_scatter<float>, dim3(n_oblk), dim3(kObjBlk), 0, s, near, dn, ds, n, k,
-                       (const int32_t *)blkcnt, (const int32_t *)seg_off, srow, sdn, sds,
-                       (const DevState *)st);
+                       segtot, (const DevState *)st);
+    hipLaunchKernelGGL(k_seg_scatter<float>, dim3(n_oblk), dim3(kObjBlk), (size_t)(k + 1) * 4, s,
+                       near, dn, ds, n, k, (const int32_t *)blkcnt, (const int32_t *)segtot, seg_off,
+                       (const double *)tdp, n_oblk, L, Q, static_cast<ChunkInfo *>(cinfo), srow, sdn,
+                       sds, st);
     return hipGetLastError();
 }
 
