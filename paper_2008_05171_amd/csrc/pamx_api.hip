@@ -284,7 +284,7 @@ int make_rc_layout(int64_t n, int32_t k, int32_t dim, const pamx_options *opt, R
     R->tdp = take((size_t)R->n_oblk * 2 * 8);
     R->segtot = take((size_t)k * 4);
     R->seg_off = take((size_t)(k + 1) * 4);
-    R->cinfo = take((size_t)R->Q * 12);
+    R->cinfo = take((size_t)R->Q * 16);
     R->is_med = take((size_t)n);
     R->mx = take(2 * 8);
     R->eps0 = take(4 * 8);

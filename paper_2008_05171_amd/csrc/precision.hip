@@ -315,7 +315,7 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(3))) void k
     const __bf16 *__restrict__ Xs, int32_t KP, const float *__restrict__ nb, int64_t n, int32_t k,
     const int32_t *__restrict__ srow, const float *__restrict__ sdn, const float *__restrict__ sds,
     const float *__restrict__ sthr, const float *__restrict__ snb, const double *__restrict__ eps0,
-    const int32_t *__restrict__ seg_off, const double *__restrict__ R64, const int32_t *__restrict__ cinfo3,
+    const int32_t *__restrict__ seg_off, const double *__restrict__ R64, const int32_t *__restrict__ cinfo4,
     int32_t L, int64_t ncp, ACC *__restrict__ part, int32_t *__restrict__ part_i,
     const DevState *__restrict__ st) {
     if (st->done) return;
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int64_t a = (int64_t)q * L, b = min(a + (int64_t)L, n);
     const int64_t cbase = (int64_t)blockIdx.x * kRT + w * 64;
     const int64_t c = cbase + lane;
-    const int sa = cinfo3[3 * q], sb = cinfo3[3 * q + 1], flags = cinfo3[3 * q + 2];
+    const int sa = cinfo4[4 * q], sb = cinfo4[4 * q + 1], flags = cinfo4[4 * q + 2];
     bf16x8 bh[2][KS], bl[2][KS];
     load_bq<KS>(Xs, KP, n, cbase, bh, bl);
     const float nc = (c < n) ? nb[c] : 0.0f;
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(3))) void k
 template <typename ACC>
 __global__ __launch_bounds__(256) void k_rc_swap_merge(
     const ACC *__restrict__ part, const int32_t *__restrict__ part_i,
-    const int32_t *__restrict__ cinfo3, int32_t Q, int64_t n, int32_t k, int64_t ncp,
+    const int32_t *__restrict__ cinfo4, int32_t Q, int64_t n, int32_t k, int64_t ncp,
     const double *__restrict__ R64, const uint8_t *__restrict__ is_med,
     const DevState *__restrict__ st, const double *__restrict__ bnd, double *__restrict__ cand_v,
     double *__restrict__ cand_b, double *__restrict__ wg_u) {
@@ -444,7 +444,7 @@ __global__ __launch_bounds__(256) void k_rc_swap_merge(
             cn += pi[2 * ncp];
             const int32_t i = pi[0];
             if (i != INT_MAX && lt2(pq[3 * ncp], i, bestv, besti)) { bestv = pq[3 * ncp]; besti = i; }
-            const int sa = cinfo3[3 * q], sb = cinfo3[3 * q + 1], fl = cinfo3[3 * q + 2];
+            const int sa = cinfo4[4 * q], sb = cinfo4[4 * q + 1], fl = cinfo4[4 * q + 2];
             if (fl & 1) {
                 if (sa == run_s) run_m += pq[1 * ncp];
                 else { flush(); run_s = sa; run_m = pq[1 * ncp]; }
@@ -1095,7 +1095,7 @@ struct RcPtrs {
     float *nb, *dn32, *ds32, *sdn, *sds, *sthr, *snb;
     void *part;
     double *eo, *dn64, *ds64, *R64, *mx, *eps0, *bnd, *wg_u, *res_v, *cand_v, *cand_b, *tdp;
-    int32_t *near, *sec, *srow, *blkcnt, *segtot, *seg_off, *cinfo3, *part_i, *list, *res_i, *rlist;
+    int32_t *near, *sec, *srow, *blkcnt, *segtot, *seg_off, *cinfo4, *part_i, *list, *res_i, *rlist;
     uint8_t *is_med;
     DevState *st;
     double *acur, *lold, *lnew;
@@ -1108,7 +1108,7 @@ static void rc_swap_pass_launch(const RcPtrs &p, const RcLayout &R, int64_t n, i
                        (const __bf16 *)p.Xs, R.KP, (const float *)p.nb, n, k,
                        (const int32_t *)p.srow, (const float *)p.sdn, (const float *)p.sds,
                        (const float *)p.sthr, (const float *)p.snb, (const double *)p.eps0,
-                       (const int32_t *)p.seg_off, (const double *)p.R64, (const int32_t *)p.cinfo3,
+                       (const int32_t *)p.seg_off, (const double *)p.R64, (const int32_t *)p.cinfo4,
                        R.L, R.ncp, static_cast<ACC *>(p.part), p.part_i, (const DevState *)p.st);
 }
 
@@ -1170,7 +1170,7 @@ static RcPtrs rc_ptrs(const RcLayout &R, void *ws) {
     p.tdp = reinterpret_cast<double *>(w + R.tdp);
     p.segtot = reinterpret_cast<int32_t *>(w + R.segtot);
     p.seg_off = reinterpret_cast<int32_t *>(w + R.seg_off);
-    p.cinfo3 = reinterpret_cast<int32_t *>(w + R.cinfo);
+    p.cinfo4 = reinterpret_cast<int32_t *>(w + R.cinfo);
     p.is_med = reinterpret_cast<uint8_t *>(w + R.is_med);
     p.mx = reinterpret_cast<double *>(w + R.mx);
     p.eps0 = reinterpret_cast<double *>(w + R.eps0);
@@ -1302,7 +1302,7 @@ hipError_t rc_swap_iteration(const float *X, int32_t dim, const RcLayout &R, int
     const unsigned ob = (unsigned)((n + 255) / 256);
     const int nmwg = (int)((n + 255) / 256);
     hipError_t e = launch_segments_f32(p.near, p.dn32, p.ds32, n, k, R.n_oblk, p.blkcnt, p.tdp,
-                                       p.segtot, p.seg_off, R.L, R.Q, p.cinfo3, p.srow, p.sdn, p.sds,
+                                       p.segtot, p.seg_off, R.L, R.Q, p.cinfo4, p.srow, p.sdn, p.sds,
                                        p.st, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rc_seg_const, dim3((k + 3) / 4), dim3(256), 0, s, (const int32_t *)p.srow,
@@ -1320,12 +1320,12 @@ hipError_t rc_swap_iteration(const float *X, int32_t dim, const RcLayout &R, int
     if (ev1) (void)hipEventRecord(ev1, s);
     if (acc64)
         hipLaunchKernelGGL(k_rc_swap_merge<double>, dim3(nmwg), dim3(256), 0, s, (const double *)p.part,
-                           (const int32_t *)p.part_i, (const int32_t *)p.cinfo3, R.Q, n, k, R.ncp,
+                           (const int32_t *)p.part_i, (const int32_t *)p.cinfo4, R.Q, n, k, R.ncp,
                            (const double *)p.R64, (const uint8_t *)p.is_med, (const DevState *)p.st,
                            (const double *)p.bnd, p.cand_v, p.cand_b, p.wg_u);
     else
         hipLaunchKernelGGL(k_rc_swap_merge<float>, dim3(nmwg), dim3(256), 0, s, (const float *)p.part,
-                           (const int32_t *)p.part_i, (const int32_t *)p.cinfo3, R.Q, n, k, R.ncp,
+                           (const int32_t *)p.part_i, (const int32_t *)p.cinfo4, R.Q, n, k, R.ncp,
                            (const double *)p.R64, (const uint8_t *)p.is_med, (const DevState *)p.st,
                            (const double *)p.bnd, p.cand_v, p.cand_b, p.wg_u);
     hipLaunchKernelGGL(k_rc_upper, dim3(1), dim3(1024), 0, s, (const double *)p.wg_u, nmwg, p.st);

@@ -644,6 +644,7 @@ __global__ __launch_bounds__(256) void k_seg_colscan(int32_t *__restrict__ blkcn
 
 struct ChunkInfo {
     int32_t sa, sb, flags;  // segment of the first / last object, carry flags
+    int32_t se0;            // end of segment sa (seg_off[sa + 1])
 };
 constexpr int kHead = 1, kTail = 2;
 
@@ -714,7 +715,7 @@ __global__ __launch_bounds__(kObjBlk) void k_seg_scatter(
             int f = 0;
             if (soff[sa] < qa || soff[sa + 1] > qb) f |= kHead;
             if (sb != sa && soff[sb + 1] > qb) f |= kTail;
-            cinfo[q] = ChunkInfo{sa, sb, f};
+            cinfo[q] = ChunkInfo{sa, sb, f, soff[sa + 1]};
         }
         __syncthreads();
         if (t == 0) {
@@ -812,7 +813,7 @@ __device__ __forceinline__ void pass_tile(
         // inside a block closes the segment there (a wave-uniform branch), so
         // loads are never cut short at segment edges.
         int s = ci.sa;                                   // segment of the current row
-        int64_t se = min((int64_t)seg_off[s + 1], b);    // its end within the chunk
+        int64_t se = min((int64_t)ci.se0, b);            // its end within the chunk
         A M[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) M[e] = 0;
@@ -917,7 +918,15 @@ __global__ __launch_bounds__(kWG) void k_swap_pass(
     AccT<T> *__restrict__ cdn, const ChunkInfo *__restrict__ cinfo, int32_t L, int64_t ncp,
     AccT<T> *__restrict__ part, int32_t *__restrict__ part_i, AccT<T> *__restrict__ P,
     const DevState *__restrict__ st) {
-    if (st->done) return;
+    if constexpr (!WIN) {
+        // the chunk's map entry and first row are read with the state, so
+        // one memory round trip precedes the first rows of D
+        const ChunkInfo ci0 = cinfo[blockIdx.y];
+        const int32_t r0 = srow[(int64_t)blockIdx.y * L];
+        if (st->done || r0 < 0 || ci0.sa < 0) return;   // rows and slots are never negative
+    } else {
+        if (st->done) return;
+    }
     if constexpr (WIN) {
         // one work-group per object chunk, over every tile of the window
         const int64_t cb = st->fw_base, ce = st->fw_end;
