@@ -252,6 +252,22 @@ def test_k1_and_k_equals_n():
         assert res.stats["iterations"] == ref.iterations
 
 
+@pytest.mark.parametrize("seed,n,k", [(31, 800, 600), (32, 1200, 1100)])
+@pytest.mark.parametrize("variant", ["fastpam1", "fastpam2"])
+def test_large_k_bitexact(seed, n, k, variant):
+    # k well above the 256 threads of the segment kernels: each thread scans
+    # a run of several slot totals into the segment offsets
+    _say("large_k", seed, n, k, variant)
+    X, D = _int_case(n, seed)
+    if variant == "fastpam2":
+        ref = oracle.pam(k, D=D, variant=oracle.FASTPAM2)
+    else:
+        ref = oracle.pam(k, D=D)
+    res = px().fit(_t(X), k, variant=variant, trace=True)
+    _check_same(res, ref, k)
+    assert res.stats["iterations"] == ref.iterations
+
+
 def test_tiny_n():
     _say("tiny_n")
     for n in (1, 2, 3):
