@@ -19,7 +19,8 @@
  *     stream.  Every call returns after the work on `stream` has finished.
  *   - The library allocates no device memory.  Scratch space is the caller's
  *     workspace `ws` of `ws_bytes` bytes, 256-byte aligned, sized by
- *     pamx_workspace_bytes() for the same arguments.
+ *     pamx_workspace_bytes() for the same arguments (pamx_swap_noalloc uses
+ *     a fixed scratch array of the library instead).
  *   - Dissimilarities are a row-major n x n matrix with leading dimension
  *     `ld` >= n (elements): D[o*ld + c] = d(x_o, x_c).  D must be symmetric,
  *     non-negative and have a zero diagonal (Sec. 2 requires only a
@@ -224,6 +225,25 @@ int pamx_build(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
 int pamx_swap(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
               const pamx_options *opt, int32_t *medoids, int32_t *labels, double *td,
               pamx_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* pamx_swap without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Arguments, results and errors are those of pamx_swap,
+ * and the same kernels run, so the results equal pamx_swap's bit for bit.
+ * The scratch is a fixed device array of PAMX_NOALLOC_SCRATCH_BYTES inside
+ * the library: each GPU it runs on holds one copy until the process ends,
+ * and every call on that GPU reuses it, so calls that overlap on one GPU
+ * (other streams, other host threads) race and must not be made.  Arguments
+ * whose workspace (pamx_workspace_bytes(n, k, 0, PAMX_INPUT_D, dtype, opt))
+ * exceeds that size return PAMX_ERR_WORKSPACE before any device work.
+ * opt->profile, opt->graph and chunk = PAMX_CHUNK_TUNE are refused
+ * (PAMX_ERR_ARG): each would create HIP events or graphs.  The stats'
+ * durations (ms_*) are 0.  Allocates nothing: no hipMalloc, no hipFree, no
+ * event creation. */
+#define PAMX_NOALLOC_SCRATCH_BYTES (64ll << 20) /* 64 MiB per GPU */
+int pamx_swap_noalloc(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                      const pamx_options *opt, int32_t *medoids, int32_t *labels, double *td,
+                      pamx_stats *stats, void *stream);
 
 /* Whole fit: distances (for points), BUILD, SWAP, labels and TD.
  *   XorD  device: n x n matrix (input_kind PAMX_INPUT_D, ld = n) or n x dim

@@ -481,15 +481,18 @@ extern "C" int pamx_read_probe(const void *D, int64_t n, int64_t ld, int32_t chu
 namespace {
 
 struct Timer {
-    hipEvent_t e[6];
+    hipEvent_t e[6] = {};
     bool ok = false;
-    Timer() {
+    // on = false: no events are created and every duration reads 0
+    explicit Timer(bool on = true) {
+        if (!on) return;
         ok = true;
         for (auto &x : e)
             if (hipEventCreate(&x) != hipSuccess) ok = false;
     }
     ~Timer() {
-        for (auto &x : e) (void)hipEventDestroy(x);
+        for (auto &x : e)
+            if (x) (void)hipEventDestroy(x);
     }
     void rec(int i, hipStream_t s) {
         if (ok) (void)hipEventRecord(e[i], s);
@@ -1009,6 +1012,79 @@ extern "C" int pamx_swap(const void *D, int32_t dtype, int64_t n, int64_t ld, in
         stats->ms_swap = tm.ms(2, 3);
         stats->ms_total = tm.ms(0, 4);
     }
+    return rc;
+}
+
+// ---------------------------------------------------------------- SWAP with no allocation
+// pamx_swap for callers that cannot allocate: the workspace is a fixed
+// device array of this library instead of a caller's buffer.  Each GPU the
+// library runs on holds its own copy until the process ends; every call on
+// that GPU reuses it (calls that overlap on one GPU race).  Every region the
+// SWAP kernels read is written by the same call first (state, caches,
+// segments, partials), so what the previous call left there does not matter.
+static __device__ __align__(256) unsigned char scratch[PAMX_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevs = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kScratchDevs] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call on that device (with it current) and kept.  Host code uses only this
+// address: the array's name on the host is a stand-in, not device memory.
+int scratch_on_device(void **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevs)
+        return fail(PAMX_ERR_HIP, "device %d beyond the %d devices with a scratch address", dev,
+                    kScratchDevs);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(PAMX_ERR_HIP, "hipGetSymbolAddress gave no address for the scratch array");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return PAMX_OK;
+}
+}  // namespace
+
+extern "C" int pamx_swap_noalloc(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                                 const pamx_options *opt_in, int32_t *medoids, int32_t *labels,
+                                 double *td, pamx_stats *stats, void *stream) {
+    pamx_options opt;
+    pamx_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    int rc = swap_args(D, dtype, n, ld, k, &opt, medoids);
+    if (rc) return rc;
+    // each of these creates HIP events or graphs
+    if (opt.profile) return fail(PAMX_ERR_ARG, "pamx_swap_noalloc: profile must be 0");
+    if (opt.graph) return fail(PAMX_ERR_ARG, "pamx_swap_noalloc: graph must be 0");
+    if (opt.chunk == PAMX_CHUNK_TUNE)
+        return fail(PAMX_ERR_ARG, "pamx_swap_noalloc: no chunk tuning (PAMX_CHUNK_TUNE)");
+    Layout L;
+    make_layout(n, k, 0, PAMX_INPUT_D, dtype, ld, &opt, &L, D);
+    const size_t need = layout_need(L, &opt);
+    if (need > (size_t)PAMX_NOALLOC_SCRATCH_BYTES)
+        return fail(PAMX_ERR_WORKSPACE,
+                    "pamx_swap_noalloc: these arguments need %zu bytes of scratch, more than its "
+                    "fixed %zu (use pamx_swap with a workspace)",
+                    need, (size_t)PAMX_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    rc = scratch_on_device(&ws);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    Timer tm(false);
+    if (dtype == PAMX_F32)
+        rc = swap_impl<float>(static_cast<const float *>(D), ld, L, k, opt, medoids, labels, td,
+                              stats, ws, s, tm);
+    else
+        rc = swap_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, opt, medoids, labels, td,
+                                stats, ws, s, tm);
+    if (rc < 0) return rc;
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(PAMX_ERR_HIP, "stream synchronize failed");
     return rc;
 }
 

@@ -65,7 +65,8 @@ EXPORTS = ("pamx_default_options", "pamx_workspace_bytes", "pamx_dist", "pamx_bu
            "pamx_swap", "pamx_fit", "pamx_batched_workspace_bytes", "pamx_fit_batched",
            "pamx_init_workspace_bytes", "pamx_init_dw", "pamx_init_lab", "pamx_clarans",
            "pamx_rect_workspace_bytes", "pamx_fit_rect", "pamx_swap_rect",
-           "pamx_check_dissimilarity", "pamx_read_probe", "pamx_last_error")
+           "pamx_check_dissimilarity", "pamx_read_probe", "pamx_swap_noalloc",
+           "pamx_last_error")
 
 
 class PamxError(RuntimeError):
@@ -111,12 +112,14 @@ def load(path: str = LIB_PATH):
     lib.pamx_check_dissimilarity.argtypes = [P, i32, i64, i64, ctypes.POINTER(ctypes.c_int32),
                                              ctypes.POINTER(ctypes.c_int64), P, sz, P]
     lib.pamx_read_probe.argtypes = [P, i64, i64, i32, P, i64, P]
+    lib.pamx_swap_noalloc.argtypes = [P, i32, i64, i64, i32, opt_p, P, P, dbl_p, st_p, P]
     lib.pamx_last_error.argtypes = []
     lib.pamx_last_error.restype = ctypes.c_char_p
     for name in ("pamx_workspace_bytes", "pamx_dist", "pamx_build", "pamx_swap", "pamx_fit",
                  "pamx_batched_workspace_bytes", "pamx_fit_batched", "pamx_init_workspace_bytes",
                  "pamx_init_dw", "pamx_init_lab", "pamx_clarans", "pamx_rect_workspace_bytes",
-                 "pamx_fit_rect", "pamx_swap_rect", "pamx_check_dissimilarity", "pamx_read_probe"):
+                 "pamx_fit_rect", "pamx_swap_rect", "pamx_check_dissimilarity", "pamx_read_probe",
+                 "pamx_swap_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -219,6 +222,22 @@ def pamx_swap(D, k, medoids, ws, labels=None, opt=None, n=None, ld=None, stream=
                                  _ptr(labels), ctypes.byref(td), ctypes.byref(st), _ptr(ws),
                                  ws.numel() * ws.element_size(), _stream(stream)))
     return rc, td.value, st
+
+
+def pamx_swap_noalloc(D, k, medoids, labels=None, opt=None, n=None, ld=None, stream=None):
+    """pamx_swap with the library's fixed scratch array instead of a workspace."""
+    n = D.shape[0] if n is None else n
+    ld = D.stride(0) if ld is None else ld
+    td = ctypes.c_double()
+    st = pamx_stats()
+    rc = _check(load().pamx_swap_noalloc(_ptr(D), _dtype_code(D), int(n), int(ld), int(k),
+                                         ctypes.byref(opt) if opt is not None else None,
+                                         _ptr(medoids), _ptr(labels), ctypes.byref(td),
+                                         ctypes.byref(st), _stream(stream)))
+    return rc, td.value, st
+
+
+PAMX_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def pamx_fit(XorD, input_kind, k, medoids, labels, ws, metric=PAMX_L2, opt=None, stream=None):

@@ -292,3 +292,32 @@ def test_read_probe_argument_errors(lib):
     assert call(n=100000, ld=100000, chunk=1, slen=10 ** 9) == abi.PAMX_ERR_ARG  # > 65535 chunks
     assert call(s=None) == abi.PAMX_ERR_ARG
     assert call(slen=39) == abi.PAMX_ERR_ARG   # 2 tiles x 20 chunks = 40 sums
+
+
+def test_noalloc_host_errors(lib):
+    """pamx_swap_noalloc refuses, before any device work, arguments whose
+    workspace exceeds its fixed scratch and the options that would create
+    events or graphs."""
+    fake = ctypes.c_void_p(0x100000)          # never dereferenced: rejected first
+
+    def call(n, k, opt=None, dtype=abi.PAMX_F32):
+        return lib.pamx_swap_noalloc(fake, dtype, n, n, k, ctypes.byref(opt) if opt else None,
+                                     fake, None, None, None, None)
+
+    o2 = abi.pamx_default_options()
+    o2.variant = abi.PAMX_FASTPAM2        # 500 x 1e5 per-medoid changes: 400 MB
+    assert abi.pamx_workspace_bytes(100000, 500, 0, abi.PAMX_INPUT_D, abi.PAMX_F32,
+                                    o2) > abi.PAMX_NOALLOC_SCRATCH_BYTES
+    assert call(100000, 500, o2) == abi.PAMX_ERR_WORKSPACE
+    assert "scratch" in abi.pamx_last_error()
+    for field in ("profile", "graph"):
+        o = abi.pamx_default_options()
+        setattr(o, field, 1)
+        assert call(1000, 5, o) == abi.PAMX_ERR_ARG
+        assert field in abi.pamx_last_error()
+    o = abi.pamx_default_options()
+    o.chunk = abi.PAMX_CHUNK_TUNE
+    assert call(1000, 5, o) == abi.PAMX_ERR_ARG
+    assert call(10, 11) == abi.PAMX_ERR_ARG
+    assert lib.pamx_swap_noalloc(None, abi.PAMX_F32, 10, 10, 2, None, fake, None, None, None,
+                                 None) == abi.PAMX_ERR_ARG
