@@ -40,6 +40,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 L1 = 1
 L2 = 2
+L2F32 = 3        # Euclidean, each distance rounded to the nearest FP32 value
 PAM = 1          # best swap per iteration (PAM == FastPAM1 result)
 FASTPAM2 = 2     # best swap per medoid, applied eagerly
 FASTERPAM = 3    # Alg. 4: eager swap of each improving candidate in scan order
@@ -48,11 +49,15 @@ _lib = None
 
 
 def compile_oracle(force: bool = False) -> str:
-    """Compile pam_oracle.c into liboracle.so with gcc (OpenMP, -O2)."""
+    """Compile pam_oracle.c into liboracle.so with gcc (OpenMP, -O3 for the
+    host's own CPU).  Floating-point contraction stays off and no fast-math
+    flag is given, so every FP64 operation is rounded as written and the
+    results do not depend on the CPU it was built for."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+            ["gcc", "-O3", "-march=native", "-ffp-contract=off", "-std=c11", "-fopenmp", "-fPIC",
+             "-shared", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -65,6 +70,8 @@ def _load():
     P = ctypes.c_void_p
     i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_num_threads.restype = ctypes.c_int
     lib.orc_dist_matrix.argtypes = [P, i64, i32, i32, P]
     lib.orc_nearest.argtypes = [P, P, i64, i32, i32, P, i32, P, P, P]
     lib.orc_td.argtypes = [P, P, i64, i32, i32, P, i32, P]
@@ -118,6 +125,11 @@ class _Src:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(t: int) -> int:
+    """Threads of the oracle's parallel loops from now on; returns the count."""
+    return int(_load().orc_set_num_threads(int(t)))
 
 
 def dist_matrix(X, metric=L2) -> np.ndarray:

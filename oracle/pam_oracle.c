@@ -111,7 +111,9 @@ typedef struct {
     const double *X;  /* row-major n x dim points, used when D is NULL */
     int64_t n;
     int32_t dim;
-    int32_t metric;   /* 1 = Manhattan (L1), 2 = Euclidean (L2) */
+    int32_t metric;   /* 1 = Manhattan (L1), 2 = Euclidean (L2), 3 = the Euclidean
+                         distance rounded to the nearest FP32 value (the
+                         entries of an FP32 dissimilarity matrix) */
 } src_t;
 
 static double dist(const src_t *s, int64_t a, int64_t b)
@@ -128,6 +130,7 @@ static double dist(const src_t *s, int64_t a, int64_t b)
         double t = x[j] - y[j];
         acc += t * t;
     }
+    if (s->metric == 3) return (double)(float)sqrt(acc);
     return sqrt(acc);
 }
 
@@ -135,7 +138,7 @@ static int make_src(src_t *s, const double *D, const double *X, int64_t n,
                     int32_t dim, int32_t metric)
 {
     if (n < 1) return ORC_ERR_ARG;
-    if (!D && (!X || dim < 1 || (metric != 1 && metric != 2))) return ORC_ERR_ARG;
+    if (!D && (!X || dim < 1 || metric < 1 || metric > 3)) return ORC_ERR_ARG;
     s->D = D; s->X = X; s->n = n; s->dim = dim; s->metric = metric;
     return ORC_OK;
 }
@@ -145,6 +148,19 @@ int orc_num_threads(void)
 #ifdef _OPENMP
     return omp_get_max_threads();
 #else
+    return 1;
+#endif
+}
+
+/* Threads used by the parallel loops that follow (t >= 1); returns the
+ * count now in effect. */
+int orc_set_num_threads(int t)
+{
+#ifdef _OPENMP
+    if (t >= 1) omp_set_num_threads(t);
+    return omp_get_max_threads();
+#else
+    (void)t;
     return 1;
 #endif
 }

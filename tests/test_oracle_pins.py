@@ -138,6 +138,39 @@ def test_dist_matrix_vs_scipy():
     assert np.array_equal(oracle.dist_rows(Xi, rows, oracle.L1), cdist(Xi[rows], Xi, "cityblock"))
 
 
+def test_l2f32_is_the_fp32_rounding_of_the_distance():
+    """Metric L2F32: every Euclidean distance rounded to the nearest FP32
+    value (what an FP32 matrix holds).  scipy's FP64 distances rounded by
+    numpy agree except where the two FP64 values straddle a rounding
+    boundary (then within one FP32 ulp); the swap changes in this metric
+    equal those computed from that FP32 matrix, and are the TD differences
+    of the swaps (brute force)."""
+    rng = np.random.default_rng(31)
+    X = rng.normal(size=(60, 7)) * 3.0
+    ref = cdist(X, X).astype(np.float32)
+    got = oracle.dist_matrix(X, oracle.L2F32)
+    assert np.all(got == got.astype(np.float32))             # FP32 values
+    ulp = np.spacing(ref)
+    assert np.all(np.abs(got - ref.astype(np.float64)) <= ulp)
+    assert np.mean(got == ref) > 0.99
+    rows = np.array([59, 3, 3])
+    assert np.array_equal(oracle.dist_rows(X, rows, oracle.L2F32), got[rows])
+    med = [4, 17, 33, 50]
+    cand = np.arange(60)
+    tabx = oracle.swap_list(med, cand, X=X, metric=oracle.L2F32)
+    tabd = oracle.swap_list(med, cand, D=got)
+    assert np.array_equal(np.isnan(tabx), np.isnan(tabd))
+    assert np.array_equal(tabx[~np.isnan(tabx)], tabd[~np.isnan(tabd)])
+    Dl = got.tolist()
+    td0 = brute.td_of(Dl, med)
+    for c in (0, 9, 59):
+        for i in range(4):
+            m2 = list(med)
+            m2[i] = c
+            assert tabx[c, i] == pytest.approx(brute.td_of(Dl, m2) - td0, abs=1e-12)
+    assert oracle.td(med, X=X, metric=oracle.L2F32)[0] == pytest.approx(td0, abs=1e-12)
+
+
 # ---------------------------------------------------------------- BUILD
 @pytest.mark.parametrize("exclude_self", [False, True])
 def test_build_is_greedy_td(exclude_self):
