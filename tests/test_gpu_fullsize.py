@@ -98,6 +98,22 @@ def _check_build_step(bm, t, cand, exact=False, full=False, **src):
             assert cand[order[0]] == bm[t], t
 
 
+def _assert_best_swap(tab, cands, slot, cand, tol):
+    """(slot, cand) is the first minimum of the oracle's table (rows: cands,
+    columns: slots) in (change, slot, candidate) order, whenever the
+    runner-up lies more than 2 tol above it (closer values may trade places
+    under a different FP64 summation order)."""
+    vals = np.where(np.isnan(tab), np.inf, tab)
+    k = vals.shape[1]
+    slots = np.broadcast_to(np.arange(k)[None, :], vals.shape).ravel()
+    cidx = np.broadcast_to(np.asarray(cands)[:, None], vals.shape).ravel()
+    flat = vals.ravel()
+    order = np.lexsort((cidx, slots, flat))
+    best, second = int(order[0]), int(order[1])
+    if flat[second] - flat[best] > 2 * tol:
+        assert (int(slots[best]), int(cidx[best])) == (slot, cand), (slots[best], cidx[best])
+
+
 # ============================================================ n = 20000, FP32 matrix
 @pytest.fixture(scope="module")
 def gmm16():
@@ -149,9 +165,13 @@ def test_gmm16_swap_full(gmm16, variant):
         tol = _swap_tol(meds[j], n, D=Dq)
         want = oracle.swap_list(meds[j], [cand], D=Dq)[0, slot]
         assert dl < 0 and abs(dl - want) <= tol, (j, dl, want, tol)
-        if variant == "fastpam1":                    # the best swap of its iteration
-            size = 2048 if j == 0 else 512
-            tab = oracle.swap_list(meds[j], _non_medoid_sample(rng, n, meds[j], size), D=Dq)
+        if variant == "fastpam1" and j == 0:         # the first search over every candidate
+            allc = np.arange(n)
+            tab = oracle.swap_list(meds[0], allc, D=Dq)
+            assert dl <= np.nanmin(tab) + tol, (dl, np.nanmin(tab))
+            _assert_best_swap(tab, allc, slot, cand, tol)
+        elif variant == "fastpam1":                  # the best swap of its iteration
+            tab = oracle.swap_list(meds[j], _non_medoid_sample(rng, n, meds[j], 512), D=Dq)
             assert dl <= np.nanmin(tab) + tol, (j, dl, np.nanmin(tab))
     final = r.medoids.cpu().numpy()
     assert np.array_equal(final, meds[-1])
@@ -239,6 +259,65 @@ def _build_td_plus_changes(r, bm, Xi):
     return oracle.td(bm, X=Xi, metric=oracle.L1)[0] + sum(d for _, _, d in r.trace)
 
 
+def _oracle_f32_matrix(X, block=1000):
+    """The n x n matrix of Euclidean distances rounded to FP32 (the oracle's
+    metric L2F32), computed by the oracle a block of rows at a time and
+    copied to the device (the host never holds it whole)."""
+    n = X.shape[0]
+    X64 = np.ascontiguousarray(X, dtype=np.float64)
+    D = torch.empty((n, n), dtype=torch.float32, device=DEV)
+    for r0 in range(0, n, block):
+        rows = np.arange(r0, min(r0 + block, n))
+        blk = oracle.dist_rows(X64, rows, oracle.L2F32).astype(np.float32)
+        D[r0:r0 + len(rows)].copy_(torch.from_numpy(blk))
+    return D
+
+
+def test_zipf32_f32_matrix_fastpam2_full():
+    """The 40 GB FP32 workload, eager FastPAM2, on a matrix the oracle
+    computed (FP64 distances of the points rounded once to FP32): both sides
+    read the same FP32 values, so BUILD steps, every sampled swap's change,
+    the final TD and labels agree up to the order of FP64 sums, and no
+    sampled swap improves at convergence."""
+    X = datagen.workload_gmm32_zipf()
+    n, k = X.shape[0], 500
+    _say("zipf32 f32 matrix fastpam2", n, k)
+    D = _oracle_f32_matrix(X)
+    src = dict(X=X, metric=oracle.L2F32)
+    _say("zipf32 f32 matrix: built")
+    rb = px().fit(D, k, input_kind=px().PAMX_INPUT_D, max_iter=0)
+    bm = rb.medoids.cpu().numpy()
+    assert len(set(bm.tolist())) == k
+    assert rb.td == pytest.approx(oracle.td(bm, **src)[0], rel=1e-12)
+    rng = np.random.default_rng(23)
+    for t in (0, 1, 250, k - 1):
+        _check_build_step(bm, t, _non_medoid_sample(rng, n, bm[:t], 512), **src)
+    r = px().fit(D, k, input_kind=px().PAMX_INPUT_D, variant="fastpam2", trace=True)
+    assert r.rc == 0 and r.stats["swaps"] == len(r.trace) >= 1
+    assert r.stats["td_build"] == rb.td
+    meds = _medoid_sets(bm, r.trace)
+    m = len(r.trace)
+    check = sorted((set(range(4)) | set(range(m - 4, m)) |
+                    set(rng.choice(m, size=min(6, m), replace=False).tolist())) & set(range(m)))
+    for j in check:
+        slot, cand, dl = r.trace[j]
+        tol = _swap_tol(meds[j], n, **src)
+        want = oracle.swap_list(meds[j], [cand], **src)[0, slot]
+        assert dl < 0 and abs(dl - want) <= tol, (j, dl, want, tol)
+    final = r.medoids.cpu().numpy()
+    assert np.array_equal(final, meds[-1])
+    td_ref, lab_ref = oracle.td(final, **src)
+    assert r.td == pytest.approx(td_ref, rel=1e-12)
+    assert np.array_equal(r.labels.cpu().numpy(), lab_ref)
+    ftol = _swap_tol(final, n, **src)
+    assert abs(rb.td + sum(d for _, _, d in r.trace) - r.td) <= (m + 2) * ftol
+    # local optimum: no sampled swap lowers TD beyond the summation bound
+    tab = oracle.swap_list(final, _non_medoid_sample(rng, n, final, 2048), **src)
+    assert np.nanmin(tab) >= -ftol, (np.nanmin(tab), ftol)
+    print("TD", r.td, "swaps", m, "searches", r.stats["iterations"], "min change", np.nanmin(tab),
+          flush=True)
+
+
 def test_zipf32_float_fastpam2_full():
     """The FP32 Euclidean workload with its 40 GB matrix: sampled rows within
     the Gram rounding bound; TD within the summed per-object bound."""
@@ -252,13 +331,17 @@ def test_zipf32_float_fastpam2_full():
     rows = rng.choice(n, size=48, replace=False)
     Dg = px().dist(Xt)
     g = Dg[torch.from_numpy(rows).to(DEV)].cpu().numpy().astype(np.float64)
-    del Dg
-    torch.cuda.empty_cache()
     e = oracle.dist_rows(X, rows)
     bound = 2.0 * (dim + 4) * U24 * (nrm[rows, None] + nrm[None, :]) ** 2
     assert (np.abs(g * g - e * e) <= bound).all()
-    r = px().fit(Xt, k, variant="fastpam2")
+    r = px().fit(Xt, k, variant="fastpam2", trace=True)
     assert r.rc == 0
+    # fitting the points (as the benchmark does) = fitting the GPU's own matrix
+    rd = px().fit(Dg, k, input_kind=px().PAMX_INPUT_D, variant="fastpam2", trace=True)
+    assert torch.equal(r.medoids, rd.medoids) and torch.equal(r.labels, rd.labels)
+    assert r.td == rd.td and r.trace == rd.trace
+    del Dg, rd
+    torch.cuda.empty_cache()
     final = r.medoids.cpu().numpy()
     _, dn, _ = oracle.nearest(final, X=X)
     # |min_i d~_i - min_i d_i| <= max_i |d~_i - d_i|, and every d_i >= dn
@@ -271,19 +354,24 @@ def test_zipf32_float_fastpam2_full():
 
 
 # ============================================================ n = 50000, BF16 recompute
-def test_gmm64_bf16_full():
+@pytest.mark.parametrize("accum", ["f64", "f32"])
+def test_gmm64_bf16_full(accum):
+    """BF16 Gram distances with FP64 sums, or FP32 sums (the mixed-precision
+    form as configured: FP32 loss changes, FP64 re-scoring of every candidate
+    whose rigorous FP32 error bound reaches the best)."""
     X = datagen.workload_gmm64()
     n, k = X.shape[0], 200
-    _say("gmm64 bf16", n, X.shape[1], k)
+    _say("gmm64 bf16", accum, n, X.shape[1], k)
+    acc = px().PAMX_ACC_F32 if accum == "f32" else px().PAMX_ACC_F64
     Xt = torch.from_numpy(X).to(DEV)
-    rb = px().fit(Xt, k, dist_mode="bf16", max_iter=0)
+    rb = px().fit(Xt, k, dist_mode="bf16", accum=acc, max_iter=0)
     assert rb.stats["swaps"] == 0
     bm = rb.medoids.cpu().numpy()
     assert rb.td == pytest.approx(oracle.td(bm, X=X)[0], rel=1e-12)
     rng = np.random.default_rng(19)
     for t in (0, 1, 100, k - 1):
         _check_build_step(bm, t, _non_medoid_sample(rng, n, bm[:t], 1024), X=X)
-    r = px().fit(Xt, k, dist_mode="bf16", trace=True)
+    r = px().fit(Xt, k, dist_mode="bf16", accum=acc, trace=True)
     assert r.rc == 0 and r.stats["swaps"] == len(r.trace) >= 1
     assert r.stats["iterations"] == r.stats["swaps"] + 1
     meds = _medoid_sets(bm, r.trace)
