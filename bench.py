@@ -329,10 +329,15 @@ def run_form(which, reps):
         print(json.dumps(out))
         return
     if which == "bf16":
-        out["workload"] = "gmm64: n=50000 d=64, 200 components, k=200, BF16 form (no stored matrix)"
+        out["workload"] = ("gmm64: n=50000 d=64, 200 components, k=200, BF16 form (no stored "
+                           "matrix): FP32 loss-change sums, FP64 re-scoring of near-ties")
         X = torch.from_numpy(datagen.workload_gmm64()).cuda()
-        stats, td, med = fits(X, 200, "fastpam1", reps, 0, dist_mode="bf16")
+        stats, td, med = fits(X, 200, "fastpam1", reps, 0, dist_mode="bf16", accum="f32")
         out["runs"] = [run_summary(st, t) for st, t in zip(stats, td)]
+        # the same form with FP64 sums
+        st64, td64, med64 = fits(X, 200, "fastpam1", 1, 0, dist_mode="bf16")
+        out["fp64_sums"] = dict(run_summary(st64[-1], td64[-1]),
+                                same_medoids=set(med64.tolist()) == set(med.tolist()))
         # the plain FP32 path (stored 10 GB matrix) on the same points
         st32, td32, med32 = fits(X, 200, "fastpam1", 1, 0)
         a, b = set(med.tolist()), set(med32.tolist())
@@ -343,7 +348,7 @@ def run_form(which, reps):
         torch.cuda.empty_cache()
         # at n = 5000 against the FP64 oracle's own result
         Xs = torch.from_numpy(datagen.workload_gmm64(n=5000)).cuda()
-        sts, tds, meds = fits(Xs, 200, "fastpam1", 1, 1, dist_mode="bf16")
+        sts, tds, meds = fits(Xs, 200, "fastpam1", 1, 1, dist_mode="bf16", accum="f32")
         out["n5000_vs_fp64_oracle"] = dict(fp64_agreement("gmm64_n5000", "pam", meds.tolist(),
                                                           tds[-1]) or {},
                                            swaps=sts[-1]["swaps"], rescored=sts[-1]["rescored"])
@@ -359,14 +364,17 @@ def run_form(which, reps):
     print(json.dumps(out))
 
 
-def fits(X, k, variant, steps, warmup, dist_mode="stored", stream=None, on_step=None):
+def fits(X, k, variant, steps, warmup, dist_mode="stored", stream=None, on_step=None,
+         accum="f64"):
     """`warmup` untimed then `steps` whole fits of the points X (profiling
-    events on); returns (per-fit stats dicts, TDs, medoids of the last fit)."""
+    events on); returns (per-fit stats dicts, TDs, medoids of the last fit).
+    accum: "f64" or "f32" loss-change sums (FP32 only with dist_mode bf16)."""
     import torch
     import paper_2008_05171_amd as px
     from paper_2008_05171_amd import pamx as abi
     n, dim = X.shape
-    opt = px._options(variant=variant, dist_mode=dist_mode)
+    opt = px._options(variant=variant, dist_mode=dist_mode,
+                      accum=px.PAMX_ACC_F32 if accum == "f32" else px.PAMX_ACC_F64)
     opt.profile = 1
     nbytes = abi.pamx_workspace_bytes(n, k, dim, abi.PAMX_INPUT_X, abi.PAMX_F32, opt)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)

@@ -61,7 +61,8 @@ extern "C" {
 #define PAMX_INPUT_X 1 /* n points of `dim` coordinates, row-major */
 
 /* metrics for points */
-#define PAMX_L1 1 /* Manhattan: int32 points give exact int32 distances */
+#define PAMX_L1 1 /* Manhattan: int32 points give exact int32 distances
+                     (coordinate ranges must sum to at most INT32_MAX - 1) */
 #define PAMX_L2 2 /* Euclidean: float32 points */
 
 /* SWAP variants */
@@ -201,9 +202,14 @@ int pamx_workspace_bytes(int64_t n, int32_t k, int32_t dim, int32_t input_kind,
  *          the Gram term on MFMA; pamx_fit computes the same bits).
  *   D      device, n x ld output of the same element type; ld >= n,
  *          a multiple of 4.  Diagonal written as 0, D symmetric bitwise.
- *   ws     device scratch of at least 4*dim bytes for PAMX_F32 (the
- *          coordinate means; PAMX_ERR_WORKSPACE otherwise); unused, may
- *          be NULL, for PAMX_I32. */
+ *   ws     device scratch, 4-byte aligned, of at least 4*dim bytes for
+ *          PAMX_F32 (the coordinate means) or 8*dim bytes for PAMX_I32 (the
+ *          coordinate ranges); PAMX_ERR_WORKSPACE otherwise.
+ * PAMX_I32 points whose per-coordinate ranges (max - min) sum past
+ * INT32_MAX - 1 are refused with PAMX_ERR_ARG before any distance is
+ * formed: such points could have L1 distances outside int32 (INT32_MAX is
+ * the "no medoid" sentinel).  pamx_fit and pamx_fit_batched check their
+ * integer points the same way.  This check waits for the stream. */
 int pamx_dist(const void *X, int32_t dtype, int64_t n, int32_t dim, int32_t metric,
               void *D, int64_t ld, void *ws, size_t ws_bytes, void *stream);
 
@@ -245,9 +251,14 @@ int pamx_swap_noalloc(const void *D, int32_t dtype, int64_t n, int64_t ld, int32
                       const pamx_options *opt, int32_t *medoids, int32_t *labels, double *td,
                       pamx_stats *stats, void *stream);
 
-/* Whole fit: distances (for points), BUILD, SWAP, labels and TD.
+/* Whole fit (Sec. 2: PAM consumes a dissimilarity matrix; Alg. 1 BUILD, then
+ * SWAP as Alg. 3 FastPAM1, the eager FastPAM2 reading of Sec. 3.2, or Alg. 4
+ * FasterPAM; TD by Eq. td): distances (for points), BUILD, SWAP, labels, TD.
  *   XorD  device: n x n matrix (input_kind PAMX_INPUT_D, ld = n) or n x dim
- *         points (PAMX_INPUT_X; the matrix is written into the workspace). */
+ *         points (PAMX_INPUT_X; the matrix is written into the workspace).
+ *   medoids device int32[k] output, slot order; labels device int32[n]
+ *         output (may be NULL); td, stats host outputs (may be NULL).
+ * Errors as for pamx_build and pamx_swap; PAMX_I32 points as for pamx_dist. */
 int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int64_t n, int32_t dim,
              int32_t metric, int32_t k, const pamx_options *opt, int32_t *medoids,
              int32_t *labels, double *td, pamx_stats *stats, void *ws, size_t ws_bytes,
@@ -262,9 +273,10 @@ int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int64_t n, int
  * summation bound).  Draws that do not improve count as failures, a swap
  * resets the count; the search ends after `maxneighbor` failures in a row
  * (the paper uses 2.5% of n - k) -> PAMX_OK, or when the list runs out ->
- * PAMX_WARN_MAXITER.  Restarts ("numlocal") are separate calls.  The device
- * scores a window of draws per pass and applies the first improving one, so
- * the swaps are those of the sequential search (exactly for PAMX_I32).
+ * PAMX_WARN_MAXITER.  Several searches ("numlocal"): pamx_clarans_numlocal.
+ * The device scores a window of draws per pass and applies the first
+ * improving one, so the swaps are those of the sequential search (exactly
+ * for PAMX_I32).
  * labels, td, stats as for pamx_swap (stats: swaps, converged; windows =
  * passes; scan_positions = draws evaluated).  Workspace:
  * pamx_workspace_bytes(n, k, 0, PAMX_INPUT_D, dtype, opt, ...).  A draw
@@ -273,6 +285,41 @@ int pamx_clarans(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
                  const int32_t *draws, int64_t len, int64_t maxneighbor,
                  const pamx_options *opt, int32_t *medoids, int32_t *labels, double *td,
                  pamx_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- Best of several local searches.  Each search runs from its own
+ * start, one after another on `stream`; the local optimum of smallest TD is
+ * kept (the lowest search index on ties) and written to medoids (DEVICE
+ * int32[k], slot order) and labels (DEVICE int32[n], may be NULL).  td:
+ * host, the kept TD.  stats: the kept search's (ms_total covers the call).
+ * each_td: host double[R] (may be NULL), every search's TD.  best: host
+ * int32 (may be NULL), the kept search.  Every start must hold k distinct
+ * indices in [0, n), else PAMX_ERR_INVALID_MEDOIDS.  Returns the kept
+ * search's code (PAMX_OK or PAMX_WARN_MAXITER) or the first error.
+ * Workspace (256-byte aligned): pamx_best_of_workspace_bytes, the SWAP
+ * workspace plus the current search's medoids and labels. */
+int pamx_best_of_workspace_bytes(int64_t n, int32_t k, int32_t dtype, const pamx_options *opt,
+                                 size_t *bytes);
+
+/* Restarts (Sec. 3.3: cheap starts -- uniform random, distance-weighted or
+ * LAB -- each followed by SWAP; the paper finds random starts with FasterPAM
+ * fastest at equal quality, Sec. 4.3, Tab. 1): R SWAP runs (opt->variant:
+ * FastPAM1, eager FastPAM2 or FasterPAM) from starts (DEVICE int32[R*k],
+ * start r at r*k), each exactly as pamx_swap from that start. */
+int pamx_swap_restarts(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                       int32_t restarts, const int32_t *starts, const pamx_options *opt,
+                       int32_t *medoids, int32_t *labels, double *td, pamx_stats *stats,
+                       double *each_td, int32_t *best, void *ws, size_t ws_bytes, void *stream);
+
+/* FastCLARANS with numlocal searches (Sec. 3.4; Sec. 2.1 for CLARANS's
+ * numlocal): search r starts from starts[r*k .. r*k+k) (DEVICE int32) and
+ * takes draws[r*len .. r*len+len) (DEVICE int32), each exactly as
+ * pamx_clarans with those arguments.  opt->trace_cap must be 0. */
+int pamx_clarans_numlocal(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                          int32_t numlocal, const int32_t *starts, const int32_t *draws,
+                          int64_t len, int64_t maxneighbor, const pamx_options *opt,
+                          int32_t *medoids, int32_t *labels, double *td, pamx_stats *stats,
+                          double *each_td, int32_t *best, void *ws, size_t ws_bytes,
+                          void *stream);
 
 /* ---- Bichromatic medoids (facility location, Sec. 5): consumers and
  * possible locations are separate sets.  D: DEVICE n_cons x n_loc matrix

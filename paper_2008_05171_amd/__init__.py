@@ -231,12 +231,14 @@ def clarans_maxneighbor(n, k):
     return max(1, int(round(0.025 * (n - k))))
 
 
-def clarans(D, k, *, numlocal=2, seed=0, maxneighbor=None, draws_per_search=None, trace=False,
+def clarans(D, k, *, numlocal=2, seed=0, maxneighbor=None, draws_per_search=None,
             stream=None) -> FitResult:
     """FastCLARANS (Sec. 3.4) on a stored matrix: `numlocal` local searches,
     each from k uniform random medoids over its own list of random draws
-    (seeded), keeping the smallest TD (the first on ties).  stats gain
-    "searches": [(td, swaps, draws evaluated, rc)]."""
+    (seeded), keeping the smallest TD (the first search on ties), in one
+    library call (pamx_clarans_numlocal).  stats gain "search_td" (every
+    search's TD), "best" (the search kept), "starts" [numlocal, k], "draws"
+    [numlocal, len] and "maxneighbor"."""
     import numpy as np
     import torch
     from . import datagen
@@ -244,29 +246,66 @@ def clarans(D, k, *, numlocal=2, seed=0, maxneighbor=None, draws_per_search=None
     if maxneighbor is None:
         maxneighbor = clarans_maxneighbor(n, k)
     length = draws_per_search or (64 * maxneighbor + 4 * n)
+    starts = np.stack([datagen.random_subset(n, k, seed * 1000 + 2 * r) for r in range(numlocal)])
+    draws = np.stack([datagen.int_points(length, 1, 0, n, seed=seed * 1000 + 2 * r + 1).reshape(-1)
+                      for r in range(numlocal)])
     opt = _options()
-    cap = 4 * n + 16 if trace else 0
-    nbytes = _abi.pamx_workspace_bytes(n, k, 0, PAMX_INPUT_D, _abi._dtype_code(D), opt)
-    ws = _workspace(nbytes, D.device)
-    best, runs = None, []
-    for r in range(numlocal):
-        start = datagen.random_subset(n, k, seed * 1000 + 2 * r)
-        dr = datagen.int_points(length, 1, 0, n, seed=seed * 1000 + 2 * r + 1).reshape(-1)
-        tbuf = torch.empty(cap * 16, dtype=torch.uint8, device=D.device) if trace else None
-        o = _options(trace_buf=tbuf, trace_cap=cap)
-        med = torch.from_numpy(start).to(D.device)
-        lab = torch.empty(n, dtype=torch.int32, device=D.device)
-        rc, td, st = _abi.pamx_clarans(D, k, torch.from_numpy(dr).to(D.device), maxneighbor, med,
-                                       ws, labels=lab, opt=o, stream=stream)
-        res = FitResult(med, lab, td, rc, _stats_dict(st), _trace_list(tbuf, min(st.swaps, cap)))
-        res.stats["start"] = start
-        res.stats["draws"] = dr
-        runs.append((td, st.swaps, st.scan_positions, rc))
-        if best is None or td < best.td:
-            best = res
-    best.stats["searches"] = runs
-    best.stats["maxneighbor"] = maxneighbor
-    return best
+    ws = _workspace(_abi.pamx_best_of_workspace_bytes(n, k, _abi._dtype_code(D), opt), D.device)
+    med = torch.empty(k, dtype=torch.int32, device=D.device)
+    lab = torch.empty(n, dtype=torch.int32, device=D.device)
+    rc, td, st, each, best = _abi.pamx_clarans_numlocal(
+        D, k, torch.from_numpy(starts.astype(np.int32)).to(D.device),
+        torch.from_numpy(draws.astype(np.int32)).to(D.device), maxneighbor, med, ws, labels=lab,
+        opt=opt, stream=stream)
+    res = FitResult(med, lab, td, rc, _stats_dict(st), [])
+    res.stats.update(search_td=each, best=best, starts=starts, draws=draws, maxneighbor=maxneighbor)
+    return res
+
+
+def restart_starts(D, k, restarts, init="random", seed=0):
+    """Starts for `restarts` local searches (Sec. 3.3): uniform random medoid
+    sets, distance-weighted seeds or LAB, each from its own seed; host int32
+    array [restarts, k]."""
+    import numpy as np
+    from . import datagen
+    n = D.shape[0]
+    out = []
+    for r in range(restarts):
+        sr = seed * 1000 + r
+        if init == "random":
+            out.append(datagen.random_subset(n, k, sr))
+        elif init == "dw":
+            out.append(init_dw(D, k, seed=sr).cpu().numpy())
+        elif init == "lab":
+            out.append(init_lab(D, k, seed=sr).cpu().numpy())
+        else:
+            raise ValueError("init must be random, dw or lab")
+    return np.stack(out).astype(np.int32)
+
+
+def fit_restarts(D, k, *, restarts=4, init="random", variant="fasterpam", seed=0, starts=None,
+                 max_iter=10000, stream=None) -> FitResult:
+    """Several cheap starts then SWAP (Sec. 3.3; the paper finds random starts
+    with FasterPAM fastest at equal quality, Sec. 4.3), keeping the smallest
+    TD (the first restart on ties), in one library call (pamx_swap_restarts)
+    on a stored matrix D.  `starts` (host or device int32 [R, k]) overrides
+    init/restarts/seed.  stats gain "restart_td", "best" and "starts"."""
+    import numpy as np
+    import torch
+    n = D.shape[0]
+    if starts is None:
+        starts = restart_starts(D, k, restarts, init, seed)
+    st_d = torch.as_tensor(np.asarray(starts) if not torch.is_tensor(starts) else starts,
+                           dtype=torch.int32).to(D.device).contiguous()
+    opt = _options(variant=variant, max_iter=max_iter)
+    ws = _workspace(_abi.pamx_best_of_workspace_bytes(n, k, _abi._dtype_code(D), opt), D.device)
+    med = torch.empty(k, dtype=torch.int32, device=D.device)
+    lab = torch.empty(n, dtype=torch.int32, device=D.device)
+    rc, td, st, each, best = _abi.pamx_swap_restarts(D, k, st_d, med, ws, labels=lab, opt=opt,
+                                                     stream=stream)
+    res = FitResult(med, lab, td, rc, _stats_dict(st), [])
+    res.stats.update(restart_td=each, best=best, starts=st_d.cpu().numpy())
+    return res
 
 
 def fit_rect(D, k, *, medoids=None, max_iter=10000, trace=False, stream=None) -> FitResult:

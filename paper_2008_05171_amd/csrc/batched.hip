@@ -206,7 +206,8 @@ __device__ void b_caches(const BLds<T> &L, int n, int k, int dim) {
             if (d < d1) { d2 = d1; d1 = d; j1 = j; }
             else if (d < d2) { d2 = d; }
         }
-        L.near[o] = j1; L.dn[o] = d1; L.ds[o] = d2;
+        L.near[o] = (j1 == INT_MAX) ? 0 : j1;   // NaN distances only: keep the slot in range
+        L.dn[o] = d1; L.ds[o] = d2;
     }
 }
 
@@ -259,6 +260,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
         // (srow: object, sdn: old dn, sds: new dn; free until SWAP).
         A acand[kBR];
         int nchg = 0, rows = 0;
+        bool failed = false;   // uniform: no candidate had a finite BUILD sum
         for (int step = 0; step < k; ++step) {
             A bv = VT<T>::acc_inf();
             int bc = INT_MAX, zero = 0;
@@ -300,6 +302,14 @@ __global__ __launch_bounds__(kBT) void k_clara(
             }
             wg_argmin3<A>(bv, zero, bc, rv, ri, rc);
             if (!team_argmin3<T>(bv, zero, bc, tsize, mem, j, gen, bar, xch, err, rv, ri, rc)) return;
+            // Every sum compared false: NaN distances (non-finite coordinates).
+            // bc is work-group (and team) uniform, so the whole instance stops
+            // here; its medoids are reported as -1 and the call fails.
+            if (bc == INT_MAX) {
+                if (tid == 0) atomicOr(err, 8);
+                failed = true;
+                break;
+            }
             const int m = bc;
             if (tid == 0) { L.med[step] = m; L.is_med[m] = 1; }
             T b[MD];
@@ -342,7 +352,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
 
         // ---- FastPAM1 SWAP (Alg. 3)
         int iters = 0, swaps = 0;
-        if (k >= 2 && k < n) {
+        if (!failed && k >= 2 && k < n) {
             b_caches<T, MD, FULL>(L, n, k, dim);
             __syncthreads();
             while (iters < max_iter) {
@@ -464,8 +474,9 @@ __global__ __launch_bounds__(kBT) void k_clara(
             }
         }
         // ---- results: global medoid indices, TD of the sample (fresh sum)
-        if (k >= 2 && k < n) {
-            // caches are current after the last swap
+        if (failed || (k >= 2 && k < n)) {
+            // caches are current after the last swap (a failed instance
+            // reports no medoids)
         } else {
             b_caches<T, MD, FULL>(L, n, k, dim);
         }
@@ -474,7 +485,7 @@ __global__ __launch_bounds__(kBT) void k_clara(
         for (int o = tid; o < n; o += kBT) td += (A)L.dn[o];
         td = wg_sum<A>(td, rv);
         if (mem == 0) {   // one member writes the instance's results
-            for (int s = tid; s < k; s += kBT) med_out[moff[j] + s] = sidx[base + L.med[s]];
+            for (int s = tid; s < k; s += kBT) med_out[moff[j] + s] = failed ? -1 : sidx[base + L.med[s]];
         }
         if (tid == 0 && mem == 0) {
             td_out[j] = (double)td;

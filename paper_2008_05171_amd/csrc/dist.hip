@@ -51,6 +51,45 @@ hipError_t launch_dist_l1_i32(const int32_t *X, int64_t n, int32_t dim, int32_t 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- L1 range
+// Per-coordinate minimum and maximum of integer points.  No L1 distance
+// exceeds the sum over coordinates of (max - min); the host compares that
+// sum with the int32 range of the stored distances before any distance is
+// formed.  mm[2j] / mm[2j+1] receive the minimum / maximum of coordinate j.
+constexpr int kRangePts = 4096;   // points per work-group
+__global__ __launch_bounds__(256) void k_range_init(int32_t *__restrict__ mm, int32_t dim) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < 2 * dim) mm[t] = (t & 1) ? INT_MIN : INT_MAX;
+}
+__global__ __launch_bounds__(256) void k_range_i32(const int32_t *__restrict__ X, int64_t n,
+                                                   int32_t dim, int32_t *__restrict__ mm) {
+    const int64_t o0 = (int64_t)blockIdx.x * kRangePts;
+    const int64_t o1 = min(o0 + (int64_t)kRangePts, n);
+    for (int j = blockIdx.y; j < dim; j += gridDim.y) {
+        int lo = INT_MAX, hi = INT_MIN;
+        for (int64_t o = o0 + threadIdx.x; o < o1; o += 256) {
+            const int32_t v = X[o * dim + j];
+            lo = min(lo, v);
+            hi = max(hi, v);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = min(lo, __shfl_xor(lo, off));
+            hi = max(hi, __shfl_xor(hi, off));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicMin(&mm[2 * j], lo);
+            atomicMax(&mm[2 * j + 1], hi);
+        }
+    }
+}
+
+hipError_t launch_range_i32(const int32_t *X, int64_t n, int32_t dim, int32_t *mm, hipStream_t s) {
+    hipLaunchKernelGGL(k_range_init, dim3((unsigned)((2 * dim + 255) / 256)), dim3(256), 0, s, mm, dim);
+    dim3 grid((unsigned)((n + kRangePts - 1) / kRangePts), (unsigned)(dim < 1024 ? dim : 1024));
+    hipLaunchKernelGGL(k_range_i32, grid, dim3(256), 0, s, X, n, dim, mm);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- centring
 // Subtracting the mean does not change Euclidean distances but shrinks |x|^2,
 // which bounds the cancellation error of the Gram form.  The mean of each

@@ -127,7 +127,7 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     }
     if (input_kind == PAMX_INPUT_X) {
         L->D = take((size_t)n * (size_t)L->ld_fit * 4);
-        if (dtype == PAMX_F32) L->mean = take((size_t)dim * 4);
+        L->mean = take((size_t)dim * (dtype == PAMX_F32 ? 4 : 8));   // means / ranges
     }
     L->near = take((size_t)n * 4);
     L->sec = take((size_t)n * 4);
@@ -393,14 +393,38 @@ extern "C" int pamx_workspace_bytes(int64_t n, int32_t k, int32_t dim, int32_t i
 }
 
 // ---------------------------------------------------------------- distances
+// Integer points: every L1 distance must be an int32 below INT32_MAX (the
+// "no medoid" sentinel), and no distance exceeds the sum over coordinates of
+// (max - min).  mm is device scratch of 2 * dim int32; the host waits for the
+// per-coordinate ranges and refuses points whose sum exceeds INT32_MAX - 1.
+static int check_l1_range(const int32_t *X, int64_t n, int32_t dim, int32_t *mm, hipStream_t s) {
+    HIP_TRY(launch_range_i32(X, n, dim, mm, s));
+    std::vector<int32_t> h((size_t)2 * dim);
+    HIP_TRY(hipMemcpyAsync(h.data(), mm, h.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int64_t span = 0;
+    for (int32_t j = 0; j < dim; ++j) {
+        span += (int64_t)h[2 * j + 1] - (int64_t)h[2 * j];
+        if (span > (int64_t)INT32_MAX - 1)
+            return fail(PAMX_ERR_ARG, "int32 points: the coordinate ranges sum past INT32_MAX - 1 "
+                                      "(an L1 distance could overflow int32)");
+    }
+    return PAMX_OK;
+}
+
+// scratch: 4 * dim bytes for float32 points (coordinate means), 8 * dim for
+// int32 points (coordinate ranges)
 static int dist_impl(const void *X, int32_t dtype, int64_t n, int32_t dim, int32_t metric, void *D,
-                     int64_t ld, float *mean, hipStream_t s) {
-    if (dtype == PAMX_I32 && metric == PAMX_L1)
+                     int64_t ld, void *scratch, hipStream_t s) {
+    if (dtype == PAMX_I32 && metric == PAMX_L1) {
+        const int rc = check_l1_range(static_cast<const int32_t *>(X), n, dim,
+                                      static_cast<int32_t *>(scratch), s);
+        if (rc) return rc;
         HIP_TRY(launch_dist_l1_i32(static_cast<const int32_t *>(X), n, dim, static_cast<int32_t *>(D),
                                    ld, s));
-    else
+    } else
         HIP_TRY(launch_dist_l2_f32(static_cast<const float *>(X), n, dim, static_cast<float *>(D), ld,
-                                   mean, s));
+                                   static_cast<float *>(scratch), s));
     return PAMX_OK;
 }
 
@@ -424,11 +448,14 @@ extern "C" int pamx_dist(const void *X, int32_t dtype, int64_t n, int32_t dim, i
     rc = check_matrix(D, n, ld);
     if (rc) return rc;
     if (ld % 4) return fail(PAMX_ERR_ARG, "ld must be a multiple of 4");
-    if (dtype == PAMX_F32 && (!ws || ws_bytes < (size_t)dim * 4))
-        return fail(PAMX_ERR_WORKSPACE, "float32 points need a workspace of %zu bytes (got %zu)",
-                    (size_t)dim * 4, ws ? ws_bytes : (size_t)0);
+    const size_t need = (size_t)dim * (dtype == PAMX_F32 ? 4 : 8);
+    if (!ws || ws_bytes < need)
+        return fail(PAMX_ERR_WORKSPACE, "the points need a workspace of %zu bytes (got %zu)", need,
+                    ws ? ws_bytes : (size_t)0);
+    if ((reinterpret_cast<uintptr_t>(ws) & 3) != 0)
+        return fail(PAMX_ERR_WORKSPACE, "workspace must be 4-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    rc = dist_impl(X, dtype, n, dim, metric, D, ld, static_cast<float *>(ws), s);
+    rc = dist_impl(X, dtype, n, dim, metric, D, ld, ws, s);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(s));
     return PAMX_OK;
@@ -586,16 +613,20 @@ static hipStream_t graph_stream() {
 // the workspace (and the layout in it), the medoid and trace arrays.  Graphs
 // are kept per host thread for the last few argument sets, so repeated calls
 // on the same buffers replay without capturing again.
+// Everything a captured search depends on: the arguments, and the layout's
+// counts and offsets (a rectangular matrix moves every region behind its
+// transpose, and the candidate count sets the grids).
 struct SearchKey {
     int dev;
     const void *D, *ws, *med, *trace;
-    int64_t ld, n;
-    int32_t k, dtype, variant, chunk, vec, trace_cap, fw;
-    bool operator==(const SearchKey &o) const {
-        return std::tie(dev, D, ws, med, trace, ld, n, k, dtype, variant, chunk, vec, trace_cap, fw) ==
-               std::tie(o.dev, o.D, o.ws, o.med, o.trace, o.ld, o.n, o.k, o.dtype, o.variant, o.chunk,
-                        o.vec, o.trace_cap, o.fw);
+    int64_t ld, n, nc, ldt;
+    int32_t k, dtype, variant, chunk, vec, trace_cap, fw, eg, sbS;
+    size_t DT, head, total;
+    auto tie() const {
+        return std::tie(dev, D, ws, med, trace, ld, n, nc, ldt, k, dtype, variant, chunk, vec,
+                        trace_cap, fw, eg, sbS, DT, head, total);
     }
+    bool operator==(const SearchKey &o) const { return tie() == o.tie(); }
 };
 
 struct SearchGraph {
@@ -625,8 +656,9 @@ static int search_graph(const T *D, int64_t ld, const Layout &L, int32_t *medoid
     auto &cache = *cache_p;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    const SearchKey key{dev, D, ws, medoids, opt.trace, ld, L.n, L.k, L.dtype, opt.variant,
-                        L.L, L.vec, opt.trace_cap, L.fw};
+    const SearchKey key{dev,      D,      ws,      medoids, opt.trace, ld,   L.n,
+                        L.nc,     L.ldt,  L.k,     L.dtype, opt.variant, L.L, L.vec,
+                        opt.trace_cap, L.fw, L.eg, L.sbS, L.DT, L.head, L.total};
     for (auto &g : cache)
         if (g->key == key) { *out = g.get(); return PAMX_OK; }
     std::unique_ptr<SearchGraph> g(new SearchGraph);
@@ -1128,6 +1160,152 @@ extern "C" int pamx_clarans(const void *D, int32_t dtype, int64_t n, int64_t ld,
     return rc;
 }
 
+// ---------------------------------------------------------------- best of several searches
+// Restarts (Sec. 3.3: cheap starts, then SWAP, several times) and FastCLARANS's
+// numlocal searches (Sec. 3.4) keep the local optimum of smallest TD.  The
+// searches run one after another on the caller's stream, each in the SWAP
+// workspace; behind it sit the working medoids (k int32) and labels (n int32)
+// of the current search.  The result of the smallest TD is copied out, the
+// lowest search index on ties.
+static size_t best_of_bytes(const Layout &L, const pamx_options *opt) {
+    return up256(layout_need(L, opt)) + up256((size_t)L.k * 4) + up256((size_t)L.n * 4);
+}
+
+extern "C" int pamx_best_of_workspace_bytes(int64_t n, int32_t k, int32_t dtype,
+                                            const pamx_options *opt, size_t *bytes) {
+    if (!bytes) return fail(PAMX_ERR_ARG, "bytes is NULL");
+    int rc = check_common(n, k, dtype, opt);
+    if (rc) return rc;
+    size_t need = 0;
+    for (int64_t ld : {(n + 3) & ~int64_t(3), (n % 4) ? n : n + 1}) {
+        Layout L;
+        make_layout(n, k, 0, PAMX_INPUT_D, dtype, ld, opt, &L, nullptr);
+        need = std::max(need, best_of_bytes(L, opt));
+    }
+    *bytes = need;
+    return PAMX_OK;
+}
+
+// search(r, medoids_work, labels_work, &td, &stats) runs search r in place
+template <typename F>
+static int best_of(const Layout &L, int32_t R, const int32_t *starts, const pamx_options &opt,
+                   int32_t *medoids, int32_t *labels, double *td, pamx_stats *stats,
+                   double *each_td, int32_t *best, void *ws, size_t ws_bytes, hipStream_t s,
+                   F &&search) {
+    const int32_t k = L.k;
+    if (!ws) return fail(PAMX_ERR_WORKSPACE, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return fail(PAMX_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    const size_t need = best_of_bytes(L, &opt);
+    if (ws_bytes < need)
+        return fail(PAMX_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    char *w = static_cast<char *>(ws);
+    int32_t *wmed = reinterpret_cast<int32_t *>(w + up256(layout_need(L, &opt)));
+    int32_t *wlab = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(wmed) + up256((size_t)k * 4));
+    double best_td = 0.0;
+    int32_t best_r = -1, best_rc = PAMX_OK;
+    pamx_stats best_st;
+    std::memset(&best_st, 0, sizeof(best_st));
+    Timer tm;
+    tm.rec(0, s);
+    for (int32_t r = 0; r < R; ++r) {
+        HIP_TRY(hipMemcpyAsync(wmed, starts + (size_t)r * k, (size_t)k * 4, hipMemcpyDeviceToDevice, s));
+        double tdr = 0.0;
+        pamx_stats st;
+        std::memset(&st, 0, sizeof(st));
+        const int rc = search(r, wmed, labels ? wlab : nullptr, &tdr, &st);
+        if (rc < 0) return rc;
+        if (each_td) each_td[r] = tdr;
+        if (best_r < 0 || tdr < best_td) {
+            best_td = tdr;
+            best_r = r;
+            best_rc = rc;
+            best_st = st;
+            HIP_TRY(hipMemcpyAsync(medoids, wmed, (size_t)k * 4, hipMemcpyDeviceToDevice, s));
+            if (labels)
+                HIP_TRY(hipMemcpyAsync(labels, wlab, (size_t)L.n * 4, hipMemcpyDeviceToDevice, s));
+        }
+    }
+    tm.rec(4, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(PAMX_ERR_HIP, "stream synchronize failed");
+    if (td) *td = best_td;
+    if (best) *best = best_r;
+    if (stats) {
+        *stats = best_st;
+        stats->ms_total = tm.ms(0, 4);
+    }
+    return best_rc;
+}
+
+extern "C" int pamx_swap_restarts(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                                  int32_t restarts, const int32_t *starts,
+                                  const pamx_options *opt_in, int32_t *medoids, int32_t *labels,
+                                  double *td, pamx_stats *stats, double *restart_td,
+                                  int32_t *best, void *ws, size_t ws_bytes, void *stream) {
+    pamx_options opt;
+    pamx_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    int rc = swap_args(D, dtype, n, ld, k, &opt, medoids);
+    if (rc) return rc;
+    if (restarts < 1) return fail(PAMX_ERR_ARG, "restarts must be >= 1");
+    if (!starts) return fail(PAMX_ERR_ARG, "starts is NULL");
+    Layout L;
+    make_layout(n, k, 0, PAMX_INPUT_D, dtype, ld, &opt, &L, D);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto one = [&](int32_t, int32_t *wmed, int32_t *wlab, double *tdr, pamx_stats *st) {
+        Timer t;
+        t.rec(0, s);
+        const int r = dtype == PAMX_F32
+                          ? swap_impl<float>(static_cast<const float *>(D), ld, L, k, opt, wmed, wlab,
+                                             tdr, st, ws, s, t)
+                          : swap_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, opt, wmed,
+                                               wlab, tdr, st, ws, s, t);
+        st->ms_swap = t.ms(2, 3);
+        return r;
+    };
+    return best_of(L, restarts, starts, opt, medoids, labels, td, stats, restart_td, best, ws,
+                   ws_bytes, s, one);
+}
+
+extern "C" int pamx_clarans_numlocal(const void *D, int32_t dtype, int64_t n, int64_t ld, int32_t k,
+                                     int32_t numlocal, const int32_t *starts, const int32_t *draws,
+                                     int64_t len, int64_t maxneighbor, const pamx_options *opt_in,
+                                     int32_t *medoids, int32_t *labels, double *td,
+                                     pamx_stats *stats, double *search_td, int32_t *best, void *ws,
+                                     size_t ws_bytes, void *stream) {
+    pamx_options opt;
+    pamx_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    int rc = swap_args(D, dtype, n, ld, k, &opt, medoids);
+    if (rc) return rc;
+    if (numlocal < 1) return fail(PAMX_ERR_ARG, "numlocal must be >= 1");
+    if (!starts) return fail(PAMX_ERR_ARG, "starts is NULL");
+    if (len < 0) return fail(PAMX_ERR_ARG, "len must be >= 0");
+    if (len > 0 && !draws) return fail(PAMX_ERR_ARG, "draws is NULL");
+    if (maxneighbor < 1) return fail(PAMX_ERR_ARG, "maxneighbor must be >= 1");
+    if (opt.variant != PAMX_FASTPAM1)
+        return fail(PAMX_ERR_ARG, "FastCLARANS takes no SWAP variant (leave PAMX_FASTPAM1)");
+    if (opt.trace_cap > 0)
+        return fail(PAMX_ERR_ARG, "no swap trace over several searches (trace_cap must be 0)");
+    Layout L;
+    make_layout(n, k, 0, PAMX_INPUT_D, dtype, ld, &opt, &L, D);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto one = [&](int32_t r, int32_t *wmed, int32_t *wlab, double *tdr, pamx_stats *st) {
+        Timer t;
+        t.rec(0, s);
+        const int32_t *dr = draws ? draws + (size_t)r * len : nullptr;
+        const int c = dtype == PAMX_F32
+                          ? clarans_impl<float>(static_cast<const float *>(D), ld, L, k, dr, len,
+                                                maxneighbor, opt, wmed, wlab, tdr, st, ws, s, t)
+                          : clarans_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, dr, len,
+                                                  maxneighbor, opt, wmed, wlab, tdr, st, ws, s, t);
+        st->ms_swap = t.ms(2, 3);
+        return c;
+    };
+    return best_of(L, numlocal, starts, opt, medoids, labels, td, stats, search_td, best, ws,
+                   ws_bytes, s, one);
+}
+
 // ---------------------------------------------------------------- bichromatic medoids
 static int rect_args(const void *D, int32_t dtype, int64_t nco, int64_t nl, int64_t ld, int32_t k,
                      const pamx_options *opt, const int32_t *medoids) {
@@ -1350,8 +1528,7 @@ extern "C" int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int
         char *w = static_cast<char *>(ws);
         void *Dw = w + L.D;
         ld = L.ld_fit;
-        float *mean = (dtype == PAMX_F32) ? reinterpret_cast<float *>(w + L.mean) : nullptr;
-        rc = dist_impl(XorD, dtype, n, dim, metric, Dw, ld, mean, s);
+        rc = dist_impl(XorD, dtype, n, dim, metric, Dw, ld, w + L.mean, s);
         if (rc) return rc;
         D = Dw;
     }
@@ -1397,7 +1574,7 @@ constexpr int kFullBlocks = 256;   // blocks per instance in the full-data TD
 
 struct BatchLayout {
     size_t soff, kin, moff, tk_inst, tk_mem, tsz, bar, xch, td, tdb, it, sw, rows, ctr, part, tdf,
-        total;
+        range, total;
 };
 
 BatchLayout batch_layout(int32_t n_inst) {
@@ -1420,6 +1597,7 @@ BatchLayout batch_layout(int32_t n_inst) {
     b.ctr = take(2 * 4);
     b.part = take((size_t)n_inst * kFullBlocks * 8);
     b.tdf = take((size_t)n_inst * 8);
+    b.range = take((size_t)2 * kBMaxDim * 4);   // int32 points: coordinate ranges
     b.total = off;
     return b;
 }
@@ -1487,6 +1665,12 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
         return fail(PAMX_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     if (ws_bytes < B.total) return fail(PAMX_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes",
                                         ws_bytes, B.total);
+    if (dtype == PAMX_I32) {   // the pool's ranges bound every sample's distances
+        rc = check_l1_range(static_cast<const int32_t *>(X), N, dim,
+                            reinterpret_cast<int32_t *>(static_cast<char *>(ws) + B.range),
+                            static_cast<hipStream_t>(stream));
+        if (rc) return rc;
+    }
     // Teams: with cooperative launch, an instance whose estimated cost is a
     // multiple of the balanced share (total / resident work-groups) gets that
     // many work-groups (at most kBTeamMax, and at least 256 candidates each),
@@ -1593,6 +1777,8 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
     HIP_TRY(hipMemcpyAsync(rows.data(), a.rows_out, (size_t)n_inst * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (err & 4) return fail(PAMX_ERR_HIP, "a team of the batched kernel did not meet (wait bound reached)");
+    if (err & 8) return fail(PAMX_ERR_ARG, "an instance's BUILD found no finite distance sum "
+                                           "(non-finite point coordinates)");
     if (err) return fail(PAMX_ERR_HIP, "a medoid index outside [0, N) reached the full-data TD");
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));

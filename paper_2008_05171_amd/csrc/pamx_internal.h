@@ -229,6 +229,9 @@ void set_window(Layout *L);
 // launchers (one per kernel family); each returns hipSuccess or an error.
 hipError_t launch_dist_l1_i32(const int32_t *X, int64_t n, int32_t dim, int32_t *D, int64_t ld,
                               hipStream_t s);
+// mm[2*dim] (device scratch) receives the minimum and maximum of every
+// coordinate of the integer points
+hipError_t launch_range_i32(const int32_t *X, int64_t n, int32_t dim, int32_t *mm, hipStream_t s);
 // mean[dim] (device scratch) receives the coordinate means; the distances are
 // those of the centred points
 hipError_t launch_dist_l2_f32(const float *X, int64_t n, int32_t dim, float *D, int64_t ld,

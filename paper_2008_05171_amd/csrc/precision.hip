@@ -754,7 +754,8 @@ __device__ __forceinline__ void rc_scan(const float *__restrict__ X, int dim, in
             } else if (lt2(e1, f1, d2, j2)) { d2 = e1; j2 = f1; }
         }
     }
-    nr = j1; sc = (j2 == INT_MAX) ? -1 : j2; dn = d1; ds = d2;
+    nr = (j1 == INT_MAX) ? 0 : j1;   // NaN distances only: keep the slot in range
+    sc = (j2 == INT_MAX) ? -1 : j2; dn = d1; ds = d2;
 }
 
 __global__ __launch_bounds__(256) void k_rc_cache_init(const float *__restrict__ X, int32_t dim,

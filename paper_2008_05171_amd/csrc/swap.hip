@@ -30,6 +30,18 @@
 
 #include "pamx_internal.h"
 
+#ifndef PAMX_PSTAGE
+#define PAMX_PSTAGE 8
+#endif
+#ifndef PAMX_PASS_WPE
+#define PAMX_PASS_WPE 0
+#endif
+#if PAMX_PASS_WPE > 0
+#define PAMX_PASS_ATTR __attribute__((amdgpu_waves_per_eu(PAMX_PASS_WPE)))
+#else
+#define PAMX_PASS_ATTR
+#endif
+
 namespace pamx {
 
 
@@ -484,7 +496,10 @@ template <typename T>
 __device__ __forceinline__ void store_top2(const Top2<T> &t, int64_t o, int32_t *__restrict__ near,
                                            int32_t *__restrict__ sec, T *__restrict__ dn,
                                            T *__restrict__ ds) {
-    near[o] = t.j1;
+    // j1 is a real slot for every finite or infinite distance; only NaN
+    // entries (a matrix outside the contract) leave it unset, and slot 0
+    // keeps the segment arrays in range then
+    near[o] = (t.j1 == INT_MAX) ? 0 : t.j1;
     sec[o] = (t.j2 == INT_MAX) ? -1 : t.j2;
     dn[o] = t.d1;
     ds[o] = t.d2;
@@ -500,7 +515,7 @@ __global__ __launch_bounds__(256) void k_cache_init(const T *__restrict__ D, int
     if (o >= n) return;
     const Top2<T> t = scan_medoids<T>(D, ld, k, med, o);
     store_top2<T>(t, o, near, sec, dn, ds);
-    if (labels) labels[o] = t.j1;
+    if (labels) labels[o] = (t.j1 == INT_MAX) ? 0 : t.j1;
 }
 
 // Input check: medoids distinct and in range (uses `mark` zeroed beforehand).
@@ -789,12 +804,12 @@ __device__ __forceinline__ void pass_tile(
     // segment.  A store is counted with the loads the wave waits for, so one
     // store per segment close stalled the stream each time (measured 8 %
     // slower at n = 20000).  Waves with inactive lanes store directly.
-    constexpr int kPStage = 8;
-    __shared__ A pst[4 * kPStage * 256];
-    __shared__ int32_t pseg[4 * kPStage];
+    constexpr int kPStage = PAMX_PSTAGE;
+    __shared__ A pst[4 * (kPStage > 0 ? kPStage : 1) * 256];
+    __shared__ int32_t pseg[4 * (kPStage > 0 ? kPStage : 1)];
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
     const int64_t wc0 = cb + ((int64_t)tile * kWG + (threadIdx.x & ~63)) * VEC;   // wave's first column
-    const bool wfull = VEC == 4 && wc0 + 64 * VEC <= ce;
+    const bool wfull = kPStage > 0 && VEC == 4 && wc0 + 64 * VEC <= ce;
     int nst = 0;   // staged segments (wave-uniform)
     auto flush_p = [&]() {
         __builtin_amdgcn_wave_barrier();
@@ -911,7 +926,7 @@ __device__ __forceinline__ void pass_tile(
 }
 
 template <typename T, int VEC, bool P2, bool WIN>
-__global__ __launch_bounds__(kWG) void k_swap_pass(
+__global__ __launch_bounds__(kWG) PAMX_PASS_ATTR void k_swap_pass(
     const T *__restrict__ D, int64_t ld, int64_t n, int64_t nc, int32_t k,
     const int32_t *__restrict__ srow,
     const T *__restrict__ sdn, const T *__restrict__ sds, const int32_t *__restrict__ seg_off,

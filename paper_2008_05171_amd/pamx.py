@@ -66,6 +66,7 @@ EXPORTS = ("pamx_default_options", "pamx_workspace_bytes", "pamx_dist", "pamx_bu
            "pamx_init_workspace_bytes", "pamx_init_dw", "pamx_init_lab", "pamx_clarans",
            "pamx_rect_workspace_bytes", "pamx_fit_rect", "pamx_swap_rect",
            "pamx_check_dissimilarity", "pamx_read_probe", "pamx_swap_noalloc",
+           "pamx_best_of_workspace_bytes", "pamx_swap_restarts", "pamx_clarans_numlocal",
            "pamx_last_error")
 
 
@@ -113,13 +114,19 @@ def load(path: str = LIB_PATH):
                                              ctypes.POINTER(ctypes.c_int64), P, sz, P]
     lib.pamx_read_probe.argtypes = [P, i64, i64, i32, P, i64, P]
     lib.pamx_swap_noalloc.argtypes = [P, i32, i64, i64, i32, opt_p, P, P, dbl_p, st_p, P]
+    lib.pamx_best_of_workspace_bytes.argtypes = [i64, i32, i32, opt_p, ctypes.POINTER(sz)]
+    lib.pamx_swap_restarts.argtypes = [P, i32, i64, i64, i32, i32, P, opt_p, P, P, dbl_p, st_p,
+                                       dbl_p, ctypes.POINTER(i32), P, sz, P]
+    lib.pamx_clarans_numlocal.argtypes = [P, i32, i64, i64, i32, i32, P, P, i64, i64, opt_p, P, P,
+                                          dbl_p, st_p, dbl_p, ctypes.POINTER(i32), P, sz, P]
     lib.pamx_last_error.argtypes = []
     lib.pamx_last_error.restype = ctypes.c_char_p
     for name in ("pamx_workspace_bytes", "pamx_dist", "pamx_build", "pamx_swap", "pamx_fit",
                  "pamx_batched_workspace_bytes", "pamx_fit_batched", "pamx_init_workspace_bytes",
                  "pamx_init_dw", "pamx_init_lab", "pamx_clarans", "pamx_rect_workspace_bytes",
                  "pamx_fit_rect", "pamx_swap_rect", "pamx_check_dissimilarity", "pamx_read_probe",
-                 "pamx_swap_noalloc"):
+                 "pamx_swap_noalloc", "pamx_best_of_workspace_bytes", "pamx_swap_restarts",
+                 "pamx_clarans_numlocal"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -166,12 +173,13 @@ def pamx_workspace_bytes(n, k, dim, input_kind, dtype, opt=None) -> int:
 
 
 def pamx_dist(X, metric, D, ws=None, ld=None, stream=None):
-    """ws: device scratch of >= 4*dim bytes for float32 points (allocated here if None)."""
+    """ws: device scratch of >= 4*dim bytes (float32 points) or 8*dim bytes
+    (int32 points), allocated here if None."""
     import torch
     n, dim = X.shape
     ld = D.stride(0) if ld is None else ld
     if ws is None:
-        ws = torch.empty(max(4 * dim, 256), dtype=torch.uint8, device=X.device)
+        ws = torch.empty(max(8 * dim, 256), dtype=torch.uint8, device=X.device)
     return _check(load().pamx_dist(_ptr(X), _dtype_code(X), n, dim, int(metric), _ptr(D), int(ld),
                                    _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
 
@@ -324,6 +332,55 @@ def pamx_clarans(D, k, draws, maxneighbor, medoids, ws, labels=None, opt=None, n
                                     _ptr(labels), ctypes.byref(td), ctypes.byref(st), _ptr(ws),
                                     ws.numel() * ws.element_size(), _stream(stream)))
     return rc, td.value, st
+
+
+def pamx_best_of_workspace_bytes(n, k, dtype, opt=None) -> int:
+    out = ctypes.c_size_t()
+    _check(load().pamx_best_of_workspace_bytes(int(n), int(k), int(dtype),
+                                               ctypes.byref(opt) if opt is not None else None,
+                                               ctypes.byref(out)))
+    return int(out.value)
+
+
+def pamx_swap_restarts(D, k, starts, medoids, ws, labels=None, opt=None, n=None, ld=None,
+                       stream=None):
+    """starts: device int32 [R, k]; medoids: device int32 [k] output.
+    Returns (rc, td, stats, per-restart TDs, best restart)."""
+    n = D.shape[0] if n is None else n
+    ld = D.stride(0) if ld is None else ld
+    R = starts.shape[0]
+    td = ctypes.c_double()
+    st = pamx_stats()
+    each = (ctypes.c_double * R)()
+    best = ctypes.c_int32()
+    rc = _check(load().pamx_swap_restarts(_ptr(D), _dtype_code(D), int(n), int(ld), int(k), int(R),
+                                          _ptr(starts), ctypes.byref(opt) if opt is not None else None,
+                                          _ptr(medoids), _ptr(labels), ctypes.byref(td),
+                                          ctypes.byref(st), each, ctypes.byref(best), _ptr(ws),
+                                          ws.numel() * ws.element_size(), _stream(stream)))
+    return rc, td.value, st, list(each), best.value
+
+
+def pamx_clarans_numlocal(D, k, starts, draws, maxneighbor, medoids, ws, labels=None, opt=None,
+                          n=None, ld=None, stream=None):
+    """starts: device int32 [numlocal, k]; draws: device int32 [numlocal, len];
+    medoids: device int32 [k] output.  Returns (rc, td, stats, per-search
+    TDs, best search)."""
+    n = D.shape[0] if n is None else n
+    ld = D.stride(0) if ld is None else ld
+    R, length = draws.shape
+    td = ctypes.c_double()
+    st = pamx_stats()
+    each = (ctypes.c_double * R)()
+    best = ctypes.c_int32()
+    rc = _check(load().pamx_clarans_numlocal(_ptr(D), _dtype_code(D), int(n), int(ld), int(k),
+                                             int(R), _ptr(starts), _ptr(draws), int(length),
+                                             int(maxneighbor),
+                                             ctypes.byref(opt) if opt is not None else None,
+                                             _ptr(medoids), _ptr(labels), ctypes.byref(td),
+                                             ctypes.byref(st), each, ctypes.byref(best), _ptr(ws),
+                                             ws.numel() * ws.element_size(), _stream(stream)))
+    return rc, td.value, st, list(each), best.value
 
 
 def pamx_rect_workspace_bytes(n_cons, n_loc, k, dtype, opt=None) -> int:

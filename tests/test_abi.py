@@ -321,3 +321,53 @@ def test_noalloc_host_errors(lib):
     assert call(10, 11) == abi.PAMX_ERR_ARG
     assert lib.pamx_swap_noalloc(None, abi.PAMX_F32, 10, 10, 2, None, fake, None, None, None,
                                  None) == abi.PAMX_ERR_ARG
+
+
+def test_int_points_workspace_rule(lib):
+    """Integer points need 8 bytes per coordinate of scratch (the range check)."""
+    fake = ctypes.c_void_p(0x100000)
+    rc = lib.pamx_dist(fake, abi.PAMX_I32, 10, 2, abi.PAMX_L1, fake, 12, None, 0, None)
+    assert rc == abi.PAMX_ERR_WORKSPACE
+    rc = lib.pamx_dist(fake, abi.PAMX_I32, 10, 2, abi.PAMX_L1, fake, 12, fake, 15, None)
+    assert rc == abi.PAMX_ERR_WORKSPACE
+    a = abi.pamx_workspace_bytes(1000, 5, 8, abi.PAMX_INPUT_X, abi.PAMX_I32)
+    b = abi.pamx_workspace_bytes(1000, 5, 8, abi.PAMX_INPUT_D, abi.PAMX_I32)
+    assert a >= b + 1000 * 1000 * 4 + 64
+
+
+def test_best_of_host_argument_errors(lib):
+    """Restarts and numlocal searches: argument errors come back before any
+    device work (fake device pointers are never touched)."""
+    fake = ctypes.c_void_p(0x100000)
+    ws = ctypes.c_void_p(0x200000)
+    n, k = 300, 5
+    need = abi.pamx_best_of_workspace_bytes(n, k, abi.PAMX_I32)
+    assert need > abi.pamx_workspace_bytes(n, k, 0, abi.PAMX_INPUT_D, abi.PAMX_I32) + n * 4
+    td, st, best = ctypes.c_double(), abi.pamx_stats(), ctypes.c_int32()
+
+    def restarts(R=3, starts=fake, wsb=need, opt=None):
+        return lib.pamx_swap_restarts(fake, abi.PAMX_I32, n, n, k, R, starts, opt, fake, None,
+                                      ctypes.byref(td), ctypes.byref(st), None,
+                                      ctypes.byref(best), ws, wsb, None)
+
+    assert restarts(R=0) == abi.PAMX_ERR_ARG
+    assert restarts(starts=None) == abi.PAMX_ERR_ARG
+    assert restarts(wsb=need - 1) == abi.PAMX_ERR_WORKSPACE
+
+    def numlocal(R=2, starts=fake, draws=fake, length=100, maxn=5, wsb=need, opt=None):
+        return lib.pamx_clarans_numlocal(fake, abi.PAMX_I32, n, n, k, R, starts, draws, length,
+                                         maxn, opt, fake, None, ctypes.byref(td),
+                                         ctypes.byref(st), None, ctypes.byref(best), ws, wsb, None)
+
+    assert numlocal(R=0) == abi.PAMX_ERR_ARG
+    assert numlocal(starts=None) == abi.PAMX_ERR_ARG
+    assert numlocal(draws=None) == abi.PAMX_ERR_ARG
+    assert numlocal(maxn=0) == abi.PAMX_ERR_ARG
+    assert numlocal(wsb=need - 1) == abi.PAMX_ERR_WORKSPACE
+    o = abi.pamx_default_options()
+    o.trace = 0x300000
+    o.trace_cap = 10
+    assert numlocal(opt=ctypes.byref(o)) == abi.PAMX_ERR_ARG
+    o = abi.pamx_default_options()
+    o.variant = abi.PAMX_FASTPAM2
+    assert numlocal(opt=ctypes.byref(o)) == abi.PAMX_ERR_ARG

@@ -155,9 +155,24 @@ def test_batched_largest_instance():
     assert abs(a.td_sample[0] - td_g) <= 1e-6 * td_g
 
 
+def test_batched_nan_point_is_refused():
+    """A sample holding a point with a NaN coordinate: every BUILD sum of the
+    instance is non-finite, the instance stops (uniformly, before any medoid
+    is used as an index) and the call fails; the other instances are
+    unaffected in the same launch."""
+    _say("batched_nan")
+    X = datagen.gaussian_mixture(400, 4, 5, seed=11)
+    X[17, 2] = np.nan
+    off = np.array([0, 60, 120], np.int64)
+    idx = np.concatenate([np.arange(100, 160), np.arange(0, 60)]).astype(np.int32)   # 17 in the 2nd
+    with pytest.raises(px().PamxError):
+        _run(X, off, idx, np.array([3, 4], np.int32))
+
+
 @pytest.mark.skip(reason="an out-of-range sample index hung the GPU twice (once before and once "
-                         "after a first fix); the index check now runs in its own kernel before "
-                         "any instance, but this case stays off the GPU until that is re-tested")
+                         "after a first fix) and the second cause was never established; the "
+                         "in-kernel path that hung is gone (the index check now rejects the call "
+                         "before any instance runs), and this case stays off the GPU")
 def test_batched_bad_index():
     _say("batched_bad_index")
     X = datagen.int_points(100, 2, 0, 50, seed=1)

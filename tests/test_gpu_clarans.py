@@ -156,12 +156,41 @@ def test_float_replayed_on_oracle():
 
 
 def test_numlocal_keeps_the_best_search():
+    """numlocal searches in one library call (pamx_clarans_numlocal) keep the
+    search of smallest TD, the first on ties: every search's TD, the kept
+    index, medoids and labels equal the oracle's searches over the same
+    starts and draws."""
     _say("clarans_numlocal")
     X, D = _int_case(1200, 41, hi=400)
     Di = _t(D.astype(np.int32))
-    r = px().clarans(Di, 10, numlocal=3, seed=5, trace=True)
-    tds = [s[0] for s in r.stats["searches"]]
-    assert r.td == min(tds) and len(tds) == 3
-    ref = oracle.clarans(r.stats["start"], r.stats["draws"], r.stats["maxneighbor"], D=D)
-    assert list(r.medoids.cpu().numpy()) == list(ref.medoids) and r.td == ref.td
-    assert r.trace == ref.trace
+    r = px().clarans(Di, 10, numlocal=4, seed=5)
+    refs = [oracle.clarans(r.stats["starts"][j], r.stats["draws"][j], r.stats["maxneighbor"], D=D)
+            for j in range(4)]
+    tds = [x.td for x in refs]
+    assert r.stats["search_td"] == tds
+    best = int(np.argmin(tds))
+    assert r.stats["best"] == best
+    assert list(r.medoids.cpu().numpy()) == list(refs[best].medoids) and r.td == refs[best].td
+    _, lab = oracle.td(refs[best].medoids, D=D)
+    assert np.array_equal(r.labels.cpu().numpy(), lab)
+    assert r.stats["swaps"] == refs[best].swaps
+
+
+def test_numlocal_tie_keeps_the_first_search():
+    """Two identical searches (same start, same draws): the first is kept."""
+    _say("clarans_numlocal_tie")
+    X, D = _int_case(500, 43, hi=300)
+    Di = _t(D.astype(np.int32))
+    from paper_2008_05171_amd import pamx as abi
+    start = datagen.random_subset(500, 6, 7).astype(np.int32)
+    draws = datagen.int_points(3000, 1, 0, 500, seed=8).reshape(-1)
+    starts = np.stack([start, start, datagen.random_subset(500, 6, 9)]).astype(np.int32)
+    dr = np.stack([draws, draws, draws]).astype(np.int32)
+    ws = torch.empty(abi.pamx_best_of_workspace_bytes(500, 6, abi.PAMX_I32), dtype=torch.uint8,
+                     device=DEV)
+    med = torch.empty(6, dtype=torch.int32, device=DEV)
+    rc, td, st, each, best = abi.pamx_clarans_numlocal(Di, 6, _t(starts), _t(dr), 12, med, ws)
+    refs = [oracle.clarans(starts[j], dr[j], 12, D=D) for j in range(3)]
+    assert each == [x.td for x in refs] and each[0] == each[1]
+    assert best == int(np.argmin(each)) and best != 1
+    assert list(med.cpu().numpy()) == list(refs[best].medoids)

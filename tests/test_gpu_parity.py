@@ -313,3 +313,32 @@ def test_deterministic_rerun():
     b = px().fit(_t(X), 30, variant="fastpam2")
     assert torch.equal(a.medoids, b.medoids) and torch.equal(a.labels, b.labels)
     assert a.td == b.td
+
+
+# ------------------------------------------------------------------ int32 range
+def test_int_points_range_limit():
+    """Integer points whose coordinate ranges sum past INT32_MAX - 1 are
+    refused by the distance call, the fit and the batched fit (an L1
+    distance could leave int32); at exactly INT32_MAX - 1 the distances and
+    the fit are exact (Eq. td with int64 sums)."""
+    _say("int_range_limit")
+    big = np.array([[-2 ** 30, 5], [2 ** 30 - 1, -7], [0, 2 ** 30 - 1], [3, -2 ** 30]], np.int32)
+    Xb = _t(big)
+    with pytest.raises(px().PamxError):
+        px().dist(Xb)
+    with pytest.raises(px().PamxError):
+        px().fit(Xb, 2)
+    off = np.array([0, 4], np.int64)
+    with pytest.raises(px().PamxError):
+        px().fit_batched(Xb, off, _t(np.arange(4, dtype=np.int32)), np.array([2], np.int32))
+    # one coordinate spanning INT32_MAX - 1, the other constant
+    lim = 2 ** 31 - 2
+    X = np.array([[0, 9], [lim, 9], [1, 9], [lim - 1, 9], [lim // 2, 9], [5, 9]], np.int32)
+    D = px().dist(_t(X)).cpu().numpy().astype(np.int64)
+    Dref = oracle.dist_matrix(X, oracle.L1)
+    assert np.array_equal(D.astype(np.float64), Dref)
+    assert D.max() == lim
+    ref = oracle.pam(2, D=Dref)
+    res = px().fit(_t(X), 2)
+    assert list(res.medoids.cpu().numpy()) == list(ref.medoids)
+    assert res.td == ref.td

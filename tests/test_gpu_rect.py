@@ -129,3 +129,37 @@ def test_float_matrix_and_certificate():
         new = np.minimum(other[:, None], D64).sum(0)
         new[med] = np.inf
         assert new.min() - base >= -tol
+
+
+def test_graph_replay_square_and_rect_same_buffers():
+    """Graph-replayed searches (pamx_options.graph) of a square matrix and of
+    a consumers x locations view of the same buffer, alternating, with the
+    same workspace, medoid array, object count, row stride and k: a search
+    captured for one layout is never replayed for the other, and every call
+    equals the oracle (PAM SWAP, Alg. 2; bichromatic reading R17)."""
+    _say("rect_graph_alternate")
+    from paper_2008_05171_amd import pamx as abi
+    n, nl, k = 300, 200, 5
+    X = datagen.int_points(n, 2, 0, 400, seed=61)
+    Dsq = oracle.dist_matrix(X, oracle.L1)
+    Dg = _t(Dsq.astype(np.int32))                 # n x n, row stride n
+    Drect = Dg[:, :nl]                            # the first nl points as locations
+    start_sq = datagen.random_subset(n, k, 62).astype(np.int32)
+    start_rc = datagen.random_subset(nl, k, 63).astype(np.int32)
+    ref_sq = oracle.swap(start_sq, D=Dsq)
+    ref_rc = oracle.rect_swap(start_rc, Dsq[:, :nl])
+    opt = px()._options(graph=True)
+    nb = max(abi.pamx_workspace_bytes(n, k, 0, abi.PAMX_INPUT_D, abi.PAMX_I32, opt),
+             abi.pamx_rect_workspace_bytes(n, nl, k, abi.PAMX_I32, opt))
+    ws = torch.empty(nb, dtype=torch.uint8, device=DEV)
+    med = torch.empty(k, dtype=torch.int32, device=DEV)
+    lab = torch.empty(n, dtype=torch.int32, device=DEV)
+    for rep in range(3):
+        med.copy_(_t(start_sq))
+        rc, td, st = abi.pamx_swap(Dg, k, med, ws, labels=lab, opt=opt)
+        assert rc == 0 and list(med.cpu().numpy()) == list(ref_sq.medoids), ("square", rep)
+        assert td == ref_sq.td and st.swaps == ref_sq.swaps
+        med.copy_(_t(start_rc))
+        rc, td, st = abi.pamx_rect(Drect, k, med, ws, labels=lab, opt=opt, build=False, ld=n)
+        assert rc == 0 and list(med.cpu().numpy()) == list(ref_rc.medoids), ("rect", rep)
+        assert td == ref_rc.td and st.swaps == ref_rc.swaps

@@ -1,0 +1,132 @@
+"""GPU parity of restarts (Sec. 3.3: cheap starts, each followed by SWAP,
+keeping the smallest TD; Sec. 4.3 finds random starts with FasterPAM fastest
+at equal quality) in one library call, pamx_swap_restarts.
+
+The starts are computed on the host (uniform random subsets, and the
+oracle's distance-weighted and LAB seeds from the same uniforms and
+subsamples), so no expected value comes from the GPU.  On integer matrices
+every restart's TD, the kept restart (the first on ties), its medoids and
+labels equal the oracle's SWAP (PAM, the FastPAM2 reading or FasterPAM) from
+each start; on an FP32 matrix the kept medoids equal the oracle's and the TD
+agrees to the FP64 summation bound.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_05171_amd import datagen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+ORC = {"fastpam1": oracle.PAM, "fastpam2": oracle.FASTPAM2, "fasterpam": oracle.FASTERPAM}
+
+
+def px():
+    import paper_2008_05171_amd as m
+    return m
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _starts(D, k, R, init, seed):
+    n = D.shape[0]
+    out = []
+    for r in range(R):
+        sr = seed * 1000 + r
+        if init == "random":
+            out.append(datagen.random_subset(n, k, sr))
+        elif init == "dw":
+            out.append(oracle.init_dw(k, datagen.uniforms(k, sr), D=D))
+        else:
+            m = px().lab_sample_size(n)
+            out.append(oracle.init_lab(k, datagen.subsamples(n, k, m, sr), D=D))
+    return np.stack(out).astype(np.int32)
+
+
+def _oracle_best(D, starts, variant):
+    runs = [oracle.swap(s, D=D, variant=ORC[variant]) for s in starts]
+    tds = [r.td for r in runs]
+    return runs, tds, int(np.argmin(tds))
+
+
+@pytest.mark.parametrize("variant", ["fastpam1", "fastpam2", "fasterpam"])
+@pytest.mark.parametrize("init", ["random", "dw", "lab"])
+def test_int_restarts_bitexact(variant, init):
+    _say("restarts_int", variant, init)
+    n, k, R = 900, 9, 5
+    X = datagen.int_points(n, 2, 0, 300, seed=71)
+    D = oracle.dist_matrix(X, oracle.L1)
+    starts = _starts(D, k, R, init, seed=72)
+    runs, tds, best = _oracle_best(D, starts, variant)
+    res = px().fit_restarts(_t(D.astype(np.int32)), k, starts=starts, variant=variant)
+    assert res.rc == 0
+    assert res.stats["restart_td"] == tds
+    assert res.stats["best"] == best
+    assert list(res.medoids.cpu().numpy()) == list(runs[best].medoids) and res.td == tds[best]
+    _, lab = oracle.td(runs[best].medoids, D=D)
+    assert np.array_equal(res.labels.cpu().numpy(), lab)
+    assert res.stats["swaps"] == runs[best].swaps
+
+
+def test_restart_tie_keeps_the_first():
+    """Restarts 0 and 2 share a start: equal TDs, restart 0 wins over 2."""
+    _say("restarts_tie")
+    n, k = 400, 6
+    X = datagen.int_points(n, 2, 0, 100, seed=73)
+    D = oracle.dist_matrix(X, oracle.L1)
+    a, b = datagen.random_subset(n, k, 1), datagen.random_subset(n, k, 2)
+    starts = np.stack([a, b, a, b]).astype(np.int32)
+    runs, tds, best = _oracle_best(D, starts, "fastpam1")
+    res = px().fit_restarts(_t(D.astype(np.int32)), k, starts=starts, variant="fastpam1")
+    assert res.stats["restart_td"] == tds and res.stats["best"] == best and best in (0, 1)
+    assert list(res.medoids.cpu().numpy()) == list(runs[best].medoids)
+
+
+def test_float_restarts():
+    """FP32 matrix read by both sides (the oracle widens it): every
+    restart's TD within the FP64 summation bound, the kept medoids equal."""
+    _say("restarts_f32")
+    n, k, R = 3000, 12, 4
+    X = datagen.gaussian_mixture(n, 8, 10, seed=74)
+    D32 = oracle.dist_matrix(X).astype(np.float32)
+    D = D32.astype(np.float64)
+    starts = _starts(D, k, R, "random", seed=75)
+    runs, tds, best = _oracle_best(D, starts, "fasterpam")
+    res = px().fit_restarts(_t(D32), k, starts=starts, variant="fasterpam")
+    for g, r in zip(res.stats["restart_td"], tds):
+        assert abs(g - r) <= 8 * n * 2.0 ** -53 * r
+    order = np.sort(tds)
+    if order[1] - order[0] > 16 * n * 2.0 ** -53 * order[0]:
+        assert res.stats["best"] == best
+        assert list(res.medoids.cpu().numpy()) == list(runs[best].medoids)
+
+
+def test_gpu_starts_equal_oracle_starts():
+    """restart_starts on the GPU (init_dw, init_lab kernels) gives the
+    oracle's seeds from the same uniforms and subsamples."""
+    _say("restarts_starts")
+    n, k = 700, 8
+    X = datagen.int_points(n, 2, 0, 500, seed=76)
+    D = oracle.dist_matrix(X, oracle.L1)
+    Dt = _t(D.astype(np.int32))
+    for init in ("random", "dw", "lab"):
+        g = px().restart_starts(Dt, k, 3, init, seed=77)
+        assert np.array_equal(g, _starts(D, k, 3, init, seed=77)), init
+
+
+def test_bad_start_is_refused():
+    _say("restarts_bad_start")
+    n, k = 200, 4
+    X = datagen.int_points(n, 2, 0, 100, seed=78)
+    D = _t(oracle.dist_matrix(X, oracle.L1).astype(np.int32))
+    starts = np.array([[0, 1, 2, 3], [5, 5, 6, 7]], np.int32)
+    with pytest.raises(px().PamxError):
+        px().fit_restarts(D, k, starts=starts, variant="fastpam1")
