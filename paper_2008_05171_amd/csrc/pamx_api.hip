@@ -150,7 +150,7 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->wg_v = take(nwg * 8);
     L->wg_i = take(nwg * 4);
     L->wg_c = take(nwg * 4);
-    L->P = p2 ? take((size_t)k * L->ncp * 8) : SIZE_MAX;
+    L->has_p = p2;   // P depends on the chunk count: placed with the chunk-dependent regions
     L->slot_v = take((size_t)k * 8);
     L->slot_c = take((size_t)k * 4);
     L->list = take((size_t)(n > k ? n : k) * 4);
@@ -191,6 +191,8 @@ static void place_tail(Layout *L, int32_t Lc, int64_t cols) {
     L->cdn = take((size_t)L->Q * 2 * 8);              // DN parts of carried segments
     L->part = take((size_t)L->Q * 4 * cols * 8);
     L->part_i = take((size_t)L->Q * cols * 4);
+    // FastPAM2: one row per (chunk, segment) pair at segment + chunk (k + Q rows)
+    L->P = L->has_p ? take(((size_t)L->k + L->Q) * L->ncp * 8) : SIZE_MAX;
     L->total = off;
 }
 void set_chunk(Layout *L, int32_t Lc) { place_tail(L, Lc, L->ncp); }
@@ -524,9 +526,13 @@ struct Timer {
     void rec(int i, hipStream_t s) {
         if (ok) (void)hipEventRecord(e[i], s);
     }
+    // 0 if either event was not recorded (an early error return); the
+    // failed query's error is cleared so no later launch check reports it
     double ms(int a, int b) {
         float v = 0.f;
-        if (ok && hipEventElapsedTime(&v, e[a], e[b]) == hipSuccess) return v;
+        if (!ok) return 0.0;
+        if (hipEventElapsedTime(&v, e[a], e[b]) == hipSuccess) return v;
+        (void)hipGetLastError();
         return 0.0;
     }
 };
@@ -1260,7 +1266,7 @@ extern "C" int pamx_swap_restarts(const void *D, int32_t dtype, int64_t n, int64
                                              tdr, st, ws, s, t)
                           : swap_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, opt, wmed,
                                                wlab, tdr, st, ws, s, t);
-        st->ms_swap = t.ms(2, 3);
+        if (r >= 0) st->ms_swap = t.ms(2, 3);
         return r;
     };
     return best_of(L, restarts, starts, opt, medoids, labels, td, stats, restart_td, best, ws,
@@ -1299,7 +1305,7 @@ extern "C" int pamx_clarans_numlocal(const void *D, int32_t dtype, int64_t n, in
                                                 maxneighbor, opt, wmed, wlab, tdr, st, ws, s, t)
                           : clarans_impl<int32_t>(static_cast<const int32_t *>(D), ld, L, k, dr, len,
                                                   maxneighbor, opt, wmed, wlab, tdr, st, ws, s, t);
-        st->ms_swap = t.ms(2, 3);
+        if (c >= 0) st->ms_swap = t.ms(2, 3);
         return c;
     };
     return best_of(L, numlocal, starts, opt, medoids, labels, td, stats, search_td, best, ws,

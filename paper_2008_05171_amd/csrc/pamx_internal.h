@@ -184,7 +184,8 @@ struct Layout {
     size_t part, part_i;
     size_t cand_v, cand_i, cand_a;
     size_t wg_v, wg_i, wg_c;
-    size_t P, slot_v, slot_c;
+    size_t P, slot_v, slot_c;   // P: FastPAM2 only (SIZE_MAX otherwise), (k + Q) x ncp FP64
+    bool has_p;
     size_t list, list_v, list_i, rlist;
     size_t cl_v, cl_i;   // FastCLARANS: changes and slots of a window of draws
     size_t mark;         // medoid check: one counter per candidate

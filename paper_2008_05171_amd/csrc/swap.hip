@@ -763,6 +763,17 @@ __global__ __launch_bounds__(kObjBlk) void k_seg_scatter(
     sds[pos] = ds[o];
 }
 
+// FastPAM2's buffer P of M_i(c) - DN_i, laid out so that one pass
+// work-group's values are a single contiguous run: tile-major (TW candidates
+// per pass tile), and within a tile one row per (chunk q, segment s) at row
+// s + q.  Rows of consecutive chunks never overlap (a chunk's first segment is
+// at least the previous chunk's last), so k + Q rows hold them all; a segment
+// cut by chunk edges (its sums come from the merge) lives in the row of the
+// chunk that holds its first object, seg_off[s] / L.
+__device__ __forceinline__ int64_t p_index(int64_t rows, int tw_log2, int64_t row, int64_t c) {
+    return ((((c >> tw_log2) * rows) + row) << tw_log2) + (c & ((int64_t(1) << tw_log2) - 1));
+}
+
 // DN_i = sum over segment i of dn, one wave per segment, fixed order.
 // ---- the hot pass.  See the file header for the arithmetic.
 // Output per candidate and chunk: part[q][0] = A partial, [1] head carry,
@@ -771,14 +782,16 @@ __global__ __launch_bounds__(kObjBlk) void k_seg_scatter(
 // segments into P[i][c].  WIN (FasterPAM) evaluates the candidate window
 // [fw_base, fw_end) of the state; the partials are indexed relative to
 // fw_base (ncp is then the window width).
-template <typename T, int VEC, bool P2>
+template <typename T, int VEC, bool P2, bool PF = false>
 __device__ __forceinline__ void pass_tile(
     int tile, int q, int64_t cb, int64_t ce, const T *__restrict__ D, int64_t ld, int64_t n,
     const int32_t *__restrict__ srow, const T *__restrict__ sdn, const T *__restrict__ sds,
     const int32_t *__restrict__ seg_off, AccT<T> *__restrict__ cdn,
     const ChunkInfo *__restrict__ cinfo, int32_t L, int64_t ncp, AccT<T> *__restrict__ part,
-    int32_t *__restrict__ part_i, AccT<T> *__restrict__ P) {
+    int32_t *__restrict__ part_i, AccT<T> *__restrict__ P, int64_t prows) {
     using A = AccT<T>;
+    constexpr int kTwLog2 = VEC == 4 ? 10 : 8;   // log2(kWG * VEC)
+    static_assert(kWG * VEC == (1 << kTwLog2), "pass tile width");
     // four rows in flight per lane: measured faster than eight or sixteen,
     // and than issuing the next rows before the current ones are summed,
     // for a 20000 x 20000 FP32 matrix
@@ -814,7 +827,7 @@ __device__ __forceinline__ void pass_tile(
     auto flush_p = [&]() {
         __builtin_amdgcn_wave_barrier();
         for (int t = 0; t < nst; ++t) {
-            A *dst = P + (int64_t)pseg[wv * kPStage + t] * ncp + wc0;
+            A *dst = P + p_index(prows, kTwLog2, (int64_t)pseg[wv * kPStage + t] + q, wc0);
             const A *src = pst + (wv * kPStage + t) * 256;
 #pragma unroll
             for (int e = 0; e < 4; ++e) __builtin_nontemporal_store(src[64 * e + ln], dst + 64 * e + ln);
@@ -860,7 +873,8 @@ __device__ __forceinline__ void pass_tile(
                     } else {
 #pragma unroll
                         for (int e = 0; e < VEC; ++e)
-                            __builtin_nontemporal_store(v[e], &P[(int64_t)s * ncp + c0 + e]);
+                            __builtin_nontemporal_store(
+                                v[e], &P[p_index(prows, kTwLog2, (int64_t)s + q, c0 + e)]);
                     }
                 }
             }
@@ -883,17 +897,7 @@ __device__ __forceinline__ void pass_tile(
                 M[e] += (A)vmed3(v[e], lo, hi);
             }
         };
-        int64_t j = a;
-        for (; j + U <= b; j += U) {
-            T v[U][VEC];
-            T lo[U], hi[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t o = srow[j + u];
-                load_vec<T, VEC>(D + o * ld + c0, v[u]);
-                lo[u] = sdn[j + u];
-                hi[u] = sds[j + u];
-            }
+        auto add_block = [&](int64_t j, const T (&v)[U][VEC], const T (&lo)[U], const T (&hi)[U]) {
             if (j + U <= se) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) add_row(v[u], lo[u], hi[u]);
@@ -903,6 +907,44 @@ __device__ __forceinline__ void pass_tile(
                     if (j + u == se) next_seg(j + u);
                     add_row(v[u], lo[u], hi[u]);
                 }
+            }
+        };
+        auto load_block = [&](int64_t j, T (&v)[U][VEC], T (&lo)[U], T (&hi)[U]) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t o = srow[j + u];
+                load_vec<T, VEC>(D + o * ld + c0, v[u]);
+                lo[u] = sdn[j + u];
+                hi[u] = sds[j + u];
+            }
+        };
+        int64_t j = a;
+        if constexpr (PF) {
+            // long chunks: the next block's rows are issued before the
+            // current block is summed (eight rows in flight per lane)
+            if (j + U <= b) {
+                T v[U][VEC], lo[U], hi[U];
+                load_block(j, v, lo, hi);
+                for (; j + 2 * U <= b; j += U) {
+                    T w[U][VEC], wl[U], wh[U];
+                    load_block(j + U, w, wl, wh);
+                    add_block(j, v, lo, hi);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) v[u][e] = w[u][e];
+                        lo[u] = wl[u];
+                        hi[u] = wh[u];
+                    }
+                }
+                add_block(j, v, lo, hi);
+                j += U;
+            }
+        } else {
+            for (; j + U <= b; j += U) {
+                T v[U][VEC], lo[U], hi[U];
+                load_block(j, v, lo, hi);
+                add_block(j, v, lo, hi);
             }
         }
         for (; j < b; ++j) {
@@ -925,14 +967,14 @@ __device__ __forceinline__ void pass_tile(
     }
 }
 
-template <typename T, int VEC, bool P2, bool WIN>
+template <typename T, int VEC, bool P2, bool WIN, bool PF = false>
 __global__ __launch_bounds__(kWG) PAMX_PASS_ATTR void k_swap_pass(
     const T *__restrict__ D, int64_t ld, int64_t n, int64_t nc, int32_t k,
     const int32_t *__restrict__ srow,
     const T *__restrict__ sdn, const T *__restrict__ sds, const int32_t *__restrict__ seg_off,
     AccT<T> *__restrict__ cdn, const ChunkInfo *__restrict__ cinfo, int32_t L, int64_t ncp,
     AccT<T> *__restrict__ part, int32_t *__restrict__ part_i, AccT<T> *__restrict__ P,
-    const DevState *__restrict__ st) {
+    int64_t prows, const DevState *__restrict__ st) {
     if constexpr (!WIN) {
         // the chunk's map entry and first row are read with the state, so
         // one memory round trip precedes the first rows of D
@@ -948,10 +990,10 @@ __global__ __launch_bounds__(kWG) PAMX_PASS_ATTR void k_swap_pass(
         const int nt = (int)((ce - cb + kWG * VEC - 1) / (kWG * VEC));
         for (int t = 0; t < nt; ++t)
             pass_tile<T, VEC, false>(t, blockIdx.y, cb, ce, D, ld, n, srow, sdn, sds, seg_off, cdn,
-                                     cinfo, L, ncp, part, part_i, P);
+                                     cinfo, L, ncp, part, part_i, P, prows);
     } else {
-        pass_tile<T, VEC, P2>(blockIdx.x, blockIdx.y, 0, nc, D, ld, n, srow, sdn, sds, seg_off, cdn,
-                              cinfo, L, ncp, part, part_i, P);
+        pass_tile<T, VEC, P2, PF>(blockIdx.x, blockIdx.y, 0, nc, D, ld, n, srow, sdn, sds, seg_off,
+                                  cdn, cinfo, L, ncp, part, part_i, P, prows);
     }
 }
 
@@ -976,10 +1018,13 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
     const ChunkInfo *__restrict__ cinfo, int32_t Q, int64_t nc, int32_t k, int64_t ncp,
     const AccT<T> *__restrict__ cdn, const uint8_t *__restrict__ is_med,
     const DevState *__restrict__ st, AccT<T> *__restrict__ P, AccT<T> *__restrict__ cand_a,
-    AccT<T> *__restrict__ wg_v, int32_t *__restrict__ wg_i, int32_t *__restrict__ wg_c) {
+    AccT<T> *__restrict__ wg_v, int32_t *__restrict__ wg_i, int32_t *__restrict__ wg_c,
+    const int32_t *__restrict__ seg_off, int32_t Lc, int64_t prows, int32_t tw_log2) {
     using A = AccT<T>;
     if (st->done) return;
     __shared__ RunSum<A> sm[kSmG][kSmC];
+    // row of P for a segment carried across chunks: the chunk of its first object
+    auto prow = [&](int s) { return (int64_t)s + seg_off[s] / Lc; };
     const int j = threadIdx.x % kSmC, g = threadIdx.x / kSmC;
     const int64_t c = (int64_t)blockIdx.x * kSmC + j;
     const bool live = c < nc;
@@ -1000,7 +1045,7 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
             if (s == r.ls) { r.lm += m; r.ldn += dn; return; }
             const A v = r.lm - r.ldn;   // a run between the first and the last: complete
             if (lt2(v, r.ls, r.bv, r.bi)) { r.bv = v; r.bi = r.ls; }
-            if constexpr (P2) P[(int64_t)r.ls * ncp + c] = v;
+            if constexpr (P2) P[p_index(prows, tw_log2, prow(r.ls), c)] = v;
             r.ls = s; r.lm = m; r.ldn = dn;
         };
         constexpr int UQ = 8;   // chunks whose partials are loaded together
@@ -1042,7 +1087,7 @@ __global__ __launch_bounds__(kWG) void k_swap_merge(
             if (s < 0) return;
             const A v = m - dn;
             if (lt2(v, s, bv, bi)) { bv = v; bi = s; }
-            if constexpr (P2) P[(int64_t)s * ncp + c] = v;
+            if constexpr (P2) P[p_index(prows, tw_log2, prow(s), c)] = v;
         };
         for (int h = 0; h < kSmG; ++h) {
             const RunSum<A> &x = sm[h][j];
@@ -1622,7 +1667,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_slot_best(const AccT<T> *__restrict__ P,
                                                    const AccT<T> *__restrict__ cand_a,
                                                    const int32_t *__restrict__ seg_off, int64_t n,
-                                                   int64_t ncp, const uint8_t *__restrict__ is_med,
+                                                   int32_t Lc, int64_t prows, int32_t tw_log2,
+                                                   const uint8_t *__restrict__ is_med,
                                                    AccT<T> *__restrict__ part_v,
                                                    int32_t *__restrict__ part_c, int64_t span,
                                                    const DevState *__restrict__ st) {
@@ -1631,11 +1677,11 @@ __global__ __launch_bounds__(256) void k_slot_best(const AccT<T> *__restrict__ P
     const int i = blockIdx.x, j = blockIdx.y, S = gridDim.y;
     const bool empty = seg_off[i] == seg_off[i + 1];
     const int64_t x0 = (int64_t)j * span, x1 = min(x0 + span, n);
-    const A *Pi = P + (int64_t)i * ncp;
+    const int64_t row = (int64_t)i + (empty ? 0 : seg_off[i] / Lc);
     A v = VT<T>::acc_inf();
     int c = INT_MAX, dummy = 0;
     for (int64_t x = x0 + threadIdx.x; x < x1; x += 256) {
-        const A d = (empty ? (A)0 : Pi[x]) + cand_a[x];
+        const A d = (empty ? (A)0 : P[p_index(prows, tw_log2, row, x)]) + cand_a[x];
         if (!is_med[x] && d < v) { v = d; c = (int)x; }   // ascending x: first minimum per thread
     }
     block_argmin3<A, 256>(v, dummy, c);
@@ -2015,6 +2061,18 @@ static void enqueue_segments(const Layout &L, const SwapPtrs<T> &p, hipStream_t 
                        p.st);
 }
 
+// Chunk length from which the pass issues each block's rows before summing
+// the previous block (measured on the 40 GB matrix, 20000-row chunks: faster;
+// on the 1.6 GB matrix, 800-row chunks: slower)
+#ifndef PAMX_PF_CHUNK
+#define PAMX_PF_CHUNK 4096
+#endif
+constexpr int32_t kPfChunk = PAMX_PF_CHUNK;
+
+// rows of FastPAM2's P per pass tile (k + Q, see p_index) and log2 of the tile width
+static int64_t p_rows(const Layout &L) { return (int64_t)L.k + L.Q; }
+static int32_t tw_log2(const Layout &L) { return L.vec == 4 ? 10 : 8; }
+
 // win: FasterPAM window pass (L placed by set_window: L.L, L.Q are the
 // window chunking, the partials have L.fw columns)
 template <typename T>
@@ -2022,18 +2080,24 @@ static void enqueue_pass(const T *D, int64_t ld, const Layout &L, const SwapPtrs
                          hipStream_t s, bool win = false) {
     const dim3 pgrid(win ? 1 : L.n_ctiles, L.Q);
     const int64_t cols = win ? L.fw : L.ncp;
-#define PAMX_PASS(VEC, P2, WIN)                                                               \
-    hipLaunchKernelGGL((k_swap_pass<T, VEC, P2, WIN>), pgrid, dim3(kWG), 0, s, D, ld, L.n,   \
+#define PAMX_PASS(VEC, P2, WIN, PF)                                                           \
+    hipLaunchKernelGGL((k_swap_pass<T, VEC, P2, WIN, PF>), pgrid, dim3(kWG), 0, s, D, ld, L.n, \
                        L.nc, L.k, (const int32_t *)p.srow, (const T *)p.sdn, (const T *)p.sds, \
                        (const int32_t *)p.seg_off, p.cdn,                                     \
                        (const ChunkInfo *)p.cinfo, L.L, cols, p.part, p.part_i, p.P,          \
-                       (const DevState *)p.st)
+                       p_rows(L), (const DevState *)p.st)
+    // chunks of at least kPfChunk rows: the prefetching row loop
+    const bool pf = !win && L.L >= kPfChunk;
     if (win) {
-        if (L.vec == 4) PAMX_PASS(4, false, true); else PAMX_PASS(1, false, true);
+        if (L.vec == 4) PAMX_PASS(4, false, true, false); else PAMX_PASS(1, false, true, false);
     } else if (L.vec == 4) {
-        if (p2) PAMX_PASS(4, true, false); else PAMX_PASS(4, false, false);
+        if (pf) {
+            if (p2) PAMX_PASS(4, true, false, true); else PAMX_PASS(4, false, false, true);
+        } else {
+            if (p2) PAMX_PASS(4, true, false, false); else PAMX_PASS(4, false, false, false);
+        }
     } else {
-        if (p2) PAMX_PASS(1, true, false); else PAMX_PASS(1, false, false);
+        if (p2) PAMX_PASS(1, true, false, false); else PAMX_PASS(1, false, false, false);
     }
 #undef PAMX_PASS
 }
@@ -2096,14 +2160,16 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
         hipLaunchKernelGGL((k_swap_merge<T, true>), dim3(smwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
                            L.Q, L.nc, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
-                           (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
+                           (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c,
+                           (const int32_t *)p.seg_off, L.L, p_rows(L), tw_log2(L));
         {
             A *sb_v = reinterpret_cast<A *>(static_cast<char *>(ws) + L.sb_v);
             int32_t *sb_c = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + L.sb_c);
             const int64_t span = (L.nc + L.sbS - 1) / L.sbS;
             hipLaunchKernelGGL(k_slot_best<T>, dim3(k, L.sbS), dim3(256), 0, s, (const A *)p.P,
-                               (const A *)p.cand_a, (const int32_t *)p.seg_off, L.nc, L.ncp,
-                               (const uint8_t *)p.is_med, sb_v, sb_c, span, (const DevState *)p.st);
+                               (const A *)p.cand_a, (const int32_t *)p.seg_off, L.nc, L.L,
+                               p_rows(L), tw_log2(L), (const uint8_t *)p.is_med, sb_v, sb_c, span,
+                               (const DevState *)p.st);
             hipLaunchKernelGGL(k_slot_reduce<T>, dim3((k + 255) / 256), dim3(256), 0, s,
                                (const A *)sb_v, (const int32_t *)sb_c, L.sbS, k, p.slot_v,
                                p.slot_c, (const DevState *)p.st);
@@ -2134,7 +2200,8 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
         hipLaunchKernelGGL((k_swap_merge<T, false>), dim3(smwg), dim3(kWG), 0, s,
                            (const A *)p.part, (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo,
                            L.Q, L.nc, k, L.ncp, (const A *)p.cdn, (const uint8_t *)p.is_med,
-                           (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c);
+                           (const DevState *)p.st, p.P, p.cand_a, p.wg_v, p.wg_i, p.wg_c,
+                           (const int32_t *)p.seg_off, L.L, p_rows(L), tw_log2(L));
         int64_t ldl;
         const T *Dl = loc_rows<T>(D, ld, L, ws, &ldl);
         hipLaunchKernelGGL(k_select_update<T>, dim3(ob), dim3(256), 0, s, (const A *)p.wg_v,

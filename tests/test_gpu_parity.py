@@ -120,6 +120,21 @@ def test_chunk_carries_do_not_change_results(chunk):
     _check_same(res, ref, 9)
 
 
+@pytest.mark.parametrize("variant", ["fastpam1", "fastpam2"])
+@pytest.mark.parametrize("n,chunk", [(4200, 4096), (5000, 4104), (6000, 6000)])
+def test_long_chunks_prefetching_loop(n, chunk, variant):
+    """Chunks of 4096 rows and more take the prefetching row loop (the next
+    block's rows issued before the current block is summed): one chunk, two
+    chunks with a ragged second one, segments cut at a chunk edge; bit-exact
+    against the oracle's PAM and FastPAM2 reading."""
+    _say("long_chunk", n, chunk, variant)
+    X, D = _int_case(n, 123 + n)
+    ref = oracle.pam(6, D=D, variant=oracle.PAM if variant == "fastpam1" else oracle.FASTPAM2)
+    res = px().fit(_t(X), 6, trace=True, chunk=chunk, variant=variant)
+    assert res.stats["chunk"] == chunk
+    _check_same(res, ref, 6)
+
+
 def test_chunk_tuning_keeps_results():
     """Chunk tuning times the pass for several chunk lengths and keeps the
     fastest; on integer distances every chunking gives the same sums, so the

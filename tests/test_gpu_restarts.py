@@ -130,3 +130,8 @@ def test_bad_start_is_refused():
     starts = np.array([[0, 1, 2, 3], [5, 5, 6, 7]], np.int32)
     with pytest.raises(px().PamxError):
         px().fit_restarts(D, k, starts=starts, variant="fastpam1")
+    # the refused call leaves no HIP error behind for the next calls
+    Dx = px().dist(_t(X))
+    assert torch.equal(Dx, D)
+    ok = px().fit_restarts(D, k, starts=starts[:1], variant="fastpam1")
+    assert ok.rc == 0 and ok.stats["best"] == 0
