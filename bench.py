@@ -82,9 +82,9 @@ def log(*a):
 # HBM traffic records from rocprofv3 counter runs, one per timed pass kernel
 TRAFFIC = {
     "fastpam2_gmm32": (os.path.join(ROOT, "profiles", "swap_pass_fastpam2_gmm32_traffic.json"),
-                       "pamx::k_swap_pass<float, 4, true, false>", N5, K5),
+                       "pamx::k_swap_pass<float, 4, true, false, true>", N5, K5),
     "fastpam1_gmm16": (os.path.join(ROOT, "profiles", "swap_pass_gmm16_traffic.json"),
-                       "pamx::k_swap_pass<float, 4, false, false>", N, K),
+                       "pamx::k_swap_pass<float, 4, false, false, false>", N, K),
 }
 # the SWAP pass kernel and the header it shares (its launch shape, the chunk
 # length, is recorded with the counters and compared with the timed fits')

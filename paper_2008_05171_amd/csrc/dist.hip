@@ -219,7 +219,13 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32(const float *__restrict__ X
 // DP = the dimension padded to 16, 32 or 64 with zeros (0 x 0 products leave
 // every sum unchanged).
 constexpr int kSD = 64;       // largest dimension of the strip form
-constexpr int kCT = 2;        // column tiles per work-group (measured: 2 beats 4 and 8)
+// column tiles per work-group.  Measured on the 1e5 x 32 points (40 GB
+// matrix, non-temporal stores): 2 tiles 15.4 ms, 4: 18.9, 6: 18.2, 8: 13.8,
+// 12: 17.5, 16: 16.7, 32: 16.4; on 20000 x 16 points 8 tiles equal 2 (0.47 ms).
+// Staging the tile in LDS for 16-byte stores (17.0 ms) and computing only the
+// upper triangle with the transposed tile written from the same registers
+// (23.6 ms: 32-byte row pieces per store) were slower.
+constexpr int kCT = 8;
 template <int DP>
 __global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restrict__ X,
                                                            const float *__restrict__ mean,
@@ -297,7 +303,8 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restri
             const float s = (na[r] + nb[wc + i]) - 2.0f * acc[v];
             float d = __builtin_amdgcn_sqrtf(fmaxf(s, 0.0f));   // within 1 ulp; subnormals to 0
             if (r0 + r == c) d = 0.0f;
-            if (r0 + r < n && c < n) D[(r0 + r) * ld + c] = d;
+            // streaming stores: the matrix is far larger than the caches
+            if (r0 + r < n && c < n) __builtin_nontemporal_store(d, &D[(r0 + r) * ld + c]);
         }
     }
 }
@@ -412,6 +419,7 @@ hipError_t launch_check_dis(const void *D, int32_t dtype, int64_t n, int64_t ld,
 // Work-group (tile, chunk) reads rows [chunk * L, +L) of columns
 // [tile * 1024, +1024), one 16-byte non-temporal load per lane and row, four
 // rows in flight (as the pass), and writes the sum of what it read.
+template <bool PF>
 __global__ __launch_bounds__(256) void k_read_probe(const float *__restrict__ D, int64_t ld, int64_t n,
                                                    int32_t L, float *__restrict__ sums) {
     typedef float f4 __attribute__((ext_vector_type(4)));
@@ -422,13 +430,35 @@ __global__ __launch_bounds__(256) void k_read_probe(const float *__restrict__ D,
     float acc = 0.f;
     if (c0 < n) {   // c0 + 3 < ld: ld is a multiple of 4
         int64_t o = a;
-        for (; o + U <= b; o += U) {
-            f4 v[U];
+        auto ld4 = [&](int64_t o0, f4 (&v)[U]) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                v[u] = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(D + (o + u) * ld + c0));
+                v[u] = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(D + (o0 + u) * ld + c0));
+        };
+        auto sum4 = [&](const f4 (&v)[U]) {
 #pragma unroll
             for (int u = 0; u < U; ++u) acc += (v[u][0] + v[u][1]) + (v[u][2] + v[u][3]);
+        };
+        if constexpr (PF) {   // the pass's prefetching loop: next block issued first
+            if (o + U <= b) {
+                f4 v[U];
+                ld4(o, v);
+                for (; o + 2 * U <= b; o += U) {
+                    f4 w[U];
+                    ld4(o + U, w);
+                    sum4(v);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) v[u] = w[u];
+                }
+                sum4(v);
+                o += U;
+            }
+        } else {
+            for (; o + U <= b; o += U) {
+                f4 v[U];
+                ld4(o, v);
+                sum4(v);
+            }
         }
         for (; o < b; ++o) {
             const f4 v = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(D + o * ld + c0));
@@ -446,7 +476,10 @@ __global__ __launch_bounds__(256) void k_read_probe(const float *__restrict__ D,
 hipError_t launch_read_probe(const float *D, int64_t n, int64_t ld, int32_t L, float *sums,
                              hipStream_t s) {
     const dim3 grid((unsigned)((n + 1023) / 1024), (unsigned)((n + L - 1) / L));
-    hipLaunchKernelGGL(k_read_probe, grid, dim3(256), 0, s, D, ld, n, L, sums);
+    if (L >= kPfChunk)
+        hipLaunchKernelGGL(k_read_probe<true>, grid, dim3(256), 0, s, D, ld, n, L, sums);
+    else
+        hipLaunchKernelGGL(k_read_probe<false>, grid, dim3(256), 0, s, D, ld, n, L, sums);
     return hipGetLastError();
 }
 

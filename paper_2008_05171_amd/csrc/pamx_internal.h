@@ -13,6 +13,14 @@
 namespace pamx {
 
 constexpr int kWG = 256;          // threads per work-group in pass kernels
+// Chunk length from which the pass (and the reference read in its shape)
+// issues each block's rows before summing the previous block (measured on the
+// 40 GB matrix, 20000-row chunks: faster; on the 1.6 GB one, 800-row chunks:
+// slower)
+#ifndef PAMX_PF_CHUNK
+#define PAMX_PF_CHUNK 4096
+#endif
+constexpr int32_t kPfChunk = PAMX_PF_CHUNK;
 constexpr int kObjBlk = 256;      // objects per block in segment kernels
 constexpr int kMaxK = 16000;      // largest k accepted (slot histogram and offsets in LDS)
 constexpr int kBMaxDim = 16;      // batched instances: largest point dimension

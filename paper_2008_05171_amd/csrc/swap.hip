@@ -2061,14 +2061,6 @@ static void enqueue_segments(const Layout &L, const SwapPtrs<T> &p, hipStream_t 
                        p.st);
 }
 
-// Chunk length from which the pass issues each block's rows before summing
-// the previous block (measured on the 40 GB matrix, 20000-row chunks: faster;
-// on the 1.6 GB matrix, 800-row chunks: slower)
-#ifndef PAMX_PF_CHUNK
-#define PAMX_PF_CHUNK 4096
-#endif
-constexpr int32_t kPfChunk = PAMX_PF_CHUNK;
-
 // rows of FastPAM2's P per pass tile (k + Q, see p_index) and log2 of the tile width
 static int64_t p_rows(const Layout &L) { return (int64_t)L.k + L.Q; }
 static int32_t tw_log2(const Layout &L) { return L.vec == 4 ? 10 : 8; }
