@@ -445,6 +445,42 @@ def read_probe(n, chunk, stream, launches=10):
             "bytes_per_launch": 4.0 * n * n, "launches": len(ms)}
 
 
+def write_probe(n, stream, launches=10):
+    """Average duration of pamx_write_probe over an n x n FP32 matrix (row
+    stride rounded up to 64, as the fit stores it): the distance kernel's
+    stores alone, in its launch shape."""
+    import torch
+    from paper_2008_05171_amd import pamx as abi
+    ld = (n + 63) // 64 * 64
+    Dp = torch.empty(n, ld, dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        abi.pamx_write_probe(Dp, 1.0, n=n, ld=ld, stream=stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = []
+    for _ in range(launches):
+        ev0.record(stream)
+        abi.pamx_write_probe(Dp, 1.0, n=n, ld=ld, stream=stream)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms.append(ev0.elapsed_time(ev1))
+    # a plain fill of the same matrix by torch (16-byte stores along the rows)
+    fill = []
+    for _ in range(3):
+        ev0.record(stream)
+        Dp.fill_(2.0)
+        ev1.record(stream)
+        ev1.synchronize()
+        fill.append(ev0.elapsed_time(ev1))
+    del Dp
+    torch.cuda.empty_cache()
+    avg = sum(ms) / len(ms)
+    gbs = 4.0 * n * n / (avg / 1e3) / 1e9
+    fgbs = 4.0 * n * ld / (min(fill) / 1e3) / 1e9
+    return {"avg_launch_ms": avg, "achieved": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "bytes_per_launch": 4.0 * n * n, "launches": len(ms),
+            "torch_fill_gbs": fgbs}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -578,6 +614,18 @@ def main():
         roof["frac_of_read_probe"] = roof["achieved"] / probe["achieved"]
         log("read probe: %.3f ms per launch, %.0f GB/s" % (probe["avg_launch_ms"],
                                                            probe["achieved"]))
+        # the distance kernel (its phase: mean + Gram kernel) against its stores alone
+        wp = write_probe(N5, stream)
+        dist_ms = sum(s["ms_dist"] for s in stats) / len(stats)
+        dist_gbs = 4.0 * N5 * N5 / (dist_ms / 1e3) / 1e9
+        out["distance_roofline"] = {
+            "bound": "hbm", "kernel": "k_dist_l2_f32_strip<32> (with k_center_mean)",
+            "achieved": dist_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": dist_gbs / HBM_PEAK_GBS, "avg_ms": dist_ms, "bytes": 4.0 * N5 * N5,
+            "mfma_flops": 2.0 * DIM5 * N5 * N5, "write_probe": wp,
+            "frac_of_write_probe": dist_gbs / wp["achieved"]}
+        log("write probe: %.3f ms per launch, %.0f GB/s; distances %.3f ms, %.0f GB/s" % (
+            wp["avg_launch_ms"], wp["achieved"], dist_ms, dist_gbs))
         Xc = torch.from_numpy(datagen.workload_gmm16()).to(dev)
         g = {"workload": "gmm16: n=20000 d=16, 50 equal components, stored FP32 matrix (1.6 GB), "
                          "k=100, BUILD init"}

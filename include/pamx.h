@@ -457,6 +457,19 @@ int pamx_check_dissimilarity(const void *D, int32_t dtype, int64_t n, int64_t ld
 int pamx_read_probe(const void *D, int64_t n, int64_t ld, int32_t chunk, float *sums,
                     int64_t sums_len, void *stream);
 
+/* Measurement (not part of the method): the store rate the FP32 distance
+ * kernel's output pattern can reach.  Writes `value` to D[r][c] for r, c in
+ * [0, n) in exactly the launch shape and store pattern of the distance
+ * kernel (64 x 64 tiles, eight per work-group along the row, each store
+ * instruction two 128-byte row pieces, streaming stores), with no loads and
+ * no arithmetic; 4 n^2 bytes over the time of one call is the reference the
+ * distance kernel's rate is compared with.
+ *   D      device, n x ld FP32 (ld >= n), 4-byte aligned; entries beyond
+ *          column n - 1 are not touched
+ * Asynchronous on stream.  Returns 0, PAMX_ERR_ARG for bad arguments
+ * (before any device work; n at most 65535 * 64), PAMX_ERR_HIP. */
+int pamx_write_probe(void *D, int64_t n, int64_t ld, float value, void *stream);
+
 /* Message for the last non-zero return on this thread ("" if none). */
 const char *pamx_last_error(void);
 

@@ -235,6 +235,7 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restri
     __shared__ float xa[kT * kSLd];
     __shared__ float xb[kT * kSLd];
     __shared__ float na[kT], nb[kT];
+    __shared__ float smean[DP];
     constexpr int kPer = kT * DP / 256;    // staged values per thread
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -243,20 +244,31 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restri
     const int64_t cb = (int64_t)blockIdx.x * (kT * kCT);
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
 
-    // centred coordinates of 64 points (rows p0..p0+63) into registers
+    // coordinates of 64 points (rows p0..p0+63) into registers, raw: the
+    // loads read clamped (always valid) addresses and are not used until the
+    // points are staged, so the next tile's loads stay in flight during this
+    // tile's MFMA loop.  (A load under a branch, or one used at once, ends in
+    // a wait for every outstanding memory operation, the previous tile's
+    // stores included.)
     auto load = [&](int64_t p0, float (&v)[kPer]) {
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int e = tid + u * 256;
             const int r = e / DP, kk = e % DP;
-            v[u] = (kk < dim && p0 + r < n) ? X[(p0 + r) * dim + kk] - mean[kk] : 0.0f;
+            const int kc = kk < dim ? kk : dim - 1;
+            const int64_t pr = p0 + r < n ? p0 + r : n - 1;
+            v[u] = X[pr * dim + kc];
         }
     };
-    auto store = [&](float *x, const float (&v)[kPer]) {
+    // centre and pad while staging: (x - mean) * 0 is the padding's 0 (x is a
+    // finite coordinate of a valid point)
+    auto store = [&](float *x, const float (&v)[kPer], int64_t p0) {
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int e = tid + u * 256;
-            x[(e / DP) * kSLd + e % DP] = v[u];
+            const int r = e / DP, kk = e % DP;
+            const float keep = (kk < dim && p0 + r < n) ? 1.0f : 0.0f;
+            x[r * kSLd + kk] = (v[u] - smean[kk]) * keep;
         }
     };
     // squared norms of the 64 staged points: four threads per point, each
@@ -271,10 +283,12 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restri
         s2 += __shfl_xor(s2, 2);
         if (part == 0) nrm[pnt] = s2;
     };
+    if (tid < DP) smean[tid] = tid < dim ? mean[tid] : 0.0f;
     float va[kPer], vb[kPer];
     load(r0, va);
     load(cb, vb);
-    store(xa, va);
+    __syncthreads();   // smean
+    store(xa, va, r0);
     __syncthreads();
     norms(xa, na);
     const int i = lane & 31, h = lane >> 5;
@@ -282,7 +296,7 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restri
         const int64_t c0 = cb + (int64_t)t * kT;
         if (c0 >= n) break;   // uniform
         __syncthreads();      // the previous tile's reads of xb are done
-        store(xb, vb);
+        store(xb, vb, c0);
         __syncthreads();
         if (t + 1 < kCT && c0 + kT < n) load(c0 + kT, vb);   // next tile, in flight
         norms(xb, nb);
@@ -307,6 +321,36 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restri
             if (r0 + r < n && c < n) __builtin_nontemporal_store(d, &D[(r0 + r) * ld + c]);
         }
     }
+}
+
+// Measurement: the stores of k_dist_l2_f32_strip alone -- the same grid,
+// work-group shape and store pattern (per instruction a half-wave writes 32
+// consecutive floats of one row, 16 instructions per wave and 64 x 64 tile,
+// kCT tiles per work-group, streaming stores) writing the value v, with no
+// loads and no arithmetic.  Entries (r, c), r, c < n, are written.
+__global__ __launch_bounds__(256) void k_write_probe(float *__restrict__ D, int64_t n, int64_t ld,
+                                                     float v) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.y * kT;
+    const int64_t cb = (int64_t)blockIdx.x * (kT * kCT);
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int i = lane & 31, h = lane >> 5;
+    for (int t = 0; t < kCT; ++t) {
+        const int64_t c0 = cb + (int64_t)t * kT;
+        if (c0 >= n) break;
+        const int64_t c = c0 + wc + i;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int r = wr + 8 * (u >> 2) + 4 * h + (u & 3);
+            if (r0 + r < n && c < n) __builtin_nontemporal_store(v, &D[(r0 + r) * ld + c]);
+        }
+    }
+}
+
+hipError_t launch_write_probe(float *D, int64_t n, int64_t ld, float v, hipStream_t s) {
+    dim3 grid((unsigned)((n + kT * kCT - 1) / (kT * kCT)), (unsigned)((n + kT - 1) / kT));
+    hipLaunchKernelGGL(k_write_probe, grid, dim3(256), 0, s, D, n, ld, v);
+    return hipGetLastError();
 }
 
 hipError_t launch_dist_l2_f32(const float *X, int64_t n, int32_t dim, float *D, int64_t ld,

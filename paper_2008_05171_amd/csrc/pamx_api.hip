@@ -506,6 +506,16 @@ extern "C" int pamx_read_probe(const void *D, int64_t n, int64_t ld, int32_t chu
     return PAMX_OK;
 }
 
+extern "C" int pamx_write_probe(void *D, int64_t n, int64_t ld, float value, void *stream) {
+    if (n < 1) return fail(PAMX_ERR_ARG, "n must be >= 1");
+    int rc = check_matrix(D, n, ld);
+    if (rc) return rc;
+    if ((reinterpret_cast<uintptr_t>(D) & 3) != 0) return fail(PAMX_ERR_ARG, "D must be 4-byte aligned");
+    if (n > (int64_t)65535 * 64) return fail(PAMX_ERR_ARG, "n too large for the probe grid");
+    HIP_TRY(launch_write_probe(static_cast<float *>(D), n, ld, value, static_cast<hipStream_t>(stream)));
+    return PAMX_OK;
+}
+
 // ---------------------------------------------------------------- BUILD / SWAP
 namespace {
 

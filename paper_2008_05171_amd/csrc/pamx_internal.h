@@ -238,6 +238,8 @@ void set_window(Layout *L);
 // launchers (one per kernel family); each returns hipSuccess or an error.
 hipError_t launch_dist_l1_i32(const int32_t *X, int64_t n, int32_t dim, int32_t *D, int64_t ld,
                               hipStream_t s);
+// measurement: the FP32 distance kernel's stores alone (value v into D[r][c], r, c < n)
+hipError_t launch_write_probe(float *D, int64_t n, int64_t ld, float v, hipStream_t s);
 // mm[2*dim] (device scratch) receives the minimum and maximum of every
 // coordinate of the integer points
 hipError_t launch_range_i32(const int32_t *X, int64_t n, int32_t dim, int32_t *mm, hipStream_t s);

@@ -65,7 +65,7 @@ EXPORTS = ("pamx_default_options", "pamx_workspace_bytes", "pamx_dist", "pamx_bu
            "pamx_swap", "pamx_fit", "pamx_batched_workspace_bytes", "pamx_fit_batched",
            "pamx_init_workspace_bytes", "pamx_init_dw", "pamx_init_lab", "pamx_clarans",
            "pamx_rect_workspace_bytes", "pamx_fit_rect", "pamx_swap_rect",
-           "pamx_check_dissimilarity", "pamx_read_probe", "pamx_swap_noalloc",
+           "pamx_check_dissimilarity", "pamx_read_probe", "pamx_write_probe", "pamx_swap_noalloc",
            "pamx_best_of_workspace_bytes", "pamx_swap_restarts", "pamx_clarans_numlocal",
            "pamx_last_error")
 
@@ -113,6 +113,7 @@ def load(path: str = LIB_PATH):
     lib.pamx_check_dissimilarity.argtypes = [P, i32, i64, i64, ctypes.POINTER(ctypes.c_int32),
                                              ctypes.POINTER(ctypes.c_int64), P, sz, P]
     lib.pamx_read_probe.argtypes = [P, i64, i64, i32, P, i64, P]
+    lib.pamx_write_probe.argtypes = [P, i64, i64, ctypes.c_float, P]
     lib.pamx_swap_noalloc.argtypes = [P, i32, i64, i64, i32, opt_p, P, P, dbl_p, st_p, P]
     lib.pamx_best_of_workspace_bytes.argtypes = [i64, i32, i32, opt_p, ctypes.POINTER(sz)]
     lib.pamx_swap_restarts.argtypes = [P, i32, i64, i64, i32, i32, P, opt_p, P, P, dbl_p, st_p,
@@ -125,6 +126,7 @@ def load(path: str = LIB_PATH):
                  "pamx_batched_workspace_bytes", "pamx_fit_batched", "pamx_init_workspace_bytes",
                  "pamx_init_dw", "pamx_init_lab", "pamx_clarans", "pamx_rect_workspace_bytes",
                  "pamx_fit_rect", "pamx_swap_rect", "pamx_check_dissimilarity", "pamx_read_probe",
+                 "pamx_write_probe",
                  "pamx_swap_noalloc", "pamx_best_of_workspace_bytes", "pamx_swap_restarts",
                  "pamx_clarans_numlocal"):
         getattr(lib, name).restype = ctypes.c_int
@@ -207,6 +209,14 @@ def pamx_read_probe(D, chunk, sums, n=None, ld=None, stream=None):
     ld = D.stride(0) if ld is None else ld
     return _check(load().pamx_read_probe(_ptr(D), int(n), int(ld), int(chunk), _ptr(sums),
                                          sums.numel(), _stream(stream)))
+
+
+def pamx_write_probe(D, value=1.0, n=None, ld=None, stream=None):
+    """Writes `value` to the n x n FP32 matrix D in the distance kernel's launch
+    shape and store pattern (no loads, no arithmetic)."""
+    n = D.shape[0] if n is None else n
+    ld = D.stride(0) if ld is None else ld
+    return _check(load().pamx_write_probe(_ptr(D), int(n), int(ld), float(value), _stream(stream)))
 
 
 def pamx_build(D, k, medoids, ws, opt=None, n=None, ld=None, stream=None):

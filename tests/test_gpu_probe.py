@@ -1,9 +1,11 @@
-"""GPU check of the reference read (pamx_read_probe), the plain read of a
-matrix in the SWAP pass's launch shape that the benchmark times beside the
-pass: every work-group's sum equals the sum of the block it was given
+"""GPU checks of the measurement references.  The reference read
+(pamx_read_probe), the plain read of a matrix in the SWAP pass's launch shape
+that the benchmark times beside the pass: every work-group's sum equals the
+sum of the block it was given
 (1024-column tiles, row chunks, ragged last tile and chunk, columns read up
 to the next multiple of 4; chunks of 4096 rows and more take the pass's
-prefetching loop)."""
+prefetching loop).  The reference store (pamx_write_probe), the distance
+kernel's stores alone: every entry written, the padding untouched."""
 import pytest
 
 from paper_2008_05171_amd import pamx as abi
@@ -35,3 +37,16 @@ def test_read_probe_block_sums(n, chunk):
             # FP32 sums: each lane adds 4 values per row of the chunk
             tol = max(1e-4, 4.0 * blk.shape[0] * 2.0 ** -24) * max(1.0, want)
             assert abs(got[y, x].item() - want) <= tol, (y, x, got[y, x], want)
+
+
+@pytest.mark.parametrize("n,ld", [(1, 4), (63, 64), (1000, 1003), (1537, 1600)])
+def test_write_probe_covers_the_matrix(n, ld):
+    """pamx_write_probe writes its value to every entry (r, c < n) and leaves
+    the padding columns alone (ragged tiles, padded and odd strides)."""
+    print("[case] write_probe", n, ld, flush=True)
+    buf = torch.full((n, ld), -3.0, dtype=torch.float32, device=DEV)
+    abi.pamx_write_probe(buf[:, :n], 2.5, ld=ld)
+    torch.cuda.synchronize()
+    got = buf.cpu()
+    assert bool((got[:, :n] == 2.5).all())
+    assert bool((got[:, n:] == -3.0).all())
