@@ -106,7 +106,10 @@ extern "C" {
 
 /* pamx_options.chunk: time the SWAP pass for several chunk lengths on the
  * caller's matrix (after BUILD, with its medoids) and keep the fastest; the
- * workspace must then be sized with the same option. */
+ * workspace must then be sized with the same option.  For pamx_fit_batched
+ * it times the batched launch for several team sizes (work-groups per large
+ * instance) on the first call of each instance shape and keeps the fastest
+ * for the process; the results do not depend on the team sizes. */
 #define PAMX_CHUNK_TUNE (-1)
 
 /* return codes */
@@ -386,7 +389,9 @@ typedef struct pamx_batch_stats {
     int32_t swaps;        /* swaps over all instances */
     int32_t best_inst;    /* instance with the smallest full-data TD (lowest id on ties),
                              -1 when full-data TD was not requested */
-    int32_t reserved;
+    int32_t team_scale;   /* team sizes used, in percent of the cost-balanced ones
+                             (0: no teams); chosen by timing with
+                             opt->chunk = PAMX_CHUNK_TUNE, else 100 */
     double ms_pam;        /* device time of the batched BUILD + SWAP launch */
     double ms_assign;     /* device time of the full-data TD kernels */
     double ms_total;

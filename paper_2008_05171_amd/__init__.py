@@ -365,10 +365,12 @@ class BatchResult:
 
 
 def fit_batched(X, sample_off, sample_idx, k_inst, *, metric=None, max_iter=10000,
-                exclude_self=False, full_td=True, stream=None) -> BatchResult:
+                exclude_self=False, full_td=True, tune=False, stream=None) -> BatchResult:
     """Batched CLARA: PAM (BUILD + FastPAM1) on every subsample in one launch,
     then the TD of each run over all points of X.  sample_off/k_inst are host
-    arrays, sample_idx a device int32 tensor."""
+    arrays, sample_idx a device int32 tensor.  tune=True: the team sizes are
+    timed on the first call of this instance shape and the fastest kept
+    (stats["team_scale"])."""
     import numpy as np
     import torch
     dtype = _abi._dtype_code(X)
@@ -376,7 +378,8 @@ def fit_batched(X, sample_off, sample_idx, k_inst, *, metric=None, max_iter=1000
         metric = PAMX_L1 if dtype == _abi.PAMX_I32 else PAMX_L2
     k_inst = np.asarray(k_inst, dtype=np.int32)
     sample_off = np.asarray(sample_off, dtype=np.int64)
-    opt = _options(max_iter=max_iter, exclude_self=exclude_self)
+    opt = _options(max_iter=max_iter, exclude_self=exclude_self,
+                   chunk=PAMX_CHUNK_TUNE if tune else 0)
     ws = _workspace(_abi.pamx_batched_workspace_bytes(len(k_inst), X.shape[0]), X.device)
     med = torch.empty(int(k_inst.sum()), dtype=torch.int32, device=X.device)
     rc, tds, tdf, st = _abi.pamx_fit_batched(X, metric, sample_off, sample_idx, k_inst, med, ws,

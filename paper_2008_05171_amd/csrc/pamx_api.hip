@@ -1587,6 +1587,21 @@ extern "C" int pamx_fit(const void *XorD, int32_t input_kind, int32_t dtype, int
 // ---------------------------------------------------------------- batched CLARA
 namespace {
 constexpr int kFullBlocks = 256;   // blocks per instance in the full-data TD
+// team scales (percent of the cost-balanced team sizes; 0 = no teams) timed
+// by the batched form's tuning
+constexpr int kTeamScales[] = {100, 0, 50, 200};
+struct BatchTuneKey {
+    int dev;
+    int32_t n_inst, dim, dtype, max_iter, excl;
+    int64_t N;
+    uint64_t shape;
+    bool operator<(const BatchTuneKey &o) const {
+        return std::tie(dev, n_inst, dim, dtype, max_iter, excl, N, shape) <
+               std::tie(o.dev, o.n_inst, o.dim, o.dtype, o.max_iter, o.excl, o.N, o.shape);
+    }
+};
+std::mutex g_btune_mu;
+std::map<BatchTuneKey, int> g_btuned;
 
 struct BatchLayout {
     size_t soff, kin, moff, tk_inst, tk_mem, tsz, bar, xch, td, tdb, it, sw, rows, ctr, part, tdf,
@@ -1690,32 +1705,16 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
     // Teams: with cooperative launch, an instance whose estimated cost is a
     // multiple of the balanced share (total / resident work-groups) gets that
     // many work-groups (at most kBTeamMax, and at least 256 candidates each),
-    // so the largest instances do not set the length of the launch.
+    // so the largest instances do not set the length of the launch.  `scale`
+    // (percent) multiplies the team sizes; 0 turns teams off.  The results do
+    // not depend on it: a team splits an instance's candidates, every
+    // candidate's sums are formed by one lane in a fixed order, and the team
+    // takes the same lexicographic minimum.
     int coop = 0;
     const int resident = batched_resident(dim, lds, dtype, &coop);
     if (resident < 1) return fail(PAMX_ERR_UNSUPPORTED, "the batched kernel does not fit a compute unit");
-    std::vector<int32_t> tsz(n_inst, 1);
-    if (coop && resident >= 2) {
-        double total = 0.0;
-        for (const auto &cj : cost) total += -cj.first;
-        const double share = total / resident;
-        for (const auto &cj : cost) {
-            const int32_t j = cj.second;
-            const int64_t nj = sample_off[j + 1] - sample_off[j];
-            int lim = (int)std::min<int64_t>(kBTeamMax, std::max<int64_t>(1, nj / 256));
-            if (lim > resident) lim = resident;
-            const int t = (int)std::llround(-cj.first / share);
-            tsz[j] = t < 1 ? 1 : (t > lim ? lim : t);
-        }
-    }
-    std::vector<int32_t> tk_inst, tk_mem;   // queue tickets, largest estimated cost first
-    int32_t max_team = 1;
-    for (const auto &cj : cost) {
-        const int32_t j = cj.second;
-        for (int32_t m = 0; m < tsz[j]; ++m) { tk_inst.push_back(j); tk_mem.push_back(m); }
-        max_team = tsz[j] > max_team ? tsz[j] : max_team;
-    }
-    const int32_t n_tick = (int32_t)tk_inst.size();
+    double total_cost = 0.0;
+    for (const auto &cj : cost) total_cost += -cj.first;
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *w = static_cast<char *>(ws);
@@ -1725,14 +1724,7 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
     HIP_TRY(hipMemcpyAsync(w + B.soff, sample_off, (size_t)(n_inst + 1) * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(w + B.kin, k_inst, (size_t)n_inst * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(w + B.moff, moff.data(), (size_t)(n_inst + 1) * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w + B.tk_inst, tk_inst.data(), (size_t)n_tick * 4, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w + B.tk_mem, tk_mem.data(), (size_t)n_tick * 4, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(w + B.tsz, tsz.data(), (size_t)n_inst * 4, hipMemcpyHostToDevice, s));
     int32_t *ctr = reinterpret_cast<int32_t *>(w + B.ctr);
-    hipLaunchKernelGGL(k_fill_batch<int32_t>, dim3(1), dim3(256), 0, s, ctr, (int64_t)2, 0);
-    hipLaunchKernelGGL(k_fill_batch<int32_t>, dim3((n_inst + 255) / 256), dim3(256), 0, s,
-                       reinterpret_cast<int32_t *>(w + B.bar), (int64_t)n_inst, 0);
-    HIP_TRY(hipGetLastError());
 
     BatchArgs a;
     a.soff = reinterpret_cast<const int64_t *>(w + B.soff);
@@ -1745,14 +1737,10 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
     a.bar = reinterpret_cast<int32_t *>(w + B.bar);
     a.xch = reinterpret_cast<unsigned long long *>(w + B.xch);
     a.n_inst = n_inst;
-    a.n_tick = n_tick;
-    a.coop = max_team > 1 ? 1 : 0;
     a.max_iter = opt.max_iter;
     a.excl = opt.build_exclude_self;
     a.n_max = n_max;
     a.k_max = k_max;
-    if (a.coop) a.grid = resident < n_tick ? resident : n_tick;   // all resident at once
-    else a.grid = cus < n_inst ? cus : n_inst;
     a.nblk = kFullBlocks;
     a.med_out = medoids;
     a.td_out = reinterpret_cast<double *>(w + B.td);
@@ -1764,6 +1752,50 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
     a.rows_out = reinterpret_cast<int32_t *>(w + B.rows);
     a.queue = ctr;
     a.err = ctr + 1;
+    // tickets (largest estimated cost first), counters and the PAM launch
+    // for one team scale
+    std::vector<int32_t> tsz(n_inst), tk_inst, tk_mem;
+    auto launch_pam = [&](int scale) -> hipError_t {
+        std::fill(tsz.begin(), tsz.end(), 1);
+        if (scale > 0 && coop && resident >= 2) {
+            const double share = total_cost / resident;
+            for (const auto &cj : cost) {
+                const int32_t j = cj.second;
+                const int64_t nj = sample_off[j + 1] - sample_off[j];
+                int lim = (int)std::min<int64_t>(kBTeamMax, std::max<int64_t>(1, nj / 256));
+                if (lim > resident) lim = resident;
+                const int t = (int)std::llround(-cj.first / share * scale / 100.0);
+                tsz[j] = t < 1 ? 1 : (t > lim ? lim : t);
+            }
+        }
+        tk_inst.clear();
+        tk_mem.clear();
+        int32_t max_team = 1;
+        for (const auto &cj : cost) {
+            const int32_t j = cj.second;
+            for (int32_t m = 0; m < tsz[j]; ++m) { tk_inst.push_back(j); tk_mem.push_back(m); }
+            max_team = tsz[j] > max_team ? tsz[j] : max_team;
+        }
+        a.n_tick = (int32_t)tk_inst.size();
+        a.coop = max_team > 1 ? 1 : 0;
+        if (a.coop) a.grid = resident < a.n_tick ? resident : a.n_tick;   // all resident at once
+        else a.grid = cus < n_inst ? cus : n_inst;
+        hipError_t e;
+        if ((e = hipMemcpyAsync(w + B.tk_inst, tk_inst.data(), (size_t)a.n_tick * 4,
+                                hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(w + B.tk_mem, tk_mem.data(), (size_t)a.n_tick * 4,
+                                hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(w + B.tsz, tsz.data(), (size_t)n_inst * 4, hipMemcpyHostToDevice,
+                                s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_fill_batch<int32_t>, dim3(1), dim3(1), 0, s, ctr, (int64_t)1, 0);   // queue
+        hipLaunchKernelGGL(k_fill_batch<int32_t>, dim3((n_inst + 255) / 256), dim3(256), 0, s,
+                           reinterpret_cast<int32_t *>(w + B.bar), (int64_t)n_inst, 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        return dtype == PAMX_F32 ? launch_clara<float>(static_cast<const float *>(X), N, dim, a, s)
+                                 : launch_clara<int32_t>(static_cast<const int32_t *>(X), N, dim, a, s);
+    };
+    hipLaunchKernelGGL(k_fill_batch<int32_t>, dim3(1), dim3(256), 0, s, ctr, (int64_t)2, 0);
+    HIP_TRY(hipGetLastError());
 
     // every sample index in [0, N) before any instance runs
     {
@@ -1773,10 +1805,47 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
         HIP_TRY(hipStreamSynchronize(s));
         if (e0) return fail(PAMX_ERR_ARG, "sample_idx holds an index outside [0, N)");
     }
+    // team scale: the default, or timed once per argument shape (chunk =
+    // PAMX_CHUNK_TUNE) over kTeamScales and kept for the process
+    int scale = 100;
+    if (opt.chunk == PAMX_CHUNK_TUNE && coop && resident >= 2) {
+        uint64_t hsh = 1469598103934665603ull;   // FNV-1a over the instance shapes
+        auto mix = [&](uint64_t v) { hsh = (hsh ^ v) * 1099511628211ull; };
+        for (int32_t j = 0; j <= n_inst; ++j) mix((uint64_t)sample_off[j]);
+        for (int32_t j = 0; j < n_inst; ++j) mix((uint64_t)(uint32_t)k_inst[j]);
+        const BatchTuneKey key{dev, n_inst, dim, dtype, opt.max_iter, opt.build_exclude_self, N, hsh};
+        bool found = false;
+        {
+            std::lock_guard<std::mutex> g(g_btune_mu);
+            auto it = g_btuned.find(key);
+            if (it != g_btuned.end()) { scale = it->second; found = true; }
+        }
+        if (!found) {
+            // one untimed launch first: the first launch of a process runs
+            // cold (measured 20 ms against 16 for the same work)
+            HIP_TRY(launch_pam(kTeamScales[0]));
+            Timer tt;
+            double best = 0.0;
+            for (int sc : kTeamScales) {
+                tt.rec(0, s);
+                HIP_TRY(launch_pam(sc));
+                tt.rec(1, s);
+                int32_t e1 = 0;
+                HIP_TRY(hipMemcpyAsync(&e1, ctr + 1, 4, hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                if (e1 & 4) return fail(PAMX_ERR_HIP, "a team of the batched kernel did not meet (wait bound reached)");
+                if (e1 & 8) return fail(PAMX_ERR_ARG, "an instance's BUILD found no finite distance sum "
+                                                      "(non-finite point coordinates)");
+                const double ms = tt.ms(0, 1);
+                if (sc == kTeamScales[0] || ms < best) { best = ms; scale = sc; }
+            }
+            std::lock_guard<std::mutex> g(g_btune_mu);
+            g_btuned[key] = scale;
+        }
+    }
     Timer tm;
     tm.rec(0, s);
-    if (dtype == PAMX_F32) HIP_TRY(launch_clara<float>(static_cast<const float *>(X), N, dim, a, s));
-    else HIP_TRY(launch_clara<int32_t>(static_cast<const int32_t *>(X), N, dim, a, s));
+    HIP_TRY(launch_pam(scale));
     tm.rec(1, s);
     if (td_full) {
         if (dtype == PAMX_F32) HIP_TRY(launch_full_assign<float>(static_cast<const float *>(X), N, dim, a, s));
@@ -1816,6 +1885,7 @@ extern "C" int pamx_fit_batched(const void *X, int32_t dtype, int64_t N, int32_t
                 if (td_full[j] < td_full[b]) b = j;
             stats->best_inst = b;
         }
+        stats->team_scale = (coop && resident >= 2) ? scale : 0;
         stats->ms_pam = tm.ms(0, 1);
         stats->ms_assign = tm.ms(1, 2);
         stats->ms_total = tm.ms(0, 2);

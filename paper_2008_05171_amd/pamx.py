@@ -56,7 +56,7 @@ class pamx_stats(ctypes.Structure):
 
 class pamx_batch_stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("swaps", ctypes.c_int32),
-                ("best_inst", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("best_inst", ctypes.c_int32), ("team_scale", ctypes.c_int32),
                 ("ms_pam", ctypes.c_double), ("ms_assign", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("pairs", ctypes.c_int64)]
 

@@ -155,6 +155,42 @@ def test_batched_largest_instance():
     assert abs(a.td_sample[0] - td_g) <= 1e-6 * td_g
 
 
+@pytest.mark.parametrize("dtype", ["i32", "f32"])
+def test_batched_team_tuning_keeps_results(dtype):
+    """Team-size tuning (chunk = PAMX_CHUNK_TUNE) times several team sizes and
+    keeps the fastest: the results equal the untuned call's bit for bit
+    (medoids, sample TD, full TD), the integer ones equal the oracle's, and a
+    second call reuses the tuned scale."""
+    _say("batched_tune", dtype)
+    if dtype == "i32":
+        X = datagen.int_points(20000, 3, 0, 1000, seed=13)
+    else:
+        X = datagen.gaussian_mixture(20000, 4, 20, seed=13)
+    sizes = [1900, 1200, 700, 400, 150, 60]
+    ks = np.array([11, 7, 5, 4, 3, 2], np.int32)
+    rng = np.random.default_rng(13)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    idx = np.concatenate([np.sort(rng.choice(20000, size=m, replace=False))
+                          for m in sizes]).astype(np.int32)
+    base = _run(X, off, idx, ks)
+    tuned = _run(X, off, idx, ks, tune=True)
+    again = _run(X, off, idx, ks, tune=True)
+    assert tuned.stats["team_scale"] in (0, 50, 100, 200)
+    assert again.stats["team_scale"] == tuned.stats["team_scale"]
+    assert base.stats["team_scale"] in (0, 100)
+    for r in (tuned, again):
+        assert np.array_equal(r.td_sample, base.td_sample)
+        assert np.array_equal(r.td_full, base.td_full)
+        for j in range(len(ks)):
+            assert torch.equal(r.medoids[j], base.medoids[j]), j
+    if dtype == "i32":
+        for j in (0, 1, 5):
+            sample = idx[off[j]:off[j + 1]]
+            ref = oracle.pam(int(ks[j]), D=oracle.dist_matrix(X[sample], oracle.L1))
+            assert list(tuned.medoids[j].cpu().numpy()) == list(sample[ref.medoids]), j
+            assert tuned.td_sample[j] == ref.td, j
+
+
 def test_batched_nan_point_is_refused():
     """A sample holding a point with a NaN coordinate: every BUILD sum of the
     instance is non-finite, the instance stops (uniformly, before any medoid
