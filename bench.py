@@ -621,7 +621,7 @@ def main():
         dist_ms = sum(s["ms_dist"] for s in stats) / len(stats)
         dist_gbs = 4.0 * N5 * N5 / (dist_ms / 1e3) / 1e9
         out["distance_roofline"] = {
-            "bound": "hbm", "kernel": "k_dist_l2_f32_strip<32> (with k_center_mean)",
+            "bound": "hbm", "kernel": "k_dist_l2_f32_upper<32> (with k_center_mean)",
             "achieved": dist_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dist_gbs / HBM_PEAK_GBS, "avg_ms": dist_ms, "bytes": 4.0 * N5 * N5,
             "mfma_flops": 2.0 * DIM5 * N5 * N5, "write_probe": wp,

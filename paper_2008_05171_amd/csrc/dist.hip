@@ -7,9 +7,11 @@
 //                    (v_mfma_f32_32x32x2_f32), the root by the hardware instruction
 //                    (within 1 ulp; its error is small beside the Gram term's), 64 x 64
 //                    tiles staged in LDS and written back as full 256-byte row segments.
-//  * k_dist_l2_f32_strip : the same entries for dim <= 64: a work-group keeps its
-//                    rows' points and walks two column tiles, loading the next
-//                    tile's points behind the current MFMA loop.
+//  * k_dist_l2_f32_upper : the same entries for dim <= 64, computed only for
+//                    the tiles at or right of the diagonal and written twice (as
+//                    computed and transposed) with 16-byte row stores; a work-group
+//                    keeps its rows' points and walks eight column tiles, loading
+//                    the next tile's points behind the current MFMA loop.
 //  All write a zero diagonal and are bitwise symmetric.
 #include <type_traits>
 
@@ -207,27 +209,33 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32(const float *__restrict__ X
     }
 }
 
-// Strip form for dim <= kSD: a work-group keeps its 64 rows' points in LDS
-// and walks kCT column tiles of 64; the next tile's points are loaded into
-// registers before the current tile's MFMA loop (the load latency hides
-// behind it), and results go from the accumulators straight to D (per store
-// instruction each half-wave writes 32 consecutive floats of one row).  The
-// Gram term of every entry is the tiled kernel's (the same centred values and
-// MFMA sequence over coordinates); squared norms are summed by four threads per
-// point in a fixed order, the same for rows and columns, so D is again bitwise
-// symmetric with a zero diagonal.
+// Upper-triangle form for dim <= kSD.  D is symmetric, so work-group (x, y)
+// computes only the 64 x 64 tiles (y, t) with t >= y among its column tiles
+// x*kCT .. x*kCT+kCT-1 and writes each twice: as computed (rows of block y)
+// and transposed (rows of block t), both with 16-byte row stores from an LDS
+// copy of the tile.  The MFMA work and the point loads are half the full
+// matrix's; the stores are the same 4 n^2 bytes.  The work-group keeps its
+// 64 rows' points in LDS; the next column tile's points are loaded into
+// registers before the current tile's MFMA loop and first used when they are
+// staged.  Every entry is one computed value written at (r, c) and at (c, r),
+// so D is bitwise symmetric; the diagonal tile is written once with a zero
+// diagonal.  Squared norms are summed by four threads per point in a fixed
+// order.
 // DP = the dimension padded to 16, 32 or 64 with zeros (0 x 0 products leave
 // every sum unchanged).
-constexpr int kSD = 64;       // largest dimension of the strip form
-// column tiles per work-group.  Measured on the 1e5 x 32 points (40 GB
-// matrix, non-temporal stores): 2 tiles 15.4 ms, 4: 18.9, 6: 18.2, 8: 13.8,
-// 12: 17.5, 16: 16.7, 32: 16.4; on 20000 x 16 points 8 tiles equal 2 (0.47 ms).
-// Staging the tile in LDS for 16-byte stores (17.0 ms) and computing only the
-// upper triangle with the transposed tile written from the same registers
-// (23.6 ms: 32-byte row pieces per store) were slower.
-constexpr int kCT = 8;
+// Measured on the 1e5 x 32 points (40 GB matrix): 7.55 ms = 5.3 TB/s, 94 % of
+// the same stores alone (pamx_write_probe); 4 column tiles per work-group
+// 7.78 ms, 16: 7.61.  The full-matrix strip form it replaced took 12.0 ms (its
+// stores went from the MFMA accumulators, two 128-byte row pieces per store
+// instruction; writing the transposed tile that way takes 32-byte pieces,
+// 23.6 ms).  A load under a branch, or one used at once, ends in a wait for
+// every outstanding memory operation of the wave, stores included (one
+// in-order count on gfx950), hence the clamped, deferred point loads.
+constexpr int kSD = 64;       // largest dimension of this form
+constexpr int kCT = 8;        // column tiles per work-group
+constexpr int kTL = kT + 1;   // odd row stride of the LDS tile: row and column reads both conflict-free
 template <int DP>
-__global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restrict__ X,
+__global__ __launch_bounds__(256) void k_dist_l2_f32_upper(const float *__restrict__ X,
                                                            const float *__restrict__ mean,
                                                            int64_t n, int32_t dim,
                                                            float *__restrict__ D, int64_t ld) {
@@ -236,20 +244,22 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restri
     __shared__ float xb[kT * kSLd];
     __shared__ float na[kT], nb[kT];
     __shared__ float smean[DP];
+    __shared__ float tb[kT * kTL];
     constexpr int kPer = kT * DP / 256;    // staged values per thread
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t r0 = (int64_t)blockIdx.y * kT;
-    const int64_t cb = (int64_t)blockIdx.x * (kT * kCT);
+    const int64_t yb = blockIdx.y;
+    const int64_t r0 = yb * kT;
+    const int64_t nT = (n + kT - 1) / kT;
+    int64_t t0 = (int64_t)blockIdx.x * kCT;
+    if (t0 + kCT <= yb) return;   // every tile left of the diagonal (uniform)
+    if (t0 < yb) t0 = yb;
+    const int64_t tend = min(nT, (int64_t)blockIdx.x * kCT + kCT);
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
 
-    // coordinates of 64 points (rows p0..p0+63) into registers, raw: the
-    // loads read clamped (always valid) addresses and are not used until the
-    // points are staged, so the next tile's loads stay in flight during this
-    // tile's MFMA loop.  (A load under a branch, or one used at once, ends in
-    // a wait for every outstanding memory operation, the previous tile's
-    // stores included.)
+    // coordinates of 64 points (rows p0..p0+63) into registers, raw, from
+    // clamped (always valid) addresses
     auto load = [&](int64_t p0, float (&v)[kPer]) {
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
@@ -286,19 +296,19 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restri
     if (tid < DP) smean[tid] = tid < dim ? mean[tid] : 0.0f;
     float va[kPer], vb[kPer];
     load(r0, va);
-    load(cb, vb);
+    load(t0 * kT, vb);
     __syncthreads();   // smean
     store(xa, va, r0);
     __syncthreads();
     norms(xa, na);
     const int i = lane & 31, h = lane >> 5;
-    for (int t = 0; t < kCT; ++t) {
-        const int64_t c0 = cb + (int64_t)t * kT;
-        if (c0 >= n) break;   // uniform
-        __syncthreads();      // the previous tile's reads of xb are done
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    for (int64_t t = t0; t < tend; ++t) {
+        const int64_t c0 = t * kT;
+        __syncthreads();      // the previous tile's reads of xb and tb are done
         store(xb, vb, c0);
         __syncthreads();
-        if (t + 1 < kCT && c0 + kT < n) load(c0 + kT, vb);   // next tile, in flight
+        if (t + 1 < tend) load(c0 + kT, vb);   // next tile, in flight
         norms(xb, nb);
         floatx16 acc;
 #pragma unroll
@@ -310,45 +320,91 @@ __global__ __launch_bounds__(256) void k_dist_l2_f32_strip(const float *__restri
             acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
         }
         __syncthreads();      // nb complete
-        const int64_t c = c0 + wc + i;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int r = wr + 8 * (v >> 2) + 4 * h + (v & 3);
             const float s = (na[r] + nb[wc + i]) - 2.0f * acc[v];
             float d = __builtin_amdgcn_sqrtf(fmaxf(s, 0.0f));   // within 1 ulp; subnormals to 0
-            if (r0 + r == c) d = 0.0f;
-            // streaming stores: the matrix is far larger than the caches
-            if (r0 + r < n && c < n) __builtin_nontemporal_store(d, &D[(r0 + r) * ld + c]);
+            if (r0 + r == c0 + wc + i) d = 0.0f;
+            tb[r * kTL + wc + i] = d;
+        }
+        __syncthreads();
+        const bool full = r0 + kT <= n && c0 + kT <= n;
+        // as computed: D[r0 + r][c0 + q .. c0 + q + 3]; streaming stores (the
+        // matrix is far larger than the caches)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = tid + j * 256;
+            const int r = e >> 4, q = (e & 15) * 4;
+            const float *src = tb + r * kTL + q;
+            if (full) {
+                const f4 val = {src[0], src[1], src[2], src[3]};
+                __builtin_nontemporal_store(val, reinterpret_cast<f4 *>(D + (r0 + r) * ld + c0 + q));
+            } else if (r0 + r < n) {
+                for (int u = 0; u < 4; ++u)
+                    if (c0 + q + u < n) D[(r0 + r) * ld + c0 + q + u] = src[u];
+            }
+        }
+        if (t != yb) {
+            // transposed: D[c0 + c][r0 + q .. r0 + q + 3] = tile rows q..q+3 of column c
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int e = tid + j * 256;
+                const int c = e >> 4, q = (e & 15) * 4;
+                const float *src = tb + q * kTL + c;
+                if (full) {
+                    const f4 val = {src[0], src[kTL], src[2 * kTL], src[3 * kTL]};
+                    __builtin_nontemporal_store(val, reinterpret_cast<f4 *>(D + (c0 + c) * ld + r0 + q));
+                } else if (c0 + c < n) {
+                    for (int u = 0; u < 4; ++u)
+                        if (r0 + q + u < n) D[(c0 + c) * ld + r0 + q + u] = src[u * kTL];
+                }
+            }
         }
     }
 }
 
-// Measurement: the stores of k_dist_l2_f32_strip alone -- the same grid,
-// work-group shape and store pattern (per instruction a half-wave writes 32
-// consecutive floats of one row, 16 instructions per wave and 64 x 64 tile,
-// kCT tiles per work-group, streaming stores) writing the value v, with no
-// loads and no arithmetic.  Entries (r, c), r, c < n, are written.
+// Measurement: the stores of k_dist_l2_f32_upper alone -- the same grid,
+// work-group shape and store pattern (per 64 x 64 tile at or right of the
+// diagonal, 16-byte streaming row stores as computed and transposed) writing
+// the value v, with no loads and no arithmetic.  Entries (r, c), r, c < n,
+// are written.
 __global__ __launch_bounds__(256) void k_write_probe(float *__restrict__ D, int64_t n, int64_t ld,
                                                      float v) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t r0 = (int64_t)blockIdx.y * kT;
-    const int64_t cb = (int64_t)blockIdx.x * (kT * kCT);
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    const int i = lane & 31, h = lane >> 5;
-    for (int t = 0; t < kCT; ++t) {
-        const int64_t c0 = cb + (int64_t)t * kT;
-        if (c0 >= n) break;
-        const int64_t c = c0 + wc + i;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int tid = threadIdx.x;
+    const int64_t yb = blockIdx.y;
+    const int64_t r0 = yb * kT;
+    const int64_t nT = (n + kT - 1) / kT;
+    int64_t t0 = (int64_t)blockIdx.x * kCT;
+    if (t0 + kCT <= yb) return;
+    if (t0 < yb) t0 = yb;
+    const int64_t tend = min(nT, (int64_t)blockIdx.x * kCT + kCT);
+    const f4 val = {v, v, v, v};
+    for (int64_t t = t0; t < tend; ++t) {
+        const int64_t c0 = t * kT;
+        const bool full = r0 + kT <= n && c0 + kT <= n;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int r = wr + 8 * (u >> 2) + 4 * h + (u & 3);
-            if (r0 + r < n && c < n) __builtin_nontemporal_store(v, &D[(r0 + r) * ld + c]);
+        for (int j = 0; j < 4; ++j) {
+            const int e = tid + j * 256;
+            const int r = e >> 4, q = (e & 15) * 4;
+            if (full) {
+                __builtin_nontemporal_store(val, reinterpret_cast<f4 *>(D + (r0 + r) * ld + c0 + q));
+                if (t != yb)
+                    __builtin_nontemporal_store(val, reinterpret_cast<f4 *>(D + (c0 + r) * ld + r0 + q));
+            } else {
+                for (int u = 0; u < 4; ++u) {
+                    if (r0 + r < n && c0 + q + u < n) D[(r0 + r) * ld + c0 + q + u] = v;
+                    if (t != yb && c0 + r < n && r0 + q + u < n) D[(c0 + r) * ld + r0 + q + u] = v;
+                }
+            }
         }
     }
 }
 
 hipError_t launch_write_probe(float *D, int64_t n, int64_t ld, float v, hipStream_t s) {
-    dim3 grid((unsigned)((n + kT * kCT - 1) / (kT * kCT)), (unsigned)((n + kT - 1) / kT));
+    const int64_t nT = (n + kT - 1) / kT;
+    dim3 grid((unsigned)((nT + kCT - 1) / kCT), (unsigned)nT);
     hipLaunchKernelGGL(k_write_probe, grid, dim3(256), 0, s, D, n, ld, v);
     return hipGetLastError();
 }
@@ -357,15 +413,16 @@ hipError_t launch_dist_l2_f32(const float *X, int64_t n, int32_t dim, float *D, 
                               float *mean, hipStream_t s) {
     hipLaunchKernelGGL(k_center_mean, dim3(dim), dim3(256), 0, s, X, n, dim, mean);
     if (dim <= kSD) {
-        dim3 grid((unsigned)((n + kT * kCT - 1) / (kT * kCT)), (unsigned)((n + kT - 1) / kT));
+        const int64_t nT = (n + kT - 1) / kT;
+        dim3 grid((unsigned)((nT + kCT - 1) / kCT), (unsigned)nT);
         if (dim <= 16)
-            hipLaunchKernelGGL(k_dist_l2_f32_strip<16>, grid, dim3(256), 0, s, X,
+            hipLaunchKernelGGL(k_dist_l2_f32_upper<16>, grid, dim3(256), 0, s, X,
                                (const float *)mean, n, dim, D, ld);
         else if (dim <= 32)
-            hipLaunchKernelGGL(k_dist_l2_f32_strip<32>, grid, dim3(256), 0, s, X,
+            hipLaunchKernelGGL(k_dist_l2_f32_upper<32>, grid, dim3(256), 0, s, X,
                                (const float *)mean, n, dim, D, ld);
         else
-            hipLaunchKernelGGL(k_dist_l2_f32_strip<64>, grid, dim3(256), 0, s, X,
+            hipLaunchKernelGGL(k_dist_l2_f32_upper<64>, grid, dim3(256), 0, s, X,
                                (const float *)mean, n, dim, D, ld);
     } else {
         dim3 grid((unsigned)((n + kT - 1) / kT), (unsigned)((n + kT - 1) / kT));
