@@ -135,6 +135,25 @@ def test_long_chunks_prefetching_loop(n, chunk, variant):
     _check_same(res, ref, 6)
 
 
+_MANY_SEG = {}
+
+
+@pytest.mark.parametrize("chunk", [4096, 4200])
+def test_long_chunks_many_segments(chunk):
+    """FastPAM2 over long chunks holding many segments (k = 40: about 40
+    segment values per wave and chunk, several times the per-wave ring of P
+    values that the pass's writer wave drains): bit-exact against the
+    oracle's FastPAM2 reading, with two chunks (ragged second) and one."""
+    _say("long_chunk_many_segments", chunk)
+    if not _MANY_SEG:
+        X, D = _int_case(4200, 4209)
+        _MANY_SEG["X"] = X
+        _MANY_SEG["ref"] = oracle.pam(40, D=D, variant=oracle.FASTPAM2)
+    res = px().fit(_t(_MANY_SEG["X"]), 40, trace=True, chunk=chunk, variant="fastpam2")
+    assert res.stats["chunk"] == chunk
+    _check_same(res, _MANY_SEG["ref"], 40)
+
+
 def test_chunk_tuning_keeps_results():
     """Chunk tuning times the pass for several chunk lengths and keeps the
     fastest; on integer distances every chunking gives the same sums, so the
