@@ -71,7 +71,9 @@ extern "C" {
                            eager application runs over the whole device under a
                            cooperative launch, or in one work-group when the
                            device has none or the environment sets
-                           PAMX_COOPERATIVE=0 (equal results either way) */
+                           PAMX_COOPERATIVE=0 (equal results either way);
+                           PAMX_EAGER_GRID=g caps the cooperative grid at g
+                           work-groups (equal results) */
 #define PAMX_FASTERPAM 3 /* FasterPAM (Alg. 4, Sec. 3.2): the candidates are
                             visited in index order, cyclically; each takes its
                             best slot (smallest on ties) and is swapped in at

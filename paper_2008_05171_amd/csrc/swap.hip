@@ -548,6 +548,22 @@ __device__ __forceinline__ bool cache_update_o1(int slot, T dnew, int32_t &nr, i
     return false;
 }
 
+// The same rule written as selects, for caches held in register arrays
+// (conditional stores through references would keep such arrays in memory).
+template <typename T>
+__device__ __forceinline__ bool cache_update_o1_sel(int slot, T dnew, int32_t &nr, int32_t &sc,
+                                                    T &dn, T &ds) {
+    const bool rescan = nr == slot || sc == slot;
+    const bool first = !rescan && lt2(dnew, slot, dn, nr);
+    const bool second = !rescan && !first && lt2(dnew, slot, ds, sc < 0 ? INT_MAX : sc);
+    const int32_t nr1 = first ? slot : nr;
+    const int32_t sc1 = first ? nr : (second ? slot : sc);
+    const T dn1 = first ? dnew : dn;
+    const T ds1 = first ? dn : (second ? dnew : ds);
+    nr = nr1; sc = sc1; dn = dn1; ds = ds1;
+    return rescan;
+}
+
 // One wave per listed object (the list order varies, each result does not).
 // Up to kRsMed medoids, the list of medoids is staged in LDS first, so each
 // step of a rescan waits on one global load (the row entry), not two.
@@ -1945,6 +1961,155 @@ __global__ __launch_bounds__(kEgT) void k_eager_grid(
     }
 }
 
+// The same visits with each thread's objects held in registers (at most
+// R per thread; the host picks R >= n / (grid * kEgT)).  An object's
+// caches are read once per search and written back at its end; per visit a
+// thread loads only its objects' entries of the candidate's row, all
+// together, and the update reuses them.  Rescans still write the caches to
+// memory (by a wave of the owner's work-group); the owner reloads those
+// objects after the work-group barrier that follows the rescans.  All
+// sums keep the order of k_eager_grid: the same decisions, bit for bit.
+constexpr int kEgR = 16;   // largest R
+template <typename T, int R>
+__global__ __launch_bounds__(kEgT) void k_eager_grid_r(
+    const T *__restrict__ D, int64_t ld, int64_t n, int32_t k, int32_t *__restrict__ med,
+    uint8_t *__restrict__ is_med, int32_t *__restrict__ near, int32_t *__restrict__ sec,
+    T *__restrict__ dn, T *__restrict__ ds, const AccT<T> *__restrict__ slot_v,
+    const int32_t *__restrict__ slot_c, int32_t *__restrict__ order, AccT<T> *__restrict__ red,
+    DevState *__restrict__ st, pamx_swap_record *__restrict__ trace) {
+    using A = AccT<T>;
+    namespace cg = cooperative_groups;
+    cg::grid_group grid = cg::this_grid();
+    if (st->done) return;
+    __shared__ int32_t rl[kEgT * R];
+    __shared__ int32_t nres;
+    __shared__ A tot_s;
+    __shared__ int32_t smed[kRsMed];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int G = gridDim.x;
+    const bool lmed = k <= kRsMed;
+    if (lmed)
+        for (int j = t; j < k; j += kEgT) smed[j] = med[j];
+    A thr;
+    if constexpr (std::is_same<T, float>::value) thr = -st->margin; else thr = 0;
+    int cnt = 0;
+    for (int i = blockIdx.x * kEgT + t; i < k; i += G * kEgT) {
+        const A vi = slot_v[i];
+        if (!(slot_c[i] != INT_MAX && vi < thr)) continue;
+        int r = 0;
+        for (int j = 0; j < k; ++j) {
+            const A vj = slot_v[j];
+            if (slot_c[j] != INT_MAX && vj < thr && lt2(vj, j, vi, i)) ++r;
+        }
+        order[r] = i;
+    }
+    for (int i = t; i < k; i += kEgT) cnt += (slot_c[i] != INT_MAX && slot_v[i] < thr) ? 1 : 0;
+    const int m = block_sum<int, kEgT>(cnt);
+    const int64_t stride = (int64_t)G * kEgT;
+    const int64_t o0 = (int64_t)blockIdx.x * kEgT + t;
+    int32_t rn[R], rsc[R];
+    T rdn[R], rds[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int64_t o = min(o0 + j * stride, n - 1);   // clamped: entries past n are unused
+        rn[j] = near[o]; rsc[j] = sec[o]; rdn[j] = dn[o]; rds[j] = ds[o];
+    }
+    grid.sync();
+    int applied = 0, par = 0;
+    for (int r = 0; r < m; ++r) {
+        const int i = order[r];
+        const int c = slot_c[i];
+        bool taken;
+        if (lmed) {
+            int hit = 0;
+            for (int jj = t; jj < k; jj += kEgT) hit |= (smed[jj] == c);
+            taken = __syncthreads_or(hit) != 0;
+        } else {
+            taken = is_med[c] != 0;
+        }
+        if (taken) continue;
+        const T *rowc = D + (int64_t)c * ld;
+        T dv[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) dv[j] = rowc[min(o0 + j * stride, n - 1)];
+        A s = 0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (o0 + j * stride < n) {
+                if (rn[j] == i) s += (A)vmin(dv[j], rds[j]) - (A)rdn[j];   // cases (b1), (b2)
+                else s += (A)vmin(dv[j], rdn[j]) - (A)rdn[j];               // cases (a), (c)
+            }
+        }
+        s = block_sum<A, kEgT>(s);
+        A *rb = red + (int64_t)par * kEgMax;
+        par ^= 1;
+        if (t == 0) rb[blockIdx.x] = s;
+        grid.sync();
+        if (wv == 0) {
+            A x = 0;
+            for (int j = lane; j < G; j += 64) x += rb[j];
+            for (int w = 32; w >= 1; w >>= 1) x += __shfl_xor(x, w);
+            if (lane == 0) tot_s = x;
+        }
+        __syncthreads();
+        const A tot = tot_s;
+        if (!(tot < thr)) continue;
+        if (blockIdx.x == 0 && t == 0) {
+            const int old = med[i];
+            is_med[old] = 0;
+            is_med[c] = 1;
+            med[i] = c;
+            if constexpr (std::is_same<T, float>::value) st->td += tot; else { st->td_i += tot; st->td = (double)st->td_i; }
+            if (trace && st->swaps < st->trace_cap) trace[st->swaps] = pamx_swap_record{i, c, (double)tot};
+            st->swaps += 1;
+        }
+        if (lmed) {
+            if (t == 0) smed[i] = c;
+        } else {
+            grid.sync();   // med and is_med from work-group 0 before the rescans
+        }
+        if (t == 0) nres = 0;
+        __syncthreads();
+        uint32_t resc = 0;   // bit j: object j was listed for a rescan
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int64_t o = o0 + j * stride;
+            if (cache_update_o1_sel<T>(i, dv[j], rn[j], rsc[j], rdn[j], rds[j]) && o < n) {
+                rl[atomicAdd(&nres, 1)] = (int32_t)o;
+                resc |= 1u << j;
+            }
+        }
+        __syncthreads();
+        const int mr = nres;
+        for (int idx = wv; idx < mr; idx += kEgT / 64) {
+            const int64_t q = rl[idx];
+            const Top2<T> tt = lmed ? wave_scan_medoids<T>(D, ld, k, smed, q, lane)
+                                    : wave_scan_medoids<T>(D, ld, k, med, q, lane);
+            if (lane == 0) store_top2<T>(tt, q, near, sec, dn, ds);
+        }
+        __syncthreads();
+        if (resc) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                if ((resc >> j) & 1u) {
+                    const int64_t o = o0 + j * stride;
+                    rn[j] = near[o]; rsc[j] = sec[o]; rdn[j] = dn[o]; rds[j] = ds[o];
+                }
+            }
+        }
+        ++applied;
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int64_t o = o0 + j * stride;
+        if (o < n) { near[o] = rn[j]; sec[o] = rsc[j]; dn[o] = rdn[j]; ds[o] = rds[j]; }
+    }
+    if (blockIdx.x == 0 && t == 0) {
+        st->iter += 1;
+        if (applied == 0) st->done = 1;
+    }
+}
+
 // Grid of k_eager_grid for n objects on the current device: one work-group
 // per 256 objects, at most what can be resident at once (a cooperative
 // launch requires it) and kEgMax; 0 if the device has no cooperative launch.
@@ -1958,6 +2123,11 @@ static int32_t eager_grid_t(int64_t n) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_eager_grid<T>, kEgT, 0) != hipSuccess)
         return 0;
+    int per_r = 0;   // the register forms' largest LDS use
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_r, k_eager_grid_r<T, kEgR>, kEgT, 0) !=
+        hipSuccess)
+        return 0;
+    if (per_r < per) per = per_r;
     int64_t g = (n + kEgT - 1) / kEgT;
     const int64_t cap = (int64_t)cus * per;
     if (g > cap) g = cap;
@@ -1966,6 +2136,12 @@ static int32_t eager_grid_t(int64_t n) {
     // workload 128 work-groups (about three objects per thread) beat 391 (one
     // each): SWAP phase 139.0 -> 134.8 ms per fit; 64: 136.6, 256: 136.3
     if (g > kEgCap) g = kEgCap;
+    // PAMX_EAGER_GRID=g caps the grid further (equal results: the visits and
+    // sums do not depend on it; lets small inputs take every register form)
+    if (const char *e = std::getenv("PAMX_EAGER_GRID")) {
+        const long c = std::strtol(e, nullptr, 10);
+        if (c > 0 && g > c) g = c;
+    }
     return (int32_t)(g < 1 ? 0 : g);
 }
 int32_t eager_grid(int64_t n, int32_t dtype) {
@@ -2185,8 +2361,15 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
             pamx_swap_record *a_tr = trace;
             void *args[] = {&a_D, &a_ld, &a_n, &a_k, &a_med, &a_is_med, &a_near, &a_sec,
                             &a_dn, &a_ds, &a_sv, &a_sc, &a_order, &a_red, &a_st, &a_tr};
-            const hipError_t e = hipLaunchCooperativeKernel(
-                reinterpret_cast<const void *>(k_eager_grid<T>), dim3(L.eg), dim3(kEgT), args, 0, s);
+            // objects held in registers when every thread owns at most kEgR
+            const int64_t per_t = (n + (int64_t)L.eg * kEgT - 1) / ((int64_t)L.eg * kEgT);
+            const void *kern = reinterpret_cast<const void *>(k_eager_grid<T>);
+            if (per_t <= 1) kern = reinterpret_cast<const void *>(k_eager_grid_r<T, 1>);
+            else if (per_t <= 2) kern = reinterpret_cast<const void *>(k_eager_grid_r<T, 2>);
+            else if (per_t <= 4) kern = reinterpret_cast<const void *>(k_eager_grid_r<T, 4>);
+            else if (per_t <= 8) kern = reinterpret_cast<const void *>(k_eager_grid_r<T, 8>);
+            else if (per_t <= kEgR) kern = reinterpret_cast<const void *>(k_eager_grid_r<T, kEgR>);
+            const hipError_t e = hipLaunchCooperativeKernel(kern, dim3(L.eg), dim3(kEgT), args, 0, s);
             if (e != hipSuccess) return e;
         } else {
             hipLaunchKernelGGL(k_eager_apply<T>, dim3(1), dim3(1024), 0, s, D, ld, n, k, medoids,

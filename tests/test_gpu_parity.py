@@ -226,6 +226,36 @@ def test_fastpam2_one_workgroup_apply_equals_grid(seed, n, k, hi, monkeypatch):
     _check_same(one, ref, k)
 
 
+_EG_CASES = {}
+
+
+@pytest.mark.parametrize("case,cap", [("n2000", 4), ("n2000", 8), ("n4200", 1), ("n4200", 2),
+                                      ("n4200", 4), ("n4200", 8)])
+def test_fastpam2_eager_register_forms(case, cap, monkeypatch):
+    """The cooperative eager apply holds each thread's objects in registers,
+    in forms for 1, 2, 4, 8 and 16 objects per thread, and reads them from
+    memory at every visit above that.  Capping the grid (PAMX_EAGER_GRID)
+    sends small inputs through each form: n = 2000 on 4 and 8 work-groups
+    (2 and 1 objects per thread), n = 4200 on 1, 2, 4 and 8 (17: the memory
+    form, then 9, 5, 3: the 16, 8 and 4 forms).  Bit-exact against the
+    oracle's FastPAM2 reading on integer distances."""
+    _say("fastpam2_eager_forms", case, cap)
+    if case not in _EG_CASES:
+        if case == "n2000":
+            X, D = _int_case(2000, 25, hi=1000)
+            _EG_CASES[case] = (X, oracle.pam(40, D=D, variant=oracle.FASTPAM2))
+        else:
+            if not _MANY_SEG:
+                X, D = _int_case(4200, 4209)
+                _MANY_SEG["X"] = X
+                _MANY_SEG["ref"] = oracle.pam(40, D=D, variant=oracle.FASTPAM2)
+            _EG_CASES[case] = (_MANY_SEG["X"], _MANY_SEG["ref"])
+    X, ref = _EG_CASES[case]
+    monkeypatch.setenv("PAMX_EAGER_GRID", str(cap))
+    res = px().fit(_t(X), 40, variant="fastpam2", trace=True)
+    _check_same(res, ref, 40)
+
+
 def test_fastpam2_one_workgroup_apply_float(monkeypatch):
     """FP32 matrix: the two forms add the re-score sums in different orders,
     so only rounding may differ; the swaps are the same."""
