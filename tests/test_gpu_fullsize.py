@@ -419,6 +419,29 @@ def test_clara256_int_bitexact():
     assert res.best == int(np.argmin(res.td_full))
 
 
+def test_clara256_int_all_instances():
+    """Every one of the 256 instances on the integer pool against the
+    oracle's record (tests/golden/clara256_int_reference.json, written by
+    make_clara256_reference.py from the oracle alone): the same medoids in
+    the same slots, the same sample TD and the same TD over all 1e6 points,
+    and the smallest full TD picked."""
+    import json
+    import os
+    rec = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "clara256_int_reference.json")))["instances"]
+    assert [r["j"] for r in rec] == list(range(256))
+    Xi = np.rint(datagen.workload_gmm8_pool() * 16.0).astype(np.int32)
+    _say("clara256 int, all instances", Xi.shape)
+    off, idx, ks, res, _ = _clara(Xi)
+    med = [m.cpu().numpy().tolist() for m in res.medoids]
+    bad = [r["j"] for r in rec
+           if med[r["j"]] != r["medoids"]
+           or res.td_sample[r["j"]] != r["td_sample"] or res.td_full[r["j"]] != r["td_full"]]
+    assert not bad, bad[:10]
+    tdf = np.array([r["td_full"] for r in rec])
+    assert res.best == int(np.argmin(tdf))
+
+
 def test_clara256_float():
     X = datagen.workload_gmm8_pool()
     _say("clara256 float", X.shape)
