@@ -98,14 +98,17 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     const bool p2 = opt && opt->variant == PAMX_FASTPAM2;
     if (opt && opt->variant == PAMX_FASTERPAM) {
         // largest window: the requested width rounded up to whole tiles, else
-        // 16 tiles; the pass is chunked for about two work-groups per compute
-        // unit on a one-tile window (the width after a swap)
+        // 16 tiles; the pass is chunked for about one work-group per compute
+        // unit on a one-tile window (the width after a swap): 256 chunks of
+        // eight-row blocks measured 8 % faster than 512 (at most n / 64) of
+        // four-row blocks at n = 20000 (smaller partials for the merge) and
+        // the same at n = 100000
         int64_t m = (opt->window > 0) ? (opt->window + L->tile - 1) / L->tile : 16;
         if (m < 1) m = 1;
         if (m > L->n_ctiles) m = L->n_ctiles;
         if (m > 256) m = 256;
         L->fw = (int32_t)(m * L->tile);
-        int64_t Q = 512;
+        int64_t Q = 256;
         const int64_t qmax = (n + 63) / 64;
         if (Q > qmax) Q = qmax;
         if (Q < 1) Q = 1;

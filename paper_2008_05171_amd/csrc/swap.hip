@@ -798,7 +798,7 @@ __device__ __forceinline__ int64_t p_index(int64_t rows, int tw_log2, int64_t ro
 // segments into P[i][c].  WIN (FasterPAM) evaluates the candidate window
 // [fw_base, fw_end) of the state; the partials are indexed relative to
 // fw_base (ncp is then the window width).
-template <typename T, int VEC, bool P2, bool PF = false>
+template <typename T, int VEC, bool P2, bool PF = false, int UB = 4>
 __device__ __forceinline__ void pass_tile(
     int tile, int q, int64_t cb, int64_t ce, const T *__restrict__ D, int64_t ld, int64_t n,
     const int32_t *__restrict__ srow, const T *__restrict__ sdn, const T *__restrict__ sds,
@@ -808,10 +808,11 @@ __device__ __forceinline__ void pass_tile(
     using A = AccT<T>;
     constexpr int kTwLog2 = VEC == 4 ? 10 : 8;   // log2(kWG * VEC)
     static_assert(kWG * VEC == (1 << kTwLog2), "pass tile width");
-    // four rows in flight per lane: measured faster than eight or sixteen,
-    // and than issuing the next rows before the current ones are summed,
-    // for a 20000 x 20000 FP32 matrix
-    constexpr int U = 4;
+    // UB rows in flight per lane: four for the full passes (measured faster
+    // than eight or sixteen on a 20000 x 20000 FP32 matrix), eight for the
+    // FasterPAM window pass, whose short chunks are bound by the latency of
+    // each block of rows
+    constexpr int U = UB;
     const int64_t a = (int64_t)q * L;
     const int64_t b = min(a + (int64_t)L, n);
     const int64_t cr = ((int64_t)tile * kWG + threadIdx.x) * VEC;   // partial column
@@ -1005,8 +1006,8 @@ __global__ __launch_bounds__(kWG) PAMX_PASS_ATTR void k_swap_pass(
         const int64_t cb = st->fw_base, ce = st->fw_end;
         const int nt = (int)((ce - cb + kWG * VEC - 1) / (kWG * VEC));
         for (int t = 0; t < nt; ++t)
-            pass_tile<T, VEC, false>(t, blockIdx.y, cb, ce, D, ld, n, srow, sdn, sds, seg_off, cdn,
-                                     cinfo, L, ncp, part, part_i, P, prows);
+            pass_tile<T, VEC, false, false, 8>(t, blockIdx.y, cb, ce, D, ld, n, srow, sdn, sds,
+                                               seg_off, cdn, cinfo, L, ncp, part, part_i, P, prows);
     } else {
         pass_tile<T, VEC, P2, PF>(blockIdx.x, blockIdx.y, 0, nc, D, ld, n, srow, sdn, sds, seg_off,
                                   cdn, cinfo, L, ncp, part, part_i, P, prows);
