@@ -162,7 +162,7 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
     L->rlist = take((size_t)n * 4);
     L->cl_v = take(1024 * 8);
     L->cl_i = take(1024 * 4);
-    L->egred = p2 ? take(2 * 1024 * 8) : SIZE_MAX;
+    L->egred = p2 ? take(2 * 1024 * 8 + 256) : SIZE_MAX;   // sums of two visits + barrier count
     // best-candidate scan: about 4096 work-groups in all, at least 1024
     // candidates each, at most 32 ranges per slot
     {
@@ -828,6 +828,7 @@ int swap_impl(const T *D, int64_t ld, const Layout &L_in, int32_t k, const pamx_
     HIP_TRY(enqueue_finalize<T>(D, ld, L, medoids, labels, ws, s));
     rc = read_state(L, ws, s, &st);
     if (rc) return rc;
+    if (st.sync_err) return fail(PAMX_ERR_HIP, "eager apply: a grid barrier wait expired");
     if (td) *td = st.td;
     if (stats) {
         stats->iterations = st.iter;

@@ -82,6 +82,7 @@ struct alignas(64) DevState {
     long long fw_end;
     int32_t fw_tiles;    // its width in candidate tiles
     long long fp_cols;   // candidate columns scored by the window passes
+    int32_t sync_err;    // a bounded grid-barrier wait of the eager apply expired
 };
 
 // Lexicographic "a is better than b" on (value, slot, candidate).

@@ -1971,6 +1971,7 @@ __global__ __launch_bounds__(kEgT) void k_eager_grid(
 // objects after the work-group barrier that follows the rescans.  All
 // sums keep the order of k_eager_grid: the same decisions, bit for bit.
 constexpr int kEgR = 16;   // largest R
+constexpr int kEgSpin = 1 << 24;   // polls (about 64 cycles each) before a barrier wait fails
 template <typename T, int R>
 __global__ __launch_bounds__(kEgT) void k_eager_grid_r(
     const T *__restrict__ D, int64_t ld, int64_t n, int32_t k, int32_t *__restrict__ med,
@@ -2006,6 +2007,10 @@ __global__ __launch_bounds__(kEgT) void k_eager_grid_r(
     }
     for (int i = t; i < k; i += kEgT) cnt += (slot_c[i] != INT_MAX && slot_v[i] < thr) ? 1 : 0;
     const int m = block_sum<int, kEgT>(cnt);
+    // the visits' barrier: an arrival count after the two halves of red
+    int32_t *bar = reinterpret_cast<int32_t *>(red + 2 * kEgMax);
+    if (blockIdx.x == 0 && t == 0) __hip_atomic_store(bar, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int nbar = 0;
     const int64_t stride = (int64_t)G * kEgT;
     const int64_t o0 = (int64_t)blockIdx.x * kEgT + t;
     int32_t rn[R], rsc[R];
@@ -2044,11 +2049,27 @@ __global__ __launch_bounds__(kEgT) void k_eager_grid_r(
         s = block_sum<A, kEgT>(s);
         A *rb = red + (int64_t)par * kEgMax;
         par ^= 1;
-        if (t == 0) rb[blockIdx.x] = s;
-        grid.sync();
+        // grid barrier without cache maintenance: the only data that crosses
+        // work-groups here, the sums, is written and read with device-scope
+        // atomic accesses (coherent at the device level), and the count is
+        // incremented after the sum's store has completed
+        ++nbar;
+        if (t == 0) {
+            __hip_atomic_store(&rb[blockIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);
+            __hip_atomic_fetch_add(bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int target = nbar * G;
+            int spin = 0;
+            while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (++spin > kEgSpin) { atomicOr(&st->sync_err, 1); break; }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __syncthreads();
         if (wv == 0) {
             A x = 0;
-            for (int j = lane; j < G; j += 64) x += rb[j];
+            for (int j = lane; j < G; j += 64)
+                x += __hip_atomic_load(&rb[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             for (int w = 32; w >= 1; w >>= 1) x += __shfl_xor(x, w);
             if (lane == 0) tot_s = x;
         }
