@@ -101,14 +101,19 @@ __device__ bool team_argmin3(AccT<E> &v, int &i, int &c, int T, int m, int j, in
     __shared__ int ok_s;
     unsigned long long *slot = xch + ((size_t)(2 * j + (gen & 1)) * kBTeamMax) * 2;
     if (threadIdx.x == 0) {
-        slot[2 * m] = __builtin_bit_cast(unsigned long long, v);
-        slot[2 * m + 1] = ((unsigned long long)(uint32_t)i << 32) | (uint32_t)c;
-        __threadfence();   // the post before the arrival
-        atomicAdd(&bar[j], 1);
+        // the posts and the count are device-scope atomic accesses, coherent
+        // at the device level without cache maintenance; the count is raised
+        // only after the posts' stores have completed
+        __hip_atomic_store(&slot[2 * m], __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&slot[2 * m + 1], ((unsigned long long)(uint32_t)i << 32) | (uint32_t)c,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);
+        __hip_atomic_fetch_add(&bar[j], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int want = (gen + 1) * T;
         long long spins = 0;
         int ok = 1;
-        while (__hip_atomic_load(&bar[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < want) {
+        while (__hip_atomic_load(&bar[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
             __builtin_amdgcn_s_sleep(2);
             if (++spins > kSpinMax) { ok = 0; break; }
         }
