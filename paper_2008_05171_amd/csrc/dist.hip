@@ -20,35 +20,71 @@
 namespace pamx {
 
 // ---------------------------------------------------------------- L1 int32
-// One thread computes 4 consecutive columns of one row.  Points are tiny
-// (dim is small for integer coordinates), so they are read through the cache.
+// 64-row blocks against kL1C column tiles of 64: the row and column points
+// are staged in LDS, kL1J coordinates at a time, offset by 2^31 as unsigned
+// so that |a - b| + acc is one absolute-difference instruction (v_sad_u32).
+// A thread computes 4 rows x 4 columns of a tile (rows t/16 + 16 i, columns
+// t%16 + 16 v: conflict-free LDS reads, 64-byte row pieces per store).  The
+// coordinate range check made before any distance bounds every sum below
+// INT32_MAX, so the unsigned sums are the exact distances.
+constexpr int kL1T = 64, kL1J = 64, kL1C = 4;
 __global__ __launch_bounds__(256) void k_dist_l1_i32(const int32_t *__restrict__ X, int64_t n,
                                                      int32_t dim, int32_t *__restrict__ D,
                                                      int64_t ld) {
-    const int64_t o = (int64_t)blockIdx.y * 16 + (threadIdx.x >> 4);
-    const int64_t c = ((int64_t)blockIdx.x * 16 + (threadIdx.x & 15)) * 4;
-    if (o >= n || c >= n) return;
-    int32_t acc[4] = {0, 0, 0, 0};
-    const int32_t *xo = X + o * dim;
-    for (int j = 0; j < dim; ++j) {
-        const int32_t a = xo[j];
+    __shared__ uint32_t xr[kL1T][kL1J + 1], xc[kL1T][kL1J + 1];
+    const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
+    const int64_t r0 = (int64_t)blockIdx.y * kL1T;
+    for (int ct = 0; ct < kL1C; ++ct) {
+        const int64_t c0 = ((int64_t)blockIdx.x * kL1C + ct) * kL1T;
+        if (c0 >= n) break;   // uniform over the work-group
+        uint32_t acc[4][4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            if (c + v < n) {
-                const int32_t b = X[(c + v) * dim + j];
-                acc[v] += (a > b) ? (a - b) : (b - a);
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[i][v] = 0;
+        for (int j0 = 0; j0 < dim; j0 += kL1J) {
+            const int jn = min(kL1J, dim - j0);
+            for (int e = t; e < kL1T * kL1J; e += 256) {
+                const int pnt = e / kL1J, j = e % kL1J;
+                uint32_t vr = 0x80000000u, vc = 0x80000000u;
+                if (j < jn) {
+                    if (r0 + pnt < n) vr = (uint32_t)X[(r0 + pnt) * dim + j0 + j] ^ 0x80000000u;
+                    if (c0 + pnt < n) vc = (uint32_t)X[(c0 + pnt) * dim + j0 + j] ^ 0x80000000u;
+                }
+                xr[pnt][j] = vr;
+                xc[pnt][j] = vc;
+            }
+            __syncthreads();
+            for (int j = 0; j < jn; ++j) {
+                uint32_t a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) { a[i] = xr[tr + 16 * i][j]; b[i] = xc[tc + 16 * i][j]; }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        acc[i][v] += (a[i] > b[v]) ? (a[i] - b[v]) : (b[v] - a[i]);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t r = r0 + tr + 16 * i;
+            if (r >= n) continue;
+            int32_t *row = D + r * ld;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t c = c0 + tc + 16 * v;
+                if (c < n) row[c] = (int32_t)acc[i][v];
             }
         }
     }
-    int32_t *row = D + o * ld;
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-        if (c + v < n) row[c + v] = (c + v == o) ? 0 : acc[v];
 }
 
 hipError_t launch_dist_l1_i32(const int32_t *X, int64_t n, int32_t dim, int32_t *D, int64_t ld,
                               hipStream_t s) {
-    dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n + 15) / 16));
+    const int64_t span = (int64_t)kL1T * kL1C;
+    dim3 grid((unsigned)((n + span - 1) / span), (unsigned)((n + kL1T - 1) / kL1T));
     hipLaunchKernelGGL(k_dist_l1_i32, grid, dim3(256), 0, s, X, n, dim, D, ld);
     return hipGetLastError();
 }

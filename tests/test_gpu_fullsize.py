@@ -254,6 +254,56 @@ def test_zipf32_int_fastpam2_full():
     print("TD", r.td, "swaps", m, "iterations", r.stats["iterations"], flush=True)
 
 
+def test_max_size_int_fastpam2():
+    """The largest matrix this GPU holds with room to spare: n = 200000
+    integer points (d = 32, 500 Zipf(1.1)-weighted components scaled by 4
+    and rounded), the 160 GB int32 Manhattan matrix built from the points
+    inside the fit's workspace, k = 500, BUILD + eager FastPAM2.  Every
+    64-bit offset path (rows of 800 KB, 4e10 entries) against the oracle
+    computing from the points: BUILD's TD and sampled steps, sampled swaps'
+    changes, the final TD and labels exactly, no sampled swap improving."""
+    n, k = 200000, 500
+    need = n * n * 4 + (8 << 30)
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip("needs %.0f GB of free device memory (%.0f GB free)" % (need / 1e9, free / 1e9))
+    Xi = np.rint(datagen.gaussian_mixture(n, 32, 500, seed=1006, zipf_s=1.1) * 4.0).astype(np.int32)
+    _say("max size int fastpam2", n, k)
+    Xt = torch.from_numpy(Xi).to(DEV)
+    r = px().fit(Xt, k, variant="fastpam2", trace=True)
+    assert r.rc == 0 and r.stats["swaps"] == len(r.trace) >= 1
+    torch.cuda.empty_cache()
+    rb = px().fit(Xt, k, max_iter=0)
+    bm = rb.medoids.cpu().numpy()
+    del rb
+    torch.cuda.empty_cache()
+    assert r.stats["td_build"] == oracle.td(bm, X=Xi, metric=oracle.L1)[0]
+    rng = np.random.default_rng(17)
+    for t in (0, 1, 250, k - 1):
+        _check_build_step(bm, t, _non_medoid_sample(rng, n, bm[:t], 256), exact=True, X=Xi,
+                          metric=oracle.L1)
+    meds = _medoid_sets(bm, r.trace)
+    m = len(r.trace)
+    check = sorted(set(range(3)) | set(range(m - 3, m)) |
+                   set(rng.choice(m, size=min(4, m), replace=False).tolist()))
+    for j in check:
+        if j < 0 or j >= m:
+            continue
+        slot, cand, dl = r.trace[j]
+        want = oracle.swap_list(meds[j], [cand], X=Xi, metric=oracle.L1)[0, slot]
+        assert dl == want and dl < 0, (j, dl, want)
+    final = r.medoids.cpu().numpy()
+    assert np.array_equal(final, meds[-1])
+    td_ref, lab_ref = oracle.td(final, X=Xi, metric=oracle.L1)
+    assert r.td == td_ref == _build_td_plus_changes(r, bm, Xi)
+    assert np.array_equal(r.labels.cpu().numpy(), lab_ref)
+    tab = oracle.swap_list(final, _non_medoid_sample(rng, n, final, 32), X=Xi, metric=oracle.L1)
+    assert np.nanmin(tab) >= 0
+    print("TD", r.td, "swaps", m, "iterations", r.stats["iterations"], "ms dist/build/swap",
+          r.stats["ms_dist"], r.stats["ms_build"], r.stats["ms_swap"], flush=True)
+
+
 def _build_td_plus_changes(r, bm, Xi):
     """BUILD TD plus every recorded change (integer sums: exact)."""
     return oracle.td(bm, X=Xi, metric=oracle.L1)[0] + sum(d for _, _, d in r.trace)
