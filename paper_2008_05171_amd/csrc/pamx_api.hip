@@ -3,6 +3,7 @@
 // orchestration of BUILD (Alg. 1) and SWAP (Alg. 3 / eager FastPAM2) of
 // Schubert & Rousseeuw, arXiv 2008.05171.
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <type_traits>
@@ -69,6 +70,24 @@ static int32_t auto_chunk(int64_t n, int32_t n_ctiles) {
     return (int32_t)Lc;
 }
 
+// FasterPAM window pass: chunks per work-group for window chunks of Lw
+// objects.  Short chunks are bound by the latency of their few blocks of
+// rows and the merge of their many partials, so four chunks share a
+// work-group (and one partial): SWAP phase 11.1 -> 10.5 ms at n = 20000
+// (80-object chunks).  Long chunks stream, and one chunk per work-group (its
+// four waves on the same rows, no merge through LDS) is faster: 102 against
+// 107 ms at n = 100000 (392-object chunks).
+// PAMX_FP_GROUP=1, 2 or 4 in the environment fixes it (equal results on
+// integer distances; with floating point the group sums are added in another
+// order and may round differently).
+static int32_t fp_group(int64_t Lw) {
+    if (const char *e = std::getenv("PAMX_FP_GROUP")) {
+        const int g = std::atoi(e);
+        if (g == 1 || g == 2 || g == 4) return g;
+    }
+    return Lw <= 128 ? 4 : 1;
+}
+
 int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t dtype,
                 int64_t ld, const pamx_options *opt, Layout *L, const void *D, int64_t ncand) {
     std::memset(L, 0, sizeof(*L));
@@ -117,6 +136,7 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
         if (Lw > n) Lw = n;
         L->fwL = (int32_t)Lw;
         L->fwQ = (int32_t)((n + Lw - 1) / Lw);
+        L->fwG = fp_group(Lw);
     }
 
     size_t off = 0;
@@ -183,15 +203,19 @@ int make_layout(int64_t n, int32_t k, int32_t dim, int32_t input_kind, int32_t d
 
 // The regions whose size depends on the number of object chunks Q come last,
 // so the chunk length can change between BUILD and SWAP (chunk tuning).
-static void place_tail(Layout *L, int32_t Lc, int64_t cols) {
+static void place_tail(Layout *L, int32_t Lc, int64_t cols, bool win = false) {
     if (Lc > L->n) Lc = (int32_t)L->n;
     if (Lc < 1) Lc = 1;
     L->L = Lc;
     L->Q = (int32_t)((L->n + Lc - 1) / Lc);
+    // the window pass merges fwG consecutive chunks in each work-group; the
+    // partials, DN parts and run map it leaves are per group
+    L->Qg = win ? (L->Q + L->fwG - 1) / L->fwG : L->Q;
     size_t off = L->head;
     auto take = [&](size_t bytes) { size_t o = off; off = up256(off + (bytes ? bytes : 1)); return o; };
     L->blkbase = take((size_t)L->Q * 16);            // chunk carry map
     L->cdn = take((size_t)L->Q * 2 * 8);              // DN parts of carried segments
+    L->ginfo = (win && L->fwG > 1) ? take((size_t)L->Qg * 16) : SIZE_MAX;
     L->part = take((size_t)L->Q * 4 * cols * 8);
     L->part_i = take((size_t)L->Q * cols * 4);
     // FastPAM2: one row per (chunk, segment) pair at segment + chunk (k + Q rows)
@@ -199,7 +223,7 @@ static void place_tail(Layout *L, int32_t Lc, int64_t cols) {
     L->total = off;
 }
 void set_chunk(Layout *L, int32_t Lc) { place_tail(L, Lc, L->ncp); }
-void set_window(Layout *L) { place_tail(L, L->fwL, L->fw); }
+void set_window(Layout *L) { place_tail(L, L->fwL, L->fw, true); }
 
 // Chunk lengths tried by the tuner: pass grids at or just below about 1, 1.5,
 // 2, 3, 4, 6 and 8 work-groups per compute unit.

@@ -22,6 +22,7 @@ constexpr int kWG = 256;          // threads per work-group in pass kernels
 #endif
 constexpr int32_t kPfChunk = PAMX_PF_CHUNK;
 constexpr int kObjBlk = 256;      // objects per block in segment kernels
+constexpr int kFpGroup = kWG / 64; // FasterPAM window pass: most chunks per work-group (one per wave)
 constexpr int kMaxK = 16000;      // largest k accepted (slot histogram and offsets in LDS)
 constexpr int kBMaxDim = 16;      // batched instances: largest point dimension
 constexpr int kBMaxK = 256;       // batched instances: largest k
@@ -173,11 +174,13 @@ struct Layout {
     int32_t n_ctiles;    // candidate tiles
     int32_t L;           // objects per pass work-group (chunk)
     int32_t Q;           // object chunks
+    int32_t Qg;          // FasterPAM window pass: groups of fwG chunks (= Q otherwise)
     int64_t ncp;         // padded candidate count = n_ctiles * tile
     int32_t n_oblk;      // object blocks of kObjBlk
     int32_t n_mwg;       // merge work-groups = ceil(n / kWG)
     int32_t fw;          // FasterPAM: largest window (a multiple of tile), or 0
     int32_t fwL, fwQ;    // FasterPAM: object chunk length and count of the window pass
+    int32_t fwG;         // FasterPAM: chunks per work-group of the window pass (1, 2 or 4)
     int32_t eg;          // FastPAM2: grid of the cooperative eager apply, 0 = one work-group
     int32_t sbS;         // FastPAM2: candidate ranges per slot in the best-candidate scan
     size_t esz;          // element size of D (4)
@@ -188,6 +191,7 @@ struct Layout {
     size_t near, sec, dn, ds, is_med;
     size_t srow, sdn, sds;
     size_t blkcnt, blkbase, seg_off, cdn;
+    size_t ginfo;        // FasterPAM window pass: run map of each chunk group, or SIZE_MAX
     size_t tdp;          // per-block sums of dn and ds (2 per block of kObjBlk objects)
     size_t segtot;       // objects per slot (k)
     size_t part, part_i;

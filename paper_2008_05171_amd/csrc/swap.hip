@@ -535,24 +535,12 @@ __global__ __launch_bounds__(256) void k_check_medoids(const int32_t *__restrict
 // An object that keeps both its nearest and its second medoid only compares
 // against the new one (O(1)); an object that lost one of them needs all k
 // medoids again and is returned as "rescan" (done by wave_scan_medoids).
+// Written as selects: conditional stores through the references made the
+// compiler keep the four values in scratch memory (a store and a reload on
+// every update) and, for caches held in register arrays, the whole arrays.
 template <typename T>
 __device__ __forceinline__ bool cache_update_o1(int slot, T dnew, int32_t &nr, int32_t &sc, T &dn,
                                                 T &ds) {
-    if (nr == slot || sc == slot) return true;
-    if (lt2(dnew, slot, dn, nr)) {
-        sc = nr; ds = dn;
-        nr = slot; dn = dnew;
-    } else if (lt2(dnew, slot, ds, sc < 0 ? INT_MAX : sc)) {
-        sc = slot; ds = dnew;
-    }
-    return false;
-}
-
-// The same rule written as selects, for caches held in register arrays
-// (conditional stores through references would keep such arrays in memory).
-template <typename T>
-__device__ __forceinline__ bool cache_update_o1_sel(int slot, T dnew, int32_t &nr, int32_t &sc,
-                                                    T &dn, T &ds) {
     const bool rescan = nr == slot || sc == slot;
     const bool first = !rescan && lt2(dnew, slot, dn, nr);
     const bool second = !rescan && !first && lt2(dnew, slot, ds, sc < 0 ? INT_MAX : sc);
@@ -795,9 +783,7 @@ __device__ __forceinline__ int64_t p_index(int64_t rows, int tw_log2, int64_t ro
 // Output per candidate and chunk: part[q][0] = A partial, [1] head carry,
 // [2] tail carry, [3] best value over segments complete in the chunk, and
 // part_i = its slot.  P2 (FastPAM2) also stores M_i - DN_i of complete
-// segments into P[i][c].  WIN (FasterPAM) evaluates the candidate window
-// [fw_base, fw_end) of the state; the partials are indexed relative to
-// fw_base (ncp is then the window width).
+// segments into P[i][c].  Candidates [cb, ce), partials indexed from cb.
 template <typename T, int VEC, bool P2, bool PF = false, int UB = 4>
 __device__ __forceinline__ void pass_tile(
     int tile, int q, int64_t cb, int64_t ce, const T *__restrict__ D, int64_t ld, int64_t n,
@@ -808,10 +794,8 @@ __device__ __forceinline__ void pass_tile(
     using A = AccT<T>;
     constexpr int kTwLog2 = VEC == 4 ? 10 : 8;   // log2(kWG * VEC)
     static_assert(kWG * VEC == (1 << kTwLog2), "pass tile width");
-    // UB rows in flight per lane: four for the full passes (measured faster
-    // than eight or sixteen on a 20000 x 20000 FP32 matrix), eight for the
-    // FasterPAM window pass, whose short chunks are bound by the latency of
-    // each block of rows
+    // UB rows per block: four (measured faster than eight or sixteen on a
+    // 20000 x 20000 FP32 matrix)
     constexpr int U = UB;
     const int64_t a = (int64_t)q * L;
     const int64_t b = min(a + (int64_t)L, n);
@@ -984,6 +968,13 @@ __device__ __forceinline__ void pass_tile(
     }
 }
 
+// WIN: the FasterPAM window pass over long chunks (one work-group per chunk
+// over every tile of the window [fw_base, fw_end), partials indexed from
+// fw_base; ncp is then the window width).  Its rows go in blocks of eight,
+// the next block issued before the current one is summed: 28.7 -> 26.0 us
+// per pass at n = 20000 and 106 -> 92 us at n = 100000 against blocks
+// loaded one at a time (prefetched blocks of four were slower than either).
+// Short chunks take k_fp_pass instead.
 template <typename T, int VEC, bool P2, bool WIN, bool PF = false>
 __global__ __launch_bounds__(kWG) PAMX_PASS_ATTR void k_swap_pass(
     const T *__restrict__ D, int64_t ld, int64_t n, int64_t nc, int32_t k,
@@ -998,19 +989,219 @@ __global__ __launch_bounds__(kWG) PAMX_PASS_ATTR void k_swap_pass(
         const ChunkInfo ci0 = cinfo[blockIdx.y];
         const int32_t r0 = srow[(int64_t)blockIdx.y * L];
         if (st->done || r0 < 0 || ci0.sa < 0) return;   // rows and slots are never negative
+        pass_tile<T, VEC, P2, PF>(blockIdx.x, blockIdx.y, 0, nc, D, ld, n, srow, sdn, sds, seg_off,
+                                  cdn, cinfo, L, ncp, part, part_i, P, prows);
     } else {
         if (st->done) return;
-    }
-    if constexpr (WIN) {
-        // one work-group per object chunk, over every tile of the window
         const int64_t cb = st->fw_base, ce = st->fw_end;
         const int nt = (int)((ce - cb + kWG * VEC - 1) / (kWG * VEC));
         for (int t = 0; t < nt; ++t)
-            pass_tile<T, VEC, false, false, 8>(t, blockIdx.y, cb, ce, D, ld, n, srow, sdn, sds,
-                                               seg_off, cdn, cinfo, L, ncp, part, part_i, P, prows);
-    } else {
-        pass_tile<T, VEC, P2, PF>(blockIdx.x, blockIdx.y, 0, nc, D, ld, n, srow, sdn, sds, seg_off,
-                                  cdn, cinfo, L, ncp, part, part_i, P, prows);
+            pass_tile<T, VEC, false, true, 8>(t, blockIdx.y, cb, ce, D, ld, n, srow, sdn, sds,
+                                              seg_off, cdn, cinfo, L, ncp, part, part_i, P, prows);
+    }
+}
+
+// ---- FasterPAM window pass.  The window [fw_base, fw_end) is short after a
+// swap (one tile), so the pass is spread over the objects.  A work-group
+// takes G consecutive chunks g * G + u, each with 4 / G of its waves (wave w:
+// chunk u = w / (4 / G), column block w % (4 / G)), over the columns
+// x * W + [0, W) of every window tile, W = 256 * VEC / G (rows as in
+// pass_tile: blocks of eight, the next block issued before the current one
+// is summed).  The waves then merge their chunks' summaries in chunk order
+// through LDS, so the window merge reads one summary per group of G chunks:
+// part[g][0] = A, [1] = M of the group's first segment run, [2] = M of its
+// last run, [3] = best value over segments complete inside the group,
+// part_i = its slot; ginfo[g] = {first run's slot, last run's slot, kHead if
+// there is a first run, kTail if there is a last one} and cdn[2g],
+// cdn[2g + 1] their parts of DN.  A run that continues into the next group is
+// finished by the merge (k_fp_merge), exactly as for single chunks.  For
+// short chunks (latency-bound; the merge's input a quarter with G = 4); long
+// chunks take k_swap_pass<..., WIN = true>, whose waves share their rows.
+constexpr int kFpU = 8;   // rows per block of the window pass
+template <typename T, int VEC, int G>
+__global__ __launch_bounds__(kWG) PAMX_PASS_ATTR void k_fp_pass(
+    const T *__restrict__ D, int64_t ld, int64_t n, const int32_t *__restrict__ srow,
+    const T *__restrict__ sdn, const T *__restrict__ sds, const int32_t *__restrict__ seg_off,
+    const ChunkInfo *__restrict__ cinfo, int32_t L, int32_t Q, AccT<T> *__restrict__ cdn,
+    ChunkInfo *__restrict__ ginfo, AccT<T> *__restrict__ part, int32_t *__restrict__ part_i,
+    int64_t ncp, const DevState *__restrict__ st) {
+    using A = AccT<T>;
+    constexpr int U = kFpU;
+    constexpr int CW = kFpGroup / G;     // waves per chunk
+    constexpr int W = CW * 64 * VEC;     // columns per work-group and tile
+    static_assert((G == 2 || G == 4) && G * CW == kFpGroup && kFpGroup * 64 == kWG,
+                  "waves of a work-group");
+    if (st->done) return;
+    // per wave (chunk): the summary of each of the W columns, the chunk's run
+    // map and the DN parts of its first and last runs
+    __shared__ A s_a[G][W], s_bv[G][W], s_h[G][W], s_t[G][W];
+    __shared__ int32_t s_bi[G][W];
+    __shared__ ChunkInfo s_ci[G];
+    __shared__ A s_dh[G], s_dt[G];
+    const int64_t cb = st->fw_base, ce = st->fw_end;
+    const int nt = (int)((ce - cb + kWG * VEC - 1) / (kWG * VEC));   // window tiles
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int uw = wv / CW;                         // this wave's chunk in the group
+    const int li = (wv % CW) * 64 + ln;             // and its lane's column block
+    const int g = blockIdx.y;
+    const int q = g * G + uw;
+    const bool has = q < Q;
+    const int64_t a = (int64_t)q * L;
+    const int64_t b = has ? min(a + (int64_t)L, n) : a;
+    const ChunkInfo ci = has ? cinfo[q] : ChunkInfo{0, 0, 0, 0};
+    for (int t = 0; t < nt; ++t) {
+        const int64_t wcol = (int64_t)t * kWG * VEC + (int64_t)blockIdx.x * W;   // first column
+        const int64_t c0 = cb + wcol + li * VEC;
+        A accA[VEC], bv[VEC];
+        int32_t bi[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) { accA[e] = 0; bv[e] = VT<T>::acc_inf(); bi[e] = INT_MAX; }
+        if (has && c0 < ce) {
+            int s = ci.sa;
+            int64_t se = min((int64_t)ci.se0, b);
+            A M[VEC];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) M[e] = 0;
+            A dns = 0;
+            // the chunk's first and last runs go to LDS as they close (the
+            // previous tile's merge is behind the barrier that ends it); their
+            // DN parts are the same in every lane, the chunk's first lane
+            // writes them
+            auto close_seg = [&]() {
+                if (s == ci.sa && (ci.flags & kHead)) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) s_h[uw][li * VEC + e] = M[e];
+                    if (li == 0) s_dh[uw] = dns;
+                } else if (s == ci.sb && (ci.flags & kTail)) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) s_t[uw][li * VEC + e] = M[e];
+                    if (li == 0) s_dt[uw] = dns;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const A v = M[e] - dns;
+                        if (v < bv[e]) { bv[e] = v; bi[e] = s; }
+                    }
+                }
+            };
+            auto next_seg = [&](int64_t j) {
+                close_seg();
+                do { ++s; } while (seg_off[s + 1] <= j);
+                se = min((int64_t)seg_off[s + 1], b);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) M[e] = 0;
+                dns = 0;
+            };
+            auto add_row = [&](const T (&v)[VEC], T lo, T hi) {
+                dns += (A)lo;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    accA[e] += (A)vmin(v[e], lo);
+                    M[e] += (A)vmed3(v[e], lo, hi);
+                }
+            };
+            auto add_block = [&](int64_t j, const T (&v)[U][VEC], const T (&lo)[U], const T (&hi)[U]) {
+                if (j + U <= se) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) add_row(v[u], lo[u], hi[u]);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (j + u == se) next_seg(j + u);
+                        add_row(v[u], lo[u], hi[u]);
+                    }
+                }
+            };
+            auto load_block = [&](int64_t j, T (&v)[U][VEC], T (&lo)[U], T (&hi)[U]) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t o = srow[j + u];
+                    load_vec<T, VEC>(D + o * ld + c0, v[u]);
+                    lo[u] = sdn[j + u];
+                    hi[u] = sds[j + u];
+                }
+            };
+            int64_t j = a;
+            if (j + U <= b) {
+                T v[U][VEC], lo[U], hi[U];
+                load_block(j, v, lo, hi);
+                for (; j + 2 * U <= b; j += U) {
+                    T w[U][VEC], wl[U], wh[U];
+                    load_block(j + U, w, wl, wh);
+                    add_block(j, v, lo, hi);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) v[u][e] = w[u][e];
+                        lo[u] = wl[u];
+                        hi[u] = wh[u];
+                    }
+                }
+                add_block(j, v, lo, hi);
+                j += U;
+            }
+            for (; j < b; ++j) {
+                if (j == se) next_seg(j);
+                const int64_t o = srow[j];
+                T v[VEC];
+                load_vec<T, VEC>(D + o * ld + c0, v);
+                add_row(v, sdn[j], sds[j]);
+            }
+            close_seg();
+        }
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            s_a[uw][li * VEC + e] = accA[e];
+            s_bv[uw][li * VEC + e] = bv[e];
+            s_bi[uw][li * VEC + e] = bi[e];
+        }
+        // run values are read only where the run map has the run; a chunk's
+        // first lane is active whenever any column of the work-group is (its
+        // column is the work-group's first), so columns that are read have them
+        if (li == 0) s_ci[uw] = has ? ci : ChunkInfo{0, 0, 0, 0};
+        __syncthreads();
+        // the group's summary of column wcol + j: the chunks' summaries in
+        // chunk order (runs of the same slot joined, runs that end inside
+        // the group taken as complete segments)
+        for (int jj = threadIdx.x; jj < W; jj += kWG) {
+            A sa = 0, rbv = VT<T>::acc_inf(), fm = 0, fdn = 0, lm = 0, ldn = 0;
+            int32_t rbi = INT_MAX, nr = 0, fs = 0, ls = 0;
+            auto add = [&](int sl, A m, A dn) {
+                if (nr == 0) { nr = 1; fs = sl; fm = m; fdn = dn; return; }
+                if (nr == 1) {
+                    if (sl == fs) { fm += m; fdn += dn; }
+                    else { nr = 2; ls = sl; lm = m; ldn = dn; }
+                    return;
+                }
+                if (sl == ls) { lm += m; ldn += dn; return; }
+                const A v = lm - ldn;
+                if (lt2(v, ls, rbv, rbi)) { rbv = v; rbi = ls; }
+                ls = sl; lm = m; ldn = dn;
+            };
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                sa += s_a[u][jj];
+                const int32_t xi = s_bi[u][jj];
+                const A xv = s_bv[u][jj];
+                if (xi != INT_MAX && lt2(xv, xi, rbv, rbi)) { rbv = xv; rbi = xi; }
+                const ChunkInfo cu = s_ci[u];
+                if (cu.flags & kHead) add(cu.sa, s_h[u][jj], s_dh[u]);
+                if (cu.flags & kTail) add(cu.sb, s_t[u][jj], s_dt[u]);
+            }
+            const int64_t col = wcol + jj;
+            A *pq = part + (int64_t)g * 4 * ncp + col;
+            pq[0] = sa;
+            pq[1 * ncp] = fm;
+            pq[2 * ncp] = lm;
+            pq[3 * ncp] = rbv;
+            part_i[(int64_t)g * ncp + col] = rbi;
+            if (t == 0 && blockIdx.x == 0 && jj == 0) {
+                ginfo[g] = ChunkInfo{fs, ls, (nr >= 1 ? kHead : 0) | (nr == 2 ? kTail : 0), 0};
+                cdn[2 * g] = fdn;
+                cdn[2 * g + 1] = ldn;
+            }
+        }
+        __syncthreads();   // the summaries are rewritten by the next tile
     }
 }
 
@@ -1243,9 +1434,9 @@ __global__ void k_fp_init(DevState *st, int64_t n, int64_t tile, int32_t vec, lo
     }
 }
 
-// Merge of a window pass's chunk partials.  A window has few candidates and
-// many chunks, so 16 threads share a candidate: each merges a contiguous
-// group of chunks into a summary (sum of A, best complete segment, first and
+// Merge of a window pass's partials (one per group of chunks, k_fp_pass).  A
+// window has few candidates and many chunk groups, so 16 threads share a
+// candidate: each merges a contiguous range of groups into a summary (sum of A, best complete segment, first and
 // last segment run, which may continue into the neighbouring groups), and
 // the candidate's first thread combines the 16 summaries in chunk order.
 // The work-group (16 candidates) reports its first candidate at or after the
@@ -2096,7 +2287,7 @@ __global__ __launch_bounds__(kEgT) void k_eager_grid_r(
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int64_t o = o0 + j * stride;
-            if (cache_update_o1_sel<T>(i, dv[j], rn[j], rsc[j], rdn[j], rds[j]) && o < n) {
+            if (cache_update_o1<T>(i, dv[j], rn[j], rsc[j], rdn[j], rds[j]) && o < n) {
                 rl[atomicAdd(&nres, 1)] = (int32_t)o;
                 resc |= 1u << j;
             }
@@ -2178,7 +2369,7 @@ struct SwapPtrs {
     uint8_t *is_med;
     AccT<T> *cdn, *part, *wg_v, *P, *cand_a, *slot_v, *tdp;
     int32_t *segtot;
-    ChunkInfo *cinfo;
+    ChunkInfo *cinfo, *ginfo;
     DevState *st;
 };
 
@@ -2199,6 +2390,7 @@ static SwapPtrs<T> ptrs(const Layout &L, void *ws) {
     p.segtot = reinterpret_cast<int32_t *>(w + L.segtot);
     p.seg_off = reinterpret_cast<int32_t *>(w + L.seg_off);
     p.cinfo = reinterpret_cast<ChunkInfo *>(w + L.blkbase);
+    p.ginfo = (L.ginfo != SIZE_MAX) ? reinterpret_cast<ChunkInfo *>(w + L.ginfo) : nullptr;
     p.cdn = reinterpret_cast<AccT<T> *>(w + L.cdn);
     p.part = reinterpret_cast<AccT<T> *>(w + L.part);
     p.part_i = reinterpret_cast<int32_t *>(w + L.part_i);
@@ -2269,10 +2461,26 @@ static int64_t p_rows(const Layout &L) { return (int64_t)L.k + L.Q; }
 static int32_t tw_log2(const Layout &L) { return L.vec == 4 ? 10 : 8; }
 
 // win: FasterPAM window pass (L placed by set_window: L.L, L.Q are the
-// window chunking, the partials have L.fw columns)
+// window chunking, L.Qg its groups, the partials have L.fw columns)
 template <typename T>
 static void enqueue_pass(const T *D, int64_t ld, const Layout &L, const SwapPtrs<T> &p, bool p2,
                          hipStream_t s, bool win = false) {
+    if (win && L.fwG > 1) {
+        const dim3 wgrid(L.fwG, L.Qg);   // G column blocks per tile, Qg groups
+#define PAMX_FPPASS(VEC, G)                                                                    \
+        hipLaunchKernelGGL((k_fp_pass<T, VEC, G>), wgrid, dim3(kWG), 0, s, D, ld, L.n,         \
+                           (const int32_t *)p.srow, (const T *)p.sdn, (const T *)p.sds,        \
+                           (const int32_t *)p.seg_off, (const ChunkInfo *)p.cinfo, L.L, L.Q,   \
+                           p.cdn, p.ginfo, p.part, p.part_i, (int64_t)L.fw,                    \
+                           (const DevState *)p.st)
+        if (L.vec == 4) {
+            if (L.fwG == 4) PAMX_FPPASS(4, 4); else PAMX_FPPASS(4, 2);
+        } else {
+            if (L.fwG == 4) PAMX_FPPASS(1, 4); else PAMX_FPPASS(1, 2);
+        }
+#undef PAMX_FPPASS
+        return;
+    }
     const dim3 pgrid(win ? 1 : L.n_ctiles, L.Q);
     const int64_t cols = win ? L.fw : L.ncp;
 #define PAMX_PASS(VEC, P2, WIN, PF)                                                           \
@@ -2333,8 +2541,11 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
         if (ev0) (void)hipEventRecord(ev0, s);
         enqueue_pass<T>(D, ld, L, p, false, s, true);
         if (ev1) (void)hipEventRecord(ev1, s);
+        // the merge reads per-group partials and run maps from k_fp_pass,
+        // per-chunk ones from the long-chunk pass (L.Qg = L.Q then)
         hipLaunchKernelGGL(k_fp_merge<T>, dim3(nwg), dim3(256), 0, s, (const A *)p.part,
-                           (const int32_t *)p.part_i, (const ChunkInfo *)p.cinfo, L.Q,
+                           (const int32_t *)p.part_i,
+                           (const ChunkInfo *)(L.fwG > 1 ? p.ginfo : p.cinfo), L.Qg,
                            (int64_t)L.fw, k, (const A *)p.cdn, (const uint8_t *)p.is_med,
                            (const DevState *)p.st, p.wg_v, p.wg_i, p.wg_c);
         hipLaunchKernelGGL(k_fp_select_update<T>, dim3(ob), dim3(256), 0, s, (const A *)p.wg_v,

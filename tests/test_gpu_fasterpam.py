@@ -91,6 +91,40 @@ def test_window_width_does_not_change_results(window):
     _check_same(res, ref)
 
 
+_GROUP_CASE = {}
+
+
+@pytest.mark.parametrize("group", [1, 2, 4])
+def test_window_chunk_groups(group, monkeypatch):
+    """The window pass merges 1, 2 or 4 consecutive object chunks in each
+    work-group (PAMX_FP_GROUP fixes the choice): n = 2990 makes 187 chunks of
+    16 objects, so the last group is short for 2 and 4.  Bit-exact against
+    the oracle's scan on integer distances; on an FP32 matrix (the FP64 sums
+    of a chunk group are added in another order) every choice gives the same
+    swaps, medoids and labels as 4, the changes and TD equal to 1e-12."""
+    _say("fasterpam_groups", group)
+    if not _GROUP_CASE:
+        X, D = _int_case(2990, 91, hi=400)
+        start = np.random.default_rng(91).choice(2990, size=40, replace=False).astype(np.int32)
+        _GROUP_CASE["int"] = (D, start, oracle.swap(start, D=D, variant=oracle.FASTERPAM))
+        Xf = datagen.gaussian_mixture(2990, 8, 30, seed=92)
+        Df = oracle.dist_matrix(Xf.astype(np.float64), oracle.L2).astype(np.float32)
+        monkeypatch.setenv("PAMX_FP_GROUP", "4")
+        _GROUP_CASE["float"] = (Df, px().fit(_t(Df), 30, input_kind=px().PAMX_INPUT_D,
+                                             variant="fasterpam", trace=True))
+    D, start, ref = _GROUP_CASE["int"]
+    monkeypatch.setenv("PAMX_FP_GROUP", str(group))
+    res = px().swap(_t(D.astype(np.int32)), _t(start), variant="fasterpam", trace=True)
+    _check_same(res, ref)
+    Df, f4 = _GROUP_CASE["float"]
+    f = px().fit(_t(Df), 30, input_kind=px().PAMX_INPUT_D, variant="fasterpam", trace=True)
+    assert [(i, c) for i, c, _ in f.trace] == [(i, c) for i, c, _ in f4.trace]
+    for (_, _, v), (_, _, v4) in zip(f.trace, f4.trace):
+        assert abs(v - v4) <= 1e-12 * f4.td
+    assert torch.equal(f.medoids, f4.medoids) and torch.equal(f.labels, f4.labels)
+    assert abs(f.td - f4.td) <= 1e-12 * f4.td
+
+
 def test_unaligned_ld_uses_scalar_loads():
     """A leading dimension that is not a multiple of 4 takes the 1-wide
     load path (256-candidate tiles, windows at any position)."""
