@@ -1661,6 +1661,7 @@ __global__ __launch_bounds__(256) void k_fp_select_update(
 constexpr int kClUnit = 64;      // draws in the window after a swap
 constexpr int kClMax = 1024;     // widest window (draws)
 constexpr int kClGrid = 256;     // work-groups of the scoring kernel
+constexpr int kClWaves = 16;     // its waves per work-group (the draw's segments split over them)
 
 __device__ __forceinline__ void cl_window(DevState *st) {
     const long long base = st->fp_pos;
@@ -1687,21 +1688,24 @@ __global__ void k_cl_init(DevState *st, long long len, long long maxneighbor) {
     }
 }
 
-// Change of every draw of the window: one work-group per draw; its waves
-// take the segments in turn (lanes over the segment's objects, reading the
-// candidate's row of D at the sorted objects: D symmetric), each segment
-// summed by a wave butterfly, so every sum has a fixed order.
+// Change of every draw of the window: one work-group per draw; its kClWaves
+// waves take the segments in turn (lanes over the segment's objects, reading
+// the candidate's row of D at the sorted objects: D symmetric), each segment
+// summed by a wave butterfly, so every sum has a fixed order.  A segment
+// costs two dependent reads (the sorted objects, then the row at them), so a
+// draw is a chain of about k / kClWaves such steps: sixteen waves rather
+// than four shorten it.
 template <typename T>
-__global__ __launch_bounds__(256) void k_cl_eval(
+__global__ __launch_bounds__(64 * kClWaves) void k_cl_eval(
     const T *__restrict__ D, int64_t ld, int32_t k, const int32_t *__restrict__ draws,
     const int32_t *__restrict__ srow, const T *__restrict__ sdn, const T *__restrict__ sds,
     const int32_t *__restrict__ seg_off, const uint8_t *__restrict__ is_med,
     const DevState *__restrict__ st, AccT<T> *__restrict__ out_v, int32_t *__restrict__ out_i) {
     using A = AccT<T>;
-    constexpr int U = 4;
+    constexpr int U = 4, NW = kClWaves;
     if (st->done) return;
-    __shared__ A wv[4], wa[4];
-    __shared__ int wi[4];
+    __shared__ A wv[NW], wa[NW];
+    __shared__ int wi[NW];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const long long base = st->fw_base, end = st->fw_end;
     for (long long j = base + blockIdx.x; j < end; j += gridDim.x) {
@@ -1714,7 +1718,7 @@ __global__ __launch_bounds__(256) void k_cl_eval(
         const T *row = D + c * ld;
         A accA = 0, bv = VT<T>::acc_inf();
         int bi = INT_MAX;
-        for (int sg = w; sg < k; sg += 4) {
+        for (int sg = w; sg < k; sg += NW) {
             const int32_t so = seg_off[sg], se = seg_off[sg + 1];
             if (so == se) continue;
             A M = 0, DN = 0;
@@ -1752,13 +1756,15 @@ __global__ __launch_bounds__(256) void k_cl_eval(
         if (threadIdx.x == 0) {
             A v = wv[0];
             int i = wi[0];
-            for (int u = 1; u < 4; ++u)
+            A atot = wa[0];
+            for (int u = 1; u < NW; ++u) {
                 if (lt2(wv[u], wi[u], v, i)) { v = wv[u]; i = wi[u]; }
+                atot += wa[u];
+            }
             const int e = st->empty_slot;   // an empty slot changes by 0 + B(c)
             if (e < k && lt2((A)0, e, v, i)) { v = 0; i = e; }
             A td;
             if constexpr (std::is_same<T, float>::value) td = st->td; else td = st->td_i;
-            const A atot = ((wa[0] + wa[1]) + wa[2]) + wa[3];
             out_v[r] = v + (atot - td);
             out_i[r] = i;
         }
@@ -1779,19 +1785,34 @@ __global__ __launch_bounds__(256) void k_cl_select_update(
     DevState *__restrict__ st, pamx_swap_record *__restrict__ trace) {
     using A = AccT<T>;
     if (st->done) return;
+    static_assert(4 * 256 >= kClMax, "four window entries per thread");
     __shared__ int32_t ecnt[256];
     __shared__ int first;
+    __shared__ A sv;
+    __shared__ int32_t si, sc_, sev;
     const int t = threadIdx.x;
+    // this thread's object's caches, read with the window's results (they do
+    // not depend on the decision)
+    const int64_t o = (int64_t)blockIdx.x * 256 + t;
+    int32_t nr = 0, sc = 0;
+    T a = 0, b = 0;
+    if (o < n) { nr = near[o]; sc = sec[o]; a = dn[o]; b = ds[o]; }
     const long long base = st->fw_base, end = st->fw_end;
     const int W = (int)(end - base);
     const long long fails = st->fp_quiet, maxn = st->fp_visited;
     A thr;
     if constexpr (std::is_same<T, float>::value) thr = -st->margin; else thr = 0;
-    // evaluated draws per thread (4 consecutive entries each), exclusive scan
+    // this thread's 4 consecutive entries; evaluated draws per thread,
+    // exclusive scan
+    A ev_v[4];
+    int32_t ev_i[4], ev_c[4];
     int cnt = 0;
+#pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int r = 4 * t + u;
-        if (r < W && out_i[r] >= 0) ++cnt;
+        ev_i[u] = -1; ev_v[u] = 0; ev_c[u] = 0;
+        if (r < W) { ev_i[u] = out_i[r]; ev_v[u] = out_v[r]; ev_c[u] = draws[base + r]; }
+        if (ev_i[u] >= 0) ++cnt;
     }
     ecnt[t] = cnt;
     if (t == 0) first = INT_MAX;
@@ -1801,23 +1822,31 @@ __global__ __launch_bounds__(256) void k_cl_select_update(
         if (u < t) before += ecnt[u];
         total += ecnt[u];
     }
+    int mine = -1;   // this thread's first improving entry
+#pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const int r = 4 * t + u;
-        if (r >= W || out_i[r] < 0) continue;
-        if (fails + before < maxn && out_v[r] < thr) { atomicMin(&first, r); break; }
-        ++before;
+        if (mine >= 0 || ev_i[u] < 0) continue;
+        if (fails + before < maxn && ev_v[u] < thr) { mine = u; atomicMin(&first, 4 * t + u); }
+        else ++before;
     }
     __syncthreads();
     const bool apply = first != INT_MAX;
+    // the entry's thread passes it on, with the draws evaluated up to and
+    // including it
+    if (apply && mine >= 0 && 4 * t + mine == first) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (u == mine) { sv = ev_v[u]; si = ev_i[u]; sc_ = ev_c[u]; }
+        sev = before + 1;
+    }
+    __syncthreads();
     A v = 0;
     int i = 0, c = 0;
-    if (apply) { v = out_v[first]; i = out_i[first]; c = draws[base + first]; }
+    if (apply) { v = sv; i = si; c = sc_; }
     if (blockIdx.x == 0 && t == 0) {
         st->iter += 1;
         if (apply) {
-            int ev = 0;   // evaluated draws up to and including the swap
-            for (int r = 0; r <= first; ++r) ev += (out_i[r] >= 0);
-            st->fp_cols += ev;
+            st->fp_cols += sev;
             st->best_i = i;
             st->best_c = c;
             const int old = med[i];
@@ -1855,11 +1884,8 @@ __global__ __launch_bounds__(256) void k_cl_select_update(
         }
     }
     if (!apply) return;
-    const int64_t o = (int64_t)blockIdx.x * 256 + t;
     if (o >= n) return;
     const T dnew = D[(int64_t)c * ld + o];
-    int32_t nr = near[o], sc = sec[o];
-    T a = dn[o], b = ds[o];
     if (cache_update_o1<T>(i, dnew, nr, sc, a, b)) {
         rlist[atomicAdd(&st->n_list, 1)] = (int32_t)o;
     } else {
@@ -2649,7 +2675,7 @@ hipError_t enqueue_cl_step(const T *D, int64_t ld, const Layout &L, const int32_
     pamx_swap_record *trace = static_cast<pamx_swap_record *>(opt.trace);
     const unsigned ob = (unsigned)((L.n + 255) / 256);
     enqueue_segments<T>(L, p, s);
-    hipLaunchKernelGGL(k_cl_eval<T>, dim3(kClGrid), dim3(256), 0, s, D, ld, L.k, draws,
+    hipLaunchKernelGGL(k_cl_eval<T>, dim3(kClGrid), dim3(64 * kClWaves), 0, s, D, ld, L.k, draws,
                        (const int32_t *)p.srow, (const T *)p.sdn, (const T *)p.sds,
                        (const int32_t *)p.seg_off, (const uint8_t *)p.is_med,
                        (const DevState *)p.st, clv, cli);

@@ -99,8 +99,9 @@ def test_window_chunk_groups(group, monkeypatch):
     """The window pass merges 1, 2 or 4 consecutive object chunks in each
     work-group (PAMX_FP_GROUP fixes the choice): n = 2990 makes 187 chunks of
     16 objects, so the last group is short for 2 and 4.  Bit-exact against
-    the oracle's scan on integer distances; on an FP32 matrix (the FP64 sums
-    of a chunk group are added in another order) every choice gives the same
+    the oracle's scan on integer distances (rows padded to 2992: 4-wide
+    loads); on an FP32 matrix (rows of 2990: 1-wide loads; the FP64 sums of a
+    chunk group are added in another order) every choice gives the same
     swaps, medoids and labels as 4, the changes and TD equal to 1e-12."""
     _say("fasterpam_groups", group)
     if not _GROUP_CASE:
@@ -114,7 +115,9 @@ def test_window_chunk_groups(group, monkeypatch):
                                              variant="fasterpam", trace=True))
     D, start, ref = _GROUP_CASE["int"]
     monkeypatch.setenv("PAMX_FP_GROUP", str(group))
-    res = px().swap(_t(D.astype(np.int32)), _t(start), variant="fasterpam", trace=True)
+    Dp = np.zeros((2990, 2992), np.int32)
+    Dp[:, :2990] = D
+    res = px().swap(_t(Dp)[:, :2990], _t(start), variant="fasterpam", trace=True)
     _check_same(res, ref)
     Df, f4 = _GROUP_CASE["float"]
     f = px().fit(_t(Df), 30, input_kind=px().PAMX_INPUT_D, variant="fasterpam", trace=True)
