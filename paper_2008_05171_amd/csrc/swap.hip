@@ -1708,6 +1708,42 @@ __global__ __launch_bounds__(64 * kClWaves) void k_cl_eval(
     __shared__ int wi[NW];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const long long base = st->fw_base, end = st->fw_end;
+    // this wave's segments are w, w + NW, ...; up to 64 of them their bounds
+    // stay in the lanes (read once per launch)
+    const int nseg = (w < k) ? (k - w + NW - 1) / NW : 0;
+    const bool cached = nseg <= 64;
+    int32_t c_so = 0, c_se = 0;
+    if (cached && lane < nseg) { c_so = seg_off[w + lane * NW]; c_se = seg_off[w + lane * NW + 1]; }
+    auto seg_bounds = [&](int t, int32_t &so, int32_t &se) {
+        if (cached) {
+            so = __builtin_amdgcn_readlane(c_so, t);
+            se = __builtin_amdgcn_readlane(c_se, t);
+        } else {
+            so = seg_off[w + t * NW];
+            se = seg_off[w + t * NW + 1];
+        }
+    };
+    // the first non-empty segment of this wave at or after its t-th
+    auto next_seg = [&](int t, int32_t &so, int32_t &se) {
+        for (; t < nseg; ++t) {
+            seg_bounds(t, so, se);
+            if (so < se) break;
+        }
+        return t;
+    };
+    // U slots per lane from chunk start cs of a segment [so, se), masked past
+    // its end (in bounds; unused when masked)
+    auto load_chunk = [&](int32_t cs, int32_t so, int32_t se, int32_t (&ob)[U], T (&lo)[U],
+                          T (&hi)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t p = cs + lane + u * 64;
+            const int32_t q = p < se ? p : so;
+            ob[u] = srow[q];
+            lo[u] = sdn[q];
+            hi[u] = sds[q];
+        }
+    };
     for (long long j = base + blockIdx.x; j < end; j += gridDim.x) {
         const int64_t c = draws[j];
         const int64_t r = j - base;
@@ -1718,37 +1754,49 @@ __global__ __launch_bounds__(64 * kClWaves) void k_cl_eval(
         const T *row = D + c * ld;
         A accA = 0, bv = VT<T>::acc_inf();
         int bi = INT_MAX;
-        for (int sg = w; sg < k; sg += NW) {
-            const int32_t so = seg_off[sg], se = seg_off[sg + 1];
-            if (so == se) continue;
-            A M = 0, DN = 0;
-            // U slots per lane at a time, masked past the segment's end: the
-            // object indices, then their row entries, go out together (each
-            // lane still adds its objects in order)
-            for (int32_t p0 = so + lane; p0 < se; p0 += U * 64) {
-                int32_t ob[U];
-                T d[U], lo[U], hi[U];
+        // the wave's segments as one stream of chunks of U * 64 objects (each
+        // lane adds its objects of a segment in order): the next chunk's
+        // sorted objects are read while the row entries of the current one
+        // are gathered, so a chunk costs one dependent read, not two
+        int32_t so = 0, se = 0;
+        int t = next_seg(0, so, se);
+        int32_t p0 = so;
+        int32_t ob[U] = {}, ob2[U] = {};
+        T lo[U] = {}, hi[U] = {}, lo2[U] = {}, hi2[U] = {};
+        if (t < nseg) load_chunk(p0, so, se, ob, lo, hi);
+        A M = 0, DN = 0;
+        while (t < nseg) {
+            T d[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int32_t p = p0 + u * 64;
-                    const int32_t q = p < se ? p : so;   // in bounds; unused when masked
-                    ob[u] = srow[q];
-                    lo[u] = sdn[q];
-                    hi[u] = sds[q];
-                }
+            for (int u = 0; u < U; ++u) d[u] = row[ob[u]];
+            int32_t nso = so, nse = se, np0 = p0 + U * 64;
+            int nt = t;
+            if (np0 >= se) {
+                nt = next_seg(t + 1, nso, nse);
+                np0 = nso;
+            }
+            if (nt < nseg) load_chunk(np0, nso, nse, ob2, lo2, hi2);
 #pragma unroll
-                for (int u = 0; u < U; ++u) d[u] = row[ob[u]];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (p0 + u * 64 < se) {
-                        accA += (A)vmin(d[u], lo[u]);
-                        M += (A)vmed3(d[u], lo[u], hi[u]);
-                        DN += (A)lo[u];
-                    }
+            for (int u = 0; u < U; ++u) {
+                if (p0 + lane + u * 64 < se) {
+                    accA += (A)vmin(d[u], lo[u]);
+                    M += (A)vmed3(d[u], lo[u], hi[u]);
+                    DN += (A)lo[u];
                 }
             }
-            const A v = wave_sum<A>(M) - wave_sum<A>(DN);
-            if (lt2(v, sg, bv, bi)) { bv = v; bi = sg; }
+            if (nt != t) {   // segment w + t * NW is complete
+                const int sg = w + t * NW;
+                const A v = wave_sum<A>(M) - wave_sum<A>(DN);
+                if (lt2(v, sg, bv, bi)) { bv = v; bi = sg; }
+                M = 0;
+                DN = 0;
+            }
+            t = nt;
+            p0 = np0;
+            so = nso;
+            se = nse;
+#pragma unroll
+            for (int u = 0; u < U; ++u) { ob[u] = ob2[u]; lo[u] = lo2[u]; hi[u] = hi2[u]; }
         }
         accA = wave_sum<A>(accA);
         if (lane == 0) { wv[w] = bv; wi[w] = bi; wa[w] = accA; }
