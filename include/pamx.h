@@ -85,7 +85,13 @@ extern "C" {
                             the swaps are Alg. 4's exactly (PAMX_I32) or
                             with FP64 sums of the FP32 matrix (PAMX_F32, a
                             swap taken when its change is below minus the
-                            summation bound).  max_iter caps the passes. */
+                            summation bound).  max_iter caps the passes.
+                            The window pass groups its object chunks by
+                            their length; the environment variable
+                            PAMX_FP_GROUP=1, 2 or 4 (read on every call)
+                            fixes the chunks per work-group (equal results
+                            on PAMX_I32; PAMX_F32 sums may round
+                            differently). */
 
 /* accumulation of the loss changes for PAMX_F32 dissimilarities */
 #define PAMX_ACC_F64 0 /* FP64 sums (default)                              */

@@ -1014,9 +1014,10 @@ __global__ __launch_bounds__(kWG) PAMX_PASS_ATTR void k_swap_pass(
 // part_i = its slot; ginfo[g] = {first run's slot, last run's slot, kHead if
 // there is a first run, kTail if there is a last one} and cdn[2g],
 // cdn[2g + 1] their parts of DN.  A run that continues into the next group is
-// finished by the merge (k_fp_merge), exactly as for single chunks.  For
-// short chunks (latency-bound; the merge's input a quarter with G = 4); long
-// chunks take k_swap_pass<..., WIN = true>, whose waves share their rows.
+// finished by the merge (k_fp_merge), exactly as for single chunks.  Used
+// for short chunks, which are latency-bound (with G = 4 the merge reads a
+// quarter of the partials); long chunks take k_swap_pass<..., WIN = true>,
+// whose waves share their rows.
 constexpr int kFpU = 8;   // rows per block of the window pass
 template <typename T, int VEC, int G>
 __global__ __launch_bounds__(kWG) PAMX_PASS_ATTR void k_fp_pass(
