@@ -1835,11 +1835,11 @@ __global__ __launch_bounds__(256) void k_cl_select_update(
     using A = AccT<T>;
     if (st->done) return;
     static_assert(4 * 256 >= kClMax, "four window entries per thread");
-    __shared__ int32_t ecnt[256];
+    __shared__ int32_t wsum[4];
     __shared__ int first;
     __shared__ A sv;
     __shared__ int32_t si, sc_, sev;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     // this thread's object's caches, read with the window's results (they do
     // not depend on the decision)
     const int64_t o = (int64_t)blockIdx.x * 256 + t;
@@ -1863,13 +1863,18 @@ __global__ __launch_bounds__(256) void k_cl_select_update(
         if (r < W) { ev_i[u] = out_i[r]; ev_v[u] = out_v[r]; ev_c[u] = draws[base + r]; }
         if (ev_i[u] >= 0) ++cnt;
     }
-    ecnt[t] = cnt;
+    int x = cnt;   // inclusive scan over the wave, then the wave totals in order
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
     if (t == 0) first = INT_MAX;
     __syncthreads();
-    int before = 0, total = 0;
-    for (int u = 0; u < 256; ++u) {
-        if (u < t) before += ecnt[u];
-        total += ecnt[u];
+    int before = x - cnt, total = 0;
+    for (int u = 0; u < 4; ++u) {
+        if (u < wv) before += wsum[u];
+        total += wsum[u];
     }
     int mine = -1;   // this thread's first improving entry
 #pragma unroll
