@@ -971,10 +971,10 @@ __device__ __forceinline__ void pass_tile(
 // WIN: the FasterPAM window pass over long chunks (one work-group per chunk
 // over every tile of the window [fw_base, fw_end), partials indexed from
 // fw_base; ncp is then the window width).  Its rows go in blocks of eight,
-// the next block issued before the current one is summed: 28.7 -> 26.0 us
-// per pass at n = 20000 and 106 -> 92 us at n = 100000 against blocks
-// loaded one at a time (prefetched blocks of four were slower than either).
-// Short chunks take k_fp_pass instead.
+// the next block issued before the current one is summed: 106 -> 92 us per
+// pass at n = 100000 (392-object chunks) against blocks loaded one at a
+// time; prefetched blocks of four were slower than either.  Short chunks
+// take k_fp_pass instead.
 template <typename T, int VEC, bool P2, bool WIN, bool PF = false>
 __global__ __launch_bounds__(kWG) PAMX_PASS_ATTR void k_swap_pass(
     const T *__restrict__ D, int64_t ld, int64_t n, int64_t nc, int32_t k,
@@ -1570,6 +1570,51 @@ __global__ __launch_bounds__(256) void k_fp_merge(
     }
 }
 
+// The window's outcome, by one thread: the swap (medoids, TD, trace) or the
+// scan's advance, the scan bookkeeping, the stop rule and the next window.
+template <typename T>
+__device__ __forceinline__ void fp_decide(DevState *st, bool apply, AccT<T> v, int i, int c,
+                                          int64_t n, int64_t tile, int32_t max_tiles, int32_t vec,
+                                          int32_t *med, uint8_t *is_med,
+                                          pamx_swap_record *trace) {
+    st->iter += 1;
+    const long long pos = st->fp_pos, end = st->fw_end;
+    st->fp_cols += end - st->fw_base;
+    if (apply) {
+        st->best_i = i;
+        st->best_c = c;
+        const int old = med[i];
+        is_med[old] = 0;
+        is_med[c] = 1;
+        med[i] = c;
+        st->old_med = old;
+        st->new_slot = i;
+        st->new_med = c;
+        if constexpr (std::is_same<T, float>::value) { st->best_v = v; st->td += v; }
+        else { st->best_vi = v; st->best_v = (double)v; st->td_i += v; st->td = (double)st->td_i; }
+        if (trace && st->swaps < st->trace_cap) trace[st->swaps] = pamx_swap_record{i, c, (double)v};
+        st->swaps += 1;
+        st->fp_visited += (long long)c - pos + 1;
+        st->fp_quiet = 0;
+        st->fp_pos = (c + 1 == n) ? 0 : c + 1;
+    } else {
+        st->fp_visited += end - pos;
+        st->fp_quiet += end - pos;
+        st->fp_pos = (end == n) ? 0 : end;
+    }
+    st->swapped = apply ? 1 : 0;
+    st->seg_skip = apply ? 0 : 1;
+    st->fw_tiles = apply ? 1 : min(2 * st->fw_tiles, max_tiles);
+    if (st->fp_quiet >= n) {
+        st->done = 1;
+    } else if (st->fp_visited >= st->fp_limit) {
+        st->done = 1;
+        st->capped = 1;
+    } else {
+        fp_window(st, n, tile, vec);
+    }
+}
+
 // Every block finds the window's first improving candidate (the smallest
 // one any merge work-group reported) -- the same in every block -- and,
 // when there is one, updates its objects' caches by the O(1) rule.  Block 0
@@ -1597,44 +1642,8 @@ __global__ __launch_bounds__(256) void k_fp_select_update(
     A v = 0;
     int i = 0, c = 0;
     if (apply) { v = wg_v[wb]; i = wg_i[wb]; c = wg_c[wb]; }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->iter += 1;
-        const long long pos = st->fp_pos, end = st->fw_end;
-        st->fp_cols += end - st->fw_base;
-        if (apply) {
-            st->best_i = i;
-            st->best_c = c;
-            const int old = med[i];
-            is_med[old] = 0;
-            is_med[c] = 1;
-            med[i] = c;
-            st->old_med = old;
-            st->new_slot = i;
-            st->new_med = c;
-            if constexpr (std::is_same<T, float>::value) { st->best_v = v; st->td += v; }
-            else { st->best_vi = v; st->best_v = (double)v; st->td_i += v; st->td = (double)st->td_i; }
-            if (trace && st->swaps < st->trace_cap) trace[st->swaps] = pamx_swap_record{i, c, (double)v};
-            st->swaps += 1;
-            st->fp_visited += (long long)c - pos + 1;
-            st->fp_quiet = 0;
-            st->fp_pos = (c + 1 == n) ? 0 : c + 1;
-        } else {
-            st->fp_visited += end - pos;
-            st->fp_quiet += end - pos;
-            st->fp_pos = (end == n) ? 0 : end;
-        }
-        st->swapped = apply ? 1 : 0;
-        st->seg_skip = apply ? 0 : 1;
-        st->fw_tiles = apply ? 1 : min(2 * st->fw_tiles, max_tiles);
-        if (st->fp_quiet >= n) {
-            st->done = 1;
-        } else if (st->fp_visited >= st->fp_limit) {
-            st->done = 1;
-            st->capped = 1;
-        } else {
-            fp_window(st, n, tile, vec);
-        }
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        fp_decide<T>(st, apply, v, i, c, n, tile, max_tiles, vec, med, is_med, trace);
     if (!apply) return;
     const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (o >= n) return;
@@ -1645,6 +1654,97 @@ __global__ __launch_bounds__(256) void k_fp_select_update(
         rlist[atomicAdd(&st->n_list, 1)] = (int32_t)o;
     } else {
         near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b;
+    }
+}
+
+// FasterPAM's decision, cache update and count in one launch (k <= kRsMed):
+// the decision and the O(1) update as k_fp_select_update; then every block
+// rescans its own objects that need it (one wave per object, the medoids
+// staged in LDS with the new one in its slot, so block 0's write of med does
+// not have to be seen) and does k_seg_count's work for its objects (their
+// slots counted, their dn and ds summed in the same fixed order), so the
+// rescan and count launches of the window step go away.  Objects of a
+// cluster stored together would put their rescans on one block; the synthetic
+// workloads, like most data, spread them.
+template <typename T>
+__global__ __launch_bounds__(kObjBlk) void k_fp_apply(
+    const AccT<T> *__restrict__ wg_v, const int32_t *__restrict__ wg_i,
+    const int32_t *__restrict__ wg_c, int32_t nwg, const T *__restrict__ D, int64_t ld,
+    int64_t n, int32_t k, int64_t tile, int32_t max_tiles, int32_t vec, int32_t *__restrict__ med,
+    uint8_t *__restrict__ is_med, int32_t *__restrict__ near, int32_t *__restrict__ sec,
+    T *__restrict__ dn, T *__restrict__ ds, int32_t *__restrict__ blkcnt,
+    AccT<T> *__restrict__ tdp, DevState *__restrict__ st, pamx_swap_record *__restrict__ trace) {
+    using A = AccT<T>;
+    static_assert(kObjBlk == 256, "one object per thread");
+    if (st->done) return;
+    extern __shared__ int32_t hist[];   // k counts
+    __shared__ int32_t smed[kRsMed];
+    __shared__ long long wfirst;        // (candidate << 32) | merge work-group
+    __shared__ int32_t rl[kObjBlk];     // this block's objects to rescan
+    __shared__ int32_t nrl;
+    __shared__ int32_t r_nr[kObjBlk];   // their new caches
+    __shared__ T r_dn[kObjBlk], r_ds[kObjBlk];
+    __shared__ A w1[kObjBlk / 64], w2[kObjBlk / 64];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t == 0) { wfirst = LLONG_MAX; nrl = 0; }
+    __syncthreads();
+    for (int w = t; w < nwg; w += kObjBlk) {
+        const int32_t c = wg_c[w];
+        if (c != INT_MAX) atomicMin(&wfirst, ((long long)c << 32) | w);
+    }
+    __syncthreads();
+    const bool apply = wfirst != LLONG_MAX;
+    const int wb = apply ? (int)(wfirst & 0xffffffffLL) : 0;
+    A v = 0;
+    int i = 0, c = 0;
+    if (apply) { v = wg_v[wb]; i = wg_i[wb]; c = wg_c[wb]; }
+    if (blockIdx.x == 0 && t == 0) fp_decide<T>(st, apply, v, i, c, n, tile, max_tiles, vec, med, is_med, trace);
+    if (!apply) return;   // the segments are kept (seg_skip)
+    const int64_t o = (int64_t)blockIdx.x * kObjBlk + t;
+    for (int j = t; j < k; j += kObjBlk) { smed[j] = (j == i) ? c : med[j]; hist[j] = 0; }
+    int32_t nr = 0, sc = 0;
+    T a = 0, b = 0;
+    bool resc = false;
+    if (o < n) {
+        const T dnew = D[(int64_t)c * ld + o];
+        nr = near[o]; sc = sec[o]; a = dn[o]; b = ds[o];
+        resc = cache_update_o1<T>(i, dnew, nr, sc, a, b);
+        if (resc) rl[atomicAdd(&nrl, 1)] = t;
+        else { near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b; }
+    }
+    __syncthreads();
+    const int m = nrl;
+    for (int idx = wv; idx < m; idx += kObjBlk / 64) {
+        const int lt = rl[idx];
+        const int64_t ob = (int64_t)blockIdx.x * kObjBlk + lt;
+        const Top2<T> tp = wave_scan_medoids<T>(D, ld, k, smed, ob, lane);
+        if (lane == 0) {
+            store_top2<T>(tp, ob, near, sec, dn, ds);
+            r_nr[lt] = (tp.j1 == INT_MAX) ? 0 : tp.j1;
+            r_dn[lt] = tp.d1;
+            r_ds[lt] = tp.d2;
+        }
+    }
+    __syncthreads();
+    // k_seg_count's sums for this block, in its order
+    A s1 = 0, s2 = 0;
+    if (o < n) {
+        if (resc) { nr = r_nr[t]; a = r_dn[t]; b = r_ds[t]; }
+        atomicAdd(&hist[nr], 1);
+        s1 = (A)a;
+        s2 = (A)b;
+    }
+    s1 = wave_sum<A>(s1);
+    s2 = wave_sum<A>(s2);
+    if (lane == 0) { w1[wv] = s1; w2[wv] = s2; }
+    __syncthreads();
+    int32_t *dst = blkcnt + (int64_t)blockIdx.x * k;
+    for (int j = t; j < k; j += kObjBlk) dst[j] = hist[j];
+    if (t == 0) {
+        A t1 = 0, t2 = 0;
+        for (int u = 0; u < kObjBlk / 64; ++u) { t1 += w1[u]; t2 += w2[u]; }
+        tdp[2 * blockIdx.x] = t1;
+        tdp[2 * blockIdx.x + 1] = t2;
     }
 }
 
@@ -2518,15 +2618,25 @@ static hipError_t enqueue_caches(const T *D, int64_t ld, const Layout &L, const 
     return hipGetLastError();
 }
 
-// Objects sorted by nearest slot, segment offsets, chunk map (the chunk
-// map depends on the chunk length of L).
+// FasterPAM with the fused decision, update and count (k_fp_apply)
+static bool fp_fused(const Layout &L) { return L.fw > 0 && L.k <= kRsMed; }
+
 template <typename T>
-static void enqueue_segments(const Layout &L, const SwapPtrs<T> &p, hipStream_t s) {
+static void enqueue_count(const Layout &L, const SwapPtrs<T> &p, hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_count<T>, dim3(L.n_oblk), dim3(kObjBlk), (size_t)L.k * 4, s,
+                       (const int32_t *)p.near, (const T *)p.dn, (const T *)p.ds, L.n, L.k,
+                       p.blkcnt, p.tdp, p.st);
+}
+
+// Objects sorted by nearest slot, segment offsets, chunk map (the chunk
+// map depends on the chunk length of L); count = false when the per-block
+// counts are already there (k_fp_apply).
+template <typename T>
+static void enqueue_segments(const Layout &L, const SwapPtrs<T> &p, hipStream_t s,
+                             bool count = true) {
     const int64_t n = L.n;
     const int32_t k = L.k;
-    hipLaunchKernelGGL(k_seg_count<T>, dim3(L.n_oblk), dim3(kObjBlk), (size_t)k * 4, s,
-                       (const int32_t *)p.near, (const T *)p.dn, (const T *)p.ds, n, k, p.blkcnt,
-                       p.tdp, p.st);
+    if (count) enqueue_count<T>(L, p, s);
     hipLaunchKernelGGL(k_seg_colscan, dim3((k + 3) / 4), dim3(256), 0, s, p.blkcnt, L.n_oblk, k,
                        p.segtot, (const DevState *)p.st);
     hipLaunchKernelGGL(k_seg_scatter<T>, dim3(L.n_oblk), dim3(kObjBlk), (size_t)(k + 1) * 4, s,
@@ -2617,7 +2727,8 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
     if (opt.variant == PAMX_FASTERPAM) {
         // one window of the scan (segments are rebuilt only after a swap)
         const int nwg = (L.fw / kFmCPB < kFmGrid) ? L.fw / kFmCPB : kFmGrid;   // merge work-groups
-        enqueue_segments<T>(L, p, s);
+        const bool fused = fp_fused(L);
+        enqueue_segments<T>(L, p, s, !fused);
         if (ev0) (void)hipEventRecord(ev0, s);
         enqueue_pass<T>(D, ld, L, p, false, s, true);
         if (ev1) (void)hipEventRecord(ev1, s);
@@ -2628,6 +2739,14 @@ hipError_t enqueue_swap_iteration(const T *D, int64_t ld, const Layout &L, int32
                            (const ChunkInfo *)(L.fwG > 1 ? p.ginfo : p.cinfo), L.Qg,
                            (int64_t)L.fw, k, (const A *)p.cdn, (const uint8_t *)p.is_med,
                            (const DevState *)p.st, p.wg_v, p.wg_i, p.wg_c);
+        if (fused) {
+            hipLaunchKernelGGL(k_fp_apply<T>, dim3(L.n_oblk), dim3(kObjBlk), (size_t)k * 4, s,
+                               (const A *)p.wg_v, (const int32_t *)p.wg_i,
+                               (const int32_t *)p.wg_c, nwg, D, ld, n, k, (int64_t)L.tile,
+                               L.fw / L.tile, L.vec, medoids, p.is_med, p.near, p.sec, p.dn,
+                               p.ds, p.blkcnt, p.tdp, p.st, trace);
+            return hipGetLastError();
+        }
         hipLaunchKernelGGL(k_fp_select_update<T>, dim3(ob), dim3(256), 0, s, (const A *)p.wg_v,
                            (const int32_t *)p.wg_i, (const int32_t *)p.wg_c, nwg, D, ld, n,
                            (int64_t)L.tile, L.fw / L.tile, L.vec, medoids, p.is_med, p.near,
@@ -2756,7 +2875,12 @@ hipError_t enqueue_finalize(const T *D, int64_t ld, const Layout &L, const int32
 template <typename T>
 hipError_t enqueue_swap_caches(const T *D, int64_t ld, const Layout &L, const int32_t *medoids,
                                void *ws, hipStream_t s) {
-    return enqueue_caches<T>(D, ld, L, medoids, nullptr, ws, s);
+    const hipError_t e = enqueue_caches<T>(D, ld, L, medoids, nullptr, ws, s);
+    if (e != hipSuccess) return e;
+    // FasterPAM with k_fp_apply: the first window's counts (later windows
+    // get theirs from k_fp_apply)
+    if (fp_fused(L)) enqueue_count<T>(L, ptrs<T>(L, ws), s);
+    return hipGetLastError();
 }
 
 // The segment kernels on FP32 caches, for the mixed-precision form.

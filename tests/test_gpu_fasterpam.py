@@ -128,6 +128,19 @@ def test_window_chunk_groups(group, monkeypatch):
     assert abs(f.td - f4.td) <= 1e-12 * f4.td
 
 
+def test_more_medoids_than_lds_staging():
+    """k above the 4096 medoids a work-group stages in LDS: the window step
+    falls back to the separate decision, rescan and count launches (random
+    start, integer distances, bit-exact against the oracle's scan)."""
+    _say("fasterpam_k4100")
+    X, D = _int_case(4300, 95, hi=3000)
+    start = np.random.default_rng(95).choice(4300, size=4100, replace=False).astype(np.int32)
+    ref = oracle.swap(start, D=D, variant=oracle.FASTERPAM)
+    res = px().swap(_t(D.astype(np.int32)), _t(start), variant="fasterpam", trace=True)
+    assert res.rc == 0
+    _check_same(res, ref)
+
+
 def test_unaligned_ld_uses_scalar_loads():
     """A leading dimension that is not a multiple of 4 takes the 1-wide
     load path (256-candidate tiles, windows at any position)."""
