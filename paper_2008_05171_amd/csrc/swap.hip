@@ -1657,49 +1657,28 @@ __global__ __launch_bounds__(256) void k_fp_select_update(
     }
 }
 
-// FasterPAM's decision, cache update and count in one launch (k <= kRsMed):
-// the decision and the O(1) update as k_fp_select_update; then every block
-// rescans its own objects that need it (one wave per object, the medoids
-// staged in LDS with the new one in its slot, so block 0's write of med does
-// not have to be seen) and does k_seg_count's work for its objects (their
-// slots counted, their dn and ds summed in the same fixed order), so the
-// rescan and count launches of the window step go away.  Objects of a
-// cluster stored together would put their rescans on one block; the synthetic
-// workloads, like most data, spread them.
+// After the decision of a window (slot i receives candidate c): every block
+// updates its objects' caches by the O(1) rule, rescans those of its objects
+// that need it (one wave per object, the medoids staged in LDS with the new
+// one in its slot, so block 0's write of med does not have to be seen) and
+// does k_seg_count's work for its objects (their slots counted, their dn and
+// ds summed in the same fixed order).  hist: k ints of dynamic LDS.
 template <typename T>
-__global__ __launch_bounds__(kObjBlk) void k_fp_apply(
-    const AccT<T> *__restrict__ wg_v, const int32_t *__restrict__ wg_i,
-    const int32_t *__restrict__ wg_c, int32_t nwg, const T *__restrict__ D, int64_t ld,
-    int64_t n, int32_t k, int64_t tile, int32_t max_tiles, int32_t vec, int32_t *__restrict__ med,
-    uint8_t *__restrict__ is_med, int32_t *__restrict__ near, int32_t *__restrict__ sec,
+__device__ __forceinline__ void apply_update_count(
+    int i, int c, const T *__restrict__ D, int64_t ld, int64_t n, int32_t k,
+    const int32_t *__restrict__ med, int32_t *__restrict__ near, int32_t *__restrict__ sec,
     T *__restrict__ dn, T *__restrict__ ds, int32_t *__restrict__ blkcnt,
-    AccT<T> *__restrict__ tdp, DevState *__restrict__ st, pamx_swap_record *__restrict__ trace) {
+    AccT<T> *__restrict__ tdp, int32_t *__restrict__ hist) {
     using A = AccT<T>;
     static_assert(kObjBlk == 256, "one object per thread");
-    if (st->done) return;
-    extern __shared__ int32_t hist[];   // k counts
+    constexpr int NW = kObjBlk / 64;
     __shared__ int32_t smed[kRsMed];
-    __shared__ long long wfirst;        // (candidate << 32) | merge work-group
-    __shared__ int32_t rl[kObjBlk];     // this block's objects to rescan
-    __shared__ int32_t nrl;
+    __shared__ int32_t rl[kObjBlk];     // objects to rescan: one list per wave
+    __shared__ int32_t wcnt[NW];
     __shared__ int32_t r_nr[kObjBlk];   // their new caches
     __shared__ T r_dn[kObjBlk], r_ds[kObjBlk];
-    __shared__ A w1[kObjBlk / 64], w2[kObjBlk / 64];
+    __shared__ A w1[NW], w2[NW];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    if (t == 0) { wfirst = LLONG_MAX; nrl = 0; }
-    __syncthreads();
-    for (int w = t; w < nwg; w += kObjBlk) {
-        const int32_t c = wg_c[w];
-        if (c != INT_MAX) atomicMin(&wfirst, ((long long)c << 32) | w);
-    }
-    __syncthreads();
-    const bool apply = wfirst != LLONG_MAX;
-    const int wb = apply ? (int)(wfirst & 0xffffffffLL) : 0;
-    A v = 0;
-    int i = 0, c = 0;
-    if (apply) { v = wg_v[wb]; i = wg_i[wb]; c = wg_c[wb]; }
-    if (blockIdx.x == 0 && t == 0) fp_decide<T>(st, apply, v, i, c, n, tile, max_tiles, vec, med, is_med, trace);
-    if (!apply) return;   // the segments are kept (seg_skip)
     const int64_t o = (int64_t)blockIdx.x * kObjBlk + t;
     for (int j = t; j < k; j += kObjBlk) { smed[j] = (j == i) ? c : med[j]; hist[j] = 0; }
     int32_t nr = 0, sc = 0;
@@ -1709,13 +1688,18 @@ __global__ __launch_bounds__(kObjBlk) void k_fp_apply(
         const T dnew = D[(int64_t)c * ld + o];
         nr = near[o]; sc = sec[o]; a = dn[o]; b = ds[o];
         resc = cache_update_o1<T>(i, dnew, nr, sc, a, b);
-        if (resc) rl[atomicAdd(&nrl, 1)] = t;
-        else { near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b; }
+        if (!resc) { near[o] = nr; sec[o] = sc; dn[o] = a; ds[o] = b; }
     }
+    const unsigned long long msk = __ballot(resc);
+    if (resc) rl[wv * 64 + __popcll(msk & ((1ull << lane) - 1ull))] = t;
+    if (lane == 0) wcnt[wv] = __popcll(msk);
     __syncthreads();
-    const int m = nrl;
-    for (int idx = wv; idx < m; idx += kObjBlk / 64) {
-        const int lt = rl[idx];
+    int m = 0;
+    for (int u = 0; u < NW; ++u) m += wcnt[u];
+    for (int idx = wv; idx < m; idx += NW) {
+        int q = idx, u = 0;   // entry idx of the wave lists taken in order
+        while (q >= wcnt[u]) { q -= wcnt[u]; ++u; }
+        const int lt = rl[u * 64 + q];
         const int64_t ob = (int64_t)blockIdx.x * kObjBlk + lt;
         const Top2<T> tp = wave_scan_medoids<T>(D, ld, k, smed, ob, lane);
         if (lane == 0) {
@@ -1742,10 +1726,45 @@ __global__ __launch_bounds__(kObjBlk) void k_fp_apply(
     for (int j = t; j < k; j += kObjBlk) dst[j] = hist[j];
     if (t == 0) {
         A t1 = 0, t2 = 0;
-        for (int u = 0; u < kObjBlk / 64; ++u) { t1 += w1[u]; t2 += w2[u]; }
+        for (int u = 0; u < NW; ++u) { t1 += w1[u]; t2 += w2[u]; }
         tdp[2 * blockIdx.x] = t1;
         tdp[2 * blockIdx.x + 1] = t2;
     }
+}
+
+// FasterPAM's decision, cache update and count in one launch (k <= kRsMed):
+// the decision as k_fp_select_update, then apply_update_count, so the rescan
+// and count launches of the window step go away.  Objects of a cluster
+// stored together would put their rescans on one block; the synthetic
+// workloads, like most data, spread them.
+template <typename T>
+__global__ __launch_bounds__(kObjBlk) void k_fp_apply(
+    const AccT<T> *__restrict__ wg_v, const int32_t *__restrict__ wg_i,
+    const int32_t *__restrict__ wg_c, int32_t nwg, const T *__restrict__ D, int64_t ld,
+    int64_t n, int32_t k, int64_t tile, int32_t max_tiles, int32_t vec, int32_t *__restrict__ med,
+    uint8_t *__restrict__ is_med, int32_t *__restrict__ near, int32_t *__restrict__ sec,
+    T *__restrict__ dn, T *__restrict__ ds, int32_t *__restrict__ blkcnt,
+    AccT<T> *__restrict__ tdp, DevState *__restrict__ st, pamx_swap_record *__restrict__ trace) {
+    using A = AccT<T>;
+    if (st->done) return;
+    extern __shared__ int32_t hist[];   // k counts
+    __shared__ long long wfirst;        // (candidate << 32) | merge work-group
+    const int t = threadIdx.x;
+    if (t == 0) wfirst = LLONG_MAX;
+    __syncthreads();
+    for (int w = t; w < nwg; w += kObjBlk) {
+        const int32_t c = wg_c[w];
+        if (c != INT_MAX) atomicMin(&wfirst, ((long long)c << 32) | w);
+    }
+    __syncthreads();
+    const bool apply = wfirst != LLONG_MAX;
+    const int wb = apply ? (int)(wfirst & 0xffffffffLL) : 0;
+    A v = 0;
+    int i = 0, c = 0;
+    if (apply) { v = wg_v[wb]; i = wg_i[wb]; c = wg_c[wb]; }
+    if (blockIdx.x == 0 && t == 0) fp_decide<T>(st, apply, v, i, c, n, tile, max_tiles, vec, med, is_med, trace);
+    if (!apply) return;   // the segments are kept (seg_skip)
+    apply_update_count<T>(i, c, D, ld, n, k, med, near, sec, dn, ds, blkcnt, tdp, hist);
 }
 
 // ---- FastCLARANS (Sec. 3.4): one local search over a list of random draws.
@@ -1925,12 +1944,13 @@ __global__ __launch_bounds__(64 * kClWaves) void k_cl_eval(
 // before the failure limit (the same in every block), and updates its
 // objects' caches when that draw is swapped in.  Block 0 applies the swap or
 // ends / advances the search and places the next window.
-template <typename T>
+template <typename T, bool FUSED>
 __global__ __launch_bounds__(256) void k_cl_select_update(
     const AccT<T> *__restrict__ out_v, const int32_t *__restrict__ out_i,
     const int32_t *__restrict__ draws, const T *__restrict__ D, int64_t ld, int64_t n,
     int32_t *__restrict__ med, uint8_t *__restrict__ is_med, int32_t *__restrict__ near,
     int32_t *__restrict__ sec, T *__restrict__ dn, T *__restrict__ ds, int32_t *__restrict__ rlist,
+    int32_t k, int32_t *__restrict__ blkcnt, AccT<T> *__restrict__ tdp,
     DevState *__restrict__ st, pamx_swap_record *__restrict__ trace) {
     using A = AccT<T>;
     if (st->done) return;
@@ -2038,6 +2058,12 @@ __global__ __launch_bounds__(256) void k_cl_select_update(
         }
     }
     if (!apply) return;
+    if constexpr (FUSED) {
+        // k <= kRsMed: the update, rescans and counts here (apply_update_count)
+        extern __shared__ int32_t hist[];
+        apply_update_count<T>(i, c, D, ld, n, k, med, near, sec, dn, ds, blkcnt, tdp, hist);
+        return;
+    }
     if (o >= n) return;
     const T dnew = D[(int64_t)c * ld + o];
     if (cache_update_o1<T>(i, dnew, nr, sc, a, b)) {
@@ -2833,6 +2859,8 @@ hipError_t enqueue_cl_init(const Layout &L, int64_t len, int64_t maxneighbor, vo
     auto p = ptrs<T>(L, ws);
     hipLaunchKernelGGL(k_cl_init, dim3(1), dim3(1), 0, s, p.st, (long long)len,
                        (long long)maxneighbor);
+    // the first window's counts when the decision kernel counts the others
+    if (L.k <= kRsMed) enqueue_count<T>(L, p, s);
     return hipGetLastError();
 }
 
@@ -2847,14 +2875,24 @@ hipError_t enqueue_cl_step(const T *D, int64_t ld, const Layout &L, const int32_
     int32_t *cli = reinterpret_cast<int32_t *>(w + L.cl_i);
     pamx_swap_record *trace = static_cast<pamx_swap_record *>(opt.trace);
     const unsigned ob = (unsigned)((L.n + 255) / 256);
-    enqueue_segments<T>(L, p, s);
+    // up to kRsMed medoids the decision kernel also updates, rescans and
+    // counts (the counts of the first window come from enqueue_cl_init)
+    const bool fused = L.k <= kRsMed;
+    enqueue_segments<T>(L, p, s, !fused);
     hipLaunchKernelGGL(k_cl_eval<T>, dim3(kClGrid), dim3(64 * kClWaves), 0, s, D, ld, L.k, draws,
                        (const int32_t *)p.srow, (const T *)p.sdn, (const T *)p.sds,
                        (const int32_t *)p.seg_off, (const uint8_t *)p.is_med,
                        (const DevState *)p.st, clv, cli);
-    hipLaunchKernelGGL(k_cl_select_update<T>, dim3(ob), dim3(256), 0, s, (const A *)clv,
+    if (fused) {
+        hipLaunchKernelGGL((k_cl_select_update<T, true>), dim3(ob), dim3(256), (size_t)L.k * 4, s,
+                           (const A *)clv, (const int32_t *)cli, draws, D, ld, L.n, medoids,
+                           p.is_med, p.near, p.sec, p.dn, p.ds, p.rlist, L.k, p.blkcnt, p.tdp,
+                           p.st, trace);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_cl_select_update<T, false>), dim3(ob), dim3(256), 0, s, (const A *)clv,
                        (const int32_t *)cli, draws, D, ld, L.n, medoids, p.is_med, p.near, p.sec,
-                       p.dn, p.ds, p.rlist, p.st, trace);
+                       p.dn, p.ds, p.rlist, L.k, p.blkcnt, p.tdp, p.st, trace);
     hipLaunchKernelGGL(k_cache_rescan<T>, dim3(256), dim3(256), 0, s, D, ld, L.k,
                        (const int32_t *)medoids, p.near, p.sec, p.dn, p.ds,
                        (const int32_t *)p.rlist, (const DevState *)p.st);
