@@ -1617,8 +1617,10 @@ __device__ __forceinline__ void fp_decide(DevState *st, bool apply, AccT<T> v, i
 
 // Every block finds the window's first improving candidate (the smallest
 // one any merge work-group reported) -- the same in every block -- and,
-// when there is one, updates its objects' caches by the O(1) rule.  Block 0
-// applies the swap or advances the scan, and places the next window.
+// when there is one, updates its objects' caches by the O(1) rule (objects
+// that need a rescan go to the grid-wide list of k_cache_rescan).  Block 0
+// applies the swap or advances the scan, and places the next window.  Used
+// above kRsMed medoids; k_fp_apply otherwise.
 template <typename T>
 __global__ __launch_bounds__(256) void k_fp_select_update(
     const AccT<T> *__restrict__ wg_v, const int32_t *__restrict__ wg_i,
